@@ -1,0 +1,172 @@
+/*
+ * bltt.h -- C ABI of the MI355X PMINRES solver for symmetrised block lower
+ * triangular Toeplitz (BLTT) all-at-once systems.
+ *
+ * Method: Li, Lin, Hon, Wu, "A preconditioned MINRES method for block lower
+ * triangular Toeplitz systems" (arXiv 2307.07749).  The solver runs MINRES on
+ * Y A u = Y f (Section 2, eq. (4)) preconditioned by the absolute-value block
+ * alpha-circulant matrix P_alpha = |C_alpha| (Section 3, eqs. (5)-(13)),
+ * applied as in Section 5.1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Vectors are time-major: element (n, i) of an MN-vector sits at n*M + i,
+ *    n = 0..N-1 the time step, i the lexicographic spatial index with x
+ *    fastest (i = x + m0*(y + m1*z)).
+ *  - Blocks are A_(k) = p[k] I + q[k] L_h, where L_h is the zero-Dirichlet
+ *    central-difference negative Laplacian (Section 5): h_d^-2 (2 on the
+ *    diagonal, -1 on each neighbour) summed over the dimensions.  Every block
+ *    is then diagonalised by the orthonormal sine transform (Remark 1).
+ *  - Device pointers ("_dev") are HIP device memory owned by the caller; the
+ *    library never frees them.  Host pointers are read during the call only.
+ *  - The stream argument is a hipStream_t passed as void*; NULL is the null
+ *    stream.  All device work of a handle is enqueued on that stream.
+ *  - Return codes: BLTT_OK (0) on success, BLTT_NOCONV (> 0) when the
+ *    iteration limit was reached (outputs are still valid), a negative
+ *    BLTT_E* code on error (outputs untouched unless stated).
+ *  - Size limits: N and every m_d + 1 must be powers of two with
+ *    2 <= N <= 2048 and 2 <= 2(m_d + 1) <= 2048; p may be dense; q may have at
+ *    most 4 leading non-zero taps (q[k] = 0 for k >= 4).  Other inputs give
+ *    BLTT_EUNSUPPORTED.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef BLTT_H
+#define BLTT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum bltt_status {
+  BLTT_OK = 0,
+  BLTT_NOCONV = 1,          /* maxit reached before tol; u, iters, hist valid   */
+  BLTT_EINVAL = -1,         /* bad argument (null pointer, size, alpha, tol)     */
+  BLTT_EASSUMPTION = -2,    /* Assumption 1(ii) fails: min_i(l_i^(0) -
+                               sum_k |l_i^(k)|) <= 0 (Section 2, Prop. 1)        */
+  BLTT_ENAN = -3,           /* non-finite value met in the input or iteration    */
+  BLTT_EBREAKDOWN = -4,     /* <v, P^{-1} v> < 0: preconditioner not SPD in
+                               floating point                                   */
+  BLTT_ENOMEM = -5,         /* device allocation failed                          */
+  BLTT_EHIP = -6,           /* a HIP runtime call failed                         */
+  BLTT_EUNSUPPORTED = -7    /* size or block structure outside the limits above  */
+};
+
+enum bltt_precision {
+  BLTT_FP64 = 0,            /* every step in FP64                                 */
+  BLTT_MIXED = 1,           /* FP32 transforms/matvec/Krylov vectors inside an
+                               FP64 iterative-refinement loop                     */
+  BLTT_FP32 = 2             /* step-level entry points only: FP32 arithmetic      */
+};
+
+/* Block description.  dim in {1,2,3}; m[d] interior points and h[d] spacing of
+ * dimension d (d = 0 is x, the fastest); p and q are host arrays of length N
+ * (copied during bltt_setup). */
+typedef struct {
+  int32_t dim;
+  int32_t m[3];
+  double h[3];
+  const double *p;
+  const double *q;
+} bltt_blocks;
+
+/* Solver options.  Pass NULL for the defaults. */
+typedef struct {
+  int32_t precision;      /* BLTT_FP64 (default) or BLTT_MIXED                    */
+  double inner_tol;       /* MIXED: relative tolerance of each FP32 inner solve
+                             on its own right-hand side (default 1e-4)            */
+  int32_t max_refine;     /* MIXED: maximum refinement sweeps (default 20)        */
+  double check_factor;    /* FP64: compute the true residual once the MINRES
+                             estimate |eta_j|/eta_0 <= check_factor*tol
+                             (default 10)                                         */
+} bltt_options;
+
+/* Per-solve report. */
+typedef struct {
+  int32_t iters_inner;    /* MINRES iterations (all inner sweeps in MIXED)        */
+  int32_t iters_outer;    /* refinement sweeps (MIXED), 1 for FP64                */
+  double true_relres;     /* ||Y(f - A u)||_2 / ||Y f||_2, computed in FP64       */
+  double setup_ms;        /* wall time of bltt_setup                              */
+  double solve_ms;        /* wall time of the bltt_pminres call                   */
+  double c0;              /* Assumption 1(ii) margin of the blocks                */
+} bltt_info;
+
+typedef struct bltt_handle bltt_handle;
+
+/*
+ * bltt_setup -- validate the blocks, check Assumption 1(ii) (Section 2,
+ * Proposition 1) and build the device tables the iteration needs: Laplacian
+ * eigenvalues mu_i of every sine mode, the DFTs of alpha^{j/N} p_j and
+ * alpha^{j/N} q_j that give the alpha-circulant eigenvalues
+ * lambda_i^{(k,alpha)} = sigma_k + mu_i rho_k (eq. (9)), the matvec spectra
+ * and the FFT twiddles.  Allocates the Krylov workspace for opt->precision
+ * (MIXED also allocates the FP64 refinement vectors).
+ *   blk    block description (N entries of p and q)
+ *   N      number of time steps (blocks); M must equal m[0]*...*m[dim-1]
+ *   alpha  in (0, 1]
+ *   opt    options or NULL
+ *   stream hipStream_t (void*) for all work of this handle
+ *   out    receives the new handle; untouched on error
+ * Errors: BLTT_EINVAL, BLTT_EUNSUPPORTED, BLTT_EASSUMPTION, BLTT_ENOMEM,
+ * BLTT_EHIP.
+ */
+int bltt_setup(const bltt_blocks *blk, int64_t N, int64_t M, double alpha,
+               const bltt_options *opt, void *stream, bltt_handle **out);
+
+/*
+ * bltt_pminres -- solve A u = f by preconditioned MINRES on Y A u = Y f with
+ * a zero initial guess.  Stops when ||Y(f - A u)||_2 / ||Y f||_2 <= tol.
+ *   f_dev   FP64 device vector of length N*M (not modified)
+ *   tol     relative residual target, > 0
+ *   maxit   iteration cap (>= 1); in MIXED it caps the total inner iterations
+ *   u_dev   FP64 device vector of length N*M receiving the solution; must
+ *           not overlap f_dev
+ *   iters   host, receives the number of MINRES iterations (may be NULL)
+ *   hist    host array of length maxit+1 or NULL; receives |eta_j|/eta_0, the
+ *           P^{-1}-norm residual estimate MINRES carries (hist[0] = 1); in
+ *           MIXED the inner histories are concatenated, each relative to its
+ *           own sweep's start
+ *   info    host, receives the report (may be NULL)
+ * f = 0 returns BLTT_OK with u = 0 and zero iterations.
+ * Errors: BLTT_EINVAL, BLTT_ENAN, BLTT_EBREAKDOWN, BLTT_EHIP; BLTT_NOCONV
+ * when maxit is reached.
+ */
+int bltt_pminres(bltt_handle *h, const double *f_dev, double tol, int32_t maxit,
+                 double *u_dev, int32_t *iters, double *hist, bltt_info *info);
+
+/*
+ * Step-level entry points: one application of a hot-path operator on device
+ * vectors of length N*M, in the precision given (BLTT_FP64: double*,
+ * BLTT_FP32: float*).  x_dev and y_dev must not overlap.  They use the
+ * handle's workspace for that precision (allocated on first use).
+ *
+ * bltt_apply_sym:     y = Y A x (Section 2, eq. (4); Section 5.1: FFT
+ *                     Toeplitz product along time plus the spatial stencil,
+ *                     then the time reversal).
+ * bltt_apply_precond: y = P_alpha^{-1} x = C^{-1/2} (C^{-1/2})^* x (Section
+ *                     5.1, Steps 1-3 twice: sine transform in space, per mode
+ *                     the alpha-scaled Fourier sandwich in time, inverse sine
+ *                     transform).
+ * bltt_apply_space:   y = (I_N (x) U) x, the orthonormal sine transform of
+ *                     every time slice (Steps 1 and 3 of Section 5.1).
+ * Errors: BLTT_EINVAL, BLTT_ENOMEM, BLTT_EHIP.
+ */
+int bltt_apply_sym(bltt_handle *h, int32_t precision, const void *x_dev, void *y_dev);
+int bltt_apply_precond(bltt_handle *h, int32_t precision, const void *x_dev, void *y_dev);
+int bltt_apply_space(bltt_handle *h, int32_t precision, const void *x_dev, void *y_dev);
+
+/* Release all device memory and tables of the handle (NULL is a no-op). */
+void bltt_destroy(bltt_handle *h);
+
+/* Static message for a status code. */
+const char *bltt_strerror(int code);
+
+/* Library version string. */
+const char *bltt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLTT_H */

@@ -1,0 +1,706 @@
+// C ABI of the PMINRES solver (see include/bltt.h): handle lifecycle, table
+// upload, the FP64 MINRES loop and the FP32-inside-FP64 refinement loop.
+//
+// Method: preconditioned MINRES (Paige-Saunders, in the Elman-Silvester-Wathen
+// form) on Y A u = Y f with P_alpha = |C_alpha| (Li, Lin, Hon, Wu, arXiv
+// 2307.07749, Sections 2-3 and 5.1).  Every vector operation runs in the HIP
+// kernels of this library; the host only sequences launches and reads back the
+// FP64 scalar state once per iteration.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "bltt.h"
+#include "host_tables.hpp"
+#include "launchers.hpp"
+
+using namespace bltt;
+
+namespace {
+
+template <typename T>
+struct DeviceTables {
+  cx<T>* tw_time = nullptr;
+  cx<T>* tw_dst[3] = {nullptr, nullptr, nullptr};
+  T* dinv = nullptr;
+  T* d2 = nullptr;
+  cx<T>* sigma = nullptr;
+  cx<T>* rho = nullptr;
+  T* mu = nullptr;
+  cx<T>* chat = nullptr;
+  cx<T>* shat = nullptr;
+  cx<T>* phi = nullptr;
+  bool ready = false;
+};
+
+template <typename T>
+struct Workspace {
+  T* Q = nullptr;  // matvec output / transform scratch
+  T* V[3] = {nullptr, nullptr, nullptr};
+  T* Z[2] = {nullptr, nullptr};
+  T* W[2] = {nullptr, nullptr};
+  T* X = nullptr;  // inner solution (FP32 refinement sweeps)
+  bool ready = false;
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+std::once_flag g_config_once;
+hipError_t g_config_err = hipSuccess;
+
+}  // namespace
+
+struct bltt_handle {
+  hipStream_t stream = nullptr;
+  int dim = 0;
+  int m[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int64_t N = 0, M = 0, n = 0;
+  double alpha = 1.0;
+  bltt_options opt{};
+  double c0 = 0.0;
+  std::vector<double> p, q;
+  int ptaps = 0, qtaps = 0;
+  DeviceTables<float> t32;
+  DeviceTables<double> t64;
+  Workspace<float> w32;
+  Workspace<double> w64;
+  double* R64 = nullptr;
+  double* partials = nullptr;
+  int64_t partials_cap = 0;
+  SolverState* state = nullptr;
+  SolverState* state_host = nullptr;
+  double* hist_dev = nullptr;
+  int64_t hist_cap = 0;
+  double* coef_one = nullptr;
+  double setup_ms = 0.0;
+  std::vector<void*> allocs;
+};
+
+#define HIPCHK(...)                        \
+  do {                                     \
+    hipError_t e_ = (__VA_ARGS__);         \
+    if (e_ != hipSuccess) return BLTT_EHIP; \
+  } while (0)
+
+namespace {
+
+template <typename T>
+int dalloc(bltt_handle* h, T** ptr, size_t count) {
+  void* p = nullptr;
+  if (hipMalloc(&p, count * sizeof(T) + 64) != hipSuccess) {
+    (void)hipGetLastError();
+    return BLTT_ENOMEM;
+  }
+  h->allocs.push_back(p);
+  *ptr = static_cast<T*>(p);
+  return BLTT_OK;
+}
+
+template <typename T, typename S>
+int upload(bltt_handle* h, T** dst, const std::vector<S>& src) {
+  std::vector<T> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+  int rc = dalloc(h, dst, tmp.size());
+  if (rc) return rc;
+  HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  return BLTT_OK;
+}
+
+template <typename T>
+int upload_c(bltt_handle* h, cx<T>** dst, const std::vector<host::cd>& src) {
+  std::vector<cx<T>> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = mkc<T>((T)src[i].real(), (T)src[i].imag());
+  int rc = dalloc(h, dst, tmp.size());
+  if (rc) return rc;
+  HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
+  return BLTT_OK;
+}
+
+template <typename T>
+DeviceTables<T>& tables(bltt_handle* h);
+template <>
+DeviceTables<float>& tables<float>(bltt_handle* h) { return h->t32; }
+template <>
+DeviceTables<double>& tables<double>(bltt_handle* h) { return h->t64; }
+template <typename T>
+Workspace<T>& workspace(bltt_handle* h);
+template <>
+Workspace<float>& workspace<float>(bltt_handle* h) { return h->w32; }
+template <>
+Workspace<double>& workspace<double>(bltt_handle* h) { return h->w64; }
+
+template <typename T>
+int build_tables(bltt_handle* h) {
+  DeviceTables<T>& t = tables<T>(h);
+  if (t.ready) return BLTT_OK;
+  int rc;
+  if ((rc = upload_c<T>(h, &t.tw_time, host::twiddles((int)h->N)))) return rc;
+  for (int d = 0; d < h->dim; ++d)
+    if ((rc = upload_c<T>(h, &t.tw_dst[d], host::twiddles(2 * (h->m[d] + 1))))) return rc;
+  if ((rc = upload<T>(h, &t.dinv, host::alpha_pow(h->N, h->alpha, -1.0)))) return rc;
+  if ((rc = upload<T>(h, &t.d2, host::alpha_pow(h->N, h->alpha, 2.0)))) return rc;
+  if ((rc = upload_c<T>(h, &t.sigma, host::alpha_spectrum(h->p, h->alpha)))) return rc;
+  if ((rc = upload_c<T>(h, &t.rho, host::alpha_spectrum(h->q, h->alpha)))) return rc;
+  if ((rc = upload<T>(h, &t.mu, host::lap_eigs(h->dim, h->m, h->h)))) return rc;
+  if ((rc = upload_c<T>(h, &t.chat, host::matvec_spectrum(h->p, false)))) return rc;
+  if ((rc = upload_c<T>(h, &t.shat, host::matvec_spectrum(h->p, true)))) return rc;
+  if ((rc = upload_c<T>(h, &t.phi, host::skew_phase(h->N)))) return rc;
+  t.ready = true;
+  return BLTT_OK;
+}
+
+template <typename T>
+int build_workspace(bltt_handle* h) {
+  Workspace<T>& w = workspace<T>(h);
+  if (w.ready) return BLTT_OK;
+  int rc;
+  const size_t n = (size_t)h->n;
+  if ((rc = dalloc(h, &w.Q, n))) return rc;
+  for (int i = 0; i < 3; ++i)
+    if ((rc = dalloc(h, &w.V[i], n))) return rc;
+  for (int i = 0; i < 2; ++i)
+    if ((rc = dalloc(h, &w.Z[i], n))) return rc;
+  for (int i = 0; i < 2; ++i)
+    if ((rc = dalloc(h, &w.W[i], n))) return rc;
+  if (sizeof(T) == 4)
+    if ((rc = dalloc(h, &w.X, n))) return rc;
+  w.ready = true;
+  return BLTT_OK;
+}
+
+Grid make_grid(const bltt_handle* h) {
+  Grid g;
+  g.dim = h->dim;
+  for (int d = 0; d < 3; ++d) {
+    g.m[d] = h->m[d];
+    g.inv_h2[d] = d < h->dim ? 1.0 / (h->h[d] * h->h[d]) : 0.0;
+  }
+  return g;
+}
+
+bool short_p(const bltt_handle* h) { return h->ptaps <= 8; }
+
+template <typename T>
+int64_t partials_needed(const bltt_handle* h) {
+  int64_t need = ew_blocks(h->n);
+  if (short_p(h)) {
+    const int64_t gx = (h->M + TPB_EW - 1) / TPB_EW;
+    const int64_t gy = ((h->N + 1) / 2 + 7) / 8;
+    need = std::max(need, gx * gy);
+  } else {
+    need = std::max(need, fft_blocks<T>((int)h->N, h->M));
+  }
+  need = std::max(need, fft_blocks<T>(2 * (h->m[0] + 1), h->n / h->m[0]));
+  return need;
+}
+
+// q = Y A z (MV_DOT, partial sums of <q, z>) or out = Y (fin - A z) (MV_RESID,
+// partial sums of the squared norm)
+template <typename T>
+int matvec(bltt_handle* h, int mode, const T* z, T* out, const T* fin, int64_t* np) {
+  DeviceTables<T>& t = tables<T>(h);
+  if (short_p(h)) {
+    ShortTables<T> tb;
+    for (int k = 0; k < 8; ++k) tb.p[k] = (T)(k < h->ptaps ? h->p[(size_t)k] : 0.0);
+    tb.ptaps = h->ptaps;
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
+    tb.qtaps = h->qtaps;
+    tb.grid = make_grid(h);
+    tb.N = (int)h->N;
+    tb.chunk = 8;
+    HIPCHK(launch_matvec_short<T>(mode, z, out, fin, h->M, tb, h->partials, np, h->stream));
+  } else {
+    MatvecTables<T> tb;
+    tb.tw = t.tw_time;
+    tb.chat = t.chat;
+    tb.shat = t.shat;
+    tb.phi = t.phi;
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
+    tb.qtaps = h->qtaps;
+    tb.grid = make_grid(h);
+    HIPCHK(launch_matvec_fft<T>((int)h->N, mode, z, out, fin, h->M, tb, h->partials, h->stream));
+    *np = fft_blocks<T>((int)h->N, h->M);
+  }
+  return BLTT_OK;
+}
+
+template <typename T>
+DstTables<T> dst_tables(bltt_handle* h, int d) {
+  DstTables<T> tb;
+  tb.tw = tables<T>(h).tw_dst[d];
+  tb.m = h->m[d];
+  tb.nrm = (T)(1.0 / std::sqrt(2.0 * (h->m[d] + 1)));
+  return tb;
+}
+
+// strided sine transforms along dimensions 1..dim-1 (in place on x)
+template <typename T>
+int space_strided(bltt_handle* h, T* x, bool reverse) {
+  for (int k = 1; k < h->dim; ++k) {
+    const int d = reverse ? h->dim - k : k;
+    int64_t S = 1;
+    for (int e = 0; e < d; ++e) S *= h->m[e];
+    const int64_t nlines = h->n / h->m[d];
+    HIPCHK(launch_dst_strided<T>(2 * (h->m[d] + 1), x, nlines, S, dst_tables<T>(h, d), h->stream));
+  }
+  return BLTT_OK;
+}
+
+// zout = P^{-1} vhat with vhat = coef[0] in + coef[1] v1 + coef[2] v2 (written to
+// vout when non-null); tmp is scratch and may equal `in`; partial sums of
+// <vdot, zout> are left in h->partials (count in *np).
+template <typename T>
+int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, const double* coef, T* tmp,
+            const T* vdot, T* zout, int64_t* np) {
+  int rc;
+  const int Lx = 2 * (h->m[0] + 1);
+  const int64_t nlx = h->n / h->m[0];
+  HIPCHK(launch_dst_x<T>(Lx, KIND_VUPD, in, v1, v2, vout, nullptr, tmp, nlx, dst_tables<T>(h, 0), coef, nullptr,
+                         h->stream));
+  if ((rc = space_strided<T>(h, tmp, false))) return rc;
+  TimeTables<T> tt;
+  DeviceTables<T>& t = tables<T>(h);
+  tt.tw = t.tw_time;
+  tt.dinv = t.dinv;
+  tt.d2 = t.d2;
+  tt.sigma = t.sigma;
+  tt.rho = t.rho;
+  tt.mu = t.mu;
+  HIPCHK(launch_time_prec<T>((int)h->N, tmp, h->M, tt, h->stream));
+  if ((rc = space_strided<T>(h, tmp, true))) return rc;
+  HIPCHK(launch_dst_x<T>(Lx, KIND_DOT, tmp, nullptr, nullptr, nullptr, vdot, zout, nlx, dst_tables<T>(h, 0), coef,
+                         h->partials, h->stream));
+  *np = fft_blocks<T>(Lx, nlx);
+  return BLTT_OK;
+}
+
+int scalar(bltt_handle* h, int phase, int64_t np, double* hist) {
+  HIPCHK(launch_scalar(phase, h->state, h->partials, np, hist, h->stream));
+  return BLTT_OK;
+}
+
+int read_state(bltt_handle* h) {
+  HIPCHK(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return BLTT_OK;
+}
+
+int ensure_hist(bltt_handle* h, int64_t need) {
+  if (h->hist_cap >= need) return BLTT_OK;
+  double* p = nullptr;
+  int rc = dalloc(h, &p, (size_t)need);
+  if (rc) return rc;
+  h->hist_dev = p;
+  h->hist_cap = need;
+  return BLTT_OK;
+}
+
+struct CoreResult {
+  int iters = 0;
+  int status = 0;  // BLTT_OK / BLTT_NOCONV / error
+  double relres = -1.0;
+};
+
+// MINRES on K x = b, b already in ws.V[0]; X must be zero on entry.
+// Stops when |eta_j|/eta_0 <= eta_tol, confirmed (when f_dev != nullptr, FP64
+// only) by the explicit residual ||Y(f - A x)|| <= tol * bnorm.
+template <typename T, typename TX>
+int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* f_dev, double tol, double bnorm,
+                double* hist_host, CoreResult* res) {
+  Workspace<T>& ws = workspace<T>(h);
+  hipStream_t s = h->stream;
+  int rc;
+  int64_t np = 0;
+  T* Vc = ws.V[0];
+  T* Vp = ws.V[1];
+  T* Vn = ws.V[2];
+  T* Zc = ws.Z[0];
+  T* Zn = ws.Z[1];
+  T* Wa = ws.W[0];
+  T* Wb = ws.W[1];
+  HIPCHK(launch_fill<T>(Wa, h->n, T(0), s));
+  HIPCHK(launch_fill<T>(Wb, h->n, T(0), s));
+  if ((rc = ensure_hist(h, (int64_t)maxit + 2))) return rc;
+  // z_1 = P^{-1} b, beta_1 = sqrt(<b, z_1>)
+  if ((rc = precond<T>(h, Vc, nullptr, nullptr, nullptr, h->coef_one, ws.Q, Vc, Zc, &np))) return rc;
+  if ((rc = scalar(h, SC_START, np, h->hist_dev))) return rc;
+  if ((rc = read_state(h))) return rc;
+  if (h->state_host->status == -3) return BLTT_ENAN;
+  if (h->state_host->status == -4) return BLTT_EBREAKDOWN;
+  const double* coef_v = h->state->coef_v;
+  const double* coef_w = h->state->coef_w;
+  res->status = BLTT_NOCONV;
+  int j = 0;
+  for (j = 1; j <= maxit; ++j) {
+    if ((rc = matvec<T>(h, MV_DOT, Zc, ws.Q, nullptr, &np))) return rc;
+    if ((rc = scalar(h, SC_DELTA, np, nullptr))) return rc;
+    if ((rc = precond<T>(h, ws.Q, Vc, j > 1 ? Vp : nullptr, Vn, coef_v, ws.Q, Vn, Zn, &np))) return rc;
+    if ((rc = scalar(h, SC_BETA, np, h->hist_dev))) return rc;
+    HIPCHK(launch_wx<T, TX>(Zc, Wa, Wb, X, h->n, coef_w, s));
+    {
+      T* t = Vp;
+      Vp = Vc;
+      Vc = Vn;
+      Vn = t;
+      std::swap(Zc, Zn);
+      std::swap(Wa, Wb);
+    }
+    if ((rc = read_state(h))) return rc;
+    const SolverState& st = *h->state_host;
+    if (st.status == -3) return BLTT_ENAN;
+    if (st.status == -4) return BLTT_EBREAKDOWN;
+    const double eta_rel = std::fabs(st.eta) / st.eta0;
+    if (eta_rel <= eta_tol || st.status == 1) {
+      if (f_dev) {
+        if constexpr (sizeof(TX) == 8 && sizeof(T) == 8) {
+          if ((rc = matvec<double>(h, MV_RESID, (const double*)X, (double*)ws.Q, f_dev, &np))) return rc;
+          if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+          if ((rc = read_state(h))) return rc;
+          res->relres = std::sqrt(h->state_host->norm2) / bnorm;
+          if (!(res->relres == res->relres)) return BLTT_ENAN;
+          if (res->relres <= tol || st.status == 1) {
+            res->status = BLTT_OK;
+            break;
+          }
+        }
+      } else {
+        res->status = BLTT_OK;
+        break;
+      }
+    }
+  }
+  res->iters = j > maxit ? maxit : j;
+  if (hist_host) {
+    HIPCHK(hipMemcpy(hist_host, h->hist_dev, sizeof(double) * (size_t)(res->iters + 1), hipMemcpyDeviceToHost));
+  }
+  return BLTT_OK;
+}
+
+bool overlaps(const void* a, const void* b, int64_t bytes) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + bytes && pb < pa + bytes;
+}
+
+int check_power(int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* bltt_version(void) { return "bltt-mi355x 0.1"; }
+
+const char* bltt_strerror(int code) {
+  switch (code) {
+    case BLTT_OK: return "ok";
+    case BLTT_NOCONV: return "iteration limit reached before the tolerance";
+    case BLTT_EINVAL: return "invalid argument";
+    case BLTT_EASSUMPTION: return "blocks violate Assumption 1(ii): preconditioner may be singular";
+    case BLTT_ENAN: return "non-finite value in input or iteration";
+    case BLTT_EBREAKDOWN: return "preconditioner not positive definite in floating point";
+    case BLTT_ENOMEM: return "device allocation failed";
+    case BLTT_EHIP: return "HIP runtime error";
+    case BLTT_EUNSUPPORTED: return "size or block structure not supported";
+  }
+  return "unknown status";
+}
+
+void bltt_destroy(bltt_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->state_host) (void)hipHostFree(h->state_host);
+  delete h;
+}
+
+int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const bltt_options* opt, void* stream,
+               bltt_handle** out) {
+  const double t0 = now_ms();
+  if (!blk || !out || !blk->p || !blk->q) return BLTT_EINVAL;
+  if (blk->dim < 1 || blk->dim > 3 || N < 1 || M < 1) return BLTT_EINVAL;
+  if (!(alpha > 0.0 && alpha <= 1.0)) return BLTT_EINVAL;
+  int64_t Mp = 1;
+  for (int d = 0; d < blk->dim; ++d) {
+    if (blk->m[d] < 1 || !(blk->h[d] > 0.0) || !std::isfinite(blk->h[d])) return BLTT_EINVAL;
+    Mp *= blk->m[d];
+  }
+  if (Mp != M) return BLTT_EINVAL;
+  for (int64_t k = 0; k < N; ++k)
+    if (!std::isfinite(blk->p[k]) || !std::isfinite(blk->q[k])) return BLTT_EINVAL;
+  if (opt) {
+    if (opt->precision != BLTT_FP64 && opt->precision != BLTT_MIXED) return BLTT_EINVAL;
+  }
+  if (!check_power(N, 2, 2048)) return BLTT_EUNSUPPORTED;
+  for (int d = 0; d < blk->dim; ++d)
+    if (!check_power(2 * ((int64_t)blk->m[d] + 1), 4, 2048)) return BLTT_EUNSUPPORTED;
+  int qtaps = 0, ptaps = 0;
+  for (int64_t k = 0; k < N; ++k) {
+    if (blk->q[k] != 0.0) qtaps = (int)k + 1;
+    if (blk->p[k] != 0.0) ptaps = (int)k + 1;
+  }
+  if (qtaps > 4) return BLTT_EUNSUPPORTED;
+  if (ptaps == 0 && qtaps == 0) return BLTT_EASSUMPTION;
+
+  bltt_handle* h = new (std::nothrow) bltt_handle();
+  if (!h) return BLTT_ENOMEM;
+  h->stream = (hipStream_t)stream;
+  h->dim = blk->dim;
+  for (int d = 0; d < 3; ++d) {
+    h->m[d] = d < blk->dim ? blk->m[d] : 1;
+    h->h[d] = d < blk->dim ? blk->h[d] : 1.0;
+  }
+  h->N = N;
+  h->M = M;
+  h->n = N * M;
+  h->alpha = alpha;
+  h->p.assign(blk->p, blk->p + N);
+  h->q.assign(blk->q, blk->q + N);
+  h->ptaps = ptaps;
+  h->qtaps = qtaps;
+  h->opt.precision = BLTT_FP64;
+  h->opt.inner_tol = 1e-4;
+  h->opt.max_refine = 20;
+  h->opt.check_factor = 10.0;
+  if (opt) {
+    h->opt.precision = opt->precision;
+    if (opt->inner_tol > 0.0) h->opt.inner_tol = opt->inner_tol;
+    if (opt->max_refine > 0) h->opt.max_refine = opt->max_refine;
+    if (opt->check_factor >= 1.0) h->opt.check_factor = opt->check_factor;
+  }
+  // Assumption 1(ii) (Proposition 1)
+  double mu_min = 0.0, mu_max = 0.0;
+  for (int d = 0; d < h->dim; ++d) {
+    const std::vector<double> e = host::lap_eigs_1d(h->m[d], h->h[d]);
+    mu_min += e.front();
+    mu_max += e.back();
+  }
+  h->c0 = host::assumption_margin(h->p, h->q, mu_min, mu_max);
+  if (!(h->c0 > 0.0)) {
+    delete h;
+    return BLTT_EASSUMPTION;
+  }
+
+  std::call_once(g_config_once, [] { g_config_err = configure_kernels(); });
+  if (g_config_err != hipSuccess) {
+    delete h;
+    return BLTT_EHIP;
+  }
+
+  int rc = BLTT_OK;
+  auto fail = [&](int code) {
+    bltt_destroy(h);
+    return code;
+  };
+  h->partials_cap = std::max(partials_needed<float>(h), partials_needed<double>(h));
+  if ((rc = dalloc(h, &h->partials, (size_t)h->partials_cap))) return fail(rc);
+  if ((rc = dalloc(h, &h->state, 1))) return fail(rc);
+  if (hipHostMalloc((void**)&h->state_host, sizeof(SolverState), hipHostMallocDefault) != hipSuccess)
+    return fail(BLTT_ENOMEM);
+  std::memset(h->state_host, 0, sizeof(SolverState));
+  if (hipMemcpy(h->state, h->state_host, sizeof(SolverState), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(BLTT_EHIP);
+  {
+    std::vector<double> one = {1.0, 0.0, 0.0, 0.0};
+    if ((rc = upload<double>(h, &h->coef_one, one))) return fail(rc);
+  }
+  if ((rc = build_tables<double>(h))) return fail(rc);
+  if (h->opt.precision == BLTT_MIXED) {
+    if ((rc = build_tables<float>(h))) return fail(rc);
+    if ((rc = build_workspace<float>(h))) return fail(rc);
+    if ((rc = dalloc(h, &h->R64, (size_t)h->n))) return fail(rc);
+  } else {
+    if ((rc = build_workspace<double>(h))) return fail(rc);
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(BLTT_EHIP);
+  h->setup_ms = now_ms() - t0;
+  *out = h;
+  return BLTT_OK;
+}
+
+int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit, double* u_dev, int32_t* iters,
+                 double* hist, bltt_info* info) {
+  const double t0 = now_ms();
+  if (!h || !f_dev || !u_dev || !(tol > 0.0) || maxit < 1) return BLTT_EINVAL;
+  if (overlaps(f_dev, u_dev, h->n * (int64_t)sizeof(double))) return BLTT_EINVAL;
+  hipStream_t s = h->stream;
+  int rc;
+  int64_t np = 0;
+  HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
+  int total_iters = 0, outer = 0;
+  double relres = 0.0;
+  int status = BLTT_OK;
+
+  if (h->opt.precision == BLTT_FP64) {
+    Workspace<double>& ws = h->w64;
+    // b = Y f into V[0]
+    HIPCHK(launch_rhs<double>(f_dev, ws.V[0], h->N, h->M, 1.0, h->partials, &np, s));
+    if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+    if ((rc = read_state(h))) return rc;
+    const double bn2 = h->state_host->norm2;
+    if (!std::isfinite(bn2)) return BLTT_ENAN;
+    if (bn2 == 0.0) {
+      if (iters) *iters = 0;
+      if (hist) hist[0] = 1.0;
+      if (info) {
+        info->iters_inner = 0;
+        info->iters_outer = 0;
+        info->true_relres = 0.0;
+        info->setup_ms = h->setup_ms;
+        info->solve_ms = now_ms() - t0;
+        info->c0 = h->c0;
+      }
+      HIPCHK(hipStreamSynchronize(s));
+      return BLTT_OK;
+    }
+    const double bnorm = std::sqrt(bn2);
+    CoreResult cr;
+    rc = minres_core<double, double>(h, u_dev, maxit, h->opt.check_factor * tol, f_dev, tol, bnorm, hist, &cr);
+    if (rc) return rc;
+    total_iters = cr.iters;
+    outer = 1;
+    status = cr.status;
+    relres = cr.relres;
+    if (relres < 0.0) {
+      if ((rc = matvec<double>(h, MV_RESID, u_dev, ws.Q, f_dev, &np))) return rc;
+      if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+      if ((rc = read_state(h))) return rc;
+      relres = std::sqrt(h->state_host->norm2) / bnorm;
+    }
+  } else {
+    // FP64 refinement around FP32 MINRES sweeps
+    Workspace<float>& ws = h->w32;
+    HIPCHK(launch_rhs<double>(f_dev, h->R64, h->N, h->M, 1.0, h->partials, &np, s));
+    if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+    if ((rc = read_state(h))) return rc;
+    const double bn2 = h->state_host->norm2;
+    if (!std::isfinite(bn2)) return BLTT_ENAN;
+    const double bnorm = std::sqrt(bn2);
+    double rnorm = bnorm;
+    status = BLTT_NOCONV;
+    if (bn2 == 0.0) {
+      status = BLTT_OK;
+      relres = 0.0;
+    }
+    if (hist) hist[0] = 1.0;
+    int hist_pos = 0;
+    std::vector<double> hbuf;
+    while (status != BLTT_OK) {
+      relres = rnorm / bnorm;
+      if (relres <= tol) {
+        status = BLTT_OK;
+        break;
+      }
+      if (outer >= h->opt.max_refine || total_iters >= maxit) break;
+      // inner right-hand side r / ||r|| in FP32 (state->rscale = ||r||)
+      HIPCHK(launch_scale_cast<double, float>(h->R64, ws.V[0], h->n, &h->state->rscale, 1, s));
+      HIPCHK(launch_fill<float>(ws.X, h->n, 0.0f, s));
+      CoreResult cr;
+      const int left = maxit - total_iters;
+      hbuf.assign((size_t)left + 2, 0.0);
+      rc = minres_core<float, float>(h, ws.X, left, h->opt.inner_tol, nullptr, 0.0, 1.0, hbuf.data(), &cr);
+      if (rc) return rc;
+      if (hist) {
+        for (int k = 1; k <= cr.iters; ++k) hist[hist_pos + k] = hbuf[(size_t)k];
+      }
+      hist_pos += cr.iters;
+      total_iters += cr.iters;
+      outer += 1;
+      // u += ||r|| d, then r = Y(f - A u) in FP64
+      HIPCHK(launch_axpy64<float>(u_dev, ws.X, h->n, &h->state->rscale, s));
+      if ((rc = matvec<double>(h, MV_RESID, u_dev, h->R64, f_dev, &np))) return rc;
+      if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+      if ((rc = read_state(h))) return rc;
+      rnorm = std::sqrt(h->state_host->norm2);
+      if (!std::isfinite(rnorm)) return BLTT_ENAN;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (iters) *iters = total_iters;
+  if (info) {
+    info->iters_inner = total_iters;
+    info->iters_outer = outer;
+    info->true_relres = relres;
+    info->setup_ms = h->setup_ms;
+    info->solve_ms = now_ms() - t0;
+    info->c0 = h->c0;
+  }
+  return status;
+}
+
+static int step_prepare(bltt_handle* h, int32_t precision) {
+  int rc;
+  if (precision == BLTT_FP64) {
+    if ((rc = build_tables<double>(h))) return rc;
+    return build_workspace<double>(h);
+  }
+  if (precision == BLTT_FP32) {
+    if ((rc = build_tables<float>(h))) return rc;
+    return build_workspace<float>(h);
+  }
+  return BLTT_EINVAL;
+}
+
+int bltt_apply_sym(bltt_handle* h, int32_t precision, const void* x_dev, void* y_dev) {
+  if (!h || !x_dev || !y_dev) return BLTT_EINVAL;
+  const int64_t bytes = h->n * (precision == BLTT_FP64 ? 8 : 4);
+  if (overlaps(x_dev, y_dev, bytes)) return BLTT_EINVAL;
+  int rc = step_prepare(h, precision);
+  if (rc) return rc;
+  int64_t np = 0;
+  if (precision == BLTT_FP64)
+    rc = matvec<double>(h, MV_DOT, (const double*)x_dev, (double*)y_dev, nullptr, &np);
+  else
+    rc = matvec<float>(h, MV_DOT, (const float*)x_dev, (float*)y_dev, nullptr, &np);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return BLTT_OK;
+}
+
+int bltt_apply_precond(bltt_handle* h, int32_t precision, const void* x_dev, void* y_dev) {
+  if (!h || !x_dev || !y_dev) return BLTT_EINVAL;
+  const int64_t bytes = h->n * (precision == BLTT_FP64 ? 8 : 4);
+  if (overlaps(x_dev, y_dev, bytes)) return BLTT_EINVAL;
+  int rc = step_prepare(h, precision);
+  if (rc) return rc;
+  int64_t np = 0;
+  if (precision == BLTT_FP64)
+    rc = precond<double>(h, (const double*)x_dev, nullptr, nullptr, nullptr, h->coef_one, h->w64.Q,
+                         (const double*)x_dev, (double*)y_dev, &np);
+  else
+    rc = precond<float>(h, (const float*)x_dev, nullptr, nullptr, nullptr, h->coef_one, h->w32.Q,
+                        (const float*)x_dev, (float*)y_dev, &np);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return BLTT_OK;
+}
+
+int bltt_apply_space(bltt_handle* h, int32_t precision, const void* x_dev, void* y_dev) {
+  if (!h || !x_dev || !y_dev) return BLTT_EINVAL;
+  const int64_t bytes = h->n * (precision == BLTT_FP64 ? 8 : 4);
+  if (overlaps(x_dev, y_dev, bytes)) return BLTT_EINVAL;
+  int rc = step_prepare(h, precision);
+  if (rc) return rc;
+  const int Lx = 2 * (h->m[0] + 1);
+  const int64_t nlx = h->n / h->m[0];
+  if (precision == BLTT_FP64) {
+    HIPCHK(launch_dst_x<double>(Lx, KIND_VUPD, (const double*)x_dev, nullptr, nullptr, nullptr, nullptr,
+                                (double*)y_dev, nlx, dst_tables<double>(h, 0), h->coef_one, nullptr, h->stream));
+    if ((rc = space_strided<double>(h, (double*)y_dev, false))) return rc;
+  } else {
+    HIPCHK(launch_dst_x<float>(Lx, KIND_VUPD, (const float*)x_dev, nullptr, nullptr, nullptr, nullptr,
+                               (float*)y_dev, nlx, dst_tables<float>(h, 0), h->coef_one, nullptr, h->stream));
+    if ((rc = space_strided<float>(h, (float*)y_dev, false))) return rc;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return BLTT_OK;
+}
+
+}  // extern "C"

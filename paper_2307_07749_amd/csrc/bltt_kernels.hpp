@@ -1,0 +1,639 @@
+// Kernel bodies of the PMINRES hot path (Li, Lin, Hon, Wu, arXiv 2307.07749).
+//
+// Every body is a __host__ __device__ template taking a context `Ctx` that
+// supplies the thread/block indices and the workgroup barrier, so the HIP
+// launch wrappers and a CPU workgroup emulator run the same code.
+//
+// Vector layout: time-major, element (n, i) at n*M + i, i = x + m0*(y + m1*z).
+//
+// Hot-path steps per MINRES iteration (one pass = one kernel):
+//   matvec      q = Y A z   (Section 2 eq. (4); Section 5.1: Toeplitz product
+//               along time by FFT, spatial stencil of the blocks, time
+//               reversal) + the partial sums of <q, z>
+//   dst_x_vupd  vhat = cq q + cv v_j + cvp v_{j-1} (Lanczos three-term step)
+//               fused with the sine transform along x (Step 1 of Section 5.1)
+//   dst_strided sine transform along y (and z) of every time slice
+//   time_prec   per sine mode, the two alpha-circulant half-solves of Section
+//               5.1: D^{-1} F Lambda^{-1/2} F^* D^2 F conj(Lambda)^{-1/2} F^* D^{-1}
+//   dst_strided inverse sine transform along (z and) y
+//   dst_x_dot   inverse sine transform along x (Step 3) + partial sums of
+//               <vhat, zhat>
+//   wx_update   MINRES direction and iterate update
+// The orthonormal DST-I is symmetric and its own inverse, so forward and
+// inverse sine passes are the same kernel.
+#pragma once
+
+#include "fft_engine.hpp"
+
+namespace bltt {
+
+template <typename T>
+constexpr int tpb_fft() { return sizeof(T) == 4 ? 512 : 256; }
+constexpr int TPB_EW = 256;  // elementwise / streaming kernels
+
+// ---------------------------------------------------------------------------
+// workgroup sum of one double per thread, result valid in thread 0
+// ---------------------------------------------------------------------------
+template <int TPB, class Ctx>
+BLTT_HD double block_sum(Ctx& ctx, double* red, double v) {
+  const int tid = ctx.tid;
+  ctx.sync();
+  red[tid] = v;
+  ctx.sync();
+#pragma unroll
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    ctx.sync();
+  }
+  return red[0];
+}
+
+// ---------------------------------------------------------------------------
+// spatial stencil L_h = -Delta_h, zero Dirichlet (Section 5)
+// ---------------------------------------------------------------------------
+struct Grid {
+  int dim;
+  int m[3];
+  double inv_h2[3];
+};
+
+template <typename T>
+BLTT_HD T lap_at(const T* __restrict__ z, int64_t base, int64_t i, const Grid& gr) {
+  // base = n*M, i = spatial index
+  const T zc = z[base + i];
+  T acc = T(0);
+  int64_t rest = i;
+  int64_t stride = 1;
+  for (int d = 0; d < gr.dim; ++d) {
+    const int md = gr.m[d];
+    const int coord = (int)(rest % md);
+    rest /= md;
+    T s = T(2) * zc;
+    if (coord > 0) s -= z[base + i - stride];
+    if (coord < md - 1) s -= z[base + i + stride];
+    acc += T(gr.inv_h2[d]) * s;
+    stride *= md;
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// matvec, FFT form: (A z)_n = sum_{k<=n} p_k z_{n-k} + sum_{k<qtaps} q_k L_h z_{n-k}
+// The lower-triangular Toeplitz product is (C + S)/2 with C the circulant and
+// S the skew-circulant with first column p:  C z = ifft(fft(p) fft(z)) and
+// S z = conj(phi) ifft(fft(phi p) fft(phi z)), phi_n = exp(i pi n/N).
+// Two spatial points are packed as the real and imaginary part of one complex
+// line (every operation is complex-linear with a real kernel).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MatvecTables {
+  const cx<T>* tw;     // length N: exp(-2 pi i k/N)
+  const cx<T>* chat;   // length N: fft(p)/(2N)
+  const cx<T>* shat;   // length N: fft(phi p)/(2N)
+  const cx<T>* phi;    // length N: exp(i pi n/N)
+  T q[4];
+  int qtaps;
+  Grid grid;
+};
+
+enum { MV_DOT = 0, MV_RESID = 1 };
+
+template <typename T, int L, int MODE, class Ctx>
+BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict__ z,
+                             T* __restrict__ out, const T* __restrict__ fin, int64_t M,
+                             const MatvecTables<T>& tb, double* __restrict__ partials) {
+  constexpr int TPB = tpb_fft<T>();
+  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
+  using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
+  constexpr int N = L;
+  const int tid = ctx.tid, c = tid % NL, g = tid / NL;
+  const int64_t ia = (int64_t)ctx.bid * (2 * NL) + 2 * c, ib = ia + 1;
+  const bool va = ia < M, vb = ib < M;
+
+  cx<T> v[V], acc[V];
+  // circulant part
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int64_t n = g + t * s0;
+    v[t] = mkc<T>(va ? z[n * M + ia] : T(0), vb ? z[n * M + ib] : T(0));
+  }
+  F::forward(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+  for (int w = 0; w < V / F::RL; ++w)
+#pragma unroll
+    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.chat[F::freq(g, w, u)];
+  F::inverse(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+  for (int t = 0; t < V; ++t) acc[t] = v[t];
+  // skew-circulant part
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int64_t n = g + t * s0;
+    v[t] = mkc<T>(va ? z[n * M + ia] : T(0), vb ? z[n * M + ib] : T(0)) * tb.phi[n];
+  }
+  F::forward(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+  for (int w = 0; w < V / F::RL; ++w)
+#pragma unroll
+    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.shat[F::freq(g, w, u)];
+  F::inverse(ctx, v, lds, c, g, tb.tw);
+
+  double part = 0.0;
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int64_t n = g + t * s0;
+    cx<T> y = acc[t] + v[t] * conjg(tb.phi[n]);
+    T ya = y.re, yb = y.im;
+    for (int k = 0; k < tb.qtaps; ++k) {
+      if (k > n) break;
+      const int64_t base = (n - k) * M;
+      if (va) ya += tb.q[k] * lap_at(z, base, ia, tb.grid);
+      if (vb) yb += tb.q[k] * lap_at(z, base, ib, tb.grid);
+    }
+    const int64_t nr = (int64_t)(N - 1) - n;
+    if (MODE == MV_DOT) {
+      if (va) {
+        out[nr * M + ia] = ya;
+        part += (double)ya * (double)z[nr * M + ia];
+      }
+      if (vb) {
+        out[nr * M + ib] = yb;
+        part += (double)yb * (double)z[nr * M + ib];
+      }
+    } else {
+      if (va) {
+        const T r = fin[n * M + ia] - ya;
+        out[nr * M + ia] = r;
+        part += (double)r * (double)r;
+      }
+      if (vb) {
+        const T r = fin[n * M + ib] - yb;
+        out[nr * M + ib] = r;
+        part += (double)r * (double)r;
+      }
+    }
+  }
+  const double s = block_sum<TPB>(ctx, red, part);
+  if (tid == 0) partials[ctx.bid] = s;
+}
+
+// matvec, direct form for short p (ptaps <= 8): one thread per spatial point
+// and a chunk of time steps together with their mirrors N-1-n, so the dot
+// product <Y A z, z> needs no second pass over z.
+template <typename T>
+struct ShortTables {
+  T p[8];
+  int ptaps;
+  T q[4];
+  int qtaps;
+  Grid grid;
+  int N;
+  int chunk;  // time steps per thread (from the first half)
+};
+
+template <typename T, int MODE, class Ctx>
+BLTT_HD void matvec_short_body(Ctx& ctx, double* red, const T* __restrict__ z, T* __restrict__ out,
+                               const T* __restrict__ fin, int64_t M, const ShortTables<T>& tb,
+                               double* __restrict__ partials) {
+  const int tid = ctx.tid;
+  const int64_t i = (int64_t)ctx.bid * TPB_EW + tid;
+  const int N = tb.N;
+  const int half = (N + 1) / 2;
+  const int n0 = ctx.bid_y * tb.chunk;
+  double part = 0.0;
+  if (i < M) {
+    for (int nn = n0; nn < n0 + tb.chunk && nn < half; ++nn) {
+      for (int side = 0; side < 2; ++side) {
+        const int n = side == 0 ? nn : N - 1 - nn;
+        if (side == 1 && n == nn) break;  // odd N: middle step once
+        T y = T(0);
+        for (int k = 0; k < tb.ptaps && k <= n; ++k) y += tb.p[k] * z[(int64_t)(n - k) * M + i];
+        for (int k = 0; k < tb.qtaps && k <= n; ++k) y += tb.q[k] * lap_at(z, (int64_t)(n - k) * M, i, tb.grid);
+        const int64_t nr = (int64_t)(N - 1 - n);
+        if (MODE == MV_DOT) {
+          out[nr * M + i] = y;
+          part += (double)y * (double)z[nr * M + i];
+        } else {
+          const T r = fin[(int64_t)n * M + i] - y;
+          out[nr * M + i] = r;
+          part += (double)r * (double)r;
+        }
+      }
+    }
+  }
+  const double s = block_sum<TPB_EW>(ctx, red, part);
+  if (tid == 0) partials[(int64_t)ctx.bid_y * ctx.nbx + ctx.bid] = s;
+}
+
+// ---------------------------------------------------------------------------
+// sine transforms.  DST-I of length m = L/2 - 1 through one complex FFT of
+// length L = 2(m+1) shared by two lines a, b: with e the odd extension
+// (e_0 = e_{m+1} = 0, e_p = x_{p-1}, e_{L-p} = -x_{p-1}), fft(e_a + i e_b)_k =
+// -2i S_a(k) + 2 S_b(k), S(k) = sum_j x_j sin(pi j k/(m+1)).  The orthonormal
+// transform is y_{k-1} = sqrt(2/(m+1)) S(k).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DstTables {
+  const cx<T>* tw;  // length L
+  int m;            // line length
+  T nrm;            // 1/sqrt(L) = sqrt(2/(m+1))/2
+};
+
+// Lines along x (contiguous).  KIND_VUPD: input is the Lanczos update
+// cq*Q + cv*V1 + cvp*V2 (optionally written to vout) -> out = U_x(input).
+// KIND_DOT: out = U_x(in) and partial sums of <vdot, out>.
+// `out` may alias `in` (each workgroup owns whole lines and reads them before
+// its first barrier); vout never aliases in, v1 or v2.
+enum { KIND_VUPD = 0, KIND_DOT = 1 };
+
+template <typename T, int L, int KIND, class Ctx>
+BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
+                        const T* __restrict__ v1, const T* __restrict__ v2, T* __restrict__ vout,
+                        const T* __restrict__ vdot, T* out, int64_t nlines,
+                        const DstTables<T>& tb, const double* __restrict__ coef,
+                        double* __restrict__ partials) {
+  constexpr int TPB = tpb_fft<T>();
+  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
+  using F = LineFft<T, L, NL, false, LAST_LINEAR>;
+  const int m = L / 2 - 1;
+  const int tid = ctx.tid, c = tid / G, g = tid % G;
+  const int64_t la = (int64_t)ctx.bid * (2 * NL) + 2 * c, lb = la + 1;
+  const bool va = la < nlines, vb = lb < nlines;
+  T cq = T(1), cv = T(0), cvp = T(0);
+  if (KIND == KIND_VUPD) {
+    cq = T(coef[0]);
+    cv = T(coef[1]);
+    cvp = T(coef[2]);
+  }
+  cx<T> v[V];
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int p = g + t * s0;
+    T a = T(0), b = T(0);
+    if (p != 0 && p != m + 1) {
+      const bool lo = p <= m;
+      const int xi = lo ? p - 1 : L - 1 - p;
+      if (va) {
+        const int64_t e = la * m + xi;
+        a = cq * in[e];
+        if (KIND == KIND_VUPD) {
+          if (v1) a += cv * v1[e];
+          if (v2) a += cvp * v2[e];
+          if (vout && lo) vout[e] = a;  // vout never aliases in, v1, v2
+        }
+      }
+      if (vb) {
+        const int64_t e = lb * m + xi;
+        b = cq * in[e];
+        if (KIND == KIND_VUPD) {
+          if (v1) b += cv * v1[e];
+          if (v2) b += cvp * v2[e];
+          if (vout && lo) vout[e] = b;
+        }
+      }
+      if (!lo) {
+        a = -a;
+        b = -b;
+      }
+    }
+    v[t] = mkc<T>(a, b);
+  }
+  F::forward(ctx, v, lds, c, g, tb.tw);
+  double part = 0.0;
+#pragma unroll
+  for (int w = 0; w < V / F::RL; ++w) {
+#pragma unroll
+    for (int u = 0; u < F::RL; ++u) {
+      const int k = F::freq(g, w, u);
+      if (k >= 1 && k <= m) {
+        const cx<T> zk = v[w * F::RL + u];
+        const T ya = -zk.im * tb.nrm, yb = zk.re * tb.nrm;
+        if (va) {
+          out[la * m + k - 1] = ya;
+          if (KIND == KIND_DOT) part += (double)ya * (double)vdot[la * m + k - 1];
+        }
+        if (vb) {
+          out[lb * m + k - 1] = yb;
+          if (KIND == KIND_DOT) part += (double)yb * (double)vdot[lb * m + k - 1];
+        }
+      }
+    }
+  }
+  if (KIND == KIND_DOT) {
+    const double s = block_sum<TPB>(ctx, red, part);
+    if (tid == 0) partials[ctx.bid] = s;
+  }
+}
+
+// Lines along a strided dimension: line l has elements at
+// (l / S) * S * m + (l % S) + j * S, j < m.  In place.
+template <typename T, int L, class Ctx>
+BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t nlines, int64_t S,
+                              const DstTables<T>& tb) {
+  constexpr int TPB = tpb_fft<T>();
+  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
+  using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
+  const int m = L / 2 - 1;
+  const int tid = ctx.tid, c = tid % NL, g = tid / NL;
+  const int64_t la = (int64_t)ctx.bid * (2 * NL) + 2 * c, lb = la + 1;
+  const bool va = la < nlines, vb = lb < nlines;
+  const int64_t basea = (la / S) * S * m + (la % S);
+  const int64_t baseb = (lb / S) * S * m + (lb % S);
+  cx<T> v[V];
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int p = g + t * s0;
+    T a = T(0), b = T(0);
+    if (p != 0 && p != m + 1) {
+      const bool lo = p <= m;
+      const int64_t xi = lo ? p - 1 : L - 1 - p;
+      if (va) a = x[basea + xi * S];
+      if (vb) b = x[baseb + xi * S];
+      if (!lo) {
+        a = -a;
+        b = -b;
+      }
+    }
+    v[t] = mkc<T>(a, b);
+  }
+  F::forward(ctx, v, lds, c, g, tb.tw);
+  // all reads of this workgroup's lines happened before the barriers inside forward()
+#pragma unroll
+  for (int w = 0; w < V / F::RL; ++w) {
+#pragma unroll
+    for (int u = 0; u < F::RL; ++u) {
+      const int k = F::freq(g, w, u);
+      if (k >= 1 && k <= m) {
+        const cx<T> zk = v[w * F::RL + u];
+        if (va) x[basea + (int64_t)(k - 1) * S] = -zk.im * tb.nrm;
+        if (vb) x[baseb + (int64_t)(k - 1) * S] = zk.re * tb.nrm;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// time pass of the preconditioner, per sine mode i (Section 5.1 Step 2, both
+// halves):  t <- alpha^{-n/N} t;  t <- F conj(Lambda_i)^{-1/2} F^* t;
+// t <- alpha^{2n/N} t;  t <- F Lambda_i^{-1/2} F^* t;  t <- alpha^{-n/N} t.
+// lambda_{i,k} = sigma_k + mu_i rho_k (eq. (9) for blocks p_k I + q_k L_h),
+// square roots on the principal branch (Definition 2), computed on the fly.
+// Two modes a, b share one complex line; their spectra are separated with
+// A_k = (Z_k + conj Z_{N-k})/2, B_k = (Z_k - conj Z_{N-k})/(2i).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TimeTables {
+  const cx<T>* tw;     // length N
+  const T* dinv;       // alpha^{-n/N}
+  const T* d2;         // alpha^{2n/N}
+  const cx<T>* sigma;  // fft(alpha^{j/N} p_j)
+  const cx<T>* rho;    // fft(alpha^{j/N} q_j)
+  const T* mu;         // length M, Laplacian eigenvalue of each sine mode
+};
+
+// 1 / (N s) with s the principal square root of lambda (Re lambda > 0):
+// s = sqrt((|l| + Re l)/2) + i Im l / (2 sqrt((|l| + Re l)/2)), 1/s = conj(s)/|l|.
+template <typename T>
+BLTT_HD cx<T> inv_sqrt_scaled(cx<T> lam, T invN) {
+  const T r = sqrt(lam.re * lam.re + lam.im * lam.im);
+  const T sr = sqrt((r + lam.re) * T(0.5));
+  const T si = lam.im / (T(2) * sr);
+  const T f = invN / r;
+  return mkc<T>(sr * f, -si * f);
+}
+
+template <typename T, int L, class Ctx>
+BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t M,
+                            const TimeTables<T>& tb) {
+  constexpr int TPB = tpb_fft<T>();
+  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
+  using F = LineFft<T, L, NL, true, LAST_PAIRED>;
+  constexpr int RL = F::RL, NB = V / RL;
+  const T invN = T(1) / T(L);
+  const int tid = ctx.tid, c = tid % NL, g = tid / NL;
+  const int64_t ia = (int64_t)ctx.bid * (2 * NL) + 2 * c, ib = ia + 1;
+  const bool va = ia < M, vb = ib < M;
+  const int64_t ma = ia < M ? ia : M - 1;
+  const T mua = tb.mu[ma], mub = vb ? tb.mu[ib] : mua;
+
+  cx<T> v[V];
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int64_t n = g + t * s0;
+    const T d = tb.dinv[n];
+    v[t] = mkc<T>(va ? x[n * M + ia] * d : T(0), vb ? x[n * M + ib] * d : T(0));
+  }
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    F::forward(ctx, v, lds, c, g, tb.tw);
+    cx<T> nv[V];
+#pragma unroll
+    for (int w = 0; w < NB; ++w) {
+#pragma unroll
+      for (int u = 0; u < RL; ++u) {
+        const int k = F::freq(g, w, u);
+        int w2, u2;
+        F::partner(g, w, u, w2, u2);
+        const cx<T> zk = v[w * RL + u];
+        const cx<T> zp = conjg(v[w2 * RL + u2]);
+        const cx<T> sg = tb.sigma[k], rh = tb.rho[k];
+        cx<T> ga = inv_sqrt_scaled(sg + rh * mua, invN);
+        cx<T> gb = inv_sqrt_scaled(sg + rh * mub, invN);
+        if (half == 0) {
+          ga = conjg(ga);
+          gb = conjg(gb);
+        }
+        nv[w * RL + u] = ((zk + zp) * ga + (zk - zp) * gb) * T(0.5);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < V; ++t) v[t] = nv[t];
+    F::inverse(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+      const int64_t n = g + t * s0;
+      v[t] = v[t] * (half == 0 ? tb.d2[n] : tb.dinv[n]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int64_t n = g + t * s0;
+    if (va) x[n * M + ia] = v[t].re;
+    if (vb) x[n * M + ib] = v[t].im;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// streaming kernels
+// ---------------------------------------------------------------------------
+
+// b = Y f (time reversal, Section 2) and partial sums of ||b||^2
+template <typename TO, class Ctx>
+BLTT_HD void rhs_body(Ctx& ctx, double* red, const double* __restrict__ f, TO* __restrict__ b, int64_t N,
+                      int64_t M, double scale, double* __restrict__ partials) {
+  const int64_t n_total = N * M;
+  double part = 0.0;
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) {
+    const int64_t n = e / M, i = e - n * M;
+    const double val = f[(N - 1 - n) * M + i] * scale;
+    b[e] = (TO)val;
+    part += val * val;
+  }
+  const double s = block_sum<TPB_EW>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = s;
+}
+
+// W_new = cz Z + ca Wa + cb Wb  (stored over Wa);  X += cx W_new
+template <typename T, typename TX, class Ctx>
+BLTT_HD void wx_body(Ctx& ctx, const T* __restrict__ Z, T* __restrict__ Wa, const T* __restrict__ Wb,
+                     TX* __restrict__ X, int64_t n_total, const double* __restrict__ coef) {
+  const T cz = T(coef[0]), ca = T(coef[1]), cb = T(coef[2]);
+  const TX cxv = TX(coef[3]);
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) {
+    const T w = cz * Z[e] + ca * Wa[e] + cb * Wb[e];
+    Wa[e] = w;
+    X[e] += cxv * TX(w);
+  }
+}
+
+template <typename T, class Ctx>
+BLTT_HD void fill_body(Ctx& ctx, T* __restrict__ x, int64_t n_total, T val) {
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) x[e] = val;
+}
+
+// y = (TO)(x * s)
+template <typename TI, typename TO, class Ctx>
+BLTT_HD void scale_cast_body(Ctx& ctx, const TI* __restrict__ x, TO* __restrict__ y, int64_t n_total,
+                             const double* __restrict__ sptr, int invert) {
+  double s = *sptr;
+  if (invert) s = 1.0 / s;
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) y[e] = (TO)((double)x[e] * s);
+}
+
+// u += s d   (refinement update in FP64)
+template <typename TD, class Ctx>
+BLTT_HD void axpy64_body(Ctx& ctx, double* __restrict__ u, const TD* __restrict__ d, int64_t n_total,
+                         const double* __restrict__ sptr) {
+  const double s = *sptr;
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) u[e] += s * (double)d[e];
+}
+
+// ---------------------------------------------------------------------------
+// MINRES scalar state (device resident, FP64)
+// ---------------------------------------------------------------------------
+struct SolverState {
+  double beta;       // scale of the stored V_j, Z_j: v_j = V_j/beta, z_j = Z_j/beta
+  double beta_prev;  // scale of V_{j-1}
+  double blanc;      // Lanczos beta_j (0 for j = 1)
+  double delta;
+  double c, c_prev, s, s_prev;
+  double eta, eta0;
+  double coef_v[4];  // cq, cv, cvp, unused
+  double coef_w[4];  // cz, ca, cb, cx
+  double norm2;      // last reduced squared norm (rhs or residual)
+  double rscale;     // ||r|| of the current refinement right-hand side
+  double dq;         // last reduced <q, z>
+  double bsq;        // last reduced <vhat, zhat>
+  int32_t iter;
+  int32_t status;    // 0 running, 1 exact convergence (beta = 0), -3 NaN, -4 breakdown
+  int32_t pad[2];
+};
+
+template <class Ctx>
+BLTT_HD double reduce_partials(Ctx& ctx, double* red, const double* __restrict__ partials, int64_t np) {
+  double acc = 0.0;
+  for (int64_t e = ctx.tid; e < np; e += TPB_EW) acc += partials[e];
+  return block_sum<TPB_EW>(ctx, red, acc);
+}
+
+enum {
+  SC_NORM = 0,   // norm2 = sum                              (rhs / residual norms)
+  SC_START = 1,  // beta_1 = sqrt(<b, P^{-1} b>), state reset
+  SC_DELTA = 2,  // delta_j = <q, z_j>, Lanczos coefficients
+  SC_BETA = 3    // beta_{j+1}, Givens rotation, w/x coefficients, eta
+};
+
+template <class Ctx>
+BLTT_HD void scalar_body(Ctx& ctx, double* red, int phase, SolverState* __restrict__ st,
+                         const double* __restrict__ partials, int64_t np, double* __restrict__ hist) {
+  const double sum = reduce_partials(ctx, red, partials, np);
+  if (ctx.tid != 0) return;
+  if (phase == SC_NORM) {
+    st->norm2 = sum;
+    st->rscale = sqrt(sum);
+    return;
+  }
+  if (phase == SC_START) {
+    st->bsq = sum;
+    st->iter = 0;
+    st->status = 0;
+    if (!(sum == sum) || sum > 1e300) {
+      st->status = -3;
+      return;
+    }
+    if (sum <= 0.0) {
+      st->status = -4;
+      return;
+    }
+    const double b1 = sqrt(sum);
+    st->beta = b1;
+    st->beta_prev = 1.0;
+    st->blanc = 0.0;
+    st->eta = b1;
+    st->eta0 = b1;
+    st->c = st->c_prev = 1.0;
+    st->s = st->s_prev = 0.0;
+    if (hist) hist[0] = 1.0;
+    return;
+  }
+  if (phase == SC_DELTA) {
+    st->dq = sum;
+    const double b = st->beta;
+    const double delta = sum / (b * b);
+    st->delta = delta;
+    st->coef_v[0] = 1.0 / b;
+    st->coef_v[1] = -delta / b;
+    st->coef_v[2] = st->iter == 0 ? 0.0 : -st->blanc / st->beta_prev;
+    if (!(delta == delta)) st->status = -3;
+    return;
+  }
+  // SC_BETA
+  st->bsq = sum;
+  if (!(sum == sum)) {
+    st->status = -3;
+    return;
+  }
+  if (sum < 0.0) {
+    st->status = -4;
+    return;
+  }
+  const double bn = sqrt(sum);
+  const double delta = st->delta, bl = st->blanc;
+  const double a0 = st->c * delta - st->c_prev * st->s * bl;
+  const double a1 = sqrt(a0 * a0 + bn * bn);
+  const double a2 = st->s * delta + st->c_prev * st->c * bl;
+  const double a3 = st->s_prev * bl;
+  const double cn = a0 / a1, sn = bn / a1;
+  st->coef_w[0] = 1.0 / (a1 * st->beta);
+  st->coef_w[1] = -a3 / a1;
+  st->coef_w[2] = -a2 / a1;
+  st->coef_w[3] = cn * st->eta;
+  st->eta = -sn * st->eta;
+  st->c_prev = st->c;
+  st->c = cn;
+  st->s_prev = st->s;
+  st->s = sn;
+  st->beta_prev = st->beta;
+  st->beta = bn;
+  st->blanc = bn;
+  st->iter += 1;
+  if (hist) hist[st->iter] = fabs(st->eta) / st->eta0;
+  if (bn == 0.0) st->status = 1;
+}
+
+}  // namespace bltt

@@ -1,0 +1,327 @@
+// Register/LDS line FFT engine for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// A workgroup holds NL complex "lines" of length L (a power of two, 2..2048).
+// Each line is transformed by G = L/V threads that keep V = min(L,16) complex
+// values in registers.  The transform is an in-place mixed-radix
+// decimation-in-frequency FFT: stage s applies radix r_s butterflies of
+// stride sigma_s, and consecutive stages exchange data through LDS.  The
+// forward transform leaves frequency k = sum_s d_s rho_s at position
+// sum_s d_s sigma_s (digit reversal), which is exactly the input order the
+// mirrored decimation-in-time inverse consumes.  A forward/pointwise/inverse
+// chain therefore needs no reordering, and the last forward stage, the
+// pointwise multiply and the first inverse stage all stay in registers.
+//
+// Conventions: forward X[k] = sum_n x[n] exp(-2 pi i n k / L); the inverse
+// returns L x (unnormalised).  Twiddles come from a table tw[k] =
+// exp(-2 pi i k / L), k < L, computed on the host in double precision.
+//
+// Everything here is __host__ __device__ so the same code can be run by the
+// CPU workgroup emulator used in the tests; `Ctx::sync()` is the workgroup
+// barrier.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BLTT_HD __host__ __device__ __forceinline__
+
+namespace bltt {
+
+template <typename T>
+struct cx {
+  T re, im;
+};
+
+template <typename T>
+BLTT_HD cx<T> mkc(T a, T b) {
+  cx<T> r;
+  r.re = a;
+  r.im = b;
+  return r;
+}
+template <typename T>
+BLTT_HD cx<T> operator+(cx<T> a, cx<T> b) { return mkc<T>(a.re + b.re, a.im + b.im); }
+template <typename T>
+BLTT_HD cx<T> operator-(cx<T> a, cx<T> b) { return mkc<T>(a.re - b.re, a.im - b.im); }
+template <typename T>
+BLTT_HD cx<T> operator*(cx<T> a, cx<T> b) {
+  return mkc<T>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+BLTT_HD cx<T> operator*(cx<T> a, T s) { return mkc<T>(a.re * s, a.im * s); }
+template <typename T>
+BLTT_HD cx<T> conjg(cx<T> a) { return mkc<T>(a.re, -a.im); }
+// (SIGN * i) * a
+template <int SIGN, typename T>
+BLTT_HD cx<T> mul_si(cx<T> a) {
+  return SIGN < 0 ? mkc<T>(a.im, -a.re) : mkc<T>(-a.im, a.re);
+}
+
+// ---------------------------------------------------------------------------
+// plans: V values per thread, S stages, radix r(L, s)
+// ---------------------------------------------------------------------------
+constexpr int fft_V(int L) { return L < 16 ? L : 16; }
+constexpr int fft_S(int L) { return L <= 16 ? 1 : (L <= 128 ? 2 : 3); }
+constexpr int fft_r(int L, int s) {
+  return L <= 16    ? L
+         : L <= 128 ? (s == 0 ? 16 : L / 16)
+         : L == 256 ? (s == 0 ? 16 : 4)
+         : L == 512 ? (s == 0 ? 16 : (s == 1 ? 8 : 4))
+         : L == 1024 ? (s == 0 ? 16 : 8)
+                     : (s == 2 ? 8 : 16);  // 2048
+}
+constexpr int fft_sigma(int L, int s) {
+  int p = 1;
+  for (int i = 0; i <= s; ++i) p *= fft_r(L, i);
+  return L / p;
+}
+constexpr int fft_rho(int L, int s) {
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= fft_r(L, i);
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers, natural order in and out:
+//   y_u = sum_t a_t exp(SIGN 2 pi i t u / R)
+// ---------------------------------------------------------------------------
+template <int SIGN, typename T>
+BLTT_HD void dft2(cx<T>* a) {
+  cx<T> t = a[0];
+  a[0] = t + a[1];
+  a[1] = t - a[1];
+}
+template <int SIGN, typename T>
+BLTT_HD void dft4(cx<T>* a) {
+  cx<T> t0 = a[0] + a[2], t1 = a[0] - a[2];
+  cx<T> t2 = a[1] + a[3], t3 = mul_si<SIGN>(a[1] - a[3]);
+  a[0] = t0 + t2;
+  a[2] = t0 - t2;
+  a[1] = t1 + t3;
+  a[3] = t1 - t3;
+}
+template <int SIGN, typename T>
+BLTT_HD void dft8(cx<T>* a) {
+  cx<T> e[4] = {a[0], a[2], a[4], a[6]};
+  cx<T> o[4] = {a[1], a[3], a[5], a[7]};
+  dft4<SIGN>(e);
+  dft4<SIGN>(o);
+  const T h = T(0.70710678118654752440);
+  cx<T> t1 = o[1] * mkc<T>(h, SIGN * h);
+  cx<T> t2 = mul_si<SIGN>(o[2]);
+  cx<T> t3 = o[3] * mkc<T>(-h, SIGN * h);
+  a[0] = e[0] + o[0];
+  a[4] = e[0] - o[0];
+  a[1] = e[1] + t1;
+  a[5] = e[1] - t1;
+  a[2] = e[2] + t2;
+  a[6] = e[2] - t2;
+  a[3] = e[3] + t3;
+  a[7] = e[3] - t3;
+}
+template <int SIGN, typename T>
+BLTT_HD void dft16(cx<T>* a) {
+  cx<T> e[8], o[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    e[k] = a[2 * k];
+    o[k] = a[2 * k + 1];
+  }
+  dft8<SIGN>(e);
+  dft8<SIGN>(o);
+  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+  const T h = T(0.70710678118654752440);
+  const cx<T> w[8] = {mkc<T>(T(1), T(0)),     mkc<T>(c1, SIGN * s1), mkc<T>(h, SIGN * h),
+                      mkc<T>(s1, SIGN * c1),  mkc<T>(T(0), T(SIGN)), mkc<T>(-s1, SIGN * c1),
+                      mkc<T>(-h, SIGN * h),   mkc<T>(-c1, SIGN * s1)};
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    cx<T> t = (u == 0) ? o[0] : o[u] * w[u];
+    a[u] = e[u] + t;
+    a[u + 8] = e[u] - t;
+  }
+}
+template <int R, int SIGN, typename T>
+BLTT_HD void dft(cx<T>* a) {
+  if constexpr (R == 2) dft2<SIGN>(a);
+  else if constexpr (R == 4) dft4<SIGN>(a);
+  else if constexpr (R == 8) dft8<SIGN>(a);
+  else if constexpr (R == 16) dft16<SIGN>(a);
+  else static_assert(R == 2, "unsupported radix");
+}
+
+// How the last stage's butterflies are dealt to the threads of a line.
+enum LastMode {
+  LAST_DEFAULT = 0,  // butterfly g + G*w (LDS friendly)
+  LAST_LINEAR = 1,   // frequency base k_low = g + G*w (coalesced frequency stores)
+  LAST_PAIRED = 2    // k_low and K - k_low in one thread (k <-> L-k pairs in registers)
+};
+
+template <typename T, int L, int NL, bool INTERLEAVED, int LAST>
+struct LineFft {
+  static constexpr int V = fft_V(L);
+  static constexpr int S = fft_S(L);
+  static constexpr int G = L / V;             // threads per line
+  static constexpr int RL = fft_r(L, S - 1);  // last radix
+  static constexpr int K = L / RL;            // last-stage butterflies per line
+  static constexpr int LP = L + (L >> 3);     // padded line length
+  static constexpr int LDS_ELEMS = NL * LP;
+  static_assert(S == 1 || fft_r(L, 0) == V, "first stage must use all registers");
+  static_assert(LAST != LAST_PAIRED || S == 1 || V >= 2 * RL, "pairing needs two butterflies");
+
+  BLTT_HD static int idx(int c, int pos) {
+    const int pp = pos + (pos >> 3);
+    return INTERLEAVED ? pp * NL + c : c * LP + pp;
+  }
+
+  template <int s>
+  BLTT_HD static int pos(int b, int t) {
+    constexpr int sg = fft_sigma(L, s), r = fft_r(L, s);
+    return (b / sg) * (r * sg) + (b % sg) + t * sg;
+  }
+
+  // frequency base of a last-stage butterfly, and its inverse
+  BLTT_HD static int klow_of_blk(int b) {
+    const int p = b * RL;
+    int k = 0;
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s) k += ((p / fft_sigma(L, s)) % fft_r(L, s)) * fft_rho(L, s);
+    return k;
+  }
+  BLTT_HD static int blk_of_klow(int kl) {
+    int b = 0;
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s) b += ((kl / fft_rho(L, s)) % fft_r(L, s)) * (fft_sigma(L, s) / RL);
+    return b;
+  }
+
+  BLTT_HD static int klow(int g, int w) {
+    if constexpr (S == 1) {
+      return 0;
+    } else if constexpr (LAST == LAST_PAIRED) {
+      constexpr int PP = V / (2 * RL);
+      const int q = g * PP + (w >> 1);
+      const bool first = (w & 1) == 0;
+      if (q == 0) return first ? 0 : K / 2;
+      return first ? q : K - q;
+    } else if constexpr (LAST == LAST_LINEAR) {
+      return g + G * w;
+    } else {
+      return klow_of_blk(g + G * w);
+    }
+  }
+
+  template <int s>
+  BLTT_HD static int beta(int g, int w) {
+    if constexpr (s == S - 1 && S > 1 && LAST != LAST_DEFAULT) {
+      return blk_of_klow(klow(g, w));
+    } else {
+      return g + G * w;
+    }
+  }
+
+  // frequency held by register slot (w, u) after the forward transform
+  BLTT_HD static int freq(int g, int w, int u) {
+    if constexpr (S == 1) return u;
+    else return klow(g, w) + u * K;
+  }
+
+  // register slot holding frequency L - k (mod L) for the slot (w, u)
+  // (PAIRED or single-stage plans only)
+  BLTT_HD static void partner(int g, int w, int u, int& w2, int& u2) {
+    if constexpr (S == 1) {
+      w2 = 0;
+      u2 = (L - u) % L;
+    } else {
+      constexpr int PP = V / (2 * RL);
+      const int q = g * PP + (w >> 1);
+      if (q == 0) {
+        w2 = w;
+        u2 = ((w & 1) == 0) ? (RL - u) % RL : RL - 1 - u;
+      } else {
+        w2 = w ^ 1;
+        u2 = RL - 1 - u;
+      }
+    }
+  }
+
+  // ---- forward: v[w*r0+t] = x[pos<0>(beta<0>(g,w),t)]  ->  v[w*RL+u] = X[freq(g,w,u)]
+  template <class Ctx>
+  BLTT_HD static void forward(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
+    fwd_stage<0>(ctx, v, lds, c, g, tw);
+  }
+
+  template <int s, class Ctx>
+  BLTT_HD static void fwd_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
+    constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), B = r * sg, NB = V / r;
+    if constexpr (s > 0) {
+#pragma unroll
+      for (int w = 0; w < NB; ++w) {
+        const int b = beta<s>(g, w);
+#pragma unroll
+        for (int t = 0; t < r; ++t) v[w * r + t] = lds[idx(c, pos<s>(b, t))];
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < NB; ++w) {
+      dft<r, -1>(v + w * r);
+      if constexpr (sg > 1) {
+        const int j = beta<s>(g, w) % sg;
+#pragma unroll
+        for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * tw[j * u * (L / B)];
+      }
+    }
+    if constexpr (s + 1 < S) {
+      ctx.sync();
+#pragma unroll
+      for (int w = 0; w < NB; ++w) {
+        const int b = beta<s>(g, w);
+#pragma unroll
+        for (int u = 0; u < r; ++u) lds[idx(c, pos<s>(b, u))] = v[w * r + u];
+      }
+      ctx.sync();
+      fwd_stage<s + 1>(ctx, v, lds, c, g, tw);
+    }
+  }
+
+  // ---- inverse: v[w*RL+u] = X[freq(g,w,u)]  ->  v[w*r0+t] = L x[pos<0>(beta<0>(g,w),t)]
+  template <class Ctx>
+  BLTT_HD static void inverse(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
+    inv_stage<S - 1>(ctx, v, lds, c, g, tw);
+  }
+
+  template <int s, class Ctx>
+  BLTT_HD static void inv_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
+    constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), B = r * sg, NB = V / r;
+    if constexpr (s < S - 1) {
+#pragma unroll
+      for (int w = 0; w < NB; ++w) {
+        const int b = beta<s>(g, w);
+#pragma unroll
+        for (int u = 0; u < r; ++u) v[w * r + u] = lds[idx(c, pos<s>(b, u))];
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < NB; ++w) {
+      if constexpr (sg > 1) {
+        const int j = beta<s>(g, w) % sg;
+#pragma unroll
+        for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * conjg(tw[j * u * (L / B)]);
+      }
+      dft<r, +1>(v + w * r);
+    }
+    if constexpr (s > 0) {
+      ctx.sync();
+#pragma unroll
+      for (int w = 0; w < NB; ++w) {
+        const int b = beta<s>(g, w);
+#pragma unroll
+        for (int t = 0; t < r; ++t) lds[idx(c, pos<s>(b, t))] = v[w * r + t];
+      }
+      ctx.sync();
+      inv_stage<s - 1>(ctx, v, lds, c, g, tw);
+    }
+  }
+};
+
+}  // namespace bltt

@@ -1,0 +1,113 @@
+// Sine-transform passes: contiguous x-lines (with the fused Lanczos update or
+// the fused dot product) and strided y/z-lines (in place).
+#include "launchers.hpp"
+
+namespace bltt {
+
+template <typename T, int L, int KIND>
+__global__ __launch_bounds__(tpb_fft<T>()) void k_dst_x(const T* in, const T* __restrict__ v1,
+                                                        const T* __restrict__ v2, T* __restrict__ vout,
+                                                        const T* __restrict__ vdot, T* out,
+                                                        int64_t nlines, DstTables<T> tb,
+                                                        const double* __restrict__ coef,
+                                                        double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+  using F = LineFft<T, L, NL, false, LAST_LINEAR>;
+  DevCtx ctx = make_ctx();
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
+  dst_x_body<T, L, KIND>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, v1, v2, vout, vdot, out, nlines, tb, coef,
+                         partials);
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(tpb_fft<T>()) void k_dst_strided(T* __restrict__ x, int64_t nlines, int64_t S,
+                                                              DstTables<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  DevCtx ctx = make_ctx();
+  dst_strided_body<T, L>(ctx, reinterpret_cast<cx<T>*>(smem), x, nlines, S, tb);
+}
+
+template <typename T, int L>
+static hipError_t go_dx(int kind, const T* in, const T* v1, const T* v2, T* vout, const T* vdot, T* out,
+                        int64_t nlines, const DstTables<T>& tb, const double* coef, double* partials,
+                        hipStream_t s) {
+  const int64_t blocks = fft_blocks<T>(L, nlines);
+  const size_t lds = fft_lds_bytes<T>(L);
+  if (kind == KIND_VUPD)
+    hipLaunchKernelGGL((k_dst_x<T, L, KIND_VUPD>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, in, v1, v2,
+                       vout, vdot, out, nlines, tb, coef, partials);
+  else
+    hipLaunchKernelGGL((k_dst_x<T, L, KIND_DOT>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, in, v1, v2,
+                       vout, vdot, out, nlines, tb, coef, partials);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t go_ds(T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s) {
+  const int64_t blocks = fft_blocks<T>(L, nlines);
+  const size_t lds = fft_lds_bytes<T>(L);
+  hipLaunchKernelGGL((k_dst_strided<T, L>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, x, nlines, S, tb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dst_x(int L, int kind, const T* in, const T* v1, const T* v2, T* vout, const T* vdot, T* out,
+                        int64_t nlines, const DstTables<T>& tb, const double* coef, double* partials,
+                        hipStream_t s) {
+  switch (L) {
+#define BLTT_CASE(LL) \
+  case LL: return go_dx<T, LL>(kind, in, v1, v2, vout, vdot, out, nlines, tb, coef, partials, s);
+    BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64) BLTT_CASE(128) BLTT_CASE(256)
+    BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
+#undef BLTT_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_dst_strided(int L, T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s) {
+  switch (L) {
+#define BLTT_CASE(LL) \
+  case LL: return go_ds<T, LL>(x, nlines, S, tb, s);
+    BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64) BLTT_CASE(128) BLTT_CASE(256)
+    BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
+#undef BLTT_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+#define BLTT_INST(T)                                                                                           \
+  template hipError_t launch_dst_x<T>(int, int, const T*, const T*, const T*, T*, const T*, T*, int64_t,       \
+                                      const DstTables<T>&, const double*, double*, hipStream_t);               \
+  template hipError_t launch_dst_strided<T>(int, T*, int64_t, int64_t, const DstTables<T>&, hipStream_t);
+BLTT_INST(float)
+BLTT_INST(double)
+#undef BLTT_INST
+
+template <typename T, int L>
+static hipError_t attr_dst() {
+  const int bytes = (int)fft_lds_bytes<T>(L);
+  hipError_t e;
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_DOT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+    return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_strided<T, L>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t configure_dst_kernels() {
+  hipError_t e = hipSuccess;
+#define BLTT_ATTR(L)                                          \
+  if ((e = attr_dst<float, L>()) != hipSuccess) return e;    \
+  if ((e = attr_dst<double, L>()) != hipSuccess) return e;
+  BLTT_ATTR(4) BLTT_ATTR(8) BLTT_ATTR(16) BLTT_ATTR(32) BLTT_ATTR(64) BLTT_ATTR(128) BLTT_ATTR(256)
+  BLTT_ATTR(512) BLTT_ATTR(1024) BLTT_ATTR(2048)
+#undef BLTT_ATTR
+  return e;
+}
+
+}  // namespace bltt

@@ -1,0 +1,113 @@
+// Streaming kernels (right-hand side, MINRES direction/iterate update,
+// refinement casts) and the single-workgroup scalar kernel.
+#include "launchers.hpp"
+
+namespace bltt {
+
+template <typename TO>
+__global__ __launch_bounds__(TPB_EW) void k_rhs(const double* __restrict__ f, TO* __restrict__ b, int64_t N,
+                                                int64_t M, double scale, double* __restrict__ partials) {
+  __shared__ double red[TPB_EW];
+  DevCtx ctx = make_ctx();
+  rhs_body<TO>(ctx, red, f, b, N, M, scale, partials);
+}
+
+template <typename T, typename TX>
+__global__ __launch_bounds__(TPB_EW) void k_wx(const T* __restrict__ Z, T* __restrict__ Wa, const T* __restrict__ Wb,
+                                               TX* __restrict__ X, int64_t n, const double* __restrict__ coef) {
+  DevCtx ctx = make_ctx();
+  wx_body<T, TX>(ctx, Z, Wa, Wb, X, n, coef);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB_EW) void k_fill(T* __restrict__ x, int64_t n, T val) {
+  DevCtx ctx = make_ctx();
+  fill_body<T>(ctx, x, n, val);
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(TPB_EW) void k_scale_cast(const TI* __restrict__ x, TO* __restrict__ y, int64_t n,
+                                                       const double* __restrict__ sptr, int invert) {
+  DevCtx ctx = make_ctx();
+  scale_cast_body<TI, TO>(ctx, x, y, n, sptr, invert);
+}
+
+template <typename TD>
+__global__ __launch_bounds__(TPB_EW) void k_axpy64(double* __restrict__ u, const TD* __restrict__ d, int64_t n,
+                                                   const double* __restrict__ sptr) {
+  DevCtx ctx = make_ctx();
+  axpy64_body<TD>(ctx, u, d, n, sptr);
+}
+
+__global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __restrict__ st,
+                                                   const double* __restrict__ partials, int64_t np,
+                                                   double* __restrict__ hist) {
+  __shared__ double red[TPB_EW];
+  DevCtx ctx = make_ctx();
+  scalar_body(ctx, red, phase, st, partials, np, hist);
+}
+
+template <typename TO>
+hipError_t launch_rhs(const double* f, TO* b, int64_t N, int64_t M, double scale, double* partials,
+                      int64_t* nparts, hipStream_t s) {
+  const int64_t blocks = ew_blocks(N * M);
+  if (nparts) *nparts = blocks;
+  hipLaunchKernelGGL((k_rhs<TO>), dim3((unsigned)blocks), dim3(TPB_EW), 0, s, f, b, N, M, scale, partials);
+  return hipGetLastError();
+}
+template <typename T, typename TX>
+hipError_t launch_wx(const T* Z, T* Wa, const T* Wb, TX* X, int64_t n, const double* coef, hipStream_t s) {
+  hipLaunchKernelGGL((k_wx<T, TX>), dim3((unsigned)ew_blocks(n)), dim3(TPB_EW), 0, s, Z, Wa, Wb, X, n, coef);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_fill(T* x, int64_t n, T val, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)ew_blocks(n)), dim3(TPB_EW), 0, s, x, n, val);
+  return hipGetLastError();
+}
+template <typename TI, typename TO>
+hipError_t launch_scale_cast(const TI* x, TO* y, int64_t n, const double* sptr, int invert, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale_cast<TI, TO>), dim3((unsigned)ew_blocks(n)), dim3(TPB_EW), 0, s, x, y, n, sptr,
+                     invert);
+  return hipGetLastError();
+}
+template <typename TD>
+hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy64<TD>), dim3((unsigned)ew_blocks(n)), dim3(TPB_EW), 0, s, u, d, n, sptr);
+  return hipGetLastError();
+}
+hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, double* hist,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(TPB_EW), 0, s, phase, st, partials, np, hist);
+  return hipGetLastError();
+}
+
+template hipError_t launch_rhs<float>(const double*, float*, int64_t, int64_t, double, double*, int64_t*,
+                                      hipStream_t);
+template hipError_t launch_rhs<double>(const double*, double*, int64_t, int64_t, double, double*, int64_t*,
+                                       hipStream_t);
+template hipError_t launch_wx<float, float>(const float*, float*, const float*, float*, int64_t, const double*,
+                                            hipStream_t);
+template hipError_t launch_wx<double, double>(const double*, double*, const double*, double*, int64_t,
+                                              const double*, hipStream_t);
+template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
+template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
+template hipError_t launch_scale_cast<double, float>(const double*, float*, int64_t, const double*, int,
+                                                     hipStream_t);
+template hipError_t launch_scale_cast<double, double>(const double*, double*, int64_t, const double*, int,
+                                                      hipStream_t);
+template hipError_t launch_axpy64<float>(double*, const float*, int64_t, const double*, hipStream_t);
+template hipError_t launch_axpy64<double>(double*, const double*, int64_t, const double*, hipStream_t);
+
+hipError_t configure_time_kernels();
+hipError_t configure_matvec_kernels();
+hipError_t configure_dst_kernels();
+
+hipError_t configure_kernels() {
+  hipError_t e;
+  if ((e = configure_time_kernels()) != hipSuccess) return e;
+  if ((e = configure_matvec_kernels()) != hipSuccess) return e;
+  return configure_dst_kernels();
+}
+
+}  // namespace bltt

@@ -1,0 +1,87 @@
+// Host-side launchers of the hot-path kernels (one definition per kernel
+// translation unit, explicitly instantiated for float and double).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bltt_kernels.hpp"
+
+namespace bltt {
+
+// Device-side context: thread/block indices and the workgroup barrier.
+struct DevCtx {
+  int tid, bid, bid_y, nbx;
+  __device__ void sync() { __syncthreads(); }
+};
+__device__ inline DevCtx make_ctx() {
+  DevCtx c;
+  c.tid = (int)threadIdx.x;
+  c.bid = (int)blockIdx.x;
+  c.bid_y = (int)blockIdx.y;
+  c.nbx = (int)gridDim.x;
+  return c;
+}
+
+// Workgroup geometry of the line-FFT kernels for line length L.
+template <typename T>
+inline int lines_per_block(int L) {
+  const int V = L < 16 ? L : 16;
+  return tpb_fft<T>() / (L / V);
+}
+template <typename T>
+inline size_t fft_lds_bytes(int L) {
+  const size_t NL = (size_t)lines_per_block<T>(L);
+  const size_t LP = (size_t)L + (size_t)(L >> 3);
+  return NL * LP * sizeof(cx<T>) + (size_t)tpb_fft<T>() * sizeof(double);
+}
+inline bool fft_length_ok(int L) { return L >= 2 && L <= 2048 && (L & (L - 1)) == 0; }
+
+// Number of partial sums written by the launchers below.
+template <typename T>
+inline int64_t fft_blocks(int L, int64_t units) {  // units = spatial points or lines
+  const int64_t per = 2 * (int64_t)lines_per_block<T>(L);
+  return (units + per - 1) / per;
+}
+inline int64_t ew_blocks(int64_t n) {
+  const int64_t b = (n + TPB_EW - 1) / TPB_EW;
+  return b < 1 ? 1 : (b > 16384 ? 16384 : b);
+}
+
+template <typename T>
+hipError_t launch_time_prec(int L, T* x, int64_t M, const TimeTables<T>& tb, hipStream_t s);
+
+template <typename T>
+hipError_t launch_matvec_fft(int L, int mode, const T* z, T* out, const T* fin, int64_t M,
+                             const MatvecTables<T>& tb, double* partials, hipStream_t s);
+
+template <typename T>
+hipError_t launch_matvec_short(int mode, const T* z, T* out, const T* fin, int64_t M,
+                               const ShortTables<T>& tb, double* partials, int64_t* nparts, hipStream_t s);
+
+template <typename T>
+hipError_t launch_dst_x(int L, int kind, const T* in, const T* v1, const T* v2, T* vout, const T* vdot, T* out,
+                        int64_t nlines, const DstTables<T>& tb, const double* coef, double* partials,
+                        hipStream_t s);
+
+template <typename T>
+hipError_t launch_dst_strided(int L, T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s);
+
+// one-time kernel attribute setup (dynamic LDS above 64 KiB)
+hipError_t configure_kernels();
+
+// streaming and scalar kernels
+template <typename TO>
+hipError_t launch_rhs(const double* f, TO* b, int64_t N, int64_t M, double scale, double* partials,
+                      int64_t* nparts, hipStream_t s);
+template <typename T, typename TX>
+hipError_t launch_wx(const T* Z, T* Wa, const T* Wb, TX* X, int64_t n, const double* coef, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* x, int64_t n, T val, hipStream_t s);
+template <typename TI, typename TO>
+hipError_t launch_scale_cast(const TI* x, TO* y, int64_t n, const double* sptr, int invert, hipStream_t s);
+template <typename TD>
+hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, hipStream_t s);
+hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, double* hist,
+                         hipStream_t s);
+
+}  // namespace bltt

@@ -1,0 +1,363 @@
+// CPU workgroup emulator for the HIP kernel bodies (test infrastructure).
+//
+// Runs the __host__ __device__ kernel bodies of the GPU path on host threads:
+// one std::thread per GPU thread of a workgroup, the workgroup barrier mapped
+// to a host barrier and LDS to a host array.  The tests use it to check the
+// kernels' index arithmetic and numerics on the CPU (with bounds-checked
+// buffers) before anything runs on a GPU.  Built with hipcc as host code; never
+// loaded by the solver.
+#include <condition_variable>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "bltt_kernels.hpp"
+#include "host_tables.hpp"
+
+using namespace bltt;
+
+namespace {
+
+struct Barrier {
+  explicit Barrier(int n) : count(n) {}
+  void wait() {
+    std::unique_lock<std::mutex> lk(m);
+    const int g = gen;
+    if (++waiting == count) {
+      waiting = 0;
+      ++gen;
+      cv.notify_all();
+    } else {
+      cv.wait(lk, [&] { return gen != g; });
+    }
+  }
+  std::mutex m;
+  std::condition_variable cv;
+  int count;
+  int waiting = 0;
+  int gen = 0;
+};
+
+struct HostCtx {
+  int tid, bid, bid_y, nbx;
+  Barrier* bar;
+  void sync() { bar->wait(); }
+};
+
+// LDS with guard words: out-of-range accesses are detected at the end.
+struct Lds {
+  explicit Lds(size_t bytes) : buf(bytes + 2 * kGuard, 0xA5) {}
+  unsigned char* base() { return buf.data() + kGuard; }
+  bool intact() const {
+    for (size_t i = 0; i < kGuard; ++i)
+      if (buf[i] != 0xA5 || buf[buf.size() - 1 - i] != 0xA5) return false;
+    return true;
+  }
+  static constexpr size_t kGuard = 256;
+  std::vector<unsigned char> buf;
+};
+
+int g_error = 0;
+
+void run_grid(int tpb, int gx, int gy, size_t lds_bytes,
+              const std::function<void(HostCtx&, unsigned char*)>& body) {
+  for (int by = 0; by < gy; ++by) {
+    for (int bx = 0; bx < gx; ++bx) {
+      Lds lds(lds_bytes);
+      Barrier bar(tpb);
+      std::vector<std::thread> th;
+      th.reserve((size_t)tpb);
+      for (int t = 0; t < tpb; ++t) {
+        th.emplace_back([&, t] {
+          HostCtx c{t, bx, by, gx, &bar};
+          body(c, lds.base());
+        });
+      }
+      for (auto& x : th) x.join();
+      if (!lds.intact()) g_error = 1;
+    }
+  }
+}
+
+template <typename T>
+int nl_of(int L) {
+  const int V = L < 16 ? L : 16;
+  return tpb_fft<T>() / (L / V);
+}
+template <typename T>
+size_t lds_of(int L) {
+  return (size_t)nl_of<T>(L) * (size_t)(L + (L >> 3)) * sizeof(cx<T>) + (size_t)tpb_fft<T>() * sizeof(double);
+}
+template <typename T>
+int64_t blocks_of(int L, int64_t units) {
+  const int64_t per = 2 * (int64_t)nl_of<T>(L);
+  return (units + per - 1) / per;
+}
+
+template <typename T>
+std::vector<cx<T>> to_cx(const std::vector<host::cd>& v) {
+  std::vector<cx<T>> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = mkc<T>((T)v[i].real(), (T)v[i].imag());
+  return o;
+}
+template <typename T>
+std::vector<T> to_t(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+// ---- dispatch over the compile-time line length
+template <template <int> class F, typename... A>
+void with_L(int L, A&&... a) {
+  switch (L) {
+    case 2: F<2>::run(a...); break;
+    case 4: F<4>::run(a...); break;
+    case 8: F<8>::run(a...); break;
+    case 16: F<16>::run(a...); break;
+    case 32: F<32>::run(a...); break;
+    case 64: F<64>::run(a...); break;
+    case 128: F<128>::run(a...); break;
+    case 256: F<256>::run(a...); break;
+    case 512: F<512>::run(a...); break;
+    case 1024: F<1024>::run(a...); break;
+    case 2048: F<2048>::run(a...); break;
+    default: g_error = 2;
+  }
+}
+
+template <typename T>
+struct TimeRun {
+  template <int L>
+  struct R {
+    static void run(T* x, int64_t M, const TimeTables<T>& tb) {
+      run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, M), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
+        time_prec_body<T, L>(c, reinterpret_cast<cx<T>*>(lds), x, M, tb);
+      });
+    }
+  };
+};
+
+template <typename T>
+struct DstXRun {
+  template <int L>
+  struct R {
+    static void run(const T* in, T* out, int64_t nlines, const DstTables<T>& tb, const double* coef,
+                    double* partials, const T* vdot, int kind) {
+      constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+      using Fx = LineFft<T, L, NL, false, LAST_LINEAR>;
+      run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, nlines), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
+        double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fx::LDS_ELEMS);
+        if (kind == KIND_VUPD)
+          dst_x_body<T, L, KIND_VUPD>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr, nullptr,
+                                       nullptr, out, nlines, tb, coef, partials);
+        else
+          dst_x_body<T, L, KIND_DOT>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr, nullptr, vdot,
+                                      out, nlines, tb, coef, partials);
+      });
+    }
+  };
+};
+
+template <typename T>
+struct DstSRun {
+  template <int L>
+  struct R {
+    static void run(T* x, int64_t nlines, int64_t S, const DstTables<T>& tb) {
+      run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, nlines), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
+        dst_strided_body<T, L>(c, reinterpret_cast<cx<T>*>(lds), x, nlines, S, tb);
+      });
+    }
+  };
+};
+
+template <typename T>
+struct MvRun {
+  template <int L>
+  struct R {
+    static void run(const T* z, T* out, int64_t M, const MatvecTables<T>& tb, double* partials) {
+      constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+      using Fm = LineFft<T, L, NL, true, LAST_DEFAULT>;
+      run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, M), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
+        double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
+        matvec_fft_body<T, L, MV_DOT>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb, partials);
+      });
+    }
+  };
+};
+
+struct Problem {
+  int dim;
+  int m[3];
+  double h[3];
+  int64_t N, M;
+  double alpha;
+  std::vector<double> p, q;
+};
+
+Problem make_problem(int dim, const int* m, const double* h, int64_t N, double alpha, const double* p,
+                     const double* q) {
+  Problem P;
+  P.dim = dim;
+  P.M = 1;
+  for (int d = 0; d < 3; ++d) {
+    P.m[d] = d < dim ? m[d] : 1;
+    P.h[d] = d < dim ? h[d] : 1.0;
+    if (d < dim) P.M *= m[d];
+  }
+  P.N = N;
+  P.alpha = alpha;
+  P.p.assign(p, p + N);
+  P.q.assign(q, q + N);
+  return P;
+}
+
+Grid grid_of(const Problem& P) {
+  Grid g;
+  g.dim = P.dim;
+  for (int d = 0; d < 3; ++d) {
+    g.m[d] = P.m[d];
+    g.inv_h2[d] = d < P.dim ? 1.0 / (P.h[d] * P.h[d]) : 0.0;
+  }
+  return g;
+}
+
+template <typename T>
+struct HostTables {
+  std::vector<cx<T>> tw_time, tw_dst[3], sigma, rho, chat, shat, phi;
+  std::vector<T> dinv, d2, mu;
+  explicit HostTables(const Problem& P) {
+    tw_time = to_cx<T>(host::twiddles((int)P.N));
+    for (int d = 0; d < P.dim; ++d) tw_dst[d] = to_cx<T>(host::twiddles(2 * (P.m[d] + 1)));
+    dinv = to_t<T>(host::alpha_pow(P.N, P.alpha, -1.0));
+    d2 = to_t<T>(host::alpha_pow(P.N, P.alpha, 2.0));
+    sigma = to_cx<T>(host::alpha_spectrum(P.p, P.alpha));
+    rho = to_cx<T>(host::alpha_spectrum(P.q, P.alpha));
+    mu = to_t<T>(host::lap_eigs(P.dim, P.m, P.h));
+    chat = to_cx<T>(host::matvec_spectrum(P.p, false));
+    shat = to_cx<T>(host::matvec_spectrum(P.p, true));
+    phi = to_cx<T>(host::skew_phase(P.N));
+  }
+  DstTables<T> dst(const Problem& P, int d) const {
+    DstTables<T> tb;
+    tb.tw = tw_dst[d].data();
+    tb.m = P.m[d];
+    tb.nrm = (T)(1.0 / std::sqrt(2.0 * (P.m[d] + 1)));
+    return tb;
+  }
+};
+
+template <typename T>
+void space_strided(const Problem& P, const HostTables<T>& ht, T* x, bool reverse) {
+  const int64_t n = P.N * P.M;
+  for (int k = 1; k < P.dim; ++k) {
+    const int d = reverse ? P.dim - k : k;
+    int64_t S = 1;
+    for (int e = 0; e < d; ++e) S *= P.m[e];
+    with_L<DstSRun<T>::template R>(2 * (P.m[d] + 1), x, n / P.m[d], S, ht.dst(P, d));
+  }
+}
+
+template <typename T>
+void apply_space(const Problem& P, const T* x, T* y) {
+  HostTables<T> ht(P);
+  const int64_t n = P.N * P.M;
+  const double one[4] = {1, 0, 0, 0};
+  with_L<DstXRun<T>::template R>(2 * (P.m[0] + 1), x, y, n / P.m[0], ht.dst(P, 0), one, (double*)nullptr,
+                                 (const T*)nullptr, (int)KIND_VUPD);
+  space_strided<T>(P, ht, y, false);
+}
+
+template <typename T>
+void apply_time(const Problem& P, T* x) {
+  HostTables<T> ht(P);
+  TimeTables<T> tt{ht.tw_time.data(), ht.dinv.data(), ht.d2.data(), ht.sigma.data(), ht.rho.data(), ht.mu.data()};
+  with_L<TimeRun<T>::template R>((int)P.N, x, P.M, tt);
+}
+
+template <typename T>
+void apply_precond(const Problem& P, const T* x, T* y) {
+  HostTables<T> ht(P);
+  const int64_t n = P.N * P.M;
+  std::vector<T> tmp((size_t)n);
+  const double one[4] = {1, 0, 0, 0};
+  const int Lx = 2 * (P.m[0] + 1);
+  with_L<DstXRun<T>::template R>(Lx, x, tmp.data(), n / P.m[0], ht.dst(P, 0), one, (double*)nullptr,
+                                 (const T*)nullptr, (int)KIND_VUPD);
+  space_strided<T>(P, ht, tmp.data(), false);
+  TimeTables<T> tt{ht.tw_time.data(), ht.dinv.data(), ht.d2.data(), ht.sigma.data(), ht.rho.data(), ht.mu.data()};
+  with_L<TimeRun<T>::template R>((int)P.N, tmp.data(), P.M, tt);
+  space_strided<T>(P, ht, tmp.data(), true);
+  std::vector<double> partials((size_t)blocks_of<T>(Lx, n / P.m[0]) + 1);
+  with_L<DstXRun<T>::template R>(Lx, tmp.data(), y, n / P.m[0], ht.dst(P, 0), one, partials.data(), x,
+                                 (int)KIND_DOT);
+}
+
+template <typename T>
+double apply_sym(const Problem& P, const T* z, T* out, bool force_fft) {
+  int ptaps = 0, qtaps = 0;
+  for (int64_t k = 0; k < P.N; ++k) {
+    if (P.p[(size_t)k] != 0.0) ptaps = (int)k + 1;
+    if (P.q[(size_t)k] != 0.0) qtaps = (int)k + 1;
+  }
+  double dot = 0.0;
+  if (ptaps <= 8 && !force_fft) {
+    ShortTables<T> tb;
+    for (int k = 0; k < 8; ++k) tb.p[k] = (T)(k < ptaps ? P.p[(size_t)k] : 0.0);
+    tb.ptaps = ptaps;
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+    tb.qtaps = qtaps;
+    tb.grid = grid_of(P);
+    tb.N = (int)P.N;
+    tb.chunk = 8;
+    const int gx = (int)((P.M + TPB_EW - 1) / TPB_EW);
+    const int gy = (int)(((P.N + 1) / 2 + tb.chunk - 1) / tb.chunk);
+    std::vector<double> partials((size_t)gx * gy);
+    run_grid(TPB_EW, gx, gy, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
+      matvec_short_body<T, MV_DOT>(c, reinterpret_cast<double*>(lds), z, out, (const T*)nullptr, P.M, tb,
+                                   partials.data());
+    });
+    for (double v : partials) dot += v;
+  } else {
+    HostTables<T> ht(P);
+    MatvecTables<T> tb;
+    tb.tw = ht.tw_time.data();
+    tb.chat = ht.chat.data();
+    tb.shat = ht.shat.data();
+    tb.phi = ht.phi.data();
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+    tb.qtaps = qtaps;
+    tb.grid = grid_of(P);
+    std::vector<double> partials((size_t)blocks_of<T>((int)P.N, P.M));
+    with_L<MvRun<T>::template R>((int)P.N, z, out, P.M, tb, partials.data());
+    for (double v : partials) dot += v;
+  }
+  return dot;
+}
+
+}  // namespace
+
+extern "C" {
+
+int emu_error(void) { return g_error; }
+
+#define EMU_ARGS int dim, const int *m, const double *h, int64_t N, double alpha, const double *p, const double *q
+#define EMU_P make_problem(dim, m, h, N, alpha, p, q)
+
+void emu_space_f64(EMU_ARGS, const double* x, double* y) { apply_space<double>(EMU_P, x, y); }
+void emu_space_f32(EMU_ARGS, const float* x, float* y) { apply_space<float>(EMU_P, x, y); }
+void emu_time_f64(EMU_ARGS, double* x) { apply_time<double>(EMU_P, x); }
+void emu_time_f32(EMU_ARGS, float* x) { apply_time<float>(EMU_P, x); }
+void emu_precond_f64(EMU_ARGS, const double* x, double* y) { apply_precond<double>(EMU_P, x, y); }
+void emu_precond_f32(EMU_ARGS, const float* x, float* y) { apply_precond<float>(EMU_P, x, y); }
+double emu_sym_f64(EMU_ARGS, const double* x, double* y, int force_fft) {
+  return apply_sym<double>(EMU_P, x, y, force_fft != 0);
+}
+double emu_sym_f32(EMU_ARGS, const float* x, float* y, int force_fft) {
+  return apply_sym<float>(EMU_P, x, y, force_fft != 0);
+}
+
+}  // extern "C"

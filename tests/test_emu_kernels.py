@@ -1,0 +1,95 @@
+"""CPU emulation of the HIP kernel bodies against the oracle.
+
+The same __host__ __device__ kernel code that runs on the MI355X is executed
+workgroup by workgroup on host threads (tests/native/emu.cpp), with NaN guard
+zones around every buffer.  Sizes span several workgroups and ragged tails.
+"""
+import numpy as np
+import pytest
+
+from oracle import bltt_oracle as O
+from paper_2307_07749_amd import workloads as W
+from tests import emu_lib as E
+
+TOL = {np.float64: 1e-12, np.float32: 2e-5}
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def prob_of(kind, dim, m, N, alpha=0.05, gamma=0.4):
+    if kind == "frac":
+        return W.fractional_l1(dim, m, N, gamma, alpha)
+    if kind == "heat":
+        return W.heat_bdf(dim, m, N, alpha)
+    if kind == "cn":
+        return W.heat_cn(dim, m, N, alpha)
+    raise ValueError(kind)
+
+
+SPACE_CASES = [(1, 1, 2), (1, 7, 4), (1, 31, 8), (2, 3, 4), (2, 7, 2), (2, 15, 4), (3, 3, 4), (3, 7, 2),
+               (1, 255, 2), (2, 63, 2)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("dim,m,N", SPACE_CASES)
+def test_space_transform(dim, m, N, dtype):
+    prob = prob_of("frac", dim, m, N)
+    x = np.random.default_rng(dim * 100 + m).standard_normal(prob.n)
+    got = E.space(prob, x, dtype)
+    ref = O.space_transform(x.reshape(N, -1), prob.m).ravel()
+    assert rel(got, ref) < TOL[dtype] * 10
+
+
+TIME_CASES = [("frac", 1, 7, 2), ("frac", 1, 7, 4), ("frac", 1, 5, 8), ("frac", 1, 9, 16), ("heat", 2, 3, 32),
+              ("frac", 2, 7, 64), ("cn", 1, 15, 128), ("frac", 1, 3, 256), ("frac", 1, 3, 512),
+              ("frac", 1, 1, 1024), ("heat", 1, 3, 2048)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("kind,dim,m,N", TIME_CASES)
+def test_time_pass(kind, dim, m, N, dtype):
+    prob = prob_of(kind, dim, m, N, alpha=0.05)
+    sysm = O.from_problem(prob)
+    P = O.precond_setup(sysm)
+    x = np.random.default_rng(N + m).standard_normal(prob.n)
+    got = E.time_pass(prob, x, dtype)
+    # time part alone: U P^{-1} U (U symmetric orthogonal)
+    ref = O.space_transform(O.precond_apply(P, O.space_transform(x.reshape(N, -1), prob.m)), prob.m).ravel()
+    tol = TOL[dtype] * (100 if dtype == np.float32 else 1e3)
+    assert rel(got, ref) < tol
+
+
+PRE_CASES = [("frac", 1, 31, 32, 0.01), ("heat", 2, 7, 16, 0.01), ("frac", 2, 15, 8, 0.1), ("cn", 2, 3, 4, 0.5),
+             ("frac", 3, 3, 8, 0.05), ("frac", 1, 63, 64, 0.001)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("kind,dim,m,N,alpha", PRE_CASES)
+def test_precond(kind, dim, m, N, alpha, dtype):
+    prob = prob_of(kind, dim, m, N, alpha=alpha)
+    P = O.precond_setup(O.from_problem(prob))
+    x = np.random.default_rng(7).standard_normal(prob.n)
+    got = E.precond(prob, x, dtype)
+    ref = O.precond_apply(P, x.reshape(N, -1)).ravel()
+    tol = 1e-11 if dtype == np.float64 else 5e-5 / alpha ** 0.5
+    assert rel(got, ref) < tol
+
+
+SYM_CASES = [("frac", 1, 31, 32), ("heat", 2, 7, 16), ("cn", 2, 5, 8), ("frac", 3, 3, 8), ("frac", 2, 15, 64),
+             ("heat", 1, 3, 2), ("frac", 1, 5, 256)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("force_fft", [False, True])
+@pytest.mark.parametrize("kind,dim,m,N", SYM_CASES)
+def test_sym_matvec(kind, dim, m, N, force_fft, dtype):
+    prob = prob_of(kind, dim, m, N)
+    sysm = O.from_problem(prob)
+    z = np.random.default_rng(3).standard_normal(prob.n)
+    got, dot = E.sym(prob, z, dtype, force_fft)
+    ref = O.sym_apply(sysm, z.reshape(N, -1)).ravel()
+    assert rel(got, ref) < TOL[dtype] * 50
+    zz = z.astype(dtype).astype(np.float64)
+    assert abs(dot - np.dot(ref, zz)) <= TOL[dtype] * 50 * np.linalg.norm(ref) * np.linalg.norm(zz)
