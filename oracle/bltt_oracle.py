@@ -391,3 +391,46 @@ def from_problem(prob) -> System:
     """Build a System from a workload description (duck-typed)."""
     return System(tuple(prob.m), tuple(prob.h), np.asarray(prob.p, np.float64),
                   np.asarray(prob.q, np.float64), float(prob.alpha))
+
+
+# ---------------------------------------------------------------------------
+# sampled outputs at sizes where the full oracle is too slow
+# ---------------------------------------------------------------------------
+
+def mode_vectors(sys: System, modes) -> np.ndarray:
+    """Rows of U (the orthonormal sine basis, Remark 1) for the given
+    lexicographic mode indices: shape (len(modes), M)."""
+    rows = []
+    Us = [dst1_matrix(m) for m in sys.ms]
+    for i in modes:
+        vec = np.ones(1)
+        rest = int(i)
+        ks = []
+        for m in sys.ms:
+            ks.append(rest % m)
+            rest //= m
+        for d, m in enumerate(sys.ms):
+            # dimension d is slower than all previous ones: outer factor
+            vec = np.outer(Us[d][ks[d]], vec).ravel()
+        rows.append(vec)
+    return np.array(rows)
+
+
+def project_modes(sys: System, v: np.ndarray, modes) -> np.ndarray:
+    """(U^T v_n)_i for every time step n and each mode i: shape (N, len(modes))."""
+    B = mode_vectors(sys, modes)
+    return v.reshape(sys.N, -1) @ B.T
+
+
+def exact_modes(sys: System, f: np.ndarray, modes) -> np.ndarray:
+    """(U^T u*)_i, u* = A^{-1} f, for the given modes only.  In sine
+    coordinates each mode is an independent lower-triangular Toeplitz system
+    with entries p_k + q_k mu_i (Remark 1), solved by forward substitution."""
+    mu = laplacian_eigs(sys.ms, sys.hs)[list(modes)]
+    ft = project_modes(sys, f, modes)                       # (N, K)
+    lam = sys.p[:, None] + sys.q[:, None] * mu[None, :]     # (N, K)
+    ut = np.zeros_like(ft)
+    for n in range(sys.N):
+        acc = ft[n] - (np.einsum("kj,kj->j", lam[1:n + 1], ut[n - 1::-1][:n]) if n else 0.0)
+        ut[n] = acc / lam[0]
+    return ut

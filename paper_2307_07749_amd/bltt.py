@@ -1,0 +1,194 @@
+"""Python binding of libbltt.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/bltt.h; all
+arithmetic of the solver runs in the library's HIP kernels.  PyTorch supplies
+device memory (tensors) and the current HIP stream.  If the library is not
+built, importing works but constructing a `Solver` raises `BlttUnavailable`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbltt.so")
+
+FP64, MIXED, FP32 = 0, 1, 2
+OK, NOCONV = 0, 1
+STATUS = {0: "BLTT_OK", 1: "BLTT_NOCONV", -1: "BLTT_EINVAL", -2: "BLTT_EASSUMPTION", -3: "BLTT_ENAN",
+          -4: "BLTT_EBREAKDOWN", -5: "BLTT_ENOMEM", -6: "BLTT_EHIP", -7: "BLTT_EUNSUPPORTED"}
+
+
+class BlttUnavailable(RuntimeError):
+    """libbltt.so is missing or cannot be loaded."""
+
+
+class BlttError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Blocks(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("m", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3),
+                ("p", ctypes.POINTER(ctypes.c_double)), ("q", ctypes.POINTER(ctypes.c_double))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("check_factor", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters_inner", ctypes.c_int32), ("iters_outer", ctypes.c_int32), ("true_relres", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("c0", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libbltt.so from the package directory (raises BlttUnavailable)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BlttUnavailable(f"{LIB_PATH} not built; run python -m paper_2307_07749_amd.build_lib")
+    try:
+        L = ctypes.CDLL(LIB_PATH)
+    except OSError as e:  # pragma: no cover - depends on the machine
+        raise BlttUnavailable(str(e)) from e
+    P = ctypes.c_void_p
+    L.bltt_setup.argtypes = [ctypes.POINTER(Blocks), ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                             ctypes.POINTER(Options), P, ctypes.POINTER(P)]
+    L.bltt_setup.restype = ctypes.c_int
+    L.bltt_pminres.argtypes = [P, P, ctypes.c_double, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Info)]
+    L.bltt_pminres.restype = ctypes.c_int
+    for name in ("bltt_apply_sym", "bltt_apply_precond", "bltt_apply_space"):
+        fn = getattr(L, name)
+        fn.argtypes = [P, ctypes.c_int32, P, P]
+        fn.restype = ctypes.c_int
+    L.bltt_destroy.argtypes = [P]
+    L.bltt_destroy.restype = None
+    L.bltt_strerror.argtypes = [ctypes.c_int]
+    L.bltt_strerror.restype = ctypes.c_char_p
+    L.bltt_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return load().bltt_strerror(code).decode()
+
+
+def _check(rc: int, allow=(OK,)) -> int:
+    if rc not in allow:
+        raise BlttError(rc, strerror(rc))
+    return rc
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Solver:
+    """One BLTT instance on the GPU (wraps a bltt_handle).
+
+    Blocks are ``p[k] I + q[k] L_h`` on a ``dim``-dimensional grid with ``m``
+    interior points and spacing ``h`` per dimension (x first)."""
+
+    def __init__(self, dim: int, m, h, p, q, alpha: float, precision: int = FP64, inner_tol: float = 0.0,
+                 max_refine: int = 0, check_factor: float = 0.0, stream=None):
+        L = load()
+        self._L = L
+        m = list(m)
+        h = list(h)
+        self.dim = dim
+        self.m = tuple(m)
+        self.N = len(p)
+        self.M = int(np.prod(m))
+        self.n = self.N * self.M
+        self.precision = precision
+        self._p = np.ascontiguousarray(p, dtype=np.float64)
+        self._q = np.ascontiguousarray(q, dtype=np.float64)
+        blk = Blocks()
+        blk.dim = dim
+        for d in range(3):
+            blk.m[d] = m[d] if d < dim else 1
+            blk.h[d] = h[d] if d < dim else 1.0
+        blk.p = self._p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        blk.q = self._q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        opt = Options(precision, inner_tol, max_refine, check_factor)
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        rc = L.bltt_setup(ctypes.byref(blk), self.N, self.M, float(alpha), ctypes.byref(opt),
+                          ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle))
+        _check(rc)
+        self._h = handle
+
+    @classmethod
+    def from_problem(cls, prob, **kw) -> "Solver":
+        return cls(prob.dim, prob.m, prob.h, prob.p, prob.q, prob.alpha, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.bltt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, x, dtype):
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dtype and x.is_contiguous()
+                and x.numel() == self.n):
+            raise ValueError(f"expected a contiguous CUDA tensor of {self.n} {dtype}")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def pminres(self, f, tol: float, maxit: int, u=None):
+        """Solve A u = f.  Returns (u, iters, hist, info, status)."""
+        import torch
+        fp = self._vec(f, torch.float64)
+        if u is None:
+            u = torch.empty_like(f)
+        up = self._vec(u, torch.float64)
+        iters = ctypes.c_int32(0)
+        hist = np.zeros(maxit + 2, dtype=np.float64)
+        info = Info()
+        rc = self._L.bltt_pminres(self._h, fp, float(tol), int(maxit), up, ctypes.byref(iters),
+                                  hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(info))
+        _check(rc, allow=(OK, NOCONV))
+        return u, int(iters.value), hist[: iters.value + 1].copy(), info.as_dict(), rc
+
+    def _apply(self, name, x, y=None):
+        import torch
+        prec = FP64 if x.dtype == torch.float64 else FP32
+        xp = self._vec(x, x.dtype)
+        if y is None:
+            y = torch.empty_like(x)
+        yp = self._vec(y, x.dtype)
+        _check(getattr(self._L, name)(self._h, prec, xp, yp))
+        return y
+
+    def apply_sym(self, x, y=None):
+        """y = Y A x (float64 -> FP64 kernels, float32 -> FP32 kernels)."""
+        return self._apply("bltt_apply_sym", x, y)
+
+    def apply_precond(self, x, y=None):
+        """y = P_alpha^{-1} x."""
+        return self._apply("bltt_apply_precond", x, y)
+
+    def apply_space(self, x, y=None):
+        """y = (I_N (x) U) x, the orthonormal sine transform of every time slice."""
+        return self._apply("bltt_apply_space", x, y)

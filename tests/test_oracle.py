@@ -389,3 +389,15 @@ def test_paper_table1_counts(row):
     sysm, f = _example1_system_and_rhs(row["N"], row["m_plus_1"], 1e-8)
     assert O.pminres(sysm, f, 1e-6, 100).iters == row["P_alpha"]
     assert O.pminres(sysm, f, 1e-6, 200, precond="none").iters == row["I"]
+
+
+def test_exact_modes_match_full_exact_solution():
+    sysm = tiny("frac", dim=2, m=7, N=8, alpha=0.05)
+    f = np.random.default_rng(9).standard_normal(sysm.N * sysm.M)
+    ustar = O.exact_solve(sysm, f)
+    modes = [0, 5, 17, sysm.M - 1]
+    assert np.allclose(O.exact_modes(sysm, f, modes), O.project_modes(sysm, ustar, modes), rtol=1e-12,
+                       atol=1e-14 * np.abs(ustar).max())
+    # mode vectors are rows of the full transform
+    U = oracle_matrix(lambda e: O.space_transform(e[None, :], sysm.ms)[0], sysm.M)
+    assert np.allclose(O.mode_vectors(sysm, modes), U[modes], atol=1e-14)
