@@ -1,0 +1,205 @@
+#!/usr/bin/env python
+"""Benchmark: time-to-1e-8 PMINRES solve and per-iteration HBM GB/s on one MI355X.
+
+Workload (default): 2D time-fractional sub-diffusion, L1 scheme, gamma = 0.3,
+M = 511^2 interior points (h = 1/512), N = 1024 time steps on T = 1,
+alpha = 0.01, f ~ N(0,1) seeded (seed 3), tolerance 1e-8 on the relative
+symmetrised residual.  A "step" is one complete solve A u = f by the mixed
+path (FP32 MINRES sweeps inside FP64 iterative refinement) with f already in
+HBM; the FP64 path is timed beside it on the same input.
+
+Prints one JSON line (rank 0).  `value` is mixed-path solves per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+HOT_CLASSES = ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update"]
+
+
+def cpu_baseline(workload: str, tol: float, budget_s: float = 12.0) -> dict:
+    """The CPU oracle, as it stands, on a bounded sample of the workload: the
+    same problem with m = 63 (M = 63^2) instead of 511, solved repeatedly until
+    `budget_s` seconds have passed; scaled to the full M linearly (a lower
+    bound on the oracle's time, whose sine transforms grow faster than M)."""
+    import numpy as np
+    from oracle import bltt_oracle as O
+    from paper_2307_07749_amd import workloads as W
+
+    full, seed = W.workload(workload)
+    m_s = 63
+    prob = W.fractional_l1(full.dim, m_s, full.N, full.meta["gamma"], full.alpha)
+    f = W.rhs_normal(prob, seed)
+    sysm = O.from_problem(prob)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    runs = 0
+    while True:
+        res = O.pminres(sysm, f, tol, 200)
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    per = (time.perf_counter() - t0) / runs
+    scale = full.M / prob.M
+    return {"value": 1.0 / (per * scale), "unit": "solve/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle PMINRES (dense DFT/DST products, explicit residual each iteration) on the same "
+                       f"problem with m={m_s} (M={prob.M}), N={full.N}: {per:.2f} s/solve over {runs} run(s), "
+                       f"{res.iters} iterations; scaled linearly by M x{scale:.1f} to M={full.M}")}
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if one exists for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+        entry = data.get(kernel)
+        if not entry:
+            return None
+        import hashlib
+        src = os.path.join(ROOT, "paper_2307_07749_amd", "csrc")
+        h = hashlib.sha256()
+        for name in sorted(os.listdir(src)):
+            if name.endswith((".hip", ".hpp")):
+                with open(os.path.join(src, name), "rb") as fh:
+                    h.update(fh.read())
+        if entry.get("source_sha256") != h.hexdigest():
+            return None
+        return entry.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="frac2d_m511_n1024_g03")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=300)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the solver on one GPU only "
+              f"(one MI355X holds the whole workload; see DESIGN.md for how it would shard)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2307_07749_amd import bltt
+    from paper_2307_07749_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    prob, seed = W.workload(args.workload)
+    f = torch.from_numpy(W.rhs_normal(prob, seed)).cuda()
+    torch.cuda.synchronize()
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    # ---- mixed path (the headline)
+    mixed = bltt.Solver.from_problem(prob, precision=bltt.MIXED)
+    u = torch.empty_like(f)
+    log(f"[bench] {args.workload}: n={prob.n} warmup={args.warmup} steps={args.steps}")
+    for _ in range(args.warmup):
+        mixed.pminres(f, args.tol, args.maxit, u)
+    torch.cuda.synchronize()
+    mixed.profile(True)
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        _, iters, hist, info, rc = mixed.pminres(f, args.tol, args.maxit, u)
+        infos.append((iters, info, rc))
+        log(f"[bench] mixed step {k}: {info['solve_ms']:.1f} ms iters={iters} outer={info['iters_outer']} "
+            f"relres={info['true_relres']:.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = mixed.profile_read()
+    mixed.profile(False)
+    mixed.close()
+    ms_mixed = (t1 - t0) * 1e3 / args.steps
+    iters_mixed, info_mixed, rc_mixed = infos[-1]
+
+    # per-iteration traffic of the hot path (algorithmic bytes / kernel time)
+    hot_ms = sum(prof[c]["ms"] for c in HOT_CLASSES)
+    hot_bytes = sum(prof[c]["bytes"] for c in HOT_CLASSES)
+    dom = max(HOT_CLASSES, key=lambda c: prof[c]["ms"])
+    d = prof[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+    per_launch_bytes = d["bytes"] / max(d["launches"], 1)
+    kernels = {c: {"launches": prof[c]["launches"],
+                   "avg_us": 1e3 * prof[c]["ms"] / max(prof[c]["launches"], 1),
+                   "GBps": prof[c]["bytes"] / (prof[c]["ms"] * 1e-3) / 1e9 if prof[c]["ms"] > 0 else 0.0,
+                   "share": prof[c]["ms"] / max(sum(v["ms"] for v in prof.values()), 1e-12)}
+               for c in prof}
+
+    # ---- FP64 path beside it
+    fp64 = None
+    if not args.no_fp64:
+        s64 = bltt.Solver.from_problem(prob, precision=bltt.FP64)
+        for _ in range(args.warmup):
+            s64.pminres(f, args.tol, args.maxit, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            _, it64, _, info64, rc64 = s64.pminres(f, args.tol, args.maxit, u)
+            log(f"[bench] fp64 step {k}: {info64['solve_ms']:.1f} ms iters={it64} relres={info64['true_relres']:.2e}")
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3 / args.steps
+        s64.close()
+        fp64 = {"ms_per_solve": ms64, "iters": it64, "true_relres": info64["true_relres"],
+                "mixed_speedup": ms64 / ms_mixed}
+
+    out = {
+        "metric": "time-to-1e-8 solve + GB/s per PMINRES iter, 2D M=511²,N=1024, mixed vs FP64",
+        "value": 1e3 / ms_mixed,
+        "unit": "solve/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_mixed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": prob.dim, "m": prob.m[0], "M": prob.M, "N": prob.N,
+                   "gamma": prob.meta.get("gamma"), "alpha": prob.alpha, "tol": args.tol, "seed": seed,
+                   "precision": "mixed (FP32 MINRES sweeps, FP64 refinement)"},
+        "mixed": {"ms_per_solve": ms_mixed, "iters_inner": iters_mixed, "iters_outer": info_mixed["iters_outer"],
+                  "true_relres": info_mixed["true_relres"], "status": int(rc_mixed),
+                  "hot_path_GBps": hot_bytes / (hot_ms * 1e-3) / 1e9 if hot_ms > 0 else 0.0,
+                  "kernels": kernels},
+        "fp64": fp64,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profiles(dom),
+                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "avg_launch_us": 1e3 * d["ms"] / max(d["launches"], 1)},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)...")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

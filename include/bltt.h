@@ -156,6 +156,33 @@ int bltt_apply_sym(bltt_handle *h, int32_t precision, const void *x_dev, void *y
 int bltt_apply_precond(bltt_handle *h, int32_t precision, const void *x_dev, void *y_dev);
 int bltt_apply_space(bltt_handle *h, int32_t precision, const void *x_dev, void *y_dev);
 
+/*
+ * Per-kernel timing of the hot path.  While enabled, every kernel launch the
+ * handle makes is bracketed by HIP events on the handle's stream and its
+ * algorithmic traffic (bytes the step must read and write at least once,
+ * e.g. 2*N*M*sizeof(real) for the time pass) is accumulated per kernel class.
+ * bltt_profile_enable(h, 1) clears the counters and starts recording;
+ * bltt_profile_enable(h, 0) stops.  bltt_profile_read synchronises the
+ * stream and returns, for one kernel class, the number of launches, their
+ * summed duration in milliseconds and the summed algorithmic bytes (any
+ * output pointer may be NULL).
+ * Errors: BLTT_EINVAL (null handle, class out of range), BLTT_EHIP.
+ */
+enum bltt_kernel_class {
+  BLTT_K_MATVEC = 0,        /* q = Y A z, FFT or direct form                     */
+  BLTT_K_DST_X_VUPD = 1,    /* Lanczos update + sine transform along x           */
+  BLTT_K_DST_STRIDED = 2,   /* sine transform along y / z                        */
+  BLTT_K_TIME = 3,          /* alpha-circulant time pass of the preconditioner   */
+  BLTT_K_DST_X_DOT = 4,     /* inverse sine transform along x + dot product      */
+  BLTT_K_WX = 5,            /* MINRES direction and iterate update               */
+  BLTT_K_RESID64 = 6,       /* FP64 residual Y(f - A u)                          */
+  BLTT_K_OTHER = 7,         /* right-hand side, casts, fills, scalar kernels     */
+  BLTT_K_COUNT = 8
+};
+int bltt_profile_enable(bltt_handle *h, int32_t enable);
+int bltt_profile_read(bltt_handle *h, int32_t kernel_class, int64_t *launches, double *total_ms,
+                      double *bytes);
+
 /* Release all device memory and tables of the handle (NULL is a no-op). */
 void bltt_destroy(bltt_handle *h);
 

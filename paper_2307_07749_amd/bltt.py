@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbltt.so")
 
 FP64, MIXED, FP32 = 0, 1, 2
+KERNEL_CLASSES = ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update", "resid64", "other"]
 OK, NOCONV = 0, 1
 STATUS = {0: "BLTT_OK", 1: "BLTT_NOCONV", -1: "BLTT_EINVAL", -2: "BLTT_EASSUMPTION", -3: "BLTT_ENAN",
           -4: "BLTT_EBREAKDOWN", -5: "BLTT_ENOMEM", -6: "BLTT_EHIP", -7: "BLTT_EUNSUPPORTED"}
@@ -74,6 +75,11 @@ def load() -> ctypes.CDLL:
         fn = getattr(L, name)
         fn.argtypes = [P, ctypes.c_int32, P, P]
         fn.restype = ctypes.c_int
+    L.bltt_profile_enable.argtypes = [P, ctypes.c_int32]
+    L.bltt_profile_enable.restype = ctypes.c_int
+    L.bltt_profile_read.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.bltt_profile_read.restype = ctypes.c_int
     L.bltt_destroy.argtypes = [P]
     L.bltt_destroy.restype = None
     L.bltt_strerror.argtypes = [ctypes.c_int]
@@ -188,6 +194,21 @@ class Solver:
     def apply_precond(self, x, y=None):
         """y = P_alpha^{-1} x."""
         return self._apply("bltt_apply_precond", x, y)
+
+    def profile(self, enable: bool):
+        """Start (clearing counters) or stop per-kernel event timing."""
+        _check(self._L.bltt_profile_enable(self._h, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        """{class: {"launches", "ms", "bytes"}} for every kernel class."""
+        out = {}
+        for k, name in enumerate(KERNEL_CLASSES):
+            n = ctypes.c_int64(0)
+            ms = ctypes.c_double(0.0)
+            by = ctypes.c_double(0.0)
+            _check(self._L.bltt_profile_read(self._h, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+            out[name] = {"launches": int(n.value), "ms": float(ms.value), "bytes": float(by.value)}
+        return out
 
     def apply_space(self, x, y=None):
         """y = (I_N (x) U) x, the orthonormal sine transform of every time slice."""

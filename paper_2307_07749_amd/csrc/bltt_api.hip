@@ -82,6 +82,16 @@ struct bltt_handle {
   double* coef_one = nullptr;
   double setup_ms = 0.0;
   std::vector<void*> allocs;
+  // per-kernel timing (bltt_profile_enable)
+  struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
 };
 
 #define HIPCHK(...)                        \
@@ -91,6 +101,38 @@ struct bltt_handle {
   } while (0)
 
 namespace {
+
+hipEvent_t prof_event(bltt_handle* h) {
+  if (h->pool_used == h->pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->pool.push_back(e);
+  }
+  return h->pool[h->pool_used++];
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+  ProfScope(bltt_handle* h_, int cls_, double bytes_) : h(h_), cls(cls_), bytes(bytes_) {
+    if (h->prof) {
+      a = prof_event(h);
+      if (a) (void)hipEventRecord(a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (h->prof && a) {
+      hipEvent_t b = prof_event(h);
+      if (b) {
+        (void)hipEventRecord(b, h->stream);
+        h->recs.push_back({cls, a, b, bytes});
+      }
+    }
+  }
+  bltt_handle* h;
+  int cls;
+  double bytes;
+  hipEvent_t a = nullptr;
+};
 
 template <typename T>
 int dalloc(bltt_handle* h, T** ptr, size_t count) {
@@ -216,6 +258,7 @@ int matvec(bltt_handle* h, int mode, const T* z, T* out, const T* fin, int64_t* 
     tb.grid = make_grid(h);
     tb.N = (int)h->N;
     tb.chunk = 8;
+    ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
     HIPCHK(launch_matvec_short<T>(mode, z, out, fin, h->M, tb, h->partials, np, h->stream));
   } else {
     MatvecTables<T> tb;
@@ -226,6 +269,7 @@ int matvec(bltt_handle* h, int mode, const T* z, T* out, const T* fin, int64_t* 
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
     tb.qtaps = h->qtaps;
     tb.grid = make_grid(h);
+    ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
     HIPCHK(launch_matvec_fft<T>((int)h->N, mode, z, out, fin, h->M, tb, h->partials, h->stream));
     *np = fft_blocks<T>((int)h->N, h->M);
   }
@@ -249,6 +293,7 @@ int space_strided(bltt_handle* h, T* x, bool reverse) {
     int64_t S = 1;
     for (int e = 0; e < d; ++e) S *= h->m[e];
     const int64_t nlines = h->n / h->m[d];
+    ProfScope ps(h, BLTT_K_DST_STRIDED, 2.0 * h->n * sizeof(T));
     HIPCHK(launch_dst_strided<T>(2 * (h->m[d] + 1), x, nlines, S, dst_tables<T>(h, d), h->stream));
   }
   return BLTT_OK;
@@ -263,8 +308,12 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
   int rc;
   const int Lx = 2 * (h->m[0] + 1);
   const int64_t nlx = h->n / h->m[0];
-  HIPCHK(launch_dst_x<T>(Lx, KIND_VUPD, in, v1, v2, vout, nullptr, tmp, nlx, dst_tables<T>(h, 0), coef, nullptr,
-                         h->stream));
+  {
+    const double streams = 2.0 + (v1 ? 1 : 0) + (v2 ? 1 : 0) + (vout ? 1 : 0);
+    ProfScope ps(h, BLTT_K_DST_X_VUPD, streams * h->n * sizeof(T));
+    HIPCHK(launch_dst_x<T>(Lx, KIND_VUPD, in, v1, v2, vout, nullptr, tmp, nlx, dst_tables<T>(h, 0), coef, nullptr,
+                           h->stream));
+  }
   if ((rc = space_strided<T>(h, tmp, false))) return rc;
   TimeTables<T> tt;
   DeviceTables<T>& t = tables<T>(h);
@@ -274,15 +323,22 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
   tt.sigma = t.sigma;
   tt.rho = t.rho;
   tt.mu = t.mu;
-  HIPCHK(launch_time_prec<T>((int)h->N, tmp, h->M, tt, h->stream));
+  {
+    ProfScope ps(h, BLTT_K_TIME, 2.0 * h->n * sizeof(T));
+    HIPCHK(launch_time_prec<T>((int)h->N, tmp, h->M, tt, h->stream));
+  }
   if ((rc = space_strided<T>(h, tmp, true))) return rc;
-  HIPCHK(launch_dst_x<T>(Lx, KIND_DOT, tmp, nullptr, nullptr, nullptr, vdot, zout, nlx, dst_tables<T>(h, 0), coef,
-                         h->partials, h->stream));
+  {
+    ProfScope ps(h, BLTT_K_DST_X_DOT, 3.0 * h->n * sizeof(T));
+    HIPCHK(launch_dst_x<T>(Lx, KIND_DOT, tmp, nullptr, nullptr, nullptr, vdot, zout, nlx, dst_tables<T>(h, 0), coef,
+                           h->partials, h->stream));
+  }
   *np = fft_blocks<T>(Lx, nlx);
   return BLTT_OK;
 }
 
 int scalar(bltt_handle* h, int phase, int64_t np, double* hist) {
+  ProfScope ps(h, BLTT_K_OTHER, 8.0 * np);
   HIPCHK(launch_scalar(phase, h->state, h->partials, np, hist, h->stream));
   return BLTT_OK;
 }
@@ -326,8 +382,11 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   T* Zn = ws.Z[1];
   T* Wa = ws.W[0];
   T* Wb = ws.W[1];
-  HIPCHK(launch_fill<T>(Wa, h->n, T(0), s));
-  HIPCHK(launch_fill<T>(Wb, h->n, T(0), s));
+  {
+    ProfScope ps(h, BLTT_K_OTHER, 2.0 * h->n * sizeof(T));
+    HIPCHK(launch_fill<T>(Wa, h->n, T(0), s));
+    HIPCHK(launch_fill<T>(Wb, h->n, T(0), s));
+  }
   if ((rc = ensure_hist(h, (int64_t)maxit + 2))) return rc;
   // z_1 = P^{-1} b, beta_1 = sqrt(<b, z_1>)
   if ((rc = precond<T>(h, Vc, nullptr, nullptr, nullptr, h->coef_one, ws.Q, Vc, Zc, &np))) return rc;
@@ -344,7 +403,10 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     if ((rc = scalar(h, SC_DELTA, np, nullptr))) return rc;
     if ((rc = precond<T>(h, ws.Q, Vc, j > 1 ? Vp : nullptr, Vn, coef_v, ws.Q, Vn, Zn, &np))) return rc;
     if ((rc = scalar(h, SC_BETA, np, h->hist_dev))) return rc;
-    HIPCHK(launch_wx<T, TX>(Zc, Wa, Wb, X, h->n, coef_w, s));
+    {
+      ProfScope ps(h, BLTT_K_WX, (4.0 * sizeof(T) + 2.0 * sizeof(TX)) * h->n);
+      HIPCHK(launch_wx<T, TX>(Zc, Wa, Wb, X, h->n, coef_w, s));
+    }
     {
       T* t = Vp;
       Vp = Vc;
@@ -417,6 +479,7 @@ void bltt_destroy(bltt_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (void* p : h->allocs) (void)hipFree(p);
+  for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->state_host) (void)hipHostFree(h->state_host);
   delete h;
 }
@@ -533,7 +596,10 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
   hipStream_t s = h->stream;
   int rc;
   int64_t np = 0;
-  HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
+  {
+    ProfScope ps(h, BLTT_K_OTHER, 8.0 * h->n);
+    HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
+  }
   int total_iters = 0, outer = 0;
   double relres = 0.0;
   int status = BLTT_OK;
@@ -541,7 +607,10 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
   if (h->opt.precision == BLTT_FP64) {
     Workspace<double>& ws = h->w64;
     // b = Y f into V[0]
-    HIPCHK(launch_rhs<double>(f_dev, ws.V[0], h->N, h->M, 1.0, h->partials, &np, s));
+    {
+      ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
+      HIPCHK(launch_rhs<double>(f_dev, ws.V[0], h->N, h->M, 1.0, h->partials, &np, s));
+    }
     if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
     if ((rc = read_state(h))) return rc;
     const double bn2 = h->state_host->norm2;
@@ -577,7 +646,10 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
   } else {
     // FP64 refinement around FP32 MINRES sweeps
     Workspace<float>& ws = h->w32;
-    HIPCHK(launch_rhs<double>(f_dev, h->R64, h->N, h->M, 1.0, h->partials, &np, s));
+    {
+      ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
+      HIPCHK(launch_rhs<double>(f_dev, h->R64, h->N, h->M, 1.0, h->partials, &np, s));
+    }
     if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
     if ((rc = read_state(h))) return rc;
     const double bn2 = h->state_host->norm2;
@@ -600,8 +672,11 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
       }
       if (outer >= h->opt.max_refine || total_iters >= maxit) break;
       // inner right-hand side r / ||r|| in FP32 (state->rscale = ||r||)
-      HIPCHK(launch_scale_cast<double, float>(h->R64, ws.V[0], h->n, &h->state->rscale, 1, s));
-      HIPCHK(launch_fill<float>(ws.X, h->n, 0.0f, s));
+      {
+        ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
+        HIPCHK(launch_scale_cast<double, float>(h->R64, ws.V[0], h->n, &h->state->rscale, 1, s));
+        HIPCHK(launch_fill<float>(ws.X, h->n, 0.0f, s));
+      }
       CoreResult cr;
       const int left = maxit - total_iters;
       hbuf.assign((size_t)left + 2, 0.0);
@@ -614,7 +689,10 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
       total_iters += cr.iters;
       outer += 1;
       // u += ||r|| d, then r = Y(f - A u) in FP64
-      HIPCHK(launch_axpy64<float>(u_dev, ws.X, h->n, &h->state->rscale, s));
+      {
+        ProfScope ps(h, BLTT_K_OTHER, 20.0 * h->n);
+        HIPCHK(launch_axpy64<float>(u_dev, ws.X, h->n, &h->state->rscale, s));
+      }
       if ((rc = matvec<double>(h, MV_RESID, u_dev, h->R64, f_dev, &np))) return rc;
       if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
       if ((rc = read_state(h))) return rc;
@@ -700,6 +778,36 @@ int bltt_apply_space(bltt_handle* h, int32_t precision, const void* x_dev, void*
     if ((rc = space_strided<float>(h, (float*)y_dev, false))) return rc;
   }
   HIPCHK(hipStreamSynchronize(h->stream));
+  return BLTT_OK;
+}
+
+int bltt_profile_enable(bltt_handle* h, int32_t enable) {
+  if (!h) return BLTT_EINVAL;
+  if (enable) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->recs.clear();
+    h->pool_used = 0;
+  }
+  h->prof = enable != 0;
+  return BLTT_OK;
+}
+
+int bltt_profile_read(bltt_handle* h, int32_t kernel_class, int64_t* launches, double* total_ms, double* bytes) {
+  if (!h || kernel_class < 0 || kernel_class >= BLTT_K_COUNT) return BLTT_EINVAL;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  int64_t cnt = 0;
+  double ms = 0.0, by = 0.0;
+  for (const auto& r : h->recs) {
+    if (r.cls != kernel_class) continue;
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    ++cnt;
+    ms += t;
+    by += r.bytes;
+  }
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = ms;
+  if (bytes) *bytes = by;
   return BLTT_OK;
 }
 
