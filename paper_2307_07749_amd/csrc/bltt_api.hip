@@ -323,6 +323,9 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
   tt.sigma = t.sigma;
   tt.rho = t.rho;
   tt.mu = t.mu;
+  tt.rho_const = h->qtaps <= 1 ? 1 : 0;
+  tt.rho0 = (T)h->q[0];
+  tt.log2_alpha_over_N = (T)(std::log2(h->alpha) / (double)h->N);
   {
     ProfScope ps(h, BLTT_K_TIME, 2.0 * h->n * sizeof(T));
     HIPCHK(launch_time_prec<T>((int)h->N, tmp, h->M, tt, h->stream));

@@ -29,7 +29,21 @@ namespace bltt {
 
 template <typename T>
 constexpr int tpb_fft() { return sizeof(T) == 4 ? 512 : 256; }
+// minimum waves per SIMD requested from the compiler for the FFT kernels
+// (1: no constraint beyond the workgroup size)
+template <typename T>
+constexpr int waves_fft() { return 1; }
 constexpr int TPB_EW = 256;  // elementwise / streaming kernels
+
+// ---------------------------------------------------------------------------
+// XCD-aware tile order.  Workgroups are dealt round-robin to the 8 XCDs
+// (workgroup b runs on XCD b mod 8), each with its own L2.  Mapping b to tile
+// (b mod 8) * (nb/8) + b/8 gives every XCD a contiguous run of tiles, so
+// neighbouring tiles (which share 128-byte lines at their edges and stencil
+// rows) run at the same time on the same L2.  nb must be a multiple of 8;
+// tiles past the end are empty (every load and store is masked).
+// ---------------------------------------------------------------------------
+BLTT_HD int64_t xcd_tile(int bid, int nb) { return (int64_t)(bid & 7) * (nb >> 3) + (bid >> 3); }
 
 // ---------------------------------------------------------------------------
 // workgroup sum of one double per thread, result valid in thread 0
@@ -77,6 +91,54 @@ BLTT_HD T lap_at(const T* __restrict__ z, int64_t base, int64_t i, const Grid& g
   return acc;
 }
 
+// Neighbour offsets of one spatial point, computed once per thread (the
+// point is fixed; only the time row changes).
+struct Stencil {
+  int64_t off[6];  // +-stride per dimension, 0 when the neighbour is the boundary
+  float has[6];    // 1 inside, 0 on the boundary
+  int nd;
+};
+
+BLTT_HD Stencil make_stencil(int64_t i, const Grid& gr) {
+  Stencil st;
+  int64_t rest = i, stride = 1;
+  st.nd = gr.dim;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < gr.dim) {
+      const int md = gr.m[d];
+      const int coord = (int)(rest % md);
+      rest /= md;
+      st.off[2 * d] = coord > 0 ? -stride : 0;
+      st.has[2 * d] = coord > 0 ? 1.f : 0.f;
+      st.off[2 * d + 1] = coord < md - 1 ? stride : 0;
+      st.has[2 * d + 1] = coord < md - 1 ? 1.f : 0.f;
+      stride *= md;
+    } else {
+      st.off[2 * d] = st.off[2 * d + 1] = 0;
+      st.has[2 * d] = st.has[2 * d + 1] = 0.f;
+    }
+  }
+  return st;
+}
+
+// (L_h z)_i on the row starting at zrow (zrow points at element (n, i))
+template <typename T>
+BLTT_HD T lap_row(const T* __restrict__ zrow, const Stencil& st, const Grid& gr) {
+  const T zc = zrow[0];
+  T acc = T(0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < st.nd) {
+      T s = T(2) * zc;
+      if (st.has[2 * d] != 0.f) s -= zrow[st.off[2 * d]];
+      if (st.has[2 * d + 1] != 0.f) s -= zrow[st.off[2 * d + 1]];
+      acc += T(gr.inv_h2[d]) * s;
+    }
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
 // matvec, FFT form: (A z)_n = sum_{k<=n} p_k z_{n-k} + sum_{k<qtaps} q_k L_h z_{n-k}
 // The lower-triangular Toeplitz product is (C + S)/2 with C the circulant and
@@ -107,15 +169,17 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
   constexpr int N = L;
   const int tid = ctx.tid, c = tid % NL, g = tid / NL;
-  const int64_t ia = (int64_t)ctx.bid * (2 * NL) + 2 * c, ib = ia + 1;
+  const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
+  const T* za = z + ia;
+  const T* zb = z + ib;
 
   cx<T> v[V], acc[V];
   // circulant part
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int64_t n = g + t * s0;
-    v[t] = mkc<T>(va ? z[n * M + ia] : T(0), vb ? z[n * M + ib] : T(0));
+    const int64_t off = (int64_t)(g + t * s0) * M;
+    v[t] = mkc<T>(va ? za[off] : T(0), vb ? zb[off] : T(0));
   }
   F::forward(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
@@ -128,8 +192,9 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   // skew-circulant part
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int64_t n = g + t * s0;
-    v[t] = mkc<T>(va ? z[n * M + ia] : T(0), vb ? z[n * M + ib] : T(0)) * tb.phi[n];
+    const int n = g + t * s0;
+    const int64_t off = (int64_t)n * M;
+    v[t] = mkc<T>(va ? za[off] : T(0), vb ? zb[off] : T(0)) * tb.phi[n];
   }
   F::forward(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
@@ -138,37 +203,41 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
     for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.shat[F::freq(g, w, u)];
   F::inverse(ctx, v, lds, c, g, tb.tw);
 
+  const Stencil sta = make_stencil(va ? ia : 0, tb.grid);
+  const Stencil stb = make_stencil(vb ? ib : 0, tb.grid);
+  T* oa = out + ia;
+  T* ob = out + ib;
   double part = 0.0;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int64_t n = g + t * s0;
-    cx<T> y = acc[t] + v[t] * conjg(tb.phi[n]);
+    const int n = g + t * s0;
+    const cx<T> y = acc[t] + v[t] * conjg(tb.phi[n]);
     T ya = y.re, yb = y.im;
-    for (int k = 0; k < tb.qtaps; ++k) {
-      if (k > n) break;
-      const int64_t base = (n - k) * M;
-      if (va) ya += tb.q[k] * lap_at(z, base, ia, tb.grid);
-      if (vb) yb += tb.q[k] * lap_at(z, base, ib, tb.grid);
+    for (int k = 0; k < tb.qtaps && k <= n; ++k) {
+      const int64_t off = (int64_t)(n - k) * M;
+      if (va) ya += tb.q[k] * lap_row(za + off, sta, tb.grid);
+      if (vb) yb += tb.q[k] * lap_row(zb + off, stb, tb.grid);
     }
-    const int64_t nr = (int64_t)(N - 1) - n;
+    const int64_t offr = (int64_t)(N - 1 - n) * M;
     if (MODE == MV_DOT) {
       if (va) {
-        out[nr * M + ia] = ya;
-        part += (double)ya * (double)z[nr * M + ia];
+        oa[offr] = ya;
+        part += (double)ya * (double)za[offr];
       }
       if (vb) {
-        out[nr * M + ib] = yb;
-        part += (double)yb * (double)z[nr * M + ib];
+        ob[offr] = yb;
+        part += (double)yb * (double)zb[offr];
       }
     } else {
+      const int64_t off = (int64_t)n * M;
       if (va) {
-        const T r = fin[n * M + ia] - ya;
-        out[nr * M + ia] = r;
+        const T r = fin[ia + off] - ya;
+        oa[offr] = r;
         part += (double)r * (double)r;
       }
       if (vb) {
-        const T r = fin[n * M + ib] - yb;
-        out[nr * M + ib] = r;
+        const T r = fin[ib + off] - yb;
+        ob[offr] = r;
         part += (double)r * (double)r;
       }
     }
@@ -239,6 +308,29 @@ struct DstTables {
   T nrm;            // 1/sqrt(L) = sqrt(2/(m+1))/2
 };
 
+// The odd extension holds every value twice (e_p and e_{L-p} = -e_p).  Only
+// the positions 1..m are loaded from memory; the mirrored half is filled from
+// LDS after one barrier.  The FFT that follows synchronises before it first
+// writes LDS, so the mirror reads cannot race with it.
+template <class F, typename T, int L, class Ctx>
+BLTT_HD void odd_mirror(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g) {
+  constexpr int V = fft_V(L), s0 = fft_sigma(L, 0), m = L / 2 - 1;
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int p = g + t * s0;
+    if (p >= 1 && p <= m) lds[F::idx(c, p)] = v[t];
+  }
+  ctx.sync();
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int p = g + t * s0;
+    if (p >= m + 2) {
+      const cx<T> w = lds[F::idx(c, L - p)];
+      v[t] = mkc<T>(-w.re, -w.im);
+    }
+  }
+}
+
 // Lines along x (contiguous).  KIND_VUPD: input is the Lanczos update
 // cq*Q + cv*V1 + cvp*V2 (optionally written to vout) -> out = U_x(input).
 // KIND_DOT: out = U_x(in) and partial sums of <vdot, out>.
@@ -270,16 +362,15 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
   for (int t = 0; t < V; ++t) {
     const int p = g + t * s0;
     T a = T(0), b = T(0);
-    if (p != 0 && p != m + 1) {
-      const bool lo = p <= m;
-      const int xi = lo ? p - 1 : L - 1 - p;
+    if (p >= 1 && p <= m) {
+      const int xi = p - 1;
       if (va) {
         const int64_t e = la * m + xi;
         a = cq * in[e];
         if (KIND == KIND_VUPD) {
           if (v1) a += cv * v1[e];
           if (v2) a += cvp * v2[e];
-          if (vout && lo) vout[e] = a;  // vout never aliases in, v1, v2
+          if (vout) vout[e] = a;  // vout never aliases in, v1, v2
         }
       }
       if (vb) {
@@ -288,16 +379,13 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
         if (KIND == KIND_VUPD) {
           if (v1) b += cv * v1[e];
           if (v2) b += cvp * v2[e];
-          if (vout && lo) vout[e] = b;
+          if (vout) vout[e] = b;
         }
-      }
-      if (!lo) {
-        a = -a;
-        b = -b;
       }
     }
     v[t] = mkc<T>(a, b);
   }
+  odd_mirror<F, T, L>(ctx, v, lds, c, g);
   F::forward(ctx, v, lds, c, g, tb.tw);
   double part = 0.0;
 #pragma unroll
@@ -335,7 +423,7 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
   using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
   const int m = L / 2 - 1;
   const int tid = ctx.tid, c = tid % NL, g = tid / NL;
-  const int64_t la = (int64_t)ctx.bid * (2 * NL) + 2 * c, lb = la + 1;
+  const int64_t la = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, lb = la + 1;
   const bool va = la < nlines, vb = lb < nlines;
   const int64_t basea = (la / S) * S * m + (la % S);
   const int64_t baseb = (lb / S) * S * m + (lb % S);
@@ -344,18 +432,14 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
   for (int t = 0; t < V; ++t) {
     const int p = g + t * s0;
     T a = T(0), b = T(0);
-    if (p != 0 && p != m + 1) {
-      const bool lo = p <= m;
-      const int64_t xi = lo ? p - 1 : L - 1 - p;
+    if (p >= 1 && p <= m) {
+      const int64_t xi = p - 1;
       if (va) a = x[basea + xi * S];
       if (vb) b = x[baseb + xi * S];
-      if (!lo) {
-        a = -a;
-        b = -b;
-      }
     }
     v[t] = mkc<T>(a, b);
   }
+  odd_mirror<F, T, L>(ctx, v, lds, c, g);
   F::forward(ctx, v, lds, c, g, tb.tw);
   // all reads of this workgroup's lines happened before the barriers inside forward()
 #pragma unroll
@@ -387,19 +471,110 @@ struct TimeTables {
   const T* dinv;       // alpha^{-n/N}
   const T* d2;         // alpha^{2n/N}
   const cx<T>* sigma;  // fft(alpha^{j/N} p_j)
-  const cx<T>* rho;    // fft(alpha^{j/N} q_j)
+  const cx<T>* rho;    // fft(alpha^{j/N} q_j); unused when rho_const is set
   const T* mu;         // length M, Laplacian eigenvalue of each sine mode
+  T rho0;              // q_0 when q has a single tap (rho_k = q_0 for all k)
+  int rho_const;
+  T log2_alpha_over_N; // log2(alpha)/N for the FP32 scalings
 };
 
-// 1 / (N s) with s the principal square root of lambda (Re lambda > 0):
-// s = sqrt((|l| + Re l)/2) + i Im l / (2 sqrt((|l| + Re l)/2)), 1/s = conj(s)/|l|.
-template <typename T>
-BLTT_HD cx<T> inv_sqrt_scaled(cx<T> lam, T invN) {
-  const T r = sqrt(lam.re * lam.re + lam.im * lam.im);
-  const T sr = sqrt((r + lam.re) * T(0.5));
-  const T si = lam.im / (T(2) * sr);
-  const T f = invN / r;
-  return mkc<T>(sr * f, -si * f);
+// 1 / (N s), s the principal square root of lambda (Re lambda > 0, Definition 2):
+// with r = |lambda|, s = sqrt((r + Re l)/2) + i Im l / (2 sqrt((r + Re l)/2))
+// and 1/s = conj(s)/r.  FP32 uses the hardware reciprocal square root.
+BLTT_HD cx<float> inv_sqrt_scaled(cx<float> lam, float invN) {
+  const float r2 = lam.re * lam.re + lam.im * lam.im;
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+#else
+  const float rinv = 1.0f / sqrtf(r2);
+#endif
+  const float r = r2 * rinv;
+  const float t = (r + lam.re) * 0.5f;
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float w = __builtin_amdgcn_rsqf(t);
+#else
+  const float w = 1.0f / sqrtf(t);
+#endif
+  const float sr = t * w, si = 0.5f * lam.im * w;
+  const float f = invN * rinv;
+  return mkc<float>(sr * f, -si * f);
+}
+BLTT_HD cx<double> inv_sqrt_scaled(cx<double> lam, double invN) {
+  const double r = sqrt(lam.re * lam.re + lam.im * lam.im);
+  const double sr = sqrt((r + lam.re) * 0.5);
+  const double si = lam.im / (2.0 * sr);
+  const double f = invN / r;
+  return mkc<double>(sr * f, -si * f);
+}
+
+// alpha^{e n / N}: FP32 evaluates exp2 on the fly, FP64 reads the table.
+BLTT_HD float alpha_pow_n(const TimeTables<float>& tb, const float* tab, float e, int n) {
+  (void)tab;
+  return exp2f(e * tb.log2_alpha_over_N * (float)n);
+}
+BLTT_HD double alpha_pow_n(const TimeTables<double>& tb, const double* tab, double e, int n) {
+  (void)tb;
+  (void)e;
+  return tab[n];
+}
+
+// One k <-> L-k pair of the two-for-one spectral step.  Z1 holds frequency k1
+// of the packed line (mode a real part, mode b imaginary part), Z2 frequency
+// L - k1.  The multipliers of frequency L - k are the conjugates of those of k.
+template <typename T, int HALF, bool SELF>
+BLTT_HD void spectral_pair(cx<T>& Z1, cx<T>& Z2, int k1, T mua, T mub, const TimeTables<T>& tb, T invN) {
+  const cx<T> sg = tb.sigma[k1];
+  const cx<T> rh = tb.rho_const ? mkc<T>(tb.rho0, T(0)) : tb.rho[k1];
+  cx<T> ga = inv_sqrt_scaled(sg + rh * mua, invN);
+  cx<T> gb = inv_sqrt_scaled(sg + rh * mub, invN);
+  if (HALF == 0) {
+    ga = conjg(ga);
+    gb = conjg(gb);
+  }
+  if (SELF) {
+    // k1 = L - k1: A = Re Z, i B = i Im Z, multipliers real
+    Z1 = mkc<T>(Z1.re * ga.re - Z1.im * gb.im, Z1.re * ga.im + Z1.im * gb.re);
+    return;
+  }
+  const cx<T> c2 = conjg(Z2), c1 = conjg(Z1);
+  const cx<T> n1 = ((Z1 + c2) * ga + (Z1 - c2) * gb) * T(0.5);
+  const cx<T> n2 = ((Z2 + c1) * conjg(ga) + (Z2 - c1) * conjg(gb)) * T(0.5);
+  Z1 = n1;
+  Z2 = n2;
+}
+
+template <typename T, int L, class F, int HALF>
+BLTT_HD void time_spectral(cx<T>* v, int g, T mua, T mub, const TimeTables<T>& tb, T invN) {
+  constexpr int RL = F::RL, NB = F::V / RL, K = F::K;
+  if constexpr (F::S == 1) {
+    spectral_pair<T, HALF, true>(v[0], v[0], 0, mua, mub, tb, invN);
+#pragma unroll
+    for (int u = 1; u < L / 2; ++u) spectral_pair<T, HALF, false>(v[u], v[L - u], u, mua, mub, tb, invN);
+    if constexpr (L >= 2) spectral_pair<T, HALF, true>(v[L / 2], v[L / 2], L / 2, mua, mub, tb, invN);
+  } else {
+    constexpr int PP = NB / 2;
+#pragma unroll
+    for (int p = 0; p < PP; ++p) {
+      const int q = g * PP + p;
+      cx<T>* s0 = v + (2 * p) * RL;
+      cx<T>* s1 = v + (2 * p + 1) * RL;
+      if (q != 0) {
+#pragma unroll
+        for (int u = 0; u < RL; ++u)
+          spectral_pair<T, HALF, false>(s0[u], s1[RL - 1 - u], q + u * K, mua, mub, tb, invN);
+      } else {
+        // butterflies k_low = 0 and k_low = K/2 are each closed under k -> L-k
+        spectral_pair<T, HALF, true>(s0[0], s0[0], 0, mua, mub, tb, invN);
+#pragma unroll
+        for (int u = 1; u < RL / 2; ++u)
+          spectral_pair<T, HALF, false>(s0[u], s0[RL - u], u * K, mua, mub, tb, invN);
+        spectral_pair<T, HALF, true>(s0[RL / 2], s0[RL / 2], (RL / 2) * K, mua, mub, tb, invN);
+#pragma unroll
+        for (int u = 0; u < RL / 2; ++u)
+          spectral_pair<T, HALF, false>(s1[u], s1[RL - 1 - u], K / 2 + u * K, mua, mub, tb, invN);
+      }
+    }
+  }
 }
 
 template <typename T, int L, class Ctx>
@@ -408,58 +583,38 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t M,
   constexpr int TPB = tpb_fft<T>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   using F = LineFft<T, L, NL, true, LAST_PAIRED>;
-  constexpr int RL = F::RL, NB = V / RL;
   const T invN = T(1) / T(L);
   const int tid = ctx.tid, c = tid % NL, g = tid / NL;
-  const int64_t ia = (int64_t)ctx.bid * (2 * NL) + 2 * c, ib = ia + 1;
+  const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const int64_t ma = ia < M ? ia : M - 1;
   const T mua = tb.mu[ma], mub = vb ? tb.mu[ib] : mua;
+  T* xa = x + ia;
+  T* xb = x + ib;
 
   cx<T> v[V];
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int64_t n = g + t * s0;
-    const T d = tb.dinv[n];
-    v[t] = mkc<T>(va ? x[n * M + ia] * d : T(0), vb ? x[n * M + ib] * d : T(0));
+    const int n = g + t * s0;
+    const T d = alpha_pow_n(tb, tb.dinv, T(-1), n);
+    const int64_t off = (int64_t)n * M;
+    v[t] = mkc<T>(va ? xa[off] * d : T(0), vb ? xb[off] * d : T(0));
   }
+  F::forward(ctx, v, lds, c, g, tb.tw);
+  time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN);
+  F::inverse(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    F::forward(ctx, v, lds, c, g, tb.tw);
-    cx<T> nv[V];
-#pragma unroll
-    for (int w = 0; w < NB; ++w) {
-#pragma unroll
-      for (int u = 0; u < RL; ++u) {
-        const int k = F::freq(g, w, u);
-        int w2, u2;
-        F::partner(g, w, u, w2, u2);
-        const cx<T> zk = v[w * RL + u];
-        const cx<T> zp = conjg(v[w2 * RL + u2]);
-        const cx<T> sg = tb.sigma[k], rh = tb.rho[k];
-        cx<T> ga = inv_sqrt_scaled(sg + rh * mua, invN);
-        cx<T> gb = inv_sqrt_scaled(sg + rh * mub, invN);
-        if (half == 0) {
-          ga = conjg(ga);
-          gb = conjg(gb);
-        }
-        nv[w * RL + u] = ((zk + zp) * ga + (zk - zp) * gb) * T(0.5);
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < V; ++t) v[t] = nv[t];
-    F::inverse(ctx, v, lds, c, g, tb.tw);
-#pragma unroll
-    for (int t = 0; t < V; ++t) {
-      const int64_t n = g + t * s0;
-      v[t] = v[t] * (half == 0 ? tb.d2[n] : tb.dinv[n]);
-    }
-  }
+  for (int t = 0; t < V; ++t) v[t] = v[t] * alpha_pow_n(tb, tb.d2, T(2), g + t * s0);
+  F::forward(ctx, v, lds, c, g, tb.tw);
+  time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN);
+  F::inverse(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int64_t n = g + t * s0;
-    if (va) x[n * M + ia] = v[t].re;
-    if (vb) x[n * M + ib] = v[t].im;
+    const int n = g + t * s0;
+    const T d = alpha_pow_n(tb, tb.dinv, T(-1), n);
+    const int64_t off = (int64_t)n * M;
+    if (va) xa[off] = v[t].re * d;
+    if (vb) xb[off] = v[t].im * d;
   }
 }
 

@@ -226,25 +226,6 @@ struct LineFft {
     else return klow(g, w) + u * K;
   }
 
-  // register slot holding frequency L - k (mod L) for the slot (w, u)
-  // (PAIRED or single-stage plans only)
-  BLTT_HD static void partner(int g, int w, int u, int& w2, int& u2) {
-    if constexpr (S == 1) {
-      w2 = 0;
-      u2 = (L - u) % L;
-    } else {
-      constexpr int PP = V / (2 * RL);
-      const int q = g * PP + (w >> 1);
-      if (q == 0) {
-        w2 = w;
-        u2 = ((w & 1) == 0) ? (RL - u) % RL : RL - 1 - u;
-      } else {
-        w2 = w ^ 1;
-        u2 = RL - 1 - u;
-      }
-    }
-  }
-
   // ---- forward: v[w*r0+t] = x[pos<0>(beta<0>(g,w),t)]  ->  v[w*RL+u] = X[freq(g,w,u)]
   template <class Ctx>
   BLTT_HD static void forward(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {

@@ -5,7 +5,7 @@
 namespace bltt {
 
 template <typename T, int L, int KIND>
-__global__ __launch_bounds__(tpb_fft<T>()) void k_dst_x(const T* in, const T* __restrict__ v1,
+__global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_dst_x(const T* in, const T* __restrict__ v1,
                                                         const T* __restrict__ v2, T* __restrict__ vout,
                                                         const T* __restrict__ vdot, T* out,
                                                         int64_t nlines, DstTables<T> tb,
@@ -21,7 +21,7 @@ __global__ __launch_bounds__(tpb_fft<T>()) void k_dst_x(const T* in, const T* __
 }
 
 template <typename T, int L>
-__global__ __launch_bounds__(tpb_fft<T>()) void k_dst_strided(T* __restrict__ x, int64_t nlines, int64_t S,
+__global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_dst_strided(T* __restrict__ x, int64_t nlines, int64_t S,
                                                               DstTables<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   DevCtx ctx = make_ctx();

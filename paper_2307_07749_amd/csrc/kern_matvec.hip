@@ -4,7 +4,7 @@
 namespace bltt {
 
 template <typename T, int L, int MODE>
-__global__ __launch_bounds__(tpb_fft<T>()) void k_matvec_fft(const T* __restrict__ z, T* __restrict__ out,
+__global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_matvec_fft(const T* __restrict__ z, T* __restrict__ out,
                                                              const T* __restrict__ fin, int64_t M,
                                                              MatvecTables<T> tb, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];

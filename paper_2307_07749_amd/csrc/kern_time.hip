@@ -4,7 +4,7 @@
 namespace bltt {
 
 template <typename T, int L>
-__global__ __launch_bounds__(tpb_fft<T>()) void k_time_prec(T* __restrict__ x, int64_t M, TimeTables<T> tb) {
+__global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_time_prec(T* __restrict__ x, int64_t M, TimeTables<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, true, LAST_PAIRED>;

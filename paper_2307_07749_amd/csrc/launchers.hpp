@@ -36,11 +36,13 @@ inline size_t fft_lds_bytes(int L) {
 }
 inline bool fft_length_ok(int L) { return L >= 2 && L <= 2048 && (L & (L - 1)) == 0; }
 
-// Number of partial sums written by the launchers below.
+// Number of workgroups (= partial sums written) of the line-FFT launchers:
+// rounded up to a multiple of 8 for the XCD-aware tile order.
 template <typename T>
 inline int64_t fft_blocks(int L, int64_t units) {  // units = spatial points or lines
   const int64_t per = 2 * (int64_t)lines_per_block<T>(L);
-  return (units + per - 1) / per;
+  const int64_t nb = (units + per - 1) / per;
+  return (nb + 7) / 8 * 8;
 }
 inline int64_t ew_blocks(int64_t n) {
   const int64_t b = (n + TPB_EW - 1) / TPB_EW;

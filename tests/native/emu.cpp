@@ -96,7 +96,7 @@ size_t lds_of(int L) {
 template <typename T>
 int64_t blocks_of(int L, int64_t units) {
   const int64_t per = 2 * (int64_t)nl_of<T>(L);
-  return (units + per - 1) / per;
+  return ((units + per - 1) / per + 7) / 8 * 8;
 }
 
 template <typename T>
@@ -251,6 +251,24 @@ struct HostTables {
 };
 
 template <typename T>
+TimeTables<T> time_tables(const Problem& P, const HostTables<T>& ht) {
+  int qtaps = 0;
+  for (int64_t k = 0; k < P.N; ++k)
+    if (P.q[(size_t)k] != 0.0) qtaps = (int)k + 1;
+  TimeTables<T> tt;
+  tt.tw = ht.tw_time.data();
+  tt.dinv = ht.dinv.data();
+  tt.d2 = ht.d2.data();
+  tt.sigma = ht.sigma.data();
+  tt.rho = ht.rho.data();
+  tt.mu = ht.mu.data();
+  tt.rho_const = qtaps <= 1 ? 1 : 0;
+  tt.rho0 = (T)P.q[0];
+  tt.log2_alpha_over_N = (T)(std::log2(P.alpha) / (double)P.N);
+  return tt;
+}
+
+template <typename T>
 void space_strided(const Problem& P, const HostTables<T>& ht, T* x, bool reverse) {
   const int64_t n = P.N * P.M;
   for (int k = 1; k < P.dim; ++k) {
@@ -274,7 +292,7 @@ void apply_space(const Problem& P, const T* x, T* y) {
 template <typename T>
 void apply_time(const Problem& P, T* x) {
   HostTables<T> ht(P);
-  TimeTables<T> tt{ht.tw_time.data(), ht.dinv.data(), ht.d2.data(), ht.sigma.data(), ht.rho.data(), ht.mu.data()};
+  TimeTables<T> tt = time_tables<T>(P, ht);
   with_L<TimeRun<T>::template R>((int)P.N, x, P.M, tt);
 }
 
@@ -288,7 +306,7 @@ void apply_precond(const Problem& P, const T* x, T* y) {
   with_L<DstXRun<T>::template R>(Lx, x, tmp.data(), n / P.m[0], ht.dst(P, 0), one, (double*)nullptr,
                                  (const T*)nullptr, (int)KIND_VUPD);
   space_strided<T>(P, ht, tmp.data(), false);
-  TimeTables<T> tt{ht.tw_time.data(), ht.dinv.data(), ht.d2.data(), ht.sigma.data(), ht.rho.data(), ht.mu.data()};
+  TimeTables<T> tt = time_tables<T>(P, ht);
   with_L<TimeRun<T>::template R>((int)P.N, tmp.data(), P.M, tt);
   space_strided<T>(P, ht, tmp.data(), true);
   std::vector<double> partials((size_t)blocks_of<T>(Lx, n / P.m[0]) + 1);
