@@ -31,9 +31,8 @@ struct DeviceTables {
   cx<T>* sigma = nullptr;
   cx<T>* rho = nullptr;
   T* mu = nullptr;
-  cx<T>* chat = nullptr;
-  cx<T>* shat = nullptr;
-  cx<T>* phi = nullptr;
+  cx<T>* tw_mv = nullptr;  // length 2N
+  cx<T>* phat = nullptr;
   bool ready = false;
 };
 
@@ -75,6 +74,8 @@ struct bltt_handle {
   double* R64 = nullptr;
   double* partials = nullptr;
   int64_t partials_cap = 0;
+  double* partials_aux = nullptr;  // time pass: spatial part of the next <q, z>
+  int64_t np_aux = 0;
   SolverState* state = nullptr;
   SolverState* state_host = nullptr;
   double* hist_dev = nullptr;
@@ -179,6 +180,8 @@ Workspace<float>& workspace<float>(bltt_handle* h) { return h->w32; }
 template <>
 Workspace<double>& workspace<double>(bltt_handle* h) { return h->w64; }
 
+bool short_p(const bltt_handle* h) { return h->ptaps <= 8; }
+
 template <typename T>
 int build_tables(bltt_handle* h) {
   DeviceTables<T>& t = tables<T>(h);
@@ -192,9 +195,10 @@ int build_tables(bltt_handle* h) {
   if ((rc = upload_c<T>(h, &t.sigma, host::alpha_spectrum(h->p, h->alpha)))) return rc;
   if ((rc = upload_c<T>(h, &t.rho, host::alpha_spectrum(h->q, h->alpha)))) return rc;
   if ((rc = upload<T>(h, &t.mu, host::lap_eigs(h->dim, h->m, h->h)))) return rc;
-  if ((rc = upload_c<T>(h, &t.chat, host::matvec_spectrum(h->p, false)))) return rc;
-  if ((rc = upload_c<T>(h, &t.shat, host::matvec_spectrum(h->p, true)))) return rc;
-  if ((rc = upload_c<T>(h, &t.phi, host::skew_phase(h->N)))) return rc;
+  if (!short_p(h)) {
+    if ((rc = upload_c<T>(h, &t.tw_mv, host::twiddles((int)(2 * h->N))))) return rc;
+    if ((rc = upload_c<T>(h, &t.phat, host::matvec_spectrum(h->p)))) return rc;
+  }
   t.ready = true;
   return BLTT_OK;
 }
@@ -228,8 +232,6 @@ Grid make_grid(const bltt_handle* h) {
   return g;
 }
 
-bool short_p(const bltt_handle* h) { return h->ptaps <= 8; }
-
 template <typename T>
 int64_t partials_needed(const bltt_handle* h) {
   int64_t need = ew_blocks(h->n);
@@ -238,16 +240,18 @@ int64_t partials_needed(const bltt_handle* h) {
     const int64_t gy = ((h->N + 1) / 2 + 7) / 8;
     need = std::max(need, gx * gy);
   } else {
-    need = std::max(need, fft_blocks<T>((int)h->N, h->M));
+    need = std::max(need, fft_blocks<T>((int)(2 * h->N), h->M));
   }
   need = std::max(need, fft_blocks<T>(2 * (h->m[0] + 1), h->n / h->m[0]));
   return need;
 }
 
 // q = Y A z (MV_DOT, partial sums of <q, z>) or out = Y (fin - A z) (MV_RESID,
-// partial sums of the squared norm)
+// partial sums of the squared norm).  With stencil false, MV_DOT forms only
+// Y (p * z): inside MINRES the spatial term is added by the x-line pass of the
+// preconditioner and its share of <q, z> comes from the preceding time pass.
 template <typename T>
-int matvec(bltt_handle* h, int mode, const T* z, T* out, const T* fin, int64_t* np) {
+int matvec(bltt_handle* h, int mode, bool stencil, const T* z, T* out, const T* fin, int64_t* np) {
   DeviceTables<T>& t = tables<T>(h);
   if (short_p(h)) {
     ShortTables<T> tb;
@@ -258,20 +262,20 @@ int matvec(bltt_handle* h, int mode, const T* z, T* out, const T* fin, int64_t* 
     tb.grid = make_grid(h);
     tb.N = (int)h->N;
     tb.chunk = 8;
+    tb.stencil = stencil ? 1 : 0;
     ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
     HIPCHK(launch_matvec_short<T>(mode, z, out, fin, h->M, tb, h->partials, np, h->stream));
   } else {
     MatvecTables<T> tb;
-    tb.tw = t.tw_time;
-    tb.chat = t.chat;
-    tb.shat = t.shat;
-    tb.phi = t.phi;
+    tb.tw = t.tw_mv;
+    tb.phat = t.phat;
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
     tb.qtaps = h->qtaps;
     tb.grid = make_grid(h);
     ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
-    HIPCHK(launch_matvec_fft<T>((int)h->N, mode, z, out, fin, h->M, tb, h->partials, h->stream));
-    *np = fft_blocks<T>((int)h->N, h->M);
+    HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), mode, stencil ? 1 : 0, z, out, fin, h->M, tb, h->partials,
+                                h->stream));
+    *np = fft_blocks<T>((int)(2 * h->N), h->M);
   }
   return BLTT_OK;
 }
@@ -303,16 +307,31 @@ int space_strided(bltt_handle* h, T* x, bool reverse) {
 // vout when non-null); tmp is scratch and may equal `in`; partial sums of
 // <vdot, zout> are left in h->partials (count in *np).
 template <typename T>
+VupdStencil<T> vupd_stencil(bltt_handle* h, const T* z) {
+  VupdStencil<T> st;
+  st.z = z;
+  for (int k = 0; k < 4; ++k) st.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
+  st.qtaps = h->qtaps;
+  st.grid = make_grid(h);
+  st.N = (int)h->N;
+  st.R = h->M / h->m[0];
+  return st;
+}
+
+// zstencil: z_j whose spatial matvec term joins the Lanczos update (nullptr:
+// none).  aux: when true the time pass also leaves the spatial part of the
+// next <q, z> in h->partials_aux.
+template <typename T>
 int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, const double* coef, T* tmp,
-            const T* vdot, T* zout, int64_t* np) {
+            const T* vdot, T* zout, int64_t* np, const T* zstencil = nullptr, bool aux = false) {
   int rc;
   const int Lx = 2 * (h->m[0] + 1);
   const int64_t nlx = h->n / h->m[0];
   {
-    const double streams = 2.0 + (v1 ? 1 : 0) + (v2 ? 1 : 0) + (vout ? 1 : 0);
+    const double streams = 2.0 + (v1 ? 1 : 0) + (v2 ? 1 : 0) + (vout ? 1 : 0) + (zstencil ? 1 : 0);
     ProfScope ps(h, BLTT_K_DST_X_VUPD, streams * h->n * sizeof(T));
     HIPCHK(launch_dst_x<T>(Lx, KIND_VUPD, in, v1, v2, vout, nullptr, tmp, nlx, dst_tables<T>(h, 0), coef, nullptr,
-                           h->stream));
+                           vupd_stencil<T>(h, zstencil), h->stream));
   }
   if ((rc = space_strided<T>(h, tmp, false))) return rc;
   TimeTables<T> tt;
@@ -326,6 +345,10 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
   tt.rho_const = h->qtaps <= 1 ? 1 : 0;
   tt.rho0 = (T)h->q[0];
   tt.log2_alpha_over_N = (T)(std::log2(h->alpha) / (double)h->N);
+  for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
+  tt.qtaps = h->qtaps;
+  tt.aux = aux ? h->partials_aux : nullptr;
+  if (aux) h->np_aux = fft_blocks<T>((int)h->N, h->M);
   {
     ProfScope ps(h, BLTT_K_TIME, 2.0 * h->n * sizeof(T));
     HIPCHK(launch_time_prec<T>((int)h->N, tmp, h->M, tt, h->stream));
@@ -334,15 +357,16 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
   {
     ProfScope ps(h, BLTT_K_DST_X_DOT, 3.0 * h->n * sizeof(T));
     HIPCHK(launch_dst_x<T>(Lx, KIND_DOT, tmp, nullptr, nullptr, nullptr, vdot, zout, nlx, dst_tables<T>(h, 0), coef,
-                           h->partials, h->stream));
+                           h->partials, vupd_stencil<T>(h, nullptr), h->stream));
   }
   *np = fft_blocks<T>(Lx, nlx);
   return BLTT_OK;
 }
 
-int scalar(bltt_handle* h, int phase, int64_t np, double* hist) {
+int scalar(bltt_handle* h, int phase, int64_t np, double* hist, bool with_aux = false) {
   ProfScope ps(h, BLTT_K_OTHER, 8.0 * np);
-  HIPCHK(launch_scalar(phase, h->state, h->partials, np, hist, h->stream));
+  HIPCHK(launch_scalar(phase, h->state, h->partials, np, with_aux ? h->partials_aux : nullptr,
+                       with_aux ? h->np_aux : 0, hist, h->stream));
   return BLTT_OK;
 }
 
@@ -392,7 +416,7 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   }
   if ((rc = ensure_hist(h, (int64_t)maxit + 2))) return rc;
   // z_1 = P^{-1} b, beta_1 = sqrt(<b, z_1>)
-  if ((rc = precond<T>(h, Vc, nullptr, nullptr, nullptr, h->coef_one, ws.Q, Vc, Zc, &np))) return rc;
+  if ((rc = precond<T>(h, Vc, nullptr, nullptr, nullptr, h->coef_one, ws.Q, Vc, Zc, &np, nullptr, true))) return rc;
   if ((rc = scalar(h, SC_START, np, h->hist_dev))) return rc;
   if ((rc = read_state(h))) return rc;
   if (h->state_host->status == -3) return BLTT_ENAN;
@@ -402,9 +426,9 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   res->status = BLTT_NOCONV;
   int j = 0;
   for (j = 1; j <= maxit; ++j) {
-    if ((rc = matvec<T>(h, MV_DOT, Zc, ws.Q, nullptr, &np))) return rc;
-    if ((rc = scalar(h, SC_DELTA, np, nullptr))) return rc;
-    if ((rc = precond<T>(h, ws.Q, Vc, j > 1 ? Vp : nullptr, Vn, coef_v, ws.Q, Vn, Zn, &np))) return rc;
+    if ((rc = matvec<T>(h, MV_DOT, false, Zc, ws.Q, nullptr, &np))) return rc;
+    if ((rc = scalar(h, SC_DELTA, np, nullptr, true))) return rc;
+    if ((rc = precond<T>(h, ws.Q, Vc, j > 1 ? Vp : nullptr, Vn, coef_v, ws.Q, Vn, Zn, &np, Zc, true))) return rc;
     if ((rc = scalar(h, SC_BETA, np, h->hist_dev))) return rc;
     {
       ProfScope ps(h, BLTT_K_WX, (4.0 * sizeof(T) + 2.0 * sizeof(TX)) * h->n);
@@ -426,7 +450,7 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     if (eta_rel <= eta_tol || st.status == 1) {
       if (f_dev) {
         if constexpr (sizeof(TX) == 8 && sizeof(T) == 8) {
-          if ((rc = matvec<double>(h, MV_RESID, (const double*)X, (double*)ws.Q, f_dev, &np))) return rc;
+          if ((rc = matvec<double>(h, MV_RESID, true, (const double*)X, (double*)ws.Q, f_dev, &np))) return rc;
           if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
           if ((rc = read_state(h))) return rc;
           res->relres = std::sqrt(h->state_host->norm2) / bnorm;
@@ -567,6 +591,9 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   };
   h->partials_cap = std::max(partials_needed<float>(h), partials_needed<double>(h));
   if ((rc = dalloc(h, &h->partials, (size_t)h->partials_cap))) return fail(rc);
+  if ((rc = dalloc(h, &h->partials_aux,
+                   (size_t)std::max(fft_blocks<float>((int)h->N, h->M), fft_blocks<double>((int)h->N, h->M)))))
+    return fail(rc);
   if ((rc = dalloc(h, &h->state, 1))) return fail(rc);
   if (hipHostMalloc((void**)&h->state_host, sizeof(SolverState), hipHostMallocDefault) != hipSuccess)
     return fail(BLTT_ENOMEM);
@@ -641,7 +668,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     status = cr.status;
     relres = cr.relres;
     if (relres < 0.0) {
-      if ((rc = matvec<double>(h, MV_RESID, u_dev, ws.Q, f_dev, &np))) return rc;
+      if ((rc = matvec<double>(h, MV_RESID, true, u_dev, ws.Q, f_dev, &np))) return rc;
       if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
       if ((rc = read_state(h))) return rc;
       relres = std::sqrt(h->state_host->norm2) / bnorm;
@@ -696,7 +723,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         ProfScope ps(h, BLTT_K_OTHER, 20.0 * h->n);
         HIPCHK(launch_axpy64<float>(u_dev, ws.X, h->n, &h->state->rscale, s));
       }
-      if ((rc = matvec<double>(h, MV_RESID, u_dev, h->R64, f_dev, &np))) return rc;
+      if ((rc = matvec<double>(h, MV_RESID, true, u_dev, h->R64, f_dev, &np))) return rc;
       if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
       if ((rc = read_state(h))) return rc;
       rnorm = std::sqrt(h->state_host->norm2);
@@ -737,9 +764,9 @@ int bltt_apply_sym(bltt_handle* h, int32_t precision, const void* x_dev, void* y
   if (rc) return rc;
   int64_t np = 0;
   if (precision == BLTT_FP64)
-    rc = matvec<double>(h, MV_DOT, (const double*)x_dev, (double*)y_dev, nullptr, &np);
+    rc = matvec<double>(h, MV_DOT, true, (const double*)x_dev, (double*)y_dev, nullptr, &np);
   else
-    rc = matvec<float>(h, MV_DOT, (const float*)x_dev, (float*)y_dev, nullptr, &np);
+    rc = matvec<float>(h, MV_DOT, true, (const float*)x_dev, (float*)y_dev, nullptr, &np);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(h->stream));
   return BLTT_OK;
@@ -773,11 +800,13 @@ int bltt_apply_space(bltt_handle* h, int32_t precision, const void* x_dev, void*
   const int64_t nlx = h->n / h->m[0];
   if (precision == BLTT_FP64) {
     HIPCHK(launch_dst_x<double>(Lx, KIND_VUPD, (const double*)x_dev, nullptr, nullptr, nullptr, nullptr,
-                                (double*)y_dev, nlx, dst_tables<double>(h, 0), h->coef_one, nullptr, h->stream));
+                                (double*)y_dev, nlx, dst_tables<double>(h, 0), h->coef_one, nullptr,
+                                vupd_stencil<double>(h, nullptr), h->stream));
     if ((rc = space_strided<double>(h, (double*)y_dev, false))) return rc;
   } else {
     HIPCHK(launch_dst_x<float>(Lx, KIND_VUPD, (const float*)x_dev, nullptr, nullptr, nullptr, nullptr,
-                               (float*)y_dev, nlx, dst_tables<float>(h, 0), h->coef_one, nullptr, h->stream));
+                               (float*)y_dev, nlx, dst_tables<float>(h, 0), h->coef_one, nullptr,
+                               vupd_stencil<float>(h, nullptr), h->stream));
     if ((rc = space_strided<float>(h, (float*)y_dev, false))) return rc;
   }
   HIPCHK(hipStreamSynchronize(h->stream));

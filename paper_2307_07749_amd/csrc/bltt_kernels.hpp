@@ -140,19 +140,20 @@ BLTT_HD T lap_row(const T* __restrict__ zrow, const Stencil& st, const Grid& gr)
 }
 
 // ---------------------------------------------------------------------------
-// matvec, FFT form: (A z)_n = sum_{k<=n} p_k z_{n-k} + sum_{k<qtaps} q_k L_h z_{n-k}
-// The lower-triangular Toeplitz product is (C + S)/2 with C the circulant and
-// S the skew-circulant with first column p:  C z = ifft(fft(p) fft(z)) and
-// S z = conj(phi) ifft(fft(phi p) fft(phi z)), phi_n = exp(i pi n/N).
+// matvec, FFT form: (A z)_n = sum_{k<=n} p_k z_{n-k} + sum_{k<qtaps} q_k L_h z_{n-k}.
+// The causal Toeplitz product along time is the first N samples of the cyclic
+// convolution of length L = 2N of z padded with N zeros: ifft(fft(p) fft(z)).
 // Two spatial points are packed as the real and imaginary part of one complex
-// line (every operation is complex-linear with a real kernel).
+// line (every operation is complex-linear with a real kernel).  The time
+// reversal Y is applied on the store; <Y A z, z> needs z at the mirrored time,
+// which comes from LDS.  With STENCIL false only Y (p * z) is formed (and its
+// dot with z): inside MINRES the spatial term is added by the x-line pass and
+// its dot product by the preceding time pass (sine coordinates).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct MatvecTables {
-  const cx<T>* tw;     // length N: exp(-2 pi i k/N)
-  const cx<T>* chat;   // length N: fft(p)/(2N)
-  const cx<T>* shat;   // length N: fft(phi p)/(2N)
-  const cx<T>* phi;    // length N: exp(i pi n/N)
+  const cx<T>* tw;    // length 2N: exp(-2 pi i k/(2N))
+  const cx<T>* phat;  // length 2N: fft(p padded to 2N)/(2N)
   T q[4];
   int qtaps;
   Grid grid;
@@ -160,48 +161,41 @@ struct MatvecTables {
 
 enum { MV_DOT = 0, MV_RESID = 1 };
 
-template <typename T, int L, int MODE, class Ctx>
+template <typename T, int L, int MODE, bool STENCIL, class Ctx>
 BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict__ z,
                              T* __restrict__ out, const T* __restrict__ fin, int64_t M,
                              const MatvecTables<T>& tb, double* __restrict__ partials) {
   constexpr int TPB = tpb_fft<T>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
+  constexpr int N = L / 2, VH = V / 2;  // slots t < VH hold times g + t*s0 < N
   using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
-  constexpr int N = L;
   const int tid = ctx.tid, c = tid % NL, g = tid / NL;
   const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const T* za = z + ia;
   const T* zb = z + ib;
 
-  cx<T> v[V], acc[V];
-  // circulant part
+  cx<T> v[V], zin[VH];
 #pragma unroll
-  for (int t = 0; t < V; ++t) {
+  for (int t = 0; t < VH; ++t) {
     const int64_t off = (int64_t)(g + t * s0) * M;
-    v[t] = mkc<T>(va ? za[off] : T(0), vb ? zb[off] : T(0));
+    zin[t] = mkc<T>(va ? za[off] : T(0), vb ? zb[off] : T(0));
+    v[t] = zin[t];
   }
+#pragma unroll
+  for (int t = VH; t < V; ++t) v[t] = mkc<T>(T(0), T(0));
   F::forward(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
   for (int w = 0; w < V / F::RL; ++w)
 #pragma unroll
-    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.chat[F::freq(g, w, u)];
+    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.phat[F::freq(g, w, u)];
   F::inverse(ctx, v, lds, c, g, tb.tw);
+
+  // z at the mirrored time N-1-n, for <Y A z, z>
+  ctx.sync();
 #pragma unroll
-  for (int t = 0; t < V; ++t) acc[t] = v[t];
-  // skew-circulant part
-#pragma unroll
-  for (int t = 0; t < V; ++t) {
-    const int n = g + t * s0;
-    const int64_t off = (int64_t)n * M;
-    v[t] = mkc<T>(va ? za[off] : T(0), vb ? zb[off] : T(0)) * tb.phi[n];
-  }
-  F::forward(ctx, v, lds, c, g, tb.tw);
-#pragma unroll
-  for (int w = 0; w < V / F::RL; ++w)
-#pragma unroll
-    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.shat[F::freq(g, w, u)];
-  F::inverse(ctx, v, lds, c, g, tb.tw);
+  for (int t = 0; t < VH; ++t) lds[F::idx(c, g + t * s0)] = zin[t];
+  ctx.sync();
 
   const Stencil sta = make_stencil(va ? ia : 0, tb.grid);
   const Stencil stb = make_stencil(vb ? ib : 0, tb.grid);
@@ -209,24 +203,26 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   T* ob = out + ib;
   double part = 0.0;
 #pragma unroll
-  for (int t = 0; t < V; ++t) {
+  for (int t = 0; t < VH; ++t) {
     const int n = g + t * s0;
-    const cx<T> y = acc[t] + v[t] * conjg(tb.phi[n]);
-    T ya = y.re, yb = y.im;
-    for (int k = 0; k < tb.qtaps && k <= n; ++k) {
-      const int64_t off = (int64_t)(n - k) * M;
-      if (va) ya += tb.q[k] * lap_row(za + off, sta, tb.grid);
-      if (vb) yb += tb.q[k] * lap_row(zb + off, stb, tb.grid);
+    T ya = v[t].re, yb = v[t].im;
+    if (STENCIL) {
+      for (int k = 0; k < tb.qtaps && k <= n; ++k) {
+        const int64_t off = (int64_t)(n - k) * M;
+        if (va) ya += tb.q[k] * lap_row(za + off, sta, tb.grid);
+        if (vb) yb += tb.q[k] * lap_row(zb + off, stb, tb.grid);
+      }
     }
     const int64_t offr = (int64_t)(N - 1 - n) * M;
     if (MODE == MV_DOT) {
+      const cx<T> zr = lds[F::idx(c, N - 1 - n)];
       if (va) {
         oa[offr] = ya;
-        part += (double)ya * (double)za[offr];
+        part += (double)ya * (double)zr.re;
       }
       if (vb) {
         ob[offr] = yb;
-        part += (double)yb * (double)zb[offr];
+        part += (double)yb * (double)zr.im;
       }
     } else {
       const int64_t off = (int64_t)n * M;
@@ -257,7 +253,8 @@ struct ShortTables {
   int qtaps;
   Grid grid;
   int N;
-  int chunk;  // time steps per thread (from the first half)
+  int chunk;    // time steps per thread (from the first half)
+  int stencil;  // 0: only Y (p * z); the spatial term is added by the x-line pass
 };
 
 template <typename T, int MODE, class Ctx>
@@ -277,7 +274,8 @@ BLTT_HD void matvec_short_body(Ctx& ctx, double* red, const T* __restrict__ z, T
         if (side == 1 && n == nn) break;  // odd N: middle step once
         T y = T(0);
         for (int k = 0; k < tb.ptaps && k <= n; ++k) y += tb.p[k] * z[(int64_t)(n - k) * M + i];
-        for (int k = 0; k < tb.qtaps && k <= n; ++k) y += tb.q[k] * lap_at(z, (int64_t)(n - k) * M, i, tb.grid);
+        if (tb.stencil)
+          for (int k = 0; k < tb.qtaps && k <= n; ++k) y += tb.q[k] * lap_at(z, (int64_t)(n - k) * M, i, tb.grid);
         const int64_t nr = (int64_t)(N - 1 - n);
         if (MODE == MV_DOT) {
           out[nr * M + i] = y;
@@ -308,6 +306,45 @@ struct DstTables {
   T nrm;            // 1/sqrt(L) = sqrt(2/(m+1))/2
 };
 
+// Spatial part of the matvec, added where x-lines are streamed: the Lanczos
+// update of line (n, r) needs (Y L_h (q * z))[n, r, x] = sum_k q_k
+// (L_h z)[N-1-n-k, r, x]; the neighbours along y and z are adjacent x-lines.
+// Lines are indexed l = n R + r with R = M / m0 lines per time slice.
+template <typename T>
+struct VupdStencil {
+  const T* z;  // z_j (nullptr: no stencil term)
+  T q[4];
+  int qtaps;
+  Grid grid;
+  int N;
+  int64_t R;
+};
+
+template <typename T>
+BLTT_HD T xline_stencil(const VupdStencil<T>& st, int64_t line, int x) {
+  const int m0 = st.grid.m[0];
+  const int64_t n = line / st.R, r = line - n * st.R;
+  const int yc = st.grid.dim > 1 ? (int)(r % st.grid.m[1]) : 0;
+  const int zc = st.grid.dim > 2 ? (int)(r / st.grid.m[1]) : 0;
+  const T hx = T(st.grid.inv_h2[0]), hy = T(st.grid.inv_h2[1]), hz = T(st.grid.inv_h2[2]);
+  T acc = T(0);
+  for (int k = 0; k < st.qtaps; ++k) {
+    const int64_t nt = (int64_t)st.N - 1 - n - k;
+    if (nt < 0) break;
+    const T* row = st.z + (nt * st.R + r) * m0 + x;
+    const T c = row[0];
+    T s = hx * (T(2) * c - (x > 0 ? row[-1] : T(0)) - (x < m0 - 1 ? row[1] : T(0)));
+    if (st.grid.dim > 1)
+      s += hy * (T(2) * c - (yc > 0 ? row[-m0] : T(0)) - (yc < st.grid.m[1] - 1 ? row[m0] : T(0)));
+    if (st.grid.dim > 2) {
+      const int64_t pl = (int64_t)m0 * st.grid.m[1];
+      s += hz * (T(2) * c - (zc > 0 ? row[-pl] : T(0)) - (zc < st.grid.m[2] - 1 ? row[pl] : T(0)));
+    }
+    acc += st.q[k] * s;
+  }
+  return acc;
+}
+
 // The odd extension holds every value twice (e_p and e_{L-p} = -e_p).  Only
 // the positions 1..m are loaded from memory; the mirrored half is filled from
 // LDS after one barrier.  The FFT that follows synchronises before it first
@@ -332,7 +369,8 @@ BLTT_HD void odd_mirror(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g) {
 }
 
 // Lines along x (contiguous).  KIND_VUPD: input is the Lanczos update
-// cq*Q + cv*V1 + cvp*V2 (optionally written to vout) -> out = U_x(input).
+// cq*(Q + Y L_h (q*z)) + cv*V1 + cvp*V2 (optionally written to vout) ->
+// out = U_x(input); the stencil term is skipped when sten.z is null.
 // KIND_DOT: out = U_x(in) and partial sums of <vdot, out>.
 // `out` may alias `in` (each workgroup owns whole lines and reads them before
 // its first barrier); vout never aliases in, v1 or v2.
@@ -343,7 +381,7 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
                         const T* __restrict__ v1, const T* __restrict__ v2, T* __restrict__ vout,
                         const T* __restrict__ vdot, T* out, int64_t nlines,
                         const DstTables<T>& tb, const double* __restrict__ coef,
-                        double* __restrict__ partials) {
+                        double* __restrict__ partials, const VupdStencil<T>& sten) {
   constexpr int TPB = tpb_fft<T>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   using F = LineFft<T, L, NL, false, LAST_LINEAR>;
@@ -366,7 +404,9 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
       const int xi = p - 1;
       if (va) {
         const int64_t e = la * m + xi;
-        a = cq * in[e];
+        a = in[e];
+        if (KIND == KIND_VUPD && sten.z) a += xline_stencil(sten, la, xi);
+        a *= cq;
         if (KIND == KIND_VUPD) {
           if (v1) a += cv * v1[e];
           if (v2) a += cvp * v2[e];
@@ -375,7 +415,9 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
       }
       if (vb) {
         const int64_t e = lb * m + xi;
-        b = cq * in[e];
+        b = in[e];
+        if (KIND == KIND_VUPD && sten.z) b += xline_stencil(sten, lb, xi);
+        b *= cq;
         if (KIND == KIND_VUPD) {
           if (v1) b += cv * v1[e];
           if (v2) b += cvp * v2[e];
@@ -476,6 +518,9 @@ struct TimeTables {
   T rho0;              // q_0 when q has a single tap (rho_k = q_0 for all k)
   int rho_const;
   T log2_alpha_over_N; // log2(alpha)/N for the FP32 scalings
+  T q[4];              // leading taps of q
+  int qtaps;
+  double* aux;         // per-workgroup sum_i mu_i sum_n (q * t_i)[N-1-n] t_i[n] (or null)
 };
 
 // 1 / (N s), s the principal square root of lambda (Re lambda > 0, Definition 2):
@@ -578,7 +623,7 @@ BLTT_HD void time_spectral(cx<T>* v, int g, T mua, T mub, const TimeTables<T>& t
 }
 
 template <typename T, int L, class Ctx>
-BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t M,
+BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x, int64_t M,
                             const TimeTables<T>& tb) {
   constexpr int TPB = tpb_fft<T>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
@@ -612,9 +657,36 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t M,
   for (int t = 0; t < V; ++t) {
     const int n = g + t * s0;
     const T d = alpha_pow_n(tb, tb.dinv, T(-1), n);
+    v[t] = v[t] * d;
     const int64_t off = (int64_t)n * M;
-    if (va) xa[off] = v[t].re * d;
-    if (vb) xb[off] = v[t].im * d;
+    if (va) xa[off] = v[t].re;
+    if (vb) xb[off] = v[t].im;
+  }
+  if (tb.aux) {
+    // The output t = U z in sine coordinates, where L_h = diag(mu): the
+    // spatial part of the next matvec's <Y A z, z> is
+    // sum_i mu_i sum_n sum_k q_k t_i[N-1-n-k] t_i[n].
+    ctx.sync();
+#pragma unroll
+    for (int t = 0; t < V; ++t) lds[F::idx(c, g + t * s0)] = v[t];
+    ctx.sync();
+    double part = 0.0;
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+      const int n = g + t * s0;
+      double sa = 0.0, sb = 0.0;
+      for (int k = 0; k < tb.qtaps; ++k) {
+        const int nr = L - 1 - n - k;
+        if (nr < 0) break;
+        const cx<T> w = lds[F::idx(c, nr)];
+        sa += (double)tb.q[k] * (double)w.re;
+        sb += (double)tb.q[k] * (double)w.im;
+      }
+      if (va) part += (double)mua * sa * (double)v[t].re;
+      if (vb) part += (double)mub * sb * (double)v[t].im;
+    }
+    const double sum = block_sum<TPB>(ctx, red, part);
+    if (tid == 0) tb.aux[ctx.bid] = sum;
   }
 }
 
@@ -709,14 +781,16 @@ BLTT_HD double reduce_partials(Ctx& ctx, double* red, const double* __restrict__
 enum {
   SC_NORM = 0,   // norm2 = sum                              (rhs / residual norms)
   SC_START = 1,  // beta_1 = sqrt(<b, P^{-1} b>), state reset
-  SC_DELTA = 2,  // delta_j = <q, z_j>, Lanczos coefficients
+  SC_DELTA = 2,  // delta_j = <q, z_j> (matvec part + stencil part), Lanczos coefficients
   SC_BETA = 3    // beta_{j+1}, Givens rotation, w/x coefficients, eta
 };
 
 template <class Ctx>
 BLTT_HD void scalar_body(Ctx& ctx, double* red, int phase, SolverState* __restrict__ st,
-                         const double* __restrict__ partials, int64_t np, double* __restrict__ hist) {
-  const double sum = reduce_partials(ctx, red, partials, np);
+                         const double* __restrict__ partials, int64_t np, const double* __restrict__ aux,
+                         int64_t naux, double* __restrict__ hist) {
+  double sum = reduce_partials(ctx, red, partials, np);
+  if (aux) sum += reduce_partials(ctx, red, aux, naux);
   if (ctx.tid != 0) return;
   if (phase == SC_NORM) {
     st->norm2 = sum;

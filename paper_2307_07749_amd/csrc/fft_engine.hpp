@@ -1,6 +1,6 @@
 // Register/LDS line FFT engine for gfx950 (CDNA4, 64-wide wavefronts).
 //
-// A workgroup holds NL complex "lines" of length L (a power of two, 2..2048).
+// A workgroup holds NL complex "lines" of length L (a power of two, 2..4096).
 // Each line is transformed by G = L/V threads that keep V = min(L,16) complex
 // values in registers.  The transform is an in-place mixed-radix
 // decimation-in-frequency FFT: stage s applies radix r_s butterflies of
@@ -63,12 +63,13 @@ BLTT_HD cx<T> mul_si(cx<T> a) {
 constexpr int fft_V(int L) { return L < 16 ? L : 16; }
 constexpr int fft_S(int L) { return L <= 16 ? 1 : (L <= 128 ? 2 : 3); }
 constexpr int fft_r(int L, int s) {
-  return L <= 16    ? L
-         : L <= 128 ? (s == 0 ? 16 : L / 16)
-         : L == 256 ? (s == 0 ? 16 : 4)
-         : L == 512 ? (s == 0 ? 16 : (s == 1 ? 8 : 4))
+  return L <= 16     ? L
+         : L <= 128  ? (s == 0 ? 16 : L / 16)
+         : L == 256  ? (s == 0 ? 16 : 4)
+         : L == 512  ? (s == 0 ? 16 : (s == 1 ? 8 : 4))
          : L == 1024 ? (s == 0 ? 16 : 8)
-                     : (s == 2 ? 8 : 16);  // 2048
+         : L == 2048 ? (s == 2 ? 8 : 16)
+                     : 16;  // 4096
 }
 constexpr int fft_sigma(int L, int s) {
   int p = 1;

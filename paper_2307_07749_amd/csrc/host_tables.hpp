@@ -5,7 +5,7 @@
 //  * sigma_k = sum_j alpha^{j/N} p_j exp(-2 pi i j k/N) and rho_k likewise
 //    from q, so that lambda_i^{(k,alpha)} = sigma_k + mu_i rho_k (eq. (9) for
 //    blocks p_k I + q_k L_h, whose eigenvalues are p_k + q_k mu_i);
-//  * matvec spectra fft(p)/(2N) and fft(phi p)/(2N), phi_n = exp(i pi n/N);
+//  * matvec spectrum fft(p zero-padded to 2N)/(2N);
 //  * mu_i, the eigenvalue of L_h for each sine mode (Remark 1):
 //    sum_d 4 h_d^-2 sin^2(pi k_d / (2(m_d+1))), k_d = 1..m_d.
 #pragma once
@@ -73,22 +73,15 @@ inline std::vector<cd> alpha_spectrum(const std::vector<double>& c, double alpha
   return dft(s);
 }
 
-inline std::vector<cd> matvec_spectrum(const std::vector<double>& p, bool skew) {
+// fft of p zero-padded to length 2N, divided by 2N (the unnormalised inverse
+// FFT of the kernels then returns the causal convolution directly)
+inline std::vector<cd> matvec_spectrum(const std::vector<double>& p) {
   const int64_t N = (int64_t)p.size();
-  std::vector<cd> s((size_t)N);
-  for (int64_t j = 0; j < N; ++j) {
-    const cd ph = skew ? std::conj(unit_root(j, 2 * N)) : cd(1, 0);  // exp(+i pi j / N)
-    s[(size_t)j] = ph * p[(size_t)j];
-  }
+  std::vector<cd> s((size_t)(2 * N), cd(0, 0));
+  for (int64_t j = 0; j < N; ++j) s[(size_t)j] = cd(p[(size_t)j], 0.0);
   std::vector<cd> out = dft(s);
   for (auto& v : out) v /= (double)(2 * N);
   return out;
-}
-
-inline std::vector<cd> skew_phase(int64_t N) {
-  std::vector<cd> ph((size_t)N);
-  for (int64_t n = 0; n < N; ++n) ph[(size_t)n] = std::conj(unit_root(n, 2 * N));
-  return ph;
 }
 
 inline std::vector<double> lap_eigs_1d(int m, double h) {

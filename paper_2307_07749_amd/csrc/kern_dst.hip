@@ -10,14 +10,14 @@ __global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_dst_x(const T*
                                                         const T* __restrict__ vdot, T* out,
                                                         int64_t nlines, DstTables<T> tb,
                                                         const double* __restrict__ coef,
-                                                        double* __restrict__ partials) {
+                                                        double* __restrict__ partials, VupdStencil<T> sten) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, false, LAST_LINEAR>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
   dst_x_body<T, L, KIND>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, v1, v2, vout, vdot, out, nlines, tb, coef,
-                         partials);
+                         partials, sten);
 }
 
 template <typename T, int L>
@@ -31,15 +31,15 @@ __global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_dst_strided(T*
 template <typename T, int L>
 static hipError_t go_dx(int kind, const T* in, const T* v1, const T* v2, T* vout, const T* vdot, T* out,
                         int64_t nlines, const DstTables<T>& tb, const double* coef, double* partials,
-                        hipStream_t s) {
+                        const VupdStencil<T>& sten, hipStream_t s) {
   const int64_t blocks = fft_blocks<T>(L, nlines);
   const size_t lds = fft_lds_bytes<T>(L);
   if (kind == KIND_VUPD)
     hipLaunchKernelGGL((k_dst_x<T, L, KIND_VUPD>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, in, v1, v2,
-                       vout, vdot, out, nlines, tb, coef, partials);
+                       vout, vdot, out, nlines, tb, coef, partials, sten);
   else
     hipLaunchKernelGGL((k_dst_x<T, L, KIND_DOT>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, in, v1, v2,
-                       vout, vdot, out, nlines, tb, coef, partials);
+                       vout, vdot, out, nlines, tb, coef, partials, sten);
   return hipGetLastError();
 }
 
@@ -54,10 +54,10 @@ static hipError_t go_ds(T* x, int64_t nlines, int64_t S, const DstTables<T>& tb,
 template <typename T>
 hipError_t launch_dst_x(int L, int kind, const T* in, const T* v1, const T* v2, T* vout, const T* vdot, T* out,
                         int64_t nlines, const DstTables<T>& tb, const double* coef, double* partials,
-                        hipStream_t s) {
+                        const VupdStencil<T>& sten, hipStream_t s) {
   switch (L) {
 #define BLTT_CASE(LL) \
-  case LL: return go_dx<T, LL>(kind, in, v1, v2, vout, vdot, out, nlines, tb, coef, partials, s);
+  case LL: return go_dx<T, LL>(kind, in, v1, v2, vout, vdot, out, nlines, tb, coef, partials, sten, s);
     BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64) BLTT_CASE(128) BLTT_CASE(256)
     BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
 #undef BLTT_CASE
@@ -79,7 +79,8 @@ hipError_t launch_dst_strided(int L, T* x, int64_t nlines, int64_t S, const DstT
 
 #define BLTT_INST(T)                                                                                           \
   template hipError_t launch_dst_x<T>(int, int, const T*, const T*, const T*, T*, const T*, T*, int64_t,       \
-                                      const DstTables<T>&, const double*, double*, hipStream_t);               \
+                                      const DstTables<T>&, const double*, double*, const VupdStencil<T>&,      \
+                                      hipStream_t);                                                            \
   template hipError_t launch_dst_strided<T>(int, T*, int64_t, int64_t, const DstTables<T>&, hipStream_t);
 BLTT_INST(float)
 BLTT_INST(double)

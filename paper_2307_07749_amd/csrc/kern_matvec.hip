@@ -1,9 +1,10 @@
-// Symmetrised BLTT matvec q = Y A z: FFT form (dense p) and direct form (short p).
+// Symmetrised BLTT matvec q = Y A z: FFT form (dense p, line length 2N) and
+// direct form (short p).
 #include "launchers.hpp"
 
 namespace bltt {
 
-template <typename T, int L, int MODE>
+template <typename T, int L, int MODE, bool STENCIL>
 __global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_matvec_fft(const T* __restrict__ z, T* __restrict__ out,
                                                              const T* __restrict__ fin, int64_t M,
                                                              MatvecTables<T> tb, double* __restrict__ partials) {
@@ -12,7 +13,7 @@ __global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_matvec_fft(con
   using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
-  matvec_fft_body<T, L, MODE>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb, partials);
+  matvec_fft_body<T, L, MODE, STENCIL>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb, partials);
 }
 
 template <typename T, int MODE>
@@ -25,34 +26,37 @@ __global__ __launch_bounds__(TPB_EW) void k_matvec_short(const T* __restrict__ z
 }
 
 template <typename T, int L>
-static hipError_t go_mv(int mode, const T* z, T* out, const T* fin, int64_t M, const MatvecTables<T>& tb,
-                        double* partials, hipStream_t s) {
+static hipError_t go_mv(int mode, int stencil, const T* z, T* out, const T* fin, int64_t M,
+                        const MatvecTables<T>& tb, double* partials, hipStream_t s) {
   const int64_t blocks = fft_blocks<T>(L, M);
   const size_t lds = fft_lds_bytes<T>(L);
-  if (mode == MV_DOT)
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, z, out,
-                       fin, M, tb, partials);
+  if (mode == MV_DOT && stencil)
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT, true>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, z,
+                       out, fin, M, tb, partials);
+  else if (mode == MV_DOT)
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT, false>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s,
+                       z, out, fin, M, tb, partials);
   else
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_RESID>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, z, out,
-                       fin, M, tb, partials);
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_RESID, true>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s,
+                       z, out, fin, M, tb, partials);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_matvec_fft(int L, int mode, const T* z, T* out, const T* fin, int64_t M,
+hipError_t launch_matvec_fft(int L, int mode, int stencil, const T* z, T* out, const T* fin, int64_t M,
                              const MatvecTables<T>& tb, double* partials, hipStream_t s) {
   switch (L) {
-    case 2: return go_mv<T, 2>(mode, z, out, fin, M, tb, partials, s);
-    case 4: return go_mv<T, 4>(mode, z, out, fin, M, tb, partials, s);
-    case 8: return go_mv<T, 8>(mode, z, out, fin, M, tb, partials, s);
-    case 16: return go_mv<T, 16>(mode, z, out, fin, M, tb, partials, s);
-    case 32: return go_mv<T, 32>(mode, z, out, fin, M, tb, partials, s);
-    case 64: return go_mv<T, 64>(mode, z, out, fin, M, tb, partials, s);
-    case 128: return go_mv<T, 128>(mode, z, out, fin, M, tb, partials, s);
-    case 256: return go_mv<T, 256>(mode, z, out, fin, M, tb, partials, s);
-    case 512: return go_mv<T, 512>(mode, z, out, fin, M, tb, partials, s);
-    case 1024: return go_mv<T, 1024>(mode, z, out, fin, M, tb, partials, s);
-    case 2048: return go_mv<T, 2048>(mode, z, out, fin, M, tb, partials, s);
+    case 4: return go_mv<T, 4>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 8: return go_mv<T, 8>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 16: return go_mv<T, 16>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 32: return go_mv<T, 32>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 64: return go_mv<T, 64>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 128: return go_mv<T, 128>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 256: return go_mv<T, 256>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 512: return go_mv<T, 512>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 1024: return go_mv<T, 1024>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 2048: return go_mv<T, 2048>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 4096: return go_mv<T, 4096>(mode, stencil, z, out, fin, M, tb, partials, s);
   }
   return hipErrorInvalidValue;
 }
@@ -74,7 +78,8 @@ hipError_t launch_matvec_short(int mode, const T* z, T* out, const T* fin, int64
 }
 
 #define BLTT_INST(T)                                                                                          \
-  template hipError_t launch_matvec_fft<T>(int, int, const T*, T*, const T*, int64_t, const MatvecTables<T>&, \
+  template hipError_t launch_matvec_fft<T>(int, int, int, const T*, T*, const T*, int64_t,                  \
+                                           const MatvecTables<T>&,                                           \
                                            double*, hipStream_t);                                            \
   template hipError_t launch_matvec_short<T>(int, const T*, T*, const T*, int64_t, const ShortTables<T>&,     \
                                              double*, int64_t*, hipStream_t);
@@ -84,11 +89,15 @@ BLTT_INST(double)
 
 template <typename T, int L>
 static hipError_t attr_mv() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_DOT>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds_bytes<T>(L));
+  const int bytes = (int)fft_lds_bytes<T>(L);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_DOT, true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_RESID>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds_bytes<T>(L));
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_DOT, false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_RESID, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t configure_matvec_kernels() {
@@ -96,8 +105,8 @@ hipError_t configure_matvec_kernels() {
 #define BLTT_ATTR(L)                                         \
   if ((e = attr_mv<float, L>()) != hipSuccess) return e;    \
   if ((e = attr_mv<double, L>()) != hipSuccess) return e;
-  BLTT_ATTR(2) BLTT_ATTR(4) BLTT_ATTR(8) BLTT_ATTR(16) BLTT_ATTR(32) BLTT_ATTR(64)
-  BLTT_ATTR(128) BLTT_ATTR(256) BLTT_ATTR(512) BLTT_ATTR(1024) BLTT_ATTR(2048)
+  BLTT_ATTR(4) BLTT_ATTR(8) BLTT_ATTR(16) BLTT_ATTR(32) BLTT_ATTR(64) BLTT_ATTR(128)
+  BLTT_ATTR(256) BLTT_ATTR(512) BLTT_ATTR(1024) BLTT_ATTR(2048) BLTT_ATTR(4096)
 #undef BLTT_ATTR
   return e;
 }

@@ -41,10 +41,11 @@ __global__ __launch_bounds__(TPB_EW) void k_axpy64(double* __restrict__ u, const
 
 __global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __restrict__ st,
                                                    const double* __restrict__ partials, int64_t np,
+                                                   const double* __restrict__ aux, int64_t naux,
                                                    double* __restrict__ hist) {
   __shared__ double red[TPB_EW];
   DevCtx ctx = make_ctx();
-  scalar_body(ctx, red, phase, st, partials, np, hist);
+  scalar_body(ctx, red, phase, st, partials, np, aux, naux, hist);
 }
 
 template <typename TO>
@@ -76,9 +77,9 @@ hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, 
   hipLaunchKernelGGL((k_axpy64<TD>), dim3((unsigned)ew_blocks(n)), dim3(TPB_EW), 0, s, u, d, n, sptr);
   return hipGetLastError();
 }
-hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, double* hist,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(TPB_EW), 0, s, phase, st, partials, np, hist);
+hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
+                         int64_t naux, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(TPB_EW), 0, s, phase, st, partials, np, aux, naux, hist);
   return hipGetLastError();
 }
 

@@ -8,9 +8,9 @@ __global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_time_prec(T* _
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, true, LAST_PAIRED>;
-  (void)sizeof(F);
   DevCtx ctx = make_ctx();
-  time_prec_body<T, L>(ctx, reinterpret_cast<cx<T>*>(smem), x, M, tb);
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
+  time_prec_body<T, L>(ctx, reinterpret_cast<cx<T>*>(smem), red, x, M, tb);
 }
 
 template <typename T, int L>

@@ -34,7 +34,6 @@ inline size_t fft_lds_bytes(int L) {
   const size_t LP = (size_t)L + (size_t)(L >> 3);
   return NL * LP * sizeof(cx<T>) + (size_t)tpb_fft<T>() * sizeof(double);
 }
-inline bool fft_length_ok(int L) { return L >= 2 && L <= 2048 && (L & (L - 1)) == 0; }
 
 // Number of workgroups (= partial sums written) of the line-FFT launchers:
 // rounded up to a multiple of 8 for the XCD-aware tile order.
@@ -53,7 +52,7 @@ template <typename T>
 hipError_t launch_time_prec(int L, T* x, int64_t M, const TimeTables<T>& tb, hipStream_t s);
 
 template <typename T>
-hipError_t launch_matvec_fft(int L, int mode, const T* z, T* out, const T* fin, int64_t M,
+hipError_t launch_matvec_fft(int L, int mode, int stencil, const T* z, T* out, const T* fin, int64_t M,
                              const MatvecTables<T>& tb, double* partials, hipStream_t s);
 
 template <typename T>
@@ -63,7 +62,7 @@ hipError_t launch_matvec_short(int mode, const T* z, T* out, const T* fin, int64
 template <typename T>
 hipError_t launch_dst_x(int L, int kind, const T* in, const T* v1, const T* v2, T* vout, const T* vdot, T* out,
                         int64_t nlines, const DstTables<T>& tb, const double* coef, double* partials,
-                        hipStream_t s);
+                        const VupdStencil<T>& sten, hipStream_t s);
 
 template <typename T>
 hipError_t launch_dst_strided(int L, T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s);
@@ -83,7 +82,7 @@ template <typename TI, typename TO>
 hipError_t launch_scale_cast(const TI* x, TO* y, int64_t n, const double* sptr, int invert, hipStream_t s);
 template <typename TD>
 hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, hipStream_t s);
-hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, double* hist,
-                         hipStream_t s);
+hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
+                         int64_t naux, double* hist, hipStream_t s);
 
 }  // namespace bltt

@@ -58,6 +58,11 @@ def lib():
             getattr(L, f"emu_precond_{t}").argtypes = args + [P, P]
             getattr(L, f"emu_sym_{t}").argtypes = args + [P, P, ctypes.c_int]
             getattr(L, f"emu_sym_{t}").restype = ctypes.c_double
+            getattr(L, f"emu_sym_nostencil_{t}").argtypes = args + [P, P, ctypes.c_int]
+            getattr(L, f"emu_sym_nostencil_{t}").restype = ctypes.c_double
+            getattr(L, f"emu_vupd_stencil_{t}").argtypes = args + [P, P, P]
+            getattr(L, f"emu_time_aux_{t}").argtypes = args + [P]
+            getattr(L, f"emu_time_aux_{t}").restype = ctypes.c_double
         L.emu_error.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -139,3 +144,30 @@ def sym(prob, x, dtype=np.float64, force_fft=False):
     dot = getattr(lib(), f"emu_sym_{_tag(dtype)}")(*args, gx.ptr, gy.ptr, int(force_fft))
     _check(gx, gy)
     return gy.data.copy(), dot
+
+
+def sym_nostencil(prob, x, dtype=np.float64, force_fft=False):
+    args, keep = _common(prob)
+    gx = Guarded(x, dtype)
+    gy = Guarded(np.zeros(x.size), dtype)
+    dot = getattr(lib(), f"emu_sym_nostencil_{_tag(dtype)}")(*args, gx.ptr, gy.ptr, int(force_fft))
+    _check(gx, gy)
+    return gy.data.copy(), dot
+
+
+def vupd_stencil(prob, q1, z, dtype=np.float64):
+    args, keep = _common(prob)
+    gq = Guarded(q1, dtype)
+    gz = Guarded(z, dtype)
+    gv = Guarded(np.zeros(q1.size), dtype)
+    getattr(lib(), f"emu_vupd_stencil_{_tag(dtype)}")(*args, gq.ptr, gz.ptr, gv.ptr)
+    _check(gq, gz, gv)
+    return gv.data.copy()
+
+
+def time_aux(prob, x, dtype=np.float64):
+    args, keep = _common(prob)
+    gx = Guarded(x, dtype)
+    s = getattr(lib(), f"emu_time_aux_{_tag(dtype)}")(*args, gx.ptr)
+    _check(gx)
+    return gx.data.copy(), s

@@ -129,13 +129,23 @@ void with_L(int L, A&&... a) {
   }
 }
 
+// matvec line lengths are 2N (4..4096)
+template <template <int> class F, typename... A>
+void with_L2(int L, A&&... a) {
+  if (L == 4096) F<4096>::run(a...);
+  else with_L<F>(L, a...);
+}
+
 template <typename T>
 struct TimeRun {
   template <int L>
   struct R {
     static void run(T* x, int64_t M, const TimeTables<T>& tb) {
+      constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+      using Ft = LineFft<T, L, NL, true, LAST_PAIRED>;
       run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, M), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
-        time_prec_body<T, L>(c, reinterpret_cast<cx<T>*>(lds), x, M, tb);
+        double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Ft::LDS_ELEMS);
+        time_prec_body<T, L>(c, reinterpret_cast<cx<T>*>(lds), red, x, M, tb);
       });
     }
   };
@@ -146,17 +156,17 @@ struct DstXRun {
   template <int L>
   struct R {
     static void run(const T* in, T* out, int64_t nlines, const DstTables<T>& tb, const double* coef,
-                    double* partials, const T* vdot, int kind) {
+                    double* partials, const T* vdot, int kind, T* vout, const VupdStencil<T>& sten) {
       constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
       using Fx = LineFft<T, L, NL, false, LAST_LINEAR>;
       run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, nlines), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
         double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fx::LDS_ELEMS);
         if (kind == KIND_VUPD)
-          dst_x_body<T, L, KIND_VUPD>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr, nullptr,
-                                       nullptr, out, nlines, tb, coef, partials);
+          dst_x_body<T, L, KIND_VUPD>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr, vout,
+                                       nullptr, out, nlines, tb, coef, partials, sten);
         else
           dst_x_body<T, L, KIND_DOT>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr, nullptr, vdot,
-                                      out, nlines, tb, coef, partials);
+                                      out, nlines, tb, coef, partials, sten);
       });
     }
   };
@@ -178,12 +188,16 @@ template <typename T>
 struct MvRun {
   template <int L>
   struct R {
-    static void run(const T* z, T* out, int64_t M, const MatvecTables<T>& tb, double* partials) {
+    static void run(const T* z, T* out, int64_t M, const MatvecTables<T>& tb, double* partials, bool stencil) {
       constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
       using Fm = LineFft<T, L, NL, true, LAST_DEFAULT>;
       run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, M), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
         double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
-        matvec_fft_body<T, L, MV_DOT>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb, partials);
+        if (stencil)
+          matvec_fft_body<T, L, MV_DOT, true>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb, partials);
+        else
+          matvec_fft_body<T, L, MV_DOT, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb,
+                                               partials);
       });
     }
   };
@@ -227,7 +241,7 @@ Grid grid_of(const Problem& P) {
 
 template <typename T>
 struct HostTables {
-  std::vector<cx<T>> tw_time, tw_dst[3], sigma, rho, chat, shat, phi;
+  std::vector<cx<T>> tw_time, tw_dst[3], sigma, rho, tw_mv, phat;
   std::vector<T> dinv, d2, mu;
   explicit HostTables(const Problem& P) {
     tw_time = to_cx<T>(host::twiddles((int)P.N));
@@ -237,9 +251,8 @@ struct HostTables {
     sigma = to_cx<T>(host::alpha_spectrum(P.p, P.alpha));
     rho = to_cx<T>(host::alpha_spectrum(P.q, P.alpha));
     mu = to_t<T>(host::lap_eigs(P.dim, P.m, P.h));
-    chat = to_cx<T>(host::matvec_spectrum(P.p, false));
-    shat = to_cx<T>(host::matvec_spectrum(P.p, true));
-    phi = to_cx<T>(host::skew_phase(P.N));
+    tw_mv = to_cx<T>(host::twiddles((int)(2 * P.N)));
+    phat = to_cx<T>(host::matvec_spectrum(P.p));
   }
   DstTables<T> dst(const Problem& P, int d) const {
     DstTables<T> tb;
@@ -265,7 +278,25 @@ TimeTables<T> time_tables(const Problem& P, const HostTables<T>& ht) {
   tt.rho_const = qtaps <= 1 ? 1 : 0;
   tt.rho0 = (T)P.q[0];
   tt.log2_alpha_over_N = (T)(std::log2(P.alpha) / (double)P.N);
+  for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+  tt.qtaps = qtaps;
+  tt.aux = nullptr;
   return tt;
+}
+
+template <typename T>
+VupdStencil<T> vupd_stencil(const Problem& P, const T* z) {
+  int qtaps = 0;
+  for (int64_t k = 0; k < P.N; ++k)
+    if (P.q[(size_t)k] != 0.0) qtaps = (int)k + 1;
+  VupdStencil<T> st;
+  st.z = z;
+  for (int k = 0; k < 4; ++k) st.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+  st.qtaps = qtaps;
+  st.grid = grid_of(P);
+  st.N = (int)P.N;
+  st.R = P.M / P.m[0];
+  return st;
 }
 
 template <typename T>
@@ -285,7 +316,7 @@ void apply_space(const Problem& P, const T* x, T* y) {
   const int64_t n = P.N * P.M;
   const double one[4] = {1, 0, 0, 0};
   with_L<DstXRun<T>::template R>(2 * (P.m[0] + 1), x, y, n / P.m[0], ht.dst(P, 0), one, (double*)nullptr,
-                                 (const T*)nullptr, (int)KIND_VUPD);
+                                 (const T*)nullptr, (int)KIND_VUPD, (T*)nullptr, vupd_stencil<T>(P, nullptr));
   space_strided<T>(P, ht, y, false);
 }
 
@@ -304,18 +335,18 @@ void apply_precond(const Problem& P, const T* x, T* y) {
   const double one[4] = {1, 0, 0, 0};
   const int Lx = 2 * (P.m[0] + 1);
   with_L<DstXRun<T>::template R>(Lx, x, tmp.data(), n / P.m[0], ht.dst(P, 0), one, (double*)nullptr,
-                                 (const T*)nullptr, (int)KIND_VUPD);
+                                 (const T*)nullptr, (int)KIND_VUPD, (T*)nullptr, vupd_stencil<T>(P, nullptr));
   space_strided<T>(P, ht, tmp.data(), false);
   TimeTables<T> tt = time_tables<T>(P, ht);
   with_L<TimeRun<T>::template R>((int)P.N, tmp.data(), P.M, tt);
   space_strided<T>(P, ht, tmp.data(), true);
   std::vector<double> partials((size_t)blocks_of<T>(Lx, n / P.m[0]) + 1);
   with_L<DstXRun<T>::template R>(Lx, tmp.data(), y, n / P.m[0], ht.dst(P, 0), one, partials.data(), x,
-                                 (int)KIND_DOT);
+                                 (int)KIND_DOT, (T*)nullptr, vupd_stencil<T>(P, nullptr));
 }
 
 template <typename T>
-double apply_sym(const Problem& P, const T* z, T* out, bool force_fft) {
+double apply_sym(const Problem& P, const T* z, T* out, bool force_fft, bool stencil = true) {
   int ptaps = 0, qtaps = 0;
   for (int64_t k = 0; k < P.N; ++k) {
     if (P.p[(size_t)k] != 0.0) ptaps = (int)k + 1;
@@ -331,6 +362,7 @@ double apply_sym(const Problem& P, const T* z, T* out, bool force_fft) {
     tb.grid = grid_of(P);
     tb.N = (int)P.N;
     tb.chunk = 8;
+    tb.stencil = stencil ? 1 : 0;
     const int gx = (int)((P.M + TPB_EW - 1) / TPB_EW);
     const int gy = (int)(((P.N + 1) / 2 + tb.chunk - 1) / tb.chunk);
     std::vector<double> partials((size_t)gx * gy);
@@ -342,18 +374,40 @@ double apply_sym(const Problem& P, const T* z, T* out, bool force_fft) {
   } else {
     HostTables<T> ht(P);
     MatvecTables<T> tb;
-    tb.tw = ht.tw_time.data();
-    tb.chat = ht.chat.data();
-    tb.shat = ht.shat.data();
-    tb.phi = ht.phi.data();
+    tb.tw = ht.tw_mv.data();
+    tb.phat = ht.phat.data();
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
     tb.qtaps = qtaps;
     tb.grid = grid_of(P);
-    std::vector<double> partials((size_t)blocks_of<T>((int)P.N, P.M));
-    with_L<MvRun<T>::template R>((int)P.N, z, out, P.M, tb, partials.data());
+    std::vector<double> partials((size_t)blocks_of<T>((int)(2 * P.N), P.M));
+    with_L2<MvRun<T>::template R>((int)(2 * P.N), z, out, P.M, tb, partials.data(), stencil);
     for (double v : partials) dot += v;
   }
   return dot;
+}
+
+// q1 + Y L_h (q * z) through the x-line pass (coefficients 1, 0, 0)
+template <typename T>
+void apply_vupd_stencil(const Problem& P, const T* q1, const T* z, T* vout) {
+  HostTables<T> ht(P);
+  const int64_t n = P.N * P.M;
+  std::vector<T> tmp((size_t)n);
+  const double one[4] = {1, 0, 0, 0};
+  with_L<DstXRun<T>::template R>(2 * (P.m[0] + 1), q1, tmp.data(), n / P.m[0], ht.dst(P, 0), one,
+                                 (double*)nullptr, (const T*)nullptr, (int)KIND_VUPD, vout, vupd_stencil<T>(P, z));
+}
+
+// time pass in place, returning the summed spatial dot product of its output
+template <typename T>
+double apply_time_aux(const Problem& P, T* x) {
+  HostTables<T> ht(P);
+  TimeTables<T> tt = time_tables<T>(P, ht);
+  std::vector<double> aux((size_t)blocks_of<T>((int)P.N, P.M), 0.0);
+  tt.aux = aux.data();
+  with_L<TimeRun<T>::template R>((int)P.N, x, P.M, tt);
+  double s = 0.0;
+  for (double v : aux) s += v;
+  return s;
 }
 
 }  // namespace
@@ -377,5 +431,19 @@ double emu_sym_f64(EMU_ARGS, const double* x, double* y, int force_fft) {
 double emu_sym_f32(EMU_ARGS, const float* x, float* y, int force_fft) {
   return apply_sym<float>(EMU_P, x, y, force_fft != 0);
 }
+double emu_sym_nostencil_f64(EMU_ARGS, const double* x, double* y, int force_fft) {
+  return apply_sym<double>(EMU_P, x, y, force_fft != 0, false);
+}
+double emu_sym_nostencil_f32(EMU_ARGS, const float* x, float* y, int force_fft) {
+  return apply_sym<float>(EMU_P, x, y, force_fft != 0, false);
+}
+void emu_vupd_stencil_f64(EMU_ARGS, const double* q1, const double* z, double* v) {
+  apply_vupd_stencil<double>(EMU_P, q1, z, v);
+}
+void emu_vupd_stencil_f32(EMU_ARGS, const float* q1, const float* z, float* v) {
+  apply_vupd_stencil<float>(EMU_P, q1, z, v);
+}
+double emu_time_aux_f64(EMU_ARGS, double* x) { return apply_time_aux<double>(EMU_P, x); }
+double emu_time_aux_f32(EMU_ARGS, float* x) { return apply_time_aux<float>(EMU_P, x); }
 
 }  // extern "C"

@@ -77,7 +77,7 @@ def test_precond(kind, dim, m, N, alpha, dtype):
     assert rel(got, ref) < tol
 
 
-SYM_CASES = [("frac", 1, 31, 32), ("heat", 2, 7, 16), ("cn", 2, 5, 8), ("frac", 3, 3, 8), ("frac", 2, 15, 64),
+SYM_CASES = [("frac", 1, 31, 32), ("heat", 2, 7, 16), ("cn", 2, 5, 8), ("frac", 3, 3, 8), ("frac", 2, 15, 64), ("frac", 1, 3, 2048),
              ("heat", 1, 3, 2), ("frac", 1, 5, 256)]
 
 
@@ -93,3 +93,43 @@ def test_sym_matvec(kind, dim, m, N, force_fft, dtype):
     assert rel(got, ref) < TOL[dtype] * 50
     zz = z.astype(dtype).astype(np.float64)
     assert abs(dot - np.dot(ref, zz)) <= TOL[dtype] * 50 * np.linalg.norm(ref) * np.linalg.norm(zz)
+
+
+SPLIT_CASES = [("frac", 1, 31, 32), ("heat", 2, 7, 16), ("cn", 2, 7, 8), ("frac", 3, 3, 8), ("cn", 3, 3, 4),
+               ("frac", 2, 15, 64)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("kind,dim,m,N", SPLIT_CASES)
+def test_split_matvec_equals_full(kind, dim, m, N, dtype):
+    """Inside MINRES the time-line matvec forms Y (p * z) only; the x-line pass
+    adds Y L_h (q * z); the sum must be Y A z."""
+    prob = prob_of(kind, dim, m, N)
+    sysm = O.from_problem(prob)
+    z = np.random.default_rng(13).standard_normal(prob.n)
+    q1, dot1 = E.sym_nostencil(prob, z, dtype, force_fft=True)
+    v = E.vupd_stencil(prob, q1, z, dtype)
+    ref = O.sym_apply(sysm, z.reshape(N, -1)).ravel()
+    assert rel(v, ref) < TOL[dtype] * 50
+    # the time-line part alone: blocks p_k I only
+    psys = O.System(sysm.ms, sysm.hs, sysm.p, np.zeros_like(sysm.q), sysm.alpha)
+    refp = O.sym_apply(psys, z.reshape(N, -1)).ravel()
+    assert rel(q1, refp) < TOL[dtype] * 50
+    zz = z.astype(dtype).astype(np.float64)
+    assert abs(dot1 - np.dot(refp, zz)) <= TOL[dtype] * 50 * np.linalg.norm(refp) * np.linalg.norm(zz)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("kind,dim,m,N", SPLIT_CASES)
+def test_time_pass_spatial_dot(kind, dim, m, N, dtype):
+    """The time pass output t is z in sine coordinates (z = U t); its side
+    output must equal <Y L_h (q * z), z>."""
+    prob = prob_of(kind, dim, m, N)
+    sysm = O.from_problem(prob)
+    x = np.random.default_rng(17).standard_normal(prob.n)
+    t, s = E.time_aux(prob, x, dtype)
+    z = O.space_transform(t.reshape(N, -1), prob.m)
+    qsys = O.System(sysm.ms, sysm.hs, np.zeros_like(sysm.p), sysm.q, sysm.alpha)
+    ref = float(np.vdot(O.sym_apply(qsys, z).ravel(), z.ravel()))
+    scale = np.linalg.norm(O.sym_apply(qsys, z)) * np.linalg.norm(z)
+    assert abs(s - ref) <= TOL[dtype] * 100 * scale

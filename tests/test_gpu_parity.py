@@ -50,7 +50,8 @@ def cuda(x, dtype):
 
 STEP_CASES = [("frac", 1, 31, 32, 0.01), ("heat", 2, 7, 16, 0.01), ("frac", 2, 15, 64, 0.05),
               ("cn", 2, 7, 32, 0.2), ("frac", 3, 7, 8, 0.05), ("frac", 1, 63, 1024, 0.01),
-              ("heat", 1, 3, 2048, 0.01), ("frac", 2, 31, 128, 0.001), ("frac", 1, 1, 2, 0.5)]
+              ("heat", 1, 3, 2048, 0.01), ("frac", 2, 31, 128, 0.001), ("frac", 1, 1, 2, 0.5),
+              ("frac", 1, 3, 2048, 0.01)]
 
 
 @pytest.mark.parametrize("kind,dim,m,N,alpha", STEP_CASES)
