@@ -240,10 +240,23 @@ int64_t partials_needed(const bltt_handle* h) {
     const int64_t gy = ((h->N + 1) / 2 + 7) / 8;
     need = std::max(need, gx * gy);
   } else {
-    need = std::max(need, fft_blocks<T>((int)(2 * h->N), h->M));
+    need = std::max(need, fft_blocks<T, FK_MV>((int)(2 * h->N), h->M));
   }
-  need = std::max(need, fft_blocks<T>(2 * (h->m[0] + 1), h->n / h->m[0]));
+  need = std::max(need, fft_blocks<T, FK_DSTX>(2 * (h->m[0] + 1), h->n / h->m[0]));
+  need = std::max(need, h->n / h->m[0]);  // one partial per x-line (residual stencil pass)
   return need;
+}
+
+template <typename T>
+VupdStencil<T> vupd_stencil(bltt_handle* h, const T* z) {
+  VupdStencil<T> st;
+  st.z = z;
+  for (int k = 0; k < 4; ++k) st.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
+  st.qtaps = h->qtaps;
+  st.grid = make_grid(h);
+  st.N = (int)h->N;
+  st.R = h->M / h->m[0];
+  return st;
 }
 
 // q = Y A z (MV_DOT, partial sums of <q, z>) or out = Y (fin - A z) (MV_RESID,
@@ -272,10 +285,21 @@ int matvec(bltt_handle* h, int mode, bool stencil, const T* z, T* out, const T* 
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
     tb.qtaps = h->qtaps;
     tb.grid = make_grid(h);
-    ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
-    HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), mode, stencil ? 1 : 0, z, out, fin, h->M, tb, h->partials,
-                                h->stream));
-    *np = fft_blocks<T>((int)(2 * h->N), h->M);
+    if (mode == MV_RESID) {
+      // r = Y (f - p * u) on time lines, then the spatial term and ||r||^2 on x-lines
+      const int64_t nlx = h->n / h->m[0];
+      {
+        ProfScope ps(h, BLTT_K_RESID64, 3.0 * h->n * sizeof(T));
+        HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), MV_RESID, 0, z, out, fin, h->M, tb, h->partials, h->stream));
+      }
+      ProfScope ps(h, BLTT_K_RESID64, 3.0 * h->n * sizeof(T));
+      HIPCHK(launch_resid_stencil<T>(out, vupd_stencil<T>(h, z), nlx, h->partials, np, h->stream));
+    } else {
+      ProfScope ps(h, BLTT_K_MATVEC, 2.0 * h->n * sizeof(T));
+      HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), mode, stencil ? 1 : 0, z, out, fin, h->M, tb, h->partials,
+                                  h->stream));
+      *np = fft_blocks<T, FK_MV>((int)(2 * h->N), h->M);
+    }
   }
   return BLTT_OK;
 }
@@ -306,18 +330,6 @@ int space_strided(bltt_handle* h, T* x, bool reverse) {
 // zout = P^{-1} vhat with vhat = coef[0] in + coef[1] v1 + coef[2] v2 (written to
 // vout when non-null); tmp is scratch and may equal `in`; partial sums of
 // <vdot, zout> are left in h->partials (count in *np).
-template <typename T>
-VupdStencil<T> vupd_stencil(bltt_handle* h, const T* z) {
-  VupdStencil<T> st;
-  st.z = z;
-  for (int k = 0; k < 4; ++k) st.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
-  st.qtaps = h->qtaps;
-  st.grid = make_grid(h);
-  st.N = (int)h->N;
-  st.R = h->M / h->m[0];
-  return st;
-}
-
 // zstencil: z_j whose spatial matvec term joins the Lanczos update (nullptr:
 // none).  aux: when true the time pass also leaves the spatial part of the
 // next <q, z> in h->partials_aux.
@@ -342,13 +354,11 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
   tt.sigma = t.sigma;
   tt.rho = t.rho;
   tt.mu = t.mu;
-  tt.rho_const = h->qtaps <= 1 ? 1 : 0;
-  tt.rho0 = (T)h->q[0];
   tt.log2_alpha_over_N = (T)(std::log2(h->alpha) / (double)h->N);
   for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
   tt.qtaps = h->qtaps;
   tt.aux = aux ? h->partials_aux : nullptr;
-  if (aux) h->np_aux = fft_blocks<T>((int)h->N, h->M);
+  if (aux) h->np_aux = fft_blocks<T, FK_TIME>((int)h->N, h->M);
   {
     ProfScope ps(h, BLTT_K_TIME, 2.0 * h->n * sizeof(T));
     HIPCHK(launch_time_prec<T>((int)h->N, tmp, h->M, tt, h->stream));
@@ -359,7 +369,7 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
     HIPCHK(launch_dst_x<T>(Lx, KIND_DOT, tmp, nullptr, nullptr, nullptr, vdot, zout, nlx, dst_tables<T>(h, 0), coef,
                            h->partials, vupd_stencil<T>(h, nullptr), h->stream));
   }
-  *np = fft_blocks<T>(Lx, nlx);
+  *np = fft_blocks<T, FK_DSTX>(Lx, nlx);
   return BLTT_OK;
 }
 
@@ -592,7 +602,8 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   h->partials_cap = std::max(partials_needed<float>(h), partials_needed<double>(h));
   if ((rc = dalloc(h, &h->partials, (size_t)h->partials_cap))) return fail(rc);
   if ((rc = dalloc(h, &h->partials_aux,
-                   (size_t)std::max(fft_blocks<float>((int)h->N, h->M), fft_blocks<double>((int)h->N, h->M)))))
+                   (size_t)std::max(fft_blocks<float, FK_TIME>((int)h->N, h->M),
+                                    fft_blocks<double, FK_TIME>((int)h->N, h->M)))))
     return fail(rc);
   if ((rc = dalloc(h, &h->state, 1))) return fail(rc);
   if (hipHostMalloc((void**)&h->state_host, sizeof(SolverState), hipHostMallocDefault) != hipSuccess)

@@ -27,12 +27,41 @@
 
 namespace bltt {
 
-template <typename T>
-constexpr int tpb_fft() { return sizeof(T) == 4 ? 512 : 256; }
+// Workgroup size of each line-FFT kernel class.  NL = TPB / G lines of length
+// L (G = L/16 threads per line) share a workgroup.
+enum FftKernel { FK_TIME = 0, FK_MV = 1, FK_DSTS = 2, FK_DSTX = 3 };
+template <typename T, int FK>
+constexpr int tpb_fft() {
+  return sizeof(T) == 4 ? 512 : 256;
+}
+template <typename T, int FK>
+constexpr int lines_per_block(int L) {
+  return tpb_fft<T, FK>() / (L / (L < 16 ? L : 16));
+}
+// dynamic LDS: NL padded lines + one double per thread for reductions
+template <typename T, int FK>
+constexpr size_t fft_lds_bytes(int L) {
+  return (size_t)lines_per_block<T, FK>(L) * (size_t)(L + (L >> 3)) * sizeof(cx<T>) +
+         (size_t)tpb_fft<T, FK>() * sizeof(double);
+}
+// workgroups of a launch over `units` spatial points or lines, rounded up to a
+// multiple of 8 for the XCD-aware tile order
+template <typename T, int FK>
+inline int64_t fft_blocks(int L, int64_t units) {
+  const int64_t per = 2 * (int64_t)lines_per_block<T, FK>(L);
+  const int64_t nb = (units + per - 1) / per;
+  return (nb + 7) / 8 * 8;
+}
 // minimum waves per SIMD requested from the compiler for the FFT kernels
 // (1: no constraint beyond the workgroup size)
 template <typename T>
 constexpr int waves_fft() { return 1; }
+// LDS (about 74 KB per workgroup) admits two workgroups per CU, i.e. at most 4
+// waves per SIMD (FP32, 512 threads) or 2 (FP64, 256 threads); telling the
+// compiler so lets its scheduler keep more loads in flight instead of
+// minimising registers for an occupancy that can never be reached.
+template <typename T>
+constexpr int max_waves_fft() { return sizeof(T) == 4 ? 4 : 2; }
 constexpr int TPB_EW = 256;  // elementwise / streaming kernels
 
 // ---------------------------------------------------------------------------
@@ -165,7 +194,7 @@ template <typename T, int L, int MODE, bool STENCIL, class Ctx>
 BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict__ z,
                              T* __restrict__ out, const T* __restrict__ fin, int64_t M,
                              const MatvecTables<T>& tb, double* __restrict__ partials) {
-  constexpr int TPB = tpb_fft<T>();
+  constexpr int TPB = tpb_fft<T, FK_MV>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L / 2, VH = V / 2;  // slots t < VH hold times g + t*s0 < N
   using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
@@ -175,11 +204,13 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   const T* za = z + ia;
   const T* zb = z + ib;
 
+  const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
+  const T wa = va ? T(1) : T(0), wb = vb ? T(1) : T(0);
   cx<T> v[V], zin[VH];
 #pragma unroll
   for (int t = 0; t < VH; ++t) {
     const int64_t off = (int64_t)(g + t * s0) * M;
-    zin[t] = mkc<T>(va ? za[off] : T(0), vb ? zb[off] : T(0));
+    zin[t] = mkc<T>(z[iac + off] * wa, z[ibc + off] * wb);
     v[t] = zin[t];
   }
 #pragma unroll
@@ -320,27 +351,63 @@ struct VupdStencil {
   int64_t R;
 };
 
+// Per-line data of the stencil term for one x-line, computed once per thread.
+// Neighbour rows outside the grid are replaced by the centre row with weight 0
+// so that every load is unconditional (no branches around memory accesses).
 template <typename T>
-BLTT_HD T xline_stencil(const VupdStencil<T>& st, int64_t line, int x) {
+struct LineStencil {
+  const T* row[4];   // centre row at reversed time N-1-n-k, k < 4 (clamped)
+  T wk[4];           // q_k, or 0 when the tap falls before t = 0 or k >= qtaps
+  int64_t dy_m, dy_p, dz_m, dz_p;  // element offsets of the y/z neighbours (0 when outside)
+  T wy_m, wy_p, wz_m, wz_p;
+};
+
+template <typename T>
+BLTT_HD LineStencil<T> line_stencil(const VupdStencil<T>& st, int64_t line) {
+  LineStencil<T> ls;
   const int m0 = st.grid.m[0];
   const int64_t n = line / st.R, r = line - n * st.R;
   const int yc = st.grid.dim > 1 ? (int)(r % st.grid.m[1]) : 0;
   const int zc = st.grid.dim > 2 ? (int)(r / st.grid.m[1]) : 0;
-  const T hx = T(st.grid.inv_h2[0]), hy = T(st.grid.inv_h2[1]), hz = T(st.grid.inv_h2[2]);
-  T acc = T(0);
-  for (int k = 0; k < st.qtaps; ++k) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
     const int64_t nt = (int64_t)st.N - 1 - n - k;
-    if (nt < 0) break;
-    const T* row = st.z + (nt * st.R + r) * m0 + x;
-    const T c = row[0];
-    T s = hx * (T(2) * c - (x > 0 ? row[-1] : T(0)) - (x < m0 - 1 ? row[1] : T(0)));
-    if (st.grid.dim > 1)
-      s += hy * (T(2) * c - (yc > 0 ? row[-m0] : T(0)) - (yc < st.grid.m[1] - 1 ? row[m0] : T(0)));
-    if (st.grid.dim > 2) {
-      const int64_t pl = (int64_t)m0 * st.grid.m[1];
-      s += hz * (T(2) * c - (zc > 0 ? row[-pl] : T(0)) - (zc < st.grid.m[2] - 1 ? row[pl] : T(0)));
-    }
-    acc += st.q[k] * s;
+    const bool ok = nt >= 0 && k < st.qtaps;
+    ls.row[k] = st.z + ((ok ? nt : 0) * st.R + r) * m0;
+    ls.wk[k] = ok ? st.q[k] : T(0);
+  }
+  const bool ym = st.grid.dim > 1 && yc > 0, yp = st.grid.dim > 1 && yc < st.grid.m[1] - 1;
+  const bool zm = st.grid.dim > 2 && zc > 0, zp = st.grid.dim > 2 && zc < st.grid.m[2] - 1;
+  const int64_t pl = (int64_t)m0 * st.grid.m[1];
+  ls.dy_m = ym ? -m0 : 0;
+  ls.dy_p = yp ? m0 : 0;
+  ls.dz_m = zm ? -pl : 0;
+  ls.dz_p = zp ? pl : 0;
+  ls.wy_m = ym ? T(1) : T(0);
+  ls.wy_p = yp ? T(1) : T(0);
+  ls.wz_m = zm ? T(1) : T(0);
+  ls.wz_p = zp ? T(1) : T(0);
+  return ls;
+}
+
+// sum_k q_k (L_h z)[N-1-n-k, r, x] for one element of an x-line.  Dimensions
+// beyond the grid's have zero weight and zero offset, so the same straight-line
+// code (no branches between the loads) serves 1-D, 2-D and 3-D grids.
+template <typename T, bool Q1>
+BLTT_HD T line_stencil_at(const VupdStencil<T>& st, const LineStencil<T>& ls, int x) {
+  const int m0 = st.grid.m[0];
+  const T hx = T(st.grid.inv_h2[0]), hy = T(st.grid.inv_h2[1]), hz = T(st.grid.inv_h2[2]);
+  const int xm = x > 0 ? x - 1 : x, xp = x < m0 - 1 ? x + 1 : x;
+  const T wxm = x > 0 ? T(1) : T(0), wxp = x < m0 - 1 ? T(1) : T(0);
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < (Q1 ? 1 : 4); ++k) {
+    const T* row = ls.row[k];
+    const T c = row[x];
+    const T s = hx * (T(2) * c - wxm * row[xm] - wxp * row[xp]) +
+                hy * (T(2) * c - ls.wy_m * row[x + ls.dy_m] - ls.wy_p * row[x + ls.dy_p]) +
+                hz * (T(2) * c - ls.wz_m * row[x + ls.dz_m] - ls.wz_p * row[x + ls.dz_p]);
+    acc += ls.wk[k] * s;
   }
   return acc;
 }
@@ -351,20 +418,17 @@ BLTT_HD T xline_stencil(const VupdStencil<T>& st, int64_t line, int x) {
 // writes LDS, so the mirror reads cannot race with it.
 template <class F, typename T, int L, class Ctx>
 BLTT_HD void odd_mirror(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g) {
-  constexpr int V = fft_V(L), s0 = fft_sigma(L, 0), m = L / 2 - 1;
+  constexpr int V = fft_V(L), s0 = fft_sigma(L, 0), VH = V / 2;
+  // slots t < V/2 hold positions p = g + t*s0 < L/2 (loaded), slots t >= V/2
+  // the positions p >= L/2, whose values are -e_{L-p} (e_{L/2} = 0)
 #pragma unroll
-  for (int t = 0; t < V; ++t) {
-    const int p = g + t * s0;
-    if (p >= 1 && p <= m) lds[F::idx(c, p)] = v[t];
-  }
+  for (int t = 0; t < VH; ++t) lds[F::idx(c, g + t * s0)] = v[t];
   ctx.sync();
 #pragma unroll
-  for (int t = 0; t < V; ++t) {
+  for (int t = VH; t < V; ++t) {
     const int p = g + t * s0;
-    if (p >= m + 2) {
-      const cx<T> w = lds[F::idx(c, L - p)];
-      v[t] = mkc<T>(-w.re, -w.im);
-    }
+    const cx<T> w = lds[F::idx(c, p == L / 2 ? 0 : L - p)];
+    v[t] = p == L / 2 ? mkc<T>(T(0), T(0)) : mkc<T>(-w.re, -w.im);
   }
 }
 
@@ -376,56 +440,69 @@ BLTT_HD void odd_mirror(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g) {
 // its first barrier); vout never aliases in, v1 or v2.
 enum { KIND_VUPD = 0, KIND_DOT = 1 };
 
-template <typename T, int L, int KIND, class Ctx>
+// VUPD variants: FULL = the Lanczos vectors and the stencil term are present
+// (v2 may equal v1 with cvp = 0); Q1 = q has a single tap.
+template <typename T, int L, int KIND, bool FULL, bool Q1, class Ctx>
 BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
                         const T* __restrict__ v1, const T* __restrict__ v2, T* __restrict__ vout,
                         const T* __restrict__ vdot, T* out, int64_t nlines,
                         const DstTables<T>& tb, const double* __restrict__ coef,
                         double* __restrict__ partials, const VupdStencil<T>& sten) {
-  constexpr int TPB = tpb_fft<T>();
-  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
+  constexpr int TPB = tpb_fft<T, FK_DSTX>();
+  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0), VH = V / 2;
   using F = LineFft<T, L, NL, false, LAST_LINEAR>;
   const int m = L / 2 - 1;
   const int tid = ctx.tid, c = tid / G, g = tid % G;
   const int64_t la = (int64_t)ctx.bid * (2 * NL) + 2 * c, lb = la + 1;
   const bool va = la < nlines, vb = lb < nlines;
+  // clamped line indices: every load below is in bounds and unconditional
+  const int64_t lac = va ? la : nlines - 1, lbc = vb ? lb : nlines - 1;
+  const T ma = va ? T(1) : T(0), mb = vb ? T(1) : T(0);
   T cq = T(1), cv = T(0), cvp = T(0);
   if (KIND == KIND_VUPD) {
     cq = T(coef[0]);
     cv = T(coef[1]);
     cvp = T(coef[2]);
   }
+  LineStencil<T> lsa, lsb;
+  if (KIND == KIND_VUPD && FULL) {
+    lsa = line_stencil(sten, lac);
+    lsb = line_stencil(sten, lbc);
+  }
   cx<T> v[V];
+  // positions p = g + t*s0 < L/2 for t < V/2: element x = p - 1 (p = 0 is the zero of the extension)
 #pragma unroll
-  for (int t = 0; t < V; ++t) {
+  for (int t = 0; t < VH; ++t) {
     const int p = g + t * s0;
-    T a = T(0), b = T(0);
-    if (p >= 1 && p <= m) {
-      const int xi = p - 1;
-      if (va) {
-        const int64_t e = la * m + xi;
-        a = in[e];
-        if (KIND == KIND_VUPD && sten.z) a += xline_stencil(sten, la, xi);
-        a *= cq;
-        if (KIND == KIND_VUPD) {
-          if (v1) a += cv * v1[e];
-          if (v2) a += cvp * v2[e];
-          if (vout) vout[e] = a;  // vout never aliases in, v1, v2
-        }
-      }
-      if (vb) {
-        const int64_t e = lb * m + xi;
-        b = in[e];
-        if (KIND == KIND_VUPD && sten.z) b += xline_stencil(sten, lb, xi);
-        b *= cq;
-        if (KIND == KIND_VUPD) {
-          if (v1) b += cv * v1[e];
-          if (v2) b += cvp * v2[e];
-          if (vout) vout[e] = b;
-        }
+    const int x = p > 0 ? p - 1 : 0;
+    const T wp = p > 0 ? T(1) : T(0);
+    const int64_t ea = lac * m + x, eb = lbc * m + x;
+    T a = in[ea], b = in[eb];
+    if (KIND == KIND_VUPD && FULL) {
+      a += line_stencil_at<T, Q1>(sten, lsa, x);
+      b += line_stencil_at<T, Q1>(sten, lsb, x);
+    }
+    a *= cq;
+    b *= cq;
+    if (KIND == KIND_VUPD && FULL) {
+      a += cv * v1[ea] + cvp * v2[ea];
+      b += cv * v1[eb] + cvp * v2[eb];
+    }
+    a *= wp * ma;
+    b *= wp * mb;
+    v[t] = mkc<T>(a, b);
+  }
+  if (KIND == KIND_VUPD && FULL) {
+    // the updated Lanczos vector (vout never aliases in, v1, v2); stores come
+    // after all loads so the loads above can all be in flight together
+#pragma unroll
+    for (int t = 0; t < VH; ++t) {
+      const int p = g + t * s0;
+      if (p > 0) {
+        if (va) vout[la * m + p - 1] = v[t].re;
+        if (vb) vout[lb * m + p - 1] = v[t].im;
       }
     }
-    v[t] = mkc<T>(a, b);
   }
   odd_mirror<F, T, L>(ctx, v, lds, c, g);
   F::forward(ctx, v, lds, c, g, tb.tw);
@@ -460,26 +537,25 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
 template <typename T, int L, class Ctx>
 BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t nlines, int64_t S,
                               const DstTables<T>& tb) {
-  constexpr int TPB = tpb_fft<T>();
+  constexpr int TPB = tpb_fft<T, FK_DSTS>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
   const int m = L / 2 - 1;
   const int tid = ctx.tid, c = tid % NL, g = tid / NL;
   const int64_t la = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, lb = la + 1;
   const bool va = la < nlines, vb = lb < nlines;
-  const int64_t basea = (la / S) * S * m + (la % S);
-  const int64_t baseb = (lb / S) * S * m + (lb % S);
+  const int64_t lac = va ? la : nlines - 1, lbc = vb ? lb : nlines - 1;
+  const int64_t basea = (lac / S) * S * m + (lac % S);
+  const int64_t baseb = (lbc / S) * S * m + (lbc % S);
+  const T ma = va ? T(1) : T(0), mb = vb ? T(1) : T(0);
+  constexpr int VH = V / 2;
   cx<T> v[V];
 #pragma unroll
-  for (int t = 0; t < V; ++t) {
+  for (int t = 0; t < VH; ++t) {
     const int p = g + t * s0;
-    T a = T(0), b = T(0);
-    if (p >= 1 && p <= m) {
-      const int64_t xi = p - 1;
-      if (va) a = x[basea + xi * S];
-      if (vb) b = x[baseb + xi * S];
-    }
-    v[t] = mkc<T>(a, b);
+    const int64_t xi = p > 0 ? p - 1 : 0;
+    const T w = p > 0 ? T(1) : T(0);
+    v[t] = mkc<T>(x[basea + xi * S] * (w * ma), x[baseb + xi * S] * (w * mb));
   }
   odd_mirror<F, T, L>(ctx, v, lds, c, g);
   F::forward(ctx, v, lds, c, g, tb.tw);
@@ -513,10 +589,8 @@ struct TimeTables {
   const T* dinv;       // alpha^{-n/N}
   const T* d2;         // alpha^{2n/N}
   const cx<T>* sigma;  // fft(alpha^{j/N} p_j)
-  const cx<T>* rho;    // fft(alpha^{j/N} q_j); unused when rho_const is set
+  const cx<T>* rho;    // fft(alpha^{j/N} q_j)
   const T* mu;         // length M, Laplacian eigenvalue of each sine mode
-  T rho0;              // q_0 when q has a single tap (rho_k = q_0 for all k)
-  int rho_const;
   T log2_alpha_over_N; // log2(alpha)/N for the FP32 scalings
   T q[4];              // leading taps of q
   int qtaps;
@@ -569,7 +643,7 @@ BLTT_HD double alpha_pow_n(const TimeTables<double>& tb, const double* tab, doub
 template <typename T, int HALF, bool SELF>
 BLTT_HD void spectral_pair(cx<T>& Z1, cx<T>& Z2, int k1, T mua, T mub, const TimeTables<T>& tb, T invN) {
   const cx<T> sg = tb.sigma[k1];
-  const cx<T> rh = tb.rho_const ? mkc<T>(tb.rho0, T(0)) : tb.rho[k1];
+  const cx<T> rh = tb.rho[k1];
   cx<T> ga = inv_sqrt_scaled(sg + rh * mua, invN);
   cx<T> gb = inv_sqrt_scaled(sg + rh * mub, invN);
   if (HALF == 0) {
@@ -625,15 +699,16 @@ BLTT_HD void time_spectral(cx<T>* v, int g, T mua, T mub, const TimeTables<T>& t
 template <typename T, int L, class Ctx>
 BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x, int64_t M,
                             const TimeTables<T>& tb) {
-  constexpr int TPB = tpb_fft<T>();
+  constexpr int TPB = tpb_fft<T, FK_TIME>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   using F = LineFft<T, L, NL, true, LAST_PAIRED>;
   const T invN = T(1) / T(L);
   const int tid = ctx.tid, c = tid % NL, g = tid / NL;
   const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
-  const int64_t ma = ia < M ? ia : M - 1;
-  const T mua = tb.mu[ma], mub = vb ? tb.mu[ib] : mua;
+  const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
+  const T mua = tb.mu[iac], mub = tb.mu[ibc];
+  const T wa = va ? T(1) : T(0), wb = vb ? T(1) : T(0);
   T* xa = x + ia;
   T* xb = x + ib;
 
@@ -643,7 +718,7 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
     const int n = g + t * s0;
     const T d = alpha_pow_n(tb, tb.dinv, T(-1), n);
     const int64_t off = (int64_t)n * M;
-    v[t] = mkc<T>(va ? xa[off] * d : T(0), vb ? xb[off] * d : T(0));
+    v[t] = mkc<T>(x[iac + off] * (d * wa), x[ibc + off] * (d * wb));
   }
   F::forward(ctx, v, lds, c, g, tb.tw);
   time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN);
@@ -693,6 +768,27 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 // ---------------------------------------------------------------------------
 // streaming kernels
 // ---------------------------------------------------------------------------
+
+// Spatial part of the residual r = Y (f - A u): one workgroup per x-line l of
+// r (threads along x), r[l, x] -= sum_k q_k (L_h u)[N-1-n-k, rr, x], plus the
+// partial sums of ||r||^2.  The neighbours along y and z are the adjacent
+// x-lines, read by neighbouring workgroups at the same time.
+template <typename T, bool Q1, class Ctx>
+BLTT_HD void resid_stencil_body(Ctx& ctx, double* red, T* __restrict__ r, const VupdStencil<T>& st,
+                                double* __restrict__ partials) {
+  const int64_t line = (int64_t)ctx.bid_y * ctx.nbx + ctx.bid;
+  const int m0 = st.grid.m[0];
+  const LineStencil<T> ls = line_stencil(st, line);
+  double part = 0.0;
+  for (int x = ctx.tid; x < m0; x += TPB_EW) {
+    const int64_t e = line * m0 + x;
+    const T v = r[e] - line_stencil_at<T, Q1>(st, ls, x);
+    r[e] = v;
+    part += (double)v * (double)v;
+  }
+  const double sum = block_sum<TPB_EW>(ctx, red, part);
+  if (ctx.tid == 0) partials[line] = sum;
+}
 
 // b = Y f (time reversal, Section 2) and partial sums of ||b||^2
 template <typename TO, class Ctx>

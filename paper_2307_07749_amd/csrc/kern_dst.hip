@@ -4,24 +4,24 @@
 
 namespace bltt {
 
-template <typename T, int L, int KIND>
-__global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_dst_x(const T* in, const T* __restrict__ v1,
+template <typename T, int L, int KIND, bool FULL, bool Q1>
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_DSTX>()), waves_fft<T>()) void k_dst_x(const T* in, const T* __restrict__ v1,
                                                         const T* __restrict__ v2, T* __restrict__ vout,
                                                         const T* __restrict__ vdot, T* out,
                                                         int64_t nlines, DstTables<T> tb,
                                                         const double* __restrict__ coef,
                                                         double* __restrict__ partials, VupdStencil<T> sten) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+  constexpr int NL = tpb_fft<T, FK_DSTX>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, false, LAST_LINEAR>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
-  dst_x_body<T, L, KIND>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, v1, v2, vout, vdot, out, nlines, tb, coef,
+  dst_x_body<T, L, KIND, FULL, Q1>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, v1, v2, vout, vdot, out, nlines, tb, coef,
                          partials, sten);
 }
 
 template <typename T, int L>
-__global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_dst_strided(T* __restrict__ x, int64_t nlines, int64_t S,
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_DSTS>()), waves_fft<T>()) void k_dst_strided(T* __restrict__ x, int64_t nlines, int64_t S,
                                                               DstTables<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   DevCtx ctx = make_ctx();
@@ -32,22 +32,37 @@ template <typename T, int L>
 static hipError_t go_dx(int kind, const T* in, const T* v1, const T* v2, T* vout, const T* vdot, T* out,
                         int64_t nlines, const DstTables<T>& tb, const double* coef, double* partials,
                         const VupdStencil<T>& sten, hipStream_t s) {
-  const int64_t blocks = fft_blocks<T>(L, nlines);
-  const size_t lds = fft_lds_bytes<T>(L);
-  if (kind == KIND_VUPD)
-    hipLaunchKernelGGL((k_dst_x<T, L, KIND_VUPD>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, in, v1, v2,
-                       vout, vdot, out, nlines, tb, coef, partials, sten);
+  const int64_t blocks = fft_blocks<T, FK_DSTX>(L, nlines);
+  const size_t lds = fft_lds_bytes<T, FK_DSTX>(L);
+  const dim3 grid((unsigned)blocks), block(tpb_fft<T, FK_DSTX>());
+  if (kind == KIND_DOT) {
+    hipLaunchKernelGGL((k_dst_x<T, L, KIND_DOT, false, false>), grid, block, lds, s, in, v1, v2, vout, vdot, out,
+                       nlines, tb, coef, partials, sten);
+    return hipGetLastError();
+  }
+  const bool full = v1 || vout || sten.z;
+  if (!full) {
+    hipLaunchKernelGGL((k_dst_x<T, L, KIND_VUPD, false, false>), grid, block, lds, s, in, v1, v2, vout, vdot, out,
+                       nlines, tb, coef, partials, sten);
+    return hipGetLastError();
+  }
+  // the full Lanczos update needs v1, vout and z; v2 may be absent (then coef[2] = 0)
+  if (!v1 || !vout || !sten.z) return hipErrorInvalidValue;
+  if (!v2) v2 = v1;
+  if (sten.qtaps <= 1)
+    hipLaunchKernelGGL((k_dst_x<T, L, KIND_VUPD, true, true>), grid, block, lds, s, in, v1, v2, vout, vdot, out,
+                       nlines, tb, coef, partials, sten);
   else
-    hipLaunchKernelGGL((k_dst_x<T, L, KIND_DOT>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, in, v1, v2,
-                       vout, vdot, out, nlines, tb, coef, partials, sten);
+    hipLaunchKernelGGL((k_dst_x<T, L, KIND_VUPD, true, false>), grid, block, lds, s, in, v1, v2, vout, vdot, out,
+                       nlines, tb, coef, partials, sten);
   return hipGetLastError();
 }
 
 template <typename T, int L>
 static hipError_t go_ds(T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s) {
-  const int64_t blocks = fft_blocks<T>(L, nlines);
-  const size_t lds = fft_lds_bytes<T>(L);
-  hipLaunchKernelGGL((k_dst_strided<T, L>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, x, nlines, S, tb);
+  const int64_t blocks = fft_blocks<T, FK_DSTS>(L, nlines);
+  const size_t lds = fft_lds_bytes<T, FK_DSTS>(L);
+  hipLaunchKernelGGL((k_dst_strided<T, L>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_DSTS>()), lds, s, x, nlines, S, tb);
   return hipGetLastError();
 }
 
@@ -88,16 +103,16 @@ BLTT_INST(double)
 
 template <typename T, int L>
 static hipError_t attr_dst() {
-  const int bytes = (int)fft_lds_bytes<T>(L);
+  const int bx = (int)fft_lds_bytes<T, FK_DSTX>(L), bs = (int)fft_lds_bytes<T, FK_DSTS>(L);
   hipError_t e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_DOT>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-    return e;
+  const void* ks[4] = {reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD, false, false>),
+                       reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD, true, true>),
+                       reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD, true, false>),
+                       reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_DOT, false, false>)};
+  for (const void* k : ks)
+    if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bx)) != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_strided<T, L>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bs);
 }
 
 hipError_t configure_dst_kernels() {

@@ -5,11 +5,11 @@
 namespace bltt {
 
 template <typename T, int L, int MODE, bool STENCIL>
-__global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_matvec_fft(const T* __restrict__ z, T* __restrict__ out,
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_MV>()), waves_fft<T>()) void k_matvec_fft(const T* __restrict__ z, T* __restrict__ out,
                                                              const T* __restrict__ fin, int64_t M,
                                                              MatvecTables<T> tb, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+  constexpr int NL = tpb_fft<T, FK_MV>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
@@ -28,17 +28,20 @@ __global__ __launch_bounds__(TPB_EW) void k_matvec_short(const T* __restrict__ z
 template <typename T, int L>
 static hipError_t go_mv(int mode, int stencil, const T* z, T* out, const T* fin, int64_t M,
                         const MatvecTables<T>& tb, double* partials, hipStream_t s) {
-  const int64_t blocks = fft_blocks<T>(L, M);
-  const size_t lds = fft_lds_bytes<T>(L);
+  const int64_t blocks = fft_blocks<T, FK_MV>(L, M);
+  const size_t lds = fft_lds_bytes<T, FK_MV>(L);
   if (mode == MV_DOT && stencil)
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT, true>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, z,
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, s, z,
                        out, fin, M, tb, partials);
   else if (mode == MV_DOT)
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT, false>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s,
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, s,
+                       z, out, fin, M, tb, partials);
+  else if (stencil)
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_RESID, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, s,
                        z, out, fin, M, tb, partials);
   else
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_RESID, true>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s,
-                       z, out, fin, M, tb, partials);
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_RESID, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds,
+                       s, z, out, fin, M, tb, partials);
   return hipGetLastError();
 }
 
@@ -89,14 +92,17 @@ BLTT_INST(double)
 
 template <typename T, int L>
 static hipError_t attr_mv() {
-  const int bytes = (int)fft_lds_bytes<T>(L);
+  const int bytes = (int)fft_lds_bytes<T, FK_MV>(L);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_DOT, true>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_DOT, false>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_RESID, true>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_RESID, true>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_RESID, false>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

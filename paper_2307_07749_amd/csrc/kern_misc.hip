@@ -39,6 +39,14 @@ __global__ __launch_bounds__(TPB_EW) void k_axpy64(double* __restrict__ u, const
   axpy64_body<TD>(ctx, u, d, n, sptr);
 }
 
+template <typename T, bool Q1>
+__global__ __launch_bounds__(TPB_EW) void k_resid_stencil(T* __restrict__ r, VupdStencil<T> st,
+                                                          double* __restrict__ partials) {
+  __shared__ double red[TPB_EW];
+  DevCtx ctx = make_ctx();
+  resid_stencil_body<T, Q1>(ctx, red, r, st, partials);
+}
+
 __global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __restrict__ st,
                                                    const double* __restrict__ partials, int64_t np,
                                                    const double* __restrict__ aux, int64_t naux,
@@ -47,6 +55,22 @@ __global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __res
   DevCtx ctx = make_ctx();
   scalar_body(ctx, red, phase, st, partials, np, aux, naux, hist);
 }
+
+template <typename T>
+hipError_t launch_resid_stencil(T* r, const VupdStencil<T>& st, int64_t nlines, double* partials, int64_t* nparts,
+                                hipStream_t s) {
+  if (nlines > 2147483647LL) return hipErrorInvalidValue;
+  if (nparts) *nparts = nlines;
+  if (st.qtaps <= 1)
+    hipLaunchKernelGGL((k_resid_stencil<T, true>), dim3((unsigned)nlines), dim3(TPB_EW), 0, s, r, st, partials);
+  else
+    hipLaunchKernelGGL((k_resid_stencil<T, false>), dim3((unsigned)nlines), dim3(TPB_EW), 0, s, r, st, partials);
+  return hipGetLastError();
+}
+template hipError_t launch_resid_stencil<float>(float*, const VupdStencil<float>&, int64_t, double*, int64_t*,
+                                                hipStream_t);
+template hipError_t launch_resid_stencil<double>(double*, const VupdStencil<double>&, int64_t, double*, int64_t*,
+                                                 hipStream_t);
 
 template <typename TO>
 hipError_t launch_rhs(const double* f, TO* b, int64_t N, int64_t M, double scale, double* partials,

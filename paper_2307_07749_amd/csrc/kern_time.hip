@@ -4,9 +4,9 @@
 namespace bltt {
 
 template <typename T, int L>
-__global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_time_prec(T* __restrict__ x, int64_t M, TimeTables<T> tb) {
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_TIME>()), waves_fft<T>()) void k_time_prec(T* __restrict__ x, int64_t M, TimeTables<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+  constexpr int NL = tpb_fft<T, FK_TIME>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, true, LAST_PAIRED>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
@@ -15,9 +15,9 @@ __global__ __launch_bounds__(tpb_fft<T>(), waves_fft<T>()) void k_time_prec(T* _
 
 template <typename T, int L>
 static hipError_t go_time(T* x, int64_t M, const TimeTables<T>& tb, hipStream_t s) {
-  const int64_t blocks = fft_blocks<T>(L, M);
-  const size_t lds = fft_lds_bytes<T>(L);
-  hipLaunchKernelGGL((k_time_prec<T, L>), dim3((unsigned)blocks), dim3(tpb_fft<T>()), lds, s, x, M, tb);
+  const int64_t blocks = fft_blocks<T, FK_TIME>(L, M);
+  const size_t lds = fft_lds_bytes<T, FK_TIME>(L);
+  hipLaunchKernelGGL((k_time_prec<T, L>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s, x, M, tb);
   return hipGetLastError();
 }
 
@@ -45,7 +45,7 @@ template hipError_t launch_time_prec<double>(int, double*, int64_t, const TimeTa
 template <typename T, int L>
 static hipError_t attr_time() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_prec<T, L>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds_bytes<T>(L));
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds_bytes<T, FK_TIME>(L));
 }
 
 hipError_t configure_time_kernels() {

@@ -22,27 +22,6 @@ __device__ inline DevCtx make_ctx() {
   return c;
 }
 
-// Workgroup geometry of the line-FFT kernels for line length L.
-template <typename T>
-inline int lines_per_block(int L) {
-  const int V = L < 16 ? L : 16;
-  return tpb_fft<T>() / (L / V);
-}
-template <typename T>
-inline size_t fft_lds_bytes(int L) {
-  const size_t NL = (size_t)lines_per_block<T>(L);
-  const size_t LP = (size_t)L + (size_t)(L >> 3);
-  return NL * LP * sizeof(cx<T>) + (size_t)tpb_fft<T>() * sizeof(double);
-}
-
-// Number of workgroups (= partial sums written) of the line-FFT launchers:
-// rounded up to a multiple of 8 for the XCD-aware tile order.
-template <typename T>
-inline int64_t fft_blocks(int L, int64_t units) {  // units = spatial points or lines
-  const int64_t per = 2 * (int64_t)lines_per_block<T>(L);
-  const int64_t nb = (units + per - 1) / per;
-  return (nb + 7) / 8 * 8;
-}
 inline int64_t ew_blocks(int64_t n) {
   const int64_t b = (n + TPB_EW - 1) / TPB_EW;
   return b < 1 ? 1 : (b > 16384 ? 16384 : b);
@@ -71,6 +50,9 @@ hipError_t launch_dst_strided(int L, T* x, int64_t nlines, int64_t S, const DstT
 hipError_t configure_kernels();
 
 // streaming and scalar kernels
+template <typename T>
+hipError_t launch_resid_stencil(T* r, const VupdStencil<T>& st, int64_t nlines, double* partials, int64_t* nparts,
+                                hipStream_t s);
 template <typename TO>
 hipError_t launch_rhs(const double* f, TO* b, int64_t N, int64_t M, double scale, double* partials,
                       int64_t* nparts, hipStream_t s);

@@ -63,6 +63,8 @@ def lib():
             getattr(L, f"emu_vupd_stencil_{t}").argtypes = args + [P, P, P]
             getattr(L, f"emu_time_aux_{t}").argtypes = args + [P]
             getattr(L, f"emu_time_aux_{t}").restype = ctypes.c_double
+        L.emu_resid_f64.argtypes = args + [P, P, P]
+        L.emu_resid_f64.restype = ctypes.c_double
         L.emu_error.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -171,3 +173,13 @@ def time_aux(prob, x, dtype=np.float64):
     s = getattr(lib(), f"emu_time_aux_{_tag(dtype)}")(*args, gx.ptr)
     _check(gx)
     return gx.data.copy(), s
+
+
+def resid(prob, u, f):
+    args, keep = _common(prob)
+    gu = Guarded(u, np.float64)
+    gf = Guarded(f, np.float64)
+    gr = Guarded(np.zeros(u.size), np.float64)
+    s = lib().emu_resid_f64(*args, gu.ptr, gf.ptr, gr.ptr)
+    _check(gu, gf, gr)
+    return gr.data.copy(), s

@@ -85,21 +85,6 @@ void run_grid(int tpb, int gx, int gy, size_t lds_bytes,
 }
 
 template <typename T>
-int nl_of(int L) {
-  const int V = L < 16 ? L : 16;
-  return tpb_fft<T>() / (L / V);
-}
-template <typename T>
-size_t lds_of(int L) {
-  return (size_t)nl_of<T>(L) * (size_t)(L + (L >> 3)) * sizeof(cx<T>) + (size_t)tpb_fft<T>() * sizeof(double);
-}
-template <typename T>
-int64_t blocks_of(int L, int64_t units) {
-  const int64_t per = 2 * (int64_t)nl_of<T>(L);
-  return ((units + per - 1) / per + 7) / 8 * 8;
-}
-
-template <typename T>
 std::vector<cx<T>> to_cx(const std::vector<host::cd>& v) {
   std::vector<cx<T>> o(v.size());
   for (size_t i = 0; i < v.size(); ++i) o[i] = mkc<T>((T)v[i].real(), (T)v[i].imag());
@@ -141,9 +126,10 @@ struct TimeRun {
   template <int L>
   struct R {
     static void run(T* x, int64_t M, const TimeTables<T>& tb) {
-      constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+      constexpr int NL = lines_per_block<T, FK_TIME>(L);
       using Ft = LineFft<T, L, NL, true, LAST_PAIRED>;
-      run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, M), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
+      run_grid(tpb_fft<T, FK_TIME>(), (int)fft_blocks<T, FK_TIME>(L, M), 1, fft_lds_bytes<T, FK_TIME>(L),
+               [&](HostCtx& c, unsigned char* lds) {
         double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Ft::LDS_ELEMS);
         time_prec_body<T, L>(c, reinterpret_cast<cx<T>*>(lds), red, x, M, tb);
       });
@@ -157,16 +143,26 @@ struct DstXRun {
   struct R {
     static void run(const T* in, T* out, int64_t nlines, const DstTables<T>& tb, const double* coef,
                     double* partials, const T* vdot, int kind, T* vout, const VupdStencil<T>& sten) {
-      constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+      constexpr int NL = lines_per_block<T, FK_DSTX>(L);
       using Fx = LineFft<T, L, NL, false, LAST_LINEAR>;
-      run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, nlines), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
+      run_grid(tpb_fft<T, FK_DSTX>(), (int)fft_blocks<T, FK_DSTX>(L, nlines), 1, fft_lds_bytes<T, FK_DSTX>(L),
+               [&](HostCtx& c, unsigned char* lds) {
         double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fx::LDS_ELEMS);
-        if (kind == KIND_VUPD)
-          dst_x_body<T, L, KIND_VUPD>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr, vout,
-                                       nullptr, out, nlines, tb, coef, partials, sten);
-        else
-          dst_x_body<T, L, KIND_DOT>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr, nullptr, vdot,
-                                      out, nlines, tb, coef, partials, sten);
+        if (kind == KIND_VUPD && sten.z) {
+          // full Lanczos variant: v1 = v2 = in with zero coefficients
+          if (sten.qtaps <= 1)
+            dst_x_body<T, L, KIND_VUPD, true, true>(c, reinterpret_cast<cx<T>*>(lds), red, in, in, in, vout,
+                                                    nullptr, out, nlines, tb, coef, partials, sten);
+          else
+            dst_x_body<T, L, KIND_VUPD, true, false>(c, reinterpret_cast<cx<T>*>(lds), red, in, in, in, vout,
+                                                     nullptr, out, nlines, tb, coef, partials, sten);
+        } else if (kind == KIND_VUPD) {
+          dst_x_body<T, L, KIND_VUPD, false, false>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr,
+                                                    nullptr, nullptr, out, nlines, tb, coef, partials, sten);
+        } else {
+          dst_x_body<T, L, KIND_DOT, false, false>(c, reinterpret_cast<cx<T>*>(lds), red, in, nullptr, nullptr,
+                                                   nullptr, vdot, out, nlines, tb, coef, partials, sten);
+        }
       });
     }
   };
@@ -177,7 +173,8 @@ struct DstSRun {
   template <int L>
   struct R {
     static void run(T* x, int64_t nlines, int64_t S, const DstTables<T>& tb) {
-      run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, nlines), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
+      run_grid(tpb_fft<T, FK_DSTS>(), (int)fft_blocks<T, FK_DSTS>(L, nlines), 1, fft_lds_bytes<T, FK_DSTS>(L),
+               [&](HostCtx& c, unsigned char* lds) {
         dst_strided_body<T, L>(c, reinterpret_cast<cx<T>*>(lds), x, nlines, S, tb);
       });
     }
@@ -189,9 +186,10 @@ struct MvRun {
   template <int L>
   struct R {
     static void run(const T* z, T* out, int64_t M, const MatvecTables<T>& tb, double* partials, bool stencil) {
-      constexpr int NL = tpb_fft<T>() / (L / fft_V(L));
+      constexpr int NL = lines_per_block<T, FK_MV>(L);
       using Fm = LineFft<T, L, NL, true, LAST_DEFAULT>;
-      run_grid(tpb_fft<T>(), (int)blocks_of<T>(L, M), 1, lds_of<T>(L), [&](HostCtx& c, unsigned char* lds) {
+      run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
+               [&](HostCtx& c, unsigned char* lds) {
         double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
         if (stencil)
           matvec_fft_body<T, L, MV_DOT, true>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb, partials);
@@ -275,8 +273,6 @@ TimeTables<T> time_tables(const Problem& P, const HostTables<T>& ht) {
   tt.sigma = ht.sigma.data();
   tt.rho = ht.rho.data();
   tt.mu = ht.mu.data();
-  tt.rho_const = qtaps <= 1 ? 1 : 0;
-  tt.rho0 = (T)P.q[0];
   tt.log2_alpha_over_N = (T)(std::log2(P.alpha) / (double)P.N);
   for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
   tt.qtaps = qtaps;
@@ -340,7 +336,7 @@ void apply_precond(const Problem& P, const T* x, T* y) {
   TimeTables<T> tt = time_tables<T>(P, ht);
   with_L<TimeRun<T>::template R>((int)P.N, tmp.data(), P.M, tt);
   space_strided<T>(P, ht, tmp.data(), true);
-  std::vector<double> partials((size_t)blocks_of<T>(Lx, n / P.m[0]) + 1);
+  std::vector<double> partials((size_t)fft_blocks<T, FK_DSTX>(Lx, n / P.m[0]) + 1);
   with_L<DstXRun<T>::template R>(Lx, tmp.data(), y, n / P.m[0], ht.dst(P, 0), one, partials.data(), x,
                                  (int)KIND_DOT, (T*)nullptr, vupd_stencil<T>(P, nullptr));
 }
@@ -379,11 +375,58 @@ double apply_sym(const Problem& P, const T* z, T* out, bool force_fft, bool sten
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
     tb.qtaps = qtaps;
     tb.grid = grid_of(P);
-    std::vector<double> partials((size_t)blocks_of<T>((int)(2 * P.N), P.M));
+    std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
     with_L2<MvRun<T>::template R>((int)(2 * P.N), z, out, P.M, tb, partials.data(), stencil);
     for (double v : partials) dot += v;
   }
   return dot;
+}
+
+// r = Y (f - A u) the way the solver forms it for dense p: time-line FFT pass
+// without the stencil, then the x-line stencil pass; returns ||r||^2
+template <typename T>
+struct MvResRun {
+  template <int L>
+  struct R {
+    static void run(const T* z, T* out, const T* fin, int64_t M, const MatvecTables<T>& tb, double* partials) {
+      constexpr int NL = lines_per_block<T, FK_MV>(L);
+      using Fm = LineFft<T, L, NL, true, LAST_DEFAULT>;
+      run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
+               [&](HostCtx& c, unsigned char* lds) {
+                 double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
+                 matvec_fft_body<T, L, MV_RESID, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M, tb,
+                                                        partials);
+               });
+    }
+  };
+};
+
+template <typename T>
+double apply_resid(const Problem& P, const T* u, const T* f, T* r) {
+  HostTables<T> ht(P);
+  int qtaps = 0;
+  for (int64_t k = 0; k < P.N; ++k)
+    if (P.q[(size_t)k] != 0.0) qtaps = (int)k + 1;
+  MatvecTables<T> tb;
+  tb.tw = ht.tw_mv.data();
+  tb.phat = ht.phat.data();
+  for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+  tb.qtaps = qtaps;
+  tb.grid = grid_of(P);
+  std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
+  with_L2<MvResRun<T>::template R>((int)(2 * P.N), u, r, f, P.M, tb, partials.data());
+  const int64_t nlines = P.N * P.M / P.m[0];
+  std::vector<double> lp((size_t)nlines);
+  const VupdStencil<T> st = vupd_stencil<T>(P, u);
+  run_grid(TPB_EW, (int)nlines, 1, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
+    if (st.qtaps <= 1)
+      resid_stencil_body<T, true>(c, reinterpret_cast<double*>(lds), r, st, lp.data());
+    else
+      resid_stencil_body<T, false>(c, reinterpret_cast<double*>(lds), r, st, lp.data());
+  });
+  double s = 0.0;
+  for (double v : lp) s += v;
+  return s;
 }
 
 // q1 + Y L_h (q * z) through the x-line pass (coefficients 1, 0, 0)
@@ -402,7 +445,7 @@ template <typename T>
 double apply_time_aux(const Problem& P, T* x) {
   HostTables<T> ht(P);
   TimeTables<T> tt = time_tables<T>(P, ht);
-  std::vector<double> aux((size_t)blocks_of<T>((int)P.N, P.M), 0.0);
+  std::vector<double> aux((size_t)fft_blocks<T, FK_TIME>((int)P.N, P.M), 0.0);
   tt.aux = aux.data();
   with_L<TimeRun<T>::template R>((int)P.N, x, P.M, tt);
   double s = 0.0;
@@ -444,6 +487,9 @@ void emu_vupd_stencil_f32(EMU_ARGS, const float* q1, const float* z, float* v) {
   apply_vupd_stencil<float>(EMU_P, q1, z, v);
 }
 double emu_time_aux_f64(EMU_ARGS, double* x) { return apply_time_aux<double>(EMU_P, x); }
+double emu_resid_f64(EMU_ARGS, const double* u, const double* f, double* r) {
+  return apply_resid<double>(EMU_P, u, f, r);
+}
 double emu_time_aux_f32(EMU_ARGS, float* x) { return apply_time_aux<float>(EMU_P, x); }
 
 }  // extern "C"

@@ -133,3 +133,18 @@ def test_time_pass_spatial_dot(kind, dim, m, N, dtype):
     ref = float(np.vdot(O.sym_apply(qsys, z).ravel(), z.ravel()))
     scale = np.linalg.norm(O.sym_apply(qsys, z)) * np.linalg.norm(z)
     assert abs(s - ref) <= TOL[dtype] * 100 * scale
+
+
+@pytest.mark.parametrize("kind,dim,m,N", SPLIT_CASES)
+def test_split_residual(kind, dim, m, N):
+    """r = Y (f - A u): time-line FFT pass without the stencil, then the x-line
+    stencil pass with ||r||^2 (dense-p path of the FP64 residual)."""
+    prob = prob_of(kind, dim, m, N)
+    sysm = O.from_problem(prob)
+    rng = np.random.default_rng(23)
+    u = rng.standard_normal(prob.n)
+    f = rng.standard_normal(prob.n)
+    r, s = E.resid(prob, u, f)
+    ref = O.time_reverse(f.reshape(N, -1) - O.bltt_apply(sysm, u)).ravel()
+    assert rel(r, ref) < 1e-12
+    assert abs(s - np.dot(ref, ref)) < 1e-10 * np.dot(ref, ref)
