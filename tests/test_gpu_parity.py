@@ -166,12 +166,18 @@ def test_named_workloads_fp64(name):
     assert err < 1e-9
 
 
-@pytest.mark.parametrize("precision,tol", [(bltt.MIXED, 1e-8), (bltt.FP64, 1e-8)])
-def test_full_size_2d_fractional_sampled(precision, tol):
-    """M = 511^2, N = 1024, gamma = 0.3: sampled sine-mode projections of u
-    against the oracle's per-mode exact solution."""
-    prob, seed = W.workload("frac2d_m511_n1024_g03")
-    print(f"[full size] precision={precision}", flush=True)
+FULL_CASES = [("frac2d_m511_n1024_g03", bltt.MIXED), ("frac2d_m511_n1024_g03", bltt.FP64),
+              ("frac2d_m511_n1024_g07", bltt.MIXED), ("frac3d_m127_n256", bltt.MIXED)]
+
+
+@pytest.mark.parametrize("name,precision", FULL_CASES)
+def test_full_size_sampled(name, precision):
+    """Full-size workloads (2D: M = 511^2, N = 1024, gamma 0.3 / 0.7; 3D:
+    M = 127^3, N = 256, gamma 0.5) at tol 1e-8: sampled sine-mode projections
+    of u against the oracle's per-mode exact solution."""
+    tol = 1e-8
+    prob, seed = W.workload(name)
+    print(f"[full size] {name} precision={precision}", flush=True)
     sysm = O.from_problem(prob)
     f = W.rhs_normal(prob, seed)
     s = bltt.Solver.from_problem(prob, precision=precision)
