@@ -23,7 +23,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-HOT_CLASSES = ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update"]
+# kernel classes run once per MINRES iteration, per Krylov basis
+HOT_CLASSES = {"sine": ["matvec", "time_prec", "wx_update"],
+               "physical": ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update"]}
 
 
 def cpu_baseline(workload: str, tol: float, budget_s: float = 12.0) -> dict:
@@ -60,16 +62,17 @@ def cpu_baseline(workload: str, tol: float, budget_s: float = 12.0) -> dict:
                        f"{res.iters} iterations; scaled linearly by M x{scale:.1f} to M={full.M}")}
 
 
-def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if one exists for the current kernel source."""
+def traffic_from_profiles(kernel: str, basis: str):
+    """HBM bytes per launch of kernel class `kernel` (Krylov basis `basis`)
+    from the committed rocprofv3 counter summary, if one exists for the
+    current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as fh:
             data = json.load(fh)
-        entry = data.get(kernel)
+        entry = data.get(basis, {}).get(kernel)
         if not entry:
             return None
         import hashlib
@@ -96,6 +99,8 @@ def main() -> int:
     ap.add_argument("--maxit", type=int, default=300)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--basis", choices=["sine", "physical"], default="sine",
+                    help="Krylov basis: sine coordinates (transform once) or physical space")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -116,7 +121,9 @@ def main() -> int:
         print(msg, file=sys.stderr, flush=True)
 
     # ---- mixed path (the headline)
-    mixed = bltt.Solver.from_problem(prob, precision=bltt.MIXED)
+    basis = bltt.SINE if args.basis == "sine" else bltt.PHYSICAL
+    hot = HOT_CLASSES[args.basis]
+    mixed = bltt.Solver.from_problem(prob, precision=bltt.MIXED, basis=basis)
     u = torch.empty_like(f)
     log(f"[bench] {args.workload}: n={prob.n} warmup={args.warmup} steps={args.steps}")
     for _ in range(args.warmup):
@@ -139,9 +146,9 @@ def main() -> int:
     iters_mixed, info_mixed, rc_mixed = infos[-1]
 
     # per-iteration traffic of the hot path (algorithmic bytes / kernel time)
-    hot_ms = sum(prof[c]["ms"] for c in HOT_CLASSES)
-    hot_bytes = sum(prof[c]["bytes"] for c in HOT_CLASSES)
-    dom = max(HOT_CLASSES, key=lambda c: prof[c]["ms"])
+    hot_ms = sum(prof[c]["ms"] for c in hot)
+    hot_bytes = sum(prof[c]["bytes"] for c in hot)
+    dom = max(hot, key=lambda c: prof[c]["ms"])
     d = prof[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
     per_launch_bytes = d["bytes"] / max(d["launches"], 1)
@@ -154,7 +161,7 @@ def main() -> int:
     # ---- FP64 path beside it
     fp64 = None
     if not args.no_fp64:
-        s64 = bltt.Solver.from_problem(prob, precision=bltt.FP64)
+        s64 = bltt.Solver.from_problem(prob, precision=bltt.FP64, basis=basis)
         for _ in range(args.warmup):
             s64.pminres(f, args.tol, args.maxit, u)
         torch.cuda.synchronize()
@@ -183,14 +190,14 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": prob.dim, "m": prob.m[0], "M": prob.M, "N": prob.N,
                    "gamma": prob.meta.get("gamma"), "alpha": prob.alpha, "tol": args.tol, "seed": seed,
-                   "precision": "mixed (FP32 MINRES sweeps, FP64 refinement)"},
+                   "precision": "mixed (FP32 MINRES sweeps, FP64 refinement)", "basis": args.basis},
         "mixed": {"ms_per_solve": ms_mixed, "iters_inner": iters_mixed, "iters_outer": info_mixed["iters_outer"],
                   "true_relres": info_mixed["true_relres"], "status": int(rc_mixed),
                   "hot_path_GBps": hot_bytes / (hot_ms * 1e-3) / 1e9 if hot_ms > 0 else 0.0,
                   "kernels": kernels},
         "fp64": fp64,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profiles(dom),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profiles(dom, args.basis),
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "avg_launch_us": 1e3 * d["ms"] / max(d["launches"], 1)},
     }

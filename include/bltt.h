@@ -60,6 +60,18 @@ enum bltt_precision {
   BLTT_FP32 = 2             /* step-level entry points only: FP32 arithmetic      */
 };
 
+/* Basis the Krylov iteration runs in (both give the same iterates up to the
+ * change of basis, in exact arithmetic). */
+enum bltt_basis {
+  BLTT_BASIS_SINE = 0,      /* default: f is sine-transformed once (I_N (x) U),
+                               MINRES runs on the mode-decoupled system, where
+                               L_h = diag(mu) (Remark 1) and P_alpha^{-1} is the
+                               time pass alone; u is transformed back once      */
+  BLTT_BASIS_PHYSICAL = 1   /* every iteration in physical space: stencil
+                               matvec, and sine transforms inside each
+                               preconditioner application (Section 5.1)        */
+};
+
 /* Block description.  dim in {1,2,3}; m[d] interior points and h[d] spacing of
  * dimension d (d = 0 is x, the fastest); p and q are host arrays of length N
  * (copied during bltt_setup). */
@@ -80,13 +92,17 @@ typedef struct {
   double check_factor;    /* FP64: compute the true residual once the MINRES
                              estimate |eta_j|/eta_0 <= check_factor*tol
                              (default 10)                                         */
+  int32_t basis;          /* BLTT_BASIS_SINE (default) or BLTT_BASIS_PHYSICAL     */
 } bltt_options;
 
 /* Per-solve report. */
 typedef struct {
   int32_t iters_inner;    /* MINRES iterations (all inner sweeps in MIXED)        */
   int32_t iters_outer;    /* refinement sweeps (MIXED), 1 for FP64                */
-  double true_relres;     /* ||Y(f - A u)||_2 / ||Y f||_2, computed in FP64       */
+  double true_relres;     /* ||Y(f - A u)||_2 / ||Y f||_2, computed in FP64 (in
+                             the sine basis: of the transformed system, equal
+                             to the physical one up to the FP64 rounding of the
+                             two sine transforms)                                 */
   double setup_ms;        /* wall time of bltt_setup                              */
   double solve_ms;        /* wall time of the bltt_pminres call                   */
   double c0;              /* Assumption 1(ii) margin of the blocks                */

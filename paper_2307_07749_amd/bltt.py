@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbltt.so")
 
 FP64, MIXED, FP32 = 0, 1, 2
+SINE, PHYSICAL = 0, 1  # Krylov basis (bltt_basis)
 KERNEL_CLASSES = ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update", "resid64", "other"]
 OK, NOCONV = 0, 1
 STATUS = {0: "BLTT_OK", 1: "BLTT_NOCONV", -1: "BLTT_EINVAL", -2: "BLTT_EASSUMPTION", -3: "BLTT_ENAN",
@@ -39,7 +40,7 @@ class Blocks(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("check_factor", ctypes.c_double)]
+                ("check_factor", ctypes.c_double), ("basis", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -112,7 +113,7 @@ class Solver:
     interior points and spacing ``h`` per dimension (x first)."""
 
     def __init__(self, dim: int, m, h, p, q, alpha: float, precision: int = FP64, inner_tol: float = 0.0,
-                 max_refine: int = 0, check_factor: float = 0.0, stream=None):
+                 max_refine: int = 0, check_factor: float = 0.0, basis: int = 0, stream=None):
         L = load()
         self._L = L
         m = list(m)
@@ -132,7 +133,7 @@ class Solver:
             blk.h[d] = h[d] if d < dim else 1.0
         blk.p = self._p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         blk.q = self._q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        opt = Options(precision, inner_tol, max_refine, check_factor)
+        opt = Options(precision, inner_tol, max_refine, check_factor, basis)
         self.stream = stream
         handle = ctypes.c_void_p()
         rc = L.bltt_setup(ctypes.byref(blk), self.N, self.M, float(alpha), ctypes.byref(opt),

@@ -72,8 +72,11 @@ struct bltt_handle {
   Workspace<float> w32;
   Workspace<double> w64;
   double* R64 = nullptr;
+  double* F64 = nullptr;       // sine basis: (I_N x U) f
   double* partials = nullptr;
   int64_t partials_cap = 0;
+  double* red_scratch = nullptr;  // first stage of long reductions (2 * red_half)
+  int64_t red_half = 0;
   double* partials_aux = nullptr;  // time pass: spatial part of the next <q, z>
   int64_t np_aux = 0;
   SolverState* state = nullptr;
@@ -244,6 +247,7 @@ int64_t partials_needed(const bltt_handle* h) {
   }
   need = std::max(need, fft_blocks<T, FK_DSTX>(2 * (h->m[0] + 1), h->n / h->m[0]));
   need = std::max(need, h->n / h->m[0]);  // one partial per x-line (residual stencil pass)
+  need = std::max(need, fft_blocks<T, FK_TIME>((int)h->N, h->M));
   return need;
 }
 
@@ -260,11 +264,13 @@ VupdStencil<T> vupd_stencil(bltt_handle* h, const T* z) {
 }
 
 // q = Y A z (MV_DOT, partial sums of <q, z>) or out = Y (fin - A z) (MV_RESID,
-// partial sums of the squared norm).  With stencil false, MV_DOT forms only
-// Y (p * z): inside MINRES the spatial term is added by the x-line pass of the
-// preconditioner and its share of <q, z> comes from the preceding time pass.
+// partial sums of the squared norm).  term selects the spatial part:
+// TERM_STENCIL the full physical-space operator, TERM_NONE only Y (p * z)
+// (inside the physical-space MINRES the spatial term is added by the x-line
+// pass of the preconditioner and its share of <q, z> comes from the preceding
+// time pass), TERM_SPEC the sine-coordinate operator (mu_i on mode i).
 template <typename T>
-int matvec(bltt_handle* h, int mode, bool stencil, const T* z, T* out, const T* fin, int64_t* np) {
+int matvec(bltt_handle* h, int mode, int term, const T* z, T* out, const T* fin, int64_t* np) {
   DeviceTables<T>& t = tables<T>(h);
   if (short_p(h)) {
     ShortTables<T> tb;
@@ -275,29 +281,31 @@ int matvec(bltt_handle* h, int mode, bool stencil, const T* z, T* out, const T* 
     tb.grid = make_grid(h);
     tb.N = (int)h->N;
     tb.chunk = 8;
-    tb.stencil = stencil ? 1 : 0;
+    tb.term = term;
+    tb.mu = t.mu;
     ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
     HIPCHK(launch_matvec_short<T>(mode, z, out, fin, h->M, tb, h->partials, np, h->stream));
   } else {
     MatvecTables<T> tb;
     tb.tw = t.tw_mv;
     tb.phat = t.phat;
+    tb.mu = t.mu;
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
     tb.qtaps = h->qtaps;
     tb.grid = make_grid(h);
-    if (mode == MV_RESID) {
+    if (mode == MV_RESID && term == TERM_STENCIL) {
       // r = Y (f - p * u) on time lines, then the spatial term and ||r||^2 on x-lines
       const int64_t nlx = h->n / h->m[0];
       {
         ProfScope ps(h, BLTT_K_RESID64, 3.0 * h->n * sizeof(T));
-        HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), MV_RESID, 0, z, out, fin, h->M, tb, h->partials, h->stream));
+        HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), MV_RESID, TERM_NONE, z, out, fin, h->M, tb, h->partials,
+                                    h->stream));
       }
       ProfScope ps(h, BLTT_K_RESID64, 3.0 * h->n * sizeof(T));
       HIPCHK(launch_resid_stencil<T>(out, vupd_stencil<T>(h, z), nlx, h->partials, np, h->stream));
     } else {
-      ProfScope ps(h, BLTT_K_MATVEC, 2.0 * h->n * sizeof(T));
-      HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), mode, stencil ? 1 : 0, z, out, fin, h->M, tb, h->partials,
-                                  h->stream));
+      ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
+      HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), mode, term, z, out, fin, h->M, tb, h->partials, h->stream));
       *np = fft_blocks<T, FK_MV>((int)(2 * h->N), h->M);
     }
   }
@@ -327,6 +335,37 @@ int space_strided(bltt_handle* h, T* x, bool reverse) {
   return BLTT_OK;
 }
 
+template <typename T>
+TimeTables<T> time_tables(bltt_handle* h, bool aux) {
+  TimeTables<T> tt;
+  DeviceTables<T>& t = tables<T>(h);
+  tt.tw = t.tw_time;
+  tt.dinv = t.dinv;
+  tt.d2 = t.d2;
+  tt.sigma = t.sigma;
+  tt.rho = t.rho;
+  tt.mu = t.mu;
+  tt.log2_alpha_over_N = (T)(std::log2(h->alpha) / (double)h->N);
+  for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
+  tt.qtaps = h->qtaps;
+  tt.aux = aux ? h->partials_aux : nullptr;
+  return tt;
+}
+
+// out = (I_N x U) in: sine transform of every time slice (x-line pass, then the
+// strided dimensions).  out may equal in.
+template <typename T>
+int space_transform(bltt_handle* h, const T* in, T* out) {
+  const int Lx = 2 * (h->m[0] + 1);
+  const int64_t nlx = h->n / h->m[0];
+  {
+    ProfScope ps(h, BLTT_K_DST_X_VUPD, 2.0 * h->n * sizeof(T));
+    HIPCHK(launch_dst_x<T>(Lx, KIND_VUPD, in, nullptr, nullptr, nullptr, nullptr, out, nlx, dst_tables<T>(h, 0),
+                           h->coef_one, nullptr, vupd_stencil<T>(h, nullptr), h->stream));
+  }
+  return space_strided<T>(h, out, false);
+}
+
 // zout = P^{-1} vhat with vhat = coef[0] in + coef[1] v1 + coef[2] v2 (written to
 // vout when non-null); tmp is scratch and may equal `in`; partial sums of
 // <vdot, zout> are left in h->partials (count in *np).
@@ -346,18 +385,7 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
                            vupd_stencil<T>(h, zstencil), h->stream));
   }
   if ((rc = space_strided<T>(h, tmp, false))) return rc;
-  TimeTables<T> tt;
-  DeviceTables<T>& t = tables<T>(h);
-  tt.tw = t.tw_time;
-  tt.dinv = t.dinv;
-  tt.d2 = t.d2;
-  tt.sigma = t.sigma;
-  tt.rho = t.rho;
-  tt.mu = t.mu;
-  tt.log2_alpha_over_N = (T)(std::log2(h->alpha) / (double)h->N);
-  for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
-  tt.qtaps = h->qtaps;
-  tt.aux = aux ? h->partials_aux : nullptr;
+  const TimeTables<T> tt = time_tables<T>(h, aux);
   if (aux) h->np_aux = fft_blocks<T, FK_TIME>((int)h->N, h->M);
   {
     ProfScope ps(h, BLTT_K_TIME, 2.0 * h->n * sizeof(T));
@@ -376,7 +404,7 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
 int scalar(bltt_handle* h, int phase, int64_t np, double* hist, bool with_aux = false) {
   ProfScope ps(h, BLTT_K_OTHER, 8.0 * np);
   HIPCHK(launch_scalar(phase, h->state, h->partials, np, with_aux ? h->partials_aux : nullptr,
-                       with_aux ? h->np_aux : 0, hist, h->stream));
+                       with_aux ? h->np_aux : 0, hist, h->red_scratch, h->red_half, h->stream));
   return BLTT_OK;
 }
 
@@ -436,7 +464,7 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   res->status = BLTT_NOCONV;
   int j = 0;
   for (j = 1; j <= maxit; ++j) {
-    if ((rc = matvec<T>(h, MV_DOT, false, Zc, ws.Q, nullptr, &np))) return rc;
+    if ((rc = matvec<T>(h, MV_DOT, TERM_NONE, Zc, ws.Q, nullptr, &np))) return rc;
     if ((rc = scalar(h, SC_DELTA, np, nullptr, true))) return rc;
     if ((rc = precond<T>(h, ws.Q, Vc, j > 1 ? Vp : nullptr, Vn, coef_v, ws.Q, Vn, Zn, &np, Zc, true))) return rc;
     if ((rc = scalar(h, SC_BETA, np, h->hist_dev))) return rc;
@@ -460,7 +488,105 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     if (eta_rel <= eta_tol || st.status == 1) {
       if (f_dev) {
         if constexpr (sizeof(TX) == 8 && sizeof(T) == 8) {
-          if ((rc = matvec<double>(h, MV_RESID, true, (const double*)X, (double*)ws.Q, f_dev, &np))) return rc;
+          if ((rc = matvec<double>(h, MV_RESID, TERM_STENCIL, (const double*)X, (double*)ws.Q, f_dev, &np))) return rc;
+          if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+          if ((rc = read_state(h))) return rc;
+          res->relres = std::sqrt(h->state_host->norm2) / bnorm;
+          if (!(res->relres == res->relres)) return BLTT_ENAN;
+          if (res->relres <= tol || st.status == 1) {
+            res->status = BLTT_OK;
+            break;
+          }
+        }
+      } else {
+        res->status = BLTT_OK;
+        break;
+      }
+    }
+  }
+  res->iters = j > maxit ? maxit : j;
+  if (hist_host) {
+    HIPCHK(hipMemcpy(hist_host, h->hist_dev, sizeof(double) * (size_t)(res->iters + 1), hipMemcpyDeviceToHost));
+  }
+  return BLTT_OK;
+}
+
+// MINRES in sine coordinates (every block p_k I + q_k L_h is diagonalised by
+// the sine transform, Remark 1): per iteration one time-line matvec with the
+// mu_i term, one Lanczos-update + time-pass kernel, one direction/iterate
+// update.  The right-hand side is cq * bsrc with cq = bcoef[0] (bsrc may be
+// FP64 for an FP32 sweep); it is copied into V[0] as the first Lanczos vector
+// unless bsrc already is V[0].  X must be zero on entry.  fhat (FP64 only):
+// the transformed f for the explicit residual check, as in minres_core.
+template <typename T, typename TX, typename TB>
+int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* fhat, double tol, double bnorm,
+                double* hist_host, CoreResult* res, const TB* bsrc, const double* bcoef) {
+  Workspace<T>& ws = workspace<T>(h);
+  hipStream_t s = h->stream;
+  int rc;
+  int64_t np = 0;
+  T* Vc = ws.V[0];
+  T* Vp = ws.V[1];
+  T* Vn = ws.V[2];
+  T* Zc = ws.Z[0];
+  T* Zn = ws.Z[1];
+  T* Wa = ws.W[0];
+  T* Wb = ws.W[1];
+  const double n = (double)h->n;
+  {
+    ProfScope ps(h, BLTT_K_OTHER, 2.0 * n * sizeof(T));
+    HIPCHK(launch_fill<T>(Wa, h->n, T(0), s));
+    HIPCHK(launch_fill<T>(Wb, h->n, T(0), s));
+  }
+  if ((rc = ensure_hist(h, (int64_t)maxit + 2))) return rc;
+  const TimeTables<T> tt = time_tables<T>(h, false);
+  const int L = (int)h->N;
+  const int64_t npt = fft_blocks<T, FK_TIME>(L, h->M);
+  // v_1 = b, z_1 = P^{-1} b, beta_1 = sqrt(<b, z_1>)
+  {
+    const bool copy = (const void*)bsrc != (const void*)Vc;
+    ProfScope ps(h, BLTT_K_TIME, n * (sizeof(TB) + (copy ? 2.0 : 1.0) * sizeof(T)));
+    HIPCHK(launch_time_upd<T, TB>(L, false, bsrc, nullptr, nullptr, copy ? Vc : nullptr, Zc, h->M, tt, bcoef,
+                                  h->partials, s));
+  }
+  if ((rc = scalar(h, SC_START, npt, h->hist_dev))) return rc;
+  if ((rc = read_state(h))) return rc;
+  if (h->state_host->status == -3) return BLTT_ENAN;
+  if (h->state_host->status == -4) return BLTT_EBREAKDOWN;
+  const double* coef_v = h->state->coef_v;
+  const double* coef_w = h->state->coef_w;
+  res->status = BLTT_NOCONV;
+  int j = 0;
+  for (j = 1; j <= maxit; ++j) {
+    if ((rc = matvec<T>(h, MV_DOT, TERM_SPEC, Zc, ws.Q, nullptr, &np))) return rc;
+    if ((rc = scalar(h, SC_DELTA, np, nullptr))) return rc;
+    {
+      // at j = 1 there is no v_0: V2 = V1 with a zero coefficient
+      ProfScope ps(h, BLTT_K_TIME, (j > 1 ? 5.0 : 4.0) * n * sizeof(T));
+      HIPCHK(launch_time_upd<T, T>(L, true, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, h->M, tt, coef_v, h->partials, s));
+    }
+    if ((rc = scalar(h, SC_BETA, npt, h->hist_dev))) return rc;
+    {
+      ProfScope ps(h, BLTT_K_WX, (4.0 * sizeof(T) + 2.0 * sizeof(TX)) * n);
+      HIPCHK(launch_wx<T, TX>(Zc, Wa, Wb, X, h->n, coef_w, s));
+    }
+    {
+      T* t = Vp;
+      Vp = Vc;
+      Vc = Vn;
+      Vn = t;
+      std::swap(Zc, Zn);
+      std::swap(Wa, Wb);
+    }
+    if ((rc = read_state(h))) return rc;
+    const SolverState& st = *h->state_host;
+    if (st.status == -3) return BLTT_ENAN;
+    if (st.status == -4) return BLTT_EBREAKDOWN;
+    const double eta_rel = std::fabs(st.eta) / st.eta0;
+    if (eta_rel <= eta_tol || st.status == 1) {
+      if (fhat) {
+        if constexpr (sizeof(TX) == 8 && sizeof(T) == 8) {
+          if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, (const double*)X, (double*)ws.Q, fhat, &np))) return rc;
           if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
           if ((rc = read_state(h))) return rc;
           res->relres = std::sqrt(h->state_host->norm2) / bnorm;
@@ -537,6 +663,7 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
     if (!std::isfinite(blk->p[k]) || !std::isfinite(blk->q[k])) return BLTT_EINVAL;
   if (opt) {
     if (opt->precision != BLTT_FP64 && opt->precision != BLTT_MIXED) return BLTT_EINVAL;
+    if (opt->basis != BLTT_BASIS_SINE && opt->basis != BLTT_BASIS_PHYSICAL) return BLTT_EINVAL;
   }
   if (!check_power(N, 2, 2048)) return BLTT_EUNSUPPORTED;
   for (int d = 0; d < blk->dim; ++d)
@@ -569,8 +696,10 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   h->opt.inner_tol = 1e-4;
   h->opt.max_refine = 20;
   h->opt.check_factor = 10.0;
+  h->opt.basis = BLTT_BASIS_SINE;
   if (opt) {
     h->opt.precision = opt->precision;
+    h->opt.basis = opt->basis;
     if (opt->inner_tol > 0.0) h->opt.inner_tol = opt->inner_tol;
     if (opt->max_refine > 0) h->opt.max_refine = opt->max_refine;
     if (opt->check_factor >= 1.0) h->opt.check_factor = opt->check_factor;
@@ -601,6 +730,8 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   };
   h->partials_cap = std::max(partials_needed<float>(h), partials_needed<double>(h));
   if ((rc = dalloc(h, &h->partials, (size_t)h->partials_cap))) return fail(rc);
+  h->red_half = h->partials_cap / RED_CHUNK + 2;
+  if ((rc = dalloc(h, &h->red_scratch, (size_t)(2 * h->red_half)))) return fail(rc);
   if ((rc = dalloc(h, &h->partials_aux,
                    (size_t)std::max(fft_blocks<float, FK_TIME>((int)h->N, h->M),
                                     fft_blocks<double, FK_TIME>((int)h->N, h->M)))))
@@ -623,6 +754,8 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   } else {
     if ((rc = build_workspace<double>(h))) return fail(rc);
   }
+  if (h->opt.basis == BLTT_BASIS_SINE)
+    if ((rc = dalloc(h, &h->F64, (size_t)h->n))) return fail(rc);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(BLTT_EHIP);
   h->setup_ms = now_ms() - t0;
   *out = h;
@@ -645,7 +778,81 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
   double relres = 0.0;
   int status = BLTT_OK;
 
-  if (h->opt.precision == BLTT_FP64) {
+  if (h->opt.basis == BLTT_BASIS_SINE) {
+    // fhat = (I x U) f once; the iteration and the FP64 residuals run on the
+    // mode-decoupled system; u = (I x U) uhat once at the end (U = U^T = U^{-1})
+    if ((rc = space_transform<double>(h, f_dev, h->F64))) return rc;
+    double* b64 = h->opt.precision == BLTT_FP64 ? h->w64.V[0] : h->R64;
+    {
+      ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
+      HIPCHK(launch_rhs<double>(h->F64, b64, h->N, h->M, 1.0, h->partials, &np, s));
+    }
+    if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+    if ((rc = read_state(h))) return rc;
+    const double bn2 = h->state_host->norm2;
+    if (!std::isfinite(bn2)) return BLTT_ENAN;
+    const double bnorm = std::sqrt(bn2);
+    if (hist) hist[0] = 1.0;
+    if (bn2 == 0.0) {
+      relres = 0.0;
+    } else if (h->opt.precision == BLTT_FP64) {
+      CoreResult cr;
+      rc = minres_spec<double, double, double>(h, u_dev, maxit, h->opt.check_factor * tol, h->F64, tol, bnorm, hist,
+                                               &cr, b64, h->coef_one);
+      if (rc) return rc;
+      total_iters = cr.iters;
+      outer = 1;
+      status = cr.status;
+      relres = cr.relres;
+      if (relres < 0.0) {
+        if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, u_dev, h->w64.Q, h->F64, &np))) return rc;
+        if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+        if ((rc = read_state(h))) return rc;
+        relres = std::sqrt(h->state_host->norm2) / bnorm;
+      }
+    } else {
+      // FP64 refinement around FP32 MINRES sweeps on r / ||r|| (state->rinv)
+      Workspace<float>& ws = h->w32;
+      double rnorm = bnorm;
+      status = BLTT_NOCONV;
+      int hist_pos = 0;
+      std::vector<double> hbuf;
+      while (true) {
+        relres = rnorm / bnorm;
+        if (relres <= tol) {
+          status = BLTT_OK;
+          break;
+        }
+        if (outer >= h->opt.max_refine || total_iters >= maxit) break;
+        {
+          ProfScope ps(h, BLTT_K_OTHER, 4.0 * h->n);
+          HIPCHK(launch_fill<float>(ws.X, h->n, 0.0f, s));
+        }
+        CoreResult cr;
+        const int left = maxit - total_iters;
+        hbuf.assign((size_t)left + 2, 0.0);
+        rc = minres_spec<float, float, double>(h, ws.X, left, h->opt.inner_tol, nullptr, 0.0, 1.0, hbuf.data(), &cr,
+                                               h->R64, &h->state->rinv);
+        if (rc) return rc;
+        if (hist)
+          for (int k = 1; k <= cr.iters; ++k) hist[hist_pos + k] = hbuf[(size_t)k];
+        hist_pos += cr.iters;
+        total_iters += cr.iters;
+        outer += 1;
+        // uhat += ||r|| d, then r = Y(fhat - A uhat) in FP64
+        {
+          ProfScope ps(h, BLTT_K_OTHER, 20.0 * h->n);
+          HIPCHK(launch_axpy64<float>(u_dev, ws.X, h->n, &h->state->rscale, s));
+        }
+        if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, u_dev, h->R64, h->F64, &np))) return rc;
+        if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+        if ((rc = read_state(h))) return rc;
+        rnorm = std::sqrt(h->state_host->norm2);
+        if (!std::isfinite(rnorm)) return BLTT_ENAN;
+      }
+    }
+    if ((rc = space_transform<double>(h, u_dev, u_dev))) return rc;
+  } else if (h->opt.precision == BLTT_FP64) {
     Workspace<double>& ws = h->w64;
     // b = Y f into V[0]
     {
@@ -679,7 +886,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     status = cr.status;
     relres = cr.relres;
     if (relres < 0.0) {
-      if ((rc = matvec<double>(h, MV_RESID, true, u_dev, ws.Q, f_dev, &np))) return rc;
+      if ((rc = matvec<double>(h, MV_RESID, TERM_STENCIL, u_dev, ws.Q, f_dev, &np))) return rc;
       if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
       if ((rc = read_state(h))) return rc;
       relres = std::sqrt(h->state_host->norm2) / bnorm;
@@ -734,7 +941,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         ProfScope ps(h, BLTT_K_OTHER, 20.0 * h->n);
         HIPCHK(launch_axpy64<float>(u_dev, ws.X, h->n, &h->state->rscale, s));
       }
-      if ((rc = matvec<double>(h, MV_RESID, true, u_dev, h->R64, f_dev, &np))) return rc;
+      if ((rc = matvec<double>(h, MV_RESID, TERM_STENCIL, u_dev, h->R64, f_dev, &np))) return rc;
       if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
       if ((rc = read_state(h))) return rc;
       rnorm = std::sqrt(h->state_host->norm2);
@@ -775,9 +982,9 @@ int bltt_apply_sym(bltt_handle* h, int32_t precision, const void* x_dev, void* y
   if (rc) return rc;
   int64_t np = 0;
   if (precision == BLTT_FP64)
-    rc = matvec<double>(h, MV_DOT, true, (const double*)x_dev, (double*)y_dev, nullptr, &np);
+    rc = matvec<double>(h, MV_DOT, TERM_STENCIL, (const double*)x_dev, (double*)y_dev, nullptr, &np);
   else
-    rc = matvec<float>(h, MV_DOT, true, (const float*)x_dev, (float*)y_dev, nullptr, &np);
+    rc = matvec<float>(h, MV_DOT, TERM_STENCIL, (const float*)x_dev, (float*)y_dev, nullptr, &np);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(h->stream));
   return BLTT_OK;

@@ -175,22 +175,28 @@ BLTT_HD T lap_row(const T* __restrict__ zrow, const Stencil& st, const Grid& gr)
 // Two spatial points are packed as the real and imaginary part of one complex
 // line (every operation is complex-linear with a real kernel).  The time
 // reversal Y is applied on the store; <Y A z, z> needs z at the mirrored time,
-// which comes from LDS.  With STENCIL false only Y (p * z) is formed (and its
-// dot with z): inside MINRES the spatial term is added by the x-line pass and
-// its dot product by the preceding time pass (sine coordinates).
+// which comes from LDS.  The spatial term of the blocks is
+//   TERM_NONE     absent: only Y (p * z) is formed (and its dot with z); inside
+//                 the physical-space MINRES the spatial term is added by the
+//                 x-line pass and its dot product by the preceding time pass;
+//   TERM_STENCIL  the finite-difference stencil L_h on physical-space lines;
+//   TERM_SPEC     sine coordinates (Remark 1): L_h is diag(mu), so line i gets
+//                 mu_i sum_k q_k z[n-k], with z[n-k] read from LDS.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct MatvecTables {
   const cx<T>* tw;    // length 2N: exp(-2 pi i k/(2N))
   const cx<T>* phat;  // length 2N: fft(p padded to 2N)/(2N)
+  const T* mu;        // TERM_SPEC: Laplacian eigenvalue of each sine mode (length M)
   T q[4];
   int qtaps;
   Grid grid;
 };
 
 enum { MV_DOT = 0, MV_RESID = 1 };
+enum { TERM_NONE = 0, TERM_STENCIL = 1, TERM_SPEC = 2 };
 
-template <typename T, int L, int MODE, bool STENCIL, class Ctx>
+template <typename T, int L, int MODE, int TERM, class Ctx>
 BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict__ z,
                              T* __restrict__ out, const T* __restrict__ fin, int64_t M,
                              const MatvecTables<T>& tb, double* __restrict__ partials) {
@@ -222,7 +228,7 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
     for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.phat[F::freq(g, w, u)];
   F::inverse(ctx, v, lds, c, g, tb.tw);
 
-  // z at the mirrored time N-1-n, for <Y A z, z>
+  // z at the mirrored time N-1-n, for <Y A z, z> (and z[n-k] for TERM_SPEC)
   ctx.sync();
 #pragma unroll
   for (int t = 0; t < VH; ++t) lds[F::idx(c, g + t * s0)] = zin[t];
@@ -230,6 +236,11 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
 
   const Stencil sta = make_stencil(va ? ia : 0, tb.grid);
   const Stencil stb = make_stencil(vb ? ib : 0, tb.grid);
+  T mua = T(0), mub = T(0);
+  if (TERM == TERM_SPEC) {
+    mua = tb.mu[iac];
+    mub = tb.mu[ibc];
+  }
   T* oa = out + ia;
   T* ob = out + ib;
   double part = 0.0;
@@ -237,12 +248,26 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   for (int t = 0; t < VH; ++t) {
     const int n = g + t * s0;
     T ya = v[t].re, yb = v[t].im;
-    if (STENCIL) {
+    if (TERM == TERM_STENCIL) {
       for (int k = 0; k < tb.qtaps && k <= n; ++k) {
         const int64_t off = (int64_t)(n - k) * M;
         if (va) ya += tb.q[k] * lap_row(za + off, sta, tb.grid);
         if (vb) yb += tb.q[k] * lap_row(zb + off, stb, tb.grid);
       }
+    }
+    if (TERM == TERM_SPEC) {
+      // taps beyond qtaps have q_k = 0; times before 0 read slot 0 with weight 0
+      T sa = tb.q[0] * zin[t].re, sb = tb.q[0] * zin[t].im;
+#pragma unroll
+      for (int k = 1; k < 4; ++k) {
+        const int nk = n - k;
+        const T w = nk >= 0 ? tb.q[k] : T(0);
+        const cx<T> zk = lds[F::idx(c, nk >= 0 ? nk : 0)];
+        sa += w * zk.re;
+        sb += w * zk.im;
+      }
+      ya += mua * sa;
+      yb += mub * sb;
     }
     const int64_t offr = (int64_t)(N - 1 - n) * M;
     if (MODE == MV_DOT) {
@@ -285,7 +310,8 @@ struct ShortTables {
   Grid grid;
   int N;
   int chunk;    // time steps per thread (from the first half)
-  int stencil;  // 0: only Y (p * z); the spatial term is added by the x-line pass
+  int term;     // TERM_NONE / TERM_STENCIL / TERM_SPEC, as for the FFT form
+  const T* mu;  // TERM_SPEC: Laplacian eigenvalue of each sine mode
 };
 
 template <typename T, int MODE, class Ctx>
@@ -305,8 +331,13 @@ BLTT_HD void matvec_short_body(Ctx& ctx, double* red, const T* __restrict__ z, T
         if (side == 1 && n == nn) break;  // odd N: middle step once
         T y = T(0);
         for (int k = 0; k < tb.ptaps && k <= n; ++k) y += tb.p[k] * z[(int64_t)(n - k) * M + i];
-        if (tb.stencil)
+        if (tb.term == TERM_STENCIL)
           for (int k = 0; k < tb.qtaps && k <= n; ++k) y += tb.q[k] * lap_at(z, (int64_t)(n - k) * M, i, tb.grid);
+        if (tb.term == TERM_SPEC) {
+          T s = T(0);
+          for (int k = 0; k < tb.qtaps && k <= n; ++k) s += tb.q[k] * z[(int64_t)(n - k) * M + i];
+          y += tb.mu[i] * s;
+        }
         const int64_t nr = (int64_t)(N - 1 - n);
         if (MODE == MV_DOT) {
           out[nr * M + i] = y;
@@ -766,6 +797,108 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 }
 
 // ---------------------------------------------------------------------------
+// Lanczos update fused with the time pass, for MINRES run in sine coordinates.
+// When every block is p_k I + q_k L_h, the orthonormal sine transform U
+// diagonalises L_h (Remark 1) and commutes with Y, so MINRES on
+// (I x U) Y A (I x U) with P^{-1} carried along is MINRES on Y A in another
+// orthonormal basis: the same scalars, and iterates that differ by the change
+// of basis.  In that basis P^{-1} is the time pass alone (Section 5.1 Step 2).
+// Per pair of modes a, b (one complex line):
+//   vhat = cq Q + cv V1 + cvp V2   (FULL; cq Q alone otherwise), stored to Vout
+//                                  when Vout is non-null;
+//   zhat = P^{-1} vhat             stored to Zout;
+//   partial sums of <vhat, zhat>   one per workgroup.
+// Q may be FP64 for an FP32 pass (the refinement right-hand side, scaled by cq
+// in FP64 before rounding).  FP32 keeps vhat in registers for the dot product;
+// FP64 reads it back from Vout (its own stores) or from Q.
+// ---------------------------------------------------------------------------
+template <typename T, int L, typename TQ, bool FULL, class Ctx>
+BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restrict__ Q,
+                           const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
+                           T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
+                           const double* __restrict__ coef, double* __restrict__ partials) {
+  constexpr int TPB = tpb_fft<T, FK_TIME>();
+  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
+  constexpr bool KEEP = sizeof(T) == 4;
+  using F = LineFft<T, L, NL, true, LAST_PAIRED>;
+  const T invN = T(1) / T(L);
+  const int tid = ctx.tid, c = tid % NL, g = tid / NL;
+  const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
+  const bool va = ia < M, vb = ib < M;
+  const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
+  const T mua = tb.mu[iac], mub = tb.mu[ibc];
+  const double cq = coef[0];
+  T cv = T(0), cvp = T(0);
+  if (FULL) {
+    cv = T(coef[1]);
+    cvp = T(coef[2]);
+  }
+
+  cx<T> keep[KEEP ? V : 1], v[V];
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int64_t off = (int64_t)(g + t * s0) * M;
+    T a, b;
+    if constexpr (sizeof(TQ) > sizeof(T)) {
+      a = T((double)Q[iac + off] * cq);
+      b = T((double)Q[ibc + off] * cq);
+    } else {
+      a = T(cq) * Q[iac + off];
+      b = T(cq) * Q[ibc + off];
+    }
+    if (FULL) {
+      a += cv * V1[iac + off] + cvp * V2[iac + off];
+      b += cv * V1[ibc + off] + cvp * V2[ibc + off];
+    }
+    v[t] = mkc<T>(va ? a : T(0), vb ? b : T(0));
+  }
+  if (Vout) {
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+      const int64_t off = (int64_t)(g + t * s0) * M;
+      if (va) Vout[ia + off] = v[t].re;
+      if (vb) Vout[ib + off] = v[t].im;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    if constexpr (KEEP) keep[t] = v[t];
+    v[t] = v[t] * alpha_pow_n(tb, tb.dinv, T(-1), g + t * s0);
+  }
+  F::forward(ctx, v, lds, c, g, tb.tw);
+  time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN);
+  F::inverse(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+  for (int t = 0; t < V; ++t) v[t] = v[t] * alpha_pow_n(tb, tb.d2, T(2), g + t * s0);
+  F::forward(ctx, v, lds, c, g, tb.tw);
+  time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN);
+  F::inverse(ctx, v, lds, c, g, tb.tw);
+  double part = 0.0;
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int n = g + t * s0;
+    const int64_t off = (int64_t)n * M;
+    const cx<T> z = v[t] * alpha_pow_n(tb, tb.dinv, T(-1), n);
+    if (va) Zout[ia + off] = z.re;
+    if (vb) Zout[ib + off] = z.im;
+    cx<T> in;
+    if constexpr (KEEP) {
+      in = keep[t];
+    } else if (Vout) {
+      // a lane past M reads another workgroup's element: select, never multiply
+      const T ra = Vout[iac + off], rb = Vout[ibc + off];
+      in = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
+    } else {
+      const T ra = T(cq) * T(Q[iac + off]), rb = T(cq) * T(Q[ibc + off]);
+      in = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
+    }
+    part += (double)in.re * (double)z.re + (double)in.im * (double)z.im;
+  }
+  const double sum = block_sum<TPB>(ctx, red, part);
+  if (tid == 0) partials[ctx.bid] = sum;
+}
+
+// ---------------------------------------------------------------------------
 // streaming kernels
 // ---------------------------------------------------------------------------
 
@@ -860,12 +993,38 @@ struct SolverState {
   double coef_w[4];  // cz, ca, cb, cx
   double norm2;      // last reduced squared norm (rhs or residual)
   double rscale;     // ||r|| of the current refinement right-hand side
+  double rinv;       // 1/||r|| (0 when r = 0)
   double dq;         // last reduced <q, z>
   double bsq;        // last reduced <vhat, zhat>
   int32_t iter;
   int32_t status;    // 0 running, 1 exact convergence (beta = 0), -3 NaN, -4 breakdown
   int32_t pad[2];
 };
+
+// First stage of a long reduction: workgroup b sums partials
+// [b*RED_CHUNK, (b+1)*RED_CHUNK) in a fixed order (deterministic), so the
+// single-workgroup scalar kernel reads at most a few hundred values.
+constexpr int RED_PER_THREAD = 16;
+constexpr int RED_CHUNK = RED_PER_THREAD * TPB_EW;
+
+template <class Ctx>
+BLTT_HD void reduce_chunk_body(Ctx& ctx, double* red, const double* __restrict__ in, int64_t n,
+                               double* __restrict__ out) {
+  const int64_t base = (int64_t)ctx.bid * RED_CHUNK + ctx.tid;
+  double v[RED_PER_THREAD];
+#pragma unroll
+  for (int k = 0; k < RED_PER_THREAD; ++k) {
+    const int64_t e = base + (int64_t)k * TPB_EW;
+    const double x = in[e < n ? e : n - 1];
+    v[k] = e < n ? x : 0.0;
+  }
+#pragma unroll
+  for (int w = RED_PER_THREAD / 2; w > 0; w >>= 1)
+#pragma unroll
+    for (int k = 0; k < w; ++k) v[k] += v[k + w];
+  const double sum = block_sum<TPB_EW>(ctx, red, v[0]);
+  if (ctx.tid == 0) out[ctx.bid] = sum;
+}
 
 template <class Ctx>
 BLTT_HD double reduce_partials(Ctx& ctx, double* red, const double* __restrict__ partials, int64_t np) {
@@ -891,6 +1050,7 @@ BLTT_HD void scalar_body(Ctx& ctx, double* red, int phase, SolverState* __restri
   if (phase == SC_NORM) {
     st->norm2 = sum;
     st->rscale = sqrt(sum);
+    st->rinv = sum > 0.0 ? 1.0 / st->rscale : 0.0;
     return;
   }
   if (phase == SC_START) {

@@ -4,7 +4,7 @@
 
 namespace bltt {
 
-template <typename T, int L, int MODE, bool STENCIL>
+template <typename T, int L, int MODE, int TERM>
 __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_MV>()), waves_fft<T>()) void k_matvec_fft(const T* __restrict__ z, T* __restrict__ out,
                                                              const T* __restrict__ fin, int64_t M,
                                                              MatvecTables<T> tb, double* __restrict__ partials) {
@@ -13,7 +13,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
   using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
-  matvec_fft_body<T, L, MODE, STENCIL>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb, partials);
+  matvec_fft_body<T, L, MODE, TERM>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb, partials);
 }
 
 template <typename T, int MODE>
@@ -25,41 +25,43 @@ __global__ __launch_bounds__(TPB_EW) void k_matvec_short(const T* __restrict__ z
   matvec_short_body<T, MODE>(ctx, red, z, out, fin, M, tb, partials);
 }
 
+// (mode, term) combinations in use: Y A z with the stencil (step entry point),
+// Y (p * z) alone (physical-space MINRES), the sine-coordinate forms, and the
+// residual without the stencil (its spatial term follows on x-lines)
+#define BLTT_MV_VARIANTS(X) X(MV_DOT, TERM_STENCIL) X(MV_DOT, TERM_NONE) X(MV_DOT, TERM_SPEC) \
+  X(MV_RESID, TERM_NONE) X(MV_RESID, TERM_SPEC)
+
 template <typename T, int L>
-static hipError_t go_mv(int mode, int stencil, const T* z, T* out, const T* fin, int64_t M,
+static hipError_t go_mv(int mode, int term, const T* z, T* out, const T* fin, int64_t M,
                         const MatvecTables<T>& tb, double* partials, hipStream_t s) {
   const int64_t blocks = fft_blocks<T, FK_MV>(L, M);
   const size_t lds = fft_lds_bytes<T, FK_MV>(L);
-  if (mode == MV_DOT && stencil)
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, s, z,
-                       out, fin, M, tb, partials);
-  else if (mode == MV_DOT)
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_DOT, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, s,
-                       z, out, fin, M, tb, partials);
-  else if (stencil)
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_RESID, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, s,
-                       z, out, fin, M, tb, partials);
-  else
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MV_RESID, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds,
-                       s, z, out, fin, M, tb, partials);
-  return hipGetLastError();
+#define BLTT_GO(MO, TE)                                                                                   \
+  if (mode == MO && term == TE) {                                                                         \
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MO, TE>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, \
+                       s, z, out, fin, M, tb, partials);                                                  \
+    return hipGetLastError();                                                                             \
+  }
+  BLTT_MV_VARIANTS(BLTT_GO)
+#undef BLTT_GO
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_matvec_fft(int L, int mode, int stencil, const T* z, T* out, const T* fin, int64_t M,
+hipError_t launch_matvec_fft(int L, int mode, int term, const T* z, T* out, const T* fin, int64_t M,
                              const MatvecTables<T>& tb, double* partials, hipStream_t s) {
   switch (L) {
-    case 4: return go_mv<T, 4>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 8: return go_mv<T, 8>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 16: return go_mv<T, 16>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 32: return go_mv<T, 32>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 64: return go_mv<T, 64>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 128: return go_mv<T, 128>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 256: return go_mv<T, 256>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 512: return go_mv<T, 512>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 1024: return go_mv<T, 1024>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 2048: return go_mv<T, 2048>(mode, stencil, z, out, fin, M, tb, partials, s);
-    case 4096: return go_mv<T, 4096>(mode, stencil, z, out, fin, M, tb, partials, s);
+    case 4: return go_mv<T, 4>(mode, term, z, out, fin, M, tb, partials, s);
+    case 8: return go_mv<T, 8>(mode, term, z, out, fin, M, tb, partials, s);
+    case 16: return go_mv<T, 16>(mode, term, z, out, fin, M, tb, partials, s);
+    case 32: return go_mv<T, 32>(mode, term, z, out, fin, M, tb, partials, s);
+    case 64: return go_mv<T, 64>(mode, term, z, out, fin, M, tb, partials, s);
+    case 128: return go_mv<T, 128>(mode, term, z, out, fin, M, tb, partials, s);
+    case 256: return go_mv<T, 256>(mode, term, z, out, fin, M, tb, partials, s);
+    case 512: return go_mv<T, 512>(mode, term, z, out, fin, M, tb, partials, s);
+    case 1024: return go_mv<T, 1024>(mode, term, z, out, fin, M, tb, partials, s);
+    case 2048: return go_mv<T, 2048>(mode, term, z, out, fin, M, tb, partials, s);
+    case 4096: return go_mv<T, 4096>(mode, term, z, out, fin, M, tb, partials, s);
   }
   return hipErrorInvalidValue;
 }
@@ -93,17 +95,14 @@ BLTT_INST(double)
 template <typename T, int L>
 static hipError_t attr_mv() {
   const int bytes = (int)fft_lds_bytes<T, FK_MV>(L);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_DOT, true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  hipError_t e = hipSuccess;
+#define BLTT_ATTR1(MO, TE)                                                                           \
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MO, TE>),                \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);                        \
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_DOT, false>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_RESID, true>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_RESID, false>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  BLTT_MV_VARIANTS(BLTT_ATTR1)
+#undef BLTT_ATTR1
+  return e;
 }
 
 hipError_t configure_matvec_kernels() {

@@ -47,6 +47,13 @@ __global__ __launch_bounds__(TPB_EW) void k_resid_stencil(T* __restrict__ r, Vup
   resid_stencil_body<T, Q1>(ctx, red, r, st, partials);
 }
 
+__global__ __launch_bounds__(TPB_EW) void k_reduce(const double* __restrict__ in, int64_t n,
+                                                   double* __restrict__ out) {
+  __shared__ double red[TPB_EW];
+  DevCtx ctx = make_ctx();
+  reduce_chunk_body(ctx, red, in, n, out);
+}
+
 __global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __restrict__ st,
                                                    const double* __restrict__ partials, int64_t np,
                                                    const double* __restrict__ aux, int64_t naux,
@@ -102,7 +109,23 @@ hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, 
   return hipGetLastError();
 }
 hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
-                         int64_t naux, double* hist, hipStream_t s) {
+                         int64_t naux, double* hist, double* scratch, int64_t scratch_half, hipStream_t s) {
+  // long partial-sum arrays go through one wide first stage (into scratch,
+  // aux at scratch + scratch_half)
+  if (np > RED_CHUNK) {
+    const int64_t nb = (np + RED_CHUNK - 1) / RED_CHUNK;
+    if (nb > scratch_half) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)nb), dim3(TPB_EW), 0, s, partials, np, scratch);
+    partials = scratch;
+    np = nb;
+  }
+  if (aux && naux > RED_CHUNK) {
+    const int64_t nb = (naux + RED_CHUNK - 1) / RED_CHUNK;
+    if (nb > scratch_half) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)nb), dim3(TPB_EW), 0, s, aux, naux, scratch + scratch_half);
+    aux = scratch + scratch_half;
+    naux = nb;
+  }
   hipLaunchKernelGGL(k_scalar, dim3(1), dim3(TPB_EW), 0, s, phase, st, partials, np, aux, naux, hist);
   return hipGetLastError();
 }
@@ -127,12 +150,14 @@ template hipError_t launch_axpy64<double>(double*, const double*, int64_t, const
 hipError_t configure_time_kernels();
 hipError_t configure_matvec_kernels();
 hipError_t configure_dst_kernels();
+hipError_t configure_spec_kernels();
 
 hipError_t configure_kernels() {
   hipError_t e;
   if ((e = configure_time_kernels()) != hipSuccess) return e;
   if ((e = configure_matvec_kernels()) != hipSuccess) return e;
-  return configure_dst_kernels();
+  if ((e = configure_dst_kernels()) != hipSuccess) return e;
+  return configure_spec_kernels();
 }
 
 }  // namespace bltt

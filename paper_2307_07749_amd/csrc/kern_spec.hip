@@ -1,0 +1,79 @@
+// Lanczos update fused with the time pass of the preconditioner, for MINRES in
+// sine coordinates: one workgroup per 2*NL sine modes.
+#include "launchers.hpp"
+
+namespace bltt {
+
+template <typename T, int L, typename TQ, bool FULL>
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_TIME>()), waves_fft<T>()) void k_time_upd(
+    const TQ* __restrict__ Q, const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
+    T* __restrict__ Zout, int64_t M, TimeTables<T> tb, const double* __restrict__ coef,
+    double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NL = tpb_fft<T, FK_TIME>() / (L / fft_V(L));
+  using F = LineFft<T, L, NL, true, LAST_PAIRED>;
+  DevCtx ctx = make_ctx();
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
+  time_upd_body<T, L, TQ, FULL>(ctx, reinterpret_cast<cx<T>*>(smem), red, Q, V1, V2, Vout, Zout, M, tb, coef,
+                                partials);
+}
+
+template <typename T, typename TQ, int L>
+static hipError_t go_upd(bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
+                         const TimeTables<T>& tb, const double* coef, double* partials, hipStream_t s) {
+  const int64_t blocks = fft_blocks<T, FK_TIME>(L, M);
+  const size_t lds = fft_lds_bytes<T, FK_TIME>(L);
+  if (full)
+    hipLaunchKernelGGL((k_time_upd<T, L, TQ, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s, Q,
+                       V1, V2, Vout, Zout, M, tb, coef, partials);
+  else
+    hipLaunchKernelGGL((k_time_upd<T, L, TQ, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s,
+                       Q, V1, V2, Vout, Zout, M, tb, coef, partials);
+  return hipGetLastError();
+}
+
+template <typename T, typename TQ>
+hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
+                           const TimeTables<T>& tb, const double* coef, double* partials, hipStream_t s) {
+  if (full && (!V1 || !V2)) return hipErrorInvalidValue;
+  switch (L) {
+#define BLTT_CASE(LL) \
+  case LL: return go_upd<T, TQ, LL>(full, Q, V1, V2, Vout, Zout, M, tb, coef, partials, s);
+    BLTT_CASE(2) BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64)
+    BLTT_CASE(128) BLTT_CASE(256) BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
+#undef BLTT_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+#define BLTT_INST(T, TQ)                                                                                      \
+  template hipError_t launch_time_upd<T, TQ>(int, bool, const TQ*, const T*, const T*, T*, T*, int64_t,      \
+                                             const TimeTables<T>&, const double*, double*, hipStream_t);
+BLTT_INST(float, float)
+BLTT_INST(float, double)
+BLTT_INST(double, double)
+#undef BLTT_INST
+
+template <typename T, typename TQ, int L>
+static hipError_t attr_upd() {
+  const int bytes = (int)fft_lds_bytes<T, FK_TIME>(L);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t configure_spec_kernels() {
+  hipError_t e = hipSuccess;
+#define BLTT_ATTR(L)                                                  \
+  if ((e = attr_upd<float, float, L>()) != hipSuccess) return e;     \
+  if ((e = attr_upd<float, double, L>()) != hipSuccess) return e;    \
+  if ((e = attr_upd<double, double, L>()) != hipSuccess) return e;
+  BLTT_ATTR(2) BLTT_ATTR(4) BLTT_ATTR(8) BLTT_ATTR(16) BLTT_ATTR(32) BLTT_ATTR(64)
+  BLTT_ATTR(128) BLTT_ATTR(256) BLTT_ATTR(512) BLTT_ATTR(1024) BLTT_ATTR(2048)
+#undef BLTT_ATTR
+  return e;
+}
+
+}  // namespace bltt

@@ -30,8 +30,14 @@ inline int64_t ew_blocks(int64_t n) {
 template <typename T>
 hipError_t launch_time_prec(int L, T* x, int64_t M, const TimeTables<T>& tb, hipStream_t s);
 
+// sine coordinates: vhat = cq Q (+ cv V1 + cvp V2 when full) -> Vout (optional),
+// Zout = P^{-1} vhat (time pass), per-workgroup partial sums of <vhat, Zout>
+template <typename T, typename TQ>
+hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
+                           const TimeTables<T>& tb, const double* coef, double* partials, hipStream_t s);
+
 template <typename T>
-hipError_t launch_matvec_fft(int L, int mode, int stencil, const T* z, T* out, const T* fin, int64_t M,
+hipError_t launch_matvec_fft(int L, int mode, int term, const T* z, T* out, const T* fin, int64_t M,
                              const MatvecTables<T>& tb, double* partials, hipStream_t s);
 
 template <typename T>
@@ -64,7 +70,9 @@ template <typename TI, typename TO>
 hipError_t launch_scale_cast(const TI* x, TO* y, int64_t n, const double* sptr, int invert, hipStream_t s);
 template <typename TD>
 hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, hipStream_t s);
+// scratch: 2*scratch_half doubles for the first reduction stage of long
+// partial-sum arrays (at most scratch_half workgroups of RED_CHUNK each)
 hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
-                         int64_t naux, double* hist, hipStream_t s);
+                         int64_t naux, double* hist, double* scratch, int64_t scratch_half, hipStream_t s);
 
 }  // namespace bltt

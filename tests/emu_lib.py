@@ -63,6 +63,19 @@ def lib():
             getattr(L, f"emu_vupd_stencil_{t}").argtypes = args + [P, P, P]
             getattr(L, f"emu_time_aux_{t}").argtypes = args + [P]
             getattr(L, f"emu_time_aux_{t}").restype = ctypes.c_double
+        for t in ("f64", "f32"):
+            getattr(L, f"emu_time_upd_{t}").argtypes = args + [P, P, P, P, P, P, ctypes.c_int]
+            getattr(L, f"emu_time_upd_{t}").restype = ctypes.c_double
+            getattr(L, f"emu_sym_spec_{t}").argtypes = args + [P, P, ctypes.c_int]
+            getattr(L, f"emu_sym_spec_{t}").restype = ctypes.c_double
+            getattr(L, f"emu_wx_{t}").argtypes = [P, P, P, P, ctypes.c_int64, P]
+        L.emu_time_upd_mixed.argtypes = args + [P, P, P, P]
+        L.emu_time_upd_mixed.restype = ctypes.c_double
+        L.emu_resid_spec_f64.argtypes = args + [P, P, P, ctypes.c_int]
+        L.emu_resid_spec_f64.restype = ctypes.c_double
+        L.emu_state_size.restype = ctypes.c_int64
+        L.emu_state_offsets.argtypes = [P]
+        L.emu_scalar.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P]
         L.emu_resid_f64.argtypes = args + [P, P, P]
         L.emu_resid_f64.restype = ctypes.c_double
         L.emu_error.restype = ctypes.c_int
@@ -183,3 +196,105 @@ def resid(prob, u, f):
     s = lib().emu_resid_f64(*args, gu.ptr, gf.ptr, gr.ptr)
     _check(gu, gf, gr)
     return gr.data.copy(), s
+
+
+def _ptr(g):
+    return None if g is None else g.ptr
+
+
+def time_upd(prob, Q, V1, V2, coef, full, dtype=np.float64, write_v=True):
+    """vhat = c0 Q (+ c1 V1 + c2 V2), zhat = P^{-1} vhat in sine coordinates;
+    returns (vhat as stored or None, zhat, <vhat, zhat>)."""
+    args, keep = _common(prob)
+    gq = Guarded(Q, dtype)
+    g1 = Guarded(V1, dtype) if V1 is not None else None
+    g2 = Guarded(V2, dtype) if V2 is not None else None
+    gv = Guarded(np.zeros(prob.n), dtype) if write_v else None
+    gz = Guarded(np.zeros(prob.n), dtype)
+    c = np.ascontiguousarray(coef, dtype=np.float64)
+    dot = getattr(lib(), f"emu_time_upd_{_tag(dtype)}")(*args, gq.ptr, _ptr(g1), _ptr(g2), _ptr(gv), gz.ptr,
+                                                        c.ctypes.data, int(full))
+    _check(*[g for g in (gq, g1, g2, gv, gz) if g is not None])
+    return (gv.data.copy() if gv is not None else None), gz.data.copy(), dot
+
+
+def time_upd_mixed(prob, Q64, coef):
+    """FP32 pass on an FP64 right-hand side scaled by coef[0]."""
+    args, keep = _common(prob)
+    gq = Guarded(Q64, np.float64)
+    gv = Guarded(np.zeros(prob.n), np.float32)
+    gz = Guarded(np.zeros(prob.n), np.float32)
+    c = np.ascontiguousarray(coef, dtype=np.float64)
+    dot = lib().emu_time_upd_mixed(*args, gq.ptr, gv.ptr, gz.ptr, c.ctypes.data)
+    _check(gq, gv, gz)
+    return gv.data.copy(), gz.data.copy(), dot
+
+
+def sym_spec(prob, z, dtype=np.float64, force_fft=False):
+    args, keep = _common(prob)
+    gz = Guarded(z, dtype)
+    go = Guarded(np.zeros(z.size), dtype)
+    dot = getattr(lib(), f"emu_sym_spec_{_tag(dtype)}")(*args, gz.ptr, go.ptr, int(force_fft))
+    _check(gz, go)
+    return go.data.copy(), dot
+
+
+def resid_spec(prob, u, f, force_fft=False):
+    args, keep = _common(prob)
+    gu = Guarded(u, np.float64)
+    gf = Guarded(f, np.float64)
+    gr = Guarded(np.zeros(u.size), np.float64)
+    s = lib().emu_resid_spec_f64(*args, gu.ptr, gf.ptr, gr.ptr, int(force_fft))
+    _check(gu, gf, gr)
+    return gr.data.copy(), s
+
+
+class State:
+    """The solver's device-resident scalar state, on the host."""
+
+    SC_NORM, SC_START, SC_DELTA, SC_BETA = 0, 1, 2, 3
+
+    def __init__(self):
+        L = lib()
+        self.buf = np.zeros(int(L.emu_state_size()), dtype=np.uint8)
+        off = np.zeros(8, dtype=np.int64)
+        L.emu_state_offsets(off.ctypes.data)
+        self.off = [int(o) for o in off]
+
+    @property
+    def ptr(self):
+        return self.buf.ctypes.data
+
+    def coef_v_ptr(self):
+        return self.ptr + self.off[0]
+
+    def coef_w_ptr(self):
+        return self.ptr + self.off[1]
+
+    def f64(self, k):
+        return float(np.frombuffer(self.buf, dtype=np.float64, count=1, offset=self.off[k])[0])
+
+    @property
+    def eta(self):
+        return self.f64(2)
+
+    @property
+    def eta0(self):
+        return self.f64(3)
+
+    @property
+    def status(self):
+        return int(np.frombuffer(self.buf, dtype=np.int32, count=1, offset=self.off[4])[0])
+
+    def coef_v(self):
+        return np.frombuffer(self.buf, dtype=np.float64, count=3, offset=self.off[0]).copy()
+
+    def scalar(self, phase, total, hist=None):
+        part = np.array([total], dtype=np.float64)
+        lib().emu_scalar(phase, self.ptr, part.ctypes.data, 1, None if hist is None else hist.ctypes.data)
+
+
+def wx(Z, Wa, Wb, X, coef_ptr):
+    """Wa <- c0 Z + c1 Wa + c2 Wb; X += c3 Wa (in place on numpy arrays)."""
+    tag = "f64" if Z.dtype == np.float64 else "f32"
+    getattr(lib(), f"emu_wx_{tag}")(Z.ctypes.data, Wa.ctypes.data, Wb.ctypes.data, X.ctypes.data, Z.size, coef_ptr)

@@ -10,6 +10,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <functional>
 #include <mutex>
@@ -192,10 +194,11 @@ struct MvRun {
                [&](HostCtx& c, unsigned char* lds) {
         double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
         if (stencil)
-          matvec_fft_body<T, L, MV_DOT, true>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb, partials);
+          matvec_fft_body<T, L, MV_DOT, TERM_STENCIL>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb,
+                                                      partials);
         else
-          matvec_fft_body<T, L, MV_DOT, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb,
-                                               partials);
+          matvec_fft_body<T, L, MV_DOT, TERM_NONE>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb,
+                                                   partials);
       });
     }
   };
@@ -358,7 +361,8 @@ double apply_sym(const Problem& P, const T* z, T* out, bool force_fft, bool sten
     tb.grid = grid_of(P);
     tb.N = (int)P.N;
     tb.chunk = 8;
-    tb.stencil = stencil ? 1 : 0;
+    tb.term = stencil ? TERM_STENCIL : TERM_NONE;
+    tb.mu = nullptr;
     const int gx = (int)((P.M + TPB_EW - 1) / TPB_EW);
     const int gy = (int)(((P.N + 1) / 2 + tb.chunk - 1) / tb.chunk);
     std::vector<double> partials((size_t)gx * gy);
@@ -394,8 +398,8 @@ struct MvResRun {
       run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
                [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
-                 matvec_fft_body<T, L, MV_RESID, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M, tb,
-                                                        partials);
+                 matvec_fft_body<T, L, MV_RESID, TERM_NONE>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M,
+                                                            tb, partials);
                });
     }
   };
@@ -453,9 +457,140 @@ double apply_time_aux(const Problem& P, T* x) {
   return s;
 }
 
+// Lanczos update + time pass (sine coordinates), returning the summed dot
+template <typename T, typename TQ>
+struct UpdRun {
+  template <int L>
+  struct R {
+    static void run(const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M, const TimeTables<T>& tb,
+                    const double* coef, double* partials, bool full) {
+      constexpr int NL = lines_per_block<T, FK_TIME>(L);
+      using Ft = LineFft<T, L, NL, true, LAST_PAIRED>;
+      run_grid(tpb_fft<T, FK_TIME>(), (int)fft_blocks<T, FK_TIME>(L, M), 1, fft_lds_bytes<T, FK_TIME>(L),
+               [&](HostCtx& c, unsigned char* lds) {
+                 double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Ft::LDS_ELEMS);
+                 if (full)
+                   time_upd_body<T, L, TQ, true>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout, M, tb,
+                                                 coef, partials);
+                 else
+                   time_upd_body<T, L, TQ, false>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout, M,
+                                                  tb, coef, partials);
+               });
+    }
+  };
+};
+
+template <typename T, typename TQ>
+double apply_time_upd(const Problem& P, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, const double* coef,
+                      bool full) {
+  HostTables<T> ht(P);
+  TimeTables<T> tt = time_tables<T>(P, ht);
+  std::vector<double> partials((size_t)fft_blocks<T, FK_TIME>((int)P.N, P.M), 0.0);
+  with_L<UpdRun<T, TQ>::template R>((int)P.N, Q, V1, V2, Vout, Zout, P.M, tt, coef, partials.data(), full);
+  double s = 0.0;
+  for (double v : partials) s += v;
+  return s;
+}
+
+// sine-coordinate matvec (MV_DOT) or residual (MV_RESID), FFT or direct form
+template <typename T, int MODE>
+struct MvSpecRun {
+  template <int L>
+  struct R {
+    static void run(const T* z, T* out, const T* fin, int64_t M, const MatvecTables<T>& tb, double* partials) {
+      constexpr int NL = lines_per_block<T, FK_MV>(L);
+      using Fm = LineFft<T, L, NL, true, LAST_DEFAULT>;
+      run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
+               [&](HostCtx& c, unsigned char* lds) {
+                 double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
+                 matvec_fft_body<T, L, MODE, TERM_SPEC>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M, tb,
+                                                        partials);
+               });
+    }
+  };
+};
+
+template <typename T, int MODE>
+double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force_fft) {
+  int ptaps = 0, qtaps = 0;
+  for (int64_t k = 0; k < P.N; ++k) {
+    if (P.p[(size_t)k] != 0.0) ptaps = (int)k + 1;
+    if (P.q[(size_t)k] != 0.0) qtaps = (int)k + 1;
+  }
+  HostTables<T> ht(P);
+  double dot = 0.0;
+  if (ptaps <= 8 && !force_fft) {
+    ShortTables<T> tb;
+    for (int k = 0; k < 8; ++k) tb.p[k] = (T)(k < ptaps ? P.p[(size_t)k] : 0.0);
+    tb.ptaps = ptaps;
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+    tb.qtaps = qtaps;
+    tb.grid = grid_of(P);
+    tb.N = (int)P.N;
+    tb.chunk = 8;
+    tb.term = TERM_SPEC;
+    tb.mu = ht.mu.data();
+    const int gx = (int)((P.M + TPB_EW - 1) / TPB_EW);
+    const int gy = (int)(((P.N + 1) / 2 + tb.chunk - 1) / tb.chunk);
+    std::vector<double> partials((size_t)gx * gy);
+    run_grid(TPB_EW, gx, gy, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
+      matvec_short_body<T, MODE>(c, reinterpret_cast<double*>(lds), z, out, fin, P.M, tb, partials.data());
+    });
+    for (double v : partials) dot += v;
+  } else {
+    MatvecTables<T> tb;
+    tb.tw = ht.tw_mv.data();
+    tb.phat = ht.phat.data();
+    tb.mu = ht.mu.data();
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+    tb.qtaps = qtaps;
+    tb.grid = grid_of(P);
+    std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
+    with_L2<MvSpecRun<T, MODE>::template R>((int)(2 * P.N), z, out, fin, P.M, tb, partials.data());
+    for (double v : partials) dot += v;
+  }
+  return dot;
+}
+
+// scalar phase and direction/iterate update, as the solver sequences them
+void apply_scalar(int phase, SolverState* st, const double* partials, int64_t np, double* hist) {
+  run_grid(TPB_EW, 1, 1, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
+    scalar_body(c, reinterpret_cast<double*>(lds), phase, st, partials, np, (const double*)nullptr, 0, hist);
+  });
+}
+
+template <typename T>
+void apply_wx(const T* Z, T* Wa, const T* Wb, T* X, int64_t n, const double* coef) {
+  const int nb = (int)std::min<int64_t>((n + TPB_EW - 1) / TPB_EW, 64);
+  run_grid(TPB_EW, nb, 1, 0, [&](HostCtx& c, unsigned char*) { wx_body<T, T>(c, Z, Wa, Wb, X, n, coef); });
+}
+
 }  // namespace
 
 extern "C" {
+
+int64_t emu_state_size(void) { return (int64_t)sizeof(SolverState); }
+// byte offsets: coef_v, coef_w, eta, eta0, status, rinv, rscale, iter
+void emu_state_offsets(int64_t* o) {
+  o[0] = offsetof(SolverState, coef_v);
+  o[1] = offsetof(SolverState, coef_w);
+  o[2] = offsetof(SolverState, eta);
+  o[3] = offsetof(SolverState, eta0);
+  o[4] = offsetof(SolverState, status);
+  o[5] = offsetof(SolverState, rinv);
+  o[6] = offsetof(SolverState, rscale);
+  o[7] = offsetof(SolverState, iter);
+}
+void emu_scalar(int phase, void* st, const double* partials, int64_t np, double* hist) {
+  apply_scalar(phase, reinterpret_cast<SolverState*>(st), partials, np, hist);
+}
+void emu_wx_f64(const double* Z, double* Wa, const double* Wb, double* X, int64_t n, const double* coef) {
+  apply_wx<double>(Z, Wa, Wb, X, n, coef);
+}
+void emu_wx_f32(const float* Z, float* Wa, const float* Wb, float* X, int64_t n, const double* coef) {
+  apply_wx<float>(Z, Wa, Wb, X, n, coef);
+}
+
 
 int emu_error(void) { return g_error; }
 
@@ -491,5 +626,26 @@ double emu_resid_f64(EMU_ARGS, const double* u, const double* f, double* r) {
   return apply_resid<double>(EMU_P, u, f, r);
 }
 double emu_time_aux_f32(EMU_ARGS, float* x) { return apply_time_aux<float>(EMU_P, x); }
+double emu_time_upd_f64(EMU_ARGS, const double* Q, const double* V1, const double* V2, double* Vout, double* Zout,
+                        const double* coef, int full) {
+  return apply_time_upd<double, double>(EMU_P, Q, V1, V2, Vout, Zout, coef, full != 0);
+}
+double emu_time_upd_f32(EMU_ARGS, const float* Q, const float* V1, const float* V2, float* Vout, float* Zout,
+                        const double* coef, int full) {
+  return apply_time_upd<float, float>(EMU_P, Q, V1, V2, Vout, Zout, coef, full != 0);
+}
+double emu_time_upd_mixed(EMU_ARGS, const double* Q, float* Vout, float* Zout, const double* coef) {
+  return apply_time_upd<float, double>(EMU_P, Q, (const float*)nullptr, (const float*)nullptr, Vout, Zout, coef,
+                                       false);
+}
+double emu_sym_spec_f64(EMU_ARGS, const double* z, double* out, int force_fft) {
+  return apply_spec<double, MV_DOT>(EMU_P, z, out, (const double*)nullptr, force_fft != 0);
+}
+double emu_sym_spec_f32(EMU_ARGS, const float* z, float* out, int force_fft) {
+  return apply_spec<float, MV_DOT>(EMU_P, z, out, (const float*)nullptr, force_fft != 0);
+}
+double emu_resid_spec_f64(EMU_ARGS, const double* u, const double* f, double* r, int force_fft) {
+  return apply_spec<double, MV_RESID>(EMU_P, u, r, f, force_fft != 0);
+}
 
 }  // extern "C"

@@ -1,0 +1,161 @@
+"""CPU emulation of the sine-coordinate kernels against the oracle.
+
+In sine coordinates (I_N x U) every block p_k I + q_k L_h is diagonal in
+space (Remark 1), so the operators the sine-basis MINRES applies are the
+oracle's operators conjugated by the orthonormal, symmetric transform U:
+  K_s = U (Y A) U,  P_s^{-1} = U P^{-1} U.
+The last test drives the whole sine-basis MINRES from these emulated kernels
+(and the emulated scalar and update kernels) and checks it against the
+oracle's physical-space PMINRES: same residual-estimate history, same
+iterate after transforming back.
+"""
+import numpy as np
+import pytest
+
+from oracle import bltt_oracle as O
+from paper_2307_07749_amd import workloads as W
+from tests import emu_lib as E
+
+TOL = {np.float64: 1e-12, np.float32: 2e-5}
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def prob_of(kind, dim, m, N, alpha=0.05, gamma=0.4):
+    return {"frac": lambda: W.fractional_l1(dim, m, N, gamma, alpha),
+            "heat": lambda: W.heat_bdf(dim, m, N, alpha),
+            "cn": lambda: W.heat_cn(dim, m, N, alpha)}[kind]()
+
+
+def U(prob, x):
+    return O.space_transform(np.asarray(x).reshape(prob.N, -1), prob.m).ravel()
+
+
+def ref_prec_sine(prob, sysm, P, x):
+    return U(prob, O.precond_apply(P, U(prob, x).reshape(prob.N, -1)))
+
+
+def ref_sym_sine(prob, sysm, z):
+    return U(prob, O.sym_apply(sysm, U(prob, z).reshape(prob.N, -1)))
+
+
+UPD_CASES = [("frac", 1, 31, 32, 0.01), ("heat", 2, 7, 16, 0.01), ("cn", 2, 7, 8, 0.2), ("frac", 3, 3, 8, 0.05),
+             ("frac", 1, 5, 256, 0.01), ("frac", 2, 3, 2, 0.5), ("heat", 1, 3, 2048, 0.01)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("kind,dim,m,N,alpha", UPD_CASES)
+def test_time_upd(kind, dim, m, N, alpha, dtype):
+    prob = prob_of(kind, dim, m, N, alpha)
+    sysm = O.from_problem(prob)
+    P = O.precond_setup(sysm)
+    rng = np.random.default_rng(N * 7 + m)
+    Q, V1, V2 = (rng.standard_normal(prob.n) for _ in range(3))
+    coef = [0.7, -1.3, 0.4]
+    v, z, dot = E.time_upd(prob, Q, V1, V2, coef, True, dtype)
+    cast = lambda a: a.astype(dtype).astype(np.float64)
+    vhat = coef[0] * cast(Q) + coef[1] * cast(V1) + coef[2] * cast(V2)
+    assert rel(v, vhat) < TOL[dtype]
+    ref = ref_prec_sine(prob, sysm, P, vhat)
+    # D^{-1} = diag(alpha^{-n/N}) enters twice: rounding grows like eps log2(N) / alpha^2
+    tol = max(1e-11, 2 * 2.2e-16 * np.log2(N) / alpha ** 2) if dtype == np.float64 else 5e-5 / alpha ** 0.5
+    assert rel(z, ref) < tol
+    assert abs(dot - np.dot(vhat, ref)) <= tol * np.linalg.norm(vhat) * np.linalg.norm(ref) * 10
+    # start form: cq Q alone; FP64 reads vhat back from Q when Vout is absent
+    v0, z0, dot0 = E.time_upd(prob, Q, None, None, [2.0, 0, 0], False, dtype, write_v=False)
+    ref0 = ref_prec_sine(prob, sysm, P, 2.0 * cast(Q))
+    assert v0 is None and rel(z0, ref0) < tol
+    assert abs(dot0 - np.dot(2.0 * cast(Q), ref0)) <= tol * np.linalg.norm(Q) * np.linalg.norm(ref0) * 20
+
+
+@pytest.mark.parametrize("kind,dim,m,N,alpha", UPD_CASES[:4])
+def test_time_upd_fp64_rhs(kind, dim, m, N, alpha):
+    """FP32 pass on an FP64 refinement residual scaled by 1/||r|| before rounding."""
+    prob = prob_of(kind, dim, m, N, alpha)
+    sysm = O.from_problem(prob)
+    P = O.precond_setup(sysm)
+    r = np.random.default_rng(5).standard_normal(prob.n) * 3e-9
+    s = 1.0 / np.linalg.norm(r)
+    v, z, dot = E.time_upd_mixed(prob, r, [s, 0, 0])
+    b = (r * s).astype(np.float32).astype(np.float64)
+    assert np.array_equal(v.astype(np.float64), b)
+    ref = ref_prec_sine(prob, sysm, P, b)
+    assert rel(z, ref) < 5e-5 / alpha ** 0.5
+    assert abs(dot - np.dot(b, ref)) < 1e-4 * np.linalg.norm(ref)
+
+
+SPEC_CASES = [("frac", 1, 31, 32), ("heat", 2, 7, 16), ("cn", 2, 5, 8), ("frac", 3, 3, 8), ("cn", 3, 3, 4),
+              ("frac", 1, 3, 2048), ("heat", 1, 3, 2), ("frac", 2, 15, 64)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("force_fft", [False, True])
+@pytest.mark.parametrize("kind,dim,m,N", SPEC_CASES)
+def test_sym_spec(kind, dim, m, N, force_fft, dtype):
+    prob = prob_of(kind, dim, m, N)
+    sysm = O.from_problem(prob)
+    z = np.random.default_rng(31).standard_normal(prob.n)
+    got, dot = E.sym_spec(prob, z, dtype, force_fft)
+    ref = ref_sym_sine(prob, sysm, z)
+    assert rel(got, ref) < TOL[dtype] * 50
+    zz = z.astype(dtype).astype(np.float64)
+    assert abs(dot - np.dot(ref, zz)) <= TOL[dtype] * 50 * np.linalg.norm(ref) * np.linalg.norm(zz)
+
+
+@pytest.mark.parametrize("force_fft", [False, True])
+@pytest.mark.parametrize("kind,dim,m,N", SPEC_CASES[:5])
+def test_resid_spec(kind, dim, m, N, force_fft):
+    prob = prob_of(kind, dim, m, N)
+    sysm = O.from_problem(prob)
+    rng = np.random.default_rng(41)
+    u, f = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
+    r, s = E.resid_spec(prob, u, f, force_fft)
+    ref = O.time_reverse((f - U(prob, O.bltt_apply(sysm, U(prob, u).reshape(N, -1)))).reshape(N, -1)).ravel()
+    assert rel(r, ref) < 1e-12
+    assert abs(s - np.dot(ref, ref)) < 1e-10 * np.dot(ref, ref)
+
+
+def sine_minres(prob, f, tol_eta, maxit, dtype=np.float64):
+    """The sine-basis MINRES exactly as the library sequences its kernels."""
+    n = prob.n
+    fs = U(prob, f)
+    b = O.time_reverse(fs.reshape(prob.N, -1)).ravel()
+    st = E.State()
+    hist = np.zeros(maxit + 2)
+    Vc = b.astype(dtype)
+    _, Zc, d = E.time_upd(prob, Vc, None, None, [1.0, 0, 0], False, dtype, write_v=False)
+    Zc = Zc.astype(dtype)
+    st.scalar(E.State.SC_START, d, hist)
+    Vp = np.zeros(n, dtype)
+    Wa, Wb, X = np.zeros(n, dtype), np.zeros(n, dtype), np.zeros(n, dtype)
+    j = 0
+    for j in range(1, maxit + 1):
+        q, dq = E.sym_spec(prob, Zc, dtype, force_fft=True)
+        st.scalar(E.State.SC_DELTA, dq)
+        cv = st.coef_v()
+        Vn, Zn, dv = E.time_upd(prob, q, Vc, Vp if j > 1 else Vc, cv, True, dtype)
+        st.scalar(E.State.SC_BETA, dv, hist)
+        E.wx(Zc, Wa, Wb, X, st.coef_w_ptr())
+        Vp, Vc = Vc, Vn.astype(dtype)
+        Zc = Zn.astype(dtype)
+        Wa, Wb = Wb, Wa
+        assert st.status >= 0
+        if abs(st.eta) / st.eta0 <= tol_eta or st.status == 1:
+            break
+    return U(prob, X.astype(np.float64)), j, hist[:j + 1]
+
+
+@pytest.mark.parametrize("kind,dim,m,N,alpha", [("frac", 1, 15, 32, 0.01), ("heat", 2, 7, 16, 0.01),
+                                                ("cn", 2, 7, 8, 0.05), ("frac", 3, 3, 8, 0.05)])
+def test_sine_minres_matches_oracle(kind, dim, m, N, alpha):
+    prob = prob_of(kind, dim, m, N, alpha, gamma=0.5)
+    sysm = O.from_problem(prob)
+    f = W.rhs_normal(prob, 9)
+    ores = O.pminres(sysm, f, 1e-10, 60)
+    x, iters, hist = sine_minres(prob, f, 1e-11, 60)
+    k = min(len(hist), len(ores.eta_hist))
+    assert np.allclose(hist[:k], ores.eta_hist[:k], rtol=1e-7, atol=1e-13)
+    ustar = O.exact_solve(sysm, f).ravel()
+    assert np.linalg.norm(x - ustar) / np.linalg.norm(ustar) < 1e-9

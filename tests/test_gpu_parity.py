@@ -82,22 +82,33 @@ SOLVE_CASES = [("frac", 1, 31, 32, 0.01, 1e-10), ("heat", 2, 15, 32, 0.01, 1e-10
                ("frac", 2, 31, 64, 0.01, 1e-10), ("cn", 2, 15, 16, 0.05, 1e-10), ("frac", 3, 7, 16, 0.01, 1e-10)]
 
 
+BASES = [bltt.SINE, bltt.PHYSICAL]
+
+
+@pytest.mark.parametrize("basis", BASES)
 @pytest.mark.parametrize("kind,dim,m,N,alpha,tol", SOLVE_CASES)
-def test_fp64_solve_matches_oracle(kind, dim, m, N, alpha, tol):
+def test_fp64_solve_matches_oracle(kind, dim, m, N, alpha, tol, basis):
     prob = prob_of(kind, dim, m, N, alpha, gamma=0.5)
-    print(f"[fp64 solve] {kind} dim={dim} m={m} N={N}", flush=True)
+    print(f"[fp64 solve] {kind} dim={dim} m={m} N={N} basis={basis}", flush=True)
     sysm = O.from_problem(prob)
     f = W.rhs_normal(prob, 11)
     ustar = O.exact_solve(sysm, f).ravel()
     ores = O.pminres(sysm, f, tol, 100)
-    s = bltt.Solver.from_problem(prob, precision=bltt.FP64)
+    s = bltt.Solver.from_problem(prob, precision=bltt.FP64, basis=basis)
     try:
-        u, iters, hist, info, rc = s.pminres(cuda(f, torch.float64), tol, 100)
+        ft = cuda(f, torch.float64)
+        u, iters, hist, info, rc = s.pminres(ft, tol, 100)
+        # the reported residual against the physical-space operator applied to the returned u
+        phys = relnorm(s.apply_sym(u).cpu().numpy(), O.time_reverse(f.reshape(N, -1)).ravel())
     finally:
         s.close()
     u = u.cpu().numpy()
     assert rc == bltt.OK
     assert info["true_relres"] <= tol
+    # the sine basis reports the residual of the transformed system: the two
+    # differ by the FP64 rounding of the sine transforms, amplified by at most
+    # cond(A) (~1e3 here)
+    assert abs(phys - info["true_relres"]) < 1e-11
     # same Krylov iteration: identical residual-estimate history
     k = min(len(hist), len(ores.eta_hist))
     assert np.allclose(hist[:k], ores.eta_hist[:k], rtol=1e-6, atol=1e-13)
@@ -110,14 +121,15 @@ MIXED_CASES = [("frac", 2, 31, 64, 0.01), ("heat", 2, 31, 32, 0.01), ("frac", 1,
                ("frac", 3, 7, 32, 0.01)]
 
 
+@pytest.mark.parametrize("basis", BASES)
 @pytest.mark.parametrize("kind,dim,m,N,alpha", MIXED_CASES)
-def test_mixed_solve_matches_exact(kind, dim, m, N, alpha):
+def test_mixed_solve_matches_exact(kind, dim, m, N, alpha, basis):
     prob = prob_of(kind, dim, m, N, alpha, gamma=0.3)
-    print(f"[mixed solve] {kind} dim={dim} m={m} N={N}", flush=True)
+    print(f"[mixed solve] {kind} dim={dim} m={m} N={N} basis={basis}", flush=True)
     sysm = O.from_problem(prob)
     f = W.rhs_normal(prob, 5)
     ustar = O.exact_solve(sysm, f).ravel()
-    s = bltt.Solver.from_problem(prob, precision=bltt.MIXED)
+    s = bltt.Solver.from_problem(prob, precision=bltt.MIXED, basis=basis)
     try:
         u, iters, hist, info, rc = s.pminres(cuda(f, torch.float64), 1e-8, 200)
     finally:
@@ -129,9 +141,10 @@ def test_mixed_solve_matches_exact(kind, dim, m, N, alpha):
     assert relnorm(u, ustar) < 1e-7
 
 
-def test_zero_rhs_and_noconv():
+@pytest.mark.parametrize("basis", BASES)
+def test_zero_rhs_and_noconv(basis):
     prob = prob_of("frac", 2, 7, 16, 0.01)
-    s = bltt.Solver.from_problem(prob, precision=bltt.FP64)
+    s = bltt.Solver.from_problem(prob, precision=bltt.FP64, basis=basis)
     try:
         u, iters, hist, info, rc = s.pminres(torch.zeros(prob.n, dtype=torch.float64, device="cuda"), 1e-10, 10)
         assert rc == bltt.OK and iters == 0 and float(u.abs().max()) == 0.0
@@ -166,21 +179,22 @@ def test_named_workloads_fp64(name):
     assert err < 1e-9
 
 
-FULL_CASES = [("frac2d_m511_n1024_g03", bltt.MIXED), ("frac2d_m511_n1024_g03", bltt.FP64),
-              ("frac2d_m511_n1024_g07", bltt.MIXED), ("frac3d_m127_n256", bltt.MIXED)]
+FULL_CASES = [("frac2d_m511_n1024_g03", bltt.MIXED, bltt.SINE), ("frac2d_m511_n1024_g03", bltt.FP64, bltt.SINE),
+              ("frac2d_m511_n1024_g07", bltt.MIXED, bltt.SINE), ("frac3d_m127_n256", bltt.MIXED, bltt.SINE),
+              ("frac2d_m511_n1024_g03", bltt.MIXED, bltt.PHYSICAL), ("frac3d_m127_n256", bltt.MIXED, bltt.PHYSICAL)]
 
 
-@pytest.mark.parametrize("name,precision", FULL_CASES)
-def test_full_size_sampled(name, precision):
+@pytest.mark.parametrize("name,precision,basis", FULL_CASES)
+def test_full_size_sampled(name, precision, basis):
     """Full-size workloads (2D: M = 511^2, N = 1024, gamma 0.3 / 0.7; 3D:
     M = 127^3, N = 256, gamma 0.5) at tol 1e-8: sampled sine-mode projections
     of u against the oracle's per-mode exact solution."""
     tol = 1e-8
     prob, seed = W.workload(name)
-    print(f"[full size] {name} precision={precision}", flush=True)
+    print(f"[full size] {name} precision={precision} basis={basis}", flush=True)
     sysm = O.from_problem(prob)
     f = W.rhs_normal(prob, seed)
-    s = bltt.Solver.from_problem(prob, precision=precision)
+    s = bltt.Solver.from_problem(prob, precision=precision, basis=basis)
     try:
         ft = cuda(f, torch.float64)
         u, iters, hist, info, rc = s.pminres(ft, tol, 200)
