@@ -770,7 +770,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
   hipStream_t s = h->stream;
   int rc;
   int64_t np = 0;
-  {
+  if (h->opt.basis != BLTT_BASIS_SINE) {
     ProfScope ps(h, BLTT_K_OTHER, 8.0 * h->n);
     HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
   }
@@ -779,13 +779,20 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
   int status = BLTT_OK;
 
   if (h->opt.basis == BLTT_BASIS_SINE) {
-    // fhat = (I x U) f once; the iteration and the FP64 residuals run on the
-    // mode-decoupled system; u = (I x U) uhat once at the end (U = U^T = U^{-1})
-    if ((rc = space_transform<double>(h, f_dev, h->F64))) return rc;
+    // fhat = (I x U) f once, stored mode-major (each mode's time line
+    // contiguous); the iteration and the FP64 residuals run on the
+    // mode-decoupled system in that layout; u = (I x U) uhat once at the end
+    // (U = U^T = U^{-1}).  u_dev serves as time-major scratch on the way in.
+    if ((rc = space_transform<double>(h, f_dev, u_dev))) return rc;
+    {
+      ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
+      HIPCHK(launch_transpose<double>(u_dev, h->F64, h->N, h->M, false, s));
+      HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
+    }
     double* b64 = h->opt.precision == BLTT_FP64 ? h->w64.V[0] : h->R64;
     {
       ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
-      HIPCHK(launch_rhs<double>(h->F64, b64, h->N, h->M, 1.0, h->partials, &np, s));
+      HIPCHK(launch_rhs_mm(h->F64, b64, h->N, h->M, h->partials, &np, s));
     }
     if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
     if ((rc = read_state(h))) return rc;
@@ -851,7 +858,11 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         if (!std::isfinite(rnorm)) return BLTT_ENAN;
       }
     }
-    if ((rc = space_transform<double>(h, u_dev, u_dev))) return rc;
+    {
+      ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
+      HIPCHK(launch_transpose<double>(u_dev, h->F64, h->M, h->N, false, s));
+    }
+    if ((rc = space_transform<double>(h, h->F64, u_dev))) return rc;
   } else if (h->opt.precision == BLTT_FP64) {
     Workspace<double>& ws = h->w64;
     // b = Y f into V[0]

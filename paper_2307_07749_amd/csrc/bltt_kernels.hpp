@@ -196,27 +196,37 @@ struct MatvecTables {
 enum { MV_DOT = 0, MV_RESID = 1 };
 enum { TERM_NONE = 0, TERM_STENCIL = 1, TERM_SPEC = 2 };
 
-template <typename T, int L, int MODE, int TERM, class Ctx>
+// Layout (MM): false = time-major vectors (element (i, n) at n*M + i, the ABI
+// layout), lines interleaved across the workgroup so that a row of 2*NL
+// consecutive points is one coalesced access; true = mode-major (element at
+// i*N + n, the sine-basis working layout), each line contiguous in memory and
+// owned by consecutive threads, and for N <= 512 by one wavefront.
+template <typename T, int L, int MODE, int TERM, bool MM, class Ctx>
 BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict__ z,
                              T* __restrict__ out, const T* __restrict__ fin, int64_t M,
                              const MatvecTables<T>& tb, double* __restrict__ partials) {
+  static_assert(!(MM && TERM == TERM_STENCIL), "the stencil needs the time-major layout");
   constexpr int TPB = tpb_fft<T, FK_MV>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L / 2, VH = V / 2;  // slots t < VH hold times g + t*s0 < N
-  using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
-  const int tid = ctx.tid, c = tid % NL, g = tid / NL;
+  using F = LineFft<T, L, NL, !MM, LAST_DEFAULT>;
+  const int tid = ctx.tid, c = MM ? tid / G : tid % NL, g = MM ? tid % G : tid / NL;
   const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const T* za = z + ia;
   const T* zb = z + ib;
 
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
+  // time stride and line bases (clamped for loads, exact for stores)
+  const int64_t ts = MM ? 1 : M;
+  const int64_t la = MM ? iac * N : iac, lb = MM ? ibc * N : ibc;
+  const int64_t sa = MM ? ia * N : ia, sb = MM ? ib * N : ib;
   const T wa = va ? T(1) : T(0), wb = vb ? T(1) : T(0);
   cx<T> v[V], zin[VH];
 #pragma unroll
   for (int t = 0; t < VH; ++t) {
-    const int64_t off = (int64_t)(g + t * s0) * M;
-    zin[t] = mkc<T>(z[iac + off] * wa, z[ibc + off] * wb);
+    const int64_t off = (int64_t)(g + t * s0) * ts;
+    zin[t] = mkc<T>(z[la + off] * wa, z[lb + off] * wb);
     v[t] = zin[t];
   }
 #pragma unroll
@@ -229,10 +239,10 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   F::inverse(ctx, v, lds, c, g, tb.tw);
 
   // z at the mirrored time N-1-n, for <Y A z, z> (and z[n-k] for TERM_SPEC)
-  ctx.sync();
+  F::xsync(ctx);
 #pragma unroll
   for (int t = 0; t < VH; ++t) lds[F::idx(c, g + t * s0)] = zin[t];
-  ctx.sync();
+  F::xsync(ctx);
 
   const Stencil sta = make_stencil(va ? ia : 0, tb.grid);
   const Stencil stb = make_stencil(vb ? ib : 0, tb.grid);
@@ -241,8 +251,8 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
     mua = tb.mu[iac];
     mub = tb.mu[ibc];
   }
-  T* oa = out + ia;
-  T* ob = out + ib;
+  T* oa = out + sa;
+  T* ob = out + sb;
   double part = 0.0;
 #pragma unroll
   for (int t = 0; t < VH; ++t) {
@@ -269,7 +279,7 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
       ya += mua * sa;
       yb += mub * sb;
     }
-    const int64_t offr = (int64_t)(N - 1 - n) * M;
+    const int64_t offr = (int64_t)(N - 1 - n) * ts;
     if (MODE == MV_DOT) {
       const cx<T> zr = lds[F::idx(c, N - 1 - n)];
       if (va) {
@@ -281,14 +291,14 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
         part += (double)yb * (double)zr.im;
       }
     } else {
-      const int64_t off = (int64_t)n * M;
+      const int64_t off = (int64_t)n * ts;
       if (va) {
-        const T r = fin[ia + off] - ya;
+        const T r = fin[sa + off] - ya;
         oa[offr] = r;
         part += (double)r * (double)r;
       }
       if (vb) {
-        const T r = fin[ib + off] - yb;
+        const T r = fin[sb + off] - yb;
         ob[offr] = r;
         part += (double)r * (double)r;
       }
@@ -352,6 +362,41 @@ BLTT_HD void matvec_short_body(Ctx& ctx, double* red, const T* __restrict__ z, T
   }
   const double s = block_sum<TPB_EW>(ctx, red, part);
   if (tid == 0) partials[(int64_t)ctx.bid_y * ctx.nbx + ctx.bid] = s;
+}
+
+// Direct form in the mode-major sine-basis layout (element (i, n) at i*N + n):
+// one thread per output element, consecutive threads along time, so every
+// access is coalesced and the few neighbours k <= 8 back are cache hits.
+// out[i*N + N-1-n] = (p * z_i)[n] + mu_i (q * z_i)[n] (MV_DOT, with the partial
+// sums of <out, z>) or Y (fin - ...) (MV_RESID, partial sums of ||out||^2).
+template <typename T, int MODE, class Ctx>
+BLTT_HD void matvec_short_mm_body(Ctx& ctx, double* red, const T* __restrict__ z, T* __restrict__ out,
+                                  const T* __restrict__ fin, int64_t M, const ShortTables<T>& tb, int log2N,
+                                  double* __restrict__ partials) {
+  const int N = tb.N;
+  const int64_t n_total = (int64_t)N * M;
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  double part = 0.0;
+  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) {
+    const int64_t i = e >> log2N;
+    const int n = (int)(e & (N - 1));
+    const T* zl = z + (i << log2N);
+    T y = T(0), sq = T(0);
+    for (int k = 0; k < tb.ptaps && k <= n; ++k) y += tb.p[k] * zl[n - k];
+    for (int k = 0; k < tb.qtaps && k <= n; ++k) sq += tb.q[k] * zl[n - k];
+    y += tb.mu[i] * sq;
+    const int64_t er = (i << log2N) + (N - 1 - n);
+    if (MODE == MV_DOT) {
+      out[er] = y;
+      part += (double)y * (double)zl[N - 1 - n];
+    } else {
+      const T r = fin[e] - y;
+      out[er] = r;
+      part += (double)r * (double)r;
+    }
+  }
+  const double sum = block_sum<TPB_EW>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +857,7 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 // in FP64 before rounding).  FP32 keeps vhat in registers for the dot product;
 // FP64 reads it back from Vout (its own stores) or from Q.
 // ---------------------------------------------------------------------------
-template <typename T, int L, typename TQ, bool FULL, class Ctx>
+template <typename T, int L, typename TQ, bool FULL, bool MM, class Ctx>
 BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restrict__ Q,
                            const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                            T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
@@ -820,12 +865,16 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
   constexpr int TPB = tpb_fft<T, FK_TIME>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr bool KEEP = sizeof(T) == 4;
-  using F = LineFft<T, L, NL, true, LAST_PAIRED>;
+  using F = LineFft<T, L, NL, !MM, LAST_PAIRED>;
   const T invN = T(1) / T(L);
-  const int tid = ctx.tid, c = tid % NL, g = tid / NL;
+  const int tid = ctx.tid, c = MM ? tid / G : tid % NL, g = MM ? tid % G : tid / NL;
   const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
+  // element (i, n): time-major n*M + i, or mode-major i*N + n (N = L)
+  const int64_t ts = MM ? 1 : M;
+  const int64_t la = MM ? iac * L : iac, lb = MM ? ibc * L : ibc;
+  const int64_t sa = MM ? ia * L : ia, sb = MM ? ib * L : ib;
   const T mua = tb.mu[iac], mub = tb.mu[ibc];
   const double cq = coef[0];
   T cv = T(0), cvp = T(0);
@@ -837,27 +886,27 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
   cx<T> keep[KEEP ? V : 1], v[V];
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int64_t off = (int64_t)(g + t * s0) * M;
+    const int64_t off = (int64_t)(g + t * s0) * ts;
     T a, b;
     if constexpr (sizeof(TQ) > sizeof(T)) {
-      a = T((double)Q[iac + off] * cq);
-      b = T((double)Q[ibc + off] * cq);
+      a = T((double)Q[la + off] * cq);
+      b = T((double)Q[lb + off] * cq);
     } else {
-      a = T(cq) * Q[iac + off];
-      b = T(cq) * Q[ibc + off];
+      a = T(cq) * Q[la + off];
+      b = T(cq) * Q[lb + off];
     }
     if (FULL) {
-      a += cv * V1[iac + off] + cvp * V2[iac + off];
-      b += cv * V1[ibc + off] + cvp * V2[ibc + off];
+      a += cv * V1[la + off] + cvp * V2[la + off];
+      b += cv * V1[lb + off] + cvp * V2[lb + off];
     }
     v[t] = mkc<T>(va ? a : T(0), vb ? b : T(0));
   }
   if (Vout) {
 #pragma unroll
     for (int t = 0; t < V; ++t) {
-      const int64_t off = (int64_t)(g + t * s0) * M;
-      if (va) Vout[ia + off] = v[t].re;
-      if (vb) Vout[ib + off] = v[t].im;
+      const int64_t off = (int64_t)(g + t * s0) * ts;
+      if (va) Vout[sa + off] = v[t].re;
+      if (vb) Vout[sb + off] = v[t].im;
     }
   }
 #pragma unroll
@@ -877,19 +926,19 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int n = g + t * s0;
-    const int64_t off = (int64_t)n * M;
+    const int64_t off = (int64_t)n * ts;
     const cx<T> z = v[t] * alpha_pow_n(tb, tb.dinv, T(-1), n);
-    if (va) Zout[ia + off] = z.re;
-    if (vb) Zout[ib + off] = z.im;
+    if (va) Zout[sa + off] = z.re;
+    if (vb) Zout[sb + off] = z.im;
     cx<T> in;
     if constexpr (KEEP) {
       in = keep[t];
     } else if (Vout) {
       // a lane past M reads another workgroup's element: select, never multiply
-      const T ra = Vout[iac + off], rb = Vout[ibc + off];
+      const T ra = Vout[la + off], rb = Vout[lb + off];
       in = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
     } else {
-      const T ra = T(cq) * T(Q[iac + off]), rb = T(cq) * T(Q[ibc + off]);
+      const T ra = T(cq) * T(Q[la + off]), rb = T(cq) * T(Q[lb + off]);
       in = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
     }
     part += (double)in.re * (double)z.re + (double)in.im * (double)z.im;
@@ -938,6 +987,48 @@ BLTT_HD void rhs_body(Ctx& ctx, double* red, const double* __restrict__ f, TO* _
   }
   const double s = block_sum<TPB_EW>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = s;
+}
+
+// b = Y f in the mode-major layout (each time line reversed), partial sums of ||b||^2
+template <class Ctx>
+BLTT_HD void rhs_mm_body(Ctx& ctx, double* red, const double* __restrict__ f, double* __restrict__ b, int log2N,
+                         int64_t n_total, double* __restrict__ partials) {
+  const int64_t N = (int64_t)1 << log2N;
+  double part = 0.0;
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) {
+    const int64_t i = e >> log2N, n = e & (N - 1);
+    const double val = f[(i << log2N) + (N - 1 - n)];
+    b[e] = val;
+    part += val * val;
+  }
+  const double s = block_sum<TPB_EW>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = s;
+}
+
+// out = in^T for an R x C row-major matrix (out is C x R), through a 64 x 64
+// LDS tile (padded rows); REV also reverses the order of the R index in out.
+// Moves vectors between the time-major ABI layout (R = N, C = M) and the
+// mode-major sine-basis layout (R = M, C = N for the way back).
+constexpr int TR_TILE = 64;
+template <typename T, bool REV, class Ctx>
+BLTT_HD void transpose_body(Ctx& ctx, T* tile, const T* __restrict__ in, T* __restrict__ out, int64_t R,
+                            int64_t C) {
+  constexpr int P = TR_TILE + 1, ROWS = TPB_EW / TR_TILE;
+  const int64_t tiles_c = (C + TR_TILE - 1) / TR_TILE;
+  const int64_t c0 = ((int64_t)ctx.bid % tiles_c) * TR_TILE, r0 = ((int64_t)ctx.bid / tiles_c) * TR_TILE;
+  const int tx = ctx.tid % TR_TILE, ty = ctx.tid / TR_TILE;
+#pragma unroll
+  for (int k = 0; k < TR_TILE; k += ROWS) {
+    const int64_t r = r0 + ty + k, c = c0 + tx;
+    if (r < R && c < C) tile[(ty + k) * P + tx] = in[r * C + c];
+  }
+  ctx.sync();
+#pragma unroll
+  for (int k = 0; k < TR_TILE; k += ROWS) {
+    const int64_t c = c0 + ty + k, r = r0 + tx;
+    if (r < R && c < C) out[c * R + (REV ? R - 1 - r : r)] = tile[tx * P + ty + k];
+  }
 }
 
 // W_new = cz Z + ca Wa + cb Wb  (stored over Wa);  X += cx W_new

@@ -17,7 +17,7 @@
 //
 // Everything here is __host__ __device__ so the same code can be run by the
 // CPU workgroup emulator used in the tests; `Ctx::sync()` is the workgroup
-// barrier.
+// barrier and `Ctx::wsync()` the wavefront-scope one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -151,6 +151,22 @@ BLTT_HD void dft(cx<T>* a) {
   else static_assert(R == 2, "unsupported radix");
 }
 
+// Twiddles w^u, 0 < u < R, of w = tw[e]: the powers w^(2^k) come from the
+// table and the others are products of two or three of them (at most three
+// roundings), so a radix-16 butterfly issues 4 table loads instead of 15.
+template <int R, typename T>
+BLTT_HD void twiddle_powers(cx<T>* pw, const cx<T>* tw, int e) {
+#pragma unroll
+  for (int u = 1; u < R; u <<= 1) pw[u] = tw[u * e];
+#pragma unroll
+  for (int u = 3; u < R; ++u) {
+    if ((u & (u - 1)) == 0) continue;
+    int hi = 1;
+    while (hi * 2 <= u) hi *= 2;
+    pw[u] = pw[hi] * pw[u - hi];
+  }
+}
+
 // How the last stage's butterflies are dealt to the threads of a line.
 enum LastMode {
   LAST_DEFAULT = 0,  // butterfly g + G*w (LDS friendly)
@@ -167,6 +183,17 @@ struct LineFft {
   static constexpr int K = L / RL;            // last-stage butterflies per line
   static constexpr int LP = L + (L >> 3);     // padded line length
   static constexpr int LDS_ELEMS = NL * LP;
+  // Lines stored one after another (not interleaved) and at most one
+  // wavefront per line: every exchange stays inside one wavefront, whose LDS
+  // accesses execute in order, so a wavefront-scope barrier replaces the
+  // workgroup barrier.
+  static constexpr bool WAVE_LOCAL = !INTERLEAVED && G <= 64;
+
+  template <class Ctx>
+  BLTT_HD static void xsync(Ctx& ctx) {
+    if constexpr (WAVE_LOCAL) ctx.wsync();
+    else ctx.sync();
+  }
   static_assert(S == 1 || fft_r(L, 0) == V, "first stage must use all registers");
   static_assert(LAST != LAST_PAIRED || S == 1 || V >= 2 * RL, "pairing needs two butterflies");
 
@@ -248,20 +275,21 @@ struct LineFft {
     for (int w = 0; w < NB; ++w) {
       dft<r, -1>(v + w * r);
       if constexpr (sg > 1) {
-        const int j = beta<s>(g, w) % sg;
+        cx<T> pw[r];
+        twiddle_powers<r>(pw, tw, (beta<s>(g, w) % sg) * (L / B));
 #pragma unroll
-        for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * tw[j * u * (L / B)];
+        for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * pw[u];
       }
     }
     if constexpr (s + 1 < S) {
-      ctx.sync();
+      xsync(ctx);
 #pragma unroll
       for (int w = 0; w < NB; ++w) {
         const int b = beta<s>(g, w);
 #pragma unroll
         for (int u = 0; u < r; ++u) lds[idx(c, pos<s>(b, u))] = v[w * r + u];
       }
-      ctx.sync();
+      xsync(ctx);
       fwd_stage<s + 1>(ctx, v, lds, c, g, tw);
     }
   }
@@ -286,21 +314,22 @@ struct LineFft {
 #pragma unroll
     for (int w = 0; w < NB; ++w) {
       if constexpr (sg > 1) {
-        const int j = beta<s>(g, w) % sg;
+        cx<T> pw[r];
+        twiddle_powers<r>(pw, tw, (beta<s>(g, w) % sg) * (L / B));
 #pragma unroll
-        for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * conjg(tw[j * u * (L / B)]);
+        for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * conjg(pw[u]);
       }
       dft<r, +1>(v + w * r);
     }
     if constexpr (s > 0) {
-      ctx.sync();
+      xsync(ctx);
 #pragma unroll
       for (int w = 0; w < NB; ++w) {
         const int b = beta<s>(g, w);
 #pragma unroll
         for (int t = 0; t < r; ++t) lds[idx(c, pos<s>(b, t))] = v[w * r + t];
       }
-      ctx.sync();
+      xsync(ctx);
       inv_stage<s - 1>(ctx, v, lds, c, g, tw);
     }
   }

@@ -10,10 +10,12 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
                                                              MatvecTables<T> tb, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NL = tpb_fft<T, FK_MV>() / (L / fft_V(L));
-  using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
+  using F = LineFft<T, L, NL, TERM != TERM_SPEC, LAST_DEFAULT>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
-  matvec_fft_body<T, L, MODE, TERM>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb, partials);
+  // the sine-coordinate forms work on the mode-major layout
+  matvec_fft_body<T, L, MODE, TERM, TERM == TERM_SPEC>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb,
+                                                       partials);
 }
 
 template <typename T, int MODE>
@@ -66,9 +68,32 @@ hipError_t launch_matvec_fft(int L, int mode, int term, const T* z, T* out, cons
   return hipErrorInvalidValue;
 }
 
+template <typename T, int MODE>
+__global__ __launch_bounds__(TPB_EW) void k_matvec_short_mm(const T* __restrict__ z, T* __restrict__ out,
+                                                            const T* __restrict__ fin, int64_t M, ShortTables<T> tb,
+                                                            int log2N, double* __restrict__ partials) {
+  __shared__ double red[TPB_EW];
+  DevCtx ctx = make_ctx();
+  matvec_short_mm_body<T, MODE>(ctx, red, z, out, fin, M, tb, log2N, partials);
+}
+
 template <typename T>
 hipError_t launch_matvec_short(int mode, const T* z, T* out, const T* fin, int64_t M, const ShortTables<T>& tb,
                                double* partials, int64_t* nparts, hipStream_t s) {
+  if (tb.term == TERM_SPEC) {
+    int log2N = 0;
+    while ((1 << log2N) < tb.N) ++log2N;
+    if ((1 << log2N) != tb.N) return hipErrorInvalidValue;
+    const int64_t gx = ew_blocks((int64_t)tb.N * M);
+    if (nparts) *nparts = gx;
+    if (mode == MV_DOT)
+      hipLaunchKernelGGL((k_matvec_short_mm<T, MV_DOT>), dim3((unsigned)gx), dim3(TPB_EW), 0, s, z, out, fin, M, tb,
+                         log2N, partials);
+    else
+      hipLaunchKernelGGL((k_matvec_short_mm<T, MV_RESID>), dim3((unsigned)gx), dim3(TPB_EW), 0, s, z, out, fin, M,
+                         tb, log2N, partials);
+    return hipGetLastError();
+  }
   const int64_t gx = (M + TPB_EW - 1) / TPB_EW;
   const int half = (tb.N + 1) / 2;
   const int64_t gy = (half + tb.chunk - 1) / tb.chunk;

@@ -12,6 +12,21 @@ __global__ __launch_bounds__(TPB_EW) void k_rhs(const double* __restrict__ f, TO
   rhs_body<TO>(ctx, red, f, b, N, M, scale, partials);
 }
 
+__global__ __launch_bounds__(TPB_EW) void k_rhs_mm(const double* __restrict__ f, double* __restrict__ b, int log2N,
+                                                   int64_t n, double* __restrict__ partials) {
+  __shared__ double red[TPB_EW];
+  DevCtx ctx = make_ctx();
+  rhs_mm_body(ctx, red, f, b, log2N, n, partials);
+}
+
+template <typename T, bool REV>
+__global__ __launch_bounds__(TPB_EW) void k_transpose(const T* __restrict__ in, T* __restrict__ out, int64_t R,
+                                                      int64_t C) {
+  __shared__ T tile[TR_TILE * (TR_TILE + 1)];
+  DevCtx ctx = make_ctx();
+  transpose_body<T, REV>(ctx, tile, in, out, R, C);
+}
+
 template <typename T, typename TX>
 __global__ __launch_bounds__(TPB_EW) void k_wx(const T* __restrict__ Z, T* __restrict__ Wa, const T* __restrict__ Wb,
                                                TX* __restrict__ X, int64_t n, const double* __restrict__ coef) {
@@ -62,6 +77,29 @@ __global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __res
   DevCtx ctx = make_ctx();
   scalar_body(ctx, red, phase, st, partials, np, aux, naux, hist);
 }
+
+hipError_t launch_rhs_mm(const double* f, double* b, int64_t N, int64_t M, double* partials, int64_t* nparts,
+                         hipStream_t s) {
+  int log2N = 0;
+  while (((int64_t)1 << log2N) < N) ++log2N;
+  if (((int64_t)1 << log2N) != N) return hipErrorInvalidValue;
+  const int64_t n = N * M, blocks = ew_blocks(n);
+  if (nparts) *nparts = blocks;
+  hipLaunchKernelGGL(k_rhs_mm, dim3((unsigned)blocks), dim3(TPB_EW), 0, s, f, b, log2N, n, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev, hipStream_t s) {
+  const int64_t nb = ((C + TR_TILE - 1) / TR_TILE) * ((R + TR_TILE - 1) / TR_TILE);
+  if (nb < 1 || nb > 2147483647LL) return hipErrorInvalidValue;
+  if (rev)
+    hipLaunchKernelGGL((k_transpose<T, true>), dim3((unsigned)nb), dim3(TPB_EW), 0, s, in, out, R, C);
+  else
+    hipLaunchKernelGGL((k_transpose<T, false>), dim3((unsigned)nb), dim3(TPB_EW), 0, s, in, out, R, C);
+  return hipGetLastError();
+}
+template hipError_t launch_transpose<double>(const double*, double*, int64_t, int64_t, bool, hipStream_t);
 
 template <typename T>
 hipError_t launch_resid_stencil(T* r, const VupdStencil<T>& st, int64_t nlines, double* partials, int64_t* nparts,

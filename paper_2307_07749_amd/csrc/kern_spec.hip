@@ -1,5 +1,5 @@
 // Lanczos update fused with the time pass of the preconditioner, for MINRES in
-// sine coordinates: one workgroup per 2*NL sine modes.
+// sine coordinates (mode-major vectors): one workgroup per 2*NL sine modes.
 #include "launchers.hpp"
 
 namespace bltt {
@@ -11,11 +11,11 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
     double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NL = tpb_fft<T, FK_TIME>() / (L / fft_V(L));
-  using F = LineFft<T, L, NL, true, LAST_PAIRED>;
+  using F = LineFft<T, L, NL, false, LAST_PAIRED>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
-  time_upd_body<T, L, TQ, FULL>(ctx, reinterpret_cast<cx<T>*>(smem), red, Q, V1, V2, Vout, Zout, M, tb, coef,
-                                partials);
+  time_upd_body<T, L, TQ, FULL, true>(ctx, reinterpret_cast<cx<T>*>(smem), red, Q, V1, V2, Vout, Zout, M, tb, coef,
+                                      partials);
 }
 
 template <typename T, typename TQ, int L>

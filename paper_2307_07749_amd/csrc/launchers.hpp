@@ -12,6 +12,13 @@ namespace bltt {
 struct DevCtx {
   int tid, bid, bid_y, nbx;
   __device__ void sync() { __syncthreads(); }
+  // wavefront-scope barrier: orders this wavefront's LDS accesses (the LDS
+  // executes one wavefront's instructions in order)
+  __device__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 };
 __device__ inline DevCtx make_ctx() {
   DevCtx c;
@@ -59,6 +66,12 @@ hipError_t configure_kernels();
 template <typename T>
 hipError_t launch_resid_stencil(T* r, const VupdStencil<T>& st, int64_t nlines, double* partials, int64_t* nparts,
                                 hipStream_t s);
+// b = Y f on mode-major vectors (N a power of two) and partial sums of ||b||^2
+hipError_t launch_rhs_mm(const double* f, double* b, int64_t N, int64_t M, double* partials, int64_t* nparts,
+                         hipStream_t s);
+// out (C x R) = in^T (in: R x C, row-major); rev reverses the R index
+template <typename T>
+hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev, hipStream_t s);
 template <typename TO>
 hipError_t launch_rhs(const double* f, TO* b, int64_t N, int64_t M, double scale, double* partials,
                       int64_t* nparts, hipStream_t s);

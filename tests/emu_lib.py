@@ -74,6 +74,9 @@ def lib():
         L.emu_resid_spec_f64.argtypes = args + [P, P, P, ctypes.c_int]
         L.emu_resid_spec_f64.restype = ctypes.c_double
         L.emu_state_size.restype = ctypes.c_int64
+        L.emu_transpose_f64.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+        L.emu_rhs_mm.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
+        L.emu_rhs_mm.restype = ctypes.c_double
         L.emu_state_offsets.argtypes = [P]
         L.emu_scalar.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P]
         L.emu_resid_f64.argtypes = args + [P, P, P]
@@ -298,3 +301,20 @@ def wx(Z, Wa, Wb, X, coef_ptr):
     """Wa <- c0 Z + c1 Wa + c2 Wb; X += c3 Wa (in place on numpy arrays)."""
     tag = "f64" if Z.dtype == np.float64 else "f32"
     getattr(lib(), f"emu_wx_{tag}")(Z.ctypes.data, Wa.ctypes.data, Wb.ctypes.data, X.ctypes.data, Z.size, coef_ptr)
+
+
+def transpose(x, R, C, rev=False):
+    """out (C x R) = x (R x C)^T through the library's tiled transpose."""
+    gi = Guarded(x, np.float64)
+    go = Guarded(np.zeros(x.size), np.float64)
+    lib().emu_transpose_f64(gi.ptr, go.ptr, R, C, int(rev))
+    _check(gi, go)
+    return go.data.copy()
+
+
+def rhs_mm(f, N, M):
+    gf = Guarded(f, np.float64)
+    gb = Guarded(np.zeros(f.size), np.float64)
+    s = lib().emu_rhs_mm(gf.ptr, gb.ptr, N, M)
+    _check(gf, gb)
+    return gb.data.copy(), s

@@ -49,6 +49,9 @@ struct HostCtx {
   int tid, bid, bid_y, nbx;
   Barrier* bar;
   void sync() { bar->wait(); }
+  // every thread of a workgroup runs the same sequence of barriers, so the
+  // wavefront-scope barrier can be emulated by the workgroup one
+  void wsync() { bar->wait(); }
 };
 
 // LDS with guard words: out-of-range accesses are detected at the end.
@@ -194,11 +197,11 @@ struct MvRun {
                [&](HostCtx& c, unsigned char* lds) {
         double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
         if (stencil)
-          matvec_fft_body<T, L, MV_DOT, TERM_STENCIL>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb,
-                                                      partials);
+          matvec_fft_body<T, L, MV_DOT, TERM_STENCIL, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr,
+                                                             M, tb, partials);
         else
-          matvec_fft_body<T, L, MV_DOT, TERM_NONE>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M, tb,
-                                                   partials);
+          matvec_fft_body<T, L, MV_DOT, TERM_NONE, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M,
+                                                          tb, partials);
       });
     }
   };
@@ -398,8 +401,8 @@ struct MvResRun {
       run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
                [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
-                 matvec_fft_body<T, L, MV_RESID, TERM_NONE>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M,
-                                                            tb, partials);
+                 matvec_fft_body<T, L, MV_RESID, TERM_NONE, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin,
+                                                                   M, tb, partials);
                });
     }
   };
@@ -465,16 +468,16 @@ struct UpdRun {
     static void run(const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M, const TimeTables<T>& tb,
                     const double* coef, double* partials, bool full) {
       constexpr int NL = lines_per_block<T, FK_TIME>(L);
-      using Ft = LineFft<T, L, NL, true, LAST_PAIRED>;
+      using Ft = LineFft<T, L, NL, false, LAST_PAIRED>;
       run_grid(tpb_fft<T, FK_TIME>(), (int)fft_blocks<T, FK_TIME>(L, M), 1, fft_lds_bytes<T, FK_TIME>(L),
                [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Ft::LDS_ELEMS);
                  if (full)
-                   time_upd_body<T, L, TQ, true>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout, M, tb,
-                                                 coef, partials);
+                   time_upd_body<T, L, TQ, true, true>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout, M,
+                                                       tb, coef, partials);
                  else
-                   time_upd_body<T, L, TQ, false>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout, M,
-                                                  tb, coef, partials);
+                   time_upd_body<T, L, TQ, false, true>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout,
+                                                        M, tb, coef, partials);
                });
     }
   };
@@ -499,12 +502,12 @@ struct MvSpecRun {
   struct R {
     static void run(const T* z, T* out, const T* fin, int64_t M, const MatvecTables<T>& tb, double* partials) {
       constexpr int NL = lines_per_block<T, FK_MV>(L);
-      using Fm = LineFft<T, L, NL, true, LAST_DEFAULT>;
+      using Fm = LineFft<T, L, NL, false, LAST_DEFAULT>;
       run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
                [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
-                 matvec_fft_body<T, L, MODE, TERM_SPEC>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M, tb,
-                                                        partials);
+                 matvec_fft_body<T, L, MODE, TERM_SPEC, true>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M,
+                                                              tb, partials);
                });
     }
   };
@@ -530,11 +533,13 @@ double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force
     tb.chunk = 8;
     tb.term = TERM_SPEC;
     tb.mu = ht.mu.data();
-    const int gx = (int)((P.M + TPB_EW - 1) / TPB_EW);
-    const int gy = (int)(((P.N + 1) / 2 + tb.chunk - 1) / tb.chunk);
-    std::vector<double> partials((size_t)gx * gy);
-    run_grid(TPB_EW, gx, gy, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
-      matvec_short_body<T, MODE>(c, reinterpret_cast<double*>(lds), z, out, fin, P.M, tb, partials.data());
+    int log2N = 0;
+    while ((1 << log2N) < P.N) ++log2N;
+    // a grid smaller than the vector exercises the grid-stride loop
+    const int gx = (int)std::min<int64_t>((P.N * P.M + TPB_EW - 1) / TPB_EW, 7);
+    std::vector<double> partials((size_t)gx);
+    run_grid(TPB_EW, gx, 1, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
+      matvec_short_mm_body<T, MODE>(c, reinterpret_cast<double*>(lds), z, out, fin, P.M, tb, log2N, partials.data());
     });
     for (double v : partials) dot += v;
   } else {
@@ -565,9 +570,37 @@ void apply_wx(const T* Z, T* Wa, const T* Wb, T* X, int64_t n, const double* coe
   run_grid(TPB_EW, nb, 1, 0, [&](HostCtx& c, unsigned char*) { wx_body<T, T>(c, Z, Wa, Wb, X, n, coef); });
 }
 
+void apply_transpose(const double* in, double* out, int64_t R, int64_t C, bool rev) {
+  const int64_t nb = ((C + TR_TILE - 1) / TR_TILE) * ((R + TR_TILE - 1) / TR_TILE);
+  run_grid(TPB_EW, (int)nb, 1, sizeof(double) * TR_TILE * (TR_TILE + 1), [&](HostCtx& c, unsigned char* lds) {
+    if (rev)
+      transpose_body<double, true>(c, reinterpret_cast<double*>(lds), in, out, R, C);
+    else
+      transpose_body<double, false>(c, reinterpret_cast<double*>(lds), in, out, R, C);
+  });
+}
+
+double apply_rhs_mm(const double* f, double* b, int64_t N, int64_t M) {
+  int log2N = 0;
+  while (((int64_t)1 << log2N) < N) ++log2N;
+  const int gx = (int)std::min<int64_t>((N * M + TPB_EW - 1) / TPB_EW, 5);
+  std::vector<double> partials((size_t)gx);
+  run_grid(TPB_EW, gx, 1, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
+    rhs_mm_body(c, reinterpret_cast<double*>(lds), f, b, log2N, N * M, partials.data());
+  });
+  double s = 0.0;
+  for (double v : partials) s += v;
+  return s;
+}
+
 }  // namespace
 
 extern "C" {
+
+void emu_transpose_f64(const double* in, double* out, int64_t R, int64_t C, int rev) {
+  apply_transpose(in, out, R, C, rev != 0);
+}
+double emu_rhs_mm(const double* f, double* b, int64_t N, int64_t M) { return apply_rhs_mm(f, b, N, M); }
 
 int64_t emu_state_size(void) { return (int64_t)sizeof(SolverState); }
 // byte offsets: coef_v, coef_w, eta, eta0, status, rinv, rscale, iter

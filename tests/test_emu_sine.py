@@ -3,7 +3,8 @@
 In sine coordinates (I_N x U) every block p_k I + q_k L_h is diagonal in
 space (Remark 1), so the operators the sine-basis MINRES applies are the
 oracle's operators conjugated by the orthonormal, symmetric transform U:
-  K_s = U (Y A) U,  P_s^{-1} = U P^{-1} U.
+  K_s = U (Y A) U,  P_s^{-1} = U P^{-1} U,
+on vectors stored mode-major (each mode's time line contiguous).
 The last test drives the whole sine-basis MINRES from these emulated kernels
 (and the emulated scalar and update kernels) and checks it against the
 oracle's physical-space PMINRES: same residual-estimate history, same
@@ -33,12 +34,22 @@ def U(prob, x):
     return O.space_transform(np.asarray(x).reshape(prob.N, -1), prob.m).ravel()
 
 
+# the sine-basis kernels keep vectors mode-major: element (i, n) at i*N + n
+def mm(prob, x):
+    return np.asarray(x).reshape(prob.N, prob.M).T.ravel()
+
+
+def tm(prob, x):
+    return np.asarray(x).reshape(prob.M, prob.N).T.ravel()
+
+
 def ref_prec_sine(prob, sysm, P, x):
-    return U(prob, O.precond_apply(P, U(prob, x).reshape(prob.N, -1)))
+    """U P^{-1} U on a mode-major vector, result mode-major."""
+    return mm(prob, U(prob, O.precond_apply(P, U(prob, tm(prob, x)).reshape(prob.N, -1))))
 
 
 def ref_sym_sine(prob, sysm, z):
-    return U(prob, O.sym_apply(sysm, U(prob, z).reshape(prob.N, -1)))
+    return mm(prob, U(prob, O.sym_apply(sysm, U(prob, tm(prob, z)).reshape(prob.N, -1))))
 
 
 UPD_CASES = [("frac", 1, 31, 32, 0.01), ("heat", 2, 7, 16, 0.01), ("cn", 2, 7, 8, 0.2), ("frac", 3, 3, 8, 0.05),
@@ -112,7 +123,8 @@ def test_resid_spec(kind, dim, m, N, force_fft):
     rng = np.random.default_rng(41)
     u, f = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
     r, s = E.resid_spec(prob, u, f, force_fft)
-    ref = O.time_reverse((f - U(prob, O.bltt_apply(sysm, U(prob, u).reshape(N, -1)))).reshape(N, -1)).ravel()
+    ut, ft = tm(prob, u), tm(prob, f)
+    ref = mm(prob, O.time_reverse((ft - U(prob, O.bltt_apply(sysm, U(prob, ut).reshape(N, -1)))).reshape(N, -1)))
     assert rel(r, ref) < 1e-12
     assert abs(s - np.dot(ref, ref)) < 1e-10 * np.dot(ref, ref)
 
@@ -121,7 +133,7 @@ def sine_minres(prob, f, tol_eta, maxit, dtype=np.float64):
     """The sine-basis MINRES exactly as the library sequences its kernels."""
     n = prob.n
     fs = U(prob, f)
-    b = O.time_reverse(fs.reshape(prob.N, -1)).ravel()
+    b = mm(prob, O.time_reverse(fs.reshape(prob.N, -1)))
     st = E.State()
     hist = np.zeros(maxit + 2)
     Vc = b.astype(dtype)
@@ -144,7 +156,7 @@ def sine_minres(prob, f, tol_eta, maxit, dtype=np.float64):
         assert st.status >= 0
         if abs(st.eta) / st.eta0 <= tol_eta or st.status == 1:
             break
-    return U(prob, X.astype(np.float64)), j, hist[:j + 1]
+    return U(prob, tm(prob, X.astype(np.float64))), j, hist[:j + 1]
 
 
 @pytest.mark.parametrize("kind,dim,m,N,alpha", [("frac", 1, 15, 32, 0.01), ("heat", 2, 7, 16, 0.01),
@@ -159,3 +171,22 @@ def test_sine_minres_matches_oracle(kind, dim, m, N, alpha):
     assert np.allclose(hist[:k], ores.eta_hist[:k], rtol=1e-7, atol=1e-13)
     ustar = O.exact_solve(sysm, f).ravel()
     assert np.linalg.norm(x - ustar) / np.linalg.norm(ustar) < 1e-9
+
+
+@pytest.mark.parametrize("R,C", [(1, 1), (3, 130), (64, 64), (65, 129), (1024, 7), (2, 5000)])
+@pytest.mark.parametrize("rev", [False, True])
+def test_transpose(R, C, rev):
+    x = np.random.default_rng(R * C).standard_normal(R * C)
+    got = E.transpose(x, R, C, rev)
+    A = x.reshape(R, C)
+    ref = (A[::-1] if rev else A).T.ravel()
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("N,M", [(2, 3), (64, 17), (1024, 5)])
+def test_rhs_mm(N, M):
+    f = np.random.default_rng(N + M).standard_normal(N * M)
+    b, s = E.rhs_mm(f, N, M)
+    ref = f.reshape(M, N)[:, ::-1].ravel()
+    assert np.array_equal(b, ref)
+    assert abs(s - np.dot(ref, ref)) < 1e-12 * np.dot(ref, ref)
