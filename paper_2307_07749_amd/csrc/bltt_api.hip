@@ -33,6 +33,9 @@ struct DeviceTables {
   T* mu = nullptr;
   cx<T>* tw_mv = nullptr;  // length 2N
   cx<T>* phat = nullptr;
+  cx<T>* chat = nullptr;   // circulant / skew-circulant spectra of p (sine basis)
+  cx<T>* shat = nullptr;
+  cx<T>* omega = nullptr;  // e^{i pi n/N}
   bool ready = false;
 };
 
@@ -44,6 +47,7 @@ struct Workspace {
   T* W[2] = {nullptr, nullptr};
   T* X = nullptr;  // inner solution (FP32 refinement sweeps)
   bool ready = false;
+  bool dirs = false;  // W (and X) allocated
 };
 
 double now_ms() {
@@ -84,6 +88,11 @@ struct bltt_handle {
   double* hist_dev = nullptr;
   int64_t hist_cap = 0;
   double* coef_one = nullptr;
+  // stored-basis sweeps (mixed, sine basis): Z_0..Z_{K-1} and the
+  // coefficient arrays of the directions and of the iterate
+  float* zpool[ZB_MAX] = {};
+  int zb_K = 0;
+  double* zb_dev = nullptr;  // 3*ZB_MAX doubles: om (2K), y (K)
   double setup_ms = 0.0;
   std::vector<void*> allocs;
   // per-kernel timing (bltt_profile_enable)
@@ -201,27 +210,61 @@ int build_tables(bltt_handle* h) {
   if (!short_p(h)) {
     if ((rc = upload_c<T>(h, &t.tw_mv, host::twiddles((int)(2 * h->N))))) return rc;
     if ((rc = upload_c<T>(h, &t.phat, host::matvec_spectrum(h->p)))) return rc;
+    if ((rc = upload_c<T>(h, &t.chat, host::circulant_spectrum(h->p, false)))) return rc;
+    if ((rc = upload_c<T>(h, &t.shat, host::circulant_spectrum(h->p, true)))) return rc;
+    if ((rc = upload_c<T>(h, &t.omega, host::half_roots(h->N)))) return rc;
   }
   t.ready = true;
   return BLTT_OK;
 }
 
+// Krylov workspace of one precision; dirs: also the explicit direction
+// vectors W (and the FP32 inner solution X), which the stored-basis sweeps
+// and the step entry points do not need
 template <typename T>
-int build_workspace(bltt_handle* h) {
+int build_workspace(bltt_handle* h, bool dirs) {
   Workspace<T>& w = workspace<T>(h);
-  if (w.ready) return BLTT_OK;
   int rc;
   const size_t n = (size_t)h->n;
-  if ((rc = dalloc(h, &w.Q, n))) return rc;
-  for (int i = 0; i < 3; ++i)
-    if ((rc = dalloc(h, &w.V[i], n))) return rc;
-  for (int i = 0; i < 2; ++i)
-    if ((rc = dalloc(h, &w.Z[i], n))) return rc;
-  for (int i = 0; i < 2; ++i)
-    if ((rc = dalloc(h, &w.W[i], n))) return rc;
-  if (sizeof(T) == 4)
-    if ((rc = dalloc(h, &w.X, n))) return rc;
-  w.ready = true;
+  if (!w.ready) {
+    if ((rc = dalloc(h, &w.Q, n))) return rc;
+    for (int i = 0; i < 3; ++i)
+      if ((rc = dalloc(h, &w.V[i], n))) return rc;
+    for (int i = 0; i < 2; ++i)
+      if ((rc = dalloc(h, &w.Z[i], n))) return rc;
+    w.ready = true;
+  }
+  if (dirs && !w.dirs) {
+    for (int i = 0; i < 2; ++i)
+      if ((rc = dalloc(h, &w.W[i], n))) return rc;
+    if (sizeof(T) == 4)
+      if ((rc = dalloc(h, &w.X, n))) return rc;
+    w.dirs = true;
+  }
+  return BLTT_OK;
+}
+
+// Pool of stored Z vectors for the FP32 sweeps: K = 16 (ZB_MAX at most), fewer
+// when device memory is short (at least 4).  Z[0], Z[1] of the workspace are
+// the first two.
+constexpr int ZB_DEFAULT = 16;
+int build_zpool(bltt_handle* h) {
+  if (h->zb_K) return BLTT_OK;
+  int rc;
+  Workspace<float>& w = h->w32;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return BLTT_EHIP;
+  const double per = (double)h->n * sizeof(float) + 64;
+  int K = ZB_DEFAULT;
+  const int fit = (int)std::min<double>(ZB_MAX, 2.0 + 0.6 * (double)free_b / per);
+  if (fit < K) K = fit;
+  if (K < 4) return BLTT_ENOMEM;
+  h->zpool[0] = w.Z[0];
+  h->zpool[1] = w.Z[1];
+  for (int i = 2; i < K; ++i)
+    if ((rc = dalloc(h, &h->zpool[i], (size_t)h->n))) return rc;
+  if ((rc = dalloc(h, &h->zb_dev, (size_t)(3 * ZB_MAX)))) return rc;
+  h->zb_K = K;
   return BLTT_OK;
 }
 
@@ -263,6 +306,33 @@ VupdStencil<T> vupd_stencil(bltt_handle* h, const T* z) {
   return st;
 }
 
+template <typename T>
+MatvecTables<T> mv_tables(bltt_handle* h) {
+  DeviceTables<T>& t = tables<T>(h);
+  MatvecTables<T> tb;
+  tb.tw = t.tw_mv;
+  tb.phat = t.phat;
+  tb.mu = t.mu;
+  for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
+  tb.qtaps = h->qtaps;
+  tb.grid = make_grid(h);
+  return tb;
+}
+
+template <typename T>
+MatvecCSTables<T> cs_tables(bltt_handle* h) {
+  DeviceTables<T>& t = tables<T>(h);
+  MatvecCSTables<T> tb;
+  tb.tw = t.tw_time;
+  tb.chat = t.chat;
+  tb.shat = t.shat;
+  tb.omega = t.omega;
+  tb.mu = t.mu;
+  for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
+  tb.qtaps = h->qtaps;
+  return tb;
+}
+
 // q = Y A z (MV_DOT, partial sums of <q, z>) or out = Y (fin - A z) (MV_RESID,
 // partial sums of the squared norm).  term selects the spatial part:
 // TERM_STENCIL the full physical-space operator, TERM_NONE only Y (p * z)
@@ -293,19 +363,30 @@ int matvec(bltt_handle* h, int mode, int term, const T* z, T* out, const T* fin,
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
     tb.qtaps = h->qtaps;
     tb.grid = make_grid(h);
+    IterUpd up{};
+    if (term == TERM_SPEC && sizeof(T) == 4) {
+      // FP32: N-point circulant + skew-circulant form (one wavefront per line pair)
+      ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
+      HIPCHK(launch_matvec_cs<T>((int)h->N, mode, const_cast<T*>(z), out, fin, h->M, cs_tables<T>(h), up,
+                                 h->partials, h->stream));
+      *np = fft_blocks<T, FK_TIME>((int)h->N, h->M);
+      return BLTT_OK;
+    }
     if (mode == MV_RESID && term == TERM_STENCIL) {
       // r = Y (f - p * u) on time lines, then the spatial term and ||r||^2 on x-lines
       const int64_t nlx = h->n / h->m[0];
       {
         ProfScope ps(h, BLTT_K_RESID64, 3.0 * h->n * sizeof(T));
-        HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), MV_RESID, TERM_NONE, z, out, fin, h->M, tb, h->partials,
+        HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), MV_RESID, TERM_NONE, const_cast<T*>(z), out, fin, h->M, tb, up,
+                                    h->partials,
                                     h->stream));
       }
       ProfScope ps(h, BLTT_K_RESID64, 3.0 * h->n * sizeof(T));
       HIPCHK(launch_resid_stencil<T>(out, vupd_stencil<T>(h, z), nlx, h->partials, np, h->stream));
     } else {
       ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
-      HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), mode, term, z, out, fin, h->M, tb, h->partials, h->stream));
+      HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), mode, term, const_cast<T*>(z), out, fin, h->M, tb, up, h->partials,
+                                  h->stream));
       *np = fft_blocks<T, FK_MV>((int)(2 * h->N), h->M);
     }
   }
@@ -401,10 +482,14 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
   return BLTT_OK;
 }
 
-int scalar(bltt_handle* h, int phase, int64_t np, double* hist, bool with_aux = false) {
+int scalar(bltt_handle* h, int phase, int64_t np, double* hist, bool with_aux = false, bool zbasis = false) {
   ProfScope ps(h, BLTT_K_OTHER, 8.0 * np);
+  ZBasis zb;
+  zb.om = zbasis ? h->zb_dev : nullptr;
+  zb.y = zbasis ? h->zb_dev + 2 * h->zb_K : nullptr;
+  zb.K = zbasis ? h->zb_K : 0;
   HIPCHK(launch_scalar(phase, h->state, h->partials, np, with_aux ? h->partials_aux : nullptr,
-                       with_aux ? h->np_aux : 0, hist, h->red_scratch, h->red_half, h->stream));
+                       with_aux ? h->np_aux : 0, hist, h->red_scratch, h->red_half, zb, h->stream));
   return BLTT_OK;
 }
 
@@ -518,13 +603,20 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
 // FP64 for an FP32 sweep); it is copied into V[0] as the first Lanczos vector
 // unless bsrc already is V[0].  X must be zero on entry.  fhat (FP64 only):
 // the transformed f for the explicit residual check, as in minres_core.
+//
+// zbasis (FP32 only): keep every Z_j in the stored pool instead of forming the
+// directions W and the iterate X; the sweep's iterate is sum_i y[i] Z_i with the
+// coefficients the scalar kernel carries (the caller adds it with
+// launch_combine over res->iters vectors).  A sweep then ends after at most
+// K - 1 iterations (the pool size); in the refinement loop that is a restart.
 template <typename T, typename TX, typename TB>
 int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* fhat, double tol, double bnorm,
-                double* hist_host, CoreResult* res, const TB* bsrc, const double* bcoef) {
+                double* hist_host, CoreResult* res, const TB* bsrc, const double* bcoef, bool zbasis = false) {
   Workspace<T>& ws = workspace<T>(h);
   hipStream_t s = h->stream;
   int rc;
   int64_t np = 0;
+  if (zbasis && (sizeof(T) != 4 || h->zb_K < 4)) return BLTT_EINVAL;
   T* Vc = ws.V[0];
   T* Vp = ws.V[1];
   T* Vn = ws.V[2];
@@ -533,7 +625,11 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   T* Wa = ws.W[0];
   T* Wb = ws.W[1];
   const double n = (double)h->n;
-  {
+  if (zbasis) {
+    Zc = reinterpret_cast<T*>(h->zpool[0]);
+    Zn = reinterpret_cast<T*>(h->zpool[1]);
+    maxit = std::min(maxit, h->zb_K - 1);
+  } else {
     ProfScope ps(h, BLTT_K_OTHER, 2.0 * n * sizeof(T));
     HIPCHK(launch_fill<T>(Wa, h->n, T(0), s));
     HIPCHK(launch_fill<T>(Wb, h->n, T(0), s));
@@ -549,7 +645,7 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     HIPCHK(launch_time_upd<T, TB>(L, false, bsrc, nullptr, nullptr, copy ? Vc : nullptr, Zc, h->M, tt, bcoef,
                                   h->partials, s));
   }
-  if ((rc = scalar(h, SC_START, npt, h->hist_dev))) return rc;
+  if ((rc = scalar(h, SC_START, npt, h->hist_dev, false, zbasis))) return rc;
   if ((rc = read_state(h))) return rc;
   if (h->state_host->status == -3) return BLTT_ENAN;
   if (h->state_host->status == -4) return BLTT_EBREAKDOWN;
@@ -565,8 +661,8 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
       ProfScope ps(h, BLTT_K_TIME, (j > 1 ? 5.0 : 4.0) * n * sizeof(T));
       HIPCHK(launch_time_upd<T, T>(L, true, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, h->M, tt, coef_v, h->partials, s));
     }
-    if ((rc = scalar(h, SC_BETA, npt, h->hist_dev))) return rc;
-    {
+    if ((rc = scalar(h, SC_BETA, npt, h->hist_dev, false, zbasis))) return rc;
+    if (!zbasis) {
       ProfScope ps(h, BLTT_K_WX, (4.0 * sizeof(T) + 2.0 * sizeof(TX)) * n);
       HIPCHK(launch_wx<T, TX>(Zc, Wa, Wb, X, h->n, coef_w, s));
     }
@@ -575,8 +671,13 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
       Vp = Vc;
       Vc = Vn;
       Vn = t;
-      std::swap(Zc, Zn);
-      std::swap(Wa, Wb);
+      if (zbasis) {
+        Zc = Zn;
+        Zn = j + 1 < h->zb_K ? reinterpret_cast<T*>(h->zpool[j + 1]) : nullptr;
+      } else {
+        std::swap(Zc, Zn);
+        std::swap(Wa, Wb);
+      }
     }
     if ((rc = read_state(h))) return rc;
     const SolverState& st = *h->state_host;
@@ -747,15 +848,19 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
     if ((rc = upload<double>(h, &h->coef_one, one))) return fail(rc);
   }
   if ((rc = build_tables<double>(h))) return fail(rc);
+  const bool sine = h->opt.basis == BLTT_BASIS_SINE;
   if (h->opt.precision == BLTT_MIXED) {
     if ((rc = build_tables<float>(h))) return fail(rc);
-    if ((rc = build_workspace<float>(h))) return fail(rc);
+    if ((rc = build_workspace<float>(h, !sine))) return fail(rc);
     if ((rc = dalloc(h, &h->R64, (size_t)h->n))) return fail(rc);
   } else {
-    if ((rc = build_workspace<double>(h))) return fail(rc);
+    if ((rc = build_workspace<double>(h, true))) return fail(rc);
   }
-  if (h->opt.basis == BLTT_BASIS_SINE)
+  if (sine) {
     if ((rc = dalloc(h, &h->F64, (size_t)h->n))) return fail(rc);
+    if (h->opt.precision == BLTT_MIXED)
+      if ((rc = build_zpool(h))) return fail(rc);
+  }
   if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(BLTT_EHIP);
   h->setup_ms = now_ms() - t0;
   *out = h;
@@ -787,7 +892,9 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     {
       ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
       HIPCHK(launch_transpose<double>(u_dev, h->F64, h->N, h->M, false, s));
-      HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
+      // the FP64 path and the direct-form residual read uhat from the start;
+      // the fused FFT residual of the mixed path writes it on the first sweep
+      if (h->opt.precision == BLTT_FP64 || short_p(h)) HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
     }
     double* b64 = h->opt.precision == BLTT_FP64 ? h->w64.V[0] : h->R64;
     {
@@ -802,6 +909,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     if (hist) hist[0] = 1.0;
     if (bn2 == 0.0) {
       relres = 0.0;
+      HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
     } else if (h->opt.precision == BLTT_FP64) {
       CoreResult cr;
       rc = minres_spec<double, double, double>(h, u_dev, maxit, h->opt.check_factor * tol, h->F64, tol, bnorm, hist,
@@ -831,27 +939,41 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
           break;
         }
         if (outer >= h->opt.max_refine || total_iters >= maxit) break;
-        {
-          ProfScope ps(h, BLTT_K_OTHER, 4.0 * h->n);
-          HIPCHK(launch_fill<float>(ws.X, h->n, 0.0f, s));
-        }
         CoreResult cr;
         const int left = maxit - total_iters;
         hbuf.assign((size_t)left + 2, 0.0);
-        rc = minres_spec<float, float, double>(h, ws.X, left, h->opt.inner_tol, nullptr, 0.0, 1.0, hbuf.data(), &cr,
-                                               h->R64, &h->state->rinv);
+        rc = minres_spec<float, float, double>(h, nullptr, left, h->opt.inner_tol, nullptr, 0.0, 1.0, hbuf.data(),
+                                               &cr, h->R64, &h->state->rinv, true);
         if (rc) return rc;
         if (hist)
           for (int k = 1; k <= cr.iters; ++k) hist[hist_pos + k] = hbuf[(size_t)k];
         hist_pos += cr.iters;
         total_iters += cr.iters;
         outer += 1;
-        // uhat += ||r|| d, then r = Y(fhat - A uhat) in FP64
-        {
-          ProfScope ps(h, BLTT_K_OTHER, 20.0 * h->n);
-          HIPCHK(launch_axpy64<float>(u_dev, ws.X, h->n, &h->state->rscale, s));
+        // uhat += ||r|| sum_i y_i Z_i, then r = Y(fhat - A uhat) in FP64 (one
+        // pass for dense p; the first sweep's uhat starts at zero and is not read)
+        const double* ycoef = h->zb_dev + 2 * h->zb_K;
+        if (short_p(h)) {
+          ZList<float> zl;
+          for (int i = 0; i < ZB_MAX; ++i) zl.z[i] = i < cr.iters ? h->zpool[i] : nullptr;
+          zl.k = cr.iters;
+          {
+            ProfScope ps(h, BLTT_K_WX, (16.0 + 4.0 * cr.iters) * h->n);
+            HIPCHK(launch_combine<float>(u_dev, zl, ycoef, &h->state->rscale, h->n, s));
+          }
+          if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, u_dev, h->R64, h->F64, &np))) return rc;
+        } else {
+          IterUpd up{};
+          for (int i = 0; i < ZB_MAX; ++i) up.z[i] = i < cr.iters ? h->zpool[i] : nullptr;
+          up.k = cr.iters;
+          up.y = ycoef;
+          up.s = &h->state->rscale;
+          up.u_zero = outer == 1 ? 1 : 0;
+          ProfScope ps(h, BLTT_K_RESID64, (32.0 + 4.0 * cr.iters - (up.u_zero ? 8.0 : 0.0)) * h->n);
+          HIPCHK(launch_matvec_fft<double>((int)(2 * h->N), MV_RESID, TERM_SPEC, u_dev, h->R64, h->F64, h->M,
+                                           mv_tables<double>(h), up, h->partials, s));
+          np = fft_blocks<double, FK_MV>((int)(2 * h->N), h->M);
         }
-        if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, u_dev, h->R64, h->F64, &np))) return rc;
         if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
         if ((rc = read_state(h))) return rc;
         rnorm = std::sqrt(h->state_host->norm2);
@@ -976,11 +1098,11 @@ static int step_prepare(bltt_handle* h, int32_t precision) {
   int rc;
   if (precision == BLTT_FP64) {
     if ((rc = build_tables<double>(h))) return rc;
-    return build_workspace<double>(h);
+    return build_workspace<double>(h, false);
   }
   if (precision == BLTT_FP32) {
     if ((rc = build_tables<float>(h))) return rc;
-    return build_workspace<float>(h);
+    return build_workspace<float>(h, false);
   }
   return BLTT_EINVAL;
 }

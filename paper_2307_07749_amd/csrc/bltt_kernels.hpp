@@ -63,6 +63,7 @@ constexpr int waves_fft() { return 1; }
 template <typename T>
 constexpr int max_waves_fft() { return sizeof(T) == 4 ? 4 : 2; }
 constexpr int TPB_EW = 256;  // elementwise / streaming kernels
+constexpr int ZB_MAX = 32;   // stored Z vectors of one FP32 sweep, at most
 
 // ---------------------------------------------------------------------------
 // XCD-aware tile order.  Workgroups are dealt round-robin to the 8 XCDs
@@ -196,15 +197,26 @@ struct MatvecTables {
 enum { MV_DOT = 0, MV_RESID = 1 };
 enum { TERM_NONE = 0, TERM_STENCIL = 1, TERM_SPEC = 2 };
 
+// Iterate update fused into the FP64 residual of the refinement loop:
+// u <- (u_zero ? 0 : u) + (*s) sum_{i<k} y[i] Z_i (Z_i the stored FP32 vectors of
+// the sweep), written back to u, and the residual formed from the new u.
+struct IterUpd {
+  const float* z[ZB_MAX];
+  int k;             // 0: no update
+  const double* y;
+  const double* s;
+  int u_zero;        // u not read (first sweep: the iterate starts at zero)
+};
+
 // Layout (MM): false = time-major vectors (element (i, n) at n*M + i, the ABI
 // layout), lines interleaved across the workgroup so that a row of 2*NL
 // consecutive points is one coalesced access; true = mode-major (element at
 // i*N + n, the sine-basis working layout), each line contiguous in memory and
 // owned by consecutive threads, and for N <= 512 by one wavefront.
 template <typename T, int L, int MODE, int TERM, bool MM, class Ctx>
-BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict__ z,
-                             T* __restrict__ out, const T* __restrict__ fin, int64_t M,
-                             const MatvecTables<T>& tb, double* __restrict__ partials) {
+BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restrict__ out,
+                             const T* __restrict__ fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
+                             double* __restrict__ partials) {
   static_assert(!(MM && TERM == TERM_STENCIL), "the stencil needs the time-major layout");
   constexpr int TPB = tpb_fft<T, FK_MV>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
@@ -221,12 +233,31 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   const int64_t ts = MM ? 1 : M;
   const int64_t la = MM ? iac * N : iac, lb = MM ? ibc * N : ibc;
   const int64_t sa = MM ? ia * N : ia, sb = MM ? ib * N : ib;
-  const T wa = va ? T(1) : T(0), wb = vb ? T(1) : T(0);
+  const bool upd = MODE == MV_RESID && up.k > 0;
+  const double us = upd ? *up.s : 0.0;
   cx<T> v[V], zin[VH];
 #pragma unroll
   for (int t = 0; t < VH; ++t) {
     const int64_t off = (int64_t)(g + t * s0) * ts;
-    zin[t] = mkc<T>(z[la + off] * wa, z[lb + off] * wb);
+    T ra = T(0), rb = T(0);
+    if (!(MODE == MV_RESID && up.u_zero)) {
+      ra = z[la + off];
+      rb = z[lb + off];
+    }
+    if (upd) {
+      // refinement update of the iterate, written back before its use
+      double da = 0.0, db = 0.0;
+      for (int i = 0; i < up.k; ++i) {
+        const double yi = up.y[i];
+        da += yi * (double)up.z[i][la + off];
+        db += yi * (double)up.z[i][lb + off];
+      }
+      ra = T((double)ra + us * da);
+      rb = T((double)rb + us * db);
+      if (va) z[sa + off] = ra;
+      if (vb) z[sb + off] = rb;
+    }
+    zin[t] = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
     v[t] = zin[t];
   }
 #pragma unroll
@@ -244,8 +275,11 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   for (int t = 0; t < VH; ++t) lds[F::idx(c, g + t * s0)] = zin[t];
   F::xsync(ctx);
 
-  const Stencil sta = make_stencil(va ? ia : 0, tb.grid);
-  const Stencil stb = make_stencil(vb ? ib : 0, tb.grid);
+  Stencil sta{}, stb{};
+  if constexpr (TERM == TERM_STENCIL) {
+    sta = make_stencil(va ? ia : 0, tb.grid);
+    stb = make_stencil(vb ? ib : 0, tb.grid);
+  }
   T mua = T(0), mub = T(0);
   if (TERM == TERM_SPEC) {
     mua = tb.mu[iac];
@@ -306,6 +340,136 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restr
   }
   const double s = block_sum<TPB>(ctx, red, part);
   if (tid == 0) partials[ctx.bid] = s;
+}
+
+// ---------------------------------------------------------------------------
+// matvec in sine coordinates, mode-major, with N-point transforms: the causal
+// Toeplitz product is T = (C + S)/2, C the circulant and S the skew-circulant
+// with first column p (S = D^{-1} C' D, C' circulant of D p, D = diag(e^{i pi
+// n/N}): the zero-padded 2N-point product split into its even and odd
+// frequencies).  Each line stays in the N-point layout of the time pass (one
+// wavefront per line pair for N <= 1024).  Line i gets, as in the 2N form,
+// Y (p * z + mu_i (q * z)) and the partial sums of <., z> (MV_DOT) or of the
+// squared residual Y (fin - ...) (MV_RESID).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MatvecCSTables {
+  const cx<T>* tw;     // length N
+  const cx<T>* chat;   // fft(p)/(2N)
+  const cx<T>* shat;   // fft(D p)/(2N)
+  const cx<T>* omega;  // e^{i pi n/N}
+  const T* mu;
+  T q[4];
+  int qtaps;
+};
+
+template <typename T, int L, int MODE, class Ctx>
+BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restrict__ out,
+                            const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
+                            double* __restrict__ partials) {
+  constexpr int TPB = tpb_fft<T, FK_TIME>();
+  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
+  constexpr int N = L;
+  using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
+  const int tid = ctx.tid, c = tid / G, g = tid % G;
+  const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
+  const bool va = ia < M, vb = ib < M;
+  const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
+  const int64_t la = iac * N, lb = ibc * N, sa = ia * N, sb = ib * N;
+  const bool upd = MODE == MV_RESID && up.k > 0;
+  const double us = upd ? *up.s : 0.0;
+  cx<T> zin[V], v[V], acc[V];
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int n = g + t * s0;
+    T ra = T(0), rb = T(0);
+    if (!(MODE == MV_RESID && up.u_zero)) {
+      ra = z[la + n];
+      rb = z[lb + n];
+    }
+    if (upd) {
+      double da = 0.0, db = 0.0;
+      for (int i = 0; i < up.k; ++i) {
+        const double yi = up.y[i];
+        da += yi * (double)up.z[i][la + n];
+        db += yi * (double)up.z[i][lb + n];
+      }
+      ra = T((double)ra + us * da);
+      rb = T((double)rb + us * db);
+      if (va) z[sa + n] = ra;
+      if (vb) z[sb + n] = rb;
+    }
+    zin[t] = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
+    v[t] = zin[t];
+  }
+  // circulant part
+  F::forward(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+  for (int w = 0; w < V / F::RL; ++w)
+#pragma unroll
+    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.chat[F::freq(g, w, u)];
+  F::inverse(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    acc[t] = v[t];
+    v[t] = zin[t] * tb.omega[g + t * s0];
+  }
+  // skew-circulant part
+  F::forward(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+  for (int w = 0; w < V / F::RL; ++w)
+#pragma unroll
+    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.shat[F::freq(g, w, u)];
+  F::inverse(ctx, v, lds, c, g, tb.tw);
+#pragma unroll
+  for (int t = 0; t < V; ++t) acc[t] = acc[t] + v[t] * conjg(tb.omega[g + t * s0]);
+
+  // z in LDS: the mirrored time N-1-n for the dot, z[n-k] for the mu term
+  F::xsync(ctx);
+#pragma unroll
+  for (int t = 0; t < V; ++t) lds[F::idx(c, g + t * s0)] = zin[t];
+  F::xsync(ctx);
+  const T mua = tb.mu[iac], mub = tb.mu[ibc];
+  double part = 0.0;
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    const int n = g + t * s0;
+    T sqa = tb.q[0] * zin[t].re, sqb = tb.q[0] * zin[t].im;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      const int nk = n - k;
+      const T w = nk >= 0 ? tb.q[k] : T(0);
+      const cx<T> zk = lds[F::idx(c, nk >= 0 ? nk : 0)];
+      sqa += w * zk.re;
+      sqb += w * zk.im;
+    }
+    const T ya = acc[t].re + mua * sqa, yb = acc[t].im + mub * sqb;
+    const int64_t er = N - 1 - n;
+    if (MODE == MV_DOT) {
+      const cx<T> zr = lds[F::idx(c, N - 1 - n)];
+      if (va) {
+        out[sa + er] = ya;
+        part += (double)ya * (double)zr.re;
+      }
+      if (vb) {
+        out[sb + er] = yb;
+        part += (double)yb * (double)zr.im;
+      }
+    } else {
+      if (va) {
+        const T r = fin[sa + n] - ya;
+        out[sa + er] = r;
+        part += (double)r * (double)r;
+      }
+      if (vb) {
+        const T r = fin[sb + n] - yb;
+        out[sb + er] = r;
+        part += (double)r * (double)r;
+      }
+    }
+  }
+  const double sum = block_sum<TPB>(ctx, red, part);
+  if (tid == 0) partials[ctx.bid] = sum;
 }
 
 // matvec, direct form for short p (ptaps <= 8): one thread per spatial point
@@ -1051,6 +1215,29 @@ BLTT_HD void fill_body(Ctx& ctx, T* __restrict__ x, int64_t n_total, T val) {
   for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) x[e] = val;
 }
 
+// u += s * sum_{i<k} y[i] Z_i: the iterate of a sweep kept as a combination
+// of its stored Z vectors, added to the FP64 solution (s = *sptr)
+template <typename T>
+struct ZList {
+  const T* z[ZB_MAX];
+  int k;
+};
+
+template <typename T, class Ctx>
+BLTT_HD void combine_body(Ctx& ctx, double* __restrict__ u, const ZList<T>& zl, const double* __restrict__ y,
+                          const double* __restrict__ sptr, int64_t n_total) {
+  const double s = *sptr;
+  double c[ZB_MAX];
+#pragma unroll
+  for (int i = 0; i < ZB_MAX; ++i) c[i] = i < zl.k ? s * y[i] : 0.0;
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) {
+    double acc = u[e];
+    for (int i = 0; i < zl.k; ++i) acc += c[i] * (double)zl.z[i][e];
+    u[e] = acc;
+  }
+}
+
 // y = (TO)(x * s)
 template <typename TI, typename TO, class Ctx>
 BLTT_HD void scale_cast_body(Ctx& ctx, const TI* __restrict__ x, TO* __restrict__ y, int64_t n_total,
@@ -1131,10 +1318,24 @@ enum {
   SC_BETA = 3    // beta_{j+1}, Givens rotation, w/x coefficients, eta
 };
 
+// Iterate kept as a combination of the stored preconditioned Lanczos vectors:
+// with Z_i the stored (unnormalised) z_{i+1}, w_j = sum_i om_j[i] Z_i follows
+// the direction recurrence on coefficients, and x_j = x_0 + sum_i y[i] Z_i.
+// om holds two coefficient vectors (w_{j-2}, w_{j-1}, alternating), each K long.
+struct ZBasis {
+  double* om;  // 2*K, or null when the direction vectors are kept explicitly
+  double* y;   // K
+  int K;
+};
+
 template <class Ctx>
 BLTT_HD void scalar_body(Ctx& ctx, double* red, int phase, SolverState* __restrict__ st,
                          const double* __restrict__ partials, int64_t np, const double* __restrict__ aux,
-                         int64_t naux, double* __restrict__ hist) {
+                         int64_t naux, double* __restrict__ hist, ZBasis zb) {
+  if (zb.om && phase == SC_START) {
+    for (int i = ctx.tid; i < 2 * zb.K; i += TPB_EW) zb.om[i] = 0.0;
+    for (int i = ctx.tid; i < zb.K; i += TPB_EW) zb.y[i] = 0.0;
+  }
   double sum = reduce_partials(ctx, red, partials, np);
   if (aux) sum += reduce_partials(ctx, red, aux, naux);
   if (ctx.tid != 0) return;
@@ -1199,6 +1400,15 @@ BLTT_HD void scalar_body(Ctx& ctx, double* red, int phase, SolverState* __restri
   st->coef_w[1] = -a3 / a1;
   st->coef_w[2] = -a2 / a1;
   st->coef_w[3] = cn * st->eta;
+  if (zb.om && st->iter < zb.K) {
+    // w_j over Z_0..Z_{j-1} (j = iter + 1): overwrite the coefficients of w_{j-2}
+    const int j0 = st->iter;
+    double* oa = zb.om + (j0 & 1) * zb.K;
+    const double* ob = zb.om + ((j0 + 1) & 1) * zb.K;
+    for (int i = 0; i < j0; ++i) oa[i] = st->coef_w[1] * oa[i] + st->coef_w[2] * ob[i];
+    oa[j0] = st->coef_w[0];
+    for (int i = 0; i <= j0; ++i) zb.y[i] += st->coef_w[3] * oa[i];
+  }
   st->eta = -sn * st->eta;
   st->c_prev = st->c;
   st->c = cn;

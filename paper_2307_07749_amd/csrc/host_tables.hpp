@@ -84,6 +84,27 @@ inline std::vector<cd> matvec_spectrum(const std::vector<double>& p) {
   return out;
 }
 
+// Causal Toeplitz product as circulant + skew-circulant (both N x N, first
+// column p): T = (C + S)/2 with C = F^{-1} diag(fft(p)) F and
+// S = D^{-1} F^{-1} diag(fft(D p)) F D, D = diag(e^{i pi n/N}).  Returns
+// fft(p)/(2N) and fft(D p)/(2N) (the kernels' inverse FFT is unnormalised).
+inline std::vector<cd> circulant_spectrum(const std::vector<double>& p, bool skew) {
+  const int64_t N = (int64_t)p.size();
+  std::vector<cd> s((size_t)N);
+  for (int64_t j = 0; j < N; ++j)
+    s[(size_t)j] = skew ? std::conj(unit_root(j, 2 * N)) * p[(size_t)j] : cd(p[(size_t)j], 0.0);
+  std::vector<cd> out = dft(s);
+  for (auto& v : out) v /= (double)(2 * N);
+  return out;
+}
+
+// e^{i pi n / N}, n < N
+inline std::vector<cd> half_roots(int64_t N) {
+  std::vector<cd> r((size_t)N);
+  for (int64_t n = 0; n < N; ++n) r[(size_t)n] = std::conj(unit_root(n, 2 * N));
+  return r;
+}
+
 inline std::vector<double> lap_eigs_1d(int m, double h) {
   std::vector<double> mu((size_t)m);
   const long double pi = 3.141592653589793238462643383279L;

@@ -1,0 +1,99 @@
+// Sine-coordinate matvec (mode-major vectors) with N-point circulant and
+// skew-circulant transforms; the FP64 residual variant also folds in the
+// refinement update of the iterate.  The four N-entry tables (twiddles, the
+// two spectra, e^{i pi n/N}) are staged in LDS when they fit beside the
+// exchange buffers.
+#include "launchers.hpp"
+
+namespace bltt {
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+template <typename T, int L>
+constexpr size_t cs_lds_base() { return fft_lds_bytes<T, FK_TIME>(L); }
+template <typename T, int L>
+constexpr bool cs_stage() { return cs_lds_base<T, L>() + 4 * (size_t)L * sizeof(cx<T>) <= LDS_LIMIT; }
+template <typename T, int L>
+constexpr size_t cs_lds_bytes() { return cs_lds_base<T, L>() + (cs_stage<T, L>() ? 4 * (size_t)L * sizeof(cx<T>) : 0); }
+
+template <typename T, int L, int MODE>
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_TIME>()), waves_fft<T>()) void k_matvec_cs(
+    T* z, T* __restrict__ out, const T* __restrict__ fin, int64_t M, MatvecCSTables<T> tb, IterUpd up,
+    double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NL = tpb_fft<T, FK_TIME>() / (L / fft_V(L));
+  using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
+  DevCtx ctx = make_ctx();
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
+  if constexpr (cs_stage<T, L>()) {
+    cx<T>* tabs = reinterpret_cast<cx<T>*>(smem + cs_lds_base<T, L>());
+    for (int i = ctx.tid; i < L; i += tpb_fft<T, FK_TIME>()) {
+      tabs[i] = tb.tw[i];
+      tabs[L + i] = tb.chat[i];
+      tabs[2 * L + i] = tb.shat[i];
+      tabs[3 * L + i] = tb.omega[i];
+    }
+    __syncthreads();
+    tb.tw = tabs;
+    tb.chat = tabs + L;
+    tb.shat = tabs + 2 * L;
+    tb.omega = tabs + 3 * L;
+  }
+  matvec_cs_body<T, L, MODE>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb, up, partials);
+}
+
+template <typename T, int L>
+static hipError_t go_cs(int mode, T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb,
+                        const IterUpd& up, double* partials, hipStream_t s) {
+  const int64_t blocks = fft_blocks<T, FK_TIME>(L, M);
+  const size_t lds = cs_lds_bytes<T, L>();
+  if (mode == MV_DOT)
+    hipLaunchKernelGGL((k_matvec_cs<T, L, MV_DOT>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s, z,
+                       out, fin, M, tb, up, partials);
+  else
+    hipLaunchKernelGGL((k_matvec_cs<T, L, MV_RESID>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s, z,
+                       out, fin, M, tb, up, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_matvec_cs(int L, int mode, T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb,
+                            const IterUpd& up, double* partials, hipStream_t s) {
+  if (up.k < 0 || up.k > ZB_MAX || (up.k > 0 && mode != MV_RESID)) return hipErrorInvalidValue;
+  switch (L) {
+#define BLTT_CASE(LL) \
+  case LL: return go_cs<T, LL>(mode, z, out, fin, M, tb, up, partials, s);
+    BLTT_CASE(2) BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64)
+    BLTT_CASE(128) BLTT_CASE(256) BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
+#undef BLTT_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_matvec_cs<float>(int, int, float*, float*, const float*, int64_t,
+                                            const MatvecCSTables<float>&, const IterUpd&, double*, hipStream_t);
+template hipError_t launch_matvec_cs<double>(int, int, double*, double*, const double*, int64_t,
+                                             const MatvecCSTables<double>&, const IterUpd&, double*, hipStream_t);
+
+template <typename T, int L>
+static hipError_t attr_cs() {
+  const int bytes = (int)cs_lds_bytes<T, L>();
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_cs<T, L, MV_DOT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_cs<T, L, MV_RESID>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t configure_cs_kernels() {
+  hipError_t e = hipSuccess;
+#define BLTT_ATTR(L)                                        \
+  if ((e = attr_cs<float, L>()) != hipSuccess) return e;   \
+  if ((e = attr_cs<double, L>()) != hipSuccess) return e;
+  BLTT_ATTR(2) BLTT_ATTR(4) BLTT_ATTR(8) BLTT_ATTR(16) BLTT_ATTR(32) BLTT_ATTR(64)
+  BLTT_ATTR(128) BLTT_ATTR(256) BLTT_ATTR(512) BLTT_ATTR(1024) BLTT_ATTR(2048)
+#undef BLTT_ATTR
+  return e;
+}
+
+}  // namespace bltt

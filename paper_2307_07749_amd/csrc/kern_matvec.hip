@@ -5,9 +5,10 @@
 namespace bltt {
 
 template <typename T, int L, int MODE, int TERM>
-__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_MV>()), waves_fft<T>()) void k_matvec_fft(const T* __restrict__ z, T* __restrict__ out,
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_MV>()), waves_fft<T>()) void k_matvec_fft(T* z, T* __restrict__ out,
                                                              const T* __restrict__ fin, int64_t M,
-                                                             MatvecTables<T> tb, double* __restrict__ partials) {
+                                                             MatvecTables<T> tb, IterUpd up,
+                                                             double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NL = tpb_fft<T, FK_MV>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, TERM != TERM_SPEC, LAST_DEFAULT>;
@@ -15,7 +16,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
   // the sine-coordinate forms work on the mode-major layout
   matvec_fft_body<T, L, MODE, TERM, TERM == TERM_SPEC>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb,
-                                                       partials);
+                                                       up, partials);
 }
 
 template <typename T, int MODE>
@@ -28,20 +29,21 @@ __global__ __launch_bounds__(TPB_EW) void k_matvec_short(const T* __restrict__ z
 }
 
 // (mode, term) combinations in use: Y A z with the stencil (step entry point),
-// Y (p * z) alone (physical-space MINRES), the sine-coordinate forms, and the
-// residual without the stencil (its spatial term follows on x-lines)
-#define BLTT_MV_VARIANTS(X) X(MV_DOT, TERM_STENCIL) X(MV_DOT, TERM_NONE) X(MV_DOT, TERM_SPEC) \
-  X(MV_RESID, TERM_NONE) X(MV_RESID, TERM_SPEC)
+// Y (p * z) alone (physical-space MINRES), the residual without the stencil
+// (its spatial term follows on x-lines), and the FP64 sine-coordinate forms
+// (FP32 uses the N-point kernel of kern_cs.hip).
+#define BLTT_MV_VARIANTS(X) X(MV_DOT, TERM_STENCIL) X(MV_DOT, TERM_NONE) X(MV_RESID, TERM_NONE) \
+  X(MV_DOT, TERM_SPEC) X(MV_RESID, TERM_SPEC)
 
 template <typename T, int L>
-static hipError_t go_mv(int mode, int term, const T* z, T* out, const T* fin, int64_t M,
-                        const MatvecTables<T>& tb, double* partials, hipStream_t s) {
+static hipError_t go_mv(int mode, int term, T* z, T* out, const T* fin, int64_t M,
+                        const MatvecTables<T>& tb, const IterUpd& up, double* partials, hipStream_t s) {
   const int64_t blocks = fft_blocks<T, FK_MV>(L, M);
   const size_t lds = fft_lds_bytes<T, FK_MV>(L);
 #define BLTT_GO(MO, TE)                                                                                   \
   if (mode == MO && term == TE) {                                                                         \
     hipLaunchKernelGGL((k_matvec_fft<T, L, MO, TE>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, \
-                       s, z, out, fin, M, tb, partials);                                                  \
+                       s, z, out, fin, M, tb, up, partials);                                              \
     return hipGetLastError();                                                                             \
   }
   BLTT_MV_VARIANTS(BLTT_GO)
@@ -50,20 +52,21 @@ static hipError_t go_mv(int mode, int term, const T* z, T* out, const T* fin, in
 }
 
 template <typename T>
-hipError_t launch_matvec_fft(int L, int mode, int term, const T* z, T* out, const T* fin, int64_t M,
-                             const MatvecTables<T>& tb, double* partials, hipStream_t s) {
+hipError_t launch_matvec_fft(int L, int mode, int term, T* z, T* out, const T* fin, int64_t M,
+                             const MatvecTables<T>& tb, const IterUpd& up, double* partials, hipStream_t s) {
+  if (up.k < 0 || up.k > ZB_MAX || (up.k > 0 && !(mode == MV_RESID && term == TERM_SPEC))) return hipErrorInvalidValue;
   switch (L) {
-    case 4: return go_mv<T, 4>(mode, term, z, out, fin, M, tb, partials, s);
-    case 8: return go_mv<T, 8>(mode, term, z, out, fin, M, tb, partials, s);
-    case 16: return go_mv<T, 16>(mode, term, z, out, fin, M, tb, partials, s);
-    case 32: return go_mv<T, 32>(mode, term, z, out, fin, M, tb, partials, s);
-    case 64: return go_mv<T, 64>(mode, term, z, out, fin, M, tb, partials, s);
-    case 128: return go_mv<T, 128>(mode, term, z, out, fin, M, tb, partials, s);
-    case 256: return go_mv<T, 256>(mode, term, z, out, fin, M, tb, partials, s);
-    case 512: return go_mv<T, 512>(mode, term, z, out, fin, M, tb, partials, s);
-    case 1024: return go_mv<T, 1024>(mode, term, z, out, fin, M, tb, partials, s);
-    case 2048: return go_mv<T, 2048>(mode, term, z, out, fin, M, tb, partials, s);
-    case 4096: return go_mv<T, 4096>(mode, term, z, out, fin, M, tb, partials, s);
+    case 4: return go_mv<T, 4>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 8: return go_mv<T, 8>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 16: return go_mv<T, 16>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 32: return go_mv<T, 32>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 64: return go_mv<T, 64>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 128: return go_mv<T, 128>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 256: return go_mv<T, 256>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 512: return go_mv<T, 512>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 1024: return go_mv<T, 1024>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 2048: return go_mv<T, 2048>(mode, term, z, out, fin, M, tb, up, partials, s);
+    case 4096: return go_mv<T, 4096>(mode, term, z, out, fin, M, tb, up, partials, s);
   }
   return hipErrorInvalidValue;
 }
@@ -108,9 +111,8 @@ hipError_t launch_matvec_short(int mode, const T* z, T* out, const T* fin, int64
 }
 
 #define BLTT_INST(T)                                                                                          \
-  template hipError_t launch_matvec_fft<T>(int, int, int, const T*, T*, const T*, int64_t,                  \
-                                           const MatvecTables<T>&,                                           \
-                                           double*, hipStream_t);                                            \
+  template hipError_t launch_matvec_fft<T>(int, int, int, T*, T*, const T*, int64_t, const MatvecTables<T>&,  \
+                                           const IterUpd&, double*, hipStream_t);                            \
   template hipError_t launch_matvec_short<T>(int, const T*, T*, const T*, int64_t, const ShortTables<T>&,     \
                                              double*, int64_t*, hipStream_t);
 BLTT_INST(float)

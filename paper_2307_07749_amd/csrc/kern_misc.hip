@@ -72,10 +72,18 @@ __global__ __launch_bounds__(TPB_EW) void k_reduce(const double* __restrict__ in
 __global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __restrict__ st,
                                                    const double* __restrict__ partials, int64_t np,
                                                    const double* __restrict__ aux, int64_t naux,
-                                                   double* __restrict__ hist) {
+                                                   double* __restrict__ hist, ZBasis zb) {
   __shared__ double red[TPB_EW];
   DevCtx ctx = make_ctx();
-  scalar_body(ctx, red, phase, st, partials, np, aux, naux, hist);
+  scalar_body(ctx, red, phase, st, partials, np, aux, naux, hist, zb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB_EW) void k_combine(double* __restrict__ u, ZList<T> zl,
+                                                    const double* __restrict__ y, const double* __restrict__ sptr,
+                                                    int64_t n) {
+  DevCtx ctx = make_ctx();
+  combine_body<T>(ctx, u, zl, y, sptr, n);
 }
 
 hipError_t launch_rhs_mm(const double* f, double* b, int64_t N, int64_t M, double* partials, int64_t* nparts,
@@ -100,6 +108,16 @@ hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev,
   return hipGetLastError();
 }
 template hipError_t launch_transpose<double>(const double*, double*, int64_t, int64_t, bool, hipStream_t);
+
+template <typename T>
+hipError_t launch_combine(double* u, const ZList<T>& zl, const double* y, const double* sptr, int64_t n,
+                          hipStream_t s) {
+  if (zl.k < 0 || zl.k > ZB_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_combine<T>, dim3((unsigned)ew_blocks(n)), dim3(TPB_EW), 0, s, u, zl, y, sptr, n);
+  return hipGetLastError();
+}
+template hipError_t launch_combine<float>(double*, const ZList<float>&, const double*, const double*, int64_t,
+                                          hipStream_t);
 
 template <typename T>
 hipError_t launch_resid_stencil(T* r, const VupdStencil<T>& st, int64_t nlines, double* partials, int64_t* nparts,
@@ -147,7 +165,8 @@ hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, 
   return hipGetLastError();
 }
 hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
-                         int64_t naux, double* hist, double* scratch, int64_t scratch_half, hipStream_t s) {
+                         int64_t naux, double* hist, double* scratch, int64_t scratch_half, ZBasis zb,
+                         hipStream_t s) {
   // long partial-sum arrays go through one wide first stage (into scratch,
   // aux at scratch + scratch_half)
   if (np > RED_CHUNK) {
@@ -164,7 +183,7 @@ hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int
     aux = scratch + scratch_half;
     naux = nb;
   }
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(TPB_EW), 0, s, phase, st, partials, np, aux, naux, hist);
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(TPB_EW), 0, s, phase, st, partials, np, aux, naux, hist, zb);
   return hipGetLastError();
 }
 
@@ -189,13 +208,15 @@ hipError_t configure_time_kernels();
 hipError_t configure_matvec_kernels();
 hipError_t configure_dst_kernels();
 hipError_t configure_spec_kernels();
+hipError_t configure_cs_kernels();
 
 hipError_t configure_kernels() {
   hipError_t e;
   if ((e = configure_time_kernels()) != hipSuccess) return e;
   if ((e = configure_matvec_kernels()) != hipSuccess) return e;
   if ((e = configure_dst_kernels()) != hipSuccess) return e;
-  return configure_spec_kernels();
+  if ((e = configure_spec_kernels()) != hipSuccess) return e;
+  return configure_cs_kernels();
 }
 
 }  // namespace bltt

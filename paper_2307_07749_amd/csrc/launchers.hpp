@@ -43,9 +43,17 @@ template <typename T, typename TQ>
 hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                            const TimeTables<T>& tb, const double* coef, double* partials, hipStream_t s);
 
+// up: refinement update of the iterate z (MV_RESID with TERM_SPEC only; k = 0 for none)
 template <typename T>
-hipError_t launch_matvec_fft(int L, int mode, int term, const T* z, T* out, const T* fin, int64_t M,
-                             const MatvecTables<T>& tb, double* partials, hipStream_t s);
+hipError_t launch_matvec_fft(int L, int mode, int term, T* z, T* out, const T* fin, int64_t M,
+                             const MatvecTables<T>& tb, const IterUpd& up, double* partials, hipStream_t s);
+
+// sine coordinates, mode-major: Y (p * z + mu (q * z)) with N-point transforms
+// (MV_DOT: out, partial sums of <out, z>; MV_RESID: out = Y (fin - A u) after
+// u <- u + s sum y_i Z_i when up.k > 0, partial sums of ||out||^2)
+template <typename T>
+hipError_t launch_matvec_cs(int L, int mode, T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb,
+                            const IterUpd& up, double* partials, hipStream_t s);
 
 template <typename T>
 hipError_t launch_matvec_short(int mode, const T* z, T* out, const T* fin, int64_t M,
@@ -86,6 +94,11 @@ hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, 
 // scratch: 2*scratch_half doubles for the first reduction stage of long
 // partial-sum arrays (at most scratch_half workgroups of RED_CHUNK each)
 hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
-                         int64_t naux, double* hist, double* scratch, int64_t scratch_half, hipStream_t s);
+                         int64_t naux, double* hist, double* scratch, int64_t scratch_half, ZBasis zb,
+                         hipStream_t s);
+// u += (*sptr) * sum_i y[i] Z_i over the zl.k stored vectors
+template <typename T>
+hipError_t launch_combine(double* u, const ZList<T>& zl, const double* y, const double* sptr, int64_t n,
+                          hipStream_t s);
 
 }  // namespace bltt

@@ -73,12 +73,16 @@ def lib():
         L.emu_time_upd_mixed.restype = ctypes.c_double
         L.emu_resid_spec_f64.argtypes = args + [P, P, P, ctypes.c_int]
         L.emu_resid_spec_f64.restype = ctypes.c_double
+        L.emu_resid_upd_f64.argtypes = args + [P, P, P, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
+                                               ctypes.c_int]
+        L.emu_resid_upd_f64.restype = ctypes.c_double
         L.emu_state_size.restype = ctypes.c_int64
         L.emu_transpose_f64.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
         L.emu_rhs_mm.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
         L.emu_rhs_mm.restype = ctypes.c_double
         L.emu_state_offsets.argtypes = [P]
-        L.emu_scalar.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P]
+        L.emu_scalar.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P, P, P, ctypes.c_int]
+        L.emu_combine_f32.argtypes = [P, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int64]
         L.emu_resid_f64.argtypes = args + [P, P, P]
         L.emu_resid_f64.restype = ctypes.c_double
         L.emu_error.restype = ctypes.c_int
@@ -233,21 +237,27 @@ def time_upd_mixed(prob, Q64, coef):
     return gv.data.copy(), gz.data.copy(), dot
 
 
-def sym_spec(prob, z, dtype=np.float64, force_fft=False):
+FORMS = {"direct": 0, "cs": 1, "2n": 2}
+
+
+def sym_spec(prob, z, dtype=np.float64, force_fft=False, form=None):
+    """form: 'direct' (short p), 'cs' (N-point), '2n' (2N-point); force_fft=True means 'cs'."""
     args, keep = _common(prob)
     gz = Guarded(z, dtype)
     go = Guarded(np.zeros(z.size), dtype)
-    dot = getattr(lib(), f"emu_sym_spec_{_tag(dtype)}")(*args, gz.ptr, go.ptr, int(force_fft))
+    f = FORMS[form] if form else (1 if force_fft else 0)
+    dot = getattr(lib(), f"emu_sym_spec_{_tag(dtype)}")(*args, gz.ptr, go.ptr, f)
     _check(gz, go)
     return go.data.copy(), dot
 
 
-def resid_spec(prob, u, f, force_fft=False):
+def resid_spec(prob, u, f, force_fft=False, form=None):
     args, keep = _common(prob)
     gu = Guarded(u, np.float64)
     gf = Guarded(f, np.float64)
     gr = Guarded(np.zeros(u.size), np.float64)
-    s = lib().emu_resid_spec_f64(*args, gu.ptr, gf.ptr, gr.ptr, int(force_fft))
+    fm = FORMS[form] if form else (1 if force_fft else 0)
+    s = lib().emu_resid_spec_f64(*args, gu.ptr, gf.ptr, gr.ptr, fm)
     _check(gu, gf, gr)
     return gr.data.copy(), s
 
@@ -292,9 +302,11 @@ class State:
     def coef_v(self):
         return np.frombuffer(self.buf, dtype=np.float64, count=3, offset=self.off[0]).copy()
 
-    def scalar(self, phase, total, hist=None):
+    def scalar(self, phase, total, hist=None, zb=None):
+        """zb: (om, y) float64 arrays of lengths 2K and K for the stored-basis iterate."""
         part = np.array([total], dtype=np.float64)
-        lib().emu_scalar(phase, self.ptr, part.ctypes.data, 1, None if hist is None else hist.ctypes.data)
+        om, y, K = (None, None, 0) if zb is None else (zb[0].ctypes.data, zb[1].ctypes.data, zb[1].size)
+        lib().emu_scalar(phase, self.ptr, part.ctypes.data, 1, None if hist is None else hist.ctypes.data, om, y, K)
 
 
 def wx(Z, Wa, Wb, X, coef_ptr):
@@ -318,3 +330,27 @@ def rhs_mm(f, N, M):
     s = lib().emu_rhs_mm(gf.ptr, gb.ptr, N, M)
     _check(gf, gb)
     return gb.data.copy(), s
+
+
+def combine_f32(u, Zs, y, s):
+    """u += s * sum_i y[i] Zs[i] (u float64, Zs float32 rows), in place on a copy."""
+    k = len(Zs)
+    zs = np.ascontiguousarray(np.stack(Zs).astype(np.float32))
+    out = np.ascontiguousarray(u, dtype=np.float64).copy()
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    lib().emu_combine_f32(out.ctypes.data, zs.ctypes.data, k, yy.ctypes.data, float(s), out.size)
+    return out
+
+
+def resid_upd(prob, u, f, Zs, y, s, u_zero, two_n=False):
+    """(u_new, r, ||r||^2): u_new = (0 if u_zero else u) + s sum y_i Zs[i]; r = Y(f - A u_new)."""
+    args, keep = _common(prob)
+    gu = Guarded(u, np.float64)
+    gf = Guarded(f, np.float64)
+    gr = Guarded(np.zeros(u.size), np.float64)
+    zs = np.ascontiguousarray(np.stack(Zs).astype(np.float32))
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    ss = lib().emu_resid_upd_f64(*args, gu.ptr, gf.ptr, gr.ptr, zs.ctypes.data, len(Zs), yy.ctypes.data, float(s),
+                                 int(u_zero), int(two_n))
+    _check(gu, gf, gr)
+    return gu.data.copy(), gr.data.copy(), ss

@@ -197,11 +197,11 @@ struct MvRun {
                [&](HostCtx& c, unsigned char* lds) {
         double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
         if (stencil)
-          matvec_fft_body<T, L, MV_DOT, TERM_STENCIL, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr,
-                                                             M, tb, partials);
+          matvec_fft_body<T, L, MV_DOT, TERM_STENCIL, false>(c, reinterpret_cast<cx<T>*>(lds), red, const_cast<T*>(z),
+                                                             out, nullptr, M, tb, IterUpd{}, partials);
         else
-          matvec_fft_body<T, L, MV_DOT, TERM_NONE, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, nullptr, M,
-                                                          tb, partials);
+          matvec_fft_body<T, L, MV_DOT, TERM_NONE, false>(c, reinterpret_cast<cx<T>*>(lds), red, const_cast<T*>(z), out,
+                                                          nullptr, M, tb, IterUpd{}, partials);
       });
     }
   };
@@ -401,8 +401,9 @@ struct MvResRun {
       run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
                [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
-                 matvec_fft_body<T, L, MV_RESID, TERM_NONE, false>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin,
-                                                                   M, tb, partials);
+                 matvec_fft_body<T, L, MV_RESID, TERM_NONE, false>(c, reinterpret_cast<cx<T>*>(lds), red,
+                                                                   const_cast<T*>(z), out, fin, M, tb, IterUpd{},
+                                                                   partials);
                });
     }
   };
@@ -500,21 +501,41 @@ template <typename T, int MODE>
 struct MvSpecRun {
   template <int L>
   struct R {
-    static void run(const T* z, T* out, const T* fin, int64_t M, const MatvecTables<T>& tb, double* partials) {
+    static void run(T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
+                    double* partials) {
+      constexpr int NL = lines_per_block<T, FK_TIME>(L);
+      using Fm = LineFft<T, L, NL, false, LAST_DEFAULT>;
+      run_grid(tpb_fft<T, FK_TIME>(), (int)fft_blocks<T, FK_TIME>(L, M), 1, fft_lds_bytes<T, FK_TIME>(L),
+               [&](HostCtx& c, unsigned char* lds) {
+                 double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
+                 matvec_cs_body<T, L, MODE>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M, tb, up, partials);
+               });
+    }
+  };
+};
+
+// 2N-point form on mode-major vectors (the FP64 sine-coordinate kernels)
+template <typename T, int MODE>
+struct MvSpec2nRun {
+  template <int L>
+  struct R {
+    static void run(T* z, T* out, const T* fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
+                    double* partials) {
       constexpr int NL = lines_per_block<T, FK_MV>(L);
       using Fm = LineFft<T, L, NL, false, LAST_DEFAULT>;
       run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
                [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
                  matvec_fft_body<T, L, MODE, TERM_SPEC, true>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M,
-                                                              tb, partials);
+                                                              tb, up, partials);
                });
     }
   };
 };
 
 template <typename T, int MODE>
-double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force_fft) {
+double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force_fft, const IterUpd* upd = nullptr,
+                  bool two_n = false) {
   int ptaps = 0, qtaps = 0;
   for (int64_t k = 0; k < P.N; ++k) {
     if (P.p[(size_t)k] != 0.0) ptaps = (int)k + 1;
@@ -542,7 +563,7 @@ double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force
       matvec_short_mm_body<T, MODE>(c, reinterpret_cast<double*>(lds), z, out, fin, P.M, tb, log2N, partials.data());
     });
     for (double v : partials) dot += v;
-  } else {
+  } else if (two_n) {
     MatvecTables<T> tb;
     tb.tw = ht.tw_mv.data();
     tb.phat = ht.phat.data();
@@ -550,17 +571,37 @@ double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
     tb.qtaps = qtaps;
     tb.grid = grid_of(P);
+    IterUpd up{};
+    if (upd) up = *upd;
     std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
-    with_L2<MvSpecRun<T, MODE>::template R>((int)(2 * P.N), z, out, fin, P.M, tb, partials.data());
+    with_L2<MvSpec2nRun<T, MODE>::template R>((int)(2 * P.N), const_cast<T*>(z), out, fin, P.M, tb, up,
+                                             partials.data());
+    for (double v : partials) dot += v;
+  } else {
+    const std::vector<cx<T>> chat = to_cx<T>(host::circulant_spectrum(P.p, false));
+    const std::vector<cx<T>> shat = to_cx<T>(host::circulant_spectrum(P.p, true));
+    const std::vector<cx<T>> omega = to_cx<T>(host::half_roots(P.N));
+    MatvecCSTables<T> tb;
+    tb.tw = ht.tw_time.data();
+    tb.chat = chat.data();
+    tb.shat = shat.data();
+    tb.omega = omega.data();
+    tb.mu = ht.mu.data();
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+    tb.qtaps = qtaps;
+    IterUpd up{};
+    if (upd) up = *upd;
+    std::vector<double> partials((size_t)fft_blocks<T, FK_TIME>((int)P.N, P.M));
+    with_L<MvSpecRun<T, MODE>::template R>((int)P.N, const_cast<T*>(z), out, fin, P.M, tb, up, partials.data());
     for (double v : partials) dot += v;
   }
   return dot;
 }
 
 // scalar phase and direction/iterate update, as the solver sequences them
-void apply_scalar(int phase, SolverState* st, const double* partials, int64_t np, double* hist) {
+void apply_scalar(int phase, SolverState* st, const double* partials, int64_t np, double* hist, ZBasis zb) {
   run_grid(TPB_EW, 1, 1, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
-    scalar_body(c, reinterpret_cast<double*>(lds), phase, st, partials, np, (const double*)nullptr, 0, hist);
+    scalar_body(c, reinterpret_cast<double*>(lds), phase, st, partials, np, (const double*)nullptr, 0, hist, zb);
   });
 }
 
@@ -614,8 +655,21 @@ void emu_state_offsets(int64_t* o) {
   o[6] = offsetof(SolverState, rscale);
   o[7] = offsetof(SolverState, iter);
 }
-void emu_scalar(int phase, void* st, const double* partials, int64_t np, double* hist) {
-  apply_scalar(phase, reinterpret_cast<SolverState*>(st), partials, np, hist);
+void emu_scalar(int phase, void* st, const double* partials, int64_t np, double* hist, double* om, double* y,
+                int K) {
+  ZBasis zb;
+  zb.om = om;
+  zb.y = y;
+  zb.K = K;
+  apply_scalar(phase, reinterpret_cast<SolverState*>(st), partials, np, hist, zb);
+}
+// u += s * sum_i y[i] Z_i, Z_i = zs + i*n (FP32)
+void emu_combine_f32(double* u, const float* zs, int k, const double* y, double s, int64_t n) {
+  ZList<float> zl;
+  for (int i = 0; i < ZB_MAX; ++i) zl.z[i] = i < k ? zs + (int64_t)i * n : nullptr;
+  zl.k = k;
+  const int nb = (int)std::min<int64_t>((n + TPB_EW - 1) / TPB_EW, 9);
+  run_grid(TPB_EW, nb, 1, 0, [&](HostCtx& c, unsigned char*) { combine_body<float>(c, u, zl, y, &s, n); });
 }
 void emu_wx_f64(const double* Z, double* Wa, const double* Wb, double* X, int64_t n, const double* coef) {
   apply_wx<double>(Z, Wa, Wb, X, n, coef);
@@ -671,14 +725,28 @@ double emu_time_upd_mixed(EMU_ARGS, const double* Q, float* Vout, float* Zout, c
   return apply_time_upd<float, double>(EMU_P, Q, (const float*)nullptr, (const float*)nullptr, Vout, Zout, coef,
                                        false);
 }
-double emu_sym_spec_f64(EMU_ARGS, const double* z, double* out, int force_fft) {
-  return apply_spec<double, MV_DOT>(EMU_P, z, out, (const double*)nullptr, force_fft != 0);
+// form: 0 direct (short p), 1 N-point circulant + skew-circulant, 2 zero-padded 2N-point
+double emu_sym_spec_f64(EMU_ARGS, const double* z, double* out, int form) {
+  return apply_spec<double, MV_DOT>(EMU_P, z, out, (const double*)nullptr, form != 0, nullptr, form == 2);
 }
-double emu_sym_spec_f32(EMU_ARGS, const float* z, float* out, int force_fft) {
-  return apply_spec<float, MV_DOT>(EMU_P, z, out, (const float*)nullptr, force_fft != 0);
+double emu_sym_spec_f32(EMU_ARGS, const float* z, float* out, int form) {
+  return apply_spec<float, MV_DOT>(EMU_P, z, out, (const float*)nullptr, form != 0, nullptr, form == 2);
 }
-double emu_resid_spec_f64(EMU_ARGS, const double* u, const double* f, double* r, int force_fft) {
-  return apply_spec<double, MV_RESID>(EMU_P, u, r, f, force_fft != 0);
+double emu_resid_spec_f64(EMU_ARGS, const double* u, const double* f, double* r, int form) {
+  return apply_spec<double, MV_RESID>(EMU_P, u, r, f, form != 0, nullptr, form == 2);
+}
+// u <- (u_zero ? 0 : u) + s sum_i y[i] Z_i (Z_i = zs + i*n, FP32), then r = Y(f - A u): the
+// refinement step of the mixed path in one pass (FFT form)
+double emu_resid_upd_f64(EMU_ARGS, double* u, const double* f, double* r, const float* zs, int k, const double* y,
+                         double s, int u_zero, int two_n) {
+  const Problem P = EMU_P;
+  IterUpd up{};
+  for (int i = 0; i < ZB_MAX; ++i) up.z[i] = i < k ? zs + (int64_t)i * P.N * P.M : nullptr;
+  up.k = k;
+  up.y = y;
+  up.s = &s;
+  up.u_zero = u_zero;
+  return apply_spec<double, MV_RESID>(P, u, r, f, true, &up, two_n != 0);
 }
 
 }  // extern "C"

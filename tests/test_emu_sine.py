@@ -102,27 +102,27 @@ SPEC_CASES = [("frac", 1, 31, 32), ("heat", 2, 7, 16), ("cn", 2, 5, 8), ("frac",
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("force_fft", [False, True])
+@pytest.mark.parametrize("form", ["direct", "cs", "2n"])
 @pytest.mark.parametrize("kind,dim,m,N", SPEC_CASES)
-def test_sym_spec(kind, dim, m, N, force_fft, dtype):
+def test_sym_spec(kind, dim, m, N, form, dtype):
     prob = prob_of(kind, dim, m, N)
     sysm = O.from_problem(prob)
     z = np.random.default_rng(31).standard_normal(prob.n)
-    got, dot = E.sym_spec(prob, z, dtype, force_fft)
+    got, dot = E.sym_spec(prob, z, dtype, form=form)
     ref = ref_sym_sine(prob, sysm, z)
     assert rel(got, ref) < TOL[dtype] * 50
     zz = z.astype(dtype).astype(np.float64)
     assert abs(dot - np.dot(ref, zz)) <= TOL[dtype] * 50 * np.linalg.norm(ref) * np.linalg.norm(zz)
 
 
-@pytest.mark.parametrize("force_fft", [False, True])
+@pytest.mark.parametrize("form", ["direct", "cs", "2n"])
 @pytest.mark.parametrize("kind,dim,m,N", SPEC_CASES[:5])
-def test_resid_spec(kind, dim, m, N, force_fft):
+def test_resid_spec(kind, dim, m, N, form):
     prob = prob_of(kind, dim, m, N)
     sysm = O.from_problem(prob)
     rng = np.random.default_rng(41)
     u, f = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
-    r, s = E.resid_spec(prob, u, f, force_fft)
+    r, s = E.resid_spec(prob, u, f, form=form)
     ut, ft = tm(prob, u), tm(prob, f)
     ref = mm(prob, O.time_reverse((ft - U(prob, O.bltt_apply(sysm, U(prob, ut).reshape(N, -1)))).reshape(N, -1)))
     assert rel(r, ref) < 1e-12
@@ -190,3 +190,80 @@ def test_rhs_mm(N, M):
     ref = f.reshape(M, N)[:, ::-1].ravel()
     assert np.array_equal(b, ref)
     assert abs(s - np.dot(ref, ref)) < 1e-12 * np.dot(ref, ref)
+
+
+def sine_minres_stored(prob, f, tol_eta, maxit, K=16):
+    """FP32 sweep as the mixed path runs it: every Z_j kept, no direction
+    vectors; the iterate is combined from the Z_j at the end."""
+    n = prob.n
+    fs = U(prob, f)
+    b = mm(prob, O.time_reverse(fs.reshape(prob.N, -1)))
+    st = E.State()
+    hist = np.zeros(maxit + 2)
+    om, y = np.zeros(2 * K), np.zeros(K)
+    Vc = b.astype(np.float32)
+    _, Z0, d = E.time_upd(prob, Vc, None, None, [1.0, 0, 0], False, np.float32, write_v=False)
+    Zs = [Z0.astype(np.float32)]
+    st.scalar(E.State.SC_START, d, hist, zb=(om, y))
+    Vp = np.zeros(n, np.float32)
+    j = 0
+    for j in range(1, min(maxit, K - 1) + 1):
+        q, dq = E.sym_spec(prob, Zs[-1], np.float32, force_fft=True)
+        st.scalar(E.State.SC_DELTA, dq)
+        Vn, Zn, dv = E.time_upd(prob, q, Vc, Vp if j > 1 else Vc, st.coef_v(), True, np.float32)
+        st.scalar(E.State.SC_BETA, dv, hist, zb=(om, y))
+        Vp, Vc = Vc, Vn.astype(np.float32)
+        Zs.append(Zn.astype(np.float32))
+        if abs(st.eta) / st.eta0 <= tol_eta or st.status == 1:
+            break
+    u = E.combine_f32(np.zeros(n), Zs[:j], y[:j], 1.0)
+    return U(prob, tm(prob, u)), j, hist[:j + 1]
+
+
+@pytest.mark.parametrize("kind,dim,m,N,alpha", [("frac", 1, 15, 32, 0.01), ("heat", 2, 7, 16, 0.05)])
+def test_stored_basis_sweep_matches_explicit(kind, dim, m, N, alpha):
+    """The stored-basis iterate equals the one the explicit direction
+    recurrence builds (FP32 sweep to 1e-4), and the oracle's iterate at the
+    same iteration."""
+    prob = prob_of(kind, dim, m, N, alpha, gamma=0.5)
+    sysm = O.from_problem(prob)
+    f = W.rhs_normal(prob, 12)
+    x1, it1, h1 = sine_minres(prob, f, 1e-4, 30, np.float32)
+    x2, it2, h2 = sine_minres_stored(prob, f, 1e-4, 30)
+    assert it1 == it2 and np.allclose(h1, h2, rtol=1e-6)
+    assert np.linalg.norm(x1 - x2) <= 1e-5 * np.linalg.norm(x1)
+    ores = O.pminres(sysm, f, 1e-30, it1)
+    assert np.linalg.norm(x2 - ores.x.ravel()) <= 1e-4 * np.linalg.norm(ores.x)
+
+
+def test_stored_basis_cap():
+    """A sweep stops after K - 1 iterations when the pool is full; the iterate
+    is still the MINRES iterate at that step."""
+    prob = prob_of("frac", 1, 15, 32, 0.5, gamma=0.5)
+    sysm = O.from_problem(prob)
+    f = W.rhs_normal(prob, 13)
+    x, it, h = sine_minres_stored(prob, f, 1e-12, 30, K=4)
+    assert it == 3
+    ores = O.pminres(sysm, f, 1e-30, 3)
+    assert np.linalg.norm(x - ores.x.ravel()) <= 1e-4 * np.linalg.norm(ores.x)
+
+
+@pytest.mark.parametrize("two_n", [False, True])
+@pytest.mark.parametrize("u_zero", [False, True])
+@pytest.mark.parametrize("kind,dim,m,N", [("frac", 1, 31, 32), ("cn", 2, 5, 8), ("frac", 2, 7, 64)])
+def test_resid_with_update(kind, dim, m, N, u_zero, two_n):
+    """The mixed path's fused refinement step: u <- u + s sum_i y_i Z_i, then
+    r = Y(f - A u), against the same two steps in FP64 on the host."""
+    prob = prob_of(kind, dim, m, N)
+    sysm = O.from_problem(prob)
+    rng = np.random.default_rng(51)
+    u, f = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
+    Zs = [rng.standard_normal(prob.n).astype(np.float32) for _ in range(3)]
+    y, s = np.array([0.5, -1.25, 2.0]), 0.37
+    unew, r, ss = E.resid_upd(prob, u, f, Zs, y, s, u_zero, two_n)
+    uref = (0.0 if u_zero else u) + s * sum(yi * z.astype(np.float64) for yi, z in zip(y, Zs))
+    assert np.allclose(unew, uref, rtol=1e-14, atol=1e-14)
+    ut, ft = tm(prob, uref), tm(prob, f)
+    ref = mm(prob, O.time_reverse((ft - U(prob, O.bltt_apply(sysm, U(prob, ut).reshape(N, -1)))).reshape(N, -1)))
+    assert rel(r, ref) < 1e-12
+    assert abs(ss - np.dot(ref, ref)) < 1e-10 * np.dot(ref, ref)
