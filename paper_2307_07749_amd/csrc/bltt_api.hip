@@ -80,6 +80,7 @@ struct bltt_handle {
   double* partials = nullptr;
   int64_t partials_cap = 0;
   double* red_scratch = nullptr;  // first stage of long reductions (2 * red_half)
+  int64_t max_blocks = 1024;      // workgroups of the persistent sine-basis kernels
   int64_t red_half = 0;
   double* partials_aux = nullptr;  // time pass: spatial part of the next <q, z>
   int64_t np_aux = 0;
@@ -291,6 +292,7 @@ int64_t partials_needed(const bltt_handle* h) {
   need = std::max(need, fft_blocks<T, FK_DSTX>(2 * (h->m[0] + 1), h->n / h->m[0]));
   need = std::max(need, h->n / h->m[0]);  // one partial per x-line (residual stencil pass)
   need = std::max(need, fft_blocks<T, FK_TIME>((int)h->N, h->M));
+  need = std::max(need, fft_tiles<T, FK_SPEC>((int)h->N, h->M));  // sine-basis kernels
   return need;
 }
 
@@ -368,8 +370,7 @@ int matvec(bltt_handle* h, int mode, int term, const T* z, T* out, const T* fin,
       // FP32: N-point circulant + skew-circulant form (one wavefront per line pair)
       ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
       HIPCHK(launch_matvec_cs<T>((int)h->N, mode, const_cast<T*>(z), out, fin, h->M, cs_tables<T>(h), up,
-                                 h->partials, h->stream));
-      *np = fft_blocks<T, FK_TIME>((int)h->N, h->M);
+                                 h->partials, h->max_blocks, np, h->stream));
       return BLTT_OK;
     }
     if (mode == MV_RESID && term == TERM_STENCIL) {
@@ -637,13 +638,13 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   if ((rc = ensure_hist(h, (int64_t)maxit + 2))) return rc;
   const TimeTables<T> tt = time_tables<T>(h, false);
   const int L = (int)h->N;
-  const int64_t npt = fft_blocks<T, FK_TIME>(L, h->M);
+  int64_t npt = 0;
   // v_1 = b, z_1 = P^{-1} b, beta_1 = sqrt(<b, z_1>)
   {
     const bool copy = (const void*)bsrc != (const void*)Vc;
     ProfScope ps(h, BLTT_K_TIME, n * (sizeof(TB) + (copy ? 2.0 : 1.0) * sizeof(T)));
     HIPCHK(launch_time_upd<T, TB>(L, false, bsrc, nullptr, nullptr, copy ? Vc : nullptr, Zc, h->M, tt, bcoef,
-                                  h->partials, s));
+                                  h->partials, h->max_blocks, &npt, s));
   }
   if ((rc = scalar(h, SC_START, npt, h->hist_dev, false, zbasis))) return rc;
   if ((rc = read_state(h))) return rc;
@@ -659,7 +660,8 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     {
       // at j = 1 there is no v_0: V2 = V1 with a zero coefficient
       ProfScope ps(h, BLTT_K_TIME, (j > 1 ? 5.0 : 4.0) * n * sizeof(T));
-      HIPCHK(launch_time_upd<T, T>(L, true, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, h->M, tt, coef_v, h->partials, s));
+      HIPCHK(launch_time_upd<T, T>(L, true, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, h->M, tt, coef_v, h->partials,
+                                   h->max_blocks, &npt, s));
     }
     if ((rc = scalar(h, SC_BETA, npt, h->hist_dev, false, zbasis))) return rc;
     if (!zbasis) {
@@ -819,6 +821,16 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   }
 
   std::call_once(g_config_once, [] { g_config_err = configure_kernels(); });
+  {
+    // persistent kernels: two workgroups per compute unit resident, two rounds
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+      delete h;
+      return BLTT_EHIP;
+    }
+    h->max_blocks = 4 * (int64_t)cus;
+  }
   if (g_config_err != hipSuccess) {
     delete h;
     return BLTT_EHIP;

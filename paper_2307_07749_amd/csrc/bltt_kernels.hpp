@@ -29,10 +29,12 @@ namespace bltt {
 
 // Workgroup size of each line-FFT kernel class.  NL = TPB / G lines of length
 // L (G = L/16 threads per line) share a workgroup.
-enum FftKernel { FK_TIME = 0, FK_MV = 1, FK_DSTS = 2, FK_DSTX = 3 };
+// FK_SPEC: the sine-basis time-line kernels (mode-major lines, one wavefront
+// per line pair): smaller workgroups schedule independently of each other.
+enum FftKernel { FK_TIME = 0, FK_MV = 1, FK_DSTS = 2, FK_DSTX = 3, FK_SPEC = 4 };
 template <typename T, int FK>
 constexpr int tpb_fft() {
-  return sizeof(T) == 4 ? 512 : 256;
+  return FK == FK_SPEC ? 256 : (sizeof(T) == 4 ? 512 : 256);
 }
 template <typename T, int FK>
 constexpr int lines_per_block(int L) {
@@ -52,6 +54,13 @@ inline int64_t fft_blocks(int L, int64_t units) {
   const int64_t nb = (units + per - 1) / per;
   return (nb + 7) / 8 * 8;
 }
+// tiles of 2*NL sine modes of the sine-basis kernels
+template <typename T, int FK>
+BLTT_HD int64_t fft_tiles(int L, int64_t units) {
+  const int64_t per = 2 * (int64_t)lines_per_block<T, FK>(L);
+  return (units + per - 1) / per;
+}
+
 // minimum waves per SIMD requested from the compiler for the FFT kernels
 // (1: no constraint beyond the workgroup size)
 template <typename T>
@@ -364,15 +373,14 @@ struct MatvecCSTables {
 };
 
 template <typename T, int L, int MODE, class Ctx>
-BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restrict__ out,
-                            const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
-                            double* __restrict__ partials) {
-  constexpr int TPB = tpb_fft<T, FK_TIME>();
+BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
+                              const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up) {
+  constexpr int TPB = tpb_fft<T, FK_SPEC>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L;
   using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
   const int tid = ctx.tid, c = tid / G, g = tid % G;
-  const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
+  const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
   const int64_t la = iac * N, lb = ibc * N, sa = ia * N, sb = ib * N;
@@ -468,8 +476,21 @@ BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restri
       }
     }
   }
-  const double sum = block_sum<TPB>(ctx, red, part);
-  if (tid == 0) partials[ctx.bid] = sum;
+  // the next tile's first exchange must not overwrite z before every lane has read it
+  F::xsync(ctx);
+  return part;
+}
+
+// One tile per workgroup (a loop over tiles lets the compiler keep the
+// loop-invariant twiddle and spectrum loads live across tiles, which costs
+// half the occupancy here); one partial sum per workgroup.
+template <typename T, int L, int MODE, class Ctx>
+BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restrict__ out,
+                            const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
+                            double* __restrict__ partials) {
+  const double part = matvec_cs_tile<T, L, MODE>(ctx, lds, ctx.bid, z, out, fin, M, tb, up);
+  const double sum = block_sum<tpb_fft<T, FK_SPEC>()>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = sum;
 }
 
 // matvec, direct form for short p (ptaps <= 8): one thread per spatial point
@@ -1022,17 +1043,17 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 // FP64 reads it back from Vout (its own stores) or from Q.
 // ---------------------------------------------------------------------------
 template <typename T, int L, typename TQ, bool FULL, bool MM, class Ctx>
-BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restrict__ Q,
-                           const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
-                           T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
-                           const double* __restrict__ coef, double* __restrict__ partials) {
-  constexpr int TPB = tpb_fft<T, FK_TIME>();
+BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __restrict__ Q,
+                             const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
+                             T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
+                             const double* __restrict__ coef) {
+  constexpr int TPB = tpb_fft<T, FK_SPEC>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr bool KEEP = sizeof(T) == 4;
   using F = LineFft<T, L, NL, !MM, LAST_PAIRED>;
   const T invN = T(1) / T(L);
   const int tid = ctx.tid, c = MM ? tid / G : tid % NL, g = MM ? tid % G : tid / NL;
-  const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
+  const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
   // element (i, n): time-major n*M + i, or mode-major i*N + n (N = L)
@@ -1107,8 +1128,30 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
     }
     part += (double)in.re * (double)z.re + (double)in.im * (double)z.im;
   }
-  const double sum = block_sum<TPB>(ctx, red, part);
-  if (tid == 0) partials[ctx.bid] = sum;
+  return part;
+}
+
+// FP32 runs persistently (workgroup b takes tiles b, b + nbx, ...); FP64,
+// whose registers allow one wavefront per SIMD, one tile per workgroup.  One
+// partial sum of <vhat, zhat> per workgroup.
+template <typename T>
+constexpr bool upd_persistent() { return sizeof(T) == 4; }
+
+template <typename T, int L, typename TQ, bool FULL, bool MM, class Ctx>
+BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restrict__ Q,
+                           const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
+                           T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
+                           const double* __restrict__ coef, double* __restrict__ partials) {
+  const int64_t ntiles = fft_tiles<T, FK_SPEC>(L, M);
+  double part = 0.0;
+  if constexpr (upd_persistent<T>()) {
+    for (int64_t tile = ctx.bid; tile < ntiles; tile += ctx.nbx)
+      part += time_upd_tile<T, L, TQ, FULL, MM>(ctx, lds, tile, Q, V1, V2, Vout, Zout, M, tb, coef);
+  } else {
+    part = time_upd_tile<T, L, TQ, FULL, MM>(ctx, lds, ctx.bid, Q, V1, V2, Vout, Zout, M, tb, coef);
+  }
+  const double sum = block_sum<tpb_fft<T, FK_SPEC>()>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = sum;
 }
 
 // ---------------------------------------------------------------------------

@@ -3,6 +3,8 @@
 // refinement update of the iterate.  The four N-entry tables (twiddles, the
 // two spectra, e^{i pi n/N}) are staged in LDS when they fit beside the
 // exchange buffers.
+#include <algorithm>
+
 #include "launchers.hpp"
 
 namespace bltt {
@@ -10,24 +12,24 @@ namespace bltt {
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
 template <typename T, int L>
-constexpr size_t cs_lds_base() { return fft_lds_bytes<T, FK_TIME>(L); }
+constexpr size_t cs_lds_base() { return fft_lds_bytes<T, FK_SPEC>(L); }
 template <typename T, int L>
 constexpr bool cs_stage() { return cs_lds_base<T, L>() + 4 * (size_t)L * sizeof(cx<T>) <= LDS_LIMIT; }
 template <typename T, int L>
 constexpr size_t cs_lds_bytes() { return cs_lds_base<T, L>() + (cs_stage<T, L>() ? 4 * (size_t)L * sizeof(cx<T>) : 0); }
 
 template <typename T, int L, int MODE>
-__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_TIME>()), waves_fft<T>()) void k_matvec_cs(
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_matvec_cs(
     T* z, T* __restrict__ out, const T* __restrict__ fin, int64_t M, MatvecCSTables<T> tb, IterUpd up,
     double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int NL = tpb_fft<T, FK_TIME>() / (L / fft_V(L));
+  constexpr int NL = tpb_fft<T, FK_SPEC>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
   if constexpr (cs_stage<T, L>()) {
     cx<T>* tabs = reinterpret_cast<cx<T>*>(smem + cs_lds_base<T, L>());
-    for (int i = ctx.tid; i < L; i += tpb_fft<T, FK_TIME>()) {
+    for (int i = ctx.tid; i < L; i += tpb_fft<T, FK_SPEC>()) {
       tabs[i] = tb.tw[i];
       tabs[L + i] = tb.chat[i];
       tabs[2 * L + i] = tb.shat[i];
@@ -44,25 +46,28 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
 
 template <typename T, int L>
 static hipError_t go_cs(int mode, T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb,
-                        const IterUpd& up, double* partials, hipStream_t s) {
-  const int64_t blocks = fft_blocks<T, FK_TIME>(L, M);
+                        const IterUpd& up, double* partials, int64_t max_blocks, int64_t* nparts, hipStream_t s) {
+  (void)max_blocks;  // one tile per workgroup
+  const int64_t blocks = fft_tiles<T, FK_SPEC>(L, M);
   const size_t lds = cs_lds_bytes<T, L>();
+  if (nparts) *nparts = blocks;
   if (mode == MV_DOT)
-    hipLaunchKernelGGL((k_matvec_cs<T, L, MV_DOT>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s, z,
+    hipLaunchKernelGGL((k_matvec_cs<T, L, MV_DOT>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds, s, z,
                        out, fin, M, tb, up, partials);
   else
-    hipLaunchKernelGGL((k_matvec_cs<T, L, MV_RESID>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s, z,
+    hipLaunchKernelGGL((k_matvec_cs<T, L, MV_RESID>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds, s, z,
                        out, fin, M, tb, up, partials);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_matvec_cs(int L, int mode, T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb,
-                            const IterUpd& up, double* partials, hipStream_t s) {
+                            const IterUpd& up, double* partials, int64_t max_blocks, int64_t* nparts,
+                            hipStream_t s) {
   if (up.k < 0 || up.k > ZB_MAX || (up.k > 0 && mode != MV_RESID)) return hipErrorInvalidValue;
   switch (L) {
 #define BLTT_CASE(LL) \
-  case LL: return go_cs<T, LL>(mode, z, out, fin, M, tb, up, partials, s);
+  case LL: return go_cs<T, LL>(mode, z, out, fin, M, tb, up, partials, max_blocks, nparts, s);
     BLTT_CASE(2) BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64)
     BLTT_CASE(128) BLTT_CASE(256) BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
 #undef BLTT_CASE
@@ -71,9 +76,11 @@ hipError_t launch_matvec_cs(int L, int mode, T* z, T* out, const T* fin, int64_t
 }
 
 template hipError_t launch_matvec_cs<float>(int, int, float*, float*, const float*, int64_t,
-                                            const MatvecCSTables<float>&, const IterUpd&, double*, hipStream_t);
+                                            const MatvecCSTables<float>&, const IterUpd&, double*, int64_t, int64_t*,
+                                            hipStream_t);
 template hipError_t launch_matvec_cs<double>(int, int, double*, double*, const double*, int64_t,
-                                             const MatvecCSTables<double>&, const IterUpd&, double*, hipStream_t);
+                                             const MatvecCSTables<double>&, const IterUpd&, double*, int64_t,
+                                             int64_t*, hipStream_t);
 
 template <typename T, int L>
 static hipError_t attr_cs() {

@@ -1,44 +1,72 @@
 // Lanczos update fused with the time pass of the preconditioner, for MINRES in
 // sine coordinates (mode-major vectors): one workgroup per 2*NL sine modes.
+#include <algorithm>
+
 #include "launchers.hpp"
 
 namespace bltt {
 
+constexpr size_t LDS_LIMIT_SPEC = 160 * 1024;
+template <typename T, int L>
+constexpr size_t upd_lds_base() { return fft_lds_bytes<T, FK_SPEC>(L); }
+// twiddles and the two alpha-spectra staged in LDS
+// (measured slower for the persistent time pass than cached global reads: off)
+template <typename T, int L>
+constexpr bool upd_stage() { return false; }
+template <typename T, int L>
+constexpr size_t upd_lds_bytes() { return upd_lds_base<T, L>() + (upd_stage<T, L>() ? 3 * (size_t)L * sizeof(cx<T>) : 0); }
+
 template <typename T, int L, typename TQ, bool FULL>
-__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_TIME>()), waves_fft<T>()) void k_time_upd(
+__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_time_upd(
     const TQ* __restrict__ Q, const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
     T* __restrict__ Zout, int64_t M, TimeTables<T> tb, const double* __restrict__ coef,
     double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int NL = tpb_fft<T, FK_TIME>() / (L / fft_V(L));
+  constexpr int NL = tpb_fft<T, FK_SPEC>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, false, LAST_PAIRED>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
+  if constexpr (upd_stage<T, L>()) {
+    cx<T>* tabs = reinterpret_cast<cx<T>*>(smem + upd_lds_base<T, L>());
+    for (int i = ctx.tid; i < L; i += tpb_fft<T, FK_SPEC>()) {
+      tabs[i] = tb.tw[i];
+      tabs[L + i] = tb.sigma[i];
+      tabs[2 * L + i] = tb.rho[i];
+    }
+    __syncthreads();
+    tb.tw = tabs;
+    tb.sigma = tabs + L;
+    tb.rho = tabs + 2 * L;
+  }
   time_upd_body<T, L, TQ, FULL, true>(ctx, reinterpret_cast<cx<T>*>(smem), red, Q, V1, V2, Vout, Zout, M, tb, coef,
                                       partials);
 }
 
 template <typename T, typename TQ, int L>
 static hipError_t go_upd(bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
-                         const TimeTables<T>& tb, const double* coef, double* partials, hipStream_t s) {
-  const int64_t blocks = fft_blocks<T, FK_TIME>(L, M);
-  const size_t lds = fft_lds_bytes<T, FK_TIME>(L);
+                         const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
+                         int64_t* nparts, hipStream_t s) {
+  const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
+  const int64_t blocks = upd_persistent<T>() ? std::max<int64_t>(1, std::min(tiles, max_blocks)) : tiles;
+  const size_t lds = upd_lds_bytes<T, L>();
+  if (nparts) *nparts = blocks;
   if (full)
-    hipLaunchKernelGGL((k_time_upd<T, L, TQ, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s, Q,
+    hipLaunchKernelGGL((k_time_upd<T, L, TQ, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds, s, Q,
                        V1, V2, Vout, Zout, M, tb, coef, partials);
   else
-    hipLaunchKernelGGL((k_time_upd<T, L, TQ, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_TIME>()), lds, s,
+    hipLaunchKernelGGL((k_time_upd<T, L, TQ, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds, s,
                        Q, V1, V2, Vout, Zout, M, tb, coef, partials);
   return hipGetLastError();
 }
 
 template <typename T, typename TQ>
 hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
-                           const TimeTables<T>& tb, const double* coef, double* partials, hipStream_t s) {
+                           const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
+                           int64_t* nparts, hipStream_t s) {
   if (full && (!V1 || !V2)) return hipErrorInvalidValue;
   switch (L) {
 #define BLTT_CASE(LL) \
-  case LL: return go_upd<T, TQ, LL>(full, Q, V1, V2, Vout, Zout, M, tb, coef, partials, s);
+  case LL: return go_upd<T, TQ, LL>(full, Q, V1, V2, Vout, Zout, M, tb, coef, partials, max_blocks, nparts, s);
     BLTT_CASE(2) BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64)
     BLTT_CASE(128) BLTT_CASE(256) BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
 #undef BLTT_CASE
@@ -48,7 +76,8 @@ hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* 
 
 #define BLTT_INST(T, TQ)                                                                                      \
   template hipError_t launch_time_upd<T, TQ>(int, bool, const TQ*, const T*, const T*, T*, T*, int64_t,      \
-                                             const TimeTables<T>&, const double*, double*, hipStream_t);
+                                             const TimeTables<T>&, const double*, double*, int64_t, int64_t*,  \
+                                             hipStream_t);
 BLTT_INST(float, float)
 BLTT_INST(float, double)
 BLTT_INST(double, double)
@@ -56,7 +85,7 @@ BLTT_INST(double, double)
 
 template <typename T, typename TQ, int L>
 static hipError_t attr_upd() {
-  const int bytes = (int)fft_lds_bytes<T, FK_TIME>(L);
+  const int bytes = (int)upd_lds_bytes<T, L>();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, true>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;

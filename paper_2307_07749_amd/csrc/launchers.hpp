@@ -39,9 +39,11 @@ hipError_t launch_time_prec(int L, T* x, int64_t M, const TimeTables<T>& tb, hip
 
 // sine coordinates: vhat = cq Q (+ cv V1 + cvp V2 when full) -> Vout (optional),
 // Zout = P^{-1} vhat (time pass), per-workgroup partial sums of <vhat, Zout>
+// (persistent: at most max_blocks workgroups, *nparts receives the partial count)
 template <typename T, typename TQ>
 hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
-                           const TimeTables<T>& tb, const double* coef, double* partials, hipStream_t s);
+                           const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
+                           int64_t* nparts, hipStream_t s);
 
 // up: refinement update of the iterate z (MV_RESID with TERM_SPEC only; k = 0 for none)
 template <typename T>
@@ -53,7 +55,8 @@ hipError_t launch_matvec_fft(int L, int mode, int term, T* z, T* out, const T* f
 // u <- u + s sum y_i Z_i when up.k > 0, partial sums of ||out||^2)
 template <typename T>
 hipError_t launch_matvec_cs(int L, int mode, T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb,
-                            const IterUpd& up, double* partials, hipStream_t s);
+                            const IterUpd& up, double* partials, int64_t max_blocks, int64_t* nparts,
+                            hipStream_t s);
 
 template <typename T>
 hipError_t launch_matvec_short(int mode, const T* z, T* out, const T* fin, int64_t M,

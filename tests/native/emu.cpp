@@ -468,10 +468,12 @@ struct UpdRun {
   struct R {
     static void run(const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M, const TimeTables<T>& tb,
                     const double* coef, double* partials, bool full) {
-      constexpr int NL = lines_per_block<T, FK_TIME>(L);
+      constexpr int NL = lines_per_block<T, FK_SPEC>(L);
       using Ft = LineFft<T, L, NL, false, LAST_PAIRED>;
-      run_grid(tpb_fft<T, FK_TIME>(), (int)fft_blocks<T, FK_TIME>(L, M), 1, fft_lds_bytes<T, FK_TIME>(L),
-               [&](HostCtx& c, unsigned char* lds) {
+      // fewer workgroups than tiles: every workgroup walks several tiles
+      const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
+      run_grid(tpb_fft<T, FK_SPEC>(), (int)(upd_persistent<T>() ? std::min<int64_t>(tiles, 3) : tiles), 1,
+               fft_lds_bytes<T, FK_SPEC>(L), [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Ft::LDS_ELEMS);
                  if (full)
                    time_upd_body<T, L, TQ, true, true>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout, M,
@@ -489,7 +491,7 @@ double apply_time_upd(const Problem& P, const TQ* Q, const T* V1, const T* V2, T
                       bool full) {
   HostTables<T> ht(P);
   TimeTables<T> tt = time_tables<T>(P, ht);
-  std::vector<double> partials((size_t)fft_blocks<T, FK_TIME>((int)P.N, P.M), 0.0);
+  std::vector<double> partials((size_t)fft_tiles<T, FK_SPEC>((int)P.N, P.M), 0.0);
   with_L<UpdRun<T, TQ>::template R>((int)P.N, Q, V1, V2, Vout, Zout, P.M, tt, coef, partials.data(), full);
   double s = 0.0;
   for (double v : partials) s += v;
@@ -503,10 +505,10 @@ struct MvSpecRun {
   struct R {
     static void run(T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
                     double* partials) {
-      constexpr int NL = lines_per_block<T, FK_TIME>(L);
+      constexpr int NL = lines_per_block<T, FK_SPEC>(L);
       using Fm = LineFft<T, L, NL, false, LAST_DEFAULT>;
-      run_grid(tpb_fft<T, FK_TIME>(), (int)fft_blocks<T, FK_TIME>(L, M), 1, fft_lds_bytes<T, FK_TIME>(L),
-               [&](HostCtx& c, unsigned char* lds) {
+      run_grid(tpb_fft<T, FK_SPEC>(), (int)fft_tiles<T, FK_SPEC>(L, M), 1,
+               fft_lds_bytes<T, FK_SPEC>(L), [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
                  matvec_cs_body<T, L, MODE>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M, tb, up, partials);
                });
@@ -591,7 +593,7 @@ double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force
     tb.qtaps = qtaps;
     IterUpd up{};
     if (upd) up = *upd;
-    std::vector<double> partials((size_t)fft_blocks<T, FK_TIME>((int)P.N, P.M));
+    std::vector<double> partials((size_t)fft_tiles<T, FK_SPEC>((int)P.N, P.M), 0.0);
     with_L<MvSpecRun<T, MODE>::template R>((int)P.N, const_cast<T*>(z), out, fin, P.M, tb, up, partials.data());
     for (double v : partials) dot += v;
   }
