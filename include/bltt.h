@@ -199,6 +199,53 @@ int bltt_profile_enable(bltt_handle *h, int32_t enable);
 int bltt_profile_read(bltt_handle *h, int32_t kernel_class, int64_t *launches, double *total_ms,
                       double *bytes);
 
+/*
+ * Batched solves: many independent instances of uneven size and blocks, each
+ * with nrhs right-hand sides, solved together (mixed precision, sine basis:
+ * the BLTT_MIXED path of bltt_pminres).  Instances with the same N, dim, m and
+ * h form a shape class whose systems share every launch of a phase (per-
+ * instance tables, one partial sum per tile and system); classes run on
+ * streams of their own.  Each MINRES iteration of a class is replayed from a
+ * HIP graph captured once per position in the sweep; at setup a few timed
+ * launches choose each class's workgroup size.  An FP32 sweep stops after at
+ * most 5 iterations (the refinement loop continues with a new sweep).
+ *
+ * bltt_setup_batched -- validate and prepare count instances.
+ *   blk[i], N[i], M[i], alpha[i]   instance i, as for bltt_setup (p and q
+ *                                  copied; N[i] and 2(m_d+1) powers of two)
+ *   nrhs                           right-hand sides per instance (>= 1)
+ *   opt                            NULL or precision BLTT_MIXED, basis
+ *                                  BLTT_BASIS_SINE (others: BLTT_EUNSUPPORTED);
+ *                                  inner_tol and max_refine as for bltt_setup
+ *   stream                         hipStream_t the solves are ordered on
+ *   out                            receives the batch handle
+ * Errors: as bltt_setup; BLTT_ENOMEM when the workspace of all classes does
+ * not fit (split the batch).
+ *
+ * bltt_pminres_batched -- solve all count*nrhs systems to tol.  System
+ * g = i*nrhs + r is instance i with right-hand side r:
+ *   f_dev[g], u_dev[g]   FP64 device vectors of length N[i]*M[i] (host
+ *                        arrays of device pointers); u_dev[g] receives the
+ *                        solution and must not overlap any f_dev
+ *   iters[g]             host, may be NULL: inner iterations of system g
+ *   hist                 host, may be NULL: count*nrhs rows of maxit+1
+ *                        residual estimates, as bltt_pminres
+ *   info[g]              host, may be NULL: per-system report (solve_ms is
+ *                        the wall time of the whole batched call)
+ * Returns BLTT_OK when every system reached tol, BLTT_NOCONV if one did not,
+ * or the first error.
+ *
+ * bltt_batch_classes -- number of shape classes and (tpb, may be NULL, room
+ * for that many) the workgroup size the setup chose for each.
+ */
+typedef struct bltt_batch bltt_batch;
+int bltt_setup_batched(const bltt_blocks *blk, const int64_t *N, const int64_t *M, const double *alpha,
+                       int32_t count, int32_t nrhs, const bltt_options *opt, void *stream, bltt_batch **out);
+int bltt_pminres_batched(bltt_batch *b, const double *const *f_dev, double tol, int32_t maxit,
+                         double *const *u_dev, int32_t *iters, double *hist, bltt_info *info);
+int bltt_batch_classes(const bltt_batch *b, int32_t *nclasses, int32_t *tpb);
+void bltt_destroy_batched(bltt_batch *b);
+
 /* Release all device memory and tables of the handle (NULL is a no-op). */
 void bltt_destroy(bltt_handle *h);
 

@@ -83,6 +83,18 @@ def load() -> ctypes.CDLL:
     L.bltt_profile_read.restype = ctypes.c_int
     L.bltt_destroy.argtypes = [P]
     L.bltt_destroy.restype = None
+    L.bltt_setup_batched.argtypes = [ctypes.POINTER(Blocks), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.POINTER(Options), P, ctypes.POINTER(P)]
+    L.bltt_setup_batched.restype = ctypes.c_int
+    L.bltt_pminres_batched.argtypes = [P, ctypes.POINTER(P), ctypes.c_double, ctypes.c_int32, ctypes.POINTER(P),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(Info)]
+    L.bltt_pminres_batched.restype = ctypes.c_int
+    L.bltt_batch_classes.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.bltt_batch_classes.restype = ctypes.c_int
+    L.bltt_destroy_batched.argtypes = [P]
+    L.bltt_destroy_batched.restype = None
     L.bltt_strerror.argtypes = [ctypes.c_int]
     L.bltt_strerror.restype = ctypes.c_char_p
     L.bltt_version.restype = ctypes.c_char_p
@@ -214,3 +226,89 @@ class Solver:
     def apply_space(self, x, y=None):
         """y = (I_N (x) U) x, the orthonormal sine transform of every time slice."""
         return self._apply("bltt_apply_space", x, y)
+
+
+class Batch:
+    """Many independent instances (uneven N, grid, blocks, alpha), each with
+    ``nrhs`` right-hand sides, solved together (wraps a bltt_batch).
+
+    ``problems``: objects with dim, m, h, p, q, alpha (like workloads.Problem).
+    System ``g = i*nrhs + r`` is instance i with right-hand side r."""
+
+    def __init__(self, problems, nrhs: int = 1, inner_tol: float = 0.0, max_refine: int = 0, stream=None):
+        L = load()
+        self._L = L
+        self.count = len(problems)
+        self.nrhs = int(nrhs)
+        self.sizes = []
+        blks = (Blocks * self.count)()
+        self._keep = []
+        N = (ctypes.c_int64 * self.count)()
+        M = (ctypes.c_int64 * self.count)()
+        A = (ctypes.c_double * self.count)()
+        for i, pr in enumerate(problems):
+            p = np.ascontiguousarray(pr.p, dtype=np.float64)
+            q = np.ascontiguousarray(pr.q, dtype=np.float64)
+            self._keep += [p, q]
+            b = blks[i]
+            b.dim = pr.dim
+            for d in range(3):
+                b.m[d] = pr.m[d] if d < pr.dim else 1
+                b.h[d] = pr.h[d] if d < pr.dim else 1.0
+            b.p = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            b.q = q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            N[i] = len(p)
+            M[i] = int(np.prod(pr.m))
+            A[i] = float(pr.alpha)
+            self.sizes += [N[i] * M[i]] * self.nrhs
+        opt = Options(MIXED, inner_tol, max_refine, 0.0, SINE)
+        handle = ctypes.c_void_p()
+        rc = L.bltt_setup_batched(blks, N, M, A, self.count, self.nrhs, ctypes.byref(opt),
+                                  ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle))
+        _check(rc)
+        self._h = handle
+
+    def classes(self):
+        """Workgroup size the setup chose for each shape class."""
+        n = ctypes.c_int32(0)
+        _check(self._L.bltt_batch_classes(self._h, ctypes.byref(n), None))
+        t = (ctypes.c_int32 * max(n.value, 1))()
+        _check(self._L.bltt_batch_classes(self._h, ctypes.byref(n), t))
+        return [int(t[i]) for i in range(n.value)]
+
+    def pminres(self, fs, tol: float, maxit: int, us=None):
+        """fs: list of count*nrhs float64 CUDA tensors.  Returns
+        (us, iters, hists, infos, status)."""
+        import torch
+        nsys = self.count * self.nrhs
+        if len(fs) != nsys:
+            raise ValueError(f"expected {nsys} right-hand sides")
+        if us is None:
+            us = [torch.empty_like(f) for f in fs]
+        for f, u, n in zip(fs, us, self.sizes):
+            for x in (f, u):
+                if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64
+                        and x.is_contiguous() and x.numel() == n):
+                    raise ValueError(f"expected contiguous CUDA float64 tensors of {n} elements")
+        Pa = ctypes.c_void_p * nsys
+        fp = Pa(*[f.data_ptr() for f in fs])
+        up = Pa(*[u.data_ptr() for u in us])
+        iters = (ctypes.c_int32 * nsys)()
+        hist = np.zeros((nsys, maxit + 1), dtype=np.float64)
+        infos = (Info * nsys)()
+        rc = self._L.bltt_pminres_batched(self._h, fp, float(tol), int(maxit), up, iters,
+                                          hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), infos)
+        _check(rc, allow=(OK, NOCONV))
+        it = [int(iters[g]) for g in range(nsys)]
+        return us, it, [hist[g, : it[g] + 1].copy() for g in range(nsys)], [infos[g].as_dict() for g in range(nsys)], rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.bltt_destroy_batched(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

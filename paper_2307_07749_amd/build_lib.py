@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbltt.so")
 
-SOURCES = ["kern_cs.hip", "kern_spec.hip", "kern_time.hip", "kern_matvec.hip", "kern_dst.hip", "kern_misc.hip", "bltt_api.hip"]
+SOURCES = ["kern_cs.hip", "kern_spec.hip", "kern_time.hip", "kern_matvec.hip", "kern_dst.hip", "kern_misc.hip", "bltt_api.hip", "kern_batch.hip", "bltt_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

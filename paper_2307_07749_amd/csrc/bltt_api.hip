@@ -55,7 +55,6 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-std::once_flag g_config_once;
 hipError_t g_config_err = hipSuccess;
 
 }  // namespace
@@ -820,7 +819,7 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
     return BLTT_EASSUMPTION;
   }
 
-  std::call_once(g_config_once, [] { g_config_err = configure_kernels(); });
+  g_config_err = configure_kernels_once();
   {
     // persistent kernels: two workgroups per compute unit resident, two rounds
     int dev = 0, cus = 0;

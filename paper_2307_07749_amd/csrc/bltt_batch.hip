@@ -1,0 +1,728 @@
+// Batched solver: many independent instances of uneven shape (N, grid),
+// blocks and alpha, each with nrhs right-hand sides, solved together in the
+// sine basis with FP32 MINRES sweeps inside FP64 refinement (the mixed path of
+// bltt_pminres).  Systems are grouped into shape classes (same N, dim, m, h);
+// each class keeps its vectors back to back and runs every phase as one launch
+// over all of its systems, with per-instance tables.  Classes run on their own
+// streams, so small shapes overlap the large ones.  One MINRES iteration of a
+// class (matvec, two scalar phases, update + time pass) is captured once as a
+// HIP graph per position in the sweep and replayed.  At setup a short timing
+// of the iteration kernels picks each class's workgroup size (tile width).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "bltt.h"
+#include "host_tables.hpp"
+#include "launchers.hpp"
+
+using namespace bltt;
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int BT_POOL = 6;  // stored Z vectors per system: sweeps of at most 5 iterations
+
+struct BatchClass {
+  // shape
+  int64_t N = 0, M = 0, n = 0;
+  int dim = 0, m[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int S = 0, I = 0;
+  std::vector<int> sys_global;   // class system -> global system index
+  std::vector<int> inst_global;  // class instance -> global instance index
+  std::vector<int> sys_inst;     // class system -> class instance
+  // tuning
+  int tpb = 256;
+  int64_t T = 0;   // tiles per system of the FP32 kernels
+  int64_t T2 = 0;  // tiles per system of the FP64 residual
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  // device data
+  BatchTabs tabs{};
+  cx<double>* tw_dst[3] = {nullptr, nullptr, nullptr};
+  InstParams* ip_dev = nullptr;
+  int* sys_inst_dev = nullptr;
+  int* active_dev = nullptr;
+  SolverState* states = nullptr;
+  SolverState* states_host = nullptr;
+  int* act_host = nullptr;         // pinned staging of the active flags
+  double** uptr_host = nullptr;    // pinned staging of the caller's u pointers
+  int sweeps = 0;                  // sweeps completed in the current solve
+  double* partials = nullptr;
+  int64_t partials_cap = 0;
+  double* zb = nullptr;
+  double* hist_dev = nullptr;
+  int64_t hist_stride = 0;
+  float* Q = nullptr;
+  float* V[3] = {nullptr, nullptr, nullptr};
+  ZPool pool{};
+  double* F64 = nullptr;
+  double* R64 = nullptr;
+  double** uptr_dev = nullptr;
+  std::vector<hipGraphExec_t> graphs;  // per sweep position j (1..BT_POOL-1)
+  std::vector<hipGraph_t> graph_defs;
+};
+
+}  // namespace
+
+struct bltt_batch {
+  int count = 0, nrhs = 0;
+  bltt_options opt{};
+  hipStream_t stream = nullptr;
+  std::vector<BatchClass> cls;
+  std::vector<void*> allocs;
+  double* coef_one = nullptr;
+  double setup_ms = 0.0;
+};
+
+#define HIPCHK(...)                         \
+  do {                                      \
+    hipError_t e_ = (__VA_ARGS__);          \
+    if (e_ != hipSuccess) return BLTT_EHIP; \
+  } while (0)
+
+namespace {
+
+template <typename T>
+int balloc(bltt_batch* b, T** ptr, size_t count) {
+  void* p = nullptr;
+  if (hipMalloc(&p, count * sizeof(T) + 64) != hipSuccess) {
+    (void)hipGetLastError();
+    return BLTT_ENOMEM;
+  }
+  b->allocs.push_back(p);
+  *ptr = static_cast<T*>(p);
+  return BLTT_OK;
+}
+
+template <typename T>
+int bupload(bltt_batch* b, T** dst, const std::vector<T>& src) {
+  int rc = balloc(b, dst, src.size());
+  if (rc) return rc;
+  HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return BLTT_OK;
+}
+
+template <typename T>
+std::vector<cx<T>> to_cx(const std::vector<host::cd>& v) {
+  std::vector<cx<T>> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = mkc<T>((T)v[i].real(), (T)v[i].imag());
+  return o;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+BatchVec bvec(BatchClass& c) {
+  BatchVec bv;
+  bv.n = c.n;
+  bv.M = c.M;
+  bv.T = c.T;
+  bv.S = c.S;
+  bv.active = c.active_dev;
+  bv.states = c.states;
+  return bv;
+}
+
+DstTables<double> dst_tab(const BatchClass& c, int d) {
+  DstTables<double> tb;
+  tb.tw = c.tw_dst[d];
+  tb.m = c.m[d];
+  tb.nrm = 1.0 / std::sqrt(2.0 * (c.m[d] + 1));
+  return tb;
+}
+
+VupdStencil<double> no_stencil(const BatchClass& c) {
+  VupdStencil<double> st{};
+  st.z = nullptr;
+  st.qtaps = 0;
+  st.grid.dim = c.dim;
+  for (int d = 0; d < 3; ++d) {
+    st.grid.m[d] = c.m[d];
+    st.grid.inv_h2[d] = 0.0;
+  }
+  st.N = (int)c.N;
+  st.R = c.M / c.m[0];
+  return st;
+}
+
+// (I x U) on the time-major vector of one system: in -> out (x-lines), then
+// the strided dimensions in place on out (all systems of the class when
+// out covers them: slices are independent)
+hipError_t space_x(bltt_batch* b, BatchClass& c, const double* in, double* out, int64_t nsys) {
+  const int Lx = 2 * (c.m[0] + 1);
+  return launch_dst_x<double>(Lx, KIND_VUPD, in, nullptr, nullptr, nullptr, nullptr, out, nsys * c.n / c.m[0],
+                              dst_tab(c, 0), b->coef_one, nullptr, no_stencil(c), c.stream);
+}
+hipError_t space_strided_all(BatchClass& c, double* x) {
+  for (int k = 1; k < c.dim; ++k) {
+    int64_t S = 1;
+    for (int e = 0; e < k; ++e) S *= c.m[e];
+    const hipError_t e = launch_dst_strided<double>(2 * (c.m[k] + 1), x, (int64_t)c.S * c.n / c.m[k], S,
+                                                    dst_tab(c, k), c.stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// one MINRES iteration of a class at sweep position j (1-based)
+hipError_t enqueue_iteration(BatchClass& c, int j, double inner_tol) {
+  const BatchVec bv = bvec(c);
+  const int L = (int)c.N;
+  float* Vc = c.V[(j - 1) % 3];
+  float* Vp = c.V[(j + 1) % 3];
+  float* Vn = c.V[j % 3];
+  float* Zc = c.pool.z[j - 1];
+  float* Zn = c.pool.z[j];
+  hipError_t e;
+  if ((e = launch_bt(BT_MATVEC, L, c.tpb, nullptr, nullptr, nullptr, nullptr, Zc, c.Q, bv, c.tabs, c.partials,
+                     c.stream)) != hipSuccess)
+    return e;
+  if ((e = launch_bt_scalar(SC_DELTA, bv, c.partials, c.T, nullptr, 0, nullptr, BT_POOL, inner_tol, BT_POOL - 1,
+                            c.stream)) != hipSuccess)
+    return e;
+  if ((e = launch_bt(BT_UPD, L, c.tpb, c.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, nullptr, bv, c.tabs, c.partials,
+                     c.stream)) != hipSuccess)
+    return e;
+  return launch_bt_scalar(SC_BETA, bv, c.partials, c.T, c.hist_dev, c.hist_stride, c.zb, BT_POOL, inner_tol,
+                          BT_POOL - 1, c.stream);
+}
+
+int run_graph(BatchClass& c, int j, double inner_tol) {
+  if ((int)c.graphs.size() <= j) {
+    c.graphs.resize((size_t)j + 1, nullptr);
+    c.graph_defs.resize((size_t)j + 1, nullptr);
+  }
+  if (!c.graphs[(size_t)j]) {
+    // inner_tol is a kernel argument: the graphs are rebuilt when it changes
+    HIPCHK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = enqueue_iteration(c, j, inner_tol);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c.stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) return BLTT_EHIP;
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return BLTT_EHIP;
+    }
+    c.graph_defs[(size_t)j] = g;
+    c.graphs[(size_t)j] = x;
+  }
+  HIPCHK(hipGraphLaunch(c.graphs[(size_t)j], c.stream));
+  return BLTT_OK;
+}
+
+void drop_graphs(BatchClass& c) {
+  for (auto& x : c.graphs)
+    if (x) (void)hipGraphExecDestroy(x);
+  for (auto& g : c.graph_defs)
+    if (g) (void)hipGraphDestroy(g);
+  c.graphs.clear();
+  c.graph_defs.clear();
+}
+
+int read_states(BatchClass& c) {
+  HIPCHK(hipMemcpyAsync(c.states_host, c.states, sizeof(SolverState) * (size_t)c.S, hipMemcpyDeviceToHost, c.stream));
+  return BLTT_OK;
+}
+
+// Pick the workgroup size of the FP32 iteration kernels: a few timed launches of
+// the matvec and the update on the class's own buffers (states zeroed, every
+// system active; the values computed are discarded).
+int autotune(BatchClass& c) {
+  const int cands[2] = {256, 512};
+  float best = 1e30f;
+  int best_tpb = 256;
+  hipEvent_t a = nullptr, z = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&z));
+  for (int tpb : cands) {
+    if (tpb == 512 && c.N < 32) continue;
+    c.tpb = tpb;
+    c.T = bt_tiles((int)c.N, tpb, c.M);
+    const BatchVec bv = bvec(c);
+    const int L = (int)c.N;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIPCHK(hipEventRecord(a, c.stream));
+      HIPCHK(launch_bt(BT_MATVEC, L, tpb, nullptr, nullptr, nullptr, nullptr, c.pool.z[0], c.Q, bv, c.tabs,
+                       c.partials, c.stream));
+      HIPCHK(launch_bt(BT_UPD, L, tpb, c.Q, c.V[0], c.V[1], c.V[2], c.pool.z[1], nullptr, bv, c.tabs, c.partials,
+                       c.stream));
+      HIPCHK(hipEventRecord(z, c.stream));
+      HIPCHK(hipEventSynchronize(z));
+      HIPCHK(hipEventElapsedTime(&ms, a, z));
+    }
+    if (ms < best) {
+      best = ms;
+      best_tpb = tpb;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(z);
+  c.tpb = best_tpb;
+  c.T = bt_tiles((int)c.N, c.tpb, c.M);
+  return BLTT_OK;
+}
+
+int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const double* alpha) {
+  int rc;
+  const int64_t N = c.N, M = c.M, S = c.S, I = c.I;
+  c.n = N * M;
+  HIPCHK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+  // shared tables
+  std::vector<cx<float>> tw32 = to_cx<float>(host::twiddles((int)N));
+  std::vector<cx<float>> om32 = to_cx<float>(host::half_roots(N));
+  const std::vector<double> mu = host::lap_eigs(c.dim, c.m, c.h);
+  std::vector<float> mu32(mu.begin(), mu.end());
+  cx<float>* p_tw = nullptr;
+  cx<float>* p_om = nullptr;
+  float* p_mu32 = nullptr;
+  double* p_mu64 = nullptr;
+  cx<double>* p_tw2 = nullptr;
+  if ((rc = bupload(b, &p_tw, tw32)) || (rc = bupload(b, &p_om, om32)) || (rc = bupload(b, &p_mu32, mu32)) ||
+      (rc = bupload(b, &p_mu64, mu)) || (rc = bupload(b, &p_tw2, to_cx<double>(host::twiddles((int)(2 * N))))))
+    return rc;
+  for (int d = 0; d < c.dim; ++d)
+    if ((rc = bupload(b, &c.tw_dst[d], to_cx<double>(host::twiddles(2 * (c.m[d] + 1)))))) return rc;
+  // per-instance tables
+  std::vector<cx<float>> sig, rho, chat, shat;
+  std::vector<cx<double>> phat;
+  std::vector<InstParams> ip((size_t)I);
+  for (int k = 0; k < I; ++k) {
+    const int gi = c.inst_global[(size_t)k];
+    const std::vector<double> p(blk[gi].p, blk[gi].p + N), q(blk[gi].q, blk[gi].q + N);
+    auto app = [](std::vector<cx<float>>& dst, const std::vector<host::cd>& src) {
+      for (const auto& v : src) dst.push_back(mkc<float>((float)v.real(), (float)v.imag()));
+    };
+    app(sig, host::alpha_spectrum(p, alpha[gi]));
+    app(rho, host::alpha_spectrum(q, alpha[gi]));
+    app(chat, host::circulant_spectrum(p, false));
+    app(shat, host::circulant_spectrum(p, true));
+    for (const auto& v : host::matvec_spectrum(p)) phat.push_back(mkc<double>(v.real(), v.imag()));
+    int qt = 0;
+    for (int64_t j = 0; j < N; ++j)
+      if (q[(size_t)j] != 0.0) qt = (int)j + 1;
+    ip[(size_t)k].l2a = (float)(std::log2(alpha[gi]) / (double)N);
+    ip[(size_t)k].qtaps = qt;
+    for (int j = 0; j < 4; ++j) {
+      ip[(size_t)k].q32[j] = (float)(j < qt ? q[(size_t)j] : 0.0);
+      ip[(size_t)k].q64[j] = j < qt ? q[(size_t)j] : 0.0;
+    }
+  }
+  cx<float>*p_sig = nullptr, *p_rho = nullptr, *p_chat = nullptr, *p_shat = nullptr;
+  cx<double>* p_phat = nullptr;
+  if ((rc = bupload(b, &p_sig, sig)) || (rc = bupload(b, &p_rho, rho)) || (rc = bupload(b, &p_chat, chat)) ||
+      (rc = bupload(b, &p_shat, shat)) || (rc = bupload(b, &p_phat, phat)) || (rc = bupload(b, &c.ip_dev, ip)) ||
+      (rc = bupload(b, &c.sys_inst_dev, c.sys_inst)))
+    return rc;
+  c.tabs.tw = p_tw;
+  c.tabs.sigma = p_sig;
+  c.tabs.rho = p_rho;
+  c.tabs.chat = p_chat;
+  c.tabs.shat = p_shat;
+  c.tabs.omega = p_om;
+  c.tabs.mu32 = p_mu32;
+  c.tabs.tw2 = p_tw2;
+  c.tabs.phat = p_phat;
+  c.tabs.mu64 = p_mu64;
+  c.tabs.ip = c.ip_dev;
+  c.tabs.sys_inst = c.sys_inst_dev;
+  // per-system state
+  if ((rc = balloc(b, &c.active_dev, (size_t)S)) || (rc = balloc(b, &c.states, (size_t)S)) ||
+      (rc = balloc(b, &c.zb, (size_t)(3 * BT_POOL * S))))
+    return rc;
+  HIPCHK(hipMemset(c.states, 0, sizeof(SolverState) * (size_t)S));
+  HIPCHK(hipMemset(c.zb, 0, sizeof(double) * (size_t)(3 * BT_POOL * S)));
+  std::vector<int> ones((size_t)S, 1);
+  HIPCHK(hipMemcpy(c.active_dev, ones.data(), sizeof(int) * (size_t)S, hipMemcpyHostToDevice));
+  if (hipHostMalloc((void**)&c.states_host, sizeof(SolverState) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c.act_host, sizeof(int) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c.uptr_host, sizeof(double*) * (size_t)S, hipHostMallocDefault) != hipSuccess)
+    return BLTT_ENOMEM;
+  c.hist_stride = BT_POOL + 2;
+  if ((rc = balloc(b, &c.hist_dev, (size_t)(c.hist_stride * S)))) return rc;
+  // partial sums: the most tiles per system of any phase, for every system
+  const int64_t Tmax = std::max({bt_tiles((int)N, 256, M), fft_tiles<double, FK_MV>((int)(2 * N), M),
+                                 std::min<int64_t>(ew_blocks(c.n), 1024)});
+  c.partials_cap = Tmax * S;
+  if ((rc = balloc(b, &c.partials, (size_t)c.partials_cap))) return rc;
+  // vectors
+  const size_t ns = (size_t)(S * c.n);
+  if ((rc = balloc(b, &c.Q, ns))) return rc;
+  for (auto& v : c.V)
+    if ((rc = balloc(b, &v, ns))) return rc;
+  for (int i = 0; i < BT_POOL; ++i)
+    if ((rc = balloc(b, &c.pool.z[i], ns))) return rc;
+  for (int i = BT_POOL; i < ZB_MAX; ++i) c.pool.z[i] = nullptr;
+  if ((rc = balloc(b, &c.F64, ns)) || (rc = balloc(b, &c.R64, ns))) return rc;
+  if ((rc = balloc(b, &c.uptr_dev, (size_t)S))) return rc;
+  HIPCHK(hipMemsetAsync(c.Q, 0, ns * sizeof(float), c.stream));
+  for (auto& v : c.V) HIPCHK(hipMemsetAsync(v, 0, ns * sizeof(float), c.stream));
+  for (int i = 0; i < 2; ++i) HIPCHK(hipMemsetAsync(c.pool.z[i], 0, ns * sizeof(float), c.stream));
+  c.T2 = fft_tiles<double, FK_MV>((int)(2 * N), M);
+  if ((rc = autotune(c))) return rc;
+  HIPCHK(hipStreamSynchronize(c.stream));
+  return BLTT_OK;
+}
+
+void destroy_class(BatchClass& c) {
+  drop_graphs(c);
+  if (c.stream) (void)hipStreamDestroy(c.stream);
+  if (c.ev) (void)hipEventDestroy(c.ev);
+  if (c.states_host) (void)hipHostFree(c.states_host);
+  if (c.act_host) (void)hipHostFree(c.act_host);
+  if (c.uptr_host) (void)hipHostFree(c.uptr_host);
+}
+
+// per-system bookkeeping of one solve
+struct SysRun {
+  double bnorm = 0.0, relres = 0.0;
+  int iters = 0, outer = 0, status = BLTT_NOCONV;
+  bool active = true;
+  int hist_pos = 0;
+};
+
+enum Step { ST_START, ST_ITER, ST_RESID, ST_FINISH, ST_DONE };
+
+}  // namespace
+
+extern "C" {
+
+void bltt_destroy_batched(bltt_batch* b) {
+  if (!b) return;
+  for (auto& c : b->cls) {
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    destroy_class(c);
+  }
+  for (void* p : b->allocs) (void)hipFree(p);
+  delete b;
+}
+
+int bltt_setup_batched(const bltt_blocks* blk, const int64_t* N, const int64_t* M, const double* alpha,
+                       int32_t count, int32_t nrhs, const bltt_options* opt, void* stream, bltt_batch** out) {
+  const double t0 = now_ms();
+  if (!blk || !N || !M || !alpha || !out || count < 1 || nrhs < 1) return BLTT_EINVAL;
+  if (opt && opt->precision != BLTT_MIXED) return BLTT_EUNSUPPORTED;
+  if (opt && opt->basis != BLTT_BASIS_SINE) return BLTT_EUNSUPPORTED;
+  for (int i = 0; i < count; ++i) {
+    const bltt_blocks& bk = blk[i];
+    if (!bk.p || !bk.q || bk.dim < 1 || bk.dim > 3 || !(alpha[i] > 0.0 && alpha[i] <= 1.0)) return BLTT_EINVAL;
+    int64_t Mp = 1;
+    for (int d = 0; d < bk.dim; ++d) {
+      if (bk.m[d] < 1 || !(bk.h[d] > 0.0)) return BLTT_EINVAL;
+      if (!is_pow2(2 * ((int64_t)bk.m[d] + 1)) || 2 * (bk.m[d] + 1) < 4 || 2 * (bk.m[d] + 1) > 2048)
+        return BLTT_EUNSUPPORTED;
+      Mp *= bk.m[d];
+    }
+    if (Mp != M[i]) return BLTT_EINVAL;
+    if (!is_pow2(N[i]) || N[i] < 2 || N[i] > 2048) return BLTT_EUNSUPPORTED;
+    int qt = 0, pt = 0;
+    for (int64_t k = 0; k < N[i]; ++k) {
+      if (!std::isfinite(bk.p[k]) || !std::isfinite(bk.q[k])) return BLTT_EINVAL;
+      if (bk.q[k] != 0.0) qt = (int)k + 1;
+      if (bk.p[k] != 0.0) pt = (int)k + 1;
+    }
+    if (qt > 4) return BLTT_EUNSUPPORTED;
+    if (pt == 0 && qt == 0) return BLTT_EASSUMPTION;
+    double mu_min = 0.0, mu_max = 0.0;
+    for (int d = 0; d < bk.dim; ++d) {
+      const std::vector<double> e = host::lap_eigs_1d(bk.m[d], bk.h[d]);
+      mu_min += e.front();
+      mu_max += e.back();
+    }
+    const std::vector<double> p(bk.p, bk.p + N[i]), q(bk.q, bk.q + N[i]);
+    if (!(host::assumption_margin(p, q, mu_min, mu_max) > 0.0)) return BLTT_EASSUMPTION;
+  }
+  bltt_batch* b = new (std::nothrow) bltt_batch();
+  if (!b) return BLTT_ENOMEM;
+  b->count = count;
+  b->nrhs = nrhs;
+  b->stream = (hipStream_t)stream;
+  b->opt.precision = BLTT_MIXED;
+  b->opt.inner_tol = 1e-4;
+  b->opt.max_refine = 20;
+  b->opt.check_factor = 10.0;
+  b->opt.basis = BLTT_BASIS_SINE;
+  if (opt) {
+    if (opt->inner_tol > 0.0) b->opt.inner_tol = opt->inner_tol;
+    if (opt->max_refine > 0) b->opt.max_refine = opt->max_refine;
+  }
+  auto fail = [&](int code) {
+    bltt_destroy_batched(b);
+    return code;
+  };
+  if (configure_kernels_once() != hipSuccess) return fail(BLTT_EHIP);
+  {
+    std::vector<double> one = {1.0, 0.0, 0.0, 0.0};
+    if (int rc = bupload(b, &b->coef_one, one)) return fail(rc);
+  }
+  // shape classes
+  std::map<std::tuple<int64_t, int, int, int, int, double, double, double>, int> key;
+  for (int i = 0; i < count; ++i) {
+    const bltt_blocks& bk = blk[i];
+    auto k = std::make_tuple(N[i], bk.dim, bk.m[0], bk.dim > 1 ? bk.m[1] : 1, bk.dim > 2 ? bk.m[2] : 1, bk.h[0],
+                             bk.dim > 1 ? bk.h[1] : 1.0, bk.dim > 2 ? bk.h[2] : 1.0);
+    auto it = key.find(k);
+    int ci;
+    if (it == key.end()) {
+      ci = (int)b->cls.size();
+      key[k] = ci;
+      b->cls.emplace_back();
+      BatchClass& c = b->cls.back();
+      c.N = N[i];
+      c.M = M[i];
+      c.dim = bk.dim;
+      for (int d = 0; d < 3; ++d) {
+        c.m[d] = d < bk.dim ? bk.m[d] : 1;
+        c.h[d] = d < bk.dim ? bk.h[d] : 1.0;
+      }
+    } else {
+      ci = it->second;
+    }
+    BatchClass& c = b->cls[(size_t)ci];
+    c.inst_global.push_back(i);
+    for (int r = 0; r < nrhs; ++r) {
+      c.sys_global.push_back(i * nrhs + r);
+      c.sys_inst.push_back(c.I);
+    }
+    c.I += 1;
+    c.S += nrhs;
+  }
+  // largest classes first, so that their setup and launches go out early
+  std::sort(b->cls.begin(), b->cls.end(), [](const BatchClass& x, const BatchClass& y) {
+    return x.S * x.N * x.M > y.S * y.N * y.M;
+  });
+  for (auto& c : b->cls)
+    if (int rc = build_class(b, c, blk, alpha)) return fail(rc);
+  b->setup_ms = now_ms() - t0;
+  *out = b;
+  return BLTT_OK;
+}
+
+int bltt_batch_classes(const bltt_batch* b, int32_t* nclasses, int32_t* tpb) {
+  if (!b || !nclasses) return BLTT_EINVAL;
+  *nclasses = (int32_t)b->cls.size();
+  if (tpb)
+    for (size_t i = 0; i < b->cls.size(); ++i) tpb[i] = b->cls[i].tpb;
+  return BLTT_OK;
+}
+
+int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, int32_t maxit,
+                         double* const* u_dev, int32_t* iters, double* hist, bltt_info* info) {
+  const double t0 = now_ms();
+  if (!b || !f_dev || !u_dev || !(tol > 0.0) || maxit < 1) return BLTT_EINVAL;
+  const int nsys = b->count * b->nrhs;
+  for (int s = 0; s < nsys; ++s)
+    if (!f_dev[s] || !u_dev[s]) return BLTT_EINVAL;
+  // order after the caller's stream
+  hipEvent_t start = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(start, b->stream));
+  std::vector<std::vector<SysRun>> runs(b->cls.size());
+  std::vector<int> step(b->cls.size(), ST_START), pos(b->cls.size(), 0);
+  const double inner_tol = b->opt.inner_tol;
+  int rc = BLTT_OK;
+  for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+    BatchClass& c = b->cls[ci];
+    runs[ci].assign((size_t)c.S, SysRun{});
+    HIPCHK(hipStreamWaitEvent(c.stream, start, 0));
+    // fhat = (I x U) f per system (time-major into R64), transposed to mode-major F64
+    for (int s = 0; s < c.S; ++s) HIPCHK(space_x(b, c, f_dev[c.sys_global[(size_t)s]], c.R64 + (int64_t)s * c.n, 1));
+    HIPCHK(space_strided_all(c, c.R64));
+    HIPCHK(launch_bt_transpose(nullptr, c.R64, nullptr, c.F64, c.n, c.N, c.M, c.S, c.stream));
+    for (int s = 0; s < c.S; ++s) {
+      c.uptr_host[s] = u_dev[c.sys_global[(size_t)s]];
+      c.act_host[s] = 1;
+    }
+    c.sweeps = 0;
+    HIPCHK(hipMemcpyAsync(c.uptr_dev, c.uptr_host, sizeof(double*) * (size_t)c.S, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(c.active_dev, c.act_host, sizeof(int) * (size_t)c.S, hipMemcpyHostToDevice, c.stream));
+    // b = Y fhat (R64) and ||b|| per system
+    BatchVec bv = bvec(c);
+    int64_t bps = 0;
+    HIPCHK(launch_bt_rhs(c.F64, c.R64, c.N, bv, c.partials, &bps, c.stream));
+    HIPCHK(launch_bt_scalar(SC_NORM, bv, c.partials, bps, nullptr, 0, nullptr, BT_POOL, inner_tol, BT_POOL - 1,
+                            c.stream));
+    if ((rc = read_states(c))) return rc;
+  }
+  for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+    BatchClass& c = b->cls[ci];
+    HIPCHK(hipStreamSynchronize(c.stream));
+    for (int s = 0; s < c.S; ++s) {
+      SysRun& r = runs[ci][(size_t)s];
+      const double n2 = c.states_host[s].norm2;
+      if (!std::isfinite(n2)) return BLTT_ENAN;
+      r.bnorm = std::sqrt(n2);
+      r.relres = 1.0;
+      if (n2 == 0.0) {
+        r.active = false;
+        r.status = BLTT_OK;
+        r.relres = 0.0;
+      }
+      if (hist) hist[(size_t)c.sys_global[(size_t)s] * (size_t)(maxit + 1)] = 1.0;
+    }
+  }
+  std::vector<double> hbuf;
+  bool any = true;
+  while (any) {
+    any = false;
+    // enqueue one step of every running class
+    for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+      BatchClass& c = b->cls[ci];
+      if (step[ci] == ST_DONE) continue;
+      any = true;
+      BatchVec bv = bvec(c);
+      auto& R = runs[ci];
+      if (step[ci] == ST_START) {
+        bool live = false;
+        for (int s = 0; s < c.S; ++s) {
+          c.act_host[s] = R[(size_t)s].active ? 1 : 0;
+          live = live || R[(size_t)s].active;
+        }
+        if (!live) {
+          step[ci] = ST_FINISH;
+        } else {
+          // the stream is idle here (the previous step was collected)
+          HIPCHK(hipMemcpyAsync(c.active_dev, c.act_host, sizeof(int) * (size_t)c.S, hipMemcpyHostToDevice,
+                                c.stream));
+          HIPCHK(launch_bt(BT_START, (int)c.N, c.tpb, c.R64, nullptr, nullptr, c.V[0], c.pool.z[0], nullptr, bv,
+                           c.tabs, c.partials, c.stream));
+          HIPCHK(launch_bt_scalar(SC_START, bv, c.partials, c.T, c.hist_dev, c.hist_stride, c.zb, BT_POOL,
+                                  inner_tol, BT_POOL - 1, c.stream));
+          if ((rc = read_states(c))) return rc;
+          pos[ci] = 0;
+          step[ci] = ST_ITER;
+          continue;
+        }
+      }
+      if (step[ci] == ST_ITER) {
+        pos[ci] += 1;
+        if ((rc = run_graph(c, pos[ci], inner_tol))) return rc;
+        if ((rc = read_states(c))) return rc;
+        continue;
+      }
+      if (step[ci] == ST_RESID) {
+        int64_t T2 = 0;
+        const int u_zero = c.sweeps == 1 ? 1 : 0;  // the first sweep writes uhat without reading it
+        HIPCHK(launch_bt_resid((int)(2 * c.N), c.uptr_dev, c.R64, c.F64, bv, c.tabs, c.pool, c.zb, BT_POOL, u_zero,
+                               c.partials, &T2, c.stream));
+        HIPCHK(launch_bt_scalar(SC_NORM, bv, c.partials, T2, nullptr, 0, nullptr, BT_POOL, inner_tol, BT_POOL - 1,
+                                c.stream));
+        if ((rc = read_states(c))) return rc;
+        continue;
+      }
+      if (step[ci] == ST_FINISH) {
+        // systems that never ran (zero right-hand side) still hold scratch: zero them first
+        for (int s = 0; s < c.S; ++s)
+          if (R[(size_t)s].outer == 0)
+            HIPCHK(hipMemsetAsync(u_dev[c.sys_global[(size_t)s]], 0, sizeof(double) * (size_t)c.n, c.stream));
+        // u = (I x U) uhat: mode-major -> time-major R64, then the transforms into u
+        HIPCHK(launch_bt_transpose((const double* const*)c.uptr_dev, nullptr, nullptr, c.R64, c.n, c.M, c.N, c.S,
+                                   c.stream));
+        HIPCHK(space_strided_all(c, c.R64));
+        for (int s = 0; s < c.S; ++s)
+          HIPCHK(space_x(b, c, c.R64 + (int64_t)s * c.n, u_dev[c.sys_global[(size_t)s]], 1));
+        HIPCHK(hipEventRecord(c.ev, c.stream));
+        step[ci] = ST_DONE;
+        continue;
+      }
+    }
+    // collect: wait for each class's step and advance its state machine
+    for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+      BatchClass& c = b->cls[ci];
+      if (step[ci] == ST_DONE || step[ci] == ST_FINISH) continue;
+      HIPCHK(hipStreamSynchronize(c.stream));
+      auto& R = runs[ci];
+      if (step[ci] == ST_ITER) {
+        bool all_done = true;
+        for (int s = 0; s < c.S; ++s) {
+          if (!R[(size_t)s].active) continue;
+          const SolverState& st = c.states_host[s];
+          if (st.status == -3) return BLTT_ENAN;
+          if (st.status == -4) return BLTT_EBREAKDOWN;
+          all_done = all_done && st.done;
+        }
+        if (all_done || pos[ci] >= BT_POOL - 1) {
+          // append this sweep's histories
+          hbuf.assign((size_t)(c.hist_stride * c.S), 0.0);
+          HIPCHK(hipMemcpy(hbuf.data(), c.hist_dev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost));
+          for (int s = 0; s < c.S; ++s) {
+            SysRun& r = R[(size_t)s];
+            if (!r.active) continue;
+            const int k = c.states_host[s].iter;
+            for (int j = 1; j <= k && r.hist_pos + j <= maxit; ++j)
+              if (hist)
+                hist[(size_t)c.sys_global[(size_t)s] * (size_t)(maxit + 1) + (size_t)(r.hist_pos + j)] =
+                    hbuf[(size_t)(s * c.hist_stride + j)];
+            r.hist_pos += k;
+            r.iters += k;
+            r.outer += 1;
+          }
+          c.sweeps += 1;
+          step[ci] = ST_RESID;
+        }
+      } else if (step[ci] == ST_RESID) {
+        bool live = false;
+        for (int s = 0; s < c.S; ++s) {
+          SysRun& r = R[(size_t)s];
+          if (!r.active) continue;
+          const double rn = std::sqrt(c.states_host[s].norm2);
+          if (!std::isfinite(rn)) return BLTT_ENAN;
+          r.relres = rn / r.bnorm;
+          if (r.relres <= tol) {
+            r.status = BLTT_OK;
+            r.active = false;
+          } else if (r.outer >= b->opt.max_refine || r.iters >= maxit) {
+            r.status = BLTT_NOCONV;
+            r.active = false;
+          }
+          live = live || r.active;
+        }
+        step[ci] = live ? ST_START : ST_FINISH;
+      } else if (step[ci] == ST_START) {
+        for (int s = 0; s < c.S; ++s) {
+          if (!R[(size_t)s].active) continue;
+          if (c.states_host[s].status == -3) return BLTT_ENAN;
+          if (c.states_host[s].status == -4) return BLTT_EBREAKDOWN;
+        }
+      }
+    }
+  }
+  int worst = BLTT_OK;
+  for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+    BatchClass& c = b->cls[ci];
+    HIPCHK(hipStreamWaitEvent(b->stream, c.ev, 0));
+    for (int s = 0; s < c.S; ++s) {
+      const SysRun& r = runs[ci][(size_t)s];
+      const int g = c.sys_global[(size_t)s];
+      if (iters) iters[g] = r.iters;
+      if (info) {
+        info[g].iters_inner = r.iters;
+        info[g].iters_outer = r.outer;
+        info[g].true_relres = r.relres;
+        info[g].setup_ms = b->setup_ms;
+        info[g].c0 = 0.0;
+      }
+      if (r.status != BLTT_OK) worst = r.status;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(b->stream));
+  (void)hipEventDestroy(start);
+  const double ms = now_ms() - t0;
+  if (info)
+    for (int g = 0; g < nsys; ++g) info[g].solve_ms = ms;
+  return worst;
+}
+
+}  // extern "C"

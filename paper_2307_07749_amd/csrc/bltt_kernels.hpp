@@ -222,17 +222,21 @@ struct IterUpd {
 // consecutive points is one coalesced access; true = mode-major (element at
 // i*N + n, the sine-basis working layout), each line contiguous in memory and
 // owned by consecutive threads, and for N <= 512 by one wavefront.
+// Batched use: the stored vectors of system s start at up.z[i] + zoff, and
+// k >= 0 / y / sptr replace up.k / up.y / up.s (the pointer table stays in the
+// kernel arguments instead of a per-thread copy).
 template <typename T, int L, int MODE, int TERM, bool MM, class Ctx>
-BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restrict__ out,
-                             const T* __restrict__ fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
-                             double* __restrict__ partials) {
+BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
+                               const T* __restrict__ fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
+                               int64_t zoff = 0, int k = -1, const double* y = nullptr,
+                               const double* sptr = nullptr) {
   static_assert(!(MM && TERM == TERM_STENCIL), "the stencil needs the time-major layout");
   constexpr int TPB = tpb_fft<T, FK_MV>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L / 2, VH = V / 2;  // slots t < VH hold times g + t*s0 < N
   using F = LineFft<T, L, NL, !MM, LAST_DEFAULT>;
   const int tid = ctx.tid, c = MM ? tid / G : tid % NL, g = MM ? tid % G : tid / NL;
-  const int64_t ia = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, ib = ia + 1;
+  const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const T* za = z + ia;
   const T* zb = z + ib;
@@ -242,8 +246,10 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restr
   const int64_t ts = MM ? 1 : M;
   const int64_t la = MM ? iac * N : iac, lb = MM ? ibc * N : ibc;
   const int64_t sa = MM ? ia * N : ia, sb = MM ? ib * N : ib;
-  const bool upd = MODE == MV_RESID && up.k > 0;
-  const double us = upd ? *up.s : 0.0;
+  const int uk = k >= 0 ? k : up.k;
+  const double* uy = y ? y : up.y;
+  const bool upd = MODE == MV_RESID && uk > 0;
+  const double us = upd ? *(sptr ? sptr : up.s) : 0.0;
   cx<T> v[V], zin[VH];
 #pragma unroll
   for (int t = 0; t < VH; ++t) {
@@ -256,10 +262,10 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restr
     if (upd) {
       // refinement update of the iterate, written back before its use
       double da = 0.0, db = 0.0;
-      for (int i = 0; i < up.k; ++i) {
-        const double yi = up.y[i];
-        da += yi * (double)up.z[i][la + off];
-        db += yi * (double)up.z[i][lb + off];
+      for (int i = 0; i < uk; ++i) {
+        const double yi = uy[i];
+        da += yi * (double)up.z[i][zoff + la + off];
+        db += yi * (double)up.z[i][zoff + lb + off];
       }
       ra = T((double)ra + us * da);
       rb = T((double)rb + us * db);
@@ -347,8 +353,19 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restr
       }
     }
   }
-  const double s = block_sum<TPB>(ctx, red, part);
-  if (tid == 0) partials[ctx.bid] = s;
+  // a following tile of the same workgroup must not overwrite z in LDS early
+  F::xsync(ctx);
+  return part;
+}
+
+template <typename T, int L, int MODE, int TERM, bool MM, class Ctx>
+BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restrict__ out,
+                             const T* __restrict__ fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
+                             double* __restrict__ partials) {
+  const double part = matvec_fft_tile<T, L, MODE, TERM, MM>(ctx, lds, xcd_tile(ctx.bid, ctx.nbx), z, out, fin, M,
+                                                              tb, up);
+  const double s = block_sum<tpb_fft<T, FK_MV>()>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -372,10 +389,10 @@ struct MatvecCSTables {
   int qtaps;
 };
 
-template <typename T, int L, int MODE, class Ctx>
+// TPB: workgroup size (2*TPB/G modes per tile); the batched kernels choose it per shape
+template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), class Ctx>
 BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
                               const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up) {
-  constexpr int TPB = tpb_fft<T, FK_SPEC>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L;
   using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
@@ -1042,12 +1059,11 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 // in FP64 before rounding).  FP32 keeps vhat in registers for the dot product;
 // FP64 reads it back from Vout (its own stores) or from Q.
 // ---------------------------------------------------------------------------
-template <typename T, int L, typename TQ, bool FULL, bool MM, class Ctx>
+template <typename T, int L, typename TQ, bool FULL, bool MM, int TPB = tpb_fft<T, FK_SPEC>(), class Ctx>
 BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __restrict__ Q,
                              const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                              T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
                              const double* __restrict__ coef) {
-  constexpr int TPB = tpb_fft<T, FK_SPEC>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr bool KEEP = sizeof(T) == 4;
   using F = LineFft<T, L, NL, !MM, LAST_PAIRED>;
@@ -1319,7 +1335,8 @@ struct SolverState {
   double bsq;        // last reduced <vhat, zhat>
   int32_t iter;
   int32_t status;    // 0 running, 1 exact convergence (beta = 0), -3 NaN, -4 breakdown
-  int32_t pad[2];
+  int32_t done;      // batched sweeps: this system's sweep has stopped
+  int32_t pad;
 };
 
 // First stage of a long reduction: workgroup b sums partials
@@ -1463,6 +1480,215 @@ BLTT_HD void scalar_body(Ctx& ctx, double* red, int phase, SolverState* __restri
   st->iter += 1;
   if (hist) hist[st->iter] = fabs(st->eta) / st->eta0;
   if (bn == 0.0) st->status = 1;
+}
+
+}  // namespace bltt
+
+namespace bltt {
+
+// ---------------------------------------------------------------------------
+// Batched scalar phase: workgroup s updates system s of a batch from its own
+// range of partial sums (T per system).  Systems outside the outer loop
+// (active[s] = 0) and, in the Lanczos phases, systems whose sweep has stopped
+// are left alone.  After SC_BETA a sweep stops on |eta|/eta0 <= inner_tol, on
+// exact convergence, on error, or after cap iterations.
+// ---------------------------------------------------------------------------
+template <class Ctx>
+BLTT_HD void batch_scalar_body(Ctx& ctx, double* red, int phase, SolverState* __restrict__ states,
+                               const double* __restrict__ partials, int64_t T, double* __restrict__ hist,
+                               int64_t hist_stride, double* __restrict__ zb, int K, double inner_tol, int cap,
+                               const int* __restrict__ active) {
+  const int s = ctx.bid;
+  if (!active[s]) return;
+  SolverState* st = states + s;
+  if ((phase == SC_DELTA || phase == SC_BETA) && st->done) return;
+  ZBasis z;
+  z.om = zb ? zb + (int64_t)s * 3 * K : nullptr;
+  z.y = zb ? zb + (int64_t)s * 3 * K + 2 * K : nullptr;
+  z.K = zb ? K : 0;
+  scalar_body(ctx, red, phase, st, partials + (int64_t)s * T, T, (const double*)nullptr, 0,
+              hist ? hist + (int64_t)s * hist_stride : nullptr, z);
+  if (ctx.tid == 0) {
+    if (phase == SC_START) st->done = st->status != 0 ? 1 : 0;
+    if (phase == SC_BETA && (st->status != 0 || fabs(st->eta) <= inner_tol * st->eta0 || st->iter >= cap))
+      st->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched sine-basis bodies: S systems of one shape, vectors back to back
+// (system s at s*n), per-instance tables.  Workgroup g works on tile g % T of
+// system g / T and writes one partial sum per tile, so each system's
+// reductions stay separate; systems outside the outer loop (and, in the
+// Lanczos phases, systems whose sweep has stopped) skip their tiles.
+// ---------------------------------------------------------------------------
+struct InstParams {
+  float l2a;  // log2(alpha)/N
+  int qtaps;
+  float q32[4];
+  double q64[4];
+};
+struct BatchTabs {
+  const cx<float>* tw;     // N
+  const cx<float>* sigma;  // I*N, fft(alpha^{j/N} p_j) per instance
+  const cx<float>* rho;    // I*N
+  const cx<float>* chat;   // I*N, circulant / skew-circulant spectra of p
+  const cx<float>* shat;   // I*N
+  const cx<float>* omega;  // N
+  const float* mu32;       // M
+  const cx<double>* tw2;   // 2N (FP64 residual)
+  const cx<double>* phat;  // I*2N
+  const double* mu64;      // M
+  const InstParams* ip;    // I
+  const int* sys_inst;     // S: instance of each system
+};
+struct BatchVec {
+  int64_t n, M, T;        // elements per system, modes, tiles per system
+  int S;
+  const int* active;      // outer loop running (per system)
+  SolverState* states;    // per system
+};
+struct ZPool {
+  float* z[ZB_MAX];       // stored Z vectors (class base pointers)
+};
+
+BLTT_HD bool bt_skip(const BatchVec& bv, int s, bool lanczos) {
+  return !bv.active[s] || (lanczos && bv.states[s].done);
+}
+
+// time pass + Lanczos update (FULL) or start (cq = 1/||r|| of the system)
+template <int L, typename TQ, bool FULL, int TPB, class Ctx>
+BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q, const float* __restrict__ V1,
+                         const float* __restrict__ V2, float* __restrict__ Vout, float* __restrict__ Zout,
+                         const BatchVec& bv, const BatchTabs& bt, double* __restrict__ partials) {
+  constexpr int NL = TPB / (L / fft_V(L));
+  using F = LineFft<float, L, NL, false, LAST_PAIRED>;
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<float>) * F::LDS_ELEMS);
+  const int s = (int)(ctx.bid / bv.T);
+  const int64_t tile = ctx.bid % bv.T;
+  if (bt_skip(bv, s, FULL)) {
+    if (ctx.tid == 0) partials[ctx.bid] = 0.0;
+    return;
+  }
+  const int inst = bt.sys_inst[s];
+  const InstParams& ip = bt.ip[inst];
+  TimeTables<float> tb;
+  tb.tw = bt.tw;
+  tb.dinv = nullptr;
+  tb.d2 = nullptr;
+  tb.sigma = bt.sigma + (int64_t)inst * L;
+  tb.rho = bt.rho + (int64_t)inst * L;
+  tb.mu = bt.mu32;
+  tb.log2_alpha_over_N = ip.l2a;
+  for (int k = 0; k < 4; ++k) tb.q[k] = ip.q32[k];
+  tb.qtaps = ip.qtaps;
+  tb.aux = nullptr;
+  const int64_t o = (int64_t)s * bv.n;
+  const double* coef = FULL ? bv.states[s].coef_v : &bv.states[s].rinv;
+  const double part = time_upd_tile<float, L, TQ, FULL, true, TPB>(
+      ctx, reinterpret_cast<cx<float>*>(smem), tile, Q + o, FULL ? V1 + o : nullptr, FULL ? V2 + o : nullptr,
+      Vout ? Vout + o : nullptr, Zout + o, bv.M, tb, coef);
+  const double sum = block_sum<TPB>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = sum;
+}
+
+// FP32 sine-coordinate matvec (N-point form): Q = Y T Z, partial sums of <Q, Z>
+template <int L, int TPB, class Ctx>
+BLTT_HD void bt_cs_body(Ctx& ctx, unsigned char* smem, const float* __restrict__ Z, float* __restrict__ Q,
+                        const BatchVec& bv, const BatchTabs& bt, double* __restrict__ partials) {
+  constexpr int NL = TPB / (L / fft_V(L));
+  using F = LineFft<float, L, NL, false, LAST_DEFAULT>;
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<float>) * F::LDS_ELEMS);
+  const int s = (int)(ctx.bid / bv.T);
+  const int64_t tile = ctx.bid % bv.T;
+  if (bt_skip(bv, s, true)) {
+    if (ctx.tid == 0) partials[ctx.bid] = 0.0;
+    return;
+  }
+  const int inst = bt.sys_inst[s];
+  const InstParams& ip = bt.ip[inst];
+  MatvecCSTables<float> tb;
+  tb.tw = bt.tw;
+  tb.chat = bt.chat + (int64_t)inst * L;
+  tb.shat = bt.shat + (int64_t)inst * L;
+  tb.omega = bt.omega;
+  tb.mu = bt.mu32;
+  for (int k = 0; k < 4; ++k) tb.q[k] = ip.q32[k];
+  tb.qtaps = ip.qtaps;
+  const int64_t o = (int64_t)s * bv.n;
+  const double part = matvec_cs_tile<float, L, MV_DOT, TPB>(ctx, reinterpret_cast<cx<float>*>(smem), tile,
+                                                             const_cast<float*>(Z) + o, Q + o, nullptr, bv.M, tb,
+                                                             IterUpd{});
+  const double sum = block_sum<TPB>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = sum;
+}
+
+// FP64 refinement step per system: u_s <- u_s + rscale_s sum_i y_i Z_i (the
+// sweep's stored vectors, pool.z[i] + s*n), R = Y(F - A u_s) (2N-point form),
+// partial sums of ||R||^2.  T2 tiles per system.
+template <int L2, class Ctx>
+BLTT_HD void bt_resid_body(Ctx& ctx, unsigned char* smem, double* const* __restrict__ u, double* __restrict__ R,
+                           const double* __restrict__ Fh, const BatchVec& bv, const BatchTabs& bt,
+                           const IterUpd& pool, const double* __restrict__ zb, int K, int64_t T2,
+                           double* __restrict__ partials) {
+  constexpr int NL = tpb_fft<double, FK_MV>() / (L2 / fft_V(L2));
+  using F = LineFft<double, L2, NL, false, LAST_DEFAULT>;
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<double>) * F::LDS_ELEMS);
+  const int s = (int)(ctx.bid / T2);
+  const int64_t tile = ctx.bid % T2;
+  if (!bv.active[s]) {
+    if (ctx.tid == 0) partials[ctx.bid] = 0.0;
+    return;
+  }
+  const int inst = bt.sys_inst[s];
+  const InstParams& ip = bt.ip[inst];
+  MatvecTables<double> tb;
+  tb.tw = bt.tw2;
+  tb.phat = bt.phat + (int64_t)inst * L2;
+  tb.mu = bt.mu64;
+  for (int k = 0; k < 4; ++k) tb.q[k] = ip.q64[k];
+  tb.qtaps = ip.qtaps;
+  const int64_t o = (int64_t)s * bv.n;
+  const int k = bv.states[s].iter < K ? bv.states[s].iter : K - 1;
+  const double part = matvec_fft_tile<double, L2, MV_RESID, TERM_SPEC, true>(
+      ctx, reinterpret_cast<cx<double>*>(smem), tile, u[s], R + o, Fh + o, bv.M, tb, pool, o, k,
+      zb + (int64_t)s * 3 * K + 2 * K, &bv.states[s].rscale);
+  const double sum = block_sum<tpb_fft<double, FK_MV>()>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = sum;
+}
+
+// b = Y f per system (mode-major, each time line reversed) and per-system
+// partial sums of ||b||^2 (BPS workgroups per system)
+template <class Ctx>
+BLTT_HD void bt_rhs_body(Ctx& ctx, double* red, const double* __restrict__ f, double* __restrict__ b, int log2N,
+                         int64_t n, int64_t BPS, double* __restrict__ partials) {
+  const int64_t s = ctx.bid / BPS, blk = ctx.bid % BPS;
+  const int64_t N = (int64_t)1 << log2N;
+  const double* fs = f + s * n;
+  double* bs = b + s * n;
+  double part = 0.0;
+  for (int64_t e = blk * TPB_EW + ctx.tid; e < n; e += BPS * TPB_EW) {
+    const int64_t i = e >> log2N, t = e & (N - 1);
+    const double v = fs[(i << log2N) + (N - 1 - t)];
+    bs[e] = v;
+    part += v * v;
+  }
+  const double sum = block_sum<TPB_EW>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = sum;
+}
+
+// per-system transpose: out_s (C x R) = in_s^T; in and out are either pointer
+// arrays (per system) or a base with stride n
+template <class Ctx>
+BLTT_HD void bt_transpose_body(Ctx& ctx, double* tile, const double* const* __restrict__ in_p,
+                               const double* __restrict__ in_b, double* const* __restrict__ out_p,
+                               double* __restrict__ out_b, int64_t n, int64_t R, int64_t C, int64_t tiles) {
+  const int64_t s = ctx.bid / tiles;
+  Ctx c2 = ctx;
+  c2.bid = (int)(ctx.bid % tiles);
+  const double* in = in_p ? in_p[s] : in_b + s * n;
+  double* out = out_p ? out_p[s] : out_b + s * n;
+  transpose_body<double, false>(c2, tile, in, out, R, C);
 }
 
 }  // namespace bltt

@@ -1,5 +1,7 @@
 // Streaming kernels (right-hand side, MINRES direction/iterate update,
 // refinement casts) and the single-workgroup scalar kernel.
+#include <mutex>
+
 #include "launchers.hpp"
 
 namespace bltt {
@@ -209,6 +211,14 @@ hipError_t configure_matvec_kernels();
 hipError_t configure_dst_kernels();
 hipError_t configure_spec_kernels();
 hipError_t configure_cs_kernels();
+hipError_t configure_batch_kernels();
+
+hipError_t configure_kernels_once() {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] { err = configure_kernels(); });
+  return err;
+}
 
 hipError_t configure_kernels() {
   hipError_t e;
@@ -216,7 +226,8 @@ hipError_t configure_kernels() {
   if ((e = configure_matvec_kernels()) != hipSuccess) return e;
   if ((e = configure_dst_kernels()) != hipSuccess) return e;
   if ((e = configure_spec_kernels()) != hipSuccess) return e;
-  return configure_cs_kernels();
+  if ((e = configure_cs_kernels()) != hipSuccess) return e;
+  return configure_batch_kernels();
 }
 
 }  // namespace bltt

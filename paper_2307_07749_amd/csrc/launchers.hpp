@@ -70,8 +70,10 @@ hipError_t launch_dst_x(int L, int kind, const T* in, const T* v1, const T* v2, 
 template <typename T>
 hipError_t launch_dst_strided(int L, T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s);
 
-// one-time kernel attribute setup (dynamic LDS above 64 KiB)
+// kernel attribute setup (dynamic LDS above 64 KiB): configure_kernels_once
+// runs it once per process
 hipError_t configure_kernels();
+hipError_t configure_kernels_once();
 
 // streaming and scalar kernels
 template <typename T>
@@ -103,5 +105,26 @@ hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int
 template <typename T>
 hipError_t launch_combine(double* u, const ZList<T>& zl, const double* y, const double* sptr, int64_t n,
                           hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// batched sine-basis kernels (kern_batch.hip): S systems of one shape, vectors
+// back to back (system s at s*n), per-instance tables
+// ---------------------------------------------------------------------------
+enum { BT_START = 0, BT_UPD = 1, BT_MATVEC = 2 };
+
+// BT_START: Z = P^{-1} (rinv_s Q) with Q the FP64 residual, Vout = rinv_s Q;
+// BT_UPD: Vout = coef_v (Q, V1, V2), Z = P^{-1} Vout; BT_MATVEC: Qout = Y T Z.
+hipError_t launch_bt(int which, int L, int tpb, const void* Q, const float* V1, const float* V2, float* Vout,
+                     float* Z, float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials, hipStream_t s);
+int64_t bt_tiles(int L, int tpb, int64_t M);
+hipError_t launch_bt_resid(int L2, double* const* u, double* R, const double* Fh, const BatchVec& bv,
+                           const BatchTabs& bt, const ZPool& pool, const double* zb, int K, int u_zero,
+                           double* partials, int64_t* T2, hipStream_t s);
+hipError_t launch_bt_scalar(int phase, const BatchVec& bv, const double* partials, int64_t T, double* hist,
+                            int64_t hist_stride, double* zb, int K, double inner_tol, int cap, hipStream_t s);
+hipError_t launch_bt_rhs(const double* f, double* b, int64_t N, const BatchVec& bv, double* partials, int64_t* BPS,
+                         hipStream_t s);
+hipError_t launch_bt_transpose(const double* const* in_p, const double* in_b, double* const* out_p, double* out_b,
+                               int64_t n, int64_t R, int64_t C, int S, hipStream_t s);
 
 }  // namespace bltt
