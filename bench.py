@@ -89,12 +89,56 @@ def traffic_from_profiles(kernel: str, basis: str):
         return None
 
 
+def batched_bench(args) -> int:
+    """The uneven batched workload (64 2D fractional instances, M from {63^2,
+    127^2, 255^2}, N from {64, 256, 1024}, gamma ~ U(0.2, 0.8), alpha ~
+    logU(1e-3, 1e-1), 4 right-hand sides each, seeds 4000 + 4i + r): one step
+    is one batched solve of all 256 systems to tol.  Prints one JSON line."""
+    import torch
+    from paper_2307_07749_amd import bltt
+    from paper_2307_07749_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    params = W.batched_instances(64, 4)
+    probs = [W.fractional_l1(2, m, N, g, a) for (m, N, g, a) in params]
+    nrhs = 4
+    fs = [torch.from_numpy(W.rhs_normal(pr, 4000 + 4 * i + r)).cuda() for i, pr in enumerate(probs)
+          for r in range(nrhs)]
+    us = [torch.empty_like(f) for f in fs]
+    unknowns = sum(f.numel() for f in fs)
+    print(f"[bench] batched: {len(fs)} systems, {unknowns / 1e9:.2f} G unknowns", file=sys.stderr, flush=True)
+    b = bltt.Batch(probs, nrhs)
+    for _ in range(args.warmup):
+        b.pminres(fs, args.tol, args.maxit, us)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        _, iters, _, infos, rc = b.pminres(fs, args.tol, args.maxit, us)
+        print(f"[bench] batched step {k}: {infos[0]['solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    tpbs = b.classes()
+    b.close()
+    out = {"metric": "batched time-to-1e-8 solves, 64 uneven 2D fractional instances x 4 RHS",
+           "value": len(fs) * 1e3 / ms, "unit": "system-solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "batched64x4", "systems": len(fs), "unknowns": unknowns, "tol": args.tol,
+                      "classes": len(tpbs), "workgroup_sizes": tpbs},
+           "iters": {"min": min(iters), "max": max(iters)},
+           "max_true_relres": max(inf["true_relres"] for inf in infos), "status": int(rc),
+           "unknowns_per_s": unknowns * 1e3 / ms}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="frac2d_m511_n1024_g03")
+    ap.add_argument("--workload", default="frac2d_m511_n1024_g03",
+                    help="a named single workload, or batched64x4 for the uneven batched workload")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=300)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
@@ -107,6 +151,9 @@ def main() -> int:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the solver on one GPU only "
               f"(one MI355X holds the whole workload; see DESIGN.md for how it would shard)", file=sys.stderr)
         return 2
+
+    if args.workload == "batched64x4":
+        return batched_bench(args)
 
     import torch
     from paper_2307_07749_amd import bltt

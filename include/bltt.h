@@ -72,6 +72,15 @@ enum bltt_basis {
                                preconditioner application (Section 5.1)        */
 };
 
+/* Preconditioner.  BLTT_PRECOND_NONE runs plain MINRES on Y A u = Y f (the
+ * MINRES-I comparator of Section 5); it is supported with BLTT_FP64 and the
+ * sine basis.  The P_1 comparator of Section 5 is BLTT_PRECOND_ABAC with
+ * alpha = 1. */
+enum bltt_precond {
+  BLTT_PRECOND_ABAC = 0,    /* P_alpha = |C_alpha| (default)                       */
+  BLTT_PRECOND_NONE = 1     /* identity                                          */
+};
+
 /* Block description.  dim in {1,2,3}; m[d] interior points and h[d] spacing of
  * dimension d (d = 0 is x, the fastest); p and q are host arrays of length N
  * (copied during bltt_setup). */
@@ -93,6 +102,7 @@ typedef struct {
                              estimate |eta_j|/eta_0 <= check_factor*tol
                              (default 10)                                         */
   int32_t basis;          /* BLTT_BASIS_SINE (default) or BLTT_BASIS_PHYSICAL     */
+  int32_t precond;        /* BLTT_PRECOND_ABAC (default) or BLTT_PRECOND_NONE     */
 } bltt_options;
 
 /* Per-solve report. */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libbltt.so")
 
 FP64, MIXED, FP32 = 0, 1, 2
 SINE, PHYSICAL = 0, 1  # Krylov basis (bltt_basis)
+PRECOND_ABAC, PRECOND_NONE = 0, 1  # bltt_precond
 KERNEL_CLASSES = ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update", "resid64", "other"]
 OK, NOCONV = 0, 1
 STATUS = {0: "BLTT_OK", 1: "BLTT_NOCONV", -1: "BLTT_EINVAL", -2: "BLTT_EASSUMPTION", -3: "BLTT_ENAN",
@@ -40,7 +41,7 @@ class Blocks(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("check_factor", ctypes.c_double), ("basis", ctypes.c_int32)]
+                ("check_factor", ctypes.c_double), ("basis", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -125,7 +126,7 @@ class Solver:
     interior points and spacing ``h`` per dimension (x first)."""
 
     def __init__(self, dim: int, m, h, p, q, alpha: float, precision: int = FP64, inner_tol: float = 0.0,
-                 max_refine: int = 0, check_factor: float = 0.0, basis: int = 0, stream=None):
+                 max_refine: int = 0, check_factor: float = 0.0, basis: int = 0, precond: int = 0, stream=None):
         L = load()
         self._L = L
         m = list(m)
@@ -145,7 +146,7 @@ class Solver:
             blk.h[d] = h[d] if d < dim else 1.0
         blk.p = self._p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         blk.q = self._q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        opt = Options(precision, inner_tol, max_refine, check_factor, basis)
+        opt = Options(precision, inner_tol, max_refine, check_factor, basis, precond)
         self.stream = stream
         handle = ctypes.c_void_p()
         rc = L.bltt_setup(ctypes.byref(blk), self.N, self.M, float(alpha), ctypes.byref(opt),
@@ -261,7 +262,7 @@ class Batch:
             M[i] = int(np.prod(pr.m))
             A[i] = float(pr.alpha)
             self.sizes += [N[i] * M[i]] * self.nrhs
-        opt = Options(MIXED, inner_tol, max_refine, 0.0, SINE)
+        opt = Options(MIXED, inner_tol, max_refine, 0.0, SINE, PRECOND_ABAC)
         handle = ctypes.c_void_p()
         rc = L.bltt_setup_batched(blks, N, M, A, self.count, self.nrhs, ctypes.byref(opt),
                                   ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle))

@@ -642,7 +642,7 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   {
     const bool copy = (const void*)bsrc != (const void*)Vc;
     ProfScope ps(h, BLTT_K_TIME, n * (sizeof(TB) + (copy ? 2.0 : 1.0) * sizeof(T)));
-    HIPCHK(launch_time_upd<T, TB>(L, false, bsrc, nullptr, nullptr, copy ? Vc : nullptr, Zc, h->M, tt, bcoef,
+    HIPCHK(launch_time_upd<T, TB>(L, false, h->opt.precond == BLTT_PRECOND_ABAC, bsrc, nullptr, nullptr, copy ? Vc : nullptr, Zc, h->M, tt, bcoef,
                                   h->partials, h->max_blocks, &npt, s));
   }
   if ((rc = scalar(h, SC_START, npt, h->hist_dev, false, zbasis))) return rc;
@@ -659,7 +659,7 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     {
       // at j = 1 there is no v_0: V2 = V1 with a zero coefficient
       ProfScope ps(h, BLTT_K_TIME, (j > 1 ? 5.0 : 4.0) * n * sizeof(T));
-      HIPCHK(launch_time_upd<T, T>(L, true, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, h->M, tt, coef_v, h->partials,
+      HIPCHK(launch_time_upd<T, T>(L, true, h->opt.precond == BLTT_PRECOND_ABAC, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, h->M, tt, coef_v, h->partials,
                                    h->max_blocks, &npt, s));
     }
     if ((rc = scalar(h, SC_BETA, npt, h->hist_dev, false, zbasis))) return rc;
@@ -766,6 +766,10 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   if (opt) {
     if (opt->precision != BLTT_FP64 && opt->precision != BLTT_MIXED) return BLTT_EINVAL;
     if (opt->basis != BLTT_BASIS_SINE && opt->basis != BLTT_BASIS_PHYSICAL) return BLTT_EINVAL;
+    if (opt->precond != BLTT_PRECOND_ABAC && opt->precond != BLTT_PRECOND_NONE) return BLTT_EINVAL;
+    // the unpreconditioned comparator runs the FP64 sine-basis path
+    if (opt->precond == BLTT_PRECOND_NONE && (opt->precision != BLTT_FP64 || opt->basis != BLTT_BASIS_SINE))
+      return BLTT_EUNSUPPORTED;
   }
   if (!check_power(N, 2, 2048)) return BLTT_EUNSUPPORTED;
   for (int d = 0; d < blk->dim; ++d)
@@ -799,9 +803,11 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   h->opt.max_refine = 20;
   h->opt.check_factor = 10.0;
   h->opt.basis = BLTT_BASIS_SINE;
+  h->opt.precond = BLTT_PRECOND_ABAC;
   if (opt) {
     h->opt.precision = opt->precision;
     h->opt.basis = opt->basis;
+    h->opt.precond = opt->precond;
     if (opt->inner_tol > 0.0) h->opt.inner_tol = opt->inner_tol;
     if (opt->max_refine > 0) h->opt.max_refine = opt->max_refine;
     if (opt->check_factor >= 1.0) h->opt.check_factor = opt->check_factor;

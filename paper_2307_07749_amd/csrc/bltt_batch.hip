@@ -415,6 +415,7 @@ int bltt_setup_batched(const bltt_blocks* blk, const int64_t* N, const int64_t* 
   if (!blk || !N || !M || !alpha || !out || count < 1 || nrhs < 1) return BLTT_EINVAL;
   if (opt && opt->precision != BLTT_MIXED) return BLTT_EUNSUPPORTED;
   if (opt && opt->basis != BLTT_BASIS_SINE) return BLTT_EUNSUPPORTED;
+  if (opt && opt->precond != BLTT_PRECOND_ABAC) return BLTT_EUNSUPPORTED;
   for (int i = 0; i < count; ++i) {
     const bltt_blocks& bk = blk[i];
     if (!bk.p || !bk.q || bk.dim < 1 || bk.dim > 3 || !(alpha[i] > 0.0 && alpha[i] <= 1.0)) return BLTT_EINVAL;

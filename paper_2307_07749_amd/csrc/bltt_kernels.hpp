@@ -1059,7 +1059,9 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 // in FP64 before rounding).  FP32 keeps vhat in registers for the dot product;
 // FP64 reads it back from Vout (its own stores) or from Q.
 // ---------------------------------------------------------------------------
-template <typename T, int L, typename TQ, bool FULL, bool MM, int TPB = tpb_fft<T, FK_SPEC>(), class Ctx>
+// PREC false: no preconditioner (zhat = vhat), the MINRES-I comparator
+template <typename T, int L, typename TQ, bool FULL, bool MM, int TPB = tpb_fft<T, FK_SPEC>(), bool PREC = true,
+          class Ctx>
 BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __restrict__ Q,
                              const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                              T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
@@ -1113,26 +1115,30 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     if constexpr (KEEP) keep[t] = v[t];
-    v[t] = v[t] * alpha_pow_n(tb, tb.dinv, T(-1), g + t * s0);
+    if constexpr (PREC) v[t] = v[t] * alpha_pow_n(tb, tb.dinv, T(-1), g + t * s0);
   }
-  F::forward(ctx, v, lds, c, g, tb.tw);
-  time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN);
-  F::inverse(ctx, v, lds, c, g, tb.tw);
+  if constexpr (PREC) {
+    F::forward(ctx, v, lds, c, g, tb.tw);
+    time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN);
+    F::inverse(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
-  for (int t = 0; t < V; ++t) v[t] = v[t] * alpha_pow_n(tb, tb.d2, T(2), g + t * s0);
-  F::forward(ctx, v, lds, c, g, tb.tw);
-  time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN);
-  F::inverse(ctx, v, lds, c, g, tb.tw);
+    for (int t = 0; t < V; ++t) v[t] = v[t] * alpha_pow_n(tb, tb.d2, T(2), g + t * s0);
+    F::forward(ctx, v, lds, c, g, tb.tw);
+    time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN);
+    F::inverse(ctx, v, lds, c, g, tb.tw);
+  }
   double part = 0.0;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int n = g + t * s0;
     const int64_t off = (int64_t)n * ts;
-    const cx<T> z = v[t] * alpha_pow_n(tb, tb.dinv, T(-1), n);
+    const cx<T> z = PREC ? v[t] * alpha_pow_n(tb, tb.dinv, T(-1), n) : v[t];
     if (va) Zout[sa + off] = z.re;
     if (vb) Zout[sb + off] = z.im;
     cx<T> in;
-    if constexpr (KEEP) {
+    if constexpr (!PREC) {
+      in = z;
+    } else if constexpr (KEEP) {
       in = keep[t];
     } else if (Vout) {
       // a lane past M reads another workgroup's element: select, never multiply
@@ -1153,7 +1159,7 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
 template <typename T>
 constexpr bool upd_persistent() { return sizeof(T) == 4; }
 
-template <typename T, int L, typename TQ, bool FULL, bool MM, class Ctx>
+template <typename T, int L, typename TQ, bool FULL, bool MM, bool PREC = true, class Ctx>
 BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restrict__ Q,
                            const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                            T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
@@ -1162,9 +1168,11 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
   double part = 0.0;
   if constexpr (upd_persistent<T>()) {
     for (int64_t tile = ctx.bid; tile < ntiles; tile += ctx.nbx)
-      part += time_upd_tile<T, L, TQ, FULL, MM>(ctx, lds, tile, Q, V1, V2, Vout, Zout, M, tb, coef);
+      part += time_upd_tile<T, L, TQ, FULL, MM, tpb_fft<T, FK_SPEC>(), PREC>(ctx, lds, tile, Q, V1, V2, Vout, Zout,
+                                                                             M, tb, coef);
   } else {
-    part = time_upd_tile<T, L, TQ, FULL, MM>(ctx, lds, ctx.bid, Q, V1, V2, Vout, Zout, M, tb, coef);
+    part = time_upd_tile<T, L, TQ, FULL, MM, tpb_fft<T, FK_SPEC>(), PREC>(ctx, lds, ctx.bid, Q, V1, V2, Vout, Zout,
+                                                                            M, tb, coef);
   }
   const double sum = block_sum<tpb_fft<T, FK_SPEC>()>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;

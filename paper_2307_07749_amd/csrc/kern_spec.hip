@@ -16,7 +16,7 @@ constexpr bool upd_stage() { return false; }
 template <typename T, int L>
 constexpr size_t upd_lds_bytes() { return upd_lds_base<T, L>() + (upd_stage<T, L>() ? 3 * (size_t)L * sizeof(cx<T>) : 0); }
 
-template <typename T, int L, typename TQ, bool FULL>
+template <typename T, int L, typename TQ, bool FULL, bool PREC>
 __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_time_upd(
     const TQ* __restrict__ Q, const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
     T* __restrict__ Zout, int64_t M, TimeTables<T> tb, const double* __restrict__ coef,
@@ -38,35 +38,48 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
     tb.sigma = tabs + L;
     tb.rho = tabs + 2 * L;
   }
-  time_upd_body<T, L, TQ, FULL, true>(ctx, reinterpret_cast<cx<T>*>(smem), red, Q, V1, V2, Vout, Zout, M, tb, coef,
-                                      partials);
+  time_upd_body<T, L, TQ, FULL, true, PREC>(ctx, reinterpret_cast<cx<T>*>(smem), red, Q, V1, V2, Vout, Zout, M, tb,
+                                            coef, partials);
 }
 
 template <typename T, typename TQ, int L>
-static hipError_t go_upd(bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
+static hipError_t go_upd(bool full, bool prec, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                          const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
                          int64_t* nparts, hipStream_t s) {
   const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
   const int64_t blocks = upd_persistent<T>() ? std::max<int64_t>(1, std::min(tiles, max_blocks)) : tiles;
   const size_t lds = upd_lds_bytes<T, L>();
   if (nparts) *nparts = blocks;
+  if (!prec) {
+    // no preconditioner (MINRES-I): FP64 only
+    if constexpr (sizeof(T) == 8) {
+      if (full)
+        hipLaunchKernelGGL((k_time_upd<T, L, TQ, true, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()),
+                           lds, s, Q, V1, V2, Vout, Zout, M, tb, coef, partials);
+      else
+        hipLaunchKernelGGL((k_time_upd<T, L, TQ, false, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()),
+                           lds, s, Q, V1, V2, Vout, Zout, M, tb, coef, partials);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   if (full)
-    hipLaunchKernelGGL((k_time_upd<T, L, TQ, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds, s, Q,
-                       V1, V2, Vout, Zout, M, tb, coef, partials);
-  else
-    hipLaunchKernelGGL((k_time_upd<T, L, TQ, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds, s,
+    hipLaunchKernelGGL((k_time_upd<T, L, TQ, true, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds, s,
                        Q, V1, V2, Vout, Zout, M, tb, coef, partials);
+  else
+    hipLaunchKernelGGL((k_time_upd<T, L, TQ, false, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds,
+                       s, Q, V1, V2, Vout, Zout, M, tb, coef, partials);
   return hipGetLastError();
 }
 
 template <typename T, typename TQ>
-hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
+hipError_t launch_time_upd(int L, bool full, bool prec, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                            const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
                            int64_t* nparts, hipStream_t s) {
   if (full && (!V1 || !V2)) return hipErrorInvalidValue;
   switch (L) {
 #define BLTT_CASE(LL) \
-  case LL: return go_upd<T, TQ, LL>(full, Q, V1, V2, Vout, Zout, M, tb, coef, partials, max_blocks, nparts, s);
+  case LL: return go_upd<T, TQ, LL>(full, prec, Q, V1, V2, Vout, Zout, M, tb, coef, partials, max_blocks, nparts, s);
     BLTT_CASE(2) BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64)
     BLTT_CASE(128) BLTT_CASE(256) BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
 #undef BLTT_CASE
@@ -75,7 +88,7 @@ hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* 
 }
 
 #define BLTT_INST(T, TQ)                                                                                      \
-  template hipError_t launch_time_upd<T, TQ>(int, bool, const TQ*, const T*, const T*, T*, T*, int64_t,      \
+  template hipError_t launch_time_upd<T, TQ>(int, bool, bool, const TQ*, const T*, const T*, T*, T*, int64_t,      \
                                              const TimeTables<T>&, const double*, double*, int64_t, int64_t*,  \
                                              hipStream_t);
 BLTT_INST(float, float)
@@ -86,10 +99,16 @@ BLTT_INST(double, double)
 template <typename T, typename TQ, int L>
 static hipError_t attr_upd() {
   const int bytes = (int)upd_lds_bytes<T, L>();
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, true>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, true, true>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, false>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, false, true>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess || sizeof(T) != 8) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, true, false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_time_upd<T, L, TQ, false, false>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

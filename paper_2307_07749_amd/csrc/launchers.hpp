@@ -40,8 +40,9 @@ hipError_t launch_time_prec(int L, T* x, int64_t M, const TimeTables<T>& tb, hip
 // sine coordinates: vhat = cq Q (+ cv V1 + cvp V2 when full) -> Vout (optional),
 // Zout = P^{-1} vhat (time pass), per-workgroup partial sums of <vhat, Zout>
 // (persistent: at most max_blocks workgroups, *nparts receives the partial count)
+// prec false: no preconditioner (Zout = vhat; FP64 only)
 template <typename T, typename TQ>
-hipError_t launch_time_upd(int L, bool full, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
+hipError_t launch_time_upd(int L, bool full, bool prec, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                            const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
                            int64_t* nparts, hipStream_t s);
 

@@ -18,6 +18,7 @@ import scipy.sparse.linalg as spla
 
 from oracle import bltt_oracle as O
 from paper_2307_07749_amd import workloads as W
+from tests.paper_examples import example1_system_and_rhs, example3_system_and_rhs, golden_counts
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -342,51 +343,21 @@ def test_iteration_count_flat_in_N():
 # iteration counts printed in the paper (Tables 1, 4-6)
 # ---------------------------------------------------------------------------
 
-def _example3_system_and_rhs(gamma, N, mp1, alpha):
-    """Example 3: (0,pi)^2, T=1, u = sin x sin y t^2, u0 = 0,
-    f = sin x sin y [2 t^{2-gamma}/Gamma(3-gamma) + 2 t^2]."""
-    prob = W.fractional_l1(2, mp1 - 1, N, gamma, alpha, length=math.pi)
-    sysm = O.from_problem(prob)
-    h = math.pi / mp1
-    x = h * np.arange(1, mp1)
-    S = np.outer(np.sin(x), np.sin(x)).ravel()           # y slow, x fast
-    t = (np.arange(1, N + 1) / N)[:, None]
-    f = S[None, :] * (2 * t ** (2 - gamma) / math.gamma(3 - gamma) + 2 * t ** 2)
-    return sysm, f
-
-
-def _example1_system_and_rhs(N, mp1, alpha):
-    """Example 1 (BDF), read with diffusion 1e-6 and first block + u0/tau."""
-    eps = 1e-6
-    prob = W.heat_bdf(2, mp1 - 1, N, alpha, diffusion=eps)
-    sysm = O.from_problem(prob)
-    h = 1.0 / mp1
-    x = h * np.arange(1, mp1)
-    X1 = np.tile(x, mp1 - 1)        # x fastest
-    X2 = np.repeat(x, mp1 - 1)
-    g = X1 * (X1 - 1) * X2 * (X2 - 1)
-    t = (np.arange(1, N + 1) / N)[:, None]
-    f = np.exp(t) * (g[None, :] - 2 * eps * (X1 * (X1 - 1) + X2 * (X2 - 1))[None, :])
-    f[0] += g * N                    # + u0 / tau
-    return sysm, f
-
-
 def _golden():
-    with open(os.path.join(GOLDEN, "paper_iteration_counts.json")) as fh:
-        return json.load(fh)
+    return golden_counts()
 
 
 @pytest.mark.parametrize("row", _golden()["example3_fractional"]["rows"])
 def test_paper_table4to6_counts(row):
-    sysm, f = _example3_system_and_rhs(row["gamma"], row["N"], row["m_plus_1"], 1e-8)
+    sysm, f = example3_system_and_rhs(row["gamma"], row["N"], row["m_plus_1"], 1e-8)
     assert O.pminres(sysm, f, 1e-6, 100).iters == row["P_alpha"]
-    sysm1, _ = _example3_system_and_rhs(row["gamma"], row["N"], row["m_plus_1"], 1.0)
+    sysm1, _ = example3_system_and_rhs(row["gamma"], row["N"], row["m_plus_1"], 1.0)
     assert O.pminres(sysm1, f, 1e-6, 100).iters == row["P_1"]
 
 
 @pytest.mark.parametrize("row", _golden()["example1_heat_bdf"]["rows"])
 def test_paper_table1_counts(row):
-    sysm, f = _example1_system_and_rhs(row["N"], row["m_plus_1"], 1e-8)
+    sysm, f = example1_system_and_rhs(row["N"], row["m_plus_1"], 1e-8)
     assert O.pminres(sysm, f, 1e-6, 100).iters == row["P_alpha"]
     assert O.pminres(sysm, f, 1e-6, 200, precond="none").iters == row["I"]
 
