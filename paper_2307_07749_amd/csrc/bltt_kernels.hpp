@@ -71,6 +71,11 @@ constexpr int waves_fft() { return 1; }
 // minimising registers for an occupancy that can never be reached.
 template <typename T>
 constexpr int max_waves_fft() { return sizeof(T) == 4 ? 4 : 2; }
+// The FP32 time pass is bound by instruction issue: two waves per SIMD (at
+// most 256 VGPRs) let one wave's LDS and memory waits overlap the other's ALU
+// work.
+template <typename T>
+constexpr int min_waves_upd() { return sizeof(T) == 4 ? 2 : 1; }
 constexpr int TPB_EW = 256;  // elementwise / streaming kernels
 constexpr int ZB_MAX = 32;   // stored Z vectors of one FP32 sweep, at most
 
@@ -915,39 +920,104 @@ BLTT_HD double alpha_pow_n(const TimeTables<double>& tb, const double* tab, doub
   return tab[n];
 }
 
-// One k <-> L-k pair of the two-for-one spectral step.  Z1 holds frequency k1
-// of the packed line (mode a real part, mode b imaginary part), Z2 frequency
-// L - k1.  The multipliers of frequency L - k are the conjugates of those of k.
-template <typename T, int HALF, bool SELF>
-BLTT_HD void spectral_pair(cx<T>& Z1, cx<T>& Z2, int k1, T mua, T mub, const TimeTables<T>& tb, T invN) {
-  const cx<T> sg = tb.sigma[k1];
-  const cx<T> rh = tb.rho[k1];
-  cx<T> ga = inv_sqrt_scaled(sg + rh * mua, invN);
-  cx<T> gb = inv_sqrt_scaled(sg + rh * mub, invN);
-  if (HALF == 0) {
-    ga = conjg(ga);
-    gb = conjg(gb);
+// Multiplies v[t] (time n = g + t*s0) by alpha^{e n/N}.  FP32: two exp2 per
+// thread and a product chain over t (relative error below 2e-6 for V = 16);
+// FP64: the table.  With DOT, also returns sum_t <v_t before, v_t after>.
+template <typename T, int V, int s0, bool DOT = false>
+BLTT_HD T scale_alpha(cx<T>* v, const TimeTables<T>& tb, const T* tab, T e, int g) {
+  T acc0 = T(0), acc1 = T(0);
+  T d = T(0), st = T(0);
+  if constexpr (sizeof(T) == 4) {
+    d = alpha_pow_n(tb, tab, e, g);
+    st = alpha_pow_n(tb, tab, e, s0);
   }
-  if (SELF) {
-    // k1 = L - k1: A = Re Z, i B = i Im Z, multipliers real
-    Z1 = mkc<T>(Z1.re * ga.re - Z1.im * gb.im, Z1.re * ga.im + Z1.im * gb.re);
-    return;
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    if constexpr (sizeof(T) != 4) d = alpha_pow_n(tb, tab, e, g + t * s0);
+    const cx<T> w = v[t] * d;
+    if (DOT) {
+      T& acc = (t & 1) ? acc1 : acc0;
+      acc += v[t].re * w.re + v[t].im * w.im;
+    }
+    v[t] = w;
+    if constexpr (sizeof(T) == 4) d *= st;
   }
-  const cx<T> c2 = conjg(Z2), c1 = conjg(Z1);
-  const cx<T> n1 = ((Z1 + c2) * ga + (Z1 - c2) * gb) * T(0.5);
-  const cx<T> n2 = ((Z2 + c1) * conjg(ga) + (Z2 - c1) * conjg(gb)) * T(0.5);
+  return acc0 + acc1;
+}
+
+// The two-for-one spectral step.  A packed line holds mode a in its real part
+// and mode b in its imaginary part; with A_k = (Z_k + conj Z_{L-k})/2 and
+// B_k = (Z_k - conj Z_{L-k})/(2i) and per-mode multipliers g_a, g_b at k, the
+// new values are Z_k <- Z_k hp + conj(Z_{L-k}) hm with hp = (g_a + g_b)/2,
+// hm = (g_a - g_b)/2; the multipliers of L - k are the conjugates of those of
+// k.  The multipliers are 1/(N s), s the principal square root of lambda; the
+// first half-solve uses their conjugates.  The first half computes them and
+// keeps (hp, hm) in `gm`, the second reuses them.
+template <typename T>
+struct SpecMul {
+  cx<T> p, m;
+};
+
+template <typename T>
+BLTT_HD SpecMul<T> spectral_mul(int k, T mua, T mub, const TimeTables<T>& tb, T halfInvN) {
+  const cx<T> sg = tb.sigma[k];
+  const cx<T> rh = tb.rho[k];
+  const cx<T> ga = inv_sqrt_scaled(sg + rh * mua, halfInvN);
+  const cx<T> gb = inv_sqrt_scaled(sg + rh * mub, halfInvN);
+  SpecMul<T> r;
+  r.p = ga + gb;
+  r.m = ga - gb;
+  return r;
+}
+
+// frequencies k (Z1) and L - k (Z2)
+template <typename T, int HALF>
+BLTT_HD void spectral_apply(cx<T>& Z1, cx<T>& Z2, const SpecMul<T>& g) {
+  const cx<T> hp = HALF == 0 ? conjg(g.p) : g.p, hm = HALF == 0 ? conjg(g.m) : g.m;
+  const cx<T> n1 = Z1 * hp + conjg(Z2) * hm;
+  const cx<T> n2 = Z2 * conjg(hp) + conjg(Z1) * conjg(hm);
   Z1 = n1;
   Z2 = n2;
 }
 
+// a frequency equal to its own mirror (k = 0 or L/2)
+template <typename T, int HALF>
+BLTT_HD void spectral_self(cx<T>& Z, const SpecMul<T>& g) {
+  const cx<T> hp = HALF == 0 ? conjg(g.p) : g.p, hm = HALF == 0 ? conjg(g.m) : g.m;
+  Z = Z * hp + conjg(Z) * hm;
+}
+
+// multiplier slots one thread keeps between the halves
+template <int L, class F>
+constexpr int spec_slots() {
+  return F::S == 1 ? L / 2 + 1 : (F::V / F::RL / 2) * F::RL + 1;
+}
+
+// After the forward transform a thread holds, per pair p of its last-stage
+// butterflies, s0[u] at frequency q + u K and s1[RL-1-u] at L - (q + u K)
+// (q = g PP + p), except on the one lane with q = 0, whose butterflies hold
+// k = u K and k = K/2 + u K: there the mirrors sit at s0[RL-u] and
+// s1[RL-1-u], and k = 0, L/2 are their own mirrors.  That lane's values are
+// re-dealt with selects into the common pattern (the two self frequencies
+// sharing the last slot), so every lane runs the same instructions.
+// select between two values (a conditional expression on two class lvalues
+// would select their addresses and keep the operands in memory)
+template <typename T>
+BLTT_HD cx<T> csel(bool c, cx<T> a, cx<T> b) {
+  return mkc<T>(c ? a.re : b.re, c ? a.im : b.im);
+}
+
 template <typename T, int L, class F, int HALF>
-BLTT_HD void time_spectral(cx<T>* v, int g, T mua, T mub, const TimeTables<T>& tb, T invN) {
+BLTT_HD void time_spectral(cx<T>* v, int g, T mua, T mub, const TimeTables<T>& tb, T invN, SpecMul<T>* gm) {
   constexpr int RL = F::RL, NB = F::V / RL, K = F::K;
+  const T hinv = T(0.5) * invN;
   if constexpr (F::S == 1) {
-    spectral_pair<T, HALF, true>(v[0], v[0], 0, mua, mub, tb, invN);
+    if (HALF == 0)
+      for (int u = 0; u <= L / 2; ++u) gm[u] = spectral_mul(u, mua, mub, tb, hinv);
+    spectral_self<T, HALF>(v[0], gm[0]);
 #pragma unroll
-    for (int u = 1; u < L / 2; ++u) spectral_pair<T, HALF, false>(v[u], v[L - u], u, mua, mub, tb, invN);
-    if constexpr (L >= 2) spectral_pair<T, HALF, true>(v[L / 2], v[L / 2], L / 2, mua, mub, tb, invN);
+    for (int u = 1; u < L / 2; ++u) spectral_apply<T, HALF>(v[u], v[L - u], gm[u]);
+    if constexpr (L >= 2) spectral_self<T, HALF>(v[L / 2], gm[L / 2]);
   } else {
     constexpr int PP = NB / 2;
 #pragma unroll
@@ -955,20 +1025,63 @@ BLTT_HD void time_spectral(cx<T>* v, int g, T mua, T mub, const TimeTables<T>& t
       const int q = g * PP + p;
       cx<T>* s0 = v + (2 * p) * RL;
       cx<T>* s1 = v + (2 * p + 1) * RL;
-      if (q != 0) {
+      SpecMul<T>* m = gm + p * RL;
+      if (p != 0) {
+        // q >= 1 on every lane
 #pragma unroll
-        for (int u = 0; u < RL; ++u)
-          spectral_pair<T, HALF, false>(s0[u], s1[RL - 1 - u], q + u * K, mua, mub, tb, invN);
-      } else {
-        // butterflies k_low = 0 and k_low = K/2 are each closed under k -> L-k
-        spectral_pair<T, HALF, true>(s0[0], s0[0], 0, mua, mub, tb, invN);
+        for (int u = 0; u < RL; ++u) {
+          if (HALF == 0) m[u] = spectral_mul(q + u * K, mua, mub, tb, hinv);
+          spectral_apply<T, HALF>(s0[u], s1[RL - 1 - u], m[u]);
+        }
+        continue;
+      }
+      const bool q0 = q == 0;
+      cx<T> X[RL], Y[RL];
 #pragma unroll
-        for (int u = 1; u < RL / 2; ++u)
-          spectral_pair<T, HALF, false>(s0[u], s0[RL - u], u * K, mua, mub, tb, invN);
-        spectral_pair<T, HALF, true>(s0[RL / 2], s0[RL / 2], (RL / 2) * K, mua, mub, tb, invN);
+      for (int u = 0; u < RL; ++u) {
+        Y[u] = s1[u];
+        if (u < RL / 2) {
+          X[u] = csel(q0, s1[u], s0[u]);
+        } else if (u < RL - 1) {
+          X[u] = csel(q0, s0[u - RL / 2 + 1], s0[u]);
+          Y[RL - 1 - u] = csel(q0, s0[3 * RL / 2 - 1 - u], s1[RL - 1 - u]);
+        } else {
+          X[u] = csel(q0, s0[0], s0[u]);
+        }
+      }
+      Y[0] = csel(q0, s0[RL / 2], s1[0]);
+      if (HALF == 0) {
 #pragma unroll
-        for (int u = 0; u < RL / 2; ++u)
-          spectral_pair<T, HALF, false>(s1[u], s1[RL - 1 - u], K / 2 + u * K, mua, mub, tb, invN);
+        for (int u = 0; u < RL; ++u) {
+          const int kq0 = u < RL / 2 ? K / 2 + u * K : (u < RL - 1 ? (u - RL / 2 + 1) * K : 0);
+          m[u] = spectral_mul(q0 ? kq0 : q + u * K, mua, mub, tb, hinv);
+        }
+        gm[PP * RL] = spectral_mul(L / 2, mua, mub, tb, hinv);
+      }
+#pragma unroll
+      for (int u = 0; u < RL - 1; ++u) spectral_apply<T, HALF>(X[u], Y[RL - 1 - u], m[u]);
+      {
+        cx<T> x = X[RL - 1], y = Y[0], xs = x, ys = y;
+        spectral_apply<T, HALF>(x, y, m[RL - 1]);
+        spectral_self<T, HALF>(xs, m[RL - 1]);
+        spectral_self<T, HALF>(ys, gm[PP * RL]);
+        X[RL - 1] = csel(q0, xs, x);
+        Y[0] = csel(q0, ys, y);
+      }
+      // deal back
+#pragma unroll
+      for (int u = 0; u < RL; ++u) {
+        cx<T> a0;  // s0[u] on the q = 0 lane
+        if (u == 0)
+          a0 = X[RL - 1];
+        else if (u < RL / 2)
+          a0 = X[u + RL / 2 - 1];
+        else if (u == RL / 2)
+          a0 = Y[0];
+        else
+          a0 = Y[u - RL / 2];
+        s0[u] = csel(q0, a0, X[u]);
+        s1[u] = u < RL / 2 ? csel(q0, X[u], Y[u]) : Y[u];
       }
     }
   }
@@ -998,13 +1111,13 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
     const int64_t off = (int64_t)n * M;
     v[t] = mkc<T>(x[iac + off] * (d * wa), x[ibc + off] * (d * wb));
   }
+  SpecMul<T> gm[spec_slots<L, F>()];
   F::forward(ctx, v, lds, c, g, tb.tw);
-  time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN);
+  time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN, gm);
   F::inverse(ctx, v, lds, c, g, tb.tw);
-#pragma unroll
-  for (int t = 0; t < V; ++t) v[t] = v[t] * alpha_pow_n(tb, tb.d2, T(2), g + t * s0);
+  scale_alpha<T, V, s0>(v, tb, tb.d2, T(2), g);
   F::forward(ctx, v, lds, c, g, tb.tw);
-  time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN);
+  time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN, gm);
   F::inverse(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
   for (int t = 0; t < V; ++t) {
@@ -1056,8 +1169,10 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 //   zhat = P^{-1} vhat             stored to Zout;
 //   partial sums of <vhat, zhat>   one per workgroup.
 // Q may be FP64 for an FP32 pass (the refinement right-hand side, scaled by cq
-// in FP64 before rounding).  FP32 keeps vhat in registers for the dot product;
-// FP64 reads it back from Vout (its own stores) or from Q.
+// in FP64 before rounding).  Since P^{-1} = C^{-1/2} (C^{-1/2})^* with C^{-1/2}
+// real (Section 3), <vhat, P^{-1} vhat> = ||(C^{-1/2})^* vhat||^2: the dot is
+// taken on the intermediate after the first half-solve, so vhat need not be
+// kept or read again.
 // ---------------------------------------------------------------------------
 // PREC false: no preconditioner (zhat = vhat), the MINRES-I comparator
 template <typename T, int L, typename TQ, bool FULL, bool MM, int TPB = tpb_fft<T, FK_SPEC>(), bool PREC = true,
@@ -1067,10 +1182,16 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
                              T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
                              const double* __restrict__ coef) {
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
-  constexpr bool KEEP = sizeof(T) == 4;
   using F = LineFft<T, L, NL, !MM, LAST_PAIRED>;
   const T invN = T(1) / T(L);
-  const int tid = ctx.tid, c = MM ? tid / G : tid % NL, g = MM ? tid % G : tid / NL;
+  const int tid = ctx.tid, c = MM ? tid / G : tid % NL;
+  int g = MM ? tid % G : tid / NL;
+#if defined(__HIP_DEVICE_COMPILE__)
+  // g is opaque to the compiler here, so that a tile loop around this function
+  // does not keep g-dependent table loads (twiddles, spectra) live across
+  // tiles at the cost of occupancy
+  asm volatile("" : "+v"(g));
+#endif
   const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
@@ -1086,7 +1207,7 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
     cvp = T(coef[2]);
   }
 
-  cx<T> keep[KEEP ? V : 1], v[V];
+  cx<T> v[V];
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int64_t off = (int64_t)(g + t * s0) * ts;
@@ -1112,43 +1233,27 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
       if (vb) Vout[sb + off] = v[t].im;
     }
   }
-#pragma unroll
-  for (int t = 0; t < V; ++t) {
-    if constexpr (KEEP) keep[t] = v[t];
-    if constexpr (PREC) v[t] = v[t] * alpha_pow_n(tb, tb.dinv, T(-1), g + t * s0);
-  }
-  if constexpr (PREC) {
-    F::forward(ctx, v, lds, c, g, tb.tw);
-    time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN);
-    F::inverse(ctx, v, lds, c, g, tb.tw);
-#pragma unroll
-    for (int t = 0; t < V; ++t) v[t] = v[t] * alpha_pow_n(tb, tb.d2, T(2), g + t * s0);
-    F::forward(ctx, v, lds, c, g, tb.tw);
-    time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN);
-    F::inverse(ctx, v, lds, c, g, tb.tw);
-  }
   double part = 0.0;
+  if constexpr (PREC) {
+    SpecMul<T> gm[spec_slots<L, F>()];
+    scale_alpha<T, V, s0>(v, tb, tb.dinv, T(-1), g);
+    F::forward(ctx, v, lds, c, g, tb.tw);
+    time_spectral<T, L, F, 0>(v, g, mua, mub, tb, invN, gm);
+    F::inverse(ctx, v, lds, c, g, tb.tw);
+    // v = D^{-1} (C^{-1/2})^* vhat here, so with w = (C^{-1/2})^* vhat,
+    // ||w||^2 = sum_t <v, D^2 v>, taken while scaling by the middle D^2
+    part = (double)scale_alpha<T, V, s0, true>(v, tb, tb.d2, T(2), g);
+    F::forward(ctx, v, lds, c, g, tb.tw);
+    time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN, gm);
+    F::inverse(ctx, v, lds, c, g, tb.tw);
+    scale_alpha<T, V, s0>(v, tb, tb.dinv, T(-1), g);
+  }
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int n = g + t * s0;
-    const int64_t off = (int64_t)n * ts;
-    const cx<T> z = PREC ? v[t] * alpha_pow_n(tb, tb.dinv, T(-1), n) : v[t];
-    if (va) Zout[sa + off] = z.re;
-    if (vb) Zout[sb + off] = z.im;
-    cx<T> in;
-    if constexpr (!PREC) {
-      in = z;
-    } else if constexpr (KEEP) {
-      in = keep[t];
-    } else if (Vout) {
-      // a lane past M reads another workgroup's element: select, never multiply
-      const T ra = Vout[la + off], rb = Vout[lb + off];
-      in = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
-    } else {
-      const T ra = T(cq) * T(Q[la + off]), rb = T(cq) * T(Q[lb + off]);
-      in = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
-    }
-    part += (double)in.re * (double)z.re + (double)in.im * (double)z.im;
+    const int64_t off = (int64_t)(g + t * s0) * ts;
+    if (va) Zout[sa + off] = v[t].re;
+    if (vb) Zout[sb + off] = v[t].im;
+    if constexpr (!PREC) part += (double)v[t].re * (double)v[t].re + (double)v[t].im * (double)v[t].im;
   }
   return part;
 }

@@ -154,17 +154,26 @@ BLTT_HD void dft(cx<T>* a) {
 // Twiddles w^u, 0 < u < R, of w = tw[e]: the powers w^(2^k) come from the
 // table and the others are products of two or three of them (at most three
 // roundings), so a radix-16 butterfly issues 4 table loads instead of 15.
+constexpr int high_pow2(int u) {
+  int h = 1;
+  while (h * 2 <= u) h *= 2;
+  return h;
+}
+// pw[U..R-1] from the powers of two below them (compile-time indices only, so
+// pw stays in registers)
+template <int R, int U, typename T>
+BLTT_HD void twiddle_products(cx<T>* pw) {
+  if constexpr (U < R) {
+    constexpr int hi = high_pow2(U);
+    if constexpr (hi != U) pw[U] = pw[hi] * pw[U - hi];
+    twiddle_products<R, U + 1>(pw);
+  }
+}
 template <int R, typename T>
 BLTT_HD void twiddle_powers(cx<T>* pw, const cx<T>* tw, int e) {
 #pragma unroll
   for (int u = 1; u < R; u <<= 1) pw[u] = tw[u * e];
-#pragma unroll
-  for (int u = 3; u < R; ++u) {
-    if ((u & (u - 1)) == 0) continue;
-    int hi = 1;
-    while (hi * 2 <= u) hi *= 2;
-    pw[u] = pw[hi] * pw[u - hi];
-  }
+  twiddle_products<R, 3>(pw);
 }
 
 // How the last stage's butterflies are dealt to the threads of a line.

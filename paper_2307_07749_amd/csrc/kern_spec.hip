@@ -17,7 +17,7 @@ template <typename T, int L>
 constexpr size_t upd_lds_bytes() { return upd_lds_base<T, L>() + (upd_stage<T, L>() ? 3 * (size_t)L * sizeof(cx<T>) : 0); }
 
 template <typename T, int L, typename TQ, bool FULL, bool PREC>
-__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_time_upd(
+__global__ __attribute__((amdgpu_waves_per_eu(min_waves_upd<T>(), max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_time_upd(
     const TQ* __restrict__ Q, const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
     T* __restrict__ Zout, int64_t M, TimeTables<T> tb, const double* __restrict__ coef,
     double* __restrict__ partials) {
