@@ -212,8 +212,9 @@ enum { MV_DOT = 0, MV_RESID = 1 };
 enum { TERM_NONE = 0, TERM_STENCIL = 1, TERM_SPEC = 2 };
 
 // Iterate update fused into the FP64 residual of the refinement loop:
-// u <- (u_zero ? 0 : u) + (*s) sum_{i<k} y[i] Z_i (Z_i the stored FP32 vectors of
-// the sweep), written back to u, and the residual formed from the new u.
+// u <- (u_zero ? 0 : u) + sum_{i<k} (*s) y[i] Z_i (Z_i the stored FP32 vectors
+// of the sweep, added in order in FP64), written back to u, and the residual
+// formed from the new u.
 struct IterUpd {
   const float* z[ZB_MAX];
   int k;             // 0: no update
@@ -256,28 +257,55 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
   const bool upd = MODE == MV_RESID && uk > 0;
   const double us = upd ? *(sptr ? sptr : up.s) : 0.0;
   cx<T> v[V], zin[VH];
+  T ra[VH], rb[VH];
 #pragma unroll
   for (int t = 0; t < VH; ++t) {
     const int64_t off = (int64_t)(g + t * s0) * ts;
-    T ra = T(0), rb = T(0);
+    ra[t] = T(0);
+    rb[t] = T(0);
     if (!(MODE == MV_RESID && up.u_zero)) {
-      ra = z[la + off];
-      rb = z[lb + off];
+      ra[t] = z[la + off];
+      rb[t] = z[lb + off];
     }
-    if (upd) {
-      // refinement update of the iterate, written back before its use
-      double da = 0.0, db = 0.0;
-      for (int i = 0; i < uk; ++i) {
-        const double yi = uy[i];
-        da += yi * (double)up.z[i][zoff + la + off];
-        db += yi * (double)up.z[i][zoff + lb + off];
+  }
+  if (upd) {
+    // refinement update of the iterate, written back before its use; the
+    // loop over the stored vectors is outside the one over times, so each
+    // vector's loads are all in flight together
+    double da[VH], db[VH];
+#pragma unroll
+    for (int t = 0; t < VH; ++t) {
+      da[t] = (double)ra[t];
+      db[t] = (double)rb[t];
+    }
+    for (int i = 0; i < uk; ++i) {
+      const double yi = us * uy[i];
+      const float* zi = up.z[i] + zoff;
+      float xa[VH], xb[VH];
+#pragma unroll
+      for (int t = 0; t < VH; ++t) {
+        const int64_t off = (int64_t)(g + t * s0) * ts;
+        xa[t] = zi[la + off];
+        xb[t] = zi[lb + off];
       }
-      ra = T((double)ra + us * da);
-      rb = T((double)rb + us * db);
-      if (va) z[sa + off] = ra;
-      if (vb) z[sb + off] = rb;
+#pragma unroll
+      for (int t = 0; t < VH; ++t) {
+        da[t] += yi * (double)xa[t];
+        db[t] += yi * (double)xb[t];
+      }
     }
-    zin[t] = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
+#pragma unroll
+    for (int t = 0; t < VH; ++t) {
+      const int64_t off = (int64_t)(g + t * s0) * ts;
+      ra[t] = T(da[t]);
+      rb[t] = T(db[t]);
+      if (va) z[sa + off] = ra[t];
+      if (vb) z[sb + off] = rb[t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < VH; ++t) {
+    zin[t] = mkc<T>(va ? ra[t] : T(0), vb ? rb[t] : T(0));
     v[t] = zin[t];
   }
 #pragma unroll
@@ -409,27 +437,52 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   const bool upd = MODE == MV_RESID && up.k > 0;
   const double us = upd ? *up.s : 0.0;
   cx<T> zin[V], v[V], acc[V];
+  T ra[V], rb[V];
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int n = g + t * s0;
-    T ra = T(0), rb = T(0);
+    ra[t] = T(0);
+    rb[t] = T(0);
     if (!(MODE == MV_RESID && up.u_zero)) {
-      ra = z[la + n];
-      rb = z[lb + n];
+      ra[t] = z[la + n];
+      rb[t] = z[lb + n];
     }
-    if (upd) {
-      double da = 0.0, db = 0.0;
-      for (int i = 0; i < up.k; ++i) {
-        const double yi = up.y[i];
-        da += yi * (double)up.z[i][la + n];
-        db += yi * (double)up.z[i][lb + n];
+  }
+  if (upd) {
+    // stored-vector loop outside the time loop: one vector's loads in flight together
+    double da[V], db[V];
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+      da[t] = (double)ra[t];
+      db[t] = (double)rb[t];
+    }
+    for (int i = 0; i < up.k; ++i) {
+      const double yi = us * up.y[i];
+      const float* zi = up.z[i];
+      float xa[V], xb[V];
+#pragma unroll
+      for (int t = 0; t < V; ++t) {
+        xa[t] = zi[la + g + t * s0];
+        xb[t] = zi[lb + g + t * s0];
       }
-      ra = T((double)ra + us * da);
-      rb = T((double)rb + us * db);
-      if (va) z[sa + n] = ra;
-      if (vb) z[sb + n] = rb;
+#pragma unroll
+      for (int t = 0; t < V; ++t) {
+        da[t] += yi * (double)xa[t];
+        db[t] += yi * (double)xb[t];
+      }
     }
-    zin[t] = mkc<T>(va ? ra : T(0), vb ? rb : T(0));
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+      const int n = g + t * s0;
+      ra[t] = T(da[t]);
+      rb[t] = T(db[t]);
+      if (va) z[sa + n] = ra[t];
+      if (vb) z[sb + n] = rb[t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    zin[t] = mkc<T>(va ? ra[t] : T(0), vb ? rb[t] : T(0));
     v[t] = zin[t];
   }
   // circulant part

@@ -25,7 +25,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<float>()))) __lau
 }
 
 template <int L2>
-__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<double>()))) __launch_bounds__((tpb_fft<double, FK_MV>()), 1) void k_bt_resid(
+__global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<double>()))) __launch_bounds__((tpb_fft<double, FK_MV>()), 1) void k_bt_resid(
     double* const* __restrict__ u, double* __restrict__ R, const double* __restrict__ Fh, BatchVec bv, BatchTabs bt,
     IterUpd pool, const double* __restrict__ zb, int K, int64_t T2, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];

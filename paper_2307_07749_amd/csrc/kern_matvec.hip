@@ -5,7 +5,7 @@
 namespace bltt {
 
 template <typename T, int L, int MODE, int TERM>
-__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_MV>()), waves_fft<T>()) void k_matvec_fft(T* z, T* __restrict__ out,
+__global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_MV>()), waves_fft<T>()) void k_matvec_fft(T* z, T* __restrict__ out,
                                                              const T* __restrict__ fin, int64_t M,
                                                              MatvecTables<T> tb, IterUpd up,
                                                              double* __restrict__ partials) {
