@@ -292,6 +292,7 @@ int64_t partials_needed(const bltt_handle* h) {
   need = std::max(need, h->n / h->m[0]);  // one partial per x-line (residual stencil pass)
   need = std::max(need, fft_blocks<T, FK_TIME>((int)h->N, h->M));
   need = std::max(need, fft_tiles<T, FK_SPEC>((int)h->N, h->M));  // sine-basis kernels
+  need = std::max(need, ((h->M + TR_TILE - 1) / TR_TILE) * ((h->N + TR_TILE - 1) / TR_TILE));  // transpose + norm
   return need;
 }
 
@@ -601,7 +602,8 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
 // mu_i term, one Lanczos-update + time-pass kernel, one direction/iterate
 // update.  The right-hand side is cq * bsrc with cq = bcoef[0] (bsrc may be
 // FP64 for an FP32 sweep); it is copied into V[0] as the first Lanczos vector
-// unless bsrc already is V[0].  X must be zero on entry.  fhat (FP64 only):
+// unless bsrc already is V[0]; brev: the right-hand side is Y bsrc (bsrc read
+// with its time lines reversed).  X must be zero on entry.  fhat (FP64 only):
 // the transformed f for the explicit residual check, as in minres_core.
 //
 // zbasis (FP32 only): keep every Z_j in the stored pool instead of forming the
@@ -611,7 +613,8 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
 // K - 1 iterations (the pool size); in the refinement loop that is a restart.
 template <typename T, typename TX, typename TB>
 int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* fhat, double tol, double bnorm,
-                double* hist_host, CoreResult* res, const TB* bsrc, const double* bcoef, bool zbasis = false) {
+                double* hist_host, CoreResult* res, const TB* bsrc, const double* bcoef, bool zbasis = false,
+                bool brev = false) {
   Workspace<T>& ws = workspace<T>(h);
   hipStream_t s = h->stream;
   int rc;
@@ -643,7 +646,7 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     const bool copy = (const void*)bsrc != (const void*)Vc;
     ProfScope ps(h, BLTT_K_TIME, n * (sizeof(TB) + (copy ? 2.0 : 1.0) * sizeof(T)));
     HIPCHK(launch_time_upd<T, TB>(L, false, h->opt.precond == BLTT_PRECOND_ABAC, bsrc, nullptr, nullptr, copy ? Vc : nullptr, Zc, h->M, tt, bcoef,
-                                  h->partials, h->max_blocks, &npt, s));
+                                  h->partials, h->max_blocks, &npt, s, brev));
   }
   if ((rc = scalar(h, SC_START, npt, h->hist_dev, false, zbasis))) return rc;
   if ((rc = read_state(h))) return rc;
@@ -907,16 +910,13 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     // (U = U^T = U^{-1}).  u_dev serves as time-major scratch on the way in.
     if ((rc = space_transform<double>(h, f_dev, u_dev))) return rc;
     {
+      // fhat to the mode-major layout, with ||fhat||^2 = ||Y fhat||^2 on the way;
+      // b = Y fhat is never stored: the first Lanczos start reads fhat reversed
       ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
-      HIPCHK(launch_transpose<double>(u_dev, h->F64, h->N, h->M, false, s));
+      HIPCHK(launch_transpose<double>(u_dev, h->F64, h->N, h->M, false, h->partials, &np, s));
       // the FP64 path and the direct-form residual read uhat from the start;
       // the fused FFT residual of the mixed path writes it on the first sweep
       if (h->opt.precision == BLTT_FP64 || short_p(h)) HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
-    }
-    double* b64 = h->opt.precision == BLTT_FP64 ? h->w64.V[0] : h->R64;
-    {
-      ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
-      HIPCHK(launch_rhs_mm(h->F64, b64, h->N, h->M, h->partials, &np, s));
     }
     if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
     if ((rc = read_state(h))) return rc;
@@ -930,7 +930,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     } else if (h->opt.precision == BLTT_FP64) {
       CoreResult cr;
       rc = minres_spec<double, double, double>(h, u_dev, maxit, h->opt.check_factor * tol, h->F64, tol, bnorm, hist,
-                                               &cr, b64, h->coef_one);
+                                               &cr, h->F64, h->coef_one, false, true);
       if (rc) return rc;
       total_iters = cr.iters;
       outer = 1;
@@ -959,8 +959,9 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         CoreResult cr;
         const int left = maxit - total_iters;
         hbuf.assign((size_t)left + 2, 0.0);
+        // r = b = Y fhat on the first sweep (read from fhat reversed), then the residual
         rc = minres_spec<float, float, double>(h, nullptr, left, h->opt.inner_tol, nullptr, 0.0, 1.0, hbuf.data(),
-                                               &cr, h->R64, &h->state->rinv, true);
+                                               &cr, outer == 0 ? h->F64 : h->R64, &h->state->rinv, true, outer == 0);
         if (rc) return rc;
         if (hist)
           for (int k = 1; k <= cr.iters; ++k) hist[hist_pos + k] = hbuf[(size_t)k];
@@ -999,7 +1000,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     }
     {
       ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
-      HIPCHK(launch_transpose<double>(u_dev, h->F64, h->M, h->N, false, s));
+      HIPCHK(launch_transpose<double>(u_dev, h->F64, h->M, h->N, false, nullptr, nullptr, s));
     }
     if ((rc = space_transform<double>(h, h->F64, u_dev))) return rc;
   } else if (h->opt.precision == BLTT_FP64) {

@@ -1222,7 +1222,7 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 //   zhat = P^{-1} vhat             stored to Zout;
 //   partial sums of <vhat, zhat>   one per workgroup.
 // Q may be FP64 for an FP32 pass (the refinement right-hand side, scaled by cq
-// in FP64 before rounding).  Since P^{-1} = C^{-1/2} (C^{-1/2})^* with C^{-1/2}
+// in FP64 before rounding), and the start may read it time-reversed (Y Q).  Since P^{-1} = C^{-1/2} (C^{-1/2})^* with C^{-1/2}
 // real (Section 3), <vhat, P^{-1} vhat> = ||(C^{-1/2})^* vhat||^2: the dot is
 // taken on the intermediate after the first half-solve, so vhat need not be
 // kept or read again.
@@ -1233,7 +1233,7 @@ template <typename T, int L, typename TQ, bool FULL, bool MM, int TPB = tpb_fft<
 BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __restrict__ Q,
                              const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                              T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
-                             const double* __restrict__ coef) {
+                             const double* __restrict__ coef, bool qrev = false) {
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   using F = LineFft<T, L, NL, !MM, LAST_PAIRED>;
   const T invN = T(1) / T(L);
@@ -1264,13 +1264,15 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int64_t off = (int64_t)(g + t * s0) * ts;
+    // qrev (start only): Q read with its time lines reversed, i.e. Y Q
+    const int64_t offq = (!FULL && qrev) ? (int64_t)(L - 1 - (g + t * s0)) * ts : off;
     T a, b;
     if constexpr (sizeof(TQ) > sizeof(T)) {
-      a = T((double)Q[la + off] * cq);
-      b = T((double)Q[lb + off] * cq);
+      a = T((double)Q[la + offq] * cq);
+      b = T((double)Q[lb + offq] * cq);
     } else {
-      a = T(cq) * Q[la + off];
-      b = T(cq) * Q[lb + off];
+      a = T(cq) * Q[la + offq];
+      b = T(cq) * Q[lb + offq];
     }
     if (FULL) {
       a += cv * V1[la + off] + cvp * V2[la + off];
@@ -1321,16 +1323,16 @@ template <typename T, int L, typename TQ, bool FULL, bool MM, bool PREC = true, 
 BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restrict__ Q,
                            const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                            T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
-                           const double* __restrict__ coef, double* __restrict__ partials) {
+                           const double* __restrict__ coef, double* __restrict__ partials, bool qrev = false) {
   const int64_t ntiles = fft_tiles<T, FK_SPEC>(L, M);
   double part = 0.0;
   if constexpr (upd_persistent<T>()) {
     for (int64_t tile = ctx.bid; tile < ntiles; tile += ctx.nbx)
       part += time_upd_tile<T, L, TQ, FULL, MM, tpb_fft<T, FK_SPEC>(), PREC>(ctx, lds, tile, Q, V1, V2, Vout, Zout,
-                                                                             M, tb, coef);
+                                                                             M, tb, coef, qrev);
   } else {
     part = time_upd_tile<T, L, TQ, FULL, MM, tpb_fft<T, FK_SPEC>(), PREC>(ctx, lds, ctx.bid, Q, V1, V2, Vout, Zout,
-                                                                            M, tb, coef);
+                                                                            M, tb, coef, qrev);
   }
   const double sum = block_sum<tpb_fft<T, FK_SPEC>()>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;
@@ -1378,45 +1380,39 @@ BLTT_HD void rhs_body(Ctx& ctx, double* red, const double* __restrict__ f, TO* _
   if (ctx.tid == 0) partials[ctx.bid] = s;
 }
 
-// b = Y f in the mode-major layout (each time line reversed), partial sums of ||b||^2
-template <class Ctx>
-BLTT_HD void rhs_mm_body(Ctx& ctx, double* red, const double* __restrict__ f, double* __restrict__ b, int log2N,
-                         int64_t n_total, double* __restrict__ partials) {
-  const int64_t N = (int64_t)1 << log2N;
-  double part = 0.0;
-  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
-  for (int64_t e = (int64_t)ctx.bid * TPB_EW + ctx.tid; e < n_total; e += stride) {
-    const int64_t i = e >> log2N, n = e & (N - 1);
-    const double val = f[(i << log2N) + (N - 1 - n)];
-    b[e] = val;
-    part += val * val;
-  }
-  const double s = block_sum<TPB_EW>(ctx, red, part);
-  if (ctx.tid == 0) partials[ctx.bid] = s;
-}
-
 // out = in^T for an R x C row-major matrix (out is C x R), through a 64 x 64
 // LDS tile (padded rows); REV also reverses the order of the R index in out.
 // Moves vectors between the time-major ABI layout (R = N, C = M) and the
-// mode-major sine-basis layout (R = M, C = N for the way back).
+// mode-major sine-basis layout (R = M, C = N for the way back).  With
+// partials (and red, TPB_EW doubles of LDS), also one partial sum of the
+// squares of the values moved per workgroup (the norm of the right-hand side).
 constexpr int TR_TILE = 64;
 template <typename T, bool REV, class Ctx>
 BLTT_HD void transpose_body(Ctx& ctx, T* tile, const T* __restrict__ in, T* __restrict__ out, int64_t R,
-                            int64_t C) {
+                            int64_t C, double* red = nullptr, double* __restrict__ partials = nullptr) {
   constexpr int P = TR_TILE + 1, ROWS = TPB_EW / TR_TILE;
   const int64_t tiles_c = (C + TR_TILE - 1) / TR_TILE;
   const int64_t c0 = ((int64_t)ctx.bid % tiles_c) * TR_TILE, r0 = ((int64_t)ctx.bid / tiles_c) * TR_TILE;
   const int tx = ctx.tid % TR_TILE, ty = ctx.tid / TR_TILE;
+  double part = 0.0;
 #pragma unroll
   for (int k = 0; k < TR_TILE; k += ROWS) {
     const int64_t r = r0 + ty + k, c = c0 + tx;
-    if (r < R && c < C) tile[(ty + k) * P + tx] = in[r * C + c];
+    if (r < R && c < C) {
+      const T x = in[r * C + c];
+      tile[(ty + k) * P + tx] = x;
+      part += (double)x * (double)x;
+    }
   }
   ctx.sync();
 #pragma unroll
   for (int k = 0; k < TR_TILE; k += ROWS) {
     const int64_t c = c0 + ty + k, r = r0 + tx;
     if (r < R && c < C) out[c * R + (REV ? R - 1 - r : r)] = tile[tx * P + ty + k];
+  }
+  if (partials) {
+    const double sum = block_sum<TPB_EW>(ctx, red, part);
+    if (ctx.tid == 0) partials[ctx.bid] = sum;
   }
 }
 

@@ -14,19 +14,13 @@ __global__ __launch_bounds__(TPB_EW) void k_rhs(const double* __restrict__ f, TO
   rhs_body<TO>(ctx, red, f, b, N, M, scale, partials);
 }
 
-__global__ __launch_bounds__(TPB_EW) void k_rhs_mm(const double* __restrict__ f, double* __restrict__ b, int log2N,
-                                                   int64_t n, double* __restrict__ partials) {
-  __shared__ double red[TPB_EW];
-  DevCtx ctx = make_ctx();
-  rhs_mm_body(ctx, red, f, b, log2N, n, partials);
-}
-
 template <typename T, bool REV>
 __global__ __launch_bounds__(TPB_EW) void k_transpose(const T* __restrict__ in, T* __restrict__ out, int64_t R,
-                                                      int64_t C) {
+                                                      int64_t C, double* __restrict__ partials) {
   __shared__ T tile[TR_TILE * (TR_TILE + 1)];
+  __shared__ double red[TPB_EW];
   DevCtx ctx = make_ctx();
-  transpose_body<T, REV>(ctx, tile, in, out, R, C);
+  transpose_body<T, REV>(ctx, tile, in, out, R, C, red, partials);
 }
 
 template <typename T, typename TX>
@@ -88,28 +82,20 @@ __global__ __launch_bounds__(TPB_EW) void k_combine(double* __restrict__ u, ZLis
   combine_body<T>(ctx, u, zl, y, sptr, n);
 }
 
-hipError_t launch_rhs_mm(const double* f, double* b, int64_t N, int64_t M, double* partials, int64_t* nparts,
-                         hipStream_t s) {
-  int log2N = 0;
-  while (((int64_t)1 << log2N) < N) ++log2N;
-  if (((int64_t)1 << log2N) != N) return hipErrorInvalidValue;
-  const int64_t n = N * M, blocks = ew_blocks(n);
-  if (nparts) *nparts = blocks;
-  hipLaunchKernelGGL(k_rhs_mm, dim3((unsigned)blocks), dim3(TPB_EW), 0, s, f, b, log2N, n, partials);
-  return hipGetLastError();
-}
-
 template <typename T>
-hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev, hipStream_t s) {
+hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev, double* partials, int64_t* nparts,
+                            hipStream_t s) {
   const int64_t nb = ((C + TR_TILE - 1) / TR_TILE) * ((R + TR_TILE - 1) / TR_TILE);
   if (nb < 1 || nb > 2147483647LL) return hipErrorInvalidValue;
+  if (nparts) *nparts = nb;
   if (rev)
-    hipLaunchKernelGGL((k_transpose<T, true>), dim3((unsigned)nb), dim3(TPB_EW), 0, s, in, out, R, C);
+    hipLaunchKernelGGL((k_transpose<T, true>), dim3((unsigned)nb), dim3(TPB_EW), 0, s, in, out, R, C, partials);
   else
-    hipLaunchKernelGGL((k_transpose<T, false>), dim3((unsigned)nb), dim3(TPB_EW), 0, s, in, out, R, C);
+    hipLaunchKernelGGL((k_transpose<T, false>), dim3((unsigned)nb), dim3(TPB_EW), 0, s, in, out, R, C, partials);
   return hipGetLastError();
 }
-template hipError_t launch_transpose<double>(const double*, double*, int64_t, int64_t, bool, hipStream_t);
+template hipError_t launch_transpose<double>(const double*, double*, int64_t, int64_t, bool, double*, int64_t*,
+                                             hipStream_t);
 
 template <typename T>
 hipError_t launch_combine(double* u, const ZList<T>& zl, const double* y, const double* sptr, int64_t n,

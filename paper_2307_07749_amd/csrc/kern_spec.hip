@@ -20,7 +20,7 @@ template <typename T, int L, typename TQ, bool FULL, bool PREC>
 __global__ __attribute__((amdgpu_waves_per_eu(min_waves_upd<T>(), max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_time_upd(
     const TQ* __restrict__ Q, const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
     T* __restrict__ Zout, int64_t M, TimeTables<T> tb, const double* __restrict__ coef,
-    double* __restrict__ partials) {
+    double* __restrict__ partials, int qrev) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NL = tpb_fft<T, FK_SPEC>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, false, LAST_PAIRED>;
@@ -39,11 +39,11 @@ __global__ __attribute__((amdgpu_waves_per_eu(min_waves_upd<T>(), max_waves_fft<
     tb.rho = tabs + 2 * L;
   }
   time_upd_body<T, L, TQ, FULL, true, PREC>(ctx, reinterpret_cast<cx<T>*>(smem), red, Q, V1, V2, Vout, Zout, M, tb,
-                                            coef, partials);
+                                            coef, partials, qrev != 0);
 }
 
 template <typename T, typename TQ, int L>
-static hipError_t go_upd(bool full, bool prec, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
+static hipError_t go_upd(bool full, bool prec, bool qrev, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                          const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
                          int64_t* nparts, hipStream_t s) {
   const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
@@ -55,31 +55,32 @@ static hipError_t go_upd(bool full, bool prec, const TQ* Q, const T* V1, const T
     if constexpr (sizeof(T) == 8) {
       if (full)
         hipLaunchKernelGGL((k_time_upd<T, L, TQ, true, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()),
-                           lds, s, Q, V1, V2, Vout, Zout, M, tb, coef, partials);
+                           lds, s, Q, V1, V2, Vout, Zout, M, tb, coef, partials, qrev ? 1 : 0);
       else
         hipLaunchKernelGGL((k_time_upd<T, L, TQ, false, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()),
-                           lds, s, Q, V1, V2, Vout, Zout, M, tb, coef, partials);
+                           lds, s, Q, V1, V2, Vout, Zout, M, tb, coef, partials, qrev ? 1 : 0);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
   }
   if (full)
     hipLaunchKernelGGL((k_time_upd<T, L, TQ, true, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds, s,
-                       Q, V1, V2, Vout, Zout, M, tb, coef, partials);
+                       Q, V1, V2, Vout, Zout, M, tb, coef, partials, qrev ? 1 : 0);
   else
     hipLaunchKernelGGL((k_time_upd<T, L, TQ, false, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_SPEC>()), lds,
-                       s, Q, V1, V2, Vout, Zout, M, tb, coef, partials);
+                       s, Q, V1, V2, Vout, Zout, M, tb, coef, partials, qrev ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename T, typename TQ>
 hipError_t launch_time_upd(int L, bool full, bool prec, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                            const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
-                           int64_t* nparts, hipStream_t s) {
+                           int64_t* nparts, hipStream_t s, bool qrev) {
   if (full && (!V1 || !V2)) return hipErrorInvalidValue;
+  if (full && qrev) return hipErrorInvalidValue;
   switch (L) {
 #define BLTT_CASE(LL) \
-  case LL: return go_upd<T, TQ, LL>(full, prec, Q, V1, V2, Vout, Zout, M, tb, coef, partials, max_blocks, nparts, s);
+  case LL: return go_upd<T, TQ, LL>(full, prec, qrev, Q, V1, V2, Vout, Zout, M, tb, coef, partials, max_blocks, nparts, s);
     BLTT_CASE(2) BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64)
     BLTT_CASE(128) BLTT_CASE(256) BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
 #undef BLTT_CASE
@@ -90,7 +91,7 @@ hipError_t launch_time_upd(int L, bool full, bool prec, const TQ* Q, const T* V1
 #define BLTT_INST(T, TQ)                                                                                      \
   template hipError_t launch_time_upd<T, TQ>(int, bool, bool, const TQ*, const T*, const T*, T*, T*, int64_t,      \
                                              const TimeTables<T>&, const double*, double*, int64_t, int64_t*,  \
-                                             hipStream_t);
+                                             hipStream_t, bool);
 BLTT_INST(float, float)
 BLTT_INST(float, double)
 BLTT_INST(double, double)

@@ -41,10 +41,11 @@ hipError_t launch_time_prec(int L, T* x, int64_t M, const TimeTables<T>& tb, hip
 // Zout = P^{-1} vhat (time pass), per-workgroup partial sums of <vhat, Zout>
 // (persistent: at most max_blocks workgroups, *nparts receives the partial count)
 // prec false: no preconditioner (Zout = vhat; FP64 only)
+// qrev (start only): read Q with its time lines reversed, i.e. vhat = cq Y Q
 template <typename T, typename TQ>
 hipError_t launch_time_upd(int L, bool full, bool prec, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                            const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
-                           int64_t* nparts, hipStream_t s);
+                           int64_t* nparts, hipStream_t s, bool qrev = false);
 
 // up: refinement update of the iterate z (MV_RESID with TERM_SPEC only; k = 0 for none)
 template <typename T>
@@ -80,12 +81,11 @@ hipError_t configure_kernels_once();
 template <typename T>
 hipError_t launch_resid_stencil(T* r, const VupdStencil<T>& st, int64_t nlines, double* partials, int64_t* nparts,
                                 hipStream_t s);
-// b = Y f on mode-major vectors (N a power of two) and partial sums of ||b||^2
-hipError_t launch_rhs_mm(const double* f, double* b, int64_t N, int64_t M, double* partials, int64_t* nparts,
-                         hipStream_t s);
-// out (C x R) = in^T (in: R x C, row-major); rev reverses the R index
+// out (C x R) = in^T (in: R x C, row-major); rev reverses the R index; with
+// partials, one partial sum of squares per workgroup (*nparts of them)
 template <typename T>
-hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev, hipStream_t s);
+hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev, double* partials,
+                            int64_t* nparts, hipStream_t s);
 template <typename TO>
 hipError_t launch_rhs(const double* f, TO* b, int64_t N, int64_t M, double scale, double* partials,
                       int64_t* nparts, hipStream_t s);

@@ -69,7 +69,7 @@ def lib():
             getattr(L, f"emu_sym_spec_{t}").argtypes = args + [P, P, ctypes.c_int]
             getattr(L, f"emu_sym_spec_{t}").restype = ctypes.c_double
             getattr(L, f"emu_wx_{t}").argtypes = [P, P, P, P, ctypes.c_int64, P]
-        L.emu_time_upd_mixed.argtypes = args + [P, P, P, P]
+        L.emu_time_upd_mixed.argtypes = args + [P, P, P, P, ctypes.c_int]
         L.emu_time_upd_mixed.restype = ctypes.c_double
         L.emu_resid_spec_f64.argtypes = args + [P, P, P, ctypes.c_int]
         L.emu_resid_spec_f64.restype = ctypes.c_double
@@ -78,8 +78,7 @@ def lib():
         L.emu_resid_upd_f64.restype = ctypes.c_double
         L.emu_state_size.restype = ctypes.c_int64
         L.emu_transpose_f64.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
-        L.emu_rhs_mm.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
-        L.emu_rhs_mm.restype = ctypes.c_double
+        L.emu_transpose_f64.restype = ctypes.c_double
         L.emu_state_offsets.argtypes = [P]
         L.emu_scalar.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P, P, P, ctypes.c_int]
         L.emu_combine_f32.argtypes = [P, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int64]
@@ -209,9 +208,10 @@ def _ptr(g):
     return None if g is None else g.ptr
 
 
-def time_upd(prob, Q, V1, V2, coef, full, dtype=np.float64, write_v=True):
-    """vhat = c0 Q (+ c1 V1 + c2 V2), zhat = P^{-1} vhat in sine coordinates;
-    returns (vhat as stored or None, zhat, <vhat, zhat>)."""
+def time_upd(prob, Q, V1, V2, coef, full, dtype=np.float64, write_v=True, qrev=False):
+    """vhat = c0 Q (+ c1 V1 + c2 V2), zhat = P^{-1} vhat in sine coordinates
+    (qrev, start only: vhat = c0 Y Q); returns (vhat as stored or None, zhat,
+    <vhat, zhat>)."""
     args, keep = _common(prob)
     gq = Guarded(Q, dtype)
     g1 = Guarded(V1, dtype) if V1 is not None else None
@@ -220,19 +220,19 @@ def time_upd(prob, Q, V1, V2, coef, full, dtype=np.float64, write_v=True):
     gz = Guarded(np.zeros(prob.n), dtype)
     c = np.ascontiguousarray(coef, dtype=np.float64)
     dot = getattr(lib(), f"emu_time_upd_{_tag(dtype)}")(*args, gq.ptr, _ptr(g1), _ptr(g2), _ptr(gv), gz.ptr,
-                                                        c.ctypes.data, int(full))
+                                                        c.ctypes.data, 2 if qrev else int(full))
     _check(*[g for g in (gq, g1, g2, gv, gz) if g is not None])
     return (gv.data.copy() if gv is not None else None), gz.data.copy(), dot
 
 
-def time_upd_mixed(prob, Q64, coef):
-    """FP32 pass on an FP64 right-hand side scaled by coef[0]."""
+def time_upd_mixed(prob, Q64, coef, qrev=False):
+    """FP32 pass on an FP64 right-hand side scaled by coef[0] (qrev: on Y Q64)."""
     args, keep = _common(prob)
     gq = Guarded(Q64, np.float64)
     gv = Guarded(np.zeros(prob.n), np.float32)
     gz = Guarded(np.zeros(prob.n), np.float32)
     c = np.ascontiguousarray(coef, dtype=np.float64)
-    dot = lib().emu_time_upd_mixed(*args, gq.ptr, gv.ptr, gz.ptr, c.ctypes.data)
+    dot = lib().emu_time_upd_mixed(*args, gq.ptr, gv.ptr, gz.ptr, c.ctypes.data, int(qrev))
     _check(gq, gv, gz)
     return gv.data.copy(), gz.data.copy(), dot
 
@@ -315,21 +315,14 @@ def wx(Z, Wa, Wb, X, coef_ptr):
     getattr(lib(), f"emu_wx_{tag}")(Z.ctypes.data, Wa.ctypes.data, Wb.ctypes.data, X.ctypes.data, Z.size, coef_ptr)
 
 
-def transpose(x, R, C, rev=False):
-    """out (C x R) = x (R x C)^T through the library's tiled transpose."""
+def transpose(x, R, C, rev=False, with_norm=False):
+    """out (C x R) = x (R x C)^T through the library's tiled transpose (and the
+    sum of squares its workgroups report)."""
     gi = Guarded(x, np.float64)
     go = Guarded(np.zeros(x.size), np.float64)
-    lib().emu_transpose_f64(gi.ptr, go.ptr, R, C, int(rev))
+    s = lib().emu_transpose_f64(gi.ptr, go.ptr, R, C, int(rev))
     _check(gi, go)
-    return go.data.copy()
-
-
-def rhs_mm(f, N, M):
-    gf = Guarded(f, np.float64)
-    gb = Guarded(np.zeros(f.size), np.float64)
-    s = lib().emu_rhs_mm(gf.ptr, gb.ptr, N, M)
-    _check(gf, gb)
-    return gb.data.copy(), s
+    return (go.data.copy(), s) if with_norm else go.data.copy()
 
 
 def combine_f32(u, Zs, y, s):

@@ -467,7 +467,7 @@ struct UpdRun {
   template <int L>
   struct R {
     static void run(const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M, const TimeTables<T>& tb,
-                    const double* coef, double* partials, bool full) {
+                    const double* coef, double* partials, bool full, bool qrev) {
       constexpr int NL = lines_per_block<T, FK_SPEC>(L);
       using Ft = LineFft<T, L, NL, false, LAST_PAIRED>;
       // fewer workgroups than tiles: every workgroup walks several tiles
@@ -480,7 +480,7 @@ struct UpdRun {
                                                        tb, coef, partials);
                  else
                    time_upd_body<T, L, TQ, false, true>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout,
-                                                        M, tb, coef, partials);
+                                                        M, tb, coef, partials, qrev);
                });
     }
   };
@@ -488,11 +488,11 @@ struct UpdRun {
 
 template <typename T, typename TQ>
 double apply_time_upd(const Problem& P, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, const double* coef,
-                      bool full) {
+                      bool full, bool qrev = false) {
   HostTables<T> ht(P);
   TimeTables<T> tt = time_tables<T>(P, ht);
   std::vector<double> partials((size_t)fft_tiles<T, FK_SPEC>((int)P.N, P.M), 0.0);
-  with_L<UpdRun<T, TQ>::template R>((int)P.N, Q, V1, V2, Vout, Zout, P.M, tt, coef, partials.data(), full);
+  with_L<UpdRun<T, TQ>::template R>((int)P.N, Q, V1, V2, Vout, Zout, P.M, tt, coef, partials.data(), full, qrev);
   double s = 0.0;
   for (double v : partials) s += v;
   return s;
@@ -613,24 +613,19 @@ void apply_wx(const T* Z, T* Wa, const T* Wb, T* X, int64_t n, const double* coe
   run_grid(TPB_EW, nb, 1, 0, [&](HostCtx& c, unsigned char*) { wx_body<T, T>(c, Z, Wa, Wb, X, n, coef); });
 }
 
-void apply_transpose(const double* in, double* out, int64_t R, int64_t C, bool rev) {
+// the tiled transpose, and the sum of its per-workgroup partial sums of squares
+double apply_transpose(const double* in, double* out, int64_t R, int64_t C, bool rev) {
   const int64_t nb = ((C + TR_TILE - 1) / TR_TILE) * ((R + TR_TILE - 1) / TR_TILE);
-  run_grid(TPB_EW, (int)nb, 1, sizeof(double) * TR_TILE * (TR_TILE + 1), [&](HostCtx& c, unsigned char* lds) {
-    if (rev)
-      transpose_body<double, true>(c, reinterpret_cast<double*>(lds), in, out, R, C);
-    else
-      transpose_body<double, false>(c, reinterpret_cast<double*>(lds), in, out, R, C);
-  });
-}
-
-double apply_rhs_mm(const double* f, double* b, int64_t N, int64_t M) {
-  int log2N = 0;
-  while (((int64_t)1 << log2N) < N) ++log2N;
-  const int gx = (int)std::min<int64_t>((N * M + TPB_EW - 1) / TPB_EW, 5);
-  std::vector<double> partials((size_t)gx);
-  run_grid(TPB_EW, gx, 1, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
-    rhs_mm_body(c, reinterpret_cast<double*>(lds), f, b, log2N, N * M, partials.data());
-  });
+  std::vector<double> partials((size_t)nb, 0.0);
+  run_grid(TPB_EW, (int)nb, 1, sizeof(double) * (TR_TILE * (TR_TILE + 1) + TPB_EW),
+           [&](HostCtx& c, unsigned char* lds) {
+             double* tile = reinterpret_cast<double*>(lds);
+             double* red = tile + TR_TILE * (TR_TILE + 1);
+             if (rev)
+               transpose_body<double, true>(c, tile, in, out, R, C, red, partials.data());
+             else
+               transpose_body<double, false>(c, tile, in, out, R, C, red, partials.data());
+           });
   double s = 0.0;
   for (double v : partials) s += v;
   return s;
@@ -640,10 +635,9 @@ double apply_rhs_mm(const double* f, double* b, int64_t N, int64_t M) {
 
 extern "C" {
 
-void emu_transpose_f64(const double* in, double* out, int64_t R, int64_t C, int rev) {
-  apply_transpose(in, out, R, C, rev != 0);
+double emu_transpose_f64(const double* in, double* out, int64_t R, int64_t C, int rev) {
+  return apply_transpose(in, out, R, C, rev != 0);
 }
-double emu_rhs_mm(const double* f, double* b, int64_t N, int64_t M) { return apply_rhs_mm(f, b, N, M); }
 
 int64_t emu_state_size(void) { return (int64_t)sizeof(SolverState); }
 // byte offsets: coef_v, coef_w, eta, eta0, status, rinv, rscale, iter
@@ -717,15 +711,15 @@ double emu_resid_f64(EMU_ARGS, const double* u, const double* f, double* r) {
 double emu_time_aux_f32(EMU_ARGS, float* x) { return apply_time_aux<float>(EMU_P, x); }
 double emu_time_upd_f64(EMU_ARGS, const double* Q, const double* V1, const double* V2, double* Vout, double* Zout,
                         const double* coef, int full) {
-  return apply_time_upd<double, double>(EMU_P, Q, V1, V2, Vout, Zout, coef, full != 0);
+  return apply_time_upd<double, double>(EMU_P, Q, V1, V2, Vout, Zout, coef, full == 1, full == 2);
 }
 double emu_time_upd_f32(EMU_ARGS, const float* Q, const float* V1, const float* V2, float* Vout, float* Zout,
                         const double* coef, int full) {
-  return apply_time_upd<float, float>(EMU_P, Q, V1, V2, Vout, Zout, coef, full != 0);
+  return apply_time_upd<float, float>(EMU_P, Q, V1, V2, Vout, Zout, coef, full == 1, full == 2);
 }
-double emu_time_upd_mixed(EMU_ARGS, const double* Q, float* Vout, float* Zout, const double* coef) {
+double emu_time_upd_mixed(EMU_ARGS, const double* Q, float* Vout, float* Zout, const double* coef, int qrev) {
   return apply_time_upd<float, double>(EMU_P, Q, (const float*)nullptr, (const float*)nullptr, Vout, Zout, coef,
-                                       false);
+                                       false, qrev != 0);
 }
 // form: 0 direct (short p), 1 N-point circulant + skew-circulant, 2 zero-padded 2N-point
 double emu_sym_spec_f64(EMU_ARGS, const double* z, double* out, int form) {
