@@ -350,13 +350,15 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
     if (TERM == TERM_SPEC) {
       // taps beyond qtaps have q_k = 0; times before 0 read slot 0 with weight 0
       T sa = tb.q[0] * zin[t].re, sb = tb.q[0] * zin[t].im;
+      if (tb.qtaps > 1) {
 #pragma unroll
-      for (int k = 1; k < 4; ++k) {
-        const int nk = n - k;
-        const T w = nk >= 0 ? tb.q[k] : T(0);
-        const cx<T> zk = lds[F::idx(c, nk >= 0 ? nk : 0)];
-        sa += w * zk.re;
-        sb += w * zk.im;
+        for (int k = 1; k < 4; ++k) {
+          const int nk = n - k;
+          const T w = nk >= 0 ? tb.q[k] : T(0);
+          const cx<T> zk = lds[F::idx(c, nk >= 0 ? nk : 0)];
+          sa += w * zk.re;
+          sb += w * zk.im;
+        }
       }
       ya += mua * sa;
       yb += mub * sb;
@@ -422,13 +424,14 @@ struct MatvecCSTables {
   int qtaps;
 };
 
-// TPB: workgroup size (2*TPB/G modes per tile); the batched kernels choose it per shape
-template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), class Ctx>
+// TPB: workgroup size (2*TPB/G modes per tile); the batched kernels choose it per shape.
+// TWL: tb.tw is the LDS stage-twiddle table (cs_stage_tables).
+template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), bool TWL = false, class Ctx>
 BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
                               const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up) {
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L;
-  using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
+  using F = LineFft<T, L, NL, false, LAST_DEFAULT, TWL>;
   const int tid = ctx.tid, c = tid / G, g = tid % G;
   const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
@@ -518,13 +521,16 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   for (int t = 0; t < V; ++t) {
     const int n = g + t * s0;
     T sqa = tb.q[0] * zin[t].re, sqb = tb.q[0] * zin[t].im;
+    if (tb.qtaps > 1) {
+      // taps beyond qtaps have q_k = 0; times before 0 read slot 0 with weight 0
 #pragma unroll
-    for (int k = 1; k < 4; ++k) {
-      const int nk = n - k;
-      const T w = nk >= 0 ? tb.q[k] : T(0);
-      const cx<T> zk = lds[F::idx(c, nk >= 0 ? nk : 0)];
-      sqa += w * zk.re;
-      sqb += w * zk.im;
+      for (int k = 1; k < 4; ++k) {
+        const int nk = n - k;
+        const T w = nk >= 0 ? tb.q[k] : T(0);
+        const cx<T> zk = lds[F::idx(c, nk >= 0 ? nk : 0)];
+        sqa += w * zk.re;
+        sqb += w * zk.im;
+      }
     }
     const T ya = acc[t].re + mua * sqa, yb = acc[t].im + mub * sqb;
     const int64_t er = N - 1 - n;
@@ -556,15 +562,51 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   return part;
 }
 
+// LDS staging of the four N-entry tables of the N-point matvec (when they fit
+// beside the exchange lines, two workgroups per CU): the stage twiddles in the
+// LineFft TWL layout, the two spectra and e^{i pi n/N}.
+template <typename T, int L>
+constexpr size_t cs_lds_base() { return fft_lds_bytes<T, FK_SPEC>(L); }
+template <typename T, int L>
+constexpr bool cs_stage() { return cs_lds_base<T, L>() + 4 * (size_t)L * sizeof(cx<T>) <= 80 * 1024; }
+template <typename T, int L>
+constexpr size_t cs_lds_bytes() { return cs_lds_base<T, L>() + (cs_stage<T, L>() ? 4 * (size_t)L * sizeof(cx<T>) : 0); }
+
+template <typename T, int L, int TPB, class Ctx>
+BLTT_HD MatvecCSTables<T> cs_stage_tables(Ctx& ctx, cx<T>* tabs, const MatvecCSTables<T>& tb) {
+  using F = LineFft<T, L, TPB / (L / fft_V(L)), false, LAST_DEFAULT, true>;
+  F::build_twl(ctx, tabs, tb.tw, TPB);
+  for (int i = ctx.tid; i < L; i += TPB) {
+    tabs[L + i] = tb.chat[i];
+    tabs[2 * L + i] = tb.shat[i];
+    tabs[3 * L + i] = tb.omega[i];
+  }
+  ctx.sync();
+  MatvecCSTables<T> t = tb;
+  t.tw = tabs;
+  t.chat = tabs + L;
+  t.shat = tabs + 2 * L;
+  t.omega = tabs + 3 * L;
+  return t;
+}
+
 // One tile per workgroup (a loop over tiles lets the compiler keep the
 // loop-invariant twiddle and spectrum loads live across tiles, which costs
-// half the occupancy here); one partial sum per workgroup.
+// half the occupancy here); one partial sum per workgroup.  `tabs`: LDS for
+// the staged tables when cs_stage holds.
 template <typename T, int L, int MODE, class Ctx>
-BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restrict__ out,
+BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, cx<T>* tabs, T* z, T* __restrict__ out,
                             const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
                             double* __restrict__ partials) {
-  const double part = matvec_cs_tile<T, L, MODE>(ctx, lds, ctx.bid, z, out, fin, M, tb, up);
-  const double sum = block_sum<tpb_fft<T, FK_SPEC>()>(ctx, red, part);
+  constexpr int TPB = tpb_fft<T, FK_SPEC>();
+  double part;
+  if constexpr (cs_stage<T, L>()) {
+    const MatvecCSTables<T> ts = cs_stage_tables<T, L, TPB>(ctx, tabs, tb);
+    part = matvec_cs_tile<T, L, MODE, TPB, true>(ctx, lds, ctx.bid, z, out, fin, M, ts, up);
+  } else {
+    part = matvec_cs_tile<T, L, MODE, TPB, false>(ctx, lds, ctx.bid, z, out, fin, M, tb, up);
+  }
+  const double sum = block_sum<TPB>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;
 }
 
@@ -1229,13 +1271,13 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 // ---------------------------------------------------------------------------
 // PREC false: no preconditioner (zhat = vhat), the MINRES-I comparator
 template <typename T, int L, typename TQ, bool FULL, bool MM, int TPB = tpb_fft<T, FK_SPEC>(), bool PREC = true,
-          class Ctx>
+          bool TWL = false, class Ctx>
 BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __restrict__ Q,
                              const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                              T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
                              const double* __restrict__ coef, bool qrev = false) {
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
-  using F = LineFft<T, L, NL, !MM, LAST_PAIRED>;
+  using F = LineFft<T, L, NL, !MM, LAST_PAIRED, TWL>;
   const T invN = T(1) / T(L);
   const int tid = ctx.tid, c = MM ? tid / G : tid % NL;
   int g = MM ? tid % G : tid / NL;
@@ -1313,6 +1355,13 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
   return part;
 }
 
+// The persistent FP32 time pass takes its stage twiddles from an LDS table
+// (tb.tw then points to it; built once per workgroup).
+template <typename T>
+constexpr bool upd_twl() { return sizeof(T) == 4; }
+template <typename T, int L>
+constexpr size_t upd_twl_bytes() { return upd_twl<T>() ? (size_t)L * sizeof(cx<T>) : 0; }
+
 // FP32 runs persistently (workgroup b takes tiles b, b + nbx, ...); FP64,
 // whose registers allow one wavefront per SIMD, one tile per workgroup.  One
 // partial sum of <vhat, zhat> per workgroup.
@@ -1324,15 +1373,25 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
                            const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                            T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
                            const double* __restrict__ coef, double* __restrict__ partials, bool qrev = false) {
+  constexpr int TPB = tpb_fft<T, FK_SPEC>();
   const int64_t ntiles = fft_tiles<T, FK_SPEC>(L, M);
+  TimeTables<T> tl = tb;
+  if constexpr (upd_twl<T>() && PREC) {
+    // the stage twiddles in LDS, after the exchange lines and the reduction slots
+    using F = LineFft<T, L, TPB / (L / fft_V(L)), !MM, LAST_PAIRED, true>;
+    cx<T>* twl = reinterpret_cast<cx<T>*>(red + TPB);
+    F::build_twl(ctx, twl, tb.tw, TPB);
+    ctx.sync();
+    tl.tw = twl;
+  }
   double part = 0.0;
   if constexpr (upd_persistent<T>()) {
     for (int64_t tile = ctx.bid; tile < ntiles; tile += ctx.nbx)
-      part += time_upd_tile<T, L, TQ, FULL, MM, tpb_fft<T, FK_SPEC>(), PREC>(ctx, lds, tile, Q, V1, V2, Vout, Zout,
-                                                                             M, tb, coef, qrev);
+      part += time_upd_tile<T, L, TQ, FULL, MM, TPB, PREC, upd_twl<T>() && PREC>(ctx, lds, tile, Q, V1, V2, Vout,
+                                                                                 Zout, M, tl, coef, qrev);
   } else {
-    part = time_upd_tile<T, L, TQ, FULL, MM, tpb_fft<T, FK_SPEC>(), PREC>(ctx, lds, ctx.bid, Q, V1, V2, Vout, Zout,
-                                                                            M, tb, coef, qrev);
+    part = time_upd_tile<T, L, TQ, FULL, MM, TPB, PREC, upd_twl<T>() && PREC>(ctx, lds, ctx.bid, Q, V1, V2, Vout,
+                                                                               Zout, M, tl, coef, qrev);
   }
   const double sum = block_sum<tpb_fft<T, FK_SPEC>()>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;

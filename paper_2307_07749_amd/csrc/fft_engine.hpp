@@ -13,7 +13,8 @@
 //
 // Conventions: forward X[k] = sum_n x[n] exp(-2 pi i n k / L); the inverse
 // returns L x (unnormalised).  Twiddles come from a table tw[k] =
-// exp(-2 pi i k / L), k < L, computed on the host in double precision.
+// exp(-2 pi i k / L), k < L, computed on the host in double precision (or
+// from a per-workgroup LDS copy of the entries each stage needs, TWL).
 //
 // Everything here is __host__ __device__ so the same code can be run by the
 // CPU workgroup emulator used in the tests; `Ctx::sync()` is the workgroup
@@ -183,7 +184,11 @@ enum LastMode {
   LAST_PAIRED = 2    // k_low and K - k_low in one thread (k <-> L-k pairs in registers)
 };
 
-template <typename T, int L, int NL, bool INTERLEAVED, int LAST>
+// TWL: the stage twiddles come from a per-workgroup LDS table (built once with
+// build_twl) instead of power products of the global table: for stage s, entry
+// off_s + (u-1) sg_s + j holds w^(u j L/B_s) for butterfly j = beta mod sg_s,
+// so consecutive lanes read consecutive entries.
+template <typename T, int L, int NL, bool INTERLEAVED, int LAST, bool TWL = false>
 struct LineFft {
   static constexpr int V = fft_V(L);
   static constexpr int S = fft_S(L);
@@ -202,6 +207,38 @@ struct LineFft {
   BLTT_HD static void xsync(Ctx& ctx) {
     if constexpr (WAVE_LOCAL) ctx.wsync();
     else ctx.sync();
+  }
+  // LDS twiddle table: offset of stage s, and the total length (< L)
+  static constexpr int twl_off(int s) {
+    int o = 0;
+    for (int i = 0; i < s; ++i) o += (fft_r(L, i) - 1) * fft_sigma(L, i);
+    return o;
+  }
+  static constexpr int TWL_LEN = twl_off(S - 1) > 0 ? twl_off(S - 1) : 1;
+  // fill the LDS table from the global one (all threads of the workgroup; the
+  // caller synchronises before first use)
+  template <class Ctx>
+  BLTT_HD static void build_twl(Ctx& ctx, cx<T>* twl, const cx<T>* tw, int nthreads) {
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s) {
+      const int r = fft_r(L, s), sg = fft_sigma(L, s), LB = L / (r * sg), o = twl_off(s);
+      for (int i = ctx.tid; i < (r - 1) * sg; i += nthreads) {
+        const int u = i / sg + 1, j = i % sg;
+        twl[o + i] = tw[u * j * LB];
+      }
+    }
+  }
+  template <int s, int r>
+  BLTT_HD static void stage_twiddles(cx<T>* pw, const cx<T>* tw, int b) {
+    constexpr int sg = fft_sigma(L, s), B = r * sg;
+    if constexpr (TWL) {
+      constexpr int o = twl_off(s);
+      const int j = b % sg;
+#pragma unroll
+      for (int u = 1; u < r; ++u) pw[u] = tw[o + (u - 1) * sg + j];
+    } else {
+      twiddle_powers<r>(pw, tw, (b % sg) * (L / B));
+    }
   }
   static_assert(S == 1 || fft_r(L, 0) == V, "first stage must use all registers");
   static_assert(LAST != LAST_PAIRED || S == 1 || V >= 2 * RL, "pairing needs two butterflies");
@@ -271,7 +308,7 @@ struct LineFft {
 
   template <int s, class Ctx>
   BLTT_HD static void fwd_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
-    constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), B = r * sg, NB = V / r;
+    constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), NB = V / r;
     if constexpr (s > 0) {
 #pragma unroll
       for (int w = 0; w < NB; ++w) {
@@ -285,7 +322,7 @@ struct LineFft {
       dft<r, -1>(v + w * r);
       if constexpr (sg > 1) {
         cx<T> pw[r];
-        twiddle_powers<r>(pw, tw, (beta<s>(g, w) % sg) * (L / B));
+        stage_twiddles<s, r>(pw, tw, beta<s>(g, w));
 #pragma unroll
         for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * pw[u];
       }
@@ -311,7 +348,7 @@ struct LineFft {
 
   template <int s, class Ctx>
   BLTT_HD static void inv_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
-    constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), B = r * sg, NB = V / r;
+    constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), NB = V / r;
     if constexpr (s < S - 1) {
 #pragma unroll
       for (int w = 0; w < NB; ++w) {
@@ -324,7 +361,7 @@ struct LineFft {
     for (int w = 0; w < NB; ++w) {
       if constexpr (sg > 1) {
         cx<T> pw[r];
-        twiddle_powers<r>(pw, tw, (beta<s>(g, w) % sg) * (L / B));
+        stage_twiddles<s, r>(pw, tw, beta<s>(g, w));
 #pragma unroll
         for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * conjg(pw[u]);
       }

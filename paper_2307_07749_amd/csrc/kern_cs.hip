@@ -1,22 +1,13 @@
 // Sine-coordinate matvec (mode-major vectors) with N-point circulant and
 // skew-circulant transforms; the FP64 residual variant also folds in the
-// refinement update of the iterate.  The four N-entry tables (twiddles, the
-// two spectra, e^{i pi n/N}) are staged in LDS when they fit beside the
-// exchange buffers.
+// refinement update of the iterate.  The four N-entry tables (stage
+// twiddles, the two spectra, e^{i pi n/N}) are staged in LDS when they fit
+// beside the exchange buffers.
 #include <algorithm>
 
 #include "launchers.hpp"
 
 namespace bltt {
-
-constexpr size_t LDS_LIMIT = 160 * 1024;
-
-template <typename T, int L>
-constexpr size_t cs_lds_base() { return fft_lds_bytes<T, FK_SPEC>(L); }
-template <typename T, int L>
-constexpr bool cs_stage() { return cs_lds_base<T, L>() + 4 * (size_t)L * sizeof(cx<T>) <= LDS_LIMIT; }
-template <typename T, int L>
-constexpr size_t cs_lds_bytes() { return cs_lds_base<T, L>() + (cs_stage<T, L>() ? 4 * (size_t)L * sizeof(cx<T>) : 0); }
 
 template <typename T, int L, int MODE>
 __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_matvec_cs(
@@ -27,21 +18,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
   using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
-  if constexpr (cs_stage<T, L>()) {
-    cx<T>* tabs = reinterpret_cast<cx<T>*>(smem + cs_lds_base<T, L>());
-    for (int i = ctx.tid; i < L; i += tpb_fft<T, FK_SPEC>()) {
-      tabs[i] = tb.tw[i];
-      tabs[L + i] = tb.chat[i];
-      tabs[2 * L + i] = tb.shat[i];
-      tabs[3 * L + i] = tb.omega[i];
-    }
-    __syncthreads();
-    tb.tw = tabs;
-    tb.chat = tabs + L;
-    tb.shat = tabs + 2 * L;
-    tb.omega = tabs + 3 * L;
-  }
-  matvec_cs_body<T, L, MODE>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb, up, partials);
+  cx<T>* tabs = reinterpret_cast<cx<T>*>(smem + cs_lds_base<T, L>());
+  matvec_cs_body<T, L, MODE>(ctx, reinterpret_cast<cx<T>*>(smem), red, tabs, z, out, fin, M, tb, up, partials);
 }
 
 template <typename T, int L>

@@ -6,15 +6,10 @@
 
 namespace bltt {
 
-constexpr size_t LDS_LIMIT_SPEC = 160 * 1024;
+// exchange lines + reduction slots (+ the LDS twiddle table of the FP32 pass)
 template <typename T, int L>
-constexpr size_t upd_lds_base() { return fft_lds_bytes<T, FK_SPEC>(L); }
-// twiddles and the two alpha-spectra staged in LDS
-// (measured slower for the persistent time pass than cached global reads: off)
-template <typename T, int L>
-constexpr bool upd_stage() { return false; }
-template <typename T, int L>
-constexpr size_t upd_lds_bytes() { return upd_lds_base<T, L>() + (upd_stage<T, L>() ? 3 * (size_t)L * sizeof(cx<T>) : 0); }
+constexpr size_t upd_lds_bytes() { return fft_lds_bytes<T, FK_SPEC>(L) + upd_twl_bytes<T, L>(); }
+static_assert(2 * upd_lds_bytes<float, 1024>() <= 160 * 1024, "two workgroups per CU");
 
 template <typename T, int L, typename TQ, bool FULL, bool PREC>
 __global__ __attribute__((amdgpu_waves_per_eu(min_waves_upd<T>(), max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_time_upd(
@@ -26,18 +21,6 @@ __global__ __attribute__((amdgpu_waves_per_eu(min_waves_upd<T>(), max_waves_fft<
   using F = LineFft<T, L, NL, false, LAST_PAIRED>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
-  if constexpr (upd_stage<T, L>()) {
-    cx<T>* tabs = reinterpret_cast<cx<T>*>(smem + upd_lds_base<T, L>());
-    for (int i = ctx.tid; i < L; i += tpb_fft<T, FK_SPEC>()) {
-      tabs[i] = tb.tw[i];
-      tabs[L + i] = tb.sigma[i];
-      tabs[2 * L + i] = tb.rho[i];
-    }
-    __syncthreads();
-    tb.tw = tabs;
-    tb.sigma = tabs + L;
-    tb.rho = tabs + 2 * L;
-  }
   time_upd_body<T, L, TQ, FULL, true, PREC>(ctx, reinterpret_cast<cx<T>*>(smem), red, Q, V1, V2, Vout, Zout, M, tb,
                                             coef, partials, qrev != 0);
 }

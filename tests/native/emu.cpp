@@ -473,7 +473,7 @@ struct UpdRun {
       // fewer workgroups than tiles: every workgroup walks several tiles
       const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
       run_grid(tpb_fft<T, FK_SPEC>(), (int)(upd_persistent<T>() ? std::min<int64_t>(tiles, 3) : tiles), 1,
-               fft_lds_bytes<T, FK_SPEC>(L), [&](HostCtx& c, unsigned char* lds) {
+               fft_lds_bytes<T, FK_SPEC>(L) + upd_twl_bytes<T, L>(), [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Ft::LDS_ELEMS);
                  if (full)
                    time_upd_body<T, L, TQ, true, true>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout, M,
@@ -508,9 +508,11 @@ struct MvSpecRun {
       constexpr int NL = lines_per_block<T, FK_SPEC>(L);
       using Fm = LineFft<T, L, NL, false, LAST_DEFAULT>;
       run_grid(tpb_fft<T, FK_SPEC>(), (int)fft_tiles<T, FK_SPEC>(L, M), 1,
-               fft_lds_bytes<T, FK_SPEC>(L), [&](HostCtx& c, unsigned char* lds) {
+               cs_lds_bytes<T, L>(), [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
-                 matvec_cs_body<T, L, MODE>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M, tb, up, partials);
+                 cx<T>* tabs = reinterpret_cast<cx<T>*>(lds + cs_lds_base<T, L>());
+                 matvec_cs_body<T, L, MODE>(c, reinterpret_cast<cx<T>*>(lds), red, tabs, z, out, fin, M, tb, up,
+                                            partials);
                });
     }
   };
