@@ -286,7 +286,7 @@ int64_t partials_needed(const bltt_handle* h) {
     const int64_t gy = ((h->N + 1) / 2 + 7) / 8;
     need = std::max(need, gx * gy);
   } else {
-    need = std::max(need, fft_blocks<T, FK_MV>((int)(2 * h->N), h->M));
+    need = std::max({need, mv_blocks<T>(false, (int)(2 * h->N), h->M), mv_blocks<T>(true, (int)(2 * h->N), h->M)});
   }
   need = std::max(need, fft_blocks<T, FK_DSTX>(2 * (h->m[0] + 1), h->n / h->m[0]));
   need = std::max(need, h->n / h->m[0]);  // one partial per x-line (residual stencil pass)
@@ -388,7 +388,7 @@ int matvec(bltt_handle* h, int mode, int term, const T* z, T* out, const T* fin,
       ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
       HIPCHK(launch_matvec_fft<T>((int)(2 * h->N), mode, term, const_cast<T*>(z), out, fin, h->M, tb, up, h->partials,
                                   h->stream));
-      *np = fft_blocks<T, FK_MV>((int)(2 * h->N), h->M);
+      *np = mv_blocks<T>(term == TERM_SPEC, (int)(2 * h->N), h->M);
     }
   }
   return BLTT_OK;
@@ -432,20 +432,6 @@ TimeTables<T> time_tables(bltt_handle* h, bool aux) {
   tt.qtaps = h->qtaps;
   tt.aux = aux ? h->partials_aux : nullptr;
   return tt;
-}
-
-// out = (I_N x U) in: sine transform of every time slice (x-line pass, then the
-// strided dimensions).  out may equal in.
-template <typename T>
-int space_transform(bltt_handle* h, const T* in, T* out) {
-  const int Lx = 2 * (h->m[0] + 1);
-  const int64_t nlx = h->n / h->m[0];
-  {
-    ProfScope ps(h, BLTT_K_DST_X_VUPD, 2.0 * h->n * sizeof(T));
-    HIPCHK(launch_dst_x<T>(Lx, KIND_VUPD, in, nullptr, nullptr, nullptr, nullptr, out, nlx, dst_tables<T>(h, 0),
-                           h->coef_one, nullptr, vupd_stencil<T>(h, nullptr), h->stream));
-  }
-  return space_strided<T>(h, out, false);
 }
 
 // zout = P^{-1} vhat with vhat = coef[0] in + coef[1] v1 + coef[2] v2 (written to
@@ -722,6 +708,41 @@ bool overlaps(const void* a, const void* b, int64_t bytes) {
 
 int check_power(int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
+// strided sine transforms along dimensions 1..dim-1 on a mode-major vector
+// (element (i, n) at i*N + n: the lines of dimension d have stride N * m_0 * ... * m_{d-1})
+int space_strided_mm(bltt_handle* h, double* x, bool reverse) {
+  for (int k = 1; k < h->dim; ++k) {
+    const int d = reverse ? h->dim - k : k;
+    int64_t S = h->N;
+    for (int e = 0; e < d; ++e) S *= h->m[e];
+    const int64_t nlines = h->n / h->m[d];
+    ProfScope ps(h, BLTT_K_DST_STRIDED, 16.0 * h->n);
+    HIPCHK(launch_dst_strided<double>(2 * (h->m[d] + 1), x, nlines, S, dst_tables<double>(h, d), h->stream));
+  }
+  return BLTT_OK;
+}
+
+// fhat = (I x U) f: f time-major (caller's), fhat mode-major; partial sums of
+// ||f||^2 = ||fhat||^2 left in h->partials (count in *np)
+int sine_forward(bltt_handle* h, const double* f, double* fhat, int64_t* np) {
+  {
+    ProfScope ps(h, BLTT_K_DST_X_VUPD, 16.0 * h->n);
+    HIPCHK(launch_dst_xt<double>(2 * (h->m[0] + 1), 0, f, fhat, h->N, h->M, dst_tables<double>(h, 0), h->partials,
+                                 np, h->stream));
+  }
+  return space_strided_mm(h, fhat, false);
+}
+
+// u = (I x U) uhat: uhat mode-major (overwritten), u time-major
+int sine_backward(bltt_handle* h, double* uhat, double* u) {
+  int rc;
+  if ((rc = space_strided_mm(h, uhat, true))) return rc;
+  ProfScope ps(h, BLTT_K_DST_X_VUPD, 16.0 * h->n);
+  HIPCHK(launch_dst_xt<double>(2 * (h->m[0] + 1), 1, uhat, u, h->N, h->M, dst_tables<double>(h, 0), nullptr,
+                               nullptr, h->stream));
+  return BLTT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -905,18 +926,19 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
 
   if (h->opt.basis == BLTT_BASIS_SINE) {
     // fhat = (I x U) f once, stored mode-major (each mode's time line
-    // contiguous); the iteration and the FP64 residuals run on the
-    // mode-decoupled system in that layout; u = (I x U) uhat once at the end
-    // (U = U^T = U^{-1}).  u_dev serves as time-major scratch on the way in.
-    if ((rc = space_transform<double>(h, f_dev, u_dev))) return rc;
-    {
-      // fhat to the mode-major layout, with ||fhat||^2 = ||Y fhat||^2 on the way;
-      // b = Y fhat is never stored: the first Lanczos start reads fhat reversed
-      ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
-      HIPCHK(launch_transpose<double>(u_dev, h->F64, h->N, h->M, false, h->partials, &np, s));
+    // contiguous) in u_dev; the iteration and the FP64 residuals run on the
+    // mode-decoupled system in that layout, with uhat in F64; u = (I x U) uhat
+    // once at the end (U = U^T = U^{-1}), over fhat.  ||fhat||^2 = ||Y fhat||^2
+    // comes from the first pass; b = Y fhat is never stored: the first Lanczos
+    // start reads fhat reversed.
+    double* fhat = u_dev;
+    double* uhat = h->F64;
+    if ((rc = sine_forward(h, f_dev, fhat, &np))) return rc;
+    if (h->opt.precision == BLTT_FP64 || short_p(h)) {
       // the FP64 path and the direct-form residual read uhat from the start;
       // the fused FFT residual of the mixed path writes it on the first sweep
-      if (h->opt.precision == BLTT_FP64 || short_p(h)) HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
+      ProfScope ps(h, BLTT_K_OTHER, 8.0 * h->n);
+      HIPCHK(launch_fill<double>(uhat, h->n, 0.0, s));
     }
     if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
     if ((rc = read_state(h))) return rc;
@@ -926,18 +948,18 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     if (hist) hist[0] = 1.0;
     if (bn2 == 0.0) {
       relres = 0.0;
-      HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
+      HIPCHK(launch_fill<double>(uhat, h->n, 0.0, s));
     } else if (h->opt.precision == BLTT_FP64) {
       CoreResult cr;
-      rc = minres_spec<double, double, double>(h, u_dev, maxit, h->opt.check_factor * tol, h->F64, tol, bnorm, hist,
-                                               &cr, h->F64, h->coef_one, false, true);
+      rc = minres_spec<double, double, double>(h, uhat, maxit, h->opt.check_factor * tol, fhat, tol, bnorm, hist,
+                                               &cr, fhat, h->coef_one, false, true);
       if (rc) return rc;
       total_iters = cr.iters;
       outer = 1;
       status = cr.status;
       relres = cr.relres;
       if (relres < 0.0) {
-        if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, u_dev, h->w64.Q, h->F64, &np))) return rc;
+        if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, uhat, h->w64.Q, fhat, &np))) return rc;
         if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
         if ((rc = read_state(h))) return rc;
         relres = std::sqrt(h->state_host->norm2) / bnorm;
@@ -961,7 +983,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         hbuf.assign((size_t)left + 2, 0.0);
         // r = b = Y fhat on the first sweep (read from fhat reversed), then the residual
         rc = minres_spec<float, float, double>(h, nullptr, left, h->opt.inner_tol, nullptr, 0.0, 1.0, hbuf.data(),
-                                               &cr, outer == 0 ? h->F64 : h->R64, &h->state->rinv, true, outer == 0);
+                                               &cr, outer == 0 ? fhat : h->R64, &h->state->rinv, true, outer == 0);
         if (rc) return rc;
         if (hist)
           for (int k = 1; k <= cr.iters; ++k) hist[hist_pos + k] = hbuf[(size_t)k];
@@ -977,9 +999,9 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
           zl.k = cr.iters;
           {
             ProfScope ps(h, BLTT_K_WX, (16.0 + 4.0 * cr.iters) * h->n);
-            HIPCHK(launch_combine<float>(u_dev, zl, ycoef, &h->state->rscale, h->n, s));
+            HIPCHK(launch_combine<float>(uhat, zl, ycoef, &h->state->rscale, h->n, s));
           }
-          if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, u_dev, h->R64, h->F64, &np))) return rc;
+          if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, uhat, h->R64, fhat, &np))) return rc;
         } else {
           IterUpd up{};
           for (int i = 0; i < ZB_MAX; ++i) up.z[i] = i < cr.iters ? h->zpool[i] : nullptr;
@@ -988,9 +1010,9 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
           up.s = &h->state->rscale;
           up.u_zero = outer == 1 ? 1 : 0;
           ProfScope ps(h, BLTT_K_RESID64, (32.0 + 4.0 * cr.iters - (up.u_zero ? 8.0 : 0.0)) * h->n);
-          HIPCHK(launch_matvec_fft<double>((int)(2 * h->N), MV_RESID, TERM_SPEC, u_dev, h->R64, h->F64, h->M,
+          HIPCHK(launch_matvec_fft<double>((int)(2 * h->N), MV_RESID, TERM_SPEC, uhat, h->R64, fhat, h->M,
                                            mv_tables<double>(h), up, h->partials, s));
-          np = fft_blocks<double, FK_MV>((int)(2 * h->N), h->M);
+          np = mv_blocks<double>(true, (int)(2 * h->N), h->M);
         }
         if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
         if ((rc = read_state(h))) return rc;
@@ -998,11 +1020,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         if (!std::isfinite(rnorm)) return BLTT_ENAN;
       }
     }
-    {
-      ProfScope ps(h, BLTT_K_OTHER, 16.0 * h->n);
-      HIPCHK(launch_transpose<double>(u_dev, h->F64, h->M, h->N, false, nullptr, nullptr, s));
-    }
-    if ((rc = space_transform<double>(h, h->F64, u_dev))) return rc;
+    if ((rc = sine_backward(h, uhat, u_dev))) return rc;
   } else if (h->opt.precision == BLTT_FP64) {
     Workspace<double>& ws = h->w64;
     // b = Y f into V[0]

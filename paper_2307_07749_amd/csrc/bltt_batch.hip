@@ -353,7 +353,7 @@ int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const doub
   c.hist_stride = BT_POOL + 2;
   if ((rc = balloc(b, &c.hist_dev, (size_t)(c.hist_stride * S)))) return rc;
   // partial sums: the most tiles per system of any phase, for every system
-  const int64_t Tmax = std::max({bt_tiles((int)N, 256, M), fft_tiles<double, FK_MV>((int)(2 * N), M),
+  const int64_t Tmax = std::max({bt_tiles((int)N, 256, M), mv_tiles<double>(true, (int)(2 * N), M),
                                  std::min<int64_t>(ew_blocks(c.n), 1024)});
   c.partials_cap = Tmax * S;
   if ((rc = balloc(b, &c.partials, (size_t)c.partials_cap))) return rc;
@@ -370,7 +370,7 @@ int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const doub
   HIPCHK(hipMemsetAsync(c.Q, 0, ns * sizeof(float), c.stream));
   for (auto& v : c.V) HIPCHK(hipMemsetAsync(v, 0, ns * sizeof(float), c.stream));
   for (int i = 0; i < 2; ++i) HIPCHK(hipMemsetAsync(c.pool.z[i], 0, ns * sizeof(float), c.stream));
-  c.T2 = fft_tiles<double, FK_MV>((int)(2 * N), M);
+  c.T2 = mv_tiles<double>(true, (int)(2 * N), M);
   if ((rc = autotune(c))) return rc;
   HIPCHK(hipStreamSynchronize(c.stream));
   return BLTT_OK;

@@ -31,10 +31,15 @@ namespace bltt {
 // L (G = L/16 threads per line) share a workgroup.
 // FK_SPEC: the sine-basis time-line kernels (mode-major lines, one wavefront
 // per line pair): smaller workgroups schedule independently of each other.
-enum FftKernel { FK_TIME = 0, FK_MV = 1, FK_DSTS = 2, FK_DSTX = 3, FK_SPEC = 4 };
+// FK_MVS: the 2N-point matvec on mode-major lines (FP64 sine basis, 2N <= 2048):
+// one line (two waves) per workgroup, so each exchange barrier waits on two
+// waves only.
+enum FftKernel { FK_TIME = 0, FK_MV = 1, FK_DSTS = 2, FK_DSTX = 3, FK_SPEC = 4, FK_MVS = 5 };
+template <bool MM, int L>
+constexpr int fk_mv() { return MM && L <= 2048 ? FK_MVS : FK_MV; }
 template <typename T, int FK>
 constexpr int tpb_fft() {
-  return FK == FK_SPEC ? 256 : (sizeof(T) == 4 ? 512 : 256);
+  return FK == FK_SPEC ? 256 : (sizeof(T) == 4 ? 512 : (FK == FK_MVS ? 128 : 256));
 }
 template <typename T, int FK>
 constexpr int lines_per_block(int L) {
@@ -63,6 +68,15 @@ BLTT_HD int64_t fft_tiles(int L, int64_t units) {
 
 // minimum waves per SIMD requested from the compiler for the FFT kernels
 // (1: no constraint beyond the workgroup size)
+// launch sizes of the 2N-point matvec (mm: mode-major lines), for host code
+template <typename T>
+inline int64_t mv_blocks(bool mm, int L, int64_t units) {
+  return mm && L <= 2048 ? fft_blocks<T, FK_MVS>(L, units) : fft_blocks<T, FK_MV>(L, units);
+}
+template <typename T>
+inline int64_t mv_tiles(bool mm, int L, int64_t units) {
+  return mm && L <= 2048 ? fft_tiles<T, FK_MVS>(L, units) : fft_tiles<T, FK_MV>(L, units);
+}
 template <typename T>
 constexpr int waves_fft() { return 1; }
 // LDS (about 74 KB per workgroup) admits two workgroups per CU, i.e. at most 4
@@ -237,7 +251,7 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
                                int64_t zoff = 0, int k = -1, const double* y = nullptr,
                                const double* sptr = nullptr) {
   static_assert(!(MM && TERM == TERM_STENCIL), "the stencil needs the time-major layout");
-  constexpr int TPB = tpb_fft<T, FK_MV>();
+  constexpr int TPB = tpb_fft<T, fk_mv<MM, L>()>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L / 2, VH = V / 2;  // slots t < VH hold times g + t*s0 < N
   using F = LineFft<T, L, NL, !MM, LAST_DEFAULT>;
@@ -399,7 +413,7 @@ BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restr
                              double* __restrict__ partials) {
   const double part = matvec_fft_tile<T, L, MODE, TERM, MM>(ctx, lds, xcd_tile(ctx.bid, ctx.nbx), z, out, fin, M,
                                                               tb, up);
-  const double s = block_sum<tpb_fft<T, FK_MV>()>(ctx, red, part);
+  const double s = block_sum<tpb_fft<T, fk_mv<MM, L>()>()>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = s;
 }
 
@@ -952,6 +966,120 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
   }
 }
 
+// Sine transform along x fused with the move between the time-major layout
+// (element (n, i) at n*M + i) and the mode-major one (i*N + n).  The x-line of
+// row r (r < M/m, i = r*m + x) at time n is one line; a workgroup takes 2*NL
+// consecutive times of one row, so the mode-major side is read or written in
+// runs of 2*NL elements and the time-major side in whole x-lines.  The
+// mode-major side goes through LDS (the exchange buffer, before or after the
+// transform).
+// DIR 0: time-major `in` -> mode-major `out`, and one partial sum of ||in||^2
+//        per workgroup (= ||out||^2, U being orthogonal; partials may be null).
+// DIR 1: mode-major `in` -> time-major `out`.
+constexpr int DSTXT_TPB = 256;
+template <typename T, int L>
+constexpr int dstxt_lines() { return 2 * (DSTXT_TPB / (L / fft_V(L))); }
+// workgroups of a launch: rows x time blocks, rounded up to a multiple of 8
+BLTT_HD int64_t dstxt_blocks(int64_t rows, int64_t N, int W2) {
+  const int64_t nb = rows * ((N + W2 - 1) / W2);
+  return (nb + 7) / 8 * 8;
+}
+template <typename T, int L, int DIR, class Ctx>
+BLTT_HD void dst_xt_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict__ in, T* __restrict__ out,
+                         int64_t N, int64_t M, const DstTables<T>& tb, double* __restrict__ partials) {
+  constexpr int TPB = DSTXT_TPB;
+  constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0), VH = V / 2, W2 = 2 * NL;
+  using F = LineFft<T, L, NL, false, DIR == 0 ? LAST_DEFAULT : LAST_LINEAR>;
+  static_assert(G <= TPB, "one line per at most one workgroup");
+  const int m = L / 2 - 1;
+  const int64_t rows = M / m, nblk = (N + W2 - 1) / W2;
+  const int64_t tile = xcd_tile(ctx.bid, ctx.nbx);
+  const bool live = tile < rows * nblk;
+  const int64_t r = live ? tile / nblk : 0, n0 = live ? (tile % nblk) * W2 : N;
+  const int tid = ctx.tid, c = tid / G, g = tid % G;
+  const int64_t na = n0 + 2 * c, nb = na + 1;
+  const bool va = na < N, vb = nb < N;
+  T* stage = reinterpret_cast<T*>(lds);  // W2 x m values, line-major
+  cx<T> v[V];
+  double part = 0.0;
+  if (DIR == 0) {
+    const int64_t nac = va ? na : 0, nbc = vb ? nb : 0;
+    const T* pa = in + nac * M + r * m;
+    const T* pb = in + nbc * M + r * m;
+    const T ma = va ? T(1) : T(0), mb = vb ? T(1) : T(0);
+#pragma unroll
+    for (int t = 0; t < VH; ++t) {
+      const int p = g + t * s0;
+      const int x = p > 0 ? p - 1 : 0;
+      const T wp = p > 0 ? T(1) : T(0);
+      const T a = pa[x] * (wp * ma), b = pb[x] * (wp * mb);
+      part += (double)a * (double)a + (double)b * (double)b;
+      v[t] = mkc<T>(a, b);
+    }
+  } else {
+    // runs of W2 consecutive times per x, into LDS line-major
+    for (int e = tid; e < W2 * m; e += TPB) {
+      const int x = e / W2, j = e % W2;
+      const int64_t n = n0 + j;
+      stage[j * m + x] = n < N ? in[(r * m + x) * N + n] : T(0);
+    }
+    ctx.sync();
+#pragma unroll
+    for (int t = 0; t < VH; ++t) {
+      const int p = g + t * s0;
+      const int x = p > 0 ? p - 1 : 0;
+      const T wp = p > 0 ? T(1) : T(0);
+      v[t] = mkc<T>(stage[(2 * c) * m + x] * wp, stage[(2 * c + 1) * m + x] * wp);
+    }
+    // the mirror below writes the exchange buffer the stage lives in
+    ctx.sync();
+  }
+  odd_mirror<F, T, L>(ctx, v, lds, c, g);
+  F::forward(ctx, v, lds, c, g, tb.tw);
+  if (DIR == 0) {
+    ctx.sync();
+#pragma unroll
+    for (int w = 0; w < V / F::RL; ++w) {
+#pragma unroll
+      for (int u = 0; u < F::RL; ++u) {
+        const int k = F::freq(g, w, u);
+        if (k >= 1 && k <= m) {
+          const cx<T> zk = v[w * F::RL + u];
+          stage[(2 * c) * m + k - 1] = -zk.im * tb.nrm;
+          stage[(2 * c + 1) * m + k - 1] = zk.re * tb.nrm;
+        }
+      }
+    }
+    ctx.sync();
+    if (live) {
+      for (int e = tid; e < W2 * m; e += TPB) {
+        const int k = e / W2, j = e % W2;
+        const int64_t n = n0 + j;
+        if (n < N) out[(r * m + k) * N + n] = stage[j * m + k];
+      }
+    }
+    if (partials) {
+      const double sum = block_sum<TPB>(ctx, red, part);
+      if (tid == 0) partials[ctx.bid] = sum;
+    }
+  } else {
+    T* oa = out + na * M + r * m;
+    T* ob = out + nb * M + r * m;
+#pragma unroll
+    for (int w = 0; w < V / F::RL; ++w) {
+#pragma unroll
+      for (int u = 0; u < F::RL; ++u) {
+        const int k = F::freq(g, w, u);
+        if (k >= 1 && k <= m) {
+          const cx<T> zk = v[w * F::RL + u];
+          if (live && va) oa[k - 1] = -zk.im * tb.nrm;
+          if (live && vb) ob[k - 1] = zk.re * tb.nrm;
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // time pass of the preconditioner, per sine mode i (Section 5.1 Step 2, both
 // halves):  t <- alpha^{-n/N} t;  t <- F conj(Lambda_i)^{-1/2} F^* t;
@@ -1441,37 +1569,26 @@ BLTT_HD void rhs_body(Ctx& ctx, double* red, const double* __restrict__ f, TO* _
 
 // out = in^T for an R x C row-major matrix (out is C x R), through a 64 x 64
 // LDS tile (padded rows); REV also reverses the order of the R index in out.
-// Moves vectors between the time-major ABI layout (R = N, C = M) and the
-// mode-major sine-basis layout (R = M, C = N for the way back).  With
-// partials (and red, TPB_EW doubles of LDS), also one partial sum of the
-// squares of the values moved per workgroup (the norm of the right-hand side).
+// Moves per-system vectors of the batched solves between the time-major ABI
+// layout (R = N, C = M) and the mode-major sine-basis layout (R = M, C = N).
 constexpr int TR_TILE = 64;
 template <typename T, bool REV, class Ctx>
 BLTT_HD void transpose_body(Ctx& ctx, T* tile, const T* __restrict__ in, T* __restrict__ out, int64_t R,
-                            int64_t C, double* red = nullptr, double* __restrict__ partials = nullptr) {
+                            int64_t C) {
   constexpr int P = TR_TILE + 1, ROWS = TPB_EW / TR_TILE;
   const int64_t tiles_c = (C + TR_TILE - 1) / TR_TILE;
   const int64_t c0 = ((int64_t)ctx.bid % tiles_c) * TR_TILE, r0 = ((int64_t)ctx.bid / tiles_c) * TR_TILE;
   const int tx = ctx.tid % TR_TILE, ty = ctx.tid / TR_TILE;
-  double part = 0.0;
 #pragma unroll
   for (int k = 0; k < TR_TILE; k += ROWS) {
     const int64_t r = r0 + ty + k, c = c0 + tx;
-    if (r < R && c < C) {
-      const T x = in[r * C + c];
-      tile[(ty + k) * P + tx] = x;
-      part += (double)x * (double)x;
-    }
+    if (r < R && c < C) tile[(ty + k) * P + tx] = in[r * C + c];
   }
   ctx.sync();
 #pragma unroll
   for (int k = 0; k < TR_TILE; k += ROWS) {
     const int64_t c = c0 + ty + k, r = r0 + tx;
     if (r < R && c < C) out[c * R + (REV ? R - 1 - r : r)] = tile[tx * P + ty + k];
-  }
-  if (partials) {
-    const double sum = block_sum<TPB_EW>(ctx, red, part);
-    if (ctx.tid == 0) partials[ctx.bid] = sum;
   }
 }
 
@@ -1852,7 +1969,7 @@ BLTT_HD void bt_resid_body(Ctx& ctx, unsigned char* smem, double* const* __restr
                            const double* __restrict__ Fh, const BatchVec& bv, const BatchTabs& bt,
                            const IterUpd& pool, const double* __restrict__ zb, int K, int64_t T2,
                            double* __restrict__ partials) {
-  constexpr int NL = tpb_fft<double, FK_MV>() / (L2 / fft_V(L2));
+  constexpr int NL = tpb_fft<double, fk_mv<true, L2>()>() / (L2 / fft_V(L2));
   using F = LineFft<double, L2, NL, false, LAST_DEFAULT>;
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<double>) * F::LDS_ELEMS);
   const int s = (int)(ctx.bid / T2);
@@ -1874,7 +1991,7 @@ BLTT_HD void bt_resid_body(Ctx& ctx, unsigned char* smem, double* const* __restr
   const double part = matvec_fft_tile<double, L2, MV_RESID, TERM_SPEC, true>(
       ctx, reinterpret_cast<cx<double>*>(smem), tile, u[s], R + o, Fh + o, bv.M, tb, pool, o, k,
       zb + (int64_t)s * 3 * K + 2 * K, &bv.states[s].rscale);
-  const double sum = block_sum<tpb_fft<double, FK_MV>()>(ctx, red, part);
+  const double sum = block_sum<tpb_fft<double, fk_mv<true, L2>()>()>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;
 }
 

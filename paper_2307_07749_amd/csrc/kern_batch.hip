@@ -25,7 +25,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<float>()))) __lau
 }
 
 template <int L2>
-__global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<double>()))) __launch_bounds__((tpb_fft<double, FK_MV>()), 1) void k_bt_resid(
+__global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<double>()))) __launch_bounds__((tpb_fft<double, fk_mv<true, L2>()>()), 1) void k_bt_resid(
     double* const* __restrict__ u, double* __restrict__ R, const double* __restrict__ Fh, BatchVec bv, BatchTabs bt,
     IterUpd pool, const double* __restrict__ zb, int K, int64_t T2, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -120,10 +120,11 @@ static hipError_t go_bt_resid(double* const* u, double* R, const double* Fh, con
   for (int i = 0; i < ZB_MAX; ++i) up.z[i] = i < K ? pool.z[i] : nullptr;
   up.k = 0;
   up.u_zero = u_zero;
-  const int64_t T2 = fft_tiles<double, FK_MV>(L2, bv.M);
+  constexpr int FK = fk_mv<true, L2>();
+  const int64_t T2 = fft_tiles<double, FK>(L2, bv.M);
   if (T2out) *T2out = T2;
-  const size_t lds = fft_lds_bytes<double, FK_MV>(L2);
-  hipLaunchKernelGGL((k_bt_resid<L2>), dim3((unsigned)(T2 * bv.S)), dim3(tpb_fft<double, FK_MV>()), lds, s, u, R, Fh,
+  const size_t lds = fft_lds_bytes<double, FK>(L2);
+  hipLaunchKernelGGL((k_bt_resid<L2>), dim3((unsigned)(T2 * bv.S)), dim3(tpb_fft<double, FK>()), lds, s, u, R, Fh,
                      bv, bt, up, zb, K, T2, partials);
   return hipGetLastError();
 }
@@ -184,7 +185,7 @@ static hipError_t attr_bt() {
 template <int L2>
 static hipError_t attr_bt_resid() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_resid<L2>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)fft_lds_bytes<double, FK_MV>(L2));
+                             (int)fft_lds_bytes<double, fk_mv<true, L2>()>(L2));
 }
 
 hipError_t configure_batch_kernels() {

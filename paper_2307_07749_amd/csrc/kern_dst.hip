@@ -1,5 +1,6 @@
 // Sine-transform passes: contiguous x-lines (with the fused Lanczos update or
-// the fused dot product) and strided y/z-lines (in place).
+// the fused dot product), x-lines fused with the move to or from the
+// mode-major layout, and strided y/z-lines (in place).
 #include "launchers.hpp"
 
 namespace bltt {
@@ -27,6 +28,55 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
   DevCtx ctx = make_ctx();
   dst_strided_body<T, L>(ctx, reinterpret_cast<cx<T>*>(smem), x, nlines, S, tb);
 }
+
+template <typename T, int L>
+constexpr size_t dstxt_lds_bytes() {
+  return (size_t)(DSTXT_TPB / (L / fft_V(L))) * (size_t)(L + (L >> 3)) * sizeof(cx<T>) + DSTXT_TPB * sizeof(double);
+}
+
+template <typename T, int L, int DIR>
+__global__ __launch_bounds__(DSTXT_TPB) void k_dst_xt(const T* __restrict__ in, T* __restrict__ out, int64_t N,
+                                                      int64_t M, DstTables<T> tb, double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NL = DSTXT_TPB / (L / fft_V(L));
+  using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
+  DevCtx ctx = make_ctx();
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
+  dst_xt_body<T, L, DIR>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, out, N, M, tb, partials);
+}
+
+template <typename T, int L>
+static hipError_t go_dxt(int dir, const T* in, T* out, int64_t N, int64_t M, const DstTables<T>& tb,
+                         double* partials, int64_t* nparts, hipStream_t s) {
+  constexpr int m = L / 2 - 1;
+  if (M % m != 0) return hipErrorInvalidValue;
+  const int64_t blocks = dstxt_blocks(M / m, N, dstxt_lines<T, L>());
+  if (blocks < 1 || blocks > 2147483647LL) return hipErrorInvalidValue;
+  if (nparts) *nparts = blocks;
+  const size_t lds = dstxt_lds_bytes<T, L>();
+  if (dir == 0)
+    hipLaunchKernelGGL((k_dst_xt<T, L, 0>), dim3((unsigned)blocks), dim3(DSTXT_TPB), lds, s, in, out, N, M, tb,
+                       partials);
+  else
+    hipLaunchKernelGGL((k_dst_xt<T, L, 1>), dim3((unsigned)blocks), dim3(DSTXT_TPB), lds, s, in, out, N, M, tb,
+                       nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dst_xt(int L, int dir, const T* in, T* out, int64_t N, int64_t M, const DstTables<T>& tb,
+                         double* partials, int64_t* nparts, hipStream_t s) {
+  switch (L) {
+#define BLTT_CASE(LL) \
+  case LL: return go_dxt<T, LL>(dir, in, out, N, M, tb, partials, nparts, s);
+    BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64) BLTT_CASE(128) BLTT_CASE(256)
+    BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
+#undef BLTT_CASE
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_dst_xt<double>(int, int, const double*, double*, int64_t, int64_t,
+                                          const DstTables<double>&, double*, int64_t*, hipStream_t);
 
 template <typename T, int L>
 static hipError_t go_dx(int kind, const T* in, const T* v1, const T* v2, T* vout, const T* vdot, T* out,
@@ -111,6 +161,15 @@ static hipError_t attr_dst() {
                        reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_DOT, false, false>)};
   for (const void* k : ks)
     if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bx)) != hipSuccess) return e;
+  if constexpr (sizeof(T) == 8) {
+    const int bt = (int)dstxt_lds_bytes<T, L>();
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_xt<T, L, 0>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bt)) != hipSuccess)
+      return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_xt<T, L, 1>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bt)) != hipSuccess)
+      return e;
+  }
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_strided<T, L>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bs);
 }

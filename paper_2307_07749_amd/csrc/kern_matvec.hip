@@ -5,12 +5,12 @@
 namespace bltt {
 
 template <typename T, int L, int MODE, int TERM>
-__global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_MV>()), waves_fft<T>()) void k_matvec_fft(T* z, T* __restrict__ out,
+__global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, fk_mv<TERM == TERM_SPEC, L>()>()), waves_fft<T>()) void k_matvec_fft(T* z, T* __restrict__ out,
                                                              const T* __restrict__ fin, int64_t M,
                                                              MatvecTables<T> tb, IterUpd up,
                                                              double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int NL = tpb_fft<T, FK_MV>() / (L / fft_V(L));
+  constexpr int NL = tpb_fft<T, fk_mv<TERM == TERM_SPEC, L>()>() / (L / fft_V(L));
   using F = LineFft<T, L, NL, TERM != TERM_SPEC, LAST_DEFAULT>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
@@ -38,13 +38,15 @@ __global__ __launch_bounds__(TPB_EW) void k_matvec_short(const T* __restrict__ z
 template <typename T, int L>
 static hipError_t go_mv(int mode, int term, T* z, T* out, const T* fin, int64_t M,
                         const MatvecTables<T>& tb, const IterUpd& up, double* partials, hipStream_t s) {
-  const int64_t blocks = fft_blocks<T, FK_MV>(L, M);
-  const size_t lds = fft_lds_bytes<T, FK_MV>(L);
-#define BLTT_GO(MO, TE)                                                                                   \
-  if (mode == MO && term == TE) {                                                                         \
-    hipLaunchKernelGGL((k_matvec_fft<T, L, MO, TE>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_MV>()), lds, \
-                       s, z, out, fin, M, tb, up, partials);                                              \
-    return hipGetLastError();                                                                             \
+#define BLTT_GO(MO, TE)                                                                               \
+  if (mode == MO && term == TE) {                                                                     \
+    constexpr int FK = fk_mv<TE == TERM_SPEC, L>();                                                      \
+    const unsigned blocks = (unsigned)fft_blocks<T, FK>(L, M);                                        \
+    const unsigned tpb = (unsigned)tpb_fft<T, FK>();                                                  \
+    const size_t lds = fft_lds_bytes<T, FK>(L);                                                       \
+    hipLaunchKernelGGL((k_matvec_fft<T, L, MO, TE>), dim3(blocks), dim3(tpb), lds, s, z, out, fin, M, tb, \
+                       up, partials);                                                                 \
+    return hipGetLastError();                                                                         \
   }
   BLTT_MV_VARIANTS(BLTT_GO)
 #undef BLTT_GO
@@ -121,11 +123,11 @@ BLTT_INST(double)
 
 template <typename T, int L>
 static hipError_t attr_mv() {
-  const int bytes = (int)fft_lds_bytes<T, FK_MV>(L);
   hipError_t e = hipSuccess;
 #define BLTT_ATTR1(MO, TE)                                                                           \
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MO, TE>),                \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);                        \
+                          hipFuncAttributeMaxDynamicSharedMemorySize,                                \
+                          (int)fft_lds_bytes<T, fk_mv<TE == TERM_SPEC, L>()>(L));                       \
   if (e != hipSuccess) return e;
   BLTT_MV_VARIANTS(BLTT_ATTR1)
 #undef BLTT_ATTR1

@@ -14,15 +14,6 @@ __global__ __launch_bounds__(TPB_EW) void k_rhs(const double* __restrict__ f, TO
   rhs_body<TO>(ctx, red, f, b, N, M, scale, partials);
 }
 
-template <typename T, bool REV>
-__global__ __launch_bounds__(TPB_EW) void k_transpose(const T* __restrict__ in, T* __restrict__ out, int64_t R,
-                                                      int64_t C, double* __restrict__ partials) {
-  __shared__ T tile[TR_TILE * (TR_TILE + 1)];
-  __shared__ double red[TPB_EW];
-  DevCtx ctx = make_ctx();
-  transpose_body<T, REV>(ctx, tile, in, out, R, C, red, partials);
-}
-
 template <typename T, typename TX>
 __global__ __launch_bounds__(TPB_EW) void k_wx(const T* __restrict__ Z, T* __restrict__ Wa, const T* __restrict__ Wb,
                                                TX* __restrict__ X, int64_t n, const double* __restrict__ coef) {
@@ -81,21 +72,6 @@ __global__ __launch_bounds__(TPB_EW) void k_combine(double* __restrict__ u, ZLis
   DevCtx ctx = make_ctx();
   combine_body<T>(ctx, u, zl, y, sptr, n);
 }
-
-template <typename T>
-hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev, double* partials, int64_t* nparts,
-                            hipStream_t s) {
-  const int64_t nb = ((C + TR_TILE - 1) / TR_TILE) * ((R + TR_TILE - 1) / TR_TILE);
-  if (nb < 1 || nb > 2147483647LL) return hipErrorInvalidValue;
-  if (nparts) *nparts = nb;
-  if (rev)
-    hipLaunchKernelGGL((k_transpose<T, true>), dim3((unsigned)nb), dim3(TPB_EW), 0, s, in, out, R, C, partials);
-  else
-    hipLaunchKernelGGL((k_transpose<T, false>), dim3((unsigned)nb), dim3(TPB_EW), 0, s, in, out, R, C, partials);
-  return hipGetLastError();
-}
-template hipError_t launch_transpose<double>(const double*, double*, int64_t, int64_t, bool, double*, int64_t*,
-                                             hipStream_t);
 
 template <typename T>
 hipError_t launch_combine(double* u, const ZList<T>& zl, const double* y, const double* sptr, int64_t n,

@@ -69,6 +69,12 @@ hipError_t launch_dst_x(int L, int kind, const T* in, const T* v1, const T* v2, 
                         int64_t nlines, const DstTables<T>& tb, const double* coef, double* partials,
                         const VupdStencil<T>& sten, hipStream_t s);
 
+// x-line sine transform fused with the layout move: dir 0 time-major in ->
+// mode-major out (+ partial sums of ||in||^2 when partials is non-null, count
+// in *nparts); dir 1 mode-major in -> time-major out.  FP64.
+template <typename T>
+hipError_t launch_dst_xt(int L, int dir, const T* in, T* out, int64_t N, int64_t M, const DstTables<T>& tb,
+                         double* partials, int64_t* nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_dst_strided(int L, T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s);
 
@@ -81,11 +87,6 @@ hipError_t configure_kernels_once();
 template <typename T>
 hipError_t launch_resid_stencil(T* r, const VupdStencil<T>& st, int64_t nlines, double* partials, int64_t* nparts,
                                 hipStream_t s);
-// out (C x R) = in^T (in: R x C, row-major); rev reverses the R index; with
-// partials, one partial sum of squares per workgroup (*nparts of them)
-template <typename T>
-hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, bool rev, double* partials,
-                            int64_t* nparts, hipStream_t s);
 template <typename TO>
 hipError_t launch_rhs(const double* f, TO* b, int64_t N, int64_t M, double scale, double* partials,
                       int64_t* nparts, hipStream_t s);

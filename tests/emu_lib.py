@@ -78,7 +78,8 @@ def lib():
         L.emu_resid_upd_f64.restype = ctypes.c_double
         L.emu_state_size.restype = ctypes.c_int64
         L.emu_transpose_f64.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
-        L.emu_transpose_f64.restype = ctypes.c_double
+        L.emu_sine_io.argtypes = args + [P, P, ctypes.c_int]
+        L.emu_sine_io.restype = ctypes.c_double
         L.emu_state_offsets.argtypes = [P]
         L.emu_scalar.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P, P, P, ctypes.c_int]
         L.emu_combine_f32.argtypes = [P, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int64]
@@ -139,6 +140,18 @@ def space(prob, x, dtype=np.float64):
     getattr(lib(), f"emu_space_{_tag(dtype)}")(*args, gx.ptr, gy.ptr)
     _check(gx, gy)
     return gy.data.copy()
+
+
+def sine_io(prob, x, direction):
+    """The sine-basis transforms in and out: direction 0 takes a time-major x
+    to (I x U) x mode-major (and returns the reported ||x||^2), direction 1 a
+    mode-major x to (I x U) x time-major."""
+    args, keep = _common(prob)
+    gx = Guarded(x, np.float64)
+    gy = Guarded(np.zeros(x.size), np.float64)
+    s = lib().emu_sine_io(*args, gx.ptr, gy.ptr, int(direction))
+    _check(gx, gy)
+    return gy.data.copy(), s
 
 
 def time_pass(prob, x, dtype=np.float64):
@@ -315,14 +328,13 @@ def wx(Z, Wa, Wb, X, coef_ptr):
     getattr(lib(), f"emu_wx_{tag}")(Z.ctypes.data, Wa.ctypes.data, Wb.ctypes.data, X.ctypes.data, Z.size, coef_ptr)
 
 
-def transpose(x, R, C, rev=False, with_norm=False):
-    """out (C x R) = x (R x C)^T through the library's tiled transpose (and the
-    sum of squares its workgroups report)."""
+def transpose(x, R, C, rev=False):
+    """out (C x R) = x (R x C)^T through the library's tiled transpose."""
     gi = Guarded(x, np.float64)
     go = Guarded(np.zeros(x.size), np.float64)
-    s = lib().emu_transpose_f64(gi.ptr, go.ptr, R, C, int(rev))
+    lib().emu_transpose_f64(gi.ptr, go.ptr, R, C, int(rev))
     _check(gi, go)
-    return (go.data.copy(), s) if with_norm else go.data.copy()
+    return go.data.copy()
 
 
 def combine_f32(u, Zs, y, s):

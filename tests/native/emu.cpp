@@ -312,6 +312,60 @@ void space_strided(const Problem& P, const HostTables<T>& ht, T* x, bool reverse
   }
 }
 
+// x-line transform fused with the layout move (FP64, the sine-basis in/out passes)
+struct DstXtRun {
+  template <int L>
+  struct R {
+    static void run(int dir, const double* in, double* out, int64_t N, int64_t M, const DstTables<double>& tb,
+                    double* partials) {
+      constexpr int NL = DSTXT_TPB / (L / fft_V(L));
+      using Fx = LineFft<double, L, NL, false, LAST_DEFAULT>;
+      constexpr int m = L / 2 - 1;
+      const int64_t blocks = dstxt_blocks(M / m, N, dstxt_lines<double, L>());
+      run_grid(DSTXT_TPB, (int)blocks, 1, sizeof(cx<double>) * Fx::LDS_ELEMS + DSTXT_TPB * sizeof(double),
+               [&](HostCtx& c, unsigned char* lds) {
+                 double* red = reinterpret_cast<double*>(lds + sizeof(cx<double>) * Fx::LDS_ELEMS);
+                 if (dir == 0)
+                   dst_xt_body<double, L, 0>(c, reinterpret_cast<cx<double>*>(lds), red, in, out, N, M, tb, partials);
+                 else
+                   dst_xt_body<double, L, 1>(c, reinterpret_cast<cx<double>*>(lds), red, in, out, N, M, tb,
+                                             nullptr);
+               });
+    }
+  };
+};
+
+// strided transforms on a mode-major vector (stride N m_0 ... m_{d-1} along d)
+void space_strided_mm(const Problem& P, const HostTables<double>& ht, double* x, bool reverse) {
+  const int64_t n = P.N * P.M;
+  for (int k = 1; k < P.dim; ++k) {
+    const int d = reverse ? P.dim - k : k;
+    int64_t S = P.N;
+    for (int e = 0; e < d; ++e) S *= P.m[e];
+    with_L<DstSRun<double>::template R>(2 * (P.m[d] + 1), x, n / P.m[d], S, ht.dst(P, d));
+  }
+}
+
+// dir 0: y (mode-major) = (I x U) x with x time-major, returns the sum of the
+// partial sums of ||x||^2; dir 1: y (time-major) = (I x U) x with x mode-major
+double apply_sine_io(const Problem& P, const double* x, double* y, int dir) {
+  HostTables<double> ht(P);
+  const int64_t n = P.N * P.M;
+  const int L = 2 * (P.m[0] + 1);
+  std::vector<double> partials((size_t)(P.M / P.m[0]) * (size_t)P.N + 8, 0.0);
+  if (dir == 0) {
+    with_L<DstXtRun::template R>(L, 0, x, y, P.N, P.M, ht.dst(P, 0), partials.data());
+    space_strided_mm(P, ht, y, false);
+  } else {
+    std::vector<double> t(x, x + n);
+    space_strided_mm(P, ht, t.data(), true);
+    with_L<DstXtRun::template R>(L, 1, (const double*)t.data(), y, P.N, P.M, ht.dst(P, 0), (double*)nullptr);
+  }
+  double s = 0.0;
+  for (double v : partials) s += v;
+  return s;
+}
+
 template <typename T>
 void apply_space(const Problem& P, const T* x, T* y) {
   HostTables<T> ht(P);
@@ -525,9 +579,10 @@ struct MvSpec2nRun {
   struct R {
     static void run(T* z, T* out, const T* fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
                     double* partials) {
-      constexpr int NL = lines_per_block<T, FK_MV>(L);
+      constexpr int FK = fk_mv<true, L>();
+      constexpr int NL = lines_per_block<T, FK>(L);
       using Fm = LineFft<T, L, NL, false, LAST_DEFAULT>;
-      run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
+      run_grid(tpb_fft<T, FK>(), (int)fft_blocks<T, FK>(L, M), 1, fft_lds_bytes<T, FK>(L),
                [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
                  matvec_fft_body<T, L, MODE, TERM_SPEC, true>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M,
@@ -577,7 +632,7 @@ double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force
     tb.grid = grid_of(P);
     IterUpd up{};
     if (upd) up = *upd;
-    std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
+    std::vector<double> partials((size_t)mv_blocks<T>(true, (int)(2 * P.N), P.M));
     with_L2<MvSpec2nRun<T, MODE>::template R>((int)(2 * P.N), const_cast<T*>(z), out, fin, P.M, tb, up,
                                              partials.data());
     for (double v : partials) dot += v;
@@ -615,30 +670,22 @@ void apply_wx(const T* Z, T* Wa, const T* Wb, T* X, int64_t n, const double* coe
   run_grid(TPB_EW, nb, 1, 0, [&](HostCtx& c, unsigned char*) { wx_body<T, T>(c, Z, Wa, Wb, X, n, coef); });
 }
 
-// the tiled transpose, and the sum of its per-workgroup partial sums of squares
-double apply_transpose(const double* in, double* out, int64_t R, int64_t C, bool rev) {
+void apply_transpose(const double* in, double* out, int64_t R, int64_t C, bool rev) {
   const int64_t nb = ((C + TR_TILE - 1) / TR_TILE) * ((R + TR_TILE - 1) / TR_TILE);
-  std::vector<double> partials((size_t)nb, 0.0);
-  run_grid(TPB_EW, (int)nb, 1, sizeof(double) * (TR_TILE * (TR_TILE + 1) + TPB_EW),
-           [&](HostCtx& c, unsigned char* lds) {
-             double* tile = reinterpret_cast<double*>(lds);
-             double* red = tile + TR_TILE * (TR_TILE + 1);
-             if (rev)
-               transpose_body<double, true>(c, tile, in, out, R, C, red, partials.data());
-             else
-               transpose_body<double, false>(c, tile, in, out, R, C, red, partials.data());
-           });
-  double s = 0.0;
-  for (double v : partials) s += v;
-  return s;
+  run_grid(TPB_EW, (int)nb, 1, sizeof(double) * TR_TILE * (TR_TILE + 1), [&](HostCtx& c, unsigned char* lds) {
+    if (rev)
+      transpose_body<double, true>(c, reinterpret_cast<double*>(lds), in, out, R, C);
+    else
+      transpose_body<double, false>(c, reinterpret_cast<double*>(lds), in, out, R, C);
+  });
 }
 
 }  // namespace
 
 extern "C" {
 
-double emu_transpose_f64(const double* in, double* out, int64_t R, int64_t C, int rev) {
-  return apply_transpose(in, out, R, C, rev != 0);
+void emu_transpose_f64(const double* in, double* out, int64_t R, int64_t C, int rev) {
+  apply_transpose(in, out, R, C, rev != 0);
 }
 
 int64_t emu_state_size(void) { return (int64_t)sizeof(SolverState); }
@@ -683,6 +730,7 @@ int emu_error(void) { return g_error; }
 #define EMU_P make_problem(dim, m, h, N, alpha, p, q)
 
 void emu_space_f64(EMU_ARGS, const double* x, double* y) { apply_space<double>(EMU_P, x, y); }
+double emu_sine_io(EMU_ARGS, const double* x, double* y, int dir) { return apply_sine_io(EMU_P, x, y, dir); }
 void emu_space_f32(EMU_ARGS, const float* x, float* y) { apply_space<float>(EMU_P, x, y); }
 void emu_time_f64(EMU_ARGS, double* x) { apply_time<double>(EMU_P, x); }
 void emu_time_f32(EMU_ARGS, float* x) { apply_time<float>(EMU_P, x); }
