@@ -708,6 +708,16 @@ bool overlaps(const void* a, const void* b, int64_t bytes) {
 
 int check_power(int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
+// Stopping tolerance of one FP32 sweep on |eta|/eta_0: the inner tolerance,
+// loosened to what the outer tolerance still asks for (tol / relres, relres the
+// current relative residual), so the last sweep does not solve past the
+// target.  |eta| estimates the P^{-1}-norm residual; the measured 2-norm
+// residual after a sweep is typically a few times below that estimate, and the
+// explicit FP64 residual that follows decides convergence either way.
+double sweep_tol(const bltt_handle* h, double tol, double relres) {
+  return relres > 0.0 ? std::max(h->opt.inner_tol, tol / relres) : h->opt.inner_tol;
+}
+
 // strided sine transforms along dimensions 1..dim-1 on a mode-major vector
 // (element (i, n) at i*N + n: the lines of dimension d have stride N * m_0 * ... * m_{d-1})
 int space_strided_mm(bltt_handle* h, double* x, bool reverse) {
@@ -982,7 +992,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         const int left = maxit - total_iters;
         hbuf.assign((size_t)left + 2, 0.0);
         // r = b = Y fhat on the first sweep (read from fhat reversed), then the residual
-        rc = minres_spec<float, float, double>(h, nullptr, left, h->opt.inner_tol, nullptr, 0.0, 1.0, hbuf.data(),
+        rc = minres_spec<float, float, double>(h, nullptr, left, sweep_tol(h, tol, relres), nullptr, 0.0, 1.0, hbuf.data(),
                                                &cr, outer == 0 ? fhat : h->R64, &h->state->rinv, true, outer == 0);
         if (rc) return rc;
         if (hist)
@@ -1097,7 +1107,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
       CoreResult cr;
       const int left = maxit - total_iters;
       hbuf.assign((size_t)left + 2, 0.0);
-      rc = minres_core<float, float>(h, ws.X, left, h->opt.inner_tol, nullptr, 0.0, 1.0, hbuf.data(), &cr);
+      rc = minres_core<float, float>(h, ws.X, left, sweep_tol(h, tol, relres), nullptr, 0.0, 1.0, hbuf.data(), &cr);
       if (rc) return rc;
       if (hist) {
         for (int k = 1; k <= cr.iters; ++k) hist[hist_pos + k] = hbuf[(size_t)k];
