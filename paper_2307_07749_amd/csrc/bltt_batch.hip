@@ -56,6 +56,8 @@ struct BatchClass {
   SolverState* states = nullptr;
   SolverState* states_host = nullptr;
   int* act_host = nullptr;         // pinned staging of the active flags
+  double* etol_dev = nullptr;      // per-system sweep tolerance
+  double* etol_host = nullptr;     // pinned staging of it
   double** uptr_host = nullptr;    // pinned staging of the caller's u pointers
   int sweeps = 0;                  // sweeps completed in the current solve
   double* partials = nullptr;
@@ -129,6 +131,7 @@ BatchVec bvec(BatchClass& c) {
   bv.T = c.T;
   bv.S = c.S;
   bv.active = c.active_dev;
+  bv.etol = c.etol_dev;
   bv.states = c.states;
   return bv;
 }
@@ -339,15 +342,19 @@ int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const doub
   c.tabs.ip = c.ip_dev;
   c.tabs.sys_inst = c.sys_inst_dev;
   // per-system state
-  if ((rc = balloc(b, &c.active_dev, (size_t)S)) || (rc = balloc(b, &c.states, (size_t)S)) ||
+  if ((rc = balloc(b, &c.active_dev, (size_t)S)) || (rc = balloc(b, &c.etol_dev, (size_t)S)) ||
+      (rc = balloc(b, &c.states, (size_t)S)) ||
       (rc = balloc(b, &c.zb, (size_t)(3 * BT_POOL * S))))
     return rc;
   HIPCHK(hipMemset(c.states, 0, sizeof(SolverState) * (size_t)S));
   HIPCHK(hipMemset(c.zb, 0, sizeof(double) * (size_t)(3 * BT_POOL * S)));
   std::vector<int> ones((size_t)S, 1);
   HIPCHK(hipMemcpy(c.active_dev, ones.data(), sizeof(int) * (size_t)S, hipMemcpyHostToDevice));
+  const std::vector<double> tol0((size_t)S, b->opt.inner_tol);
+  HIPCHK(hipMemcpy(c.etol_dev, tol0.data(), sizeof(double) * (size_t)S, hipMemcpyHostToDevice));
   if (hipHostMalloc((void**)&c.states_host, sizeof(SolverState) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c.act_host, sizeof(int) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c.etol_host, sizeof(double) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c.uptr_host, sizeof(double*) * (size_t)S, hipHostMallocDefault) != hipSuccess)
     return BLTT_ENOMEM;
   c.hist_stride = BT_POOL + 2;
@@ -382,6 +389,7 @@ void destroy_class(BatchClass& c) {
   if (c.ev) (void)hipEventDestroy(c.ev);
   if (c.states_host) (void)hipHostFree(c.states_host);
   if (c.act_host) (void)hipHostFree(c.act_host);
+  if (c.etol_host) (void)hipHostFree(c.etol_host);
   if (c.uptr_host) (void)hipHostFree(c.uptr_host);
 }
 
@@ -588,14 +596,19 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
       if (step[ci] == ST_START) {
         bool live = false;
         for (int s = 0; s < c.S; ++s) {
-          c.act_host[s] = R[(size_t)s].active ? 1 : 0;
-          live = live || R[(size_t)s].active;
+          const SysRun& r = R[(size_t)s];
+          c.act_host[s] = r.active ? 1 : 0;
+          // the sweep needs no more than the outer tolerance still asks for
+          c.etol_host[s] = r.relres > 0.0 ? std::max(inner_tol, tol / r.relres) : inner_tol;
+          live = live || r.active;
         }
         if (!live) {
           step[ci] = ST_FINISH;
         } else {
           // the stream is idle here (the previous step was collected)
           HIPCHK(hipMemcpyAsync(c.active_dev, c.act_host, sizeof(int) * (size_t)c.S, hipMemcpyHostToDevice,
+                                c.stream));
+          HIPCHK(hipMemcpyAsync(c.etol_dev, c.etol_host, sizeof(double) * (size_t)c.S, hipMemcpyHostToDevice,
                                 c.stream));
           HIPCHK(launch_bt(BT_START, (int)c.N, c.tpb, c.R64, nullptr, nullptr, c.V[0], c.pool.z[0], nullptr, bv,
                            c.tabs, c.partials, c.stream));

@@ -1828,14 +1828,15 @@ namespace bltt {
 // Batched scalar phase: workgroup s updates system s of a batch from its own
 // range of partial sums (T per system).  Systems outside the outer loop
 // (active[s] = 0) and, in the Lanczos phases, systems whose sweep has stopped
-// are left alone.  After SC_BETA a sweep stops on |eta|/eta0 <= inner_tol, on
-// exact convergence, on error, or after cap iterations.
+// are left alone.  After SC_BETA a sweep stops on |eta|/eta0 <= etol[s] (the
+// system's own sweep tolerance; inner_tol when etol is null), on exact
+// convergence, on error, or after cap iterations.
 // ---------------------------------------------------------------------------
 template <class Ctx>
 BLTT_HD void batch_scalar_body(Ctx& ctx, double* red, int phase, SolverState* __restrict__ states,
                                const double* __restrict__ partials, int64_t T, double* __restrict__ hist,
                                int64_t hist_stride, double* __restrict__ zb, int K, double inner_tol, int cap,
-                               const int* __restrict__ active) {
+                               const int* __restrict__ active, const double* __restrict__ etol = nullptr) {
   const int s = ctx.bid;
   if (!active[s]) return;
   SolverState* st = states + s;
@@ -1848,7 +1849,8 @@ BLTT_HD void batch_scalar_body(Ctx& ctx, double* red, int phase, SolverState* __
               hist ? hist + (int64_t)s * hist_stride : nullptr, z);
   if (ctx.tid == 0) {
     if (phase == SC_START) st->done = st->status != 0 ? 1 : 0;
-    if (phase == SC_BETA && (st->status != 0 || fabs(st->eta) <= inner_tol * st->eta0 || st->iter >= cap))
+    const double tol_s = etol ? etol[s] : inner_tol;
+    if (phase == SC_BETA && (st->status != 0 || fabs(st->eta) <= tol_s * st->eta0 || st->iter >= cap))
       st->done = 1;
   }
 }
@@ -1884,6 +1886,7 @@ struct BatchVec {
   int64_t n, M, T;        // elements per system, modes, tiles per system
   int S;
   const int* active;      // outer loop running (per system)
+  const double* etol;     // sweep tolerance on |eta|/eta0 (per system)
   SolverState* states;    // per system
 };
 struct ZPool {

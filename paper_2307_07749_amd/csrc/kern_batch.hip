@@ -37,10 +37,11 @@ __global__ __launch_bounds__(TPB_EW) void k_bt_scalar(int phase, SolverState* __
                                                       const double* __restrict__ partials, int64_t T,
                                                       double* __restrict__ hist, int64_t hist_stride,
                                                       double* __restrict__ zb, int K, double inner_tol, int cap,
-                                                      const int* __restrict__ active) {
+                                                      const int* __restrict__ active,
+                                                      const double* __restrict__ etol) {
   __shared__ double red[TPB_EW];
   DevCtx ctx = make_ctx();
-  batch_scalar_body(ctx, red, phase, states, partials, T, hist, hist_stride, zb, K, inner_tol, cap, active);
+  batch_scalar_body(ctx, red, phase, states, partials, T, hist, hist_stride, zb, K, inner_tol, cap, active, etol);
 }
 
 __global__ __launch_bounds__(TPB_EW) void k_bt_rhs(const double* __restrict__ f, double* __restrict__ b, int log2N,
@@ -145,7 +146,7 @@ hipError_t launch_bt_resid(int L2, double* const* u, double* R, const double* Fh
 hipError_t launch_bt_scalar(int phase, const BatchVec& bv, const double* partials, int64_t T, double* hist,
                             int64_t hist_stride, double* zb, int K, double inner_tol, int cap, hipStream_t s) {
   hipLaunchKernelGGL(k_bt_scalar, dim3((unsigned)bv.S), dim3(TPB_EW), 0, s, phase, bv.states, partials, T, hist,
-                     hist_stride, zb, K, inner_tol, cap, bv.active);
+                     hist_stride, zb, K, inner_tol, cap, bv.active, bv.etol);
   return hipGetLastError();
 }
 
