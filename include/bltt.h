@@ -141,6 +141,32 @@ int bltt_setup(const bltt_blocks *blk, int64_t N, int64_t M, double alpha,
                const bltt_options *opt, void *stream, bltt_handle **out);
 
 /*
+ * bltt_setup_varcoef -- as bltt_setup, for blocks p_k I + q_k L_{a,h} with a
+ * variable coefficient a(x) > 0: L_{a,h} = -Delta_{a,h} is the central-
+ * difference form of -div(a grad) with zero Dirichlet boundary (Section 5.2,
+ * the heat equation with variable coefficients):
+ *   (L_{a,h} v)_i = sum_d [a_{d,hi}(i) (v_i - v_{i+e_d}) + a_{d,lo}(i) (v_i - v_{i-e_d})] / h_d^2.
+ * The preconditioner is P_alpha of the mean-coefficient system, blocks
+ * p_k I + q_k abar L_h (Section 5.2): abar is the constant the caller takes
+ * for a (the paper uses the mean of a over the grid points).
+ *   face   face[d], d < dim: host arrays of a at the faces along dimension d,
+ *          lexicographic with x fastest, extents m_e for e != d and m_d + 1
+ *          along d; entry j along d lies between grid points j-1 and j (j = 0
+ *          and j = m_d are the boundary faces).  Copied at setup; every
+ *          entry must be finite and > 0.
+ *   abar   > 0
+ * The operator is not diagonalised by the sine transform, so the solver runs
+ * in the physical basis whatever opt->basis says (FP64 or MIXED precision);
+ * opt->precond must be BLTT_PRECOND_ABAC.  Assumption 1(ii) is checked for
+ * the mean-coefficient system.
+ * Errors: as bltt_setup; BLTT_EINVAL for a null face array or a coefficient
+ * that is not finite and positive.
+ */
+int bltt_setup_varcoef(const bltt_blocks *blk, const double *const *face, double abar, int64_t N,
+                       int64_t M, double alpha, const bltt_options *opt, void *stream,
+                       bltt_handle **out);
+
+/*
  * bltt_pminres -- solve A u = f by preconditioned MINRES on Y A u = Y f with
  * a zero initial guess.  Stops when ||Y(f - A u)||_2 / ||Y f||_2 <= tol.
  *   f_dev   FP64 device vector of length N*M (not modified)

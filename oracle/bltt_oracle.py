@@ -75,9 +75,16 @@ def _as_grid(v: np.ndarray, N: int, ms) -> np.ndarray:
     return v.reshape((N,) + tuple(reversed(ms)))
 
 
-def laplacian_apply(v: np.ndarray, ms, hs) -> np.ndarray:
+def laplacian_apply(v: np.ndarray, ms, hs, faces=None) -> np.ndarray:
     """L_h v for every time slice: 2d/h^2 on the diagonal, -1/h^2 on each
-    neighbour, zero Dirichlet boundary (central differences, Section 5)."""
+    neighbour, zero Dirichlet boundary (central differences, Section 5).
+
+    With ``faces`` it is L_{a,h} = -Delta_{a,h}, the central-difference form of
+    -div(a grad) (Section 5.2): per dimension d, faces[d] holds a at the points
+    halfway between neighbours along d (grid shape with m_d + 1 entries along
+    d; entry j sits between points j-1 and j, the outer two on the boundary),
+    and (L_{a,h} v)_i = sum_d [a_{j=i+1} (v_i - v_{i+1}) + a_{j=i} (v_i - v_{i-1})] / h_d^2
+    with v = 0 outside the grid."""
     N = v.shape[0]
     g = _as_grid(v, N, ms)
     out = np.zeros_like(g)
@@ -85,13 +92,26 @@ def laplacian_apply(v: np.ndarray, ms, hs) -> np.ndarray:
     for d in range(dim):
         ax = g.ndim - 1 - d          # axis of dimension d (x is last)
         inv_h2 = 1.0 / (hs[d] * hs[d])
-        out += 2.0 * inv_h2 * g
-        lo = [slice(None)] * g.ndim
-        hi = [slice(None)] * g.ndim
-        lo[ax] = slice(0, -1)
-        hi[ax] = slice(1, None)
-        out[tuple(lo)] -= inv_h2 * g[tuple(hi)]
-        out[tuple(hi)] -= inv_h2 * g[tuple(lo)]
+        if faces is None:
+            out += 2.0 * inv_h2 * g
+            lo = [slice(None)] * g.ndim
+            hi = [slice(None)] * g.ndim
+            lo[ax] = slice(0, -1)
+            hi[ax] = slice(1, None)
+            out[tuple(lo)] -= inv_h2 * g[tuple(hi)]
+            out[tuple(hi)] -= inv_h2 * g[tuple(lo)]
+        else:
+            # flux through face j: a_j (v_j - v_{j-1}), with zero ghost values
+            pad = [(0, 0)] * g.ndim
+            pad[ax] = (1, 1)
+            gp = np.pad(g, pad)
+            a = faces[d].reshape(tuple(reversed([m + (1 if e == d else 0) for e, m in enumerate(ms)])))
+            flux = a[None] * np.diff(gp, axis=ax)
+            lo = [slice(None)] * g.ndim
+            hi = [slice(None)] * g.ndim
+            lo[ax] = slice(0, -1)
+            hi[ax] = slice(1, None)
+            out += inv_h2 * (flux[tuple(lo)] - flux[tuple(hi)])
     return out.reshape(N, -1)
 
 
@@ -115,13 +135,19 @@ def space_transform(v: np.ndarray, ms) -> np.ndarray:
 
 @dataclass
 class System:
-    """A BLTT system A u = f with blocks p[k] I + q[k] L_h and parameter alpha."""
+    """A BLTT system A u = f with blocks p[k] I + q[k] L_h and parameter alpha.
+
+    With ``faces`` (see laplacian_apply) the blocks are p[k] I + q[k] L_{a,h};
+    the preconditioner is then the one of the mean-coefficient system, blocks
+    p[k] I + q[k] abar L_h (Section 5.2)."""
 
     ms: tuple
     hs: tuple
     p: np.ndarray
     q: np.ndarray
     alpha: float
+    faces: tuple | None = None
+    abar: float = 1.0
 
     @property
     def N(self) -> int:
@@ -151,7 +177,7 @@ def bltt_apply(sys: System, v: np.ndarray) -> np.ndarray:
     V = v.reshape(N, -1)
     out = lower_toeplitz(sys.p) @ V
     if np.any(sys.q != 0.0):
-        out += lower_toeplitz(sys.q) @ laplacian_apply(V, sys.ms, sys.hs)
+        out += lower_toeplitz(sys.q) @ laplacian_apply(V, sys.ms, sys.hs, sys.faces)
     return out
 
 
@@ -182,11 +208,13 @@ def alpha_scaling(N: int, alpha: float) -> np.ndarray:
 
 def alpha_eigenvalues(sys: System) -> np.ndarray:
     """lambda[k, i] = sum_j lambda_i^{(j)} alpha^{j/N} theta^{-k j} (eq. (9)),
-    with lambda_i^{(j)} = p_j + q_j mu_i the eigenvalues of block j in mode i.
+    with lambda_i^{(j)} = p_j + q_j mu_i the eigenvalues of block j in mode i
+    (mu scaled by abar for a variable-coefficient system: the eigenvalues of
+    its mean-coefficient system).
 
     Written as sqrt(N) F^* D_alpha c_i, the right-hand form of eq. (9)."""
     N = sys.N
-    mu = laplacian_eigs(sys.ms, sys.hs)
+    mu = sys.abar * laplacian_eigs(sys.ms, sys.hs)
     cols = sys.p[:, None] + sys.q[:, None] * mu[None, :]          # (N, M)
     F = fourier_unitary(N)
     return math.sqrt(N) * (F.conj().T @ (alpha_scaling(N, sys.alpha)[:, None] * cols))
@@ -363,13 +391,58 @@ def pminres(sys: System, f: np.ndarray, tol: float, maxit: int,
 # exact solution
 # ---------------------------------------------------------------------------
 
+def laplacian_matrix(ms, hs, faces=None):
+    """L_h (or L_{a,h} with faces) as a scipy.sparse matrix, assembled face by
+    face: each interior face between lexicographic points i and i' adds
+    a_f/h^2 to (i,i) and (i',i') and -a_f/h^2 to (i,i') and (i',i); each
+    boundary face adds a_f/h^2 to the diagonal of its one point."""
+    import scipy.sparse as sp
+    M = int(np.prod(ms))
+    rows, cols, vals = [], [], []
+    idx = np.arange(M).reshape(tuple(reversed(ms)))
+    for d, m in enumerate(ms):
+        ax = idx.ndim - 1 - d
+        shape = list(reversed([mm + (1 if e == d else 0) for e, mm in enumerate(ms)]))
+        a = np.ones(shape) if faces is None else faces[d].reshape(shape)
+        w = a / (hs[d] * hs[d])
+        for j in range(m + 1):
+            wj = np.take(w, j, axis=ax).ravel()
+            if j > 0:
+                left = np.take(idx, j - 1, axis=ax).ravel()
+                rows.append(left); cols.append(left); vals.append(wj)
+            if j < m:
+                right = np.take(idx, j, axis=ax).ravel()
+                rows.append(right); cols.append(right); vals.append(wj)
+            if 0 < j < m:
+                rows += [left, right]; cols += [right, left]; vals += [-wj, -wj]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(M, M))
+
+
 def exact_solve(sys: System, f: np.ndarray) -> np.ndarray:
     """u* = A^{-1} f by block forward substitution in sine-transform
-    coordinates.  Every block is diagonal there with entries
+    coordinates (physical coordinates and a sparse LU of the first block for
+    a variable-coefficient system).  Every block is diagonal there with entries
     p_k + q_k mu_i (Remark 1), so each time step is a pointwise division:
         ut_n = (ft_n - sum_{k=1}^{n} (p_k + q_k mu) ut_{n-k}) / (p_0 + q_0 mu).
     """
     N = sys.N
+    if sys.faces is not None:
+        # not sine-diagonal: forward substitution with a sparse LU of A_(0) = p_0 I + q_0 L_{a,h}
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+        L = laplacian_matrix(sys.ms, sys.hs, sys.faces)
+        lu = spla.splu((sys.p[0] * sp.identity(sys.M) + sys.q[0] * L).tocsc())
+        F = f.reshape(N, -1).astype(np.float64)
+        U = np.zeros_like(F)
+        for n in range(N):
+            rhs = F[n].copy()
+            for k in range(1, n + 1):
+                if sys.p[k] != 0.0:
+                    rhs -= sys.p[k] * U[n - k]
+                if sys.q[k] != 0.0:
+                    rhs -= sys.q[k] * (L @ U[n - k])
+            U[n] = lu.solve(rhs)
+        return U
     mu = laplacian_eigs(sys.ms, sys.hs)
     ft = space_transform(f.reshape(N, -1).astype(np.float64), sys.ms)
     lam = sys.p[:, None] + sys.q[:, None] * mu[None, :]

@@ -70,6 +70,9 @@ def load() -> ctypes.CDLL:
     L.bltt_setup.argtypes = [ctypes.POINTER(Blocks), ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                              ctypes.POINTER(Options), P, ctypes.POINTER(P)]
     L.bltt_setup.restype = ctypes.c_int
+    L.bltt_setup_varcoef.argtypes = [ctypes.POINTER(Blocks), ctypes.POINTER(P), ctypes.c_double, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_double, ctypes.POINTER(Options), P, ctypes.POINTER(P)]
+    L.bltt_setup_varcoef.restype = ctypes.c_int
     L.bltt_pminres.argtypes = [P, P, ctypes.c_double, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Info)]
     L.bltt_pminres.restype = ctypes.c_int
@@ -123,10 +126,14 @@ class Solver:
     """One BLTT instance on the GPU (wraps a bltt_handle).
 
     Blocks are ``p[k] I + q[k] L_h`` on a ``dim``-dimensional grid with ``m``
-    interior points and spacing ``h`` per dimension (x first)."""
+    interior points and spacing ``h`` per dimension (x first).  With ``face``
+    (one array per dimension, the layout of bltt_setup_varcoef) the blocks are
+    ``p[k] I + q[k] L_{a,h}`` and ``abar`` is the coefficient of the
+    mean-coefficient system the preconditioner is built from."""
 
     def __init__(self, dim: int, m, h, p, q, alpha: float, precision: int = FP64, inner_tol: float = 0.0,
-                 max_refine: int = 0, check_factor: float = 0.0, basis: int = 0, precond: int = 0, stream=None):
+                 max_refine: int = 0, check_factor: float = 0.0, basis: int = 0, precond: int = 0, stream=None,
+                 face=None, abar: float = 1.0):
         L = load()
         self._L = L
         m = list(m)
@@ -149,8 +156,14 @@ class Solver:
         opt = Options(precision, inner_tol, max_refine, check_factor, basis, precond)
         self.stream = stream
         handle = ctypes.c_void_p()
-        rc = L.bltt_setup(ctypes.byref(blk), self.N, self.M, float(alpha), ctypes.byref(opt),
-                          ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle))
+        if face is None:
+            rc = L.bltt_setup(ctypes.byref(blk), self.N, self.M, float(alpha), ctypes.byref(opt),
+                              ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle))
+        else:
+            self._face = [np.ascontiguousarray(a, dtype=np.float64) for a in face]
+            ptrs = (ctypes.c_void_p * 3)(*([a.ctypes.data for a in self._face] + [None] * (3 - len(self._face))))
+            rc = L.bltt_setup_varcoef(ctypes.byref(blk), ptrs, float(abar), self.N, self.M, float(alpha),
+                                      ctypes.byref(opt), ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle))
         _check(rc)
         self._h = handle
 

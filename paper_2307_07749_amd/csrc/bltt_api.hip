@@ -70,6 +70,11 @@ struct bltt_handle {
   double c0 = 0.0;
   std::vector<double> p, q;
   int ptaps = 0, qtaps = 0;
+  // variable coefficient (Section 5.2): L_{a,h} from face coefficients in the
+  // operator, the mean-coefficient system abar L_h in the preconditioner
+  bool var = false;
+  double abar = 1.0;
+  double* face_dev[3] = {nullptr, nullptr, nullptr};
   DeviceTables<float> t32;
   DeviceTables<double> t64;
   Workspace<float> w32;
@@ -206,7 +211,12 @@ int build_tables(bltt_handle* h) {
   if ((rc = upload<T>(h, &t.d2, host::alpha_pow(h->N, h->alpha, 2.0)))) return rc;
   if ((rc = upload_c<T>(h, &t.sigma, host::alpha_spectrum(h->p, h->alpha)))) return rc;
   if ((rc = upload_c<T>(h, &t.rho, host::alpha_spectrum(h->q, h->alpha)))) return rc;
-  if ((rc = upload<T>(h, &t.mu, host::lap_eigs(h->dim, h->m, h->h)))) return rc;
+  {
+    // Laplacian eigenvalue of each sine mode, of abar L_h for a variable coefficient
+    std::vector<double> mu = host::lap_eigs(h->dim, h->m, h->h);
+    for (double& v : mu) v *= h->abar;
+    if ((rc = upload<T>(h, &t.mu, mu))) return rc;
+  }
   if (!short_p(h)) {
     if ((rc = upload_c<T>(h, &t.tw_mv, host::twiddles((int)(2 * h->N))))) return rc;
     if ((rc = upload_c<T>(h, &t.phat, host::matvec_spectrum(h->p)))) return rc;
@@ -274,6 +284,7 @@ Grid make_grid(const bltt_handle* h) {
   for (int d = 0; d < 3; ++d) {
     g.m[d] = h->m[d];
     g.inv_h2[d] = d < h->dim ? 1.0 / (h->h[d] * h->h[d]) : 0.0;
+    g.face[d] = h->face_dev[d];
   }
   return g;
 }
@@ -373,7 +384,7 @@ int matvec(bltt_handle* h, int mode, int term, const T* z, T* out, const T* fin,
                                  h->partials, h->max_blocks, np, h->stream));
       return BLTT_OK;
     }
-    if (mode == MV_RESID && term == TERM_STENCIL) {
+    if (mode == MV_RESID && term == TERM_STENCIL && !h->var) {
       // r = Y (f - p * u) on time lines, then the spatial term and ||r||^2 on x-lines
       const int64_t nlx = h->n / h->m[0];
       {
@@ -525,8 +536,13 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     HIPCHK(launch_fill<T>(Wb, h->n, T(0), s));
   }
   if ((rc = ensure_hist(h, (int64_t)maxit + 2))) return rc;
+  // Constant coefficient: the time-line matvec leaves out the stencil, which
+  // the x-line pass of the Lanczos update adds, and the stencil's share of
+  // delta comes from the previous time pass in sine coordinates.  A variable
+  // coefficient is not sine-diagonal: the matvec carries the whole operator.
+  const bool split = !h->var;
   // z_1 = P^{-1} b, beta_1 = sqrt(<b, z_1>)
-  if ((rc = precond<T>(h, Vc, nullptr, nullptr, nullptr, h->coef_one, ws.Q, Vc, Zc, &np, nullptr, true))) return rc;
+  if ((rc = precond<T>(h, Vc, nullptr, nullptr, nullptr, h->coef_one, ws.Q, Vc, Zc, &np, nullptr, split))) return rc;
   if ((rc = scalar(h, SC_START, np, h->hist_dev))) return rc;
   if ((rc = read_state(h))) return rc;
   if (h->state_host->status == -3) return BLTT_ENAN;
@@ -536,9 +552,10 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   res->status = BLTT_NOCONV;
   int j = 0;
   for (j = 1; j <= maxit; ++j) {
-    if ((rc = matvec<T>(h, MV_DOT, TERM_NONE, Zc, ws.Q, nullptr, &np))) return rc;
-    if ((rc = scalar(h, SC_DELTA, np, nullptr, true))) return rc;
-    if ((rc = precond<T>(h, ws.Q, Vc, j > 1 ? Vp : nullptr, Vn, coef_v, ws.Q, Vn, Zn, &np, Zc, true))) return rc;
+    if ((rc = matvec<T>(h, MV_DOT, split ? TERM_NONE : TERM_STENCIL, Zc, ws.Q, nullptr, &np))) return rc;
+    if ((rc = scalar(h, SC_DELTA, np, nullptr, split))) return rc;
+    if ((rc = precond<T>(h, ws.Q, Vc, j > 1 ? Vp : nullptr, Vn, coef_v, ws.Q, Vn, Zn, &np, split ? Zc : nullptr, split)))
+      return rc;
     if ((rc = scalar(h, SC_BETA, np, h->hist_dev))) return rc;
     {
       ProfScope ps(h, BLTT_K_WX, (4.0 * sizeof(T) + 2.0 * sizeof(TX)) * h->n);
@@ -783,8 +800,12 @@ void bltt_destroy(bltt_handle* h) {
   delete h;
 }
 
-int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const bltt_options* opt, void* stream,
-               bltt_handle** out) {
+}  // extern "C"
+
+namespace {
+
+int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, int64_t N, int64_t M, double alpha,
+               const bltt_options* opt, void* stream, bltt_handle** out) {
   const double t0 = now_ms();
   if (!blk || !out || !blk->p || !blk->q) return BLTT_EINVAL;
   if (blk->dim < 1 || blk->dim > 3 || N < 1 || M < 1) return BLTT_EINVAL;
@@ -815,6 +836,21 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   }
   if (qtaps > 4) return BLTT_EUNSUPPORTED;
   if (ptaps == 0 && qtaps == 0) return BLTT_EASSUMPTION;
+  std::vector<double> face_host[3];
+  if (face) {
+    // a > 0 at every face, abar > 0; the operator is not sine-diagonal, so the
+    // physical basis runs, with the preconditioner of the mean-coefficient system
+    if (!(abar > 0.0) || !std::isfinite(abar)) return BLTT_EINVAL;
+    if (opt && opt->precond == BLTT_PRECOND_NONE) return BLTT_EUNSUPPORTED;
+    for (int d = 0; d < blk->dim; ++d) {
+      if (!face[d]) return BLTT_EINVAL;
+      int64_t cnt = 1;
+      for (int e = 0; e < blk->dim; ++e) cnt *= blk->m[e] + (e == d ? 1 : 0);
+      face_host[d].assign(face[d], face[d] + cnt);
+      for (double v : face_host[d])
+        if (!(v > 0.0) || !std::isfinite(v)) return BLTT_EINVAL;
+    }
+  }
 
   bltt_handle* h = new (std::nothrow) bltt_handle();
   if (!h) return BLTT_ENOMEM;
@@ -846,12 +882,17 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
     if (opt->max_refine > 0) h->opt.max_refine = opt->max_refine;
     if (opt->check_factor >= 1.0) h->opt.check_factor = opt->check_factor;
   }
-  // Assumption 1(ii) (Proposition 1)
+  if (face) {
+    h->var = true;
+    h->abar = abar;
+    h->opt.basis = BLTT_BASIS_PHYSICAL;
+  }
+  // Assumption 1(ii) (Proposition 1), for the system the preconditioner is built from
   double mu_min = 0.0, mu_max = 0.0;
   for (int d = 0; d < h->dim; ++d) {
     const std::vector<double> e = host::lap_eigs_1d(h->m[d], h->h[d]);
-    mu_min += e.front();
-    mu_max += e.back();
+    mu_min += h->abar * e.front();
+    mu_max += h->abar * e.back();
   }
   h->c0 = host::assumption_margin(h->p, h->q, mu_min, mu_max);
   if (!(h->c0 > 0.0)) {
@@ -898,6 +939,8 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
     std::vector<double> one = {1.0, 0.0, 0.0, 0.0};
     if ((rc = upload<double>(h, &h->coef_one, one))) return fail(rc);
   }
+  for (int d = 0; d < h->dim; ++d)
+    if (h->var && (rc = upload<double>(h, &h->face_dev[d], face_host[d]))) return fail(rc);
   if ((rc = build_tables<double>(h))) return fail(rc);
   const bool sine = h->opt.basis == BLTT_BASIS_SINE;
   if (h->opt.precision == BLTT_MIXED) {
@@ -916,6 +959,21 @@ int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const
   h->setup_ms = now_ms() - t0;
   *out = h;
   return BLTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bltt_setup(const bltt_blocks* blk, int64_t N, int64_t M, double alpha, const bltt_options* opt, void* stream,
+               bltt_handle** out) {
+  return setup_impl(blk, nullptr, 1.0, N, M, alpha, opt, stream, out);
+}
+
+int bltt_setup_varcoef(const bltt_blocks* blk, const double* const* face, double abar, int64_t N, int64_t M,
+                       double alpha, const bltt_options* opt, void* stream, bltt_handle** out) {
+  if (!face) return BLTT_EINVAL;
+  return setup_impl(blk, face, abar, N, M, alpha, opt, stream, out);
 }
 
 int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit, double* u_dev, int32_t* iters,

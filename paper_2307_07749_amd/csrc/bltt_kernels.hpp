@@ -121,66 +121,102 @@ BLTT_HD double block_sum(Ctx& ctx, double* red, double v) {
 }
 
 // ---------------------------------------------------------------------------
-// spatial stencil L_h = -Delta_h, zero Dirichlet (Section 5)
+// spatial stencil L_h = -Delta_h, zero Dirichlet (Section 5), or, with face
+// coefficients, L_{a,h} = -Delta_{a,h}, the central-difference form of
+// -div(a grad) (Section 5.2):
+//   (L_{a,h} v)_i = sum_d [a_{d,hi}(i) (v_i - v_{i+e_d}) + a_{d,lo}(i) (v_i - v_{i-e_d})] / h_d^2,
+// v = 0 outside the grid.  face[d] holds a at the faces along d: an array with
+// the grid's extents except m_d + 1 along d (lexicographic, x fastest); entry
+// j along d lies between points j-1 and j, so point c has its low face at
+// j = c_d and its high face at j = c_d + 1.  a = 1 gives L_h.
 // ---------------------------------------------------------------------------
 struct Grid {
   int dim;
   int m[3];
   double inv_h2[3];
+  const double* face[3];  // nullptr: constant coefficient 1
 };
+
+// low/high face coefficients of point coords c along dimension d
+BLTT_HD void face_pair(const Grid& gr, const int* c, int d, double& lo, double& hi) {
+  if (!gr.face[d]) {
+    lo = hi = 1.0;
+    return;
+  }
+  int64_t idx = 0, stride = 1, sd = 1;
+  for (int e = 0; e < gr.dim; ++e) {
+    if (e == d) sd = stride;
+    idx += (int64_t)c[e] * stride;
+    stride *= gr.m[e] + (e == d ? 1 : 0);
+  }
+  lo = gr.face[d][idx];
+  hi = gr.face[d][idx + sd];
+}
 
 template <typename T>
 BLTT_HD T lap_at(const T* __restrict__ z, int64_t base, int64_t i, const Grid& gr) {
   // base = n*M, i = spatial index
   const T zc = z[base + i];
-  T acc = T(0);
+  int c[3] = {0, 0, 0};
   int64_t rest = i;
+  for (int d = 0; d < gr.dim; ++d) {
+    c[d] = (int)(rest % gr.m[d]);
+    rest /= gr.m[d];
+  }
+  T acc = T(0);
   int64_t stride = 1;
   for (int d = 0; d < gr.dim; ++d) {
     const int md = gr.m[d];
-    const int coord = (int)(rest % md);
-    rest /= md;
-    T s = T(2) * zc;
-    if (coord > 0) s -= z[base + i - stride];
-    if (coord < md - 1) s -= z[base + i + stride];
+    double alo, ahi;
+    face_pair(gr, c, d, alo, ahi);
+    T s = T(alo + ahi) * zc;
+    if (c[d] > 0) s -= T(alo) * z[base + i - stride];
+    if (c[d] < md - 1) s -= T(ahi) * z[base + i + stride];
     acc += T(gr.inv_h2[d]) * s;
     stride *= md;
   }
   return acc;
 }
 
-// Neighbour offsets of one spatial point, computed once per thread (the
-// point is fixed; only the time row changes).
+// Neighbour offsets and face coefficients of one spatial point, computed once
+// per thread (the point is fixed; only the time row changes).
 struct Stencil {
   int64_t off[6];  // +-stride per dimension, 0 when the neighbour is the boundary
   float has[6];    // 1 inside, 0 on the boundary
+  double w[6];     // face coefficient (low, high) per dimension
   int nd;
 };
 
 BLTT_HD Stencil make_stencil(int64_t i, const Grid& gr) {
   Stencil st;
+  int c[3] = {0, 0, 0};
   int64_t rest = i, stride = 1;
   st.nd = gr.dim;
+  for (int d = 0; d < gr.dim; ++d) {
+    c[d] = (int)(rest % gr.m[d]);
+    rest /= gr.m[d];
+  }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < gr.dim) {
       const int md = gr.m[d];
-      const int coord = (int)(rest % md);
-      rest /= md;
+      const int coord = c[d];
       st.off[2 * d] = coord > 0 ? -stride : 0;
       st.has[2 * d] = coord > 0 ? 1.f : 0.f;
       st.off[2 * d + 1] = coord < md - 1 ? stride : 0;
       st.has[2 * d + 1] = coord < md - 1 ? 1.f : 0.f;
+      face_pair(gr, c, d, st.w[2 * d], st.w[2 * d + 1]);
       stride *= md;
     } else {
       st.off[2 * d] = st.off[2 * d + 1] = 0;
       st.has[2 * d] = st.has[2 * d + 1] = 0.f;
+      st.w[2 * d] = st.w[2 * d + 1] = 0.0;
     }
   }
   return st;
 }
 
-// (L_h z)_i on the row starting at zrow (zrow points at element (n, i))
+// (L_{a,h} z)_i on the row starting at zrow (zrow points at element (n, i))
 template <typename T>
 BLTT_HD T lap_row(const T* __restrict__ zrow, const Stencil& st, const Grid& gr) {
   const T zc = zrow[0];
@@ -188,9 +224,10 @@ BLTT_HD T lap_row(const T* __restrict__ zrow, const Stencil& st, const Grid& gr)
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < st.nd) {
-      T s = T(2) * zc;
-      if (st.has[2 * d] != 0.f) s -= zrow[st.off[2 * d]];
-      if (st.has[2 * d + 1] != 0.f) s -= zrow[st.off[2 * d + 1]];
+      const T wl = T(st.w[2 * d]), wh = T(st.w[2 * d + 1]);
+      T s = (wl + wh) * zc;
+      if (st.has[2 * d] != 0.f) s -= wl * zrow[st.off[2 * d]];
+      if (st.has[2 * d + 1] != 0.f) s -= wh * zrow[st.off[2 * d + 1]];
       acc += T(gr.inv_h2[d]) * s;
     }
   }

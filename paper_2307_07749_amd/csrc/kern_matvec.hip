@@ -28,12 +28,13 @@ __global__ __launch_bounds__(TPB_EW) void k_matvec_short(const T* __restrict__ z
   matvec_short_body<T, MODE>(ctx, red, z, out, fin, M, tb, partials);
 }
 
-// (mode, term) combinations in use: Y A z with the stencil (step entry point),
-// Y (p * z) alone (physical-space MINRES), the residual without the stencil
-// (its spatial term follows on x-lines), and the FP64 sine-coordinate forms
-// (FP32 uses the N-point kernel of kern_cs.hip).
+// (mode, term) combinations in use: Y A z with the stencil (step entry point,
+// variable-coefficient MINRES), Y (p * z) alone (physical-space MINRES), the
+// residual without the stencil (its spatial term follows on x-lines) or with
+// it (variable coefficient), and the FP64 sine-coordinate forms (FP32 uses
+// the N-point kernel of kern_cs.hip).
 #define BLTT_MV_VARIANTS(X) X(MV_DOT, TERM_STENCIL) X(MV_DOT, TERM_NONE) X(MV_RESID, TERM_NONE) \
-  X(MV_DOT, TERM_SPEC) X(MV_RESID, TERM_SPEC)
+  X(MV_DOT, TERM_SPEC) X(MV_RESID, TERM_SPEC) X(MV_RESID, TERM_STENCIL)
 
 template <typename T, int L>
 static hipError_t go_mv(int mode, int term, T* z, T* out, const T* fin, int64_t M,

@@ -78,6 +78,9 @@ def lib():
         L.emu_resid_upd_f64.restype = ctypes.c_double
         L.emu_state_size.restype = ctypes.c_int64
         L.emu_transpose_f64.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+        L.emu_set_faces.argtypes = [P, P, P]
+        L.emu_resid_full_f64.argtypes = args + [P, P, P, ctypes.c_int]
+        L.emu_resid_full_f64.restype = ctypes.c_double
         L.emu_sine_io.argtypes = args + [P, P, ctypes.c_int]
         L.emu_sine_io.restype = ctypes.c_double
         L.emu_state_offsets.argtypes = [P]
@@ -140,6 +143,34 @@ def space(prob, x, dtype=np.float64):
     getattr(lib(), f"emu_space_{_tag(dtype)}")(*args, gx.ptr, gy.ptr)
     _check(gx, gy)
     return gy.data.copy()
+
+
+class faces:
+    """Context manager: the emulated kernels use the variable-coefficient
+    stencil with these face arrays (one per dimension) while active."""
+
+    def __init__(self, arrays):
+        self.arrays = [np.ascontiguousarray(a, dtype=np.float64) for a in arrays]
+
+    def __enter__(self):
+        ptrs = [a.ctypes.data for a in self.arrays] + [None] * (3 - len(self.arrays))
+        lib().emu_set_faces(*ptrs)
+        return self
+
+    def __exit__(self, *exc):
+        lib().emu_set_faces(None, None, None)
+        return False
+
+
+def resid_full(prob, u, f, force_fft=False):
+    """r = Y (f - A u) with the stencil inside the time-line pass; returns (r, ||r||^2)."""
+    args, keep = _common(prob)
+    gu = Guarded(u, np.float64)
+    gf = Guarded(f, np.float64)
+    gr = Guarded(np.zeros(prob.n), np.float64)
+    s = lib().emu_resid_full_f64(*args, gu.ptr, gf.ptr, gr.ptr, int(force_fft))
+    _check(gu, gf, gr)
+    return gr.data.copy(), s
 
 
 def sine_io(prob, x, direction):

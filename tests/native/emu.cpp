@@ -233,12 +233,16 @@ Problem make_problem(int dim, const int* m, const double* h, int64_t N, double a
   return P;
 }
 
+// face coefficients of a variable-coefficient operator (emu_set_faces; null: a = 1)
+const double* g_faces[3] = {nullptr, nullptr, nullptr};
+
 Grid grid_of(const Problem& P) {
   Grid g;
   g.dim = P.dim;
   for (int d = 0; d < 3; ++d) {
     g.m[d] = P.m[d];
     g.inv_h2[d] = d < P.dim ? 1.0 / (P.h[d] * P.h[d]) : 0.0;
+    g.face[d] = d < P.dim ? g_faces[d] : nullptr;
   }
   return g;
 }
@@ -462,6 +466,66 @@ struct MvResRun {
     }
   };
 };
+
+// r = Y (f - A u) in one pass, stencil included (the variable-coefficient form)
+template <typename T>
+struct MvResFullRun {
+  template <int L>
+  struct R {
+    static void run(const T* z, T* out, const T* fin, int64_t M, const MatvecTables<T>& tb, double* partials) {
+      constexpr int NL = lines_per_block<T, FK_MV>(L);
+      using Fm = LineFft<T, L, NL, true, LAST_DEFAULT>;
+      run_grid(tpb_fft<T, FK_MV>(), (int)fft_blocks<T, FK_MV>(L, M), 1, fft_lds_bytes<T, FK_MV>(L),
+               [&](HostCtx& c, unsigned char* lds) {
+                 double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
+                 matvec_fft_body<T, L, MV_RESID, TERM_STENCIL, false>(c, reinterpret_cast<cx<T>*>(lds), red,
+                                                                      const_cast<T*>(z), out, fin, M, tb, IterUpd{},
+                                                                      partials);
+               });
+    }
+  };
+};
+
+template <typename T>
+double apply_resid_full(const Problem& P, const T* u, const T* f, T* r, bool force_fft) {
+  int ptaps = 0, qtaps = 0;
+  for (int64_t k = 0; k < P.N; ++k) {
+    if (P.p[(size_t)k] != 0.0) ptaps = (int)k + 1;
+    if (P.q[(size_t)k] != 0.0) qtaps = (int)k + 1;
+  }
+  double s = 0.0;
+  if (ptaps <= 8 && !force_fft) {
+    ShortTables<T> tb;
+    for (int k = 0; k < 8; ++k) tb.p[k] = (T)(k < ptaps ? P.p[(size_t)k] : 0.0);
+    tb.ptaps = ptaps;
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+    tb.qtaps = qtaps;
+    tb.grid = grid_of(P);
+    tb.N = (int)P.N;
+    tb.chunk = 8;
+    tb.term = TERM_STENCIL;
+    tb.mu = nullptr;
+    const int gx = (int)((P.M + TPB_EW - 1) / TPB_EW);
+    const int gy = (int)(((P.N + 1) / 2 + tb.chunk - 1) / tb.chunk);
+    std::vector<double> partials((size_t)gx * gy);
+    run_grid(TPB_EW, gx, gy, TPB_EW * sizeof(double), [&](HostCtx& c, unsigned char* lds) {
+      matvec_short_body<T, MV_RESID>(c, reinterpret_cast<double*>(lds), u, r, f, P.M, tb, partials.data());
+    });
+    for (double v : partials) s += v;
+  } else {
+    HostTables<T> ht(P);
+    MatvecTables<T> tb;
+    tb.tw = ht.tw_mv.data();
+    tb.phat = ht.phat.data();
+    for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
+    tb.qtaps = qtaps;
+    tb.grid = grid_of(P);
+    std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
+    with_L2<MvResFullRun<T>::template R>((int)(2 * P.N), u, r, f, P.M, tb, partials.data());
+    for (double v : partials) s += v;
+  }
+  return s;
+}
 
 template <typename T>
 double apply_resid(const Problem& P, const T* u, const T* f, T* r) {
@@ -736,6 +800,14 @@ void emu_time_f64(EMU_ARGS, double* x) { apply_time<double>(EMU_P, x); }
 void emu_time_f32(EMU_ARGS, float* x) { apply_time<float>(EMU_P, x); }
 void emu_precond_f64(EMU_ARGS, const double* x, double* y) { apply_precond<double>(EMU_P, x, y); }
 void emu_precond_f32(EMU_ARGS, const float* x, float* y) { apply_precond<float>(EMU_P, x, y); }
+void emu_set_faces(const double* f0, const double* f1, const double* f2) {
+  g_faces[0] = f0;
+  g_faces[1] = f1;
+  g_faces[2] = f2;
+}
+double emu_resid_full_f64(EMU_ARGS, const double* u, const double* f, double* r, int force_fft) {
+  return apply_resid_full<double>(EMU_P, u, f, r, force_fft != 0);
+}
 double emu_sym_f64(EMU_ARGS, const double* x, double* y, int force_fft) {
   return apply_sym<double>(EMU_P, x, y, force_fft != 0);
 }

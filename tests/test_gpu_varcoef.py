@@ -1,0 +1,98 @@
+"""Variable-coefficient blocks p_k I + q_k L_{a,h} on the GPU (Section 5.2):
+the paper's Table 3 (Example 2, Crank-Nicolson heat) and Tables 7-9
+(Example 4, L1 scheme) iteration counts with the preconditioner of the
+mean-coefficient system, solutions against the oracle's exact solve, the
+step-level operator against the oracle, and the mixed-precision path."""
+import numpy as np
+import pytest
+
+from oracle import bltt_oracle as O
+from paper_2307_07749_amd import bltt
+from tests import paper_examples as PE
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def solver(sysm, precision=bltt.FP64, **kw):
+    return bltt.Solver(len(sysm.ms), sysm.ms, sysm.hs, sysm.p, sysm.q, sysm.alpha, precision=precision,
+                       face=sysm.faces, abar=sysm.abar, **kw)
+
+
+def solve(sysm, f, tol, maxit, precision=bltt.FP64, **kw):
+    s = solver(sysm, precision, **kw)
+    try:
+        u, iters, hist, info, rc = s.pminres(torch.from_numpy(np.ascontiguousarray(f.ravel())).cuda(), tol, maxit)
+    finally:
+        s.close()
+    return u.cpu().numpy(), iters, info, rc
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("row", PE.golden_counts()["example2_heat_varcoef_cn"]["rows"])
+def test_table3_counts_on_gpu(row):
+    N, mp1 = row["N"], row["m_plus_1"]
+    print(f"[example 2] N={N} m+1={mp1}", flush=True)
+    sysm, f, _, _ = PE.example2_system_and_rhs(N, mp1, 1e-8)
+    u, it, info, rc = solve(sysm, f, 1e-6, 100, check_factor=1e12)
+    assert rc == bltt.OK and it == row["P_alpha"]
+    assert info["true_relres"] <= 1e-6
+    ref = O.pminres(sysm, f, 1e-6, 100)
+    assert rel(u, ref.x) < 1e-7
+
+
+@pytest.mark.parametrize("row", PE.golden_counts()["example4_fractional_varcoef"]["rows"])
+def test_tables7to9_counts_on_gpu(row):
+    g, N, mp1 = row["gamma"], row["N"], row["m_plus_1"]
+    print(f"[example 4] gamma={g} N={N} m+1={mp1}", flush=True)
+    sysm, f, _, _, _ = PE.example4_system_and_rhs(g, N, mp1, 1e-8)
+    u, it, info, rc = solve(sysm, f, 1e-6, 100, check_factor=1e12)
+    assert rc == bltt.OK and it == row["P_alpha"]
+    ustar = O.exact_solve(sysm, f).ravel()
+    assert rel(u, ustar) < 1e-4
+    sysm.alpha = 1.0
+    _, it1, _, rc1 = solve(sysm, f, 1e-6, 100, check_factor=1e12)
+    assert rc1 == bltt.OK and it1 == row["P_1"]
+
+
+@pytest.mark.parametrize("precision", [bltt.FP64, bltt.MIXED])
+@pytest.mark.parametrize("example,N,mp1", [(2, 64, 128), (4, 128, 64), (4, 64, 256)])
+def test_solution_matches_exact(example, N, mp1, precision):
+    """Random right-hand sides, tol 1e-10 (FP64) / 1e-8 (mixed), against the
+    oracle's forward substitution with the sparse first block."""
+    print(f"[varcoef exact] example {example} N={N} m+1={mp1} precision={precision}", flush=True)
+    if example == 2:
+        sysm, _, _, _ = PE.example2_system_and_rhs(N, mp1, 0.01)
+    else:
+        sysm, _, _, _, _ = PE.example4_system_and_rhs(0.5, N, mp1, 0.01)
+    f = np.random.default_rng(N + mp1).standard_normal(sysm.N * sysm.M)
+    tol = 1e-10 if precision == bltt.FP64 else 1e-8
+    u, it, info, rc = solve(sysm, f, tol, 200, precision)
+    assert rc == bltt.OK and info["true_relres"] <= tol
+    ustar = O.exact_solve(sysm, f).ravel()
+    # error <= condition-dependent multiple of the residual
+    assert rel(u, ustar) < (1e-7 if precision == bltt.FP64 else 1e-5)
+
+
+def test_step_operator_matches_oracle():
+    sysm, _, _, _, _ = PE.example4_system_and_rhs(0.7, 32, 16, 0.05)
+    s = solver(sysm)
+    try:
+        x = np.random.default_rng(3).standard_normal(sysm.N * sysm.M)
+        y = s.apply_sym(torch.from_numpy(x).cuda()).cpu().numpy()
+    finally:
+        s.close()
+    assert rel(y, O.sym_apply(sysm, x).ravel()) < 1e-12
