@@ -869,9 +869,10 @@ BLTT_HD void odd_mirror(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g) {
 // its first barrier); vout never aliases in, v1 or v2.
 enum { KIND_VUPD = 0, KIND_DOT = 1 };
 
-// VUPD variants: FULL = the Lanczos vectors and the stencil term are present
-// (v2 may equal v1 with cvp = 0); Q1 = q has a single tap.
-template <typename T, int L, int KIND, bool FULL, bool Q1, class Ctx>
+// VUPD variants: FULL = the Lanczos vectors are present (v2 may equal v1 with
+// cvp = 0); STEN = the stencil term is added (the constant-coefficient split
+// matvec); Q1 = q has a single tap.
+template <typename T, int L, int KIND, bool FULL, bool Q1, bool STEN = FULL, class Ctx>
 BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
                         const T* __restrict__ v1, const T* __restrict__ v2, T* __restrict__ vout,
                         const T* __restrict__ vdot, T* out, int64_t nlines,
@@ -894,7 +895,7 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
     cvp = T(coef[2]);
   }
   LineStencil<T> lsa, lsb;
-  if (KIND == KIND_VUPD && FULL) {
+  if (KIND == KIND_VUPD && STEN) {
     lsa = line_stencil(sten, lac);
     lsb = line_stencil(sten, lbc);
   }
@@ -907,7 +908,7 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
     const T wp = p > 0 ? T(1) : T(0);
     const int64_t ea = lac * m + x, eb = lbc * m + x;
     T a = in[ea], b = in[eb];
-    if (KIND == KIND_VUPD && FULL) {
+    if (KIND == KIND_VUPD && STEN) {
       a += line_stencil_at<T, Q1>(sten, lsa, x);
       b += line_stencil_at<T, Q1>(sten, lsb, x);
     }

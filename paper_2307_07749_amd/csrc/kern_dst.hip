@@ -5,7 +5,7 @@
 
 namespace bltt {
 
-template <typename T, int L, int KIND, bool FULL, bool Q1>
+template <typename T, int L, int KIND, bool FULL, bool Q1, bool STEN = FULL>
 __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_DSTX>()), waves_fft<T>()) void k_dst_x(const T* in, const T* __restrict__ v1,
                                                         const T* __restrict__ v2, T* __restrict__ vout,
                                                         const T* __restrict__ vdot, T* out,
@@ -17,7 +17,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
   using F = LineFft<T, L, NL, false, LAST_LINEAR>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
-  dst_x_body<T, L, KIND, FULL, Q1>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, v1, v2, vout, vdot, out, nlines, tb, coef,
+  dst_x_body<T, L, KIND, FULL, Q1, STEN>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, v1, v2, vout, vdot, out, nlines, tb, coef,
                          partials, sten);
 }
 
@@ -96,9 +96,15 @@ static hipError_t go_dx(int kind, const T* in, const T* v1, const T* v2, T* vout
                        nlines, tb, coef, partials, sten);
     return hipGetLastError();
   }
-  // the full Lanczos update needs v1, vout and z; v2 may be absent (then coef[2] = 0)
-  if (!v1 || !vout || !sten.z) return hipErrorInvalidValue;
+  // the full Lanczos update needs v1 and vout; v2 may be absent (then coef[2] = 0);
+  // without z there is no stencil term (the matvec carried the whole operator)
+  if (!v1 || !vout) return hipErrorInvalidValue;
   if (!v2) v2 = v1;
+  if (!sten.z) {
+    hipLaunchKernelGGL((k_dst_x<T, L, KIND_VUPD, true, false, false>), grid, block, lds, s, in, v1, v2, vout, vdot,
+                       out, nlines, tb, coef, partials, sten);
+    return hipGetLastError();
+  }
   if (sten.qtaps <= 1)
     hipLaunchKernelGGL((k_dst_x<T, L, KIND_VUPD, true, true>), grid, block, lds, s, in, v1, v2, vout, vdot, out,
                        nlines, tb, coef, partials, sten);
@@ -155,9 +161,10 @@ template <typename T, int L>
 static hipError_t attr_dst() {
   const int bx = (int)fft_lds_bytes<T, FK_DSTX>(L), bs = (int)fft_lds_bytes<T, FK_DSTS>(L);
   hipError_t e;
-  const void* ks[4] = {reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD, false, false>),
+  const void* ks[5] = {reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD, false, false>),
                        reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD, true, true>),
                        reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD, true, false>),
+                       reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_VUPD, true, false, false>),
                        reinterpret_cast<const void*>(&k_dst_x<T, L, KIND_DOT, false, false>)};
   for (const void* k : ks)
     if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bx)) != hipSuccess) return e;
