@@ -726,13 +726,14 @@ bool overlaps(const void* a, const void* b, int64_t bytes) {
 int check_power(int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
 // Stopping tolerance of one FP32 sweep on |eta|/eta_0: the inner tolerance,
-// loosened to what the outer tolerance still asks for (tol / relres, relres the
-// current relative residual), so the last sweep does not solve past the
-// target.  |eta| estimates the P^{-1}-norm residual; the measured 2-norm
-// residual after a sweep is typically a few times below that estimate, and the
-// explicit FP64 residual that follows decides convergence either way.
+// loosened to a tenth of what the outer tolerance still asks for
+// (0.1 tol / relres, relres the current relative residual), so the last sweep
+// does not solve far past the target while the solution error, which the
+// conditioning makes a multiple of the residual, keeps a decade of margin.
+// The explicit FP64 residual that follows decides convergence either way.
+constexpr double SWEEP_MARGIN = 0.1;
 double sweep_tol(const bltt_handle* h, double tol, double relres) {
-  return relres > 0.0 ? std::max(h->opt.inner_tol, tol / relres) : h->opt.inner_tol;
+  return relres > 0.0 ? std::max(h->opt.inner_tol, SWEEP_MARGIN * tol / relres) : h->opt.inner_tol;
 }
 
 // strided sine transforms along dimensions 1..dim-1 on a mode-major vector

@@ -598,8 +598,8 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
         for (int s = 0; s < c.S; ++s) {
           const SysRun& r = R[(size_t)s];
           c.act_host[s] = r.active ? 1 : 0;
-          // the sweep needs no more than the outer tolerance still asks for
-          c.etol_host[s] = r.relres > 0.0 ? std::max(inner_tol, tol / r.relres) : inner_tol;
+          // the sweep needs no more than a tenth of what the outer tolerance still asks for
+          c.etol_host[s] = r.relres > 0.0 ? std::max(inner_tol, 0.1 * tol / r.relres) : inner_tol;
           live = live || r.active;
         }
         if (!live) {
