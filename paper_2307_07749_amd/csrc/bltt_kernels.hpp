@@ -48,7 +48,7 @@ constexpr int lines_per_block(int L) {
 // dynamic LDS: NL padded lines + one double per thread for reductions
 template <typename T, int FK>
 constexpr size_t fft_lds_bytes(int L) {
-  return (size_t)lines_per_block<T, FK>(L) * (size_t)(L + (L >> 3)) * sizeof(cx<T>) +
+  return (size_t)lines_per_block<T, FK>(L) * (size_t)fft_padded(L) * sizeof(cx<T>) +
          (size_t)tpb_fft<T, FK>() * sizeof(double);
 }
 // workgroups of a launch over `units` spatial points or lines, rounded up to a
@@ -1055,11 +1055,21 @@ BLTT_HD void dst_xt_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict_
       v[t] = mkc<T>(a, b);
     }
   } else {
-    // runs of W2 consecutive times per x, into LDS line-major
-    for (int e = tid; e < W2 * m; e += TPB) {
+    // runs of W2 consecutive times per x, into LDS line-major; all loads are
+    // issued before the first LDS store
+    constexpr int IT = (W2 * m + TPB - 1) / TPB;
+    T val[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + it * TPB;
       const int x = e / W2, j = e % W2;
       const int64_t n = n0 + j;
-      stage[j * m + x] = n < N ? in[(r * m + x) * N + n] : T(0);
+      val[it] = (e < W2 * m && n < N) ? in[(r * m + x) * N + n] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + it * TPB;
+      if (e < W2 * m) stage[(e % W2) * m + e / W2] = val[it];
     }
     ctx.sync();
 #pragma unroll
@@ -1090,10 +1100,13 @@ BLTT_HD void dst_xt_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict_
     }
     ctx.sync();
     if (live) {
-      for (int e = tid; e < W2 * m; e += TPB) {
+      constexpr int IT = (W2 * m + TPB - 1) / TPB;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = tid + it * TPB;
         const int k = e / W2, j = e % W2;
         const int64_t n = n0 + j;
-        if (n < N) out[(r * m + k) * N + n] = stage[j * m + k];
+        if (e < W2 * m && n < N) out[(r * m + k) * N + n] = stage[j * m + k];
       }
     }
     if (partials) {

@@ -177,6 +177,13 @@ BLTT_HD void twiddle_powers(cx<T>* pw, const cx<T>* tw, int e) {
   twiddle_products<R, 3>(pw);
 }
 
+// LDS padding of a line: one slot per 8 elements and one more per 128.  The
+// exchanges read and write runs of consecutive positions, runs 8 apart, and
+// (paired and linear last stages) positions 64 apart; one pad per 8 alone
+// maps the latter to two banks per 16 lanes, the second pad spreads them.
+BLTT_HD constexpr int fft_pad(int pos) { return pos + (pos >> 3) + (pos >> 7); }
+BLTT_HD constexpr int fft_padded(int L) { return L + (L >> 3) + (L >> 7); }
+
 // How the last stage's butterflies are dealt to the threads of a line.
 enum LastMode {
   LAST_DEFAULT = 0,  // butterfly g + G*w (LDS friendly)
@@ -195,7 +202,7 @@ struct LineFft {
   static constexpr int G = L / V;             // threads per line
   static constexpr int RL = fft_r(L, S - 1);  // last radix
   static constexpr int K = L / RL;            // last-stage butterflies per line
-  static constexpr int LP = L + (L >> 3);     // padded line length
+  static constexpr int LP = fft_padded(L);    // padded line length
   static constexpr int LDS_ELEMS = NL * LP;
   // Lines stored one after another (not interleaved) and at most one
   // wavefront per line: every exchange stays inside one wavefront, whose LDS
@@ -244,7 +251,7 @@ struct LineFft {
   static_assert(LAST != LAST_PAIRED || S == 1 || V >= 2 * RL, "pairing needs two butterflies");
 
   BLTT_HD static int idx(int c, int pos) {
-    const int pp = pos + (pos >> 3);
+    const int pp = fft_pad(pos);
     return INTERLEAVED ? pp * NL + c : c * LP + pp;
   }
 

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(TPB_EW) void k_bt_transpose(const double* const* __
 // ---------------------------------------------------------------------------
 template <int L, int TPB>
 constexpr size_t bt_lds() {
-  return (size_t)(TPB / (L / fft_V(L))) * (size_t)(L + (L >> 3)) * sizeof(cx<float>) + (size_t)TPB * sizeof(double);
+  return (size_t)(TPB / (L / fft_V(L))) * (size_t)fft_padded(L) * sizeof(cx<float>) + (size_t)TPB * sizeof(double);
 }
 
 template <int L, int TPB>

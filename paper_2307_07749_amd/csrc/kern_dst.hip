@@ -31,7 +31,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
 
 template <typename T, int L>
 constexpr size_t dstxt_lds_bytes() {
-  return (size_t)(DSTXT_TPB / (L / fft_V(L))) * (size_t)(L + (L >> 3)) * sizeof(cx<T>) + DSTXT_TPB * sizeof(double);
+  return (size_t)(DSTXT_TPB / (L / fft_V(L))) * (size_t)fft_padded(L) * sizeof(cx<T>) + DSTXT_TPB * sizeof(double);
 }
 
 template <typename T, int L, int DIR>
