@@ -475,8 +475,18 @@ struct MatvecCSTables {
   int qtaps;
 };
 
+// Index of the spectrum entry register slot (w, u) of lane g multiplies: the
+// frequency itself, or, for tables staged in LDS (STAGED), the slot's position
+// in register order, (w RL + u) G + g, so consecutive lanes read consecutive
+// entries (by frequency they would hit a few banks).
+template <class F, bool STAGED>
+BLTT_HD int spec_index(int g, int w, int u) {
+  return STAGED ? (w * F::RL + u) * F::G + g : F::freq(g, w, u);
+}
+
 // TPB: workgroup size (2*TPB/G modes per tile); the batched kernels choose it per shape.
-// TWL: tb.tw is the LDS stage-twiddle table (cs_stage_tables).
+// TWL: the tables are the LDS copies of cs_stage_tables (stage twiddles, spectra
+// in register order).
 template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), bool TWL = false, class Ctx>
 BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
                               const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up) {
@@ -544,7 +554,7 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
 #pragma unroll
   for (int w = 0; w < V / F::RL; ++w)
 #pragma unroll
-    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.chat[F::freq(g, w, u)];
+    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.chat[spec_index<F, TWL>(g, w, u)];
   F::inverse(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
   for (int t = 0; t < V; ++t) {
@@ -556,7 +566,7 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
 #pragma unroll
   for (int w = 0; w < V / F::RL; ++w)
 #pragma unroll
-    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.shat[F::freq(g, w, u)];
+    for (int u = 0; u < F::RL; ++u) v[w * F::RL + u] = v[w * F::RL + u] * tb.shat[spec_index<F, TWL>(g, w, u)];
   F::inverse(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
   for (int t = 0; t < V; ++t) acc[t] = acc[t] + v[t] * conjg(tb.omega[g + t * s0]);
@@ -628,8 +638,11 @@ BLTT_HD MatvecCSTables<T> cs_stage_tables(Ctx& ctx, cx<T>* tabs, const MatvecCST
   using F = LineFft<T, L, TPB / (L / fft_V(L)), false, LAST_DEFAULT, true>;
   F::build_twl(ctx, tabs, tb.tw, TPB);
   for (int i = ctx.tid; i < L; i += TPB) {
-    tabs[L + i] = tb.chat[i];
-    tabs[2 * L + i] = tb.shat[i];
+    // spectra in register order: entry (w RL + u) G + g holds frequency freq(g, w, u)
+    const int g = i % F::G, j = i / F::G;
+    const int k = F::freq(g, j / F::RL, j % F::RL);
+    tabs[L + i] = tb.chat[k];
+    tabs[2 * L + i] = tb.shat[k];
     tabs[3 * L + i] = tb.omega[i];
   }
   ctx.sync();
