@@ -145,6 +145,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--basis", choices=["sine", "physical"], default="sine",
                     help="Krylov basis: sine coordinates (transform once) or physical space")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a plain streaming kernel of known size (2^28 floats negated into a second "
+                         "buffer: 1 GiB read, 1 GiB written), whose FETCH_SIZE / WRITE_SIZE counters scale "
+                         "the solver kernels' counters to bytes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -160,6 +164,13 @@ def main() -> int:
     from paper_2307_07749_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     prob, seed = W.workload(args.workload)
     f = torch.from_numpy(W.rhs_normal(prob, seed)).cuda()
     torch.cuda.synchronize()
