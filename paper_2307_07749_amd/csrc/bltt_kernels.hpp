@@ -329,20 +329,33 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
       da[t] = (double)ra[t];
       db[t] = (double)rb[t];
     }
-    for (int i = 0; i < uk; ++i) {
-      const double yi = us * uy[i];
-      const float* zi = up.z[i] + zoff;
-      float xa[VH], xb[VH];
+    // ZG vectors per group: their loads are issued together, so a sweep of k
+    // vectors costs about k/ZG memory round trips instead of k
+    constexpr int ZG = 4;
+    for (int i0 = 0; i0 < uk; i0 += ZG) {
+      float xa[ZG][VH], xb[ZG][VH];
 #pragma unroll
-      for (int t = 0; t < VH; ++t) {
-        const int64_t off = (int64_t)(g + t * s0) * ts;
-        xa[t] = zi[la + off];
-        xb[t] = zi[lb + off];
+      for (int j = 0; j < ZG; ++j) {
+        if (i0 + j < uk) {
+          const float* zi = up.z[i0 + j] + zoff;
+#pragma unroll
+          for (int t = 0; t < VH; ++t) {
+            const int64_t off = (int64_t)(g + t * s0) * ts;
+            xa[j][t] = zi[la + off];
+            xb[j][t] = zi[lb + off];
+          }
+        }
       }
 #pragma unroll
-      for (int t = 0; t < VH; ++t) {
-        da[t] += yi * (double)xa[t];
-        db[t] += yi * (double)xb[t];
+      for (int j = 0; j < ZG; ++j) {
+        if (i0 + j < uk) {
+          const double yi = us * uy[i0 + j];
+#pragma unroll
+          for (int t = 0; t < VH; ++t) {
+            da[t] += yi * (double)xa[j][t];
+            db[t] += yi * (double)xb[j][t];
+          }
+        }
       }
     }
 #pragma unroll
@@ -373,6 +386,19 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
 #pragma unroll
   for (int t = 0; t < VH; ++t) lds[F::idx(c, g + t * s0)] = zin[t];
   F::xsync(ctx);
+  // the right-hand side: all loads in flight together (clamped line bases, so
+  // unconditional), after the barrier so that they are not hoisted into the
+  // transforms; inside the guarded epilogue each would wait for the stores
+  // before it
+  T fa[MODE == MV_RESID ? VH : 1], fb[MODE == MV_RESID ? VH : 1];
+  if constexpr (MODE == MV_RESID) {
+#pragma unroll
+    for (int t = 0; t < VH; ++t) {
+      const int64_t off = (int64_t)(g + t * s0) * ts;
+      fa[t] = fin[la + off];
+      fb[t] = fin[lb + off];
+    }
+  }
 
   Stencil sta{}, stb{};
   if constexpr (TERM == TERM_STENCIL) {
@@ -428,12 +454,12 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
     } else {
       const int64_t off = (int64_t)n * ts;
       if (va) {
-        const T r = fin[sa + off] - ya;
+        const T r = fa[MODE == MV_RESID ? t : 0] - ya;
         oa[offr] = r;
         part += (double)r * (double)r;
       }
       if (vb) {
-        const T r = fin[sb + off] - yb;
+        const T r = fb[MODE == MV_RESID ? t : 0] - yb;
         ob[offr] = r;
         part += (double)r * (double)r;
       }
@@ -484,12 +510,66 @@ BLTT_HD int spec_index(int g, int w, int u) {
   return STAGED ? (w * F::RL + u) * F::G + g : F::freq(g, w, u);
 }
 
+// The N-point matvec's tables staged in LDS per workgroup, in two steps so
+// that the tile can put its own line loads between them: load() issues every
+// global load (clamped indices, so unconditional) into registers; store()
+// writes them to LDS (stage twiddles as build_twl lays them out, spectra in
+// register order: entry (w RL + u) G + g holds frequency freq(g, w, u)), with
+// no barrier (the tile takes one).
+template <typename T, int L, int TPB>
+struct CsStage {
+  using F = LineFft<T, L, TPB / (L / fft_V(L)), false, LAST_DEFAULT, true>;
+  static constexpr int PER = (L + TPB - 1) / TPB;
+  cx<T> tv[F::template twl_per<TPB>()];
+  cx<T> ch[PER], sh[PER], om[PER];
+  cx<T>* tabs;
+
+  template <class Ctx>
+  BLTT_HD void load(Ctx& ctx, const MatvecCSTables<T>& tb) {
+    F::template twl_load<TPB>(ctx, tb.tw, tv);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int i = ctx.tid + r * TPB, ii = i < L ? i : L - 1;
+      const int g = ii % F::G, j = ii / F::G;
+      const int k = F::freq(g, j / F::RL, j % F::RL);
+      ch[r] = tb.chat[k];
+      sh[r] = tb.shat[k];
+      om[r] = tb.omega[ii];
+    }
+  }
+  template <class Ctx>
+  BLTT_HD void store(Ctx& ctx) {
+    F::template twl_store<TPB>(ctx, tabs, tv);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int i = ctx.tid + r * TPB;
+      if (i < L) {
+        tabs[L + i] = ch[r];
+        tabs[2 * L + i] = sh[r];
+        tabs[3 * L + i] = om[r];
+      }
+    }
+  }
+  // the tables as the tile reads them
+  BLTT_HD MatvecCSTables<T> tables(const MatvecCSTables<T>& tb) const {
+    MatvecCSTables<T> t = tb;
+    t.tw = tabs;
+    t.chat = tabs + L;
+    t.shat = tabs + 2 * L;
+    t.omega = tabs + 3 * L;
+    return t;
+  }
+};
+
 // TPB: workgroup size (2*TPB/G modes per tile); the batched kernels choose it per shape.
-// TWL: the tables are the LDS copies of cs_stage_tables (stage twiddles, spectra
-// in register order).
-template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), bool TWL = false, class Ctx>
+// TWL: the tables are the LDS copies of CsStage (stage twiddles, spectra in
+// register order), whose registers `stage` holds: the tile stores them and
+// synchronises once its line loads are issued.
+template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), bool TWL = false, class Ctx,
+          class Stage = CsStage<T, L, TPB>>
 BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
-                              const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up) {
+                              const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
+                              Stage* stage = nullptr) {
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L;
   using F = LineFft<T, L, NL, false, LAST_DEFAULT, TWL>;
@@ -500,6 +580,7 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   const int64_t la = iac * N, lb = ibc * N, sa = ia * N, sb = ib * N;
   const bool upd = MODE == MV_RESID && up.k > 0;
   const double us = upd ? *up.s : 0.0;
+  T mua = tb.mu[iac], mub = tb.mu[ibc];
   cx<T> zin[V], v[V], acc[V];
   T ra[V], rb[V];
 #pragma unroll
@@ -511,6 +592,12 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
       ra[t] = z[la + n];
       rb[t] = z[lb + n];
     }
+  }
+  // the staged tables (CsStage) are stored and become visible here, with the
+  // line's loads already in flight
+  if constexpr (TWL) {
+    stage->store(ctx);
+    ctx.sync();
   }
   if (upd) {
     // stored-vector loop outside the time loop: one vector's loads in flight together
@@ -549,6 +636,13 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
     zin[t] = mkc<T>(va ? ra[t] : T(0), vb ? rb[t] : T(0));
     v[t] = zin[t];
   }
+#if defined(__HIP_DEVICE_COMPILE__)
+  // mu in registers with the line, before the transforms: loaded late, its
+  // first use would sit inside each guarded store of the epilogue and make
+  // every store wait for the one before it (the load counter is merged
+  // pessimistically where the guards join)
+  asm volatile("" : "+v"(mua), "+v"(mub));
+#endif
   // circulant part
   F::forward(ctx, v, lds, c, g, tb.tw);
 #pragma unroll
@@ -576,7 +670,6 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
 #pragma unroll
   for (int t = 0; t < V; ++t) lds[F::idx(c, g + t * s0)] = zin[t];
   F::xsync(ctx);
-  const T mua = tb.mu[iac], mub = tb.mu[ibc];
   double part = 0.0;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
@@ -633,27 +726,6 @@ constexpr bool cs_stage() { return cs_lds_base<T, L>() + 4 * (size_t)L * sizeof(
 template <typename T, int L>
 constexpr size_t cs_lds_bytes() { return cs_lds_base<T, L>() + (cs_stage<T, L>() ? 4 * (size_t)L * sizeof(cx<T>) : 0); }
 
-template <typename T, int L, int TPB, class Ctx>
-BLTT_HD MatvecCSTables<T> cs_stage_tables(Ctx& ctx, cx<T>* tabs, const MatvecCSTables<T>& tb) {
-  using F = LineFft<T, L, TPB / (L / fft_V(L)), false, LAST_DEFAULT, true>;
-  F::build_twl(ctx, tabs, tb.tw, TPB);
-  for (int i = ctx.tid; i < L; i += TPB) {
-    // spectra in register order: entry (w RL + u) G + g holds frequency freq(g, w, u)
-    const int g = i % F::G, j = i / F::G;
-    const int k = F::freq(g, j / F::RL, j % F::RL);
-    tabs[L + i] = tb.chat[k];
-    tabs[2 * L + i] = tb.shat[k];
-    tabs[3 * L + i] = tb.omega[i];
-  }
-  ctx.sync();
-  MatvecCSTables<T> t = tb;
-  t.tw = tabs;
-  t.chat = tabs + L;
-  t.shat = tabs + 2 * L;
-  t.omega = tabs + 3 * L;
-  return t;
-}
-
 // One tile per workgroup (a loop over tiles lets the compiler keep the
 // loop-invariant twiddle and spectrum loads live across tiles, which costs
 // half the occupancy here); one partial sum per workgroup.  `tabs`: LDS for
@@ -665,8 +737,10 @@ BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, cx<T>* tabs, T* z
   constexpr int TPB = tpb_fft<T, FK_SPEC>();
   double part;
   if constexpr (cs_stage<T, L>()) {
-    const MatvecCSTables<T> ts = cs_stage_tables<T, L, TPB>(ctx, tabs, tb);
-    part = matvec_cs_tile<T, L, MODE, TPB, true>(ctx, lds, ctx.bid, z, out, fin, M, ts, up);
+    CsStage<T, L, TPB> st;
+    st.tabs = tabs;
+    st.load(ctx, tb);
+    part = matvec_cs_tile<T, L, MODE, TPB, true>(ctx, lds, ctx.bid, z, out, fin, M, st.tables(tb), up, &st);
   } else {
     part = matvec_cs_tile<T, L, MODE, TPB, false>(ctx, lds, ctx.bid, z, out, fin, M, tb, up);
   }
@@ -1572,7 +1646,7 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
     // the stage twiddles in LDS, after the exchange lines and the reduction slots
     using F = LineFft<T, L, TPB / (L / fft_V(L)), !MM, LAST_PAIRED, true>;
     cx<T>* twl = reinterpret_cast<cx<T>*>(red + TPB);
-    F::build_twl(ctx, twl, tb.tw, TPB);
+    F::template build_twl<TPB>(ctx, twl, tb.tw);
     ctx.sync();
     tl.tw = twl;
   }

@@ -224,16 +224,38 @@ struct LineFft {
   static constexpr int TWL_LEN = twl_off(S - 1) > 0 ? twl_off(S - 1) : 1;
   // fill the LDS table from the global one (all threads of the workgroup; the
   // caller synchronises before first use)
-  template <class Ctx>
-  BLTT_HD static void build_twl(Ctx& ctx, cx<T>* twl, const cx<T>* tw, int nthreads) {
+  template <int NT>
+  static constexpr int twl_per() { return (TWL_LEN + NT - 1) / NT; }
+  // split in a load phase and a store phase so that callers can put other
+  // global loads between them (one memory round trip per workgroup)
+  template <int NT, class Ctx>
+  BLTT_HD static void twl_load(Ctx& ctx, const cx<T>* tw, cx<T>* val) {
 #pragma unroll
-    for (int s = 0; s < S - 1; ++s) {
-      const int r = fft_r(L, s), sg = fft_sigma(L, s), LB = L / (r * sg), o = twl_off(s);
-      for (int i = ctx.tid; i < (r - 1) * sg; i += nthreads) {
-        const int u = i / sg + 1, j = i % sg;
-        twl[o + i] = tw[u * j * LB];
-      }
+    for (int k = 0; k < twl_per<NT>(); ++k) {
+      const int i = ctx.tid + k * NT;
+      val[k] = tw[twl_src(i < TWL_LEN ? i : TWL_LEN - 1)];
     }
+  }
+  template <int NT, class Ctx>
+  BLTT_HD static void twl_store(Ctx& ctx, cx<T>* twl, const cx<T>* val) {
+#pragma unroll
+    for (int k = 0; k < twl_per<NT>(); ++k) {
+      const int i = ctx.tid + k * NT;
+      if (i < TWL_LEN) twl[i] = val[k];
+    }
+  }
+  template <int NT, class Ctx>
+  BLTT_HD static void build_twl(Ctx& ctx, cx<T>* twl, const cx<T>* tw) {
+    cx<T> val[twl_per<NT>()];
+    twl_load<NT>(ctx, tw, val);
+    twl_store<NT>(ctx, twl, val);
+  }
+  // global-table index of LDS table entry i (stage s, entry off_s + (u-1) sg_s + j)
+  BLTT_HD static constexpr int twl_src(int i) {
+    int s = 0;
+    while (s < S - 2 && i >= twl_off(s + 1)) ++s;
+    const int sg = fft_sigma(L, s), LB = L / (fft_r(L, s) * sg), e = i - twl_off(s);
+    return (e / sg + 1) * (e % sg) * LB;
   }
   template <int s, int r>
   BLTT_HD static void stage_twiddles(cx<T>* pw, const cx<T>* tw, int b) {

@@ -266,18 +266,20 @@ def test_stored_basis_cap():
     assert np.linalg.norm(x - ores.x.ravel()) <= 1e-4 * np.linalg.norm(ores.x)
 
 
+@pytest.mark.parametrize("nz", [3, 6])
 @pytest.mark.parametrize("two_n", [False, True])
 @pytest.mark.parametrize("u_zero", [False, True])
 @pytest.mark.parametrize("kind,dim,m,N", [("frac", 1, 31, 32), ("cn", 2, 5, 8), ("frac", 2, 7, 64)])
-def test_resid_with_update(kind, dim, m, N, u_zero, two_n):
+def test_resid_with_update(kind, dim, m, N, u_zero, two_n, nz):
     """The mixed path's fused refinement step: u <- u + s sum_i y_i Z_i, then
-    r = Y(f - A u), against the same two steps in FP64 on the host."""
+    r = Y(f - A u), against the same two steps in FP64 on the host (nz = 6:
+    a full group of stored-vector loads and a partial one)."""
     prob = prob_of(kind, dim, m, N)
     sysm = O.from_problem(prob)
     rng = np.random.default_rng(51)
     u, f = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
-    Zs = [rng.standard_normal(prob.n).astype(np.float32) for _ in range(3)]
-    y, s = np.array([0.5, -1.25, 2.0]), 0.37
+    Zs = [rng.standard_normal(prob.n).astype(np.float32) for _ in range(nz)]
+    y, s = np.array([0.5, -1.25, 2.0, 0.75, -0.3, 1.1][:nz]), 0.37
     unew, r, ss = E.resid_upd(prob, u, f, Zs, y, s, u_zero, two_n)
     uref = (0.0 if u_zero else u) + s * sum(yi * z.astype(np.float64) for yi, z in zip(y, Zs))
     assert np.allclose(unew, uref, rtol=1e-14, atol=1e-14)
