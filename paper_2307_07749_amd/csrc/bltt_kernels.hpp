@@ -1125,6 +1125,11 @@ BLTT_HD void dst_xt_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict_
   const int64_t na = n0 + 2 * c, nb = na + 1;
   const bool va = na < N, vb = nb < N;
   T* stage = reinterpret_cast<T*>(lds);  // W2 x m values, line-major
+  // DIR 1: every stage's twiddles in flight with the line's loads (faster
+  // for DIR 1 as measured, slower for DIR 0)
+  constexpr bool PF = DIR == 1;
+  cx<T> pre[PF && F::PF_LEN > 0 ? F::PF_LEN : 1];
+  if constexpr (PF) F::template pf_load<0>(pre, tb.tw, g);
   cx<T> v[V];
   double part = 0.0;
   if (DIR == 0) {
@@ -1170,7 +1175,10 @@ BLTT_HD void dst_xt_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict_
     ctx.sync();
   }
   odd_mirror<F, T, L>(ctx, v, lds, c, g);
-  F::forward(ctx, v, lds, c, g, tb.tw);
+  if constexpr (PF)
+    F::forward_pf(ctx, v, lds, c, g, pre);
+  else
+    F::forward(ctx, v, lds, c, g, tb.tw);
   if (DIR == 0) {
     ctx.sync();
 #pragma unroll

@@ -332,11 +332,51 @@ struct LineFft {
   // ---- forward: v[w*r0+t] = x[pos<0>(beta<0>(g,w),t)]  ->  v[w*RL+u] = X[freq(g,w,u)]
   template <class Ctx>
   BLTT_HD static void forward(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
-    fwd_stage<0>(ctx, v, lds, c, g, tw);
+    fwd_stage<0, false>(ctx, v, lds, c, g, tw, nullptr);
   }
 
-  template <int s, class Ctx>
-  BLTT_HD static void fwd_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
+  // Twiddle bases (table entries w^(u e), u = 1, 2, 4, ...) of every stage
+  // loaded up front from the global table, so that no stage waits for its own
+  // loads after an exchange barrier; costs the registers that hold them.
+  template <int s>
+  static constexpr int pf_per() {
+    int n = 0;
+    if (fft_sigma(L, s) > 1)
+      for (int u = 1; u < fft_r(L, s); u <<= 1) ++n;
+    return n;
+  }
+  template <int s>
+  static constexpr int pf_off() {
+    int o = 0;
+    if constexpr (s > 0) o = pf_off<s - 1>() + (V / fft_r(L, s - 1)) * pf_per<s - 1>();
+    return o;
+  }
+  static constexpr int PF_LEN = pf_off<S - 1>() + (V / fft_r(L, S - 1)) * pf_per<S - 1>();
+  template <int s>
+  BLTT_HD static void pf_load(cx<T>* pre, const cx<T>* tw, int g) {
+    if constexpr (s < S) {
+      constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), NB = V / r, P = pf_per<s>();
+      if constexpr (P > 0) {
+#pragma unroll
+        for (int w = 0; w < NB; ++w) {
+          const int e = (beta<s>(g, w) % sg) * (L / (r * sg));
+#pragma unroll
+          for (int i = 0; i < P; ++i) pre[pf_off<s>() + w * P + i] = tw[(1 << i) * e];
+        }
+      }
+      pf_load<s + 1>(pre, tw, g);
+    }
+  }
+  // pre: PF_LEN entries filled by pf_load<0>, best issued before the caller's
+  // own loads and exchanges
+  template <class Ctx>
+  BLTT_HD static void forward_pf(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* pre) {
+    static_assert(!TWL, "the LDS twiddle table needs no prefetch");
+    fwd_stage<0, true>(ctx, v, lds, c, g, nullptr, pre);
+  }
+
+  template <int s, bool PF, class Ctx>
+  BLTT_HD static void fwd_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw, const cx<T>* pre) {
     constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), NB = V / r;
     if constexpr (s > 0) {
 #pragma unroll
@@ -351,7 +391,13 @@ struct LineFft {
       dft<r, -1>(v + w * r);
       if constexpr (sg > 1) {
         cx<T> pw[r];
-        stage_twiddles<s, r>(pw, tw, beta<s>(g, w));
+        if constexpr (PF) {
+#pragma unroll
+          for (int i = 0; i < pf_per<s>(); ++i) pw[1 << i] = pre[pf_off<s>() + w * pf_per<s>() + i];
+          twiddle_products<r, 3>(pw);
+        } else {
+          stage_twiddles<s, r>(pw, tw, beta<s>(g, w));
+        }
 #pragma unroll
         for (int u = 1; u < r; ++u) v[w * r + u] = v[w * r + u] * pw[u];
       }
@@ -365,7 +411,7 @@ struct LineFft {
         for (int u = 0; u < r; ++u) lds[idx(c, pos<s>(b, u))] = v[w * r + u];
       }
       xsync(ctx);
-      fwd_stage<s + 1>(ctx, v, lds, c, g, tw);
+      fwd_stage<s + 1, PF>(ctx, v, lds, c, g, tw, pre);
     }
   }
 
