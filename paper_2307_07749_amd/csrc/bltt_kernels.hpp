@@ -1567,7 +1567,14 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
   // element (i, n): time-major n*M + i, or mode-major i*N + n (N = L)
   const int64_t ts = MM ? 1 : M;
   const int64_t la = MM ? iac * L : iac, lb = MM ? ibc * L : ibc;
-  const int64_t sa = MM ? ia * L : ia, sb = MM ? ib * L : ib;
+  // per-lane pointers at time g (Q reversed: L-1-g); the time offset t*s0*ts
+  // is then a compile-time constant in the mode-major layout (the memory
+  // instructions' immediates).  Stores go through the clamped line bases,
+  // equal to the exact ones wherever the store's guard holds.
+  const bool rq = !FULL && qrev;
+  const int64_t gq = (int64_t)(rq ? L - 1 - g : g) * ts, gv = (int64_t)g * ts;
+  const TQ* qa = Q + la + gq;
+  const TQ* qb = Q + lb + gq;
   const T mua = tb.mu[iac], mub = tb.mu[ibc];
   const double cq = coef[0];
   T cv = T(0), cvp = T(0);
@@ -1579,29 +1586,31 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
   cx<T> v[V];
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int64_t off = (int64_t)(g + t * s0) * ts;
+    const int64_t off = (int64_t)(t * s0) * ts;
     // qrev (start only): Q read with its time lines reversed, i.e. Y Q
-    const int64_t offq = (!FULL && qrev) ? (int64_t)(L - 1 - (g + t * s0)) * ts : off;
+    const int64_t offq = rq ? -off : off;
     T a, b;
     if constexpr (sizeof(TQ) > sizeof(T)) {
-      a = T((double)Q[la + offq] * cq);
-      b = T((double)Q[lb + offq] * cq);
+      a = T((double)qa[offq] * cq);
+      b = T((double)qb[offq] * cq);
     } else {
-      a = T(cq) * Q[la + offq];
-      b = T(cq) * Q[lb + offq];
+      a = T(cq) * qa[offq];
+      b = T(cq) * qb[offq];
     }
     if (FULL) {
-      a += cv * V1[la + off] + cvp * V2[la + off];
-      b += cv * V1[lb + off] + cvp * V2[lb + off];
+      a += cv * V1[la + gv + off] + cvp * V2[la + gv + off];
+      b += cv * V1[lb + gv + off] + cvp * V2[lb + gv + off];
     }
     v[t] = mkc<T>(va ? a : T(0), vb ? b : T(0));
   }
   if (Vout) {
+    T* oa = Vout + la + gv;
+    T* ob = Vout + lb + gv;
 #pragma unroll
     for (int t = 0; t < V; ++t) {
-      const int64_t off = (int64_t)(g + t * s0) * ts;
-      if (va) Vout[sa + off] = v[t].re;
-      if (vb) Vout[sb + off] = v[t].im;
+      const int64_t off = (int64_t)(t * s0) * ts;
+      if (va) oa[off] = v[t].re;
+      if (vb) ob[off] = v[t].im;
     }
   }
   double part = 0.0;
@@ -1619,11 +1628,13 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
     F::inverse(ctx, v, lds, c, g, tb.tw);
     scale_alpha<T, V, s0>(v, tb, tb.dinv, T(-1), g);
   }
+  T* za = Zout + la + gv;
+  T* zb = Zout + lb + gv;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int64_t off = (int64_t)(g + t * s0) * ts;
-    if (va) Zout[sa + off] = v[t].re;
-    if (vb) Zout[sb + off] = v[t].im;
+    const int64_t off = (int64_t)(t * s0) * ts;
+    if (va) za[off] = v[t].re;
+    if (vb) zb[off] = v[t].im;
     if constexpr (!PREC) part += (double)v[t].re * (double)v[t].re + (double)v[t].im * (double)v[t].im;
   }
   return part;
