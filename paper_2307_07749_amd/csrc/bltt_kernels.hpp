@@ -577,7 +577,12 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
-  const int64_t la = iac * N, lb = ibc * N, sa = ia * N, sb = ib * N;
+  const int64_t la = iac * N, lb = ibc * N;
+  // per-lane pointers at time g (the reversed output at N-1-g): time offsets
+  // t*s0 are then compile-time constants (memory-instruction immediates);
+  // stores go through the clamped bases, equal to the exact ones wherever the
+  // store's guard holds
+  const int64_t gr = N - 1 - g;
   const bool upd = MODE == MV_RESID && up.k > 0;
   const double us = upd ? *up.s : 0.0;
   T mua = tb.mu[iac], mub = tb.mu[ibc];
@@ -585,12 +590,11 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   T ra[V], rb[V];
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    const int n = g + t * s0;
     ra[t] = T(0);
     rb[t] = T(0);
     if (!(MODE == MV_RESID && up.u_zero)) {
-      ra[t] = z[la + n];
-      rb[t] = z[lb + n];
+      ra[t] = (z + la + g)[t * s0];
+      rb[t] = (z + lb + g)[t * s0];
     }
   }
   // the staged tables (CsStage) are stored and become visible here, with the
@@ -613,8 +617,8 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
       float xa[V], xb[V];
 #pragma unroll
       for (int t = 0; t < V; ++t) {
-        xa[t] = zi[la + g + t * s0];
-        xb[t] = zi[lb + g + t * s0];
+        xa[t] = (zi + la + g)[t * s0];
+        xb[t] = (zi + lb + g)[t * s0];
       }
 #pragma unroll
       for (int t = 0; t < V; ++t) {
@@ -627,8 +631,8 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
       const int n = g + t * s0;
       ra[t] = T(da[t]);
       rb[t] = T(db[t]);
-      if (va) z[sa + n] = ra[t];
-      if (vb) z[sb + n] = rb[t];
+      if (va) (z + la + g)[t * s0] = ra[t];
+      if (vb) (z + lb + g)[t * s0] = rb[t];
     }
   }
 #pragma unroll
@@ -687,26 +691,27 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
       }
     }
     const T ya = acc[t].re + mua * sqa, yb = acc[t].im + mub * sqb;
-    const int64_t er = N - 1 - n;
+    T* ora = out + la + gr;
+    T* orb = out + lb + gr;
     if (MODE == MV_DOT) {
       const cx<T> zr = lds[F::idx(c, N - 1 - n)];
       if (va) {
-        out[sa + er] = ya;
+        ora[-(t * s0)] = ya;
         part += (double)ya * (double)zr.re;
       }
       if (vb) {
-        out[sb + er] = yb;
+        orb[-(t * s0)] = yb;
         part += (double)yb * (double)zr.im;
       }
     } else {
       if (va) {
-        const T r = fin[sa + n] - ya;
-        out[sa + er] = r;
+        const T r = (fin + la + g)[t * s0] - ya;
+        ora[-(t * s0)] = r;
         part += (double)r * (double)r;
       }
       if (vb) {
-        const T r = fin[sb + n] - yb;
-        out[sb + er] = r;
+        const T r = (fin + lb + g)[t * s0] - yb;
+        orb[-(t * s0)] = r;
         part += (double)r * (double)r;
       }
     }
