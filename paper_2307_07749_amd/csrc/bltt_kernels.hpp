@@ -1119,7 +1119,10 @@ BLTT_HD void dst_xt_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict_
                          int64_t N, int64_t M, const DstTables<T>& tb, double* __restrict__ partials) {
   constexpr int TPB = DSTXT_TPB;
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0), VH = V / 2, W2 = 2 * NL;
-  using F = LineFft<T, L, NL, false, DIR == 0 ? LAST_DEFAULT : LAST_LINEAR>;
+  // linear last stage both ways: lane g holds frequencies g + G w + u K, so
+  // DIR 1's global stores coalesce and DIR 0's stage writes hit consecutive
+  // banks (the default deal puts consecutive lanes 16 entries apart)
+  using F = LineFft<T, L, NL, false, LAST_LINEAR>;
   static_assert(G <= TPB, "one line per at most one workgroup");
   const int m = L / 2 - 1;
   const int64_t rows = M / m, nblk = (N + W2 - 1) / W2;
