@@ -2099,6 +2099,20 @@ BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q
 }
 
 // FP32 sine-coordinate matvec (N-point form): Q = Y T Z, partial sums of <Q, Z>
+// LDS of the batched time-line kernels: NL exchange lines and one double per
+// thread.  The batched N-point matvec stages its system's tables (CsStage)
+// after them when everything fits in 80 KB (two workgroups per CU).
+template <int L, int TPB>
+constexpr size_t bt_lds_base() {
+  return (size_t)(TPB / (L / fft_V(L))) * (size_t)fft_padded(L) * sizeof(cx<float>) + (size_t)TPB * sizeof(double);
+}
+template <int L, int TPB>
+constexpr bool bt_cs_stage() { return bt_lds_base<L, TPB>() + 4 * (size_t)L * sizeof(cx<float>) <= 80 * 1024; }
+template <int L, int TPB>
+constexpr size_t bt_cs_lds() {
+  return bt_lds_base<L, TPB>() + (bt_cs_stage<L, TPB>() ? 4 * (size_t)L * sizeof(cx<float>) : 0);
+}
+
 template <int L, int TPB, class Ctx>
 BLTT_HD void bt_cs_body(Ctx& ctx, unsigned char* smem, const float* __restrict__ Z, float* __restrict__ Q,
                         const BatchVec& bv, const BatchTabs& bt, double* __restrict__ partials) {
@@ -2122,9 +2136,18 @@ BLTT_HD void bt_cs_body(Ctx& ctx, unsigned char* smem, const float* __restrict__
   for (int k = 0; k < 4; ++k) tb.q[k] = ip.q32[k];
   tb.qtaps = ip.qtaps;
   const int64_t o = (int64_t)s * bv.n;
-  const double part = matvec_cs_tile<float, L, MV_DOT, TPB>(ctx, reinterpret_cast<cx<float>*>(smem), tile,
-                                                             const_cast<float*>(Z) + o, Q + o, nullptr, bv.M, tb,
-                                                             IterUpd{});
+  double part;
+  if constexpr (bt_cs_stage<L, TPB>()) {
+    CsStage<float, L, TPB> st;
+    st.tabs = reinterpret_cast<cx<float>*>(smem + bt_lds_base<L, TPB>());
+    st.load(ctx, tb);
+    part = matvec_cs_tile<float, L, MV_DOT, TPB, true>(ctx, reinterpret_cast<cx<float>*>(smem), tile,
+                                                       const_cast<float*>(Z) + o, Q + o, nullptr, bv.M,
+                                                       st.tables(tb), IterUpd{}, &st);
+  } else {
+    part = matvec_cs_tile<float, L, MV_DOT, TPB>(ctx, reinterpret_cast<cx<float>*>(smem), tile,
+                                                 const_cast<float*>(Z) + o, Q + o, nullptr, bv.M, tb, IterUpd{});
+  }
   const double sum = block_sum<TPB>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;
 }

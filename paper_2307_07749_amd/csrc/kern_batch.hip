@@ -64,15 +64,13 @@ __global__ __launch_bounds__(TPB_EW) void k_bt_transpose(const double* const* __
 // launchers
 // ---------------------------------------------------------------------------
 template <int L, int TPB>
-constexpr size_t bt_lds() {
-  return (size_t)(TPB / (L / fft_V(L))) * (size_t)fft_padded(L) * sizeof(cx<float>) + (size_t)TPB * sizeof(double);
-}
+constexpr size_t bt_lds() { return bt_lds_base<L, TPB>(); }
 
 template <int L, int TPB>
 static hipError_t go_bt(int which, const void* Q, const float* V1, const float* V2, float* Vout, float* Z,
                         float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials, hipStream_t s) {
   const int64_t blocks = bv.T * bv.S;
-  const size_t lds = bt_lds<L, TPB>();
+  const size_t lds = bt_lds<L, TPB>(), lds_cs = bt_cs_lds<L, TPB>();
   switch (which) {
     case BT_START:
       hipLaunchKernelGGL((k_bt_upd<L, double, false, TPB>), dim3((unsigned)blocks), dim3(TPB), lds, s,
@@ -83,8 +81,8 @@ static hipError_t go_bt(int which, const void* Q, const float* V1, const float* 
                          V1, V2, Vout, Z, bv, bt, partials);
       break;
     case BT_MATVEC:
-      hipLaunchKernelGGL((k_bt_cs<L, TPB>), dim3((unsigned)blocks), dim3(TPB), lds, s, (const float*)Z, Qout, bv, bt,
-                         partials);
+      hipLaunchKernelGGL((k_bt_cs<L, TPB>), dim3((unsigned)blocks), dim3(TPB), lds_cs, s,
+                         (const float*)Z, Qout, bv, bt, partials);
       break;
     default:
       return hipErrorInvalidValue;
@@ -181,7 +179,7 @@ static hipError_t attr_bt() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
     return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_cs<L, TPB>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             bytes);
+                             (int)bt_cs_lds<L, TPB>());
 }
 template <int L2>
 static hipError_t attr_bt_resid() {
