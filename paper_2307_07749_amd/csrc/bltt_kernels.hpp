@@ -2063,6 +2063,24 @@ BLTT_HD bool bt_skip(const BatchVec& bv, int s, bool lanczos) {
 }
 
 // time pass + Lanczos update (FULL) or start (cq = 1/||r|| of the system)
+// LDS of the batched time-line kernels: NL exchange lines and one double per
+// thread.  The batched time pass keeps its stage twiddles after them (as the
+// single-system one does); the batched N-point matvec stages its system's
+// tables (CsStage) there when everything fits in 80 KB (two workgroups per CU).
+template <int L, int TPB>
+constexpr size_t bt_lds_base() {
+  return (size_t)(TPB / (L / fft_V(L))) * (size_t)fft_padded(L) * sizeof(cx<float>) + (size_t)TPB * sizeof(double);
+}
+template <int L, int TPB>
+constexpr bool bt_cs_stage() { return bt_lds_base<L, TPB>() + 4 * (size_t)L * sizeof(cx<float>) <= 80 * 1024; }
+template <int L, int TPB>
+constexpr size_t bt_cs_lds() {
+  return bt_lds_base<L, TPB>() + (bt_cs_stage<L, TPB>() ? 4 * (size_t)L * sizeof(cx<float>) : 0);
+}
+
+template <int L, int TPB>
+constexpr size_t bt_upd_lds() { return bt_lds_base<L, TPB>() + (size_t)L * sizeof(cx<float>); }
+
 template <int L, typename TQ, bool FULL, int TPB, class Ctx>
 BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q, const float* __restrict__ V1,
                          const float* __restrict__ V2, float* __restrict__ Vout, float* __restrict__ Zout,
@@ -2089,9 +2107,18 @@ BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q
   for (int k = 0; k < 4; ++k) tb.q[k] = ip.q32[k];
   tb.qtaps = ip.qtaps;
   tb.aux = nullptr;
+  // the stage twiddles in LDS (time pass with TWL), after the exchange lines
+  // and the reduction slots
+  {
+    using FT = LineFft<float, L, NL, false, LAST_PAIRED, true>;
+    cx<float>* twl = reinterpret_cast<cx<float>*>(smem + bt_lds_base<L, TPB>());
+    FT::template build_twl<TPB>(ctx, twl, bt.tw);
+    ctx.sync();
+    tb.tw = twl;
+  }
   const int64_t o = (int64_t)s * bv.n;
   const double* coef = FULL ? bv.states[s].coef_v : &bv.states[s].rinv;
-  const double part = time_upd_tile<float, L, TQ, FULL, true, TPB>(
+  const double part = time_upd_tile<float, L, TQ, FULL, true, TPB, true, true>(
       ctx, reinterpret_cast<cx<float>*>(smem), tile, Q + o, FULL ? V1 + o : nullptr, FULL ? V2 + o : nullptr,
       Vout ? Vout + o : nullptr, Zout + o, bv.M, tb, coef);
   const double sum = block_sum<TPB>(ctx, red, part);
@@ -2099,20 +2126,6 @@ BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q
 }
 
 // FP32 sine-coordinate matvec (N-point form): Q = Y T Z, partial sums of <Q, Z>
-// LDS of the batched time-line kernels: NL exchange lines and one double per
-// thread.  The batched N-point matvec stages its system's tables (CsStage)
-// after them when everything fits in 80 KB (two workgroups per CU).
-template <int L, int TPB>
-constexpr size_t bt_lds_base() {
-  return (size_t)(TPB / (L / fft_V(L))) * (size_t)fft_padded(L) * sizeof(cx<float>) + (size_t)TPB * sizeof(double);
-}
-template <int L, int TPB>
-constexpr bool bt_cs_stage() { return bt_lds_base<L, TPB>() + 4 * (size_t)L * sizeof(cx<float>) <= 80 * 1024; }
-template <int L, int TPB>
-constexpr size_t bt_cs_lds() {
-  return bt_lds_base<L, TPB>() + (bt_cs_stage<L, TPB>() ? 4 * (size_t)L * sizeof(cx<float>) : 0);
-}
-
 template <int L, int TPB, class Ctx>
 BLTT_HD void bt_cs_body(Ctx& ctx, unsigned char* smem, const float* __restrict__ Z, float* __restrict__ Q,
                         const BatchVec& bv, const BatchTabs& bt, double* __restrict__ partials) {

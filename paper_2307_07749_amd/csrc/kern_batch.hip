@@ -63,14 +63,12 @@ __global__ __launch_bounds__(TPB_EW) void k_bt_transpose(const double* const* __
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int L, int TPB>
-constexpr size_t bt_lds() { return bt_lds_base<L, TPB>(); }
 
 template <int L, int TPB>
 static hipError_t go_bt(int which, const void* Q, const float* V1, const float* V2, float* Vout, float* Z,
                         float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials, hipStream_t s) {
   const int64_t blocks = bv.T * bv.S;
-  const size_t lds = bt_lds<L, TPB>(), lds_cs = bt_cs_lds<L, TPB>();
+  const size_t lds = bt_upd_lds<L, TPB>(), lds_cs = bt_cs_lds<L, TPB>();
   switch (which) {
     case BT_START:
       hipLaunchKernelGGL((k_bt_upd<L, double, false, TPB>), dim3((unsigned)blocks), dim3(TPB), lds, s,
@@ -170,7 +168,7 @@ hipError_t launch_bt_transpose(const double* const* in_p, const double* in_b, do
 
 template <int L, int TPB>
 static hipError_t attr_bt() {
-  const int bytes = (int)bt_lds<L, TPB>();
+  const int bytes = (int)bt_upd_lds<L, TPB>();
   hipError_t e;
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_upd<L, double, false, TPB>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
