@@ -27,10 +27,13 @@ def relnorm(a, b):
 
 
 def small_batch():
-    # uneven shapes, blocks and alpha; two instances share each 2D shape
+    # uneven shapes, blocks and alpha; two instances share each 2D shape; the
+    # N = 2048 class's matvec reads its tables from global memory (too large
+    # to stage in LDS beside the exchange lines), the others stage them
     return [W.fractional_l1(2, 7, 16, 0.3, 0.01), W.fractional_l1(2, 7, 16, 0.7, 0.05),
             W.fractional_l1(2, 15, 32, 0.5, 0.003), W.heat_bdf(2, 15, 32, 0.02),
-            W.fractional_l1(1, 31, 64, 0.4, 0.01), W.heat_cn(2, 7, 8, 0.1)]
+            W.fractional_l1(1, 31, 64, 0.4, 0.01), W.heat_cn(2, 7, 8, 0.1),
+            W.fractional_l1(1, 15, 2048, 0.5, 0.01)]
 
 
 def test_batched_matches_oracle_and_single():
