@@ -637,7 +637,10 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   }
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    zin[t] = mkc<T>(va ? ra[t] : T(0), vb ? rb[t] : T(0));
+    // a line past M holds the clamped line M-1: its products stay in their
+    // own half of the packed line (C, S and the q taps are real) and all its
+    // stores and dot terms are guarded
+    zin[t] = mkc<T>(ra[t], rb[t]);
     v[t] = zin[t];
   }
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -1299,9 +1302,10 @@ BLTT_HD double alpha_pow_n(const TimeTables<double>& tb, const double* tab, doub
 
 // Multiplies v[t] (time n = g + t*s0) by alpha^{e n/N}.  FP32: two exp2 per
 // thread and a product chain over t (relative error below 2e-6 for V = 16);
-// FP64: the table.  With DOT, also returns sum_t <v_t before, v_t after>.
+// FP64: the table.  With DOT, also returns sum_t re(v_t before) re(v_t after)
+// (the real line's share of the dot), and the imaginary line's in *dot_im.
 template <typename T, int V, int s0, bool DOT = false>
-BLTT_HD T scale_alpha(cx<T>* v, const TimeTables<T>& tb, const T* tab, T e, int g) {
+BLTT_HD T scale_alpha(cx<T>* v, const TimeTables<T>& tb, const T* tab, T e, int g, T* dot_im = nullptr) {
   T acc0 = T(0), acc1 = T(0);
   T d = T(0), st = T(0);
   if constexpr (sizeof(T) == 4) {
@@ -1313,13 +1317,14 @@ BLTT_HD T scale_alpha(cx<T>* v, const TimeTables<T>& tb, const T* tab, T e, int 
     if constexpr (sizeof(T) != 4) d = alpha_pow_n(tb, tab, e, g + t * s0);
     const cx<T> w = v[t] * d;
     if (DOT) {
-      T& acc = (t & 1) ? acc1 : acc0;
-      acc += v[t].re * w.re + v[t].im * w.im;
+      acc0 += v[t].re * w.re;
+      acc1 += v[t].im * w.im;
     }
     v[t] = w;
     if constexpr (sizeof(T) == 4) d *= st;
   }
-  return acc0 + acc1;
+  if (DOT) *dot_im = acc1;
+  return acc0;
 }
 
 // The two-for-one spectral step.  A packed line holds mode a in its real part
@@ -1591,25 +1596,53 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
     cvp = T(coef[2]);
   }
 
-  cx<T> v[V];
+  // every load of the tile first, one wait after them all: the empty asm
+  // statements keep the loads above the "memory" barrier and the arithmetic
+  // on them below it (left alone, the scheduler may trade the batch for
+  // registers and wait after every few loads, once per memory round trip)
+  TQ xqa[V], xqb[V];
+  T x1a[FULL ? V : 1], x1b[FULL ? V : 1], x2a[FULL ? V : 1], x2b[FULL ? V : 1];
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int64_t off = (int64_t)(t * s0) * ts;
     // qrev (start only): Q read with its time lines reversed, i.e. Y Q
     const int64_t offq = rq ? -off : off;
+    xqa[t] = qa[offq];
+    xqb[t] = qb[offq];
+    if constexpr (FULL) {
+      x1a[t] = V1[la + gv + off];
+      x1b[t] = V1[lb + gv + off];
+      x2a[t] = V2[la + gv + off];
+      x2b[t] = V2[lb + gv + off];
+    }
+  }
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    asm volatile("" : "+v"(xqa[t]), "+v"(xqb[t]));
+    if constexpr (FULL) asm volatile("" : "+v"(x1a[t]), "+v"(x1b[t]), "+v"(x2a[t]), "+v"(x2b[t]));
+  }
+#endif
+  cx<T> v[V];
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
     T a, b;
     if constexpr (sizeof(TQ) > sizeof(T)) {
-      a = T((double)qa[offq] * cq);
-      b = T((double)qb[offq] * cq);
+      a = T((double)xqa[t] * cq);
+      b = T((double)xqb[t] * cq);
     } else {
-      a = T(cq) * qa[offq];
-      b = T(cq) * qb[offq];
+      a = T(cq) * xqa[t];
+      b = T(cq) * xqb[t];
     }
-    if (FULL) {
-      a += cv * V1[la + gv + off] + cvp * V2[la + gv + off];
-      b += cv * V1[lb + gv + off] + cvp * V2[lb + gv + off];
+    if constexpr (FULL) {
+      a += cv * x1a[t] + cvp * x2a[t];
+      b += cv * x1b[t] + cvp * x2b[t];
     }
-    v[t] = mkc<T>(va ? a : T(0), vb ? b : T(0));
+    // a line past M reads the clamped line M-1: finite values whose
+    // transforms stay in their own half of the packed line; its stores are
+    // guarded and its share of the dot is masked
+    v[t] = mkc<T>(a, b);
   }
   if (Vout) {
     T* oa = Vout + la + gv;
@@ -1630,7 +1663,9 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
     F::inverse(ctx, v, lds, c, g, tb.tw);
     // v = D^{-1} (C^{-1/2})^* vhat here, so with w = (C^{-1/2})^* vhat,
     // ||w||^2 = sum_t <v, D^2 v>, taken while scaling by the middle D^2
-    part = (double)scale_alpha<T, V, s0, true>(v, tb, tb.d2, T(2), g);
+    T dot_b;
+    const T dot_a = scale_alpha<T, V, s0, true>(v, tb, tb.d2, T(2), g, &dot_b);
+    part = (va ? (double)dot_a : 0.0) + (vb ? (double)dot_b : 0.0);
     F::forward(ctx, v, lds, c, g, tb.tw);
     time_spectral<T, L, F, 1>(v, g, mua, mub, tb, invN, gm);
     F::inverse(ctx, v, lds, c, g, tb.tw);
@@ -1643,7 +1678,8 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
     const int64_t off = (int64_t)(t * s0) * ts;
     if (va) za[off] = v[t].re;
     if (vb) zb[off] = v[t].im;
-    if constexpr (!PREC) part += (double)v[t].re * (double)v[t].re + (double)v[t].im * (double)v[t].im;
+    if constexpr (!PREC)
+      part += (va ? (double)v[t].re * (double)v[t].re : 0.0) + (vb ? (double)v[t].im * (double)v[t].im : 0.0);
   }
   return part;
 }
