@@ -1573,6 +1573,9 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
   // does not keep g-dependent table loads (twiddles, spectra) live across
   // tiles at the cost of occupancy
   asm volatile("" : "+v"(g));
+  // g < G again for the compiler: LDS positions g + t*s0 then split into a
+  // per-lane base and compile-time offsets (the ds instructions' immediates)
+  g &= G - 1;
 #endif
   const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
