@@ -103,6 +103,12 @@ typedef struct {
                              (default 10)                                         */
   int32_t basis;          /* BLTT_BASIS_SINE (default) or BLTT_BASIS_PHYSICAL     */
   int32_t precond;        /* BLTT_PRECOND_ABAC (default) or BLTT_PRECOND_NONE     */
+  int32_t initial_guess;  /* 0 (default): MINRES starts from u = 0 (Section 5);
+                             1: bltt_pminres reads its initial guess from u_dev
+                             and iterates on the residual Y(f - A u0)           */
+  const char *plan_cache; /* NULL, or a text file of kernel plans chosen by the
+                             setup autotuner: read when it holds an entry for
+                             this shape, appended to when the tuner had to run  */
 } bltt_options;
 
 /* Per-solve report. */
@@ -167,13 +173,17 @@ int bltt_setup_varcoef(const bltt_blocks *blk, const double *const *face, double
                        bltt_handle **out);
 
 /*
- * bltt_pminres -- solve A u = f by preconditioned MINRES on Y A u = Y f with
- * a zero initial guess.  Stops when ||Y(f - A u)||_2 / ||Y f||_2 <= tol.
+ * bltt_pminres -- solve A u = f by preconditioned MINRES on Y A u = Y f, from
+ * a zero initial guess (Section 5) or, when the handle was set up with
+ * opt->initial_guess = 1, from the u_dev passed in.  Stops when
+ * ||Y(f - A u)||_2 / ||Y f||_2 <= tol (an initial guess that already meets it
+ * returns with zero iterations).
  *   f_dev   FP64 device vector of length N*M (not modified)
  *   tol     relative residual target, > 0
  *   maxit   iteration cap (>= 1); in MIXED it caps the total inner iterations
- *   u_dev   FP64 device vector of length N*M receiving the solution; must
- *           not overlap f_dev
+ *   u_dev   FP64 device vector of length N*M receiving the solution (and
+ *           holding the initial guess on entry when so set up); must not
+ *           overlap f_dev
  *   iters   host, receives the number of MINRES iterations (may be NULL)
  *   hist    host array of length maxit+1 or NULL; receives |eta_j|/eta_0, the
  *           P^{-1}-norm residual estimate MINRES carries (hist[0] = 1); in
@@ -207,6 +217,51 @@ int bltt_pminres(bltt_handle *h, const double *f_dev, double tol, int32_t maxit,
 int bltt_apply_sym(bltt_handle *h, int32_t precision, const void *x_dev, void *y_dev);
 int bltt_apply_precond(bltt_handle *h, int32_t precision, const void *x_dev, void *y_dev);
 int bltt_apply_space(bltt_handle *h, int32_t precision, const void *x_dev, void *y_dev);
+
+/*
+ * Sine-coordinate step entry points: one application of a kernel of the
+ * default (sine-basis) solve.  Every block p_k I + q_k L_h is diagonal in the
+ * orthonormal sine basis (Remark 1): sine mode i sees the scalar lower
+ * triangular Toeplitz matrix T_i with first column p + mu_i q, mu_i the
+ * eigenvalue of L_h for mode i, and P_alpha^{-1} acts on each mode's time
+ * line alone (Section 5.1, Step 2).  These entry points take mode-major
+ * vectors: element (i, n) of a sine-coordinate vector sits at i*N + n.
+ * Device buffers belong to the caller; outputs must not overlap inputs.  The
+ * handle's tables for the precision used are built on first use.  Scalar
+ * results are reduced in FP64 on the device and returned through host
+ * pointers (each may be NULL).  Variable-coefficient handles
+ * (bltt_setup_varcoef) are not sine-diagonal: BLTT_EUNSUPPORTED.
+ *
+ * bltt_modes_forward:  xhat = (I_N (x) U) x, x time-major FP64 (the ABI
+ *                      layout), xhat mode-major FP64; *norm2 = ||x||^2.
+ * bltt_modes_backward: x = (I_N (x) U) xhat back to time-major; xhat is
+ *                      used as scratch and overwritten.
+ * bltt_modes_sym:      q = Y T z per mode (Section 2, eq. (4), in sine
+ *                      coordinates); *dot = <q, z>.  precision BLTT_FP64
+ *                      (double*) or BLTT_FP32 (float*).
+ * bltt_modes_lanczos:  vhat = coef[0] q + coef[1] v1 + coef[2] v2 (a NULL v1
+ *                      or v2 drops its term; coef NULL means 1, 0, 0),
+ *                      zout = P_alpha^{-1} vhat (eqs. (8)-(13), both
+ *                      half-solves), vout = vhat when vout is non-NULL, and
+ *                      *dot = <vhat, zout>: the fused Lanczos update and
+ *                      preconditioner of one MINRES iteration.  precision
+ *                      BLTT_FP64 (all double*), BLTT_FP32 (all float*), or
+ *                      BLTT_MIXED (q double*, vout/zout float*, v1 = v2 =
+ *                      NULL: the start of an FP32 refinement sweep).
+ * bltt_modes_resid:    FP64 refinement residual: first u += scale *
+ *                      sum_{j<k} y[j] z[j] (k FP32 mode-major vectors z[j],
+ *                      a host array of device pointers, and k host weights y;
+ *                      k = 0 skips it, at most 32), then r = Y (fhat - T u)
+ *                      and *norm2 = ||r||^2.  u is updated in place.
+ * Errors: BLTT_EINVAL, BLTT_EUNSUPPORTED, BLTT_ENOMEM, BLTT_EHIP.
+ */
+int bltt_modes_forward(bltt_handle *h, const double *x_dev, double *xhat_dev, double *norm2);
+int bltt_modes_backward(bltt_handle *h, double *xhat_dev, double *x_dev);
+int bltt_modes_sym(bltt_handle *h, int32_t precision, const void *z_dev, void *q_dev, double *dot);
+int bltt_modes_lanczos(bltt_handle *h, int32_t precision, const void *q_dev, const void *v1_dev,
+                       const void *v2_dev, const double *coef, void *vout_dev, void *zout_dev, double *dot);
+int bltt_modes_resid(bltt_handle *h, const double *fhat_dev, double *u_dev, double *r_dev,
+                     const float *const *z_dev, const double *y, int32_t k, double scale, double *norm2);
 
 /*
  * Per-kernel timing of the hot path.  While enabled, every kernel launch the

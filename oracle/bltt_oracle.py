@@ -507,3 +507,63 @@ def exact_modes(sys: System, f: np.ndarray, modes) -> np.ndarray:
         acc = ft[n] - (np.einsum("kj,kj->j", lam[1:n + 1], ut[n - 1::-1][:n]) if n else 0.0)
         ut[n] = acc / lam[0]
     return ut
+
+
+# ---------------------------------------------------------------------------
+# sine coordinates, mode by mode (Remark 1)
+# ---------------------------------------------------------------------------
+# Every block p_k I + q_k L_h is diagonal in the orthonormal sine basis: mode i
+# sees the scalar lower-triangular Toeplitz matrix T_i = sum_k (p_k + q_k mu_i)
+# H_0^{(k)} (eq. (3) with M = 1), and the block alpha-circulant C_alpha the
+# scalar alpha-circulant with the same first column (eqs. (5)-(7)).  These
+# functions act on the time lines of selected modes only, so that single
+# lines of a full-size vector can be checked.  Rows of Z are time lines.
+
+def mode_columns(sys: System, modes) -> np.ndarray:
+    """First columns p + mu_i q of T_i for the given modes: shape (N, K)."""
+    mu = laplacian_eigs(sys.ms, sys.hs)[np.asarray(modes, dtype=np.int64)]
+    return sys.p[:, None] + sys.q[:, None] * mu[None, :]
+
+
+def _mode_toeplitz(cols: np.ndarray, Z: np.ndarray) -> np.ndarray:
+    """Rows t_i = T_i z_i, (T_i z)_n = sum_{k<=n} cols[k, i] z_{n-k} (eq. (3))."""
+    Z = np.asarray(Z, np.float64)
+    out = np.zeros_like(Z)
+    N = Z.shape[1]
+    for k in range(N):
+        out[:, k:] += cols[k][:, None] * Z[:, :N - k]
+    return out
+
+
+def mode_sym_apply(sys: System, Z: np.ndarray, modes) -> np.ndarray:
+    """Y_N T_i z_i for each listed mode (rows of Z), the symmetrised operator
+    of eq. (4) in sine coordinates."""
+    return _mode_toeplitz(mode_columns(sys, modes), Z)[:, ::-1].copy()
+
+
+def mode_precond(sys: System, modes) -> Precond:
+    """The per-mode eigenvalues of eq. (9), lambda_i^{(k,alpha)} =
+    sum_j (p_j + mu_i q_j) alpha^{j/N} theta^{-kj}, for the listed modes only
+    (columns), with their principal square roots."""
+    N = sys.N
+    F = fourier_unitary(N)
+    d = alpha_scaling(N, sys.alpha)
+    lam = math.sqrt(N) * (F.conj().T @ (d[:, None] * mode_columns(sys, modes)))
+    if np.any(lam.real <= 0.0):
+        raise ValueError("alpha-circulant eigenvalue with non-positive real part")
+    return Precond(sys, lam, principal_sqrt(lam), F, d)
+
+
+def mode_precond_apply(sys: System, Z: np.ndarray, modes) -> np.ndarray:
+    """P_alpha^{-1} on the listed modes' time lines: the two half-solves of
+    Section 5.1 Step 2, (C^{-1/2})^* = D F conj(Lambda)^{-1/2} F^* D^{-1} first,
+    then C^{-1/2} = D^{-1} F Lambda^{-1/2} F^* D (eqs. (8)-(13))."""
+    P = mode_precond(sys, modes)
+    t = _time_sandwich(P, np.asarray(Z, np.float64).T, 1.0 / P.sq.conj(), 1.0 / P.d, P.d)
+    t = _time_sandwich(P, t, 1.0 / P.sq, P.d, 1.0 / P.d)
+    return t.T.copy()
+
+
+def mode_residual(sys: System, Fh: np.ndarray, Uh: np.ndarray, modes) -> np.ndarray:
+    """Y_N (fhat_i - T_i uhat_i) for each listed mode (rows of Fh, Uh)."""
+    return (np.asarray(Fh, np.float64) - _mode_toeplitz(mode_columns(sys, modes), Uh))[:, ::-1].copy()

@@ -41,7 +41,8 @@ class Blocks(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("check_factor", ctypes.c_double), ("basis", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("check_factor", ctypes.c_double), ("basis", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("initial_guess", ctypes.c_int32), ("plan_cache", ctypes.c_char_p)]
 
 
 class Info(ctypes.Structure):
@@ -80,6 +81,15 @@ def load() -> ctypes.CDLL:
         fn = getattr(L, name)
         fn.argtypes = [P, ctypes.c_int32, P, P]
         fn.restype = ctypes.c_int
+    D = ctypes.POINTER(ctypes.c_double)
+    L.bltt_modes_forward.argtypes = [P, P, P, D]
+    L.bltt_modes_backward.argtypes = [P, P, P]
+    L.bltt_modes_sym.argtypes = [P, ctypes.c_int32, P, P, D]
+    L.bltt_modes_lanczos.argtypes = [P, ctypes.c_int32, P, P, P, D, P, P, D]
+    L.bltt_modes_resid.argtypes = [P, P, P, P, ctypes.POINTER(P), D, ctypes.c_int32, ctypes.c_double, D]
+    for name in ("bltt_modes_forward", "bltt_modes_backward", "bltt_modes_sym", "bltt_modes_lanczos",
+                 "bltt_modes_resid"):
+        getattr(L, name).restype = ctypes.c_int
     L.bltt_profile_enable.argtypes = [P, ctypes.c_int32]
     L.bltt_profile_enable.restype = ctypes.c_int
     L.bltt_profile_read.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
@@ -133,7 +143,7 @@ class Solver:
 
     def __init__(self, dim: int, m, h, p, q, alpha: float, precision: int = FP64, inner_tol: float = 0.0,
                  max_refine: int = 0, check_factor: float = 0.0, basis: int = 0, precond: int = 0, stream=None,
-                 face=None, abar: float = 1.0):
+                 face=None, abar: float = 1.0, initial_guess: bool = False, plan_cache: str | None = None):
         L = load()
         self._L = L
         m = list(m)
@@ -153,7 +163,10 @@ class Solver:
             blk.h[d] = h[d] if d < dim else 1.0
         blk.p = self._p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         blk.q = self._q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        opt = Options(precision, inner_tol, max_refine, check_factor, basis, precond)
+        self.initial_guess = bool(initial_guess)
+        self._plan_cache = plan_cache.encode() if plan_cache else None
+        opt = Options(precision, inner_tol, max_refine, check_factor, basis, precond, int(bool(initial_guess)),
+                      self._plan_cache)
         self.stream = stream
         handle = ctypes.c_void_p()
         if face is None:
@@ -190,10 +203,13 @@ class Solver:
         return ctypes.c_void_p(x.data_ptr())
 
     def pminres(self, f, tol: float, maxit: int, u=None):
-        """Solve A u = f.  Returns (u, iters, hist, info, status)."""
+        """Solve A u = f.  Returns (u, iters, hist, info, status).  A handle
+        set up with initial_guess=True starts from the u passed in."""
         import torch
         fp = self._vec(f, torch.float64)
         if u is None:
+            if self.initial_guess:
+                raise ValueError("this solver starts from the u passed in (initial_guess=True)")
             u = torch.empty_like(f)
         up = self._vec(u, torch.float64)
         iters = ctypes.c_int32(0)
@@ -240,6 +256,72 @@ class Solver:
     def apply_space(self, x, y=None):
         """y = (I_N (x) U) x, the orthonormal sine transform of every time slice."""
         return self._apply("bltt_apply_space", x, y)
+
+    # ---- sine-coordinate steps (mode-major vectors: element (i, n) at i*N + n)
+    def modes_forward(self, x, xhat=None):
+        """xhat = (I_N (x) U) x in mode-major order; returns (xhat, ||x||^2)."""
+        import torch
+        xp = self._vec(x, torch.float64)
+        if xhat is None:
+            xhat = torch.empty_like(x)
+        nrm = ctypes.c_double(0.0)
+        _check(self._L.bltt_modes_forward(self._h, xp, self._vec(xhat, torch.float64), ctypes.byref(nrm)))
+        return xhat, float(nrm.value)
+
+    def modes_backward(self, xhat, x=None):
+        """x = (I_N (x) U) xhat in time-major order (xhat is overwritten)."""
+        import torch
+        xh = self._vec(xhat, torch.float64)
+        if x is None:
+            x = torch.empty_like(xhat)
+        _check(self._L.bltt_modes_backward(self._h, xh, self._vec(x, torch.float64)))
+        return x
+
+    def modes_sym(self, z, q=None):
+        """q = Y T z per sine mode; returns (q, <q, z>)."""
+        import torch
+        prec = FP64 if z.dtype == torch.float64 else FP32
+        zp = self._vec(z, z.dtype)
+        if q is None:
+            q = torch.empty_like(z)
+        dot = ctypes.c_double(0.0)
+        _check(self._L.bltt_modes_sym(self._h, prec, zp, self._vec(q, z.dtype), ctypes.byref(dot)))
+        return q, float(dot.value)
+
+    def modes_lanczos(self, q, v1=None, v2=None, coef=(1.0, 0.0, 0.0), z=None, want_v=False, dtype=None):
+        """vhat = coef[0] q + coef[1] v1 + coef[2] v2, z = P^{-1} vhat per mode.
+        dtype: precision of v1/v2/outputs (default q's; float32 with a
+        float64 q is the mixed sweep start).  Returns (z, vhat or None, <vhat, z>)."""
+        import torch
+        dt = dtype or q.dtype
+        prec = FP64 if dt == torch.float64 else (MIXED if q.dtype == torch.float64 else FP32)
+        qp = self._vec(q, q.dtype)
+        v1p = self._vec(v1, dt) if v1 is not None else None
+        v2p = self._vec(v2, dt) if v2 is not None else None
+        if z is None:
+            z = torch.empty(q.numel(), dtype=dt, device=q.device)
+        v = torch.empty(q.numel(), dtype=dt, device=q.device) if want_v else None
+        c = (ctypes.c_double * 4)(*[float(x) for x in coef], 0.0)
+        dot = ctypes.c_double(0.0)
+        _check(self._L.bltt_modes_lanczos(self._h, prec, qp, v1p, v2p, c, self._vec(v, dt) if v is not None else None,
+                                          self._vec(z, dt), ctypes.byref(dot)))
+        return z, v, float(dot.value)
+
+    def modes_resid(self, fhat, u, r=None, zs=(), y=(), scale=1.0):
+        """u += scale * sum_j y[j] zs[j] (FP32 zs), then r = Y (fhat - T u).
+        Returns (r, ||r||^2); u is updated in place."""
+        import torch
+        fp = self._vec(fhat, torch.float64)
+        up = self._vec(u, torch.float64)
+        if r is None:
+            r = torch.empty_like(fhat)
+        k = len(zs)
+        zp = (ctypes.c_void_p * max(k, 1))(*[self._vec(zz, torch.float32).value for zz in zs])
+        yy = (ctypes.c_double * max(k, 1))(*[float(v) for v in y])
+        nrm = ctypes.c_double(0.0)
+        _check(self._L.bltt_modes_resid(self._h, fp, up, self._vec(r, torch.float64), zp if k else None,
+                                        yy if k else None, k, float(scale), ctypes.byref(nrm)))
+        return r, float(nrm.value)
 
 
 class Batch:

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "bltt.h"
@@ -57,6 +58,9 @@ double now_ms() {
 
 hipError_t g_config_err = hipSuccess;
 
+// layout of bltt_handle::step_dev
+constexpr int STEP_COEF = 0, STEP_SCALE = 4, STEP_Y = 8, STEP_LEN = STEP_Y + ZB_MAX;
+
 }  // namespace
 
 struct bltt_handle {
@@ -93,12 +97,16 @@ struct bltt_handle {
   double* hist_dev = nullptr;
   int64_t hist_cap = 0;
   double* coef_one = nullptr;
+  // step entry points: coefficients and refinement weights copied from the host
+  // (STEP_COEF: 4 Lanczos coefficients, STEP_SCALE: 1 scale, STEP_Y: ZB_MAX weights)
+  double* step_dev = nullptr;
   // stored-basis sweeps (mixed, sine basis): Z_0..Z_{K-1} and the
   // coefficient arrays of the directions and of the iterate
   float* zpool[ZB_MAX] = {};
   int zb_K = 0;
   double* zb_dev = nullptr;  // 3*ZB_MAX doubles: om (2K), y (K)
   double setup_ms = 0.0;
+  std::string plan_cache;  // autotuner plan file ("" = none)
   std::vector<void*> allocs;
   // per-kernel timing (bltt_profile_enable)
   struct ProfRec {
@@ -717,11 +725,13 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   return BLTT_OK;
 }
 
-bool overlaps(const void* a, const void* b, int64_t bytes) {
+// [a, a + na) and [b, b + nb) share a byte
+bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
   const char* pa = (const char*)a;
   const char* pb = (const char*)b;
-  return pa < pb + bytes && pb < pa + bytes;
+  return pa < pb + nb && pb < pa + na;
 }
+bool overlaps(const void* a, const void* b, int64_t bytes) { return overlaps(a, bytes, b, bytes); }
 
 int check_power(int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
@@ -823,6 +833,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (opt->precision != BLTT_FP64 && opt->precision != BLTT_MIXED) return BLTT_EINVAL;
     if (opt->basis != BLTT_BASIS_SINE && opt->basis != BLTT_BASIS_PHYSICAL) return BLTT_EINVAL;
     if (opt->precond != BLTT_PRECOND_ABAC && opt->precond != BLTT_PRECOND_NONE) return BLTT_EINVAL;
+    if (opt->initial_guess != 0 && opt->initial_guess != 1) return BLTT_EINVAL;
     // the unpreconditioned comparator runs the FP64 sine-basis path
     if (opt->precond == BLTT_PRECOND_NONE && (opt->precision != BLTT_FP64 || opt->basis != BLTT_BASIS_SINE))
       return BLTT_EUNSUPPORTED;
@@ -882,7 +893,10 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (opt->inner_tol > 0.0) h->opt.inner_tol = opt->inner_tol;
     if (opt->max_refine > 0) h->opt.max_refine = opt->max_refine;
     if (opt->check_factor >= 1.0) h->opt.check_factor = opt->check_factor;
+    h->opt.initial_guess = opt->initial_guess;
+    if (opt->plan_cache) h->plan_cache = opt->plan_cache;
   }
+  h->opt.plan_cache = nullptr;  // the handle keeps its own copy of the path
   if (face) {
     h->var = true;
     h->abar = abar;
@@ -939,6 +953,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
   {
     std::vector<double> one = {1.0, 0.0, 0.0, 0.0};
     if ((rc = upload<double>(h, &h->coef_one, one))) return fail(rc);
+    if ((rc = dalloc(h, &h->step_dev, (size_t)STEP_LEN))) return fail(rc);
   }
   for (int d = 0; d < h->dim; ++d)
     if (h->var && (rc = upload<double>(h, &h->face_dev[d], face_host[d]))) return fail(rc);
@@ -985,7 +1000,8 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
   hipStream_t s = h->stream;
   int rc;
   int64_t np = 0;
-  if (h->opt.basis != BLTT_BASIS_SINE) {
+  const bool guess = h->opt.initial_guess != 0;
+  if (h->opt.basis != BLTT_BASIS_SINE && !guess) {
     ProfScope ps(h, BLTT_K_OTHER, 8.0 * h->n);
     HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
   }
@@ -1002,8 +1018,10 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     // start reads fhat reversed.
     double* fhat = u_dev;
     double* uhat = h->F64;
+    // an initial guess u0 enters as uhat = (I x U) u0, before fhat takes its buffer
+    if (guess && (rc = sine_forward(h, u_dev, uhat, &np))) return rc;
     if ((rc = sine_forward(h, f_dev, fhat, &np))) return rc;
-    if (h->opt.precision == BLTT_FP64 || short_p(h)) {
+    if (!guess && (h->opt.precision == BLTT_FP64 || short_p(h))) {
       // the FP64 path and the direct-form residual read uhat from the start;
       // the fused FFT residual of the mixed path writes it on the first sweep
       ProfScope ps(h, BLTT_K_OTHER, 8.0 * h->n);
@@ -1020,9 +1038,28 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
       HIPCHK(launch_fill<double>(uhat, h->n, 0.0, s));
     } else if (h->opt.precision == BLTT_FP64) {
       CoreResult cr;
-      rc = minres_spec<double, double, double>(h, uhat, maxit, h->opt.check_factor * tol, fhat, tol, bnorm, hist,
-                                               &cr, fhat, h->coef_one, false, true);
-      if (rc) return rc;
+      double r0 = 1.0;
+      if (guess) {
+        // MINRES from uhat: the Lanczos process starts from r0 = Y(fhat - T uhat)
+        if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, uhat, h->w64.V[0], fhat, &np))) return rc;
+        if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+        if ((rc = read_state(h))) return rc;
+        r0 = std::sqrt(h->state_host->norm2) / bnorm;
+        if (!std::isfinite(r0)) return BLTT_ENAN;
+      }
+      if (guess && r0 <= tol) {
+        cr.iters = 0;
+        cr.status = BLTT_OK;
+        cr.relres = r0;
+      } else if (guess) {
+        rc = minres_spec<double, double, double>(h, uhat, maxit, h->opt.check_factor * tol / r0, fhat, tol, bnorm,
+                                                 hist, &cr, h->w64.V[0], h->coef_one, false, false);
+        if (rc) return rc;
+      } else {
+        rc = minres_spec<double, double, double>(h, uhat, maxit, h->opt.check_factor * tol, fhat, tol, bnorm, hist,
+                                                 &cr, fhat, h->coef_one, false, true);
+        if (rc) return rc;
+      }
       total_iters = cr.iters;
       outer = 1;
       status = cr.status;
@@ -1035,11 +1072,18 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
       }
     } else {
       // FP64 refinement around FP32 MINRES sweeps on r / ||r|| (state->rinv)
-      Workspace<float>& ws = h->w32;
       double rnorm = bnorm;
       status = BLTT_NOCONV;
       int hist_pos = 0;
       std::vector<double> hbuf;
+      if (guess) {
+        // refinement from uhat: the first sweep solves for the residual of the guess
+        if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, uhat, h->R64, fhat, &np))) return rc;
+        if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+        if ((rc = read_state(h))) return rc;
+        rnorm = std::sqrt(h->state_host->norm2);
+        if (!std::isfinite(rnorm)) return BLTT_ENAN;
+      }
       while (true) {
         relres = rnorm / bnorm;
         if (relres <= tol) {
@@ -1051,8 +1095,9 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         const int left = maxit - total_iters;
         hbuf.assign((size_t)left + 2, 0.0);
         // r = b = Y fhat on the first sweep (read from fhat reversed), then the residual
+        const bool from_b = outer == 0 && !guess;
         rc = minres_spec<float, float, double>(h, nullptr, left, sweep_tol(h, tol, relres), nullptr, 0.0, 1.0, hbuf.data(),
-                                               &cr, outer == 0 ? fhat : h->R64, &h->state->rinv, true, outer == 0);
+                                               &cr, from_b ? fhat : h->R64, &h->state->rinv, true, from_b);
         if (rc) return rc;
         if (hist)
           for (int k = 1; k <= cr.iters; ++k) hist[hist_pos + k] = hbuf[(size_t)k];
@@ -1077,7 +1122,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
           up.k = cr.iters;
           up.y = ycoef;
           up.s = &h->state->rscale;
-          up.u_zero = outer == 1 ? 1 : 0;
+          up.u_zero = outer == 1 && !guess ? 1 : 0;
           ProfScope ps(h, BLTT_K_RESID64, (32.0 + 4.0 * cr.iters - (up.u_zero ? 8.0 : 0.0)) * h->n);
           HIPCHK(launch_matvec_fft<double>((int)(2 * h->N), MV_RESID, TERM_SPEC, uhat, h->R64, fhat, h->M,
                                            mv_tables<double>(h), up, h->partials, s));
@@ -1102,6 +1147,7 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     const double bn2 = h->state_host->norm2;
     if (!std::isfinite(bn2)) return BLTT_ENAN;
     if (bn2 == 0.0) {
+      if (guess) HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
       if (iters) *iters = 0;
       if (hist) hist[0] = 1.0;
       if (info) {
@@ -1117,8 +1163,25 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     }
     const double bnorm = std::sqrt(bn2);
     CoreResult cr;
-    rc = minres_core<double, double>(h, u_dev, maxit, h->opt.check_factor * tol, f_dev, tol, bnorm, hist, &cr);
-    if (rc) return rc;
+    double r0 = 1.0;
+    if (guess) {
+      // MINRES from u_dev: V[0] = r0 = Y(f - A u0)
+      if ((rc = matvec<double>(h, MV_RESID, TERM_STENCIL, u_dev, ws.V[0], f_dev, &np))) return rc;
+      if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+      if ((rc = read_state(h))) return rc;
+      r0 = std::sqrt(h->state_host->norm2) / bnorm;
+      if (!std::isfinite(r0)) return BLTT_ENAN;
+    }
+    if (guess && r0 <= tol) {
+      cr.iters = 0;
+      cr.status = BLTT_OK;
+      cr.relres = r0;
+      if (hist) hist[0] = 1.0;
+    } else {
+      rc = minres_core<double, double>(h, u_dev, maxit, h->opt.check_factor * tol / r0, f_dev, tol, bnorm, hist,
+                                       &cr);
+      if (rc) return rc;
+    }
     total_iters = cr.iters;
     outer = 1;
     status = cr.status;
@@ -1146,6 +1209,13 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     if (bn2 == 0.0) {
       status = BLTT_OK;
       relres = 0.0;
+      HIPCHK(launch_fill<double>(u_dev, h->n, 0.0, s));
+    } else if (guess) {
+      if ((rc = matvec<double>(h, MV_RESID, TERM_STENCIL, u_dev, h->R64, f_dev, &np))) return rc;
+      if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+      if ((rc = read_state(h))) return rc;
+      rnorm = std::sqrt(h->state_host->norm2);
+      if (!std::isfinite(rnorm)) return BLTT_ENAN;
     }
     if (hist) hist[0] = 1.0;
     int hist_pos = 0;
@@ -1267,6 +1337,176 @@ int bltt_apply_space(bltt_handle* h, int32_t precision, const void* x_dev, void*
   }
   HIPCHK(hipStreamSynchronize(h->stream));
   return BLTT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Sine-coordinate step entry points: the kernels of the default (sine-basis)
+// solve, one application each, on mode-major vectors (element (i, n) at
+// i*N + n).  Reductions go through h->partials and the scalar kernel.
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int step_tables(bltt_handle* h) {
+  return build_tables<T>(h);
+}
+
+int step_tables_for(bltt_handle* h, int32_t precision) {
+  if (precision == BLTT_FP64) return step_tables<double>(h);
+  if (precision == BLTT_FP32) return step_tables<float>(h);
+  if (precision == BLTT_MIXED) {
+    int rc = step_tables<double>(h);
+    return rc ? rc : step_tables<float>(h);
+  }
+  return BLTT_EINVAL;
+}
+
+// reduce the np partial sums left in h->partials; *out receives the sum
+int reduce_to_host(bltt_handle* h, int64_t np, double* out) {
+  int rc;
+  if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+  if ((rc = read_state(h))) return rc;
+  if (out) *out = h->state_host->norm2;
+  return BLTT_OK;
+}
+
+int upload_step(bltt_handle* h, int at, const double* src, int count) {
+  HIPCHK(hipMemcpyAsync(h->step_dev + at, src, sizeof(double) * (size_t)count, hipMemcpyHostToDevice, h->stream));
+  return BLTT_OK;
+}
+
+template <typename T, typename TQ>
+int modes_lanczos_impl(bltt_handle* h, const void* q, const void* v1, const void* v2, const double* coef,
+                       void* vout, void* zout, double* dot) {
+  const bool full = v1 || v2;
+  double c[4] = {coef ? coef[0] : 1.0, coef && v1 ? coef[1] : 0.0, coef && v2 ? coef[2] : 0.0, 0.0};
+  const T* V1 = (const T*)(v1 ? v1 : v2);
+  const T* V2 = (const T*)(v2 ? v2 : V1);
+  int rc;
+  if ((rc = upload_step(h, STEP_COEF, c, 4))) return rc;
+  int64_t np = 0;
+  {
+    ProfScope ps(h, BLTT_K_TIME, (double)h->n * (sizeof(TQ) + sizeof(T) * (1.0 + (vout ? 1 : 0) + (v1 ? 1 : 0) +
+                                                                               (v2 ? 1 : 0))));
+    HIPCHK(launch_time_upd<T, TQ>((int)h->N, full, h->opt.precond == BLTT_PRECOND_ABAC, (const TQ*)q, V1, V2,
+                                  (T*)vout, (T*)zout, h->M, time_tables<T>(h, false), h->step_dev + STEP_COEF,
+                                  h->partials, h->max_blocks, &np, h->stream));
+  }
+  return reduce_to_host(h, np, dot);
+}
+
+}  // namespace
+
+extern "C" {
+
+int bltt_modes_forward(bltt_handle* h, const double* x_dev, double* xhat_dev, double* norm2) {
+  if (!h || !x_dev || !xhat_dev) return BLTT_EINVAL;
+  if (overlaps(x_dev, xhat_dev, h->n * (int64_t)sizeof(double))) return BLTT_EINVAL;
+  int rc = step_tables<double>(h);
+  if (rc) return rc;
+  int64_t np = 0;
+  if ((rc = sine_forward(h, x_dev, xhat_dev, &np))) return rc;
+  return reduce_to_host(h, np, norm2);
+}
+
+int bltt_modes_backward(bltt_handle* h, double* xhat_dev, double* x_dev) {
+  if (!h || !x_dev || !xhat_dev) return BLTT_EINVAL;
+  if (overlaps(x_dev, xhat_dev, h->n * (int64_t)sizeof(double))) return BLTT_EINVAL;
+  int rc = step_tables<double>(h);
+  if (rc) return rc;
+  if ((rc = sine_backward(h, xhat_dev, x_dev))) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return BLTT_OK;
+}
+
+int bltt_modes_sym(bltt_handle* h, int32_t precision, const void* z_dev, void* q_dev, double* dot) {
+  if (!h || !z_dev || !q_dev) return BLTT_EINVAL;
+  if (precision != BLTT_FP64 && precision != BLTT_FP32) return BLTT_EINVAL;
+  if (h->var) return BLTT_EUNSUPPORTED;
+  const int64_t bytes = h->n * (precision == BLTT_FP64 ? 8 : 4);
+  if (overlaps(z_dev, q_dev, bytes)) return BLTT_EINVAL;
+  int rc = step_tables_for(h, precision);
+  if (rc) return rc;
+  int64_t np = 0;
+  if (precision == BLTT_FP64)
+    rc = matvec<double>(h, MV_DOT, TERM_SPEC, (const double*)z_dev, (double*)q_dev, nullptr, &np);
+  else
+    rc = matvec<float>(h, MV_DOT, TERM_SPEC, (const float*)z_dev, (float*)q_dev, nullptr, &np);
+  if (rc) return rc;
+  return reduce_to_host(h, np, dot);
+}
+
+int bltt_modes_lanczos(bltt_handle* h, int32_t precision, const void* q_dev, const void* v1_dev,
+                       const void* v2_dev, const double* coef, void* vout_dev, void* zout_dev, double* dot) {
+  if (!h || !q_dev || !zout_dev) return BLTT_EINVAL;
+  if (h->var) return BLTT_EUNSUPPORTED;
+  if (precision != BLTT_FP64 && precision != BLTT_FP32 && precision != BLTT_MIXED) return BLTT_EINVAL;
+  if (precision == BLTT_MIXED && (v1_dev || v2_dev)) return BLTT_EINVAL;
+  if (h->opt.precond != BLTT_PRECOND_ABAC && precision != BLTT_FP64) return BLTT_EUNSUPPORTED;
+  const int64_t bt = h->n * (precision == BLTT_FP64 ? 8 : 4);
+  const int64_t bq = h->n * (precision == BLTT_FP32 ? 4 : 8);
+  // outputs overlap no input and not each other
+  const void* ins[3] = {q_dev, v1_dev, v2_dev};
+  const int64_t inb[3] = {bq, bt, bt};
+  for (int i = 0; i < 3; ++i) {
+    if (!ins[i]) continue;
+    if (overlaps(ins[i], inb[i], zout_dev, bt)) return BLTT_EINVAL;
+    if (vout_dev && overlaps(ins[i], inb[i], vout_dev, bt)) return BLTT_EINVAL;
+  }
+  if (vout_dev && overlaps(vout_dev, zout_dev, bt)) return BLTT_EINVAL;
+  int rc = step_tables_for(h, precision);
+  if (rc) return rc;
+  if (precision == BLTT_FP64)
+    return modes_lanczos_impl<double, double>(h, q_dev, v1_dev, v2_dev, coef, vout_dev, zout_dev, dot);
+  if (precision == BLTT_FP32)
+    return modes_lanczos_impl<float, float>(h, q_dev, v1_dev, v2_dev, coef, vout_dev, zout_dev, dot);
+  return modes_lanczos_impl<float, double>(h, q_dev, nullptr, nullptr, coef, vout_dev, zout_dev, dot);
+}
+
+int bltt_modes_resid(bltt_handle* h, const double* fhat_dev, double* u_dev, double* r_dev,
+                     const float* const* z_dev, const double* y, int32_t k, double scale, double* norm2) {
+  if (!h || !fhat_dev || !u_dev || !r_dev) return BLTT_EINVAL;
+  if (h->var) return BLTT_EUNSUPPORTED;
+  if (k < 0 || k > ZB_MAX || (k > 0 && (!z_dev || !y))) return BLTT_EINVAL;
+  const int64_t b8 = h->n * 8;
+  if (overlaps(fhat_dev, r_dev, b8) || overlaps(u_dev, r_dev, b8) || overlaps(u_dev, fhat_dev, b8))
+    return BLTT_EINVAL;
+  for (int i = 0; i < k; ++i) {
+    if (!z_dev[i]) return BLTT_EINVAL;
+    if (overlaps(z_dev[i], h->n * 4, u_dev, b8) || overlaps(z_dev[i], h->n * 4, r_dev, b8)) return BLTT_EINVAL;
+  }
+  int rc = step_tables<double>(h);
+  if (rc) return rc;
+  int64_t np = 0;
+  if (k > 0) {
+    if ((rc = upload_step(h, STEP_Y, y, k))) return rc;
+    if ((rc = upload_step(h, STEP_SCALE, &scale, 1))) return rc;
+  }
+  if (k > 0 && short_p(h)) {
+    ZList<float> zl;
+    for (int i = 0; i < ZB_MAX; ++i) zl.z[i] = i < k ? z_dev[i] : nullptr;
+    zl.k = k;
+    ProfScope ps(h, BLTT_K_WX, (16.0 + 4.0 * k) * h->n);
+    HIPCHK(launch_combine<float>(u_dev, zl, h->step_dev + STEP_Y, h->step_dev + STEP_SCALE, h->n, h->stream));
+  }
+  if (k > 0 && !short_p(h)) {
+    IterUpd up{};
+    for (int i = 0; i < ZB_MAX; ++i) up.z[i] = i < k ? z_dev[i] : nullptr;
+    up.k = k;
+    up.y = h->step_dev + STEP_Y;
+    up.s = h->step_dev + STEP_SCALE;
+    up.u_zero = 0;
+    ProfScope ps(h, BLTT_K_RESID64, (32.0 + 4.0 * k) * h->n);
+    HIPCHK(launch_matvec_fft<double>((int)(2 * h->N), MV_RESID, TERM_SPEC, u_dev, r_dev, fhat_dev, h->M,
+                                     mv_tables<double>(h), up, h->partials, h->stream));
+    np = mv_blocks<double>(true, (int)(2 * h->N), h->M);
+  } else {
+    if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, u_dev, r_dev, fhat_dev, &np))) return rc;
+  }
+  return reduce_to_host(h, np, norm2);
 }
 
 int bltt_profile_enable(bltt_handle* h, int32_t enable) {

@@ -534,9 +534,31 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
   const int nsys = b->count * b->nrhs;
   for (int s = 0; s < nsys; ++s)
     if (!f_dev[s] || !u_dev[s]) return BLTT_EINVAL;
-  // order after the caller's stream
-  hipEvent_t start = nullptr;
-  HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  {
+    // every u_dev[g] is disjoint from every f_dev and from the other u_dev
+    std::vector<int64_t> bytes((size_t)nsys, 0);
+    for (const BatchClass& c : b->cls)
+      for (int s = 0; s < c.S; ++s) bytes[(size_t)c.sys_global[(size_t)s]] = c.n * (int64_t)sizeof(double);
+    auto olap = [](const void* a, int64_t na, const void* c, int64_t nc) {
+      const char* pa = (const char*)a;
+      const char* pc = (const char*)c;
+      return pa < pc + nc && pc < pa + na;
+    };
+    for (int g = 0; g < nsys; ++g)
+      for (int k = 0; k < nsys; ++k) {
+        if (olap(u_dev[g], bytes[(size_t)g], f_dev[k], bytes[(size_t)k])) return BLTT_EINVAL;
+        if (k != g && olap(u_dev[g], bytes[(size_t)g], u_dev[k], bytes[(size_t)k])) return BLTT_EINVAL;
+      }
+  }
+  // order after the caller's stream; the event is released on every exit path
+  struct EventGuard {
+    hipEvent_t e = nullptr;
+    ~EventGuard() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  } start_guard;
+  HIPCHK(hipEventCreateWithFlags(&start_guard.e, hipEventDisableTiming));
+  hipEvent_t start = start_guard.e;
   HIPCHK(hipEventRecord(start, b->stream));
   std::vector<std::vector<SysRun>> runs(b->cls.size());
   std::vector<int> step(b->cls.size(), ST_START), pos(b->cls.size(), 0);
@@ -732,7 +754,6 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
     }
   }
   HIPCHK(hipStreamSynchronize(b->stream));
-  (void)hipEventDestroy(start);
   const double ms = now_ms() - t0;
   if (info)
     for (int g = 0; g < nsys; ++g) info[g].solve_ms = ms;

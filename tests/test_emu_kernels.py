@@ -148,3 +148,37 @@ def test_split_residual(kind, dim, m, N):
     ref = O.time_reverse(f.reshape(N, -1) - O.bltt_apply(sysm, u)).ravel()
     assert rel(r, ref) < 1e-12
     assert abs(s - np.dot(ref, ref)) < 1e-10 * np.dot(ref, ref)
+
+
+def test_scalar_kernel_flags_breakdown_and_nan():
+    """The scalar kernel's checks that bltt_pminres turns into BLTT_EBREAKDOWN
+    (status -4: <b, P^{-1} b> <= 0 at the start, <vhat, P^{-1} vhat> < 0 later,
+    i.e. P not SPD in floating point) and BLTT_ENAN (status -3), forced from
+    the host with the partial sums the reduction would have produced."""
+    SC_START, SC_DELTA, SC_BETA = E.State.SC_START, E.State.SC_DELTA, E.State.SC_BETA
+    st = E.State()
+    st.scalar(SC_START, -1.0)
+    assert st.status == -4
+    st = E.State()
+    st.scalar(SC_START, 0.0)
+    assert st.status == -4
+    st = E.State()
+    st.scalar(SC_START, 4.0)
+    assert st.status == 0 and st.eta0 == 2.0
+    st.scalar(SC_DELTA, 0.5)
+    assert st.status == 0
+    st.scalar(SC_BETA, -1e-3)
+    assert st.status == -4
+    st = E.State()
+    st.scalar(SC_START, float("nan"))
+    assert st.status == -3
+    st = E.State()
+    st.scalar(SC_START, 1.0)
+    st.scalar(SC_DELTA, float("nan"))
+    assert st.status == -3
+    # a zero beta is the happy breakdown: exact convergence, status 1
+    st = E.State()
+    st.scalar(SC_START, 1.0)
+    st.scalar(SC_DELTA, 1.0)
+    st.scalar(SC_BETA, 0.0)
+    assert st.status == 1

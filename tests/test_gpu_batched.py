@@ -59,7 +59,7 @@ def test_batched_matches_oracle_and_single():
     for g, (sysm, f, ustar) in enumerate(refs):
         u = us[g].cpu().numpy()
         assert infos[g]["true_relres"] <= 1e-8, (g, infos[g])
-        assert relnorm(u, ustar) < 1e-7, (g, relnorm(u, ustar))
+        assert relnorm(u, ustar) <= 1e-8, (g, relnorm(u, ustar))
         assert np.array_equal(u, us2[g].cpu().numpy()) and iters[g] == iters2[g]
         assert hists[g][0] == 1.0 and np.all(np.isfinite(hists[g]))
     # the same instance solved alone by the single-system mixed path
@@ -89,7 +89,7 @@ def test_batched_zero_rhs():
     assert iters[0] == 0 and float(us[0].abs().max()) == 0.0
     sysm = O.from_problem(probs[1])
     ref = O.exact_solve(sysm, fs[1].cpu().numpy()).ravel()
-    assert relnorm(us[1].cpu().numpy(), ref) < 1e-7
+    assert relnorm(us[1].cpu().numpy(), ref) <= 1e-8
 
 
 def test_batched_uneven_full_size():
@@ -130,5 +130,28 @@ def test_batched_uneven_full_size():
         modes = [0, probs[i].M - 1] + list(rng.integers(0, probs[i].M, 3))
         got = O.project_modes(sysm, u, modes)
         ref = O.exact_modes(sysm, f, modes)
-        err = np.linalg.norm(got - ref, axis=0).max() / np.linalg.norm(u)
-        assert err < 1e-7, ((m, N), err)
+        # each sampled mode against its own exact norm
+        err = float((np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)).max())
+        print(f"  class m={m} N={N} system {gsys}: per-mode err max {err:.2e}", flush=True)
+        assert err <= 1e-8, ((m, N), err)
+
+
+def test_batched_rejects_aliased_outputs():
+    probs = [W.fractional_l1(2, 7, 16, 0.5, 0.01), W.fractional_l1(2, 15, 16, 0.5, 0.01)]
+    fs = [torch.from_numpy(W.rhs_normal(pr, 3)).cuda() for pr in probs]
+    b = bltt.Batch(probs, 1)
+    try:
+        # u equal to an f, u overlapping another system's f, two systems sharing one u
+        big = torch.empty(probs[1].n, dtype=torch.float64, device="cuda")
+        cases = [[fs[0], torch.empty_like(fs[1])],
+                 [torch.empty_like(fs[0]), fs[1]],
+                 [big[: probs[0].n], big]]
+        for us in cases:
+            with pytest.raises(bltt.BlttError) as ei:
+                b.pminres(fs, 1e-8, 50, us)
+            assert ei.value.code == -1
+        us = [torch.empty_like(f) for f in fs]
+        _, _, _, _, rc = b.pminres(fs, 1e-8, 50, us)
+        assert rc == bltt.OK
+    finally:
+        b.close()

@@ -1,0 +1,248 @@
+"""GPU parity of the sine-coordinate kernels (the default solve's hot path)
+through their step entry points, against the oracle's per-mode operators.
+
+In the sine basis every block p_k I + q_k L_h is diagonal in space
+(Remark 1): mode i sees the scalar lower-triangular Toeplitz matrix T_i, and
+P_alpha^{-1} acts on each mode's time line alone (Section 5.1, Step 2).  The
+kernels keep vectors mode-major (element (i, n) at i*N + n).
+
+Two kinds of check:
+  * whole vectors, element by element, at sizes the oracle finishes in
+    seconds: several tiles and a ragged tail (odd M, so the last pair of
+    modes has one member), N = 1024 (the bench's time-pass, N-point matvec
+    and 2N-point residual instantiations) and m = 511 (the bench's 1024-point
+    sine-transform instantiations);
+  * the bench workload itself (2D, M = 511^2, N = 1024) in the same launch
+    configuration, on sampled mode lines (and sampled time slices for the
+    inverse transform) that the oracle computes one by one.
+Every error is normalised per mode line (by that line's own largest
+reference value), so small high modes are held to the same relative bar as
+large low ones.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bltt_oracle as O
+from paper_2307_07749_amd import bltt
+from paper_2307_07749_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def line_err(got, ref):
+    """max over lines of max|got - ref| / max|ref| within the line (rows)."""
+    got = np.asarray(got, np.float64).reshape(ref.shape)
+    den = np.maximum(np.abs(ref).max(axis=1), 1e-300)
+    return float((np.abs(got - ref).max(axis=1) / den).max())
+
+
+def tol_time(dtype, N, alpha):
+    """Rounding of the time pass, relative to each line's largest value:
+    D^{-1} = diag(alpha^{-n/N}) enters twice, so errors grow like
+    eps log2(N) / alpha^2 in FP64, with a factor 8 for the four transforms
+    and a margin of two; FP32 uses the bar the kernel emulator tests derive
+    (5e-5 / sqrt(alpha))."""
+    if dtype == torch.float64:
+        return max(1e-11, 8 * 2.2e-16 * math.log2(max(N, 2)) / alpha ** 2)
+    return 5e-5 / math.sqrt(alpha)
+
+
+TOL_MV = {torch.float64: 1e-12, torch.float32: 2e-5}
+
+
+def prob_of(kind, dim, m, N, alpha, gamma=0.3):
+    return {"frac": lambda: W.fractional_l1(dim, m, N, gamma, alpha),
+            "heat": lambda: W.heat_bdf(dim, m, N, alpha),
+            "cn": lambda: W.heat_cn(dim, m, N, alpha)}[kind]()
+
+
+def cuda(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+# kind, dim, m, N, alpha: N = 1024 and m = 511 are the bench workload's kernel
+# instantiations; odd M (ragged last mode pair), N = 2 and N = 2048 the size
+# limits; heat (two p taps) runs the direct short-p matvec, CN has a q tap too
+CASES = [("frac", 2, 15, 1024, 0.01), ("frac", 1, 63, 1024, 0.001),
+         ("heat", 2, 15, 64, 0.01), ("cn", 2, 7, 32, 0.2), ("frac", 3, 7, 16, 0.05), ("frac", 1, 7, 2, 0.5),
+         ("frac", 1, 3, 2048, 0.01), ("frac", 2, 511, 8, 0.01)]
+
+
+@pytest.mark.parametrize("kind,dim,m,N,alpha", CASES)
+def test_modes_steps_whole_vectors(kind, dim, m, N, alpha):
+    prob = prob_of(kind, dim, m, N, alpha)
+    print(f"[modes steps] {kind} dim={dim} m={m} N={N} alpha={alpha}", flush=True)
+    sysm = O.from_problem(prob)
+    M = prob.M
+    modes = np.arange(M)
+    rng = np.random.default_rng(N + 7 * m)
+    s = bltt.Solver.from_problem(prob, precision=bltt.MIXED)
+    try:
+        # sine transforms in and out (FP64), time-major <-> mode-major
+        x = rng.standard_normal(prob.n)
+        xhat, n2 = s.modes_forward(cuda(x, torch.float64))
+        ref = O.space_transform(x.reshape(N, M), prob.m).T            # (M, N) mode-major
+        assert line_err(xhat.cpu().numpy(), ref) < 1e-12
+        assert abs(n2 - float(x @ x)) <= 1e-12 * float(x @ x)
+        back = s.modes_backward(cuda(ref.ravel(), torch.float64)).cpu().numpy().reshape(N, M)
+        assert line_err(back, x.reshape(N, M)) < 1e-12
+
+        for dt in (torch.float64, torch.float32):
+            cast = (lambda a: a.astype(np.float32).astype(np.float64)) if dt == torch.float32 else (lambda a: a)
+            # symmetrised matvec Y T_i z_i per mode, and <q, z>
+            z = cast(rng.standard_normal((M, N)))
+            q, dq = s.modes_sym(cuda(z.ravel(), dt))
+            ref = O.mode_sym_apply(sysm, z, modes)
+            assert line_err(q.cpu().numpy(), ref) < TOL_MV[dt], ("sym", dt)
+            dref = float(np.sum(ref * z))
+            assert abs(dq - dref) <= TOL_MV[dt] * np.linalg.norm(ref) * np.linalg.norm(z), ("sym dot", dt)
+
+            # fused Lanczos update + P^{-1}: vhat = c0 q + c1 v1 + c2 v2, z = P^{-1} vhat
+            qv, v1, v2 = (cast(rng.standard_normal((M, N))) for _ in range(3))
+            coef = (0.7, -1.3, 0.4)
+            zz, vv, dot = s.modes_lanczos(cuda(qv.ravel(), dt), cuda(v1.ravel(), dt), cuda(v2.ravel(), dt), coef,
+                                          want_v=True)
+            vhat = coef[0] * qv + coef[1] * v1 + coef[2] * v2
+            assert line_err(vv.cpu().numpy(), vhat) < (4e-15 if dt == torch.float64 else 1e-6)
+            refz = O.mode_precond_apply(sysm, vhat, modes)
+            tt = tol_time(dt, N, alpha)
+            assert line_err(zz.cpu().numpy(), refz) < tt, ("lanczos", dt, line_err(zz.cpu().numpy(), refz))
+            dref = float(np.sum(vhat * refz))
+            assert abs(dot - dref) <= 10 * tt * np.linalg.norm(vhat) * np.linalg.norm(refz), ("lanczos dot", dt)
+            # start form: c0 q alone, no v output
+            z0, v0, dot0 = s.modes_lanczos(cuda(qv.ravel(), dt), coef=(2.0, 0.0, 0.0))
+            ref0 = O.mode_precond_apply(sysm, 2.0 * qv, modes)
+            assert v0 is None and line_err(z0.cpu().numpy(), ref0) < tt
+
+        # mixed sweep start: FP64 right-hand side scaled before rounding to FP32
+        r64 = rng.standard_normal((M, N)) * 3e-9
+        sc = 1.0 / np.linalg.norm(r64)
+        zm, vm, dm = s.modes_lanczos(cuda(r64.ravel(), torch.float64), coef=(sc, 0.0, 0.0), want_v=True,
+                                     dtype=torch.float32)
+        b32 = (r64 * sc).astype(np.float32).astype(np.float64)
+        assert np.array_equal(vm.cpu().numpy().astype(np.float64), b32.ravel())
+        refm = O.mode_precond_apply(sysm, b32, modes)
+        assert line_err(zm.cpu().numpy(), refm) < tol_time(torch.float32, N, alpha)
+
+        # FP64 refinement residual with the stored-basis update u += s sum_j y_j z_j
+        fh = rng.standard_normal((M, N))
+        u0 = rng.standard_normal((M, N)) * 1e-3
+        zs = [rng.standard_normal((M, N)).astype(np.float32) for _ in range(3)]
+        y = [0.5, -0.25, 0.125]
+        sc = 2.0
+        ut = cuda(u0.ravel(), torch.float64)
+        r, rn2 = s.modes_resid(cuda(fh.ravel(), torch.float64), ut, zs=[cuda(zz_.ravel(), torch.float32)
+                                                                          for zz_ in zs], y=y, scale=sc)
+        unew = u0 + sc * sum(yj * zj.astype(np.float64) for yj, zj in zip(y, zs))
+        assert line_err(ut.cpu().numpy(), unew) < 1e-14
+        refr = O.mode_residual(sysm, fh, unew, modes)
+        assert line_err(r.cpu().numpy(), refr) < 1e-11
+        assert abs(rn2 - float(np.sum(refr * refr))) <= 1e-11 * float(np.sum(refr * refr))
+        # and without the update
+        r0, _ = s.modes_resid(cuda(fh.ravel(), torch.float64), cuda(unew.ravel(), torch.float64))
+        assert line_err(r0.cpu().numpy(), refr) < 1e-11
+    finally:
+        s.close()
+
+
+def test_modes_steps_reject_overlap_and_varcoef():
+    prob = prob_of("frac", 2, 7, 16, 0.05)
+    s = bltt.Solver.from_problem(prob, precision=bltt.FP64)
+    try:
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        for fn in (lambda: s.modes_forward(x, x), lambda: s.modes_backward(x, x), lambda: s.modes_sym(x, x),
+                   lambda: s.modes_lanczos(x, z=x), lambda: s.modes_resid(x, x, x)):
+            with pytest.raises(bltt.BlttError) as ei:
+                fn()
+            assert ei.value.code == -1
+    finally:
+        s.close()
+
+
+# --------------------------------------------------------------------------
+# the bench workload (2D L1, gamma 0.3, M = 511^2, N = 1024, alpha 0.01) in
+# the bench's launch configuration, on sampled lines
+# --------------------------------------------------------------------------
+
+def sample_modes(M, rng, k=10):
+    # both members of the first pairs, a middle pair, the ragged last mode
+    return sorted(set([0, 1, 2, 3, M // 2, M // 2 + 1, M - 2, M - 1] + list(rng.integers(0, M, k))))
+
+
+def lines(t, M, N, modes):
+    return t.view(M, N)[torch.as_tensor(modes, device=t.device)].double().cpu().numpy()
+
+
+def test_modes_steps_bench_workload_sampled():
+    prob, seed = W.workload("frac2d_m511_n1024_g03")
+    sysm = O.from_problem(prob)
+    M, N = prob.M, prob.N
+    rng = np.random.default_rng(seed)
+    modes = sample_modes(M, rng)
+    print(f"[modes steps, bench workload] M={M} N={N} sampled modes {modes}", flush=True)
+    s = bltt.Solver.from_problem(prob, precision=bltt.MIXED)
+    try:
+        # FP32 N-point matvec (k_matvec_cs at N = 1024)
+        z = torch.from_numpy(rng.standard_normal(prob.n, dtype=np.float32)).cuda()
+        q, _ = s.modes_sym(z)
+        zl = lines(z, M, N, modes)
+        err = line_err(lines(q, M, N, modes), O.mode_sym_apply(sysm, zl, modes))
+        print(f"  sym fp32 line err {err:.2e}", flush=True)
+        assert err < TOL_MV[torch.float32]
+        # FP32 fused Lanczos update + time pass (persistent kernel, full form)
+        v1 = torch.from_numpy(rng.standard_normal(prob.n, dtype=np.float32)).cuda()
+        coef = (0.9, -0.6, 0.2)
+        zz, _, _ = s.modes_lanczos(q, z, v1, coef)
+        vh = coef[0] * lines(q, M, N, modes) + coef[1] * zl + coef[2] * lines(v1, M, N, modes)
+        err = line_err(lines(zz, M, N, modes), O.mode_precond_apply(sysm, vh, modes))
+        print(f"  lanczos fp32 line err {err:.2e}", flush=True)
+        assert err < tol_time(torch.float32, N, prob.alpha)
+        del q, z, v1, zz
+        # mixed sweep start on an FP64 right-hand side read reversed-free
+        r64 = torch.from_numpy(rng.standard_normal(prob.n)).cuda()
+        zm, _, _ = s.modes_lanczos(r64, coef=(0.5, 0.0, 0.0), dtype=torch.float32)
+        b32 = (0.5 * lines(r64, M, N, modes)).astype(np.float32).astype(np.float64)
+        err = line_err(lines(zm, M, N, modes), O.mode_precond_apply(sysm, b32, modes))
+        print(f"  lanczos mixed-start line err {err:.2e}", flush=True)
+        assert err < tol_time(torch.float32, N, prob.alpha)
+        # FP64 2N-point residual with the refinement update (k = 3 stored vectors)
+        zs = [zm, torch.from_numpy(rng.standard_normal(prob.n, dtype=np.float32)).cuda(),
+              torch.from_numpy(rng.standard_normal(prob.n, dtype=np.float32)).cuda()]
+        u = torch.from_numpy(rng.standard_normal(prob.n) * 1e-6).cuda()
+        ul = lines(u, M, N, modes)
+        y = [1.5, -0.5, 0.25]
+        r, _ = s.modes_resid(r64, u, zs=zs, y=y, scale=0.75)
+        unew = ul + 0.75 * sum(yj * lines(zj, M, N, modes) for yj, zj in zip(y, zs))
+        assert line_err(lines(u, M, N, modes), unew) < 1e-14
+        err = line_err(lines(r, M, N, modes), O.mode_residual(sysm, lines(r64, M, N, modes), unew, modes))
+        print(f"  resid fp64 line err {err:.2e}", flush=True)
+        assert err < 1e-11
+        del zs, zm, u, r, r64
+        # FP64 sine transforms in (sampled modes) and out (sampled time slices)
+        x = rng.standard_normal(prob.n)
+        xh, _ = s.modes_forward(cuda(x, torch.float64))
+        ref = O.project_modes(sysm, x, modes).T
+        err = line_err(lines(xh, M, N, modes), ref)
+        print(f"  forward transform line err {err:.2e}", flush=True)
+        assert err < 1e-12
+        xhat = x.reshape(M, N)          # reuse the draw as a mode-major input
+        xt = s.modes_backward(cuda(xhat.ravel(), torch.float64)).view(N, M)
+        for n in (0, 1, 511, N - 1):
+            ref = O.space_transform(xhat[:, n][None, :], prob.m)
+            err = line_err(xt[n].cpu().numpy()[None, :], ref)
+            assert err < 1e-12, (n, err)
+    finally:
+        s.close()

@@ -85,6 +85,10 @@ SOLVE_CASES = [("frac", 1, 31, 32, 0.01, 1e-10), ("heat", 2, 15, 32, 0.01, 1e-10
 BASES = [bltt.SINE, bltt.PHYSICAL]
 
 
+# accuracy targets of the two paths: relative 2-norm error against u* = A^{-1} f
+ERR_FP64, ERR_MIXED = 1e-10, 1e-8
+
+
 @pytest.mark.parametrize("basis", BASES)
 @pytest.mark.parametrize("kind,dim,m,N,alpha,tol", SOLVE_CASES)
 def test_fp64_solve_matches_oracle(kind, dim, m, N, alpha, tol, basis):
@@ -94,7 +98,9 @@ def test_fp64_solve_matches_oracle(kind, dim, m, N, alpha, tol, basis):
     f = W.rhs_normal(prob, 11)
     ustar = O.exact_solve(sysm, f).ravel()
     ores = O.pminres(sysm, f, tol, 100)
-    s = bltt.Solver.from_problem(prob, precision=bltt.FP64, basis=basis)
+    # the explicit residual after every iteration (check_factor beyond any
+    # |eta| ratio), which is the oracle's stopping test: same iteration count
+    s = bltt.Solver.from_problem(prob, precision=bltt.FP64, basis=basis, check_factor=1e30)
     try:
         ft = cuda(f, torch.float64)
         u, iters, hist, info, rc = s.pminres(ft, tol, 100)
@@ -112,9 +118,10 @@ def test_fp64_solve_matches_oracle(kind, dim, m, N, alpha, tol, basis):
     # same Krylov iteration: identical residual-estimate history
     k = min(len(hist), len(ores.eta_hist))
     assert np.allclose(hist[:k], ores.eta_hist[:k], rtol=1e-6, atol=1e-13)
-    # the GPU confirms with the true residual only after |eta| drops: never earlier than the oracle
-    assert ores.iters <= iters <= ores.iters + 3
-    assert relnorm(u, ustar) < 10 * tol
+    assert iters == ores.iters, (iters, ores.iters)
+    err = relnorm(u, ustar)
+    print(f"  iters={iters} relres={info['true_relres']:.2e} err={err:.2e}", flush=True)
+    assert err <= ERR_FP64
 
 
 # N = 2048: the FP32 N-point matvec reads its tables from global memory (too
@@ -140,7 +147,9 @@ def test_mixed_solve_matches_exact(kind, dim, m, N, alpha, basis):
     assert rc == bltt.OK, info
     assert info["true_relres"] <= 1e-8
     assert info["iters_outer"] >= 1
-    assert relnorm(u, ustar) < 1e-7
+    err = relnorm(u, ustar)
+    print(f"  iters={iters} outer={info['iters_outer']} relres={info['true_relres']:.2e} err={err:.2e}", flush=True)
+    assert err <= ERR_MIXED
 
 
 @pytest.mark.parametrize("basis", BASES)
@@ -178,7 +187,7 @@ def test_named_workloads_fp64(name):
     err = relnorm(u, ustar)
     print(f"  iters={iters} relres={info['true_relres']:.3e} err={err:.3e}", flush=True)
     assert rc == bltt.OK
-    assert err < 1e-9
+    assert err <= ERR_FP64
 
 
 FULL_CASES = [("frac2d_m511_n1024_g03", bltt.MIXED, bltt.SINE), ("frac2d_m511_n1024_g03", bltt.FP64, bltt.SINE),
@@ -189,9 +198,12 @@ FULL_CASES = [("frac2d_m511_n1024_g03", bltt.MIXED, bltt.SINE), ("frac2d_m511_n1
 @pytest.mark.parametrize("name,precision,basis", FULL_CASES)
 def test_full_size_sampled(name, precision, basis):
     """Full-size workloads (2D: M = 511^2, N = 1024, gamma 0.3 / 0.7; 3D:
-    M = 127^3, N = 256, gamma 0.5) at tol 1e-8: sampled sine-mode projections
-    of u against the oracle's per-mode exact solution."""
-    tol = 1e-8
+    M = 127^3, N = 256, gamma 0.5): sampled sine-mode projections of u
+    against the oracle's per-mode exact solution, each mode's error relative
+    to that mode's own exact norm.  Mixed solves run to 1e-8 and are held to
+    1e-8; FP64 solves run to 1e-10 and are held to 1e-10."""
+    tol = 1e-8 if precision == bltt.MIXED else 1e-10
+    bar = ERR_MIXED if precision == bltt.MIXED else ERR_FP64
     prob, seed = W.workload(name)
     print(f"[full size] {name} precision={precision} basis={basis}", flush=True)
     sysm = O.from_problem(prob)
@@ -210,8 +222,66 @@ def test_full_size_sampled(name, precision, basis):
     modes = [0, 1, 511, prob.M - 1] + list(rng.integers(0, prob.M, 4))
     got = O.project_modes(sysm, u, modes)
     ref = O.exact_modes(sysm, f, modes)
-    # every mode's error is bounded by the global error ||u - u*|| <= c tol ||u*||
-    err = np.linalg.norm(got - ref, axis=0).max() / np.linalg.norm(u)
-    print(f"  iters={iters} outer={info['iters_outer']} relres={info['true_relres']:.3e} mode-err={err:.3e} "
+    errs = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    err = float(errs.max())
+    print(f"  iters={iters} outer={info['iters_outer']} relres={info['true_relres']:.3e} "
+          f"per-mode err max={err:.3e} (modes {modes}: {np.array2string(errs, precision=2)}) "
           f"solve_ms={info['solve_ms']:.1f}", flush=True)
-    assert err < 10 * tol
+    assert err <= bar
+
+
+@pytest.mark.parametrize("basis", BASES)
+@pytest.mark.parametrize("precision", [bltt.FP64, bltt.MIXED])
+def test_initial_guess(basis, precision):
+    """bltt_pminres from a caller's initial guess (opt.initial_guess = 1): the
+    exact solution needs no iteration; a perturbed one converges to the oracle's
+    u*, in FP64 with the oracle's own iteration count from the same guess."""
+    prob = prob_of("frac", 2, 15, 64, 0.01, gamma=0.3)
+    print(f"[initial guess] precision={precision} basis={basis}", flush=True)
+    sysm = O.from_problem(prob)
+    f = W.rhs_normal(prob, 21)
+    ustar = O.exact_solve(sysm, f).ravel()
+    tol, bar = (1e-10, ERR_FP64) if precision == bltt.FP64 else (1e-8, ERR_MIXED)
+    s = bltt.Solver.from_problem(prob, precision=precision, basis=basis, initial_guess=True, check_factor=1e30)
+    s0 = bltt.Solver.from_problem(prob, precision=precision, basis=basis, check_factor=1e30)
+    try:
+        ft = cuda(f, torch.float64)
+        u, iters, hist, info, rc = s.pminres(ft, tol, 100, cuda(ustar, torch.float64))
+        assert rc == bltt.OK and iters == 0 and info["true_relres"] <= tol
+        assert relnorm(u.cpu().numpy(), ustar) <= 1e-12
+        guess = ustar + 1e-3 * np.linalg.norm(ustar) / math.sqrt(prob.n) * \
+            np.random.default_rng(2).standard_normal(prob.n)
+        u, iters, hist, info, rc = s.pminres(ft, tol, 100, cuda(guess, torch.float64))
+        err = relnorm(u.cpu().numpy(), ustar)
+        _, iters0, _, _, _ = s0.pminres(ft, tol, 100)
+        print(f"  from the guess: iters={iters} err={err:.2e}; from zero: iters={iters0}", flush=True)
+        assert rc == bltt.OK and info["true_relres"] <= tol and err <= bar
+        assert iters <= iters0
+        if precision == bltt.FP64:
+            ores = O.pminres(sysm, f, tol, 100, x0=guess)
+            assert iters == ores.iters
+        # f = 0 returns u = 0 whatever the guess
+        z = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        u, iters, _, _, rc = s.pminres(z, tol, 100, cuda(guess, torch.float64))
+        assert rc == bltt.OK and iters == 0 and float(u.abs().max()) == 0.0
+    finally:
+        s.close()
+        s0.close()
+
+
+@pytest.mark.parametrize("basis", BASES)
+def test_aliased_f_and_u_rejected(basis):
+    prob = prob_of("frac", 2, 7, 16, 0.01)
+    s = bltt.Solver.from_problem(prob, precision=bltt.FP64, basis=basis)
+    try:
+        buf = torch.zeros(2 * prob.n, dtype=torch.float64, device="cuda")
+        f = buf[: prob.n]
+        for u in (f, buf[prob.n // 2: prob.n // 2 + prob.n]):
+            with pytest.raises(bltt.BlttError) as ei:
+                s.pminres(f, 1e-8, 10, u)
+            assert ei.value.code == -1
+        # disjoint halves are fine
+        _, _, _, _, rc = s.pminres(f, 1e-8, 10, buf[prob.n:])
+        assert rc == bltt.OK
+    finally:
+        s.close()

@@ -372,3 +372,50 @@ def test_exact_modes_match_full_exact_solution():
     # mode vectors are rows of the full transform
     U = oracle_matrix(lambda e: O.space_transform(e[None, :], sysm.ms)[0], sysm.M)
     assert np.allclose(O.mode_vectors(sysm, modes), U[modes], atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# sine-coordinate (per-mode) operators against the dense matrices of
+# eqs. (3)-(5) restricted to one sine mode (Remark 1)
+# ---------------------------------------------------------------------------
+
+def _mode_embed(sysm, i):
+    """X = I_N (x) u_i (NM x N), u_i the i-th orthonormal sine vector: a time
+    line of mode i placed in the time-major physical layout."""
+    return np.kron(np.eye(sysm.N), O.mode_vectors(sysm, [i])[0][:, None])
+
+
+@pytest.mark.parametrize("kind,alpha,dim", [("frac", 0.1, 1), ("heat", 0.01, 2), ("cn", 0.2, 2),
+                                            ("frac", 0.001, 1), ("frac", 1.0, 2)])
+def test_mode_operators_match_dense_restrictions(kind, alpha, dim):
+    m = 5 if dim == 1 else 3
+    sysm = tiny(kind, dim=dim, m=m, N=8, alpha=alpha)
+    A = dense_A(sysm)
+    Y = dense_Y(sysm.N, sysm.M)
+    Pinv = dense_Pinv(dense_C(sysm, alpha)).real
+    rng = np.random.default_rng(3)
+    for i in (0, 2, sysm.M - 1):
+        X = _mode_embed(sysm, i)
+        # Y A and P^{-1} map mode i's lines into mode i: X X^T (.) X = (.) X
+        assert np.allclose(X @ (X.T @ (Y @ A @ X)), Y @ A @ X, atol=1e-10 * np.abs(A).max())
+        assert np.allclose(X @ (X.T @ (Pinv @ X)), Pinv @ X, atol=1e-10 * np.abs(Pinv).max())
+        Ks = X.T @ Y @ A @ X
+        Ps = X.T @ Pinv @ X
+        Z = rng.standard_normal((2, sysm.N))
+        got = O.mode_sym_apply(sysm, Z, [i, i])
+        assert np.allclose(got, Z @ Ks.T, rtol=1e-12, atol=1e-12 * np.abs(Ks).max())
+        got = O.mode_precond_apply(sysm, Z, [i, i])
+        assert np.allclose(got, Z @ Ps.T, rtol=1e-10, atol=1e-10 * np.abs(Ps).max())
+        Fh, Uh = rng.standard_normal((2, 1, sysm.N))
+        r = O.mode_residual(sysm, Fh, Uh, [i])[0]
+        assert np.allclose(r, X.T @ (Y @ (X @ Fh[0] - A @ (X @ Uh[0]))), atol=1e-10 * np.abs(A).max())
+
+
+def test_mode_residual_vanishes_at_exact_modes():
+    sysm = tiny("frac", dim=2, m=7, N=16, alpha=0.05)
+    f = np.random.default_rng(4).standard_normal(sysm.N * sysm.M)
+    modes = [0, 9, sysm.M - 1]
+    Fh = O.project_modes(sysm, f, modes).T
+    Uh = O.exact_modes(sysm, f, modes).T
+    r = O.mode_residual(sysm, Fh, Uh, modes)
+    assert np.abs(r).max() < 1e-12 * np.abs(Fh).max()
