@@ -264,6 +264,31 @@ int bltt_modes_resid(bltt_handle *h, const double *fhat_dev, double *u_dev, doub
                      const float *const *z_dev, const double *y, int32_t k, double scale, double *norm2);
 
 /*
+ * bltt_modes_lanczos_noalloc -- bltt_modes_lanczos for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): same arguments, same kernels, same
+ * results, and no hipMalloc, hipFree or other allocating call.  Its partial
+ * sums, their reduction, the coefficients and the reduced <vhat, zout> live in
+ * a static device array of the library, one per GPU (about 130 KiB, held
+ * until the process ends); the caller passes inputs and outputs.
+ *   - The handle must already hold the tables of `precision` (built by
+ *     bltt_setup for its own precision, FP64 tables always; or by one call of
+ *     bltt_modes_lanczos): otherwise BLTT_EINVAL.
+ *   - At most 16384 partial sums per launch: FP32 and mixed always fit (one
+ *     per persistent workgroup); FP64 fits when ceil(M / (2 NL)) <= 16384,
+ *     NL = 256 / (N / min(N, 16)) mode-line pairs per workgroup (e.g. M up to
+ *     131072 at N = 1024).  Larger systems give BLTT_EUNSUPPORTED.
+ *   - Every call on one GPU uses that GPU's array, whatever the handle; calls
+ *     that overlap in time on one GPU (other host threads, other streams) race
+ *     and must be serialised by the caller.  Nothing in the array needs to
+ *     start at zero: each call writes what it reads.
+ * Errors: as bltt_modes_lanczos.
+ */
+int bltt_modes_lanczos_noalloc(bltt_handle *h, int32_t precision, const void *q_dev, const void *v1_dev,
+                               const void *v2_dev, const double *coef, void *vout_dev, void *zout_dev,
+                               double *dot);
+
+/*
  * Per-kernel timing of the hot path.  While enabled, every kernel launch the
  * handle makes is bracketed by HIP events on the handle's stream and its
  * algorithmic traffic (bytes the step must read and write at least once,

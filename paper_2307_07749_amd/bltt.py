@@ -86,9 +86,10 @@ def load() -> ctypes.CDLL:
     L.bltt_modes_backward.argtypes = [P, P, P]
     L.bltt_modes_sym.argtypes = [P, ctypes.c_int32, P, P, D]
     L.bltt_modes_lanczos.argtypes = [P, ctypes.c_int32, P, P, P, D, P, P, D]
+    L.bltt_modes_lanczos_noalloc.argtypes = [P, ctypes.c_int32, P, P, P, D, P, P, D]
     L.bltt_modes_resid.argtypes = [P, P, P, P, ctypes.POINTER(P), D, ctypes.c_int32, ctypes.c_double, D]
     for name in ("bltt_modes_forward", "bltt_modes_backward", "bltt_modes_sym", "bltt_modes_lanczos",
-                 "bltt_modes_resid"):
+                 "bltt_modes_lanczos_noalloc", "bltt_modes_resid"):
         getattr(L, name).restype = ctypes.c_int
     L.bltt_profile_enable.argtypes = [P, ctypes.c_int32]
     L.bltt_profile_enable.restype = ctypes.c_int
@@ -288,23 +289,37 @@ class Solver:
         _check(self._L.bltt_modes_sym(self._h, prec, zp, self._vec(q, z.dtype), ctypes.byref(dot)))
         return q, float(dot.value)
 
-    def modes_lanczos(self, q, v1=None, v2=None, coef=(1.0, 0.0, 0.0), z=None, want_v=False, dtype=None):
+    def modes_lanczos(self, q, v1=None, v2=None, coef=(1.0, 0.0, 0.0), z=None, want_v=False, dtype=None,
+                      noalloc=False, v=None):
         """vhat = coef[0] q + coef[1] v1 + coef[2] v2, z = P^{-1} vhat per mode.
         dtype: precision of v1/v2/outputs (default q's; float32 with a
-        float64 q is the mixed sweep start).  Returns (z, vhat or None, <vhat, z>)."""
+        float64 q is the mixed sweep start).  noalloc: through
+        bltt_modes_lanczos_noalloc (outputs z and, with want_v, v must then be
+        passed in).  Returns (z, vhat or None, <vhat, z>)."""
+        import torch
+        if noalloc:
+            if z is None or (want_v and v is None):
+                raise ValueError("the no-alloc entry point takes its output tensors from the caller")
+            return self._modes_lanczos_call("bltt_modes_lanczos_noalloc", q, v1, v2, coef, z, v if want_v else None,
+                                            dtype)
+        dt = dtype or q.dtype
+        if z is None:
+            z = torch.empty(q.numel(), dtype=dt, device=q.device)
+        if want_v and v is None:
+            v = torch.empty(q.numel(), dtype=dt, device=q.device)
+        return self._modes_lanczos_call("bltt_modes_lanczos", q, v1, v2, coef, z, v if want_v else None, dtype)
+
+    def _modes_lanczos_call(self, name, q, v1, v2, coef, z, v, dtype):
         import torch
         dt = dtype or q.dtype
         prec = FP64 if dt == torch.float64 else (MIXED if q.dtype == torch.float64 else FP32)
         qp = self._vec(q, q.dtype)
         v1p = self._vec(v1, dt) if v1 is not None else None
         v2p = self._vec(v2, dt) if v2 is not None else None
-        if z is None:
-            z = torch.empty(q.numel(), dtype=dt, device=q.device)
-        v = torch.empty(q.numel(), dtype=dt, device=q.device) if want_v else None
         c = (ctypes.c_double * 4)(*[float(x) for x in coef], 0.0)
         dot = ctypes.c_double(0.0)
-        _check(self._L.bltt_modes_lanczos(self._h, prec, qp, v1p, v2p, c, self._vec(v, dt) if v is not None else None,
-                                          self._vec(z, dt), ctypes.byref(dot)))
+        _check(getattr(self._L, name)(self._h, prec, qp, v1p, v2p, c, self._vec(v, dt) if v is not None else None,
+                                      self._vec(z, dt), ctypes.byref(dot)))
         return z, v, float(dot.value)
 
     def modes_resid(self, fhat, u, r=None, zs=(), y=(), scale=1.0):

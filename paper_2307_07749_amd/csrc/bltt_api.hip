@@ -21,6 +21,53 @@
 
 using namespace bltt;
 
+// ---------------------------------------------------------------------------
+// Device scratch of bltt_modes_lanczos_noalloc, one copy per GPU (a static
+// device array is instantiated on every device the library runs on and holds
+// it until the process ends).  Layout in doubles: per-workgroup partial sums,
+// the first stage of their reduction, the step's coefficients, the scalar
+// state the reduction writes.  Host code uses the address hipGetSymbolAddress
+// returns for the current device, never the array's name.
+// ---------------------------------------------------------------------------
+namespace scr {
+constexpr int64_t PARTS = 16384;    // partial sums of one launch, at most
+constexpr int64_t RED_HALF = 32;    // first reduction stage: 2 * RED_HALF doubles
+constexpr int64_t RED = PARTS;
+constexpr int64_t COEF = RED + 2 * RED_HALF;
+constexpr int64_t STATE = COEF + 8;
+constexpr int64_t LEN = STATE + (int64_t)((sizeof(SolverState) + 7) / 8);
+}  // namespace scr
+
+static __device__ __align__(256) double scratch[scr::LEN];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// this device's copy of `scratch` (dev must be the current device); resolved
+// once per device
+int scratch_init(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= MAX_DEVICES) return BLTT_EHIP;
+  if (g_scratch_ptr[dev]) return BLTT_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return BLTT_EHIP;
+  }
+  g_scratch_ptr[dev] = static_cast<double*>(p);
+  return BLTT_OK;
+}
+
+double* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return dev >= 0 && dev < MAX_DEVICES ? g_scratch_ptr[dev] : nullptr;
+}
+
+}  // namespace
+
 namespace {
 
 template <typename T>
@@ -65,6 +112,7 @@ constexpr int STEP_COEF = 0, STEP_SCALE = 4, STEP_Y = 8, STEP_LEN = STEP_Y + ZB_
 
 struct bltt_handle {
   hipStream_t stream = nullptr;
+  int device = 0;  // device current at setup (its scratch copy serves the no-alloc entry point)
   int dim = 0;
   int m[3] = {1, 1, 1};
   double h[3] = {1, 1, 1};
@@ -925,6 +973,11 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
       return BLTT_EHIP;
     }
     h->max_blocks = 4 * (int64_t)cus;
+    h->device = dev;
+    if (scratch_init(dev) != BLTT_OK) {
+      delete h;
+      return BLTT_EHIP;
+    }
   }
   if (g_config_err != hipSuccess) {
     delete h;
@@ -1439,8 +1492,13 @@ int bltt_modes_sym(bltt_handle* h, int32_t precision, const void* z_dev, void* q
   return reduce_to_host(h, np, dot);
 }
 
-int bltt_modes_lanczos(bltt_handle* h, int32_t precision, const void* q_dev, const void* v1_dev,
-                       const void* v2_dev, const double* coef, void* vout_dev, void* zout_dev, double* dot) {
+}  // extern "C"
+
+namespace {
+
+// argument checks shared by bltt_modes_lanczos and its no-alloc variant
+int lanczos_args(const bltt_handle* h, int32_t precision, const void* q_dev, const void* v1_dev, const void* v2_dev,
+                 const void* vout_dev, const void* zout_dev) {
   if (!h || !q_dev || !zout_dev) return BLTT_EINVAL;
   if (h->var) return BLTT_EUNSUPPORTED;
   if (precision != BLTT_FP64 && precision != BLTT_FP32 && precision != BLTT_MIXED) return BLTT_EINVAL;
@@ -1457,7 +1515,62 @@ int bltt_modes_lanczos(bltt_handle* h, int32_t precision, const void* q_dev, con
     if (vout_dev && overlaps(ins[i], inb[i], vout_dev, bt)) return BLTT_EINVAL;
   }
   if (vout_dev && overlaps(vout_dev, zout_dev, bt)) return BLTT_EINVAL;
-  int rc = step_tables_for(h, precision);
+  return BLTT_OK;
+}
+
+// the launch of bltt_modes_lanczos_noalloc: coefficients, partial sums,
+// reduction and scalar state in this device's scratch
+template <typename T, typename TQ>
+int lanczos_noalloc_impl(bltt_handle* h, double* scr_dev, const void* q, const void* v1, const void* v2,
+                         const double* coef, void* vout, void* zout, double* dot) {
+  const bool full = v1 || v2;
+  const double c[4] = {coef ? coef[0] : 1.0, coef && v1 ? coef[1] : 0.0, coef && v2 ? coef[2] : 0.0, 0.0};
+  const T* V1 = (const T*)(v1 ? v1 : v2);
+  const T* V2 = (const T*)(v2 ? v2 : V1);
+  HIPCHK(hipMemcpyAsync(scr_dev + scr::COEF, c, sizeof(c), hipMemcpyHostToDevice, h->stream));
+  int64_t np = 0;
+  HIPCHK(launch_time_upd<T, TQ>((int)h->N, full, h->opt.precond == BLTT_PRECOND_ABAC, (const TQ*)q, V1, V2, (T*)vout,
+                                (T*)zout, h->M, time_tables<T>(h, false), scr_dev + scr::COEF, scr_dev, h->max_blocks,
+                                &np, h->stream));
+  SolverState* st = reinterpret_cast<SolverState*>(scr_dev + scr::STATE);
+  HIPCHK(launch_scalar(SC_NORM, st, scr_dev, np, nullptr, 0, nullptr, scr_dev + scr::RED, scr::RED_HALF, ZBasis{},
+                       h->stream));
+  HIPCHK(hipMemcpyAsync(&h->state_host->norm2, &st->norm2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (dot) *dot = h->state_host->norm2;
+  return BLTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bltt_modes_lanczos_noalloc(bltt_handle* h, int32_t precision, const void* q_dev, const void* v1_dev,
+                               const void* v2_dev, const double* coef, void* vout_dev, void* zout_dev,
+                               double* dot) {
+  int rc = lanczos_args(h, precision, q_dev, v1_dev, v2_dev, vout_dev, zout_dev);
+  if (rc) return rc;
+  // the tables must exist already: building them would allocate
+  const bool ready = precision == BLTT_FP64 ? h->t64.ready
+                                            : (precision == BLTT_FP32 ? h->t32.ready : h->t32.ready && h->t64.ready);
+  if (!ready) return BLTT_EINVAL;
+  const int64_t np = precision == BLTT_FP64 ? upd_blocks<double>((int)h->N, h->M, h->max_blocks)
+                                            : upd_blocks<float>((int)h->N, h->M, h->max_blocks);
+  if (np > scr::PARTS) return BLTT_EUNSUPPORTED;
+  double* scr_dev = scratch_ptr(h->device);
+  if (!scr_dev) return BLTT_EHIP;
+  if (precision == BLTT_FP64)
+    return lanczos_noalloc_impl<double, double>(h, scr_dev, q_dev, v1_dev, v2_dev, coef, vout_dev, zout_dev, dot);
+  if (precision == BLTT_FP32)
+    return lanczos_noalloc_impl<float, float>(h, scr_dev, q_dev, v1_dev, v2_dev, coef, vout_dev, zout_dev, dot);
+  return lanczos_noalloc_impl<float, double>(h, scr_dev, q_dev, nullptr, nullptr, coef, vout_dev, zout_dev, dot);
+}
+
+int bltt_modes_lanczos(bltt_handle* h, int32_t precision, const void* q_dev, const void* v1_dev,
+                       const void* v2_dev, const double* coef, void* vout_dev, void* zout_dev, double* dot) {
+  int rc = lanczos_args(h, precision, q_dev, v1_dev, v2_dev, vout_dev, zout_dev);
+  if (rc) return rc;
+  rc = step_tables_for(h, precision);
   if (rc) return rc;
   if (precision == BLTT_FP64)
     return modes_lanczos_impl<double, double>(h, q_dev, v1_dev, v2_dev, coef, vout_dev, zout_dev, dot);

@@ -29,8 +29,7 @@ template <typename T, typename TQ, int L>
 static hipError_t go_upd(bool full, bool prec, bool qrev, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                          const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
                          int64_t* nparts, hipStream_t s) {
-  const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
-  const int64_t blocks = upd_persistent<T>() ? std::max<int64_t>(1, std::min(tiles, max_blocks)) : tiles;
+  const int64_t blocks = upd_blocks<T>(L, M, max_blocks);
   const size_t lds = upd_lds_bytes<T, L>();
   if (nparts) *nparts = blocks;
   if (!prec) {

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "bltt_kernels.hpp"
 
 namespace bltt {
@@ -36,6 +38,14 @@ inline int64_t ew_blocks(int64_t n) {
 
 template <typename T>
 hipError_t launch_time_prec(int L, T* x, int64_t M, const TimeTables<T>& tb, hipStream_t s);
+
+// workgroups (= partial sums) of one launch_time_upd: FP32 runs persistently
+// on at most max_blocks workgroups, FP64 one workgroup per tile
+template <typename T>
+inline int64_t upd_blocks(int L, int64_t M, int64_t max_blocks) {
+  const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
+  return upd_persistent<T>() ? std::max<int64_t>(1, std::min(tiles, max_blocks)) : tiles;
+}
 
 // sine coordinates: vhat = cq Q (+ cv V1 + cvp V2 when full) -> Vout (optional),
 // Zout = P^{-1} vhat (time pass), per-workgroup partial sums of <vhat, Zout>
