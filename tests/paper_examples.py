@@ -26,6 +26,8 @@ def example_problem(kind, N, mp1, alpha, gamma=None):
     """The workloads.Problem behind an example (for the GPU solver)."""
     if kind == "example3":
         return W.fractional_l1(2, mp1 - 1, N, gamma, alpha, length=math.pi)
+    if kind == "example1cn":
+        return W.heat_cn(2, mp1 - 1, N, alpha, diffusion=1e-6)
     return W.heat_bdf(2, mp1 - 1, N, alpha, diffusion=1e-6)
 
 
@@ -58,6 +60,27 @@ def example1_system_and_rhs(N, mp1, alpha):
     return sysm, f
 
 
+
+
+def example1cn_system_and_rhs(N, mp1, alpha):
+    """Example 1 with Crank-Nicolson: blocks (I + tau eps L_h / 2) / tau and
+    (-I + tau eps L_h / 2) / tau, L_h = -Delta_h, diffusion eps = 1e-6 (the
+    reading that reproduces Table 1); right-hand side f at the half steps
+    (n - 1/2) tau, and the first one plus (I - tau eps L_h / 2) u0 / tau, the
+    initial-value term of the first equation moved to the right."""
+    eps = 1e-6
+    prob = W.heat_cn(2, mp1 - 1, N, alpha, diffusion=eps)
+    sysm = O.from_problem(prob)
+    h = 1.0 / mp1
+    x = h * np.arange(1, mp1)
+    X1 = np.tile(x, mp1 - 1)        # x fastest
+    X2 = np.repeat(x, mp1 - 1)
+    g = X1 * (X1 - 1) * X2 * (X2 - 1)
+    t = ((np.arange(1, N + 1) - 0.5) / N)[:, None]
+    f = np.exp(t) * (g[None, :] - 2 * eps * (X1 * (X1 - 1) + X2 * (X2 - 1))[None, :])
+    Lu0 = O.laplacian_apply(g[None, :], sysm.ms, sysm.hs)[0]
+    f[0] += g * N - 0.5 * eps * Lu0
+    return sysm, f
 
 
 def face_samples(a, ms, hs, lo):
