@@ -81,6 +81,25 @@ enum bltt_precond {
   BLTT_PRECOND_NONE = 1     /* identity                                          */
 };
 
+/* Kernel plans of the FP32 sine-basis iteration (the mixed path's time pass and
+ * N-point matvec): the radix plan of their N-point transforms and the number of
+ * workgroups of the persistent time pass.  BLTT_PLAN_AUTO times the variants
+ * on the handle's own buffers at setup and keeps the fastest (or reads an
+ * earlier choice from opt->plan_cache); the others force a radix plan.  Radix
+ * plans differ only for N = 512 (16*8*4 or 16*4*8) and N = 1024 (16*8*8 or
+ * 16*16*4); both compute the same transform. */
+enum bltt_fft_plan {
+  BLTT_PLAN_AUTO = 0,       /* default: autotuned at setup                         */
+  BLTT_PLAN_BASE = 1,       /* radix plan 0, default workgroup count               */
+  BLTT_PLAN_ALT = 2         /* radix plan 1 where it exists, default workgroups    */
+};
+enum bltt_plan_source {
+  BLTT_PLAN_SOURCE_DEFAULT = 0,  /* defaults (FP64 handle, or nothing to tune)      */
+  BLTT_PLAN_SOURCE_TIMED = 1,    /* timed at setup                                  */
+  BLTT_PLAN_SOURCE_CACHE = 2,    /* read from the plan cache                        */
+  BLTT_PLAN_SOURCE_FORCED = 3    /* opt->fft_plan                                   */
+};
+
 /* Block description.  dim in {1,2,3}; m[d] interior points and h[d] spacing of
  * dimension d (d = 0 is x, the fastest); p and q are host arrays of length N
  * (copied during bltt_setup). */
@@ -109,6 +128,7 @@ typedef struct {
   const char *plan_cache; /* NULL, or a text file of kernel plans chosen by the
                              setup autotuner: read when it holds an entry for
                              this shape, appended to when the tuner had to run  */
+  int32_t fft_plan;       /* BLTT_PLAN_AUTO (default), _BASE or _ALT           */
 } bltt_options;
 
 /* Per-solve report. */
@@ -323,7 +343,8 @@ int bltt_profile_read(bltt_handle *h, int32_t kernel_class, int64_t *launches, d
  * instance tables, one partial sum per tile and system); classes run on
  * streams of their own.  Each MINRES iteration of a class is replayed from a
  * HIP graph captured once per position in the sweep; at setup a few timed
- * launches choose each class's workgroup size.  An FP32 sweep stops after at
+ * launches choose each class's workgroup size and radix plan (or the plan
+ * cache supplies them).  An FP32 sweep stops after at
  * most 5 iterations (the refinement loop continues with a new sweep).
  *
  * bltt_setup_batched -- validate and prepare count instances.
@@ -332,7 +353,10 @@ int bltt_profile_read(bltt_handle *h, int32_t kernel_class, int64_t *launches, d
  *   nrhs                           right-hand sides per instance (>= 1)
  *   opt                            NULL or precision BLTT_MIXED, basis
  *                                  BLTT_BASIS_SINE (others: BLTT_EUNSUPPORTED);
- *                                  inner_tol and max_refine as for bltt_setup
+ *                                  inner_tol, max_refine, plan_cache and
+ *                                  fft_plan as for bltt_setup (each class's
+ *                                  workgroup size and radix plan are tuned
+ *                                  together)
  *   stream                         hipStream_t the solves are ordered on
  *   out                            receives the batch handle
  * Errors: as bltt_setup; BLTT_ENOMEM when the workspace of all classes does
@@ -361,6 +385,19 @@ int bltt_pminres_batched(bltt_batch *b, const double *const *f_dev, double tol, 
                          double *const *u_dev, int32_t *iters, double *hist, bltt_info *info);
 int bltt_batch_classes(const bltt_batch *b, int32_t *nclasses, int32_t *tpb);
 void bltt_destroy_batched(bltt_batch *b);
+
+/*
+ * bltt_plan_info -- the kernel plans a handle runs with: radix plans of the
+ * FP32 time pass and N-point matvec (0 or 1), workgroups of the persistent
+ * FP32 time pass, and where they came from (bltt_plan_source).  Any output
+ * pointer may be NULL.  Errors: BLTT_EINVAL.
+ * bltt_batch_plans -- per shape class of a batch: the radix plan (0 or 1) the
+ * setup chose with the workgroup size of bltt_batch_classes (room for that
+ * many classes; NULL allowed).  Errors: BLTT_EINVAL.
+ */
+int bltt_plan_info(const bltt_handle *h, int32_t *time_plan, int32_t *cs_plan, int64_t *time_blocks,
+                   int32_t *source);
+int bltt_batch_plans(const bltt_batch *b, int32_t *plans);
 
 /* Release all device memory and tables of the handle (NULL is a no-op). */
 void bltt_destroy(bltt_handle *h);

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libbltt.so")
 FP64, MIXED, FP32 = 0, 1, 2
 SINE, PHYSICAL = 0, 1  # Krylov basis (bltt_basis)
 PRECOND_ABAC, PRECOND_NONE = 0, 1  # bltt_precond
+PLAN_AUTO, PLAN_BASE, PLAN_ALT = 0, 1, 2  # bltt_fft_plan
+PLAN_SOURCES = {0: "default", 1: "timed", 2: "cache", 3: "forced"}
 KERNEL_CLASSES = ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update", "resid64", "other"]
 OK, NOCONV = 0, 1
 STATUS = {0: "BLTT_OK", 1: "BLTT_NOCONV", -1: "BLTT_EINVAL", -2: "BLTT_EASSUMPTION", -3: "BLTT_ENAN",
@@ -42,7 +44,7 @@ class Blocks(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("check_factor", ctypes.c_double), ("basis", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("initial_guess", ctypes.c_int32), ("plan_cache", ctypes.c_char_p)]
+                ("initial_guess", ctypes.c_int32), ("plan_cache", ctypes.c_char_p), ("fft_plan", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -96,6 +98,11 @@ def load() -> ctypes.CDLL:
     L.bltt_profile_read.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.bltt_profile_read.restype = ctypes.c_int
+    L.bltt_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+    L.bltt_plan_info.restype = ctypes.c_int
+    L.bltt_batch_plans.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    L.bltt_batch_plans.restype = ctypes.c_int
     L.bltt_destroy.argtypes = [P]
     L.bltt_destroy.restype = None
     L.bltt_setup_batched.argtypes = [ctypes.POINTER(Blocks), ctypes.POINTER(ctypes.c_int64),
@@ -144,7 +151,8 @@ class Solver:
 
     def __init__(self, dim: int, m, h, p, q, alpha: float, precision: int = FP64, inner_tol: float = 0.0,
                  max_refine: int = 0, check_factor: float = 0.0, basis: int = 0, precond: int = 0, stream=None,
-                 face=None, abar: float = 1.0, initial_guess: bool = False, plan_cache: str | None = None):
+                 face=None, abar: float = 1.0, initial_guess: bool = False, plan_cache: str | None = None,
+                 fft_plan: int = PLAN_AUTO):
         L = load()
         self._L = L
         m = list(m)
@@ -167,7 +175,7 @@ class Solver:
         self.initial_guess = bool(initial_guess)
         self._plan_cache = plan_cache.encode() if plan_cache else None
         opt = Options(precision, inner_tol, max_refine, check_factor, basis, precond, int(bool(initial_guess)),
-                      self._plan_cache)
+                      self._plan_cache, int(fft_plan))
         self.stream = stream
         handle = ctypes.c_void_p()
         if face is None:
@@ -253,6 +261,15 @@ class Solver:
             _check(self._L.bltt_profile_read(self._h, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
             out[name] = {"launches": int(n.value), "ms": float(ms.value), "bytes": float(by.value)}
         return out
+
+    def plan_info(self) -> dict:
+        """Kernel plans of the FP32 sine-basis iteration (bltt_plan_info)."""
+        tp, cp, src = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        blocks = ctypes.c_int64(0)
+        _check(self._L.bltt_plan_info(self._h, ctypes.byref(tp), ctypes.byref(cp), ctypes.byref(blocks),
+                                      ctypes.byref(src)))
+        return {"time_plan": tp.value, "cs_plan": cp.value, "time_blocks": blocks.value,
+                "source": PLAN_SOURCES.get(src.value, src.value)}
 
     def apply_space(self, x, y=None):
         """y = (I_N (x) U) x, the orthonormal sine transform of every time slice."""
@@ -346,7 +363,8 @@ class Batch:
     ``problems``: objects with dim, m, h, p, q, alpha (like workloads.Problem).
     System ``g = i*nrhs + r`` is instance i with right-hand side r."""
 
-    def __init__(self, problems, nrhs: int = 1, inner_tol: float = 0.0, max_refine: int = 0, stream=None):
+    def __init__(self, problems, nrhs: int = 1, inner_tol: float = 0.0, max_refine: int = 0, stream=None,
+                 plan_cache: str | None = None, fft_plan: int = PLAN_AUTO):
         L = load()
         self._L = L
         self.count = len(problems)
@@ -372,7 +390,8 @@ class Batch:
             M[i] = int(np.prod(pr.m))
             A[i] = float(pr.alpha)
             self.sizes += [N[i] * M[i]] * self.nrhs
-        opt = Options(MIXED, inner_tol, max_refine, 0.0, SINE, PRECOND_ABAC)
+        self._plan_cache = plan_cache.encode() if plan_cache else None
+        opt = Options(MIXED, inner_tol, max_refine, 0.0, SINE, PRECOND_ABAC, 0, self._plan_cache, int(fft_plan))
         handle = ctypes.c_void_p()
         rc = L.bltt_setup_batched(blks, N, M, A, self.count, self.nrhs, ctypes.byref(opt),
                                   ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle))
@@ -385,6 +404,14 @@ class Batch:
         _check(self._L.bltt_batch_classes(self._h, ctypes.byref(n), None))
         t = (ctypes.c_int32 * max(n.value, 1))()
         _check(self._L.bltt_batch_classes(self._h, ctypes.byref(n), t))
+        return [int(t[i]) for i in range(n.value)]
+
+    def plans(self):
+        """Radix plan the setup chose for each shape class (with classes())."""
+        n = ctypes.c_int32(0)
+        _check(self._L.bltt_batch_classes(self._h, ctypes.byref(n), None))
+        t = (ctypes.c_int32 * max(n.value, 1))()
+        _check(self._L.bltt_batch_plans(self._h, t))
         return [int(t[i]) for i in range(n.value)]
 
     def pminres(self, fs, tol: float, maxit: int, us=None):

@@ -18,6 +18,7 @@
 #include "bltt.h"
 #include "host_tables.hpp"
 #include "launchers.hpp"
+#include "plan_cache.hpp"
 
 using namespace bltt;
 
@@ -155,6 +156,11 @@ struct bltt_handle {
   double* zb_dev = nullptr;  // 3*ZB_MAX doubles: om (2K), y (K)
   double setup_ms = 0.0;
   std::string plan_cache;  // autotuner plan file ("" = none)
+  // plans of the FP32 sine-basis kernels: radix plans of the time pass and of
+  // the N-point matvec, workgroups of the persistent time pass (tuned at setup)
+  int plan_time = 0, plan_cs = 0;
+  int64_t time_blocks = 0;  // 0: max_blocks
+  int plan_source = BLTT_PLAN_SOURCE_DEFAULT;
   std::vector<void*> allocs;
   // per-kernel timing (bltt_profile_enable)
   struct ProfRec {
@@ -254,6 +260,17 @@ template <>
 Workspace<double>& workspace<double>(bltt_handle* h) { return h->w64; }
 
 bool short_p(const bltt_handle* h) { return h->ptaps <= 8; }
+
+// workgroups and radix plan of the time pass, radix plan of the N-point matvec
+// for precision T (the tuned ones apply to FP32; FP64 runs the defaults)
+template <typename T>
+int64_t time_blocks(const bltt_handle* h) {
+  return sizeof(T) == 4 && h->time_blocks > 0 ? h->time_blocks : h->max_blocks;
+}
+template <typename T>
+int time_plan(const bltt_handle* h) { return sizeof(T) == 4 ? h->plan_time : 0; }
+template <typename T>
+int cs_plan(const bltt_handle* h) { return sizeof(T) == 4 ? h->plan_cs : 0; }
 
 template <typename T>
 int build_tables(bltt_handle* h) {
@@ -437,7 +454,7 @@ int matvec(bltt_handle* h, int mode, int term, const T* z, T* out, const T* fin,
       // FP32: N-point circulant + skew-circulant form (one wavefront per line pair)
       ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
       HIPCHK(launch_matvec_cs<T>((int)h->N, mode, const_cast<T*>(z), out, fin, h->M, cs_tables<T>(h), up,
-                                 h->partials, h->max_blocks, np, h->stream));
+                                 h->partials, h->max_blocks, np, h->stream, cs_plan<T>(h)));
       return BLTT_OK;
     }
     if (mode == MV_RESID && term == TERM_STENCIL && !h->var) {
@@ -704,8 +721,9 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   {
     const bool copy = (const void*)bsrc != (const void*)Vc;
     ProfScope ps(h, BLTT_K_TIME, n * (sizeof(TB) + (copy ? 2.0 : 1.0) * sizeof(T)));
-    HIPCHK(launch_time_upd<T, TB>(L, false, h->opt.precond == BLTT_PRECOND_ABAC, bsrc, nullptr, nullptr, copy ? Vc : nullptr, Zc, h->M, tt, bcoef,
-                                  h->partials, h->max_blocks, &npt, s, brev));
+    HIPCHK(launch_time_upd<T, TB>(L, false, h->opt.precond == BLTT_PRECOND_ABAC, bsrc, nullptr, nullptr,
+                                  copy ? Vc : nullptr, Zc, h->M, tt, bcoef, h->partials, time_blocks<T>(h), &npt, s,
+                                  brev, time_plan<T>(h)));
   }
   if ((rc = scalar(h, SC_START, npt, h->hist_dev, false, zbasis))) return rc;
   if ((rc = read_state(h))) return rc;
@@ -721,8 +739,9 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
     {
       // at j = 1 there is no v_0: V2 = V1 with a zero coefficient
       ProfScope ps(h, BLTT_K_TIME, (j > 1 ? 5.0 : 4.0) * n * sizeof(T));
-      HIPCHK(launch_time_upd<T, T>(L, true, h->opt.precond == BLTT_PRECOND_ABAC, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, h->M, tt, coef_v, h->partials,
-                                   h->max_blocks, &npt, s));
+      HIPCHK(launch_time_upd<T, T>(L, true, h->opt.precond == BLTT_PRECOND_ABAC, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn,
+                                   h->M, tt, coef_v, h->partials, time_blocks<T>(h), &npt, s, false,
+                                   time_plan<T>(h)));
     }
     if ((rc = scalar(h, SC_BETA, npt, h->hist_dev, false, zbasis))) return rc;
     if (!zbasis) {
@@ -829,11 +848,131 @@ int sine_backward(bltt_handle* h, double* uhat, double* u) {
   return BLTT_OK;
 }
 
+// Kernel plans of the FP32 sine-basis iteration.  Forced by opt.fft_plan, read
+// from the plan cache, or timed here on the handle's own buffers (filled with a
+// constant first; the values computed are discarded): the time pass in every
+// radix plan (where fft_plan_alt(N)) and with 2, 4 or 8 workgroups per compute
+// unit, the N-point matvec in every radix plan.  Each variant runs once to
+// warm up (its first launch loads its code) and three times timed; the
+// variant with the smallest of its timed runs wins.
+int tune_fp32_plans(bltt_handle* h, int cus) {
+  const int L = (int)h->N;
+  const bool alt = fft_plan_alt(L);
+  if (h->opt.fft_plan != BLTT_PLAN_AUTO) {
+    h->plan_time = h->plan_cs = (h->opt.fft_plan == BLTT_PLAN_ALT && alt) ? 1 : 0;
+    h->plan_source = BLTT_PLAN_SOURCE_FORCED;
+    return BLTT_OK;
+  }
+  const std::string key = "bltt/1 " + plans::device_tag() + " fp32-sine N=" + std::to_string(h->N) +
+                          " M=" + std::to_string(h->M) + " shortp=" + std::to_string(short_p(h) ? 1 : 0);
+  std::string val;
+  if (plans::lookup(h->plan_cache, key, &val)) {
+    auto f = plans::fields(val);
+    const int pt = (int)f["time_plan"], pc = (int)f["cs_plan"];
+    const long bpc = f["blocks_per_cu"];
+    if ((pt == 0 || (pt == 1 && alt)) && (pc == 0 || (pc == 1 && alt)) && bpc >= 1 && bpc <= 64) {
+      h->plan_time = pt;
+      h->plan_cs = pc;
+      h->time_blocks = bpc * (int64_t)cus;
+      h->plan_source = BLTT_PLAN_SOURCE_CACHE;
+      return BLTT_OK;
+    }
+  }
+  Workspace<float>& w = h->w32;
+  hipStream_t s = h->stream;
+  const int64_t n = h->n;
+  HIPCHK(launch_fill<float>(w.Q, n, 0.5f, s));
+  for (int i = 0; i < 3; ++i) HIPCHK(launch_fill<float>(w.V[i], n, 0.25f, s));
+  HIPCHK(launch_fill<float>(w.Z[0], n, 0.5f, s));
+  hipEvent_t a = nullptr, z = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  if (hipEventCreate(&z) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return BLTT_EHIP;
+  }
+  int rc = BLTT_OK;
+  auto time_it = [&](auto&& launch, float* best_ms) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && rc == BLTT_OK; ++rep) {
+      if (hipEventRecord(a, s) != hipSuccess || launch() != hipSuccess || hipEventRecord(z, s) != hipSuccess ||
+          hipEventSynchronize(z) != hipSuccess) {
+        rc = BLTT_EHIP;
+        break;
+      }
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, a, z) != hipSuccess) rc = BLTT_EHIP;
+      if (rep > 0 && ms < best) best = ms;
+    }
+    *best_ms = best;
+  };
+  const TimeTables<float> tt = time_tables<float>(h, false);
+  const int64_t tiles = fft_tiles<float, FK_SPEC>(L, h->M);
+  float best_t = 1e30f;
+  int bt_plan = 0;
+  int64_t bt_blocks = h->max_blocks;
+  for (int plan = 0; plan <= (alt ? 1 : 0); ++plan) {
+    for (int per : {2, 4, 8}) {
+      const int64_t blocks = per * (int64_t)cus;
+      if (per > 2 && (per / 2) * (int64_t)cus >= tiles) continue;  // same launch as the smaller count
+      float ms = 1e30f;
+      int64_t np = 0;
+      time_it([&]() {
+        return launch_time_upd<float, float>(L, true, true, w.Q, w.V[0], w.V[1], w.V[2], w.Z[0], h->M, tt,
+                                             h->coef_one, h->partials, blocks, &np, s, false, plan);
+      }, &ms);
+      if (rc) break;
+      if (ms < best_t) {
+        best_t = ms;
+        bt_plan = plan;
+        bt_blocks = blocks;
+      }
+    }
+  }
+  int bc_plan = 0;
+  if (rc == BLTT_OK && alt && !short_p(h)) {
+    float best_c = 1e30f;
+    for (int plan = 0; plan <= 1; ++plan) {
+      float ms = 1e30f;
+      int64_t np = 0;
+      time_it([&]() {
+        return launch_matvec_cs<float>(L, MV_DOT, w.Z[0], w.Q, nullptr, h->M, cs_tables<float>(h), IterUpd{},
+                                       h->partials, h->max_blocks, &np, s, plan);
+      }, &ms);
+      if (rc) break;
+      if (ms < best_c) {
+        best_c = ms;
+        bc_plan = plan;
+      }
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(z);
+  if (rc) return rc;
+  h->plan_time = bt_plan;
+  h->plan_cs = bc_plan;
+  h->time_blocks = bt_blocks;
+  h->plan_source = BLTT_PLAN_SOURCE_TIMED;
+  plans::store(h->plan_cache, key,
+               "time_plan=" + std::to_string(bt_plan) + " cs_plan=" + std::to_string(bc_plan) +
+                   " blocks_per_cu=" + std::to_string(bt_blocks / cus));
+  return BLTT_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* bltt_version(void) { return "bltt-mi355x 0.1"; }
+const char* bltt_version(void) { return "bltt-mi355x 0.2"; }
+
+int bltt_plan_info(const bltt_handle* h, int32_t* time_plan, int32_t* cs_plan, int64_t* time_blocks,
+                   int32_t* source) {
+  if (!h) return BLTT_EINVAL;
+  if (time_plan) *time_plan = h->plan_time;
+  if (cs_plan) *cs_plan = h->plan_cs;
+  if (time_blocks) *time_blocks = h->time_blocks > 0 ? h->time_blocks : h->max_blocks;
+  if (source) *source = h->plan_source;
+  return BLTT_OK;
+}
 
 const char* bltt_strerror(int code) {
   switch (code) {
@@ -882,6 +1021,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (opt->basis != BLTT_BASIS_SINE && opt->basis != BLTT_BASIS_PHYSICAL) return BLTT_EINVAL;
     if (opt->precond != BLTT_PRECOND_ABAC && opt->precond != BLTT_PRECOND_NONE) return BLTT_EINVAL;
     if (opt->initial_guess != 0 && opt->initial_guess != 1) return BLTT_EINVAL;
+    if (opt->fft_plan < BLTT_PLAN_AUTO || opt->fft_plan > BLTT_PLAN_ALT) return BLTT_EINVAL;
     // the unpreconditioned comparator runs the FP64 sine-basis path
     if (opt->precond == BLTT_PRECOND_NONE && (opt->precision != BLTT_FP64 || opt->basis != BLTT_BASIS_SINE))
       return BLTT_EUNSUPPORTED;
@@ -942,6 +1082,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (opt->max_refine > 0) h->opt.max_refine = opt->max_refine;
     if (opt->check_factor >= 1.0) h->opt.check_factor = opt->check_factor;
     h->opt.initial_guess = opt->initial_guess;
+    h->opt.fft_plan = opt->fft_plan;
     if (opt->plan_cache) h->plan_cache = opt->plan_cache;
   }
   h->opt.plan_cache = nullptr;  // the handle keeps its own copy of the path
@@ -1024,6 +1165,8 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (h->opt.precision == BLTT_MIXED)
       if ((rc = build_zpool(h))) return fail(rc);
   }
+  if (sine && h->opt.precision == BLTT_MIXED && h->opt.precond == BLTT_PRECOND_ABAC && !h->var)
+    if ((rc = tune_fp32_plans(h, (int)(h->max_blocks / 4)))) return fail(rc);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(BLTT_EHIP);
   h->setup_ms = now_ms() - t0;
   *out = h;
@@ -1446,7 +1589,7 @@ int modes_lanczos_impl(bltt_handle* h, const void* q, const void* v1, const void
                                                                                (v2 ? 1 : 0))));
     HIPCHK(launch_time_upd<T, TQ>((int)h->N, full, h->opt.precond == BLTT_PRECOND_ABAC, (const TQ*)q, V1, V2,
                                   (T*)vout, (T*)zout, h->M, time_tables<T>(h, false), h->step_dev + STEP_COEF,
-                                  h->partials, h->max_blocks, &np, h->stream));
+                                  h->partials, time_blocks<T>(h), &np, h->stream, false, time_plan<T>(h)));
   }
   return reduce_to_host(h, np, dot);
 }
@@ -1530,8 +1673,8 @@ int lanczos_noalloc_impl(bltt_handle* h, double* scr_dev, const void* q, const v
   HIPCHK(hipMemcpyAsync(scr_dev + scr::COEF, c, sizeof(c), hipMemcpyHostToDevice, h->stream));
   int64_t np = 0;
   HIPCHK(launch_time_upd<T, TQ>((int)h->N, full, h->opt.precond == BLTT_PRECOND_ABAC, (const TQ*)q, V1, V2, (T*)vout,
-                                (T*)zout, h->M, time_tables<T>(h, false), scr_dev + scr::COEF, scr_dev, h->max_blocks,
-                                &np, h->stream));
+                                (T*)zout, h->M, time_tables<T>(h, false), scr_dev + scr::COEF, scr_dev,
+                                time_blocks<T>(h), &np, h->stream, false, time_plan<T>(h)));
   SolverState* st = reinterpret_cast<SolverState*>(scr_dev + scr::STATE);
   HIPCHK(launch_scalar(SC_NORM, st, scr_dev, np, nullptr, 0, nullptr, scr_dev + scr::RED, scr::RED_HALF, ZBasis{},
                        h->stream));
@@ -1554,8 +1697,8 @@ int bltt_modes_lanczos_noalloc(bltt_handle* h, int32_t precision, const void* q_
   const bool ready = precision == BLTT_FP64 ? h->t64.ready
                                             : (precision == BLTT_FP32 ? h->t32.ready : h->t32.ready && h->t64.ready);
   if (!ready) return BLTT_EINVAL;
-  const int64_t np = precision == BLTT_FP64 ? upd_blocks<double>((int)h->N, h->M, h->max_blocks)
-                                            : upd_blocks<float>((int)h->N, h->M, h->max_blocks);
+  const int64_t np = precision == BLTT_FP64 ? upd_blocks<double>((int)h->N, h->M, time_blocks<double>(h))
+                                            : upd_blocks<float>((int)h->N, h->M, time_blocks<float>(h));
   if (np > scr::PARTS) return BLTT_EUNSUPPORTED;
   double* scr_dev = scratch_ptr(h->device);
   if (!scr_dev) return BLTT_EHIP;

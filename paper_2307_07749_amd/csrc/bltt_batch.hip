@@ -14,11 +14,13 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <string>
 #include <tuple>
 #include <vector>
 
 #include "bltt.h"
 #include "host_tables.hpp"
+#include "plan_cache.hpp"
 #include "launchers.hpp"
 
 using namespace bltt;
@@ -43,6 +45,7 @@ struct BatchClass {
   std::vector<int> sys_inst;     // class system -> class instance
   // tuning
   int tpb = 256;
+  int plan = 0;    // radix plan of the FP32 transforms (1 where fft_plan_alt(N))
   int64_t T = 0;   // tiles per system of the FP32 kernels
   int64_t T2 = 0;  // tiles per system of the FP64 residual
   hipStream_t stream = nullptr;
@@ -80,6 +83,7 @@ struct BatchClass {
 struct bltt_batch {
   int count = 0, nrhs = 0;
   bltt_options opt{};
+  std::string plan_cache;  // autotuner plan file ("" = none)
   hipStream_t stream = nullptr;
   std::vector<BatchClass> cls;
   std::vector<void*> allocs;
@@ -187,13 +191,13 @@ hipError_t enqueue_iteration(BatchClass& c, int j, double inner_tol) {
   float* Zc = c.pool.z[j - 1];
   float* Zn = c.pool.z[j];
   hipError_t e;
-  if ((e = launch_bt(BT_MATVEC, L, c.tpb, nullptr, nullptr, nullptr, nullptr, Zc, c.Q, bv, c.tabs, c.partials,
+  if ((e = launch_bt(BT_MATVEC, L, c.tpb, c.plan, nullptr, nullptr, nullptr, nullptr, Zc, c.Q, bv, c.tabs, c.partials,
                      c.stream)) != hipSuccess)
     return e;
   if ((e = launch_bt_scalar(SC_DELTA, bv, c.partials, c.T, nullptr, 0, nullptr, BT_POOL, inner_tol, BT_POOL - 1,
                             c.stream)) != hipSuccess)
     return e;
-  if ((e = launch_bt(BT_UPD, L, c.tpb, c.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, nullptr, bv, c.tabs, c.partials,
+  if ((e = launch_bt(BT_UPD, L, c.tpb, c.plan, c.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn, nullptr, bv, c.tabs, c.partials,
                      c.stream)) != hipSuccess)
     return e;
   return launch_bt_scalar(SC_BETA, bv, c.partials, c.T, c.hist_dev, c.hist_stride, c.zb, BT_POOL, inner_tol,
@@ -238,42 +242,74 @@ int read_states(BatchClass& c) {
   return BLTT_OK;
 }
 
-// Pick the workgroup size of the FP32 iteration kernels: a few timed launches of
-// the matvec and the update on the class's own buffers (states zeroed, every
-// system active; the values computed are discarded).
-int autotune(BatchClass& c) {
-  const int cands[2] = {256, 512};
+// Pick the workgroup size and radix plan of the FP32 iteration kernels: a few
+// timed launches of the matvec and the update on the class's own buffers
+// (states zeroed, every system active; the values computed are discarded), or
+// the choice an earlier setup stored in the plan cache for this device and
+// class shape.  opt.fft_plan other than BLTT_PLAN_AUTO fixes the radix plan
+// and times the workgroup sizes only.
+int autotune(bltt_batch* b, BatchClass& c) {
+  const int L = (int)c.N;
+  const bool alt = fft_plan_alt(L);
+  const int fixed = b->opt.fft_plan == BLTT_PLAN_BASE ? 0 : (b->opt.fft_plan == BLTT_PLAN_ALT ? (alt ? 1 : 0) : -1);
+  const std::string key = "bltt/1 " + plans::device_tag() + " fp32-batch N=" + std::to_string(c.N) +
+                          " M=" + std::to_string(c.M) + " S=" + std::to_string(c.S);
+  std::string val;
+  if (fixed < 0 && plans::lookup(b->plan_cache, key, &val)) {
+    auto f = plans::fields(val);
+    const int tpb = (int)f["tpb"], plan = (int)f["plan"];
+    if ((tpb == 256 || (tpb == 512 && c.N >= 32)) && (plan == 0 || (plan == 1 && alt))) {
+      c.tpb = tpb;
+      c.plan = plan;
+      c.T = bt_tiles(L, c.tpb, c.M);
+      return BLTT_OK;
+    }
+  }
   float best = 1e30f;
-  int best_tpb = 256;
+  int best_tpb = 256, best_plan = fixed < 0 ? 0 : fixed;
   hipEvent_t a = nullptr, z = nullptr;
   HIPCHK(hipEventCreate(&a));
-  HIPCHK(hipEventCreate(&z));
-  for (int tpb : cands) {
+  if (hipEventCreate(&z) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return BLTT_EHIP;
+  }
+  int rc = BLTT_OK;
+  for (int tpb : {256, 512}) {
     if (tpb == 512 && c.N < 32) continue;
-    c.tpb = tpb;
-    c.T = bt_tiles((int)c.N, tpb, c.M);
-    const BatchVec bv = bvec(c);
-    const int L = (int)c.N;
-    float ms = 0.0f;
-    for (int rep = 0; rep < 2; ++rep) {
-      HIPCHK(hipEventRecord(a, c.stream));
-      HIPCHK(launch_bt(BT_MATVEC, L, tpb, nullptr, nullptr, nullptr, nullptr, c.pool.z[0], c.Q, bv, c.tabs,
-                       c.partials, c.stream));
-      HIPCHK(launch_bt(BT_UPD, L, tpb, c.Q, c.V[0], c.V[1], c.V[2], c.pool.z[1], nullptr, bv, c.tabs, c.partials,
-                       c.stream));
-      HIPCHK(hipEventRecord(z, c.stream));
-      HIPCHK(hipEventSynchronize(z));
-      HIPCHK(hipEventElapsedTime(&ms, a, z));
-    }
-    if (ms < best) {
-      best = ms;
-      best_tpb = tpb;
+    for (int plan = 0; plan <= (alt ? 1 : 0) && rc == BLTT_OK; ++plan) {
+      if (fixed >= 0 && plan != fixed) continue;
+      c.tpb = tpb;
+      c.T = bt_tiles(L, tpb, c.M);
+      const BatchVec bv = bvec(c);
+      float ms = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        float t = 0.0f;
+        if (hipEventRecord(a, c.stream) != hipSuccess ||
+            launch_bt(BT_MATVEC, L, tpb, plan, nullptr, nullptr, nullptr, nullptr, c.pool.z[0], c.Q, bv, c.tabs,
+                      c.partials, c.stream) != hipSuccess ||
+            launch_bt(BT_UPD, L, tpb, plan, c.Q, c.V[0], c.V[1], c.V[2], c.pool.z[1], nullptr, bv, c.tabs,
+                      c.partials, c.stream) != hipSuccess ||
+            hipEventRecord(z, c.stream) != hipSuccess || hipEventSynchronize(z) != hipSuccess ||
+            hipEventElapsedTime(&t, a, z) != hipSuccess) {
+          rc = BLTT_EHIP;
+          break;
+        }
+        if (rep > 0) ms = t;  // the first launch of a variant loads its code
+      }
+      if (rc == BLTT_OK && ms < best) {
+        best = ms;
+        best_tpb = tpb;
+        best_plan = plan;
+      }
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(z);
+  if (rc) return rc;
   c.tpb = best_tpb;
-  c.T = bt_tiles((int)c.N, c.tpb, c.M);
+  c.plan = best_plan;
+  c.T = bt_tiles(L, c.tpb, c.M);
+  if (fixed < 0) plans::store(b->plan_cache, key, "tpb=" + std::to_string(c.tpb) + " plan=" + std::to_string(c.plan));
   return BLTT_OK;
 }
 
@@ -378,7 +414,7 @@ int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const doub
   for (auto& v : c.V) HIPCHK(hipMemsetAsync(v, 0, ns * sizeof(float), c.stream));
   for (int i = 0; i < 2; ++i) HIPCHK(hipMemsetAsync(c.pool.z[i], 0, ns * sizeof(float), c.stream));
   c.T2 = mv_tiles<double>(true, (int)(2 * N), M);
-  if ((rc = autotune(c))) return rc;
+  if ((rc = autotune(b, c))) return rc;
   HIPCHK(hipStreamSynchronize(c.stream));
   return BLTT_OK;
 }
@@ -424,6 +460,7 @@ int bltt_setup_batched(const bltt_blocks* blk, const int64_t* N, const int64_t* 
   if (opt && opt->precision != BLTT_MIXED) return BLTT_EUNSUPPORTED;
   if (opt && opt->basis != BLTT_BASIS_SINE) return BLTT_EUNSUPPORTED;
   if (opt && opt->precond != BLTT_PRECOND_ABAC) return BLTT_EUNSUPPORTED;
+  if (opt && (opt->fft_plan < BLTT_PLAN_AUTO || opt->fft_plan > BLTT_PLAN_ALT)) return BLTT_EINVAL;
   for (int i = 0; i < count; ++i) {
     const bltt_blocks& bk = blk[i];
     if (!bk.p || !bk.q || bk.dim < 1 || bk.dim > 3 || !(alpha[i] > 0.0 && alpha[i] <= 1.0)) return BLTT_EINVAL;
@@ -466,7 +503,10 @@ int bltt_setup_batched(const bltt_blocks* blk, const int64_t* N, const int64_t* 
   if (opt) {
     if (opt->inner_tol > 0.0) b->opt.inner_tol = opt->inner_tol;
     if (opt->max_refine > 0) b->opt.max_refine = opt->max_refine;
+    b->opt.fft_plan = opt->fft_plan;
+    if (opt->plan_cache) b->plan_cache = opt->plan_cache;
   }
+  b->opt.plan_cache = nullptr;
   auto fail = [&](int code) {
     bltt_destroy_batched(b);
     return code;
@@ -516,6 +556,13 @@ int bltt_setup_batched(const bltt_blocks* blk, const int64_t* N, const int64_t* 
     if (int rc = build_class(b, c, blk, alpha)) return fail(rc);
   b->setup_ms = now_ms() - t0;
   *out = b;
+  return BLTT_OK;
+}
+
+int bltt_batch_plans(const bltt_batch* b, int32_t* plans) {
+  if (!b) return BLTT_EINVAL;
+  if (plans)
+    for (size_t i = 0; i < b->cls.size(); ++i) plans[i] = b->cls[i].plan;
   return BLTT_OK;
 }
 
@@ -632,7 +679,7 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
                                 c.stream));
           HIPCHK(hipMemcpyAsync(c.etol_dev, c.etol_host, sizeof(double) * (size_t)c.S, hipMemcpyHostToDevice,
                                 c.stream));
-          HIPCHK(launch_bt(BT_START, (int)c.N, c.tpb, c.R64, nullptr, nullptr, c.V[0], c.pool.z[0], nullptr, bv,
+          HIPCHK(launch_bt(BT_START, (int)c.N, c.tpb, c.plan, c.R64, nullptr, nullptr, c.V[0], c.pool.z[0], nullptr, bv,
                            c.tabs, c.partials, c.stream));
           HIPCHK(launch_bt_scalar(SC_START, bv, c.partials, c.T, c.hist_dev, c.hist_stride, c.zb, BT_POOL,
                                   inner_tol, BT_POOL - 1, c.stream));

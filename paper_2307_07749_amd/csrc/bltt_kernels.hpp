@@ -516,9 +516,9 @@ BLTT_HD int spec_index(int g, int w, int u) {
 // writes them to LDS (stage twiddles as build_twl lays them out, spectra in
 // register order: entry (w RL + u) G + g holds frequency freq(g, w, u)), with
 // no barrier (the tile takes one).
-template <typename T, int L, int TPB>
+template <typename T, int L, int TPB, int PLAN = 0>
 struct CsStage {
-  using F = LineFft<T, L, TPB / (L / fft_V(L)), false, LAST_DEFAULT, true>;
+  using F = LineFft<T, L, TPB / (L / fft_V(L)), false, LAST_DEFAULT, true, PLAN>;
   static constexpr int PER = (L + TPB - 1) / TPB;
   cx<T> tv[F::template twl_per<TPB>()];
   cx<T> ch[PER], sh[PER], om[PER];
@@ -565,14 +565,14 @@ struct CsStage {
 // TWL: the tables are the LDS copies of CsStage (stage twiddles, spectra in
 // register order), whose registers `stage` holds: the tile stores them and
 // synchronises once its line loads are issued.
-template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), bool TWL = false, class Ctx,
-          class Stage = CsStage<T, L, TPB>>
+template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), bool TWL = false, int PLAN = 0, class Ctx,
+          class Stage = CsStage<T, L, TPB, PLAN>>
 BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
                               const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
                               Stage* stage = nullptr) {
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L;
-  using F = LineFft<T, L, NL, false, LAST_DEFAULT, TWL>;
+  using F = LineFft<T, L, NL, false, LAST_DEFAULT, TWL, PLAN>;
   const int tid = ctx.tid, c = tid / G, g = tid % G;
   const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
@@ -738,19 +738,19 @@ constexpr size_t cs_lds_bytes() { return cs_lds_base<T, L>() + (cs_stage<T, L>()
 // loop-invariant twiddle and spectrum loads live across tiles, which costs
 // half the occupancy here); one partial sum per workgroup.  `tabs`: LDS for
 // the staged tables when cs_stage holds.
-template <typename T, int L, int MODE, class Ctx>
+template <typename T, int L, int MODE, int PLAN = 0, class Ctx>
 BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, cx<T>* tabs, T* z, T* __restrict__ out,
                             const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
                             double* __restrict__ partials) {
   constexpr int TPB = tpb_fft<T, FK_SPEC>();
   double part;
   if constexpr (cs_stage<T, L>()) {
-    CsStage<T, L, TPB> st;
+    CsStage<T, L, TPB, PLAN> st;
     st.tabs = tabs;
     st.load(ctx, tb);
-    part = matvec_cs_tile<T, L, MODE, TPB, true>(ctx, lds, ctx.bid, z, out, fin, M, st.tables(tb), up, &st);
+    part = matvec_cs_tile<T, L, MODE, TPB, true, PLAN>(ctx, lds, ctx.bid, z, out, fin, M, st.tables(tb), up, &st);
   } else {
-    part = matvec_cs_tile<T, L, MODE, TPB, false>(ctx, lds, ctx.bid, z, out, fin, M, tb, up);
+    part = matvec_cs_tile<T, L, MODE, TPB, false, PLAN>(ctx, lds, ctx.bid, z, out, fin, M, tb, up);
   }
   const double sum = block_sum<TPB>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;
@@ -1558,13 +1558,13 @@ BLTT_HD void time_prec_body(Ctx& ctx, cx<T>* lds, double* red, T* __restrict__ x
 // ---------------------------------------------------------------------------
 // PREC false: no preconditioner (zhat = vhat), the MINRES-I comparator
 template <typename T, int L, typename TQ, bool FULL, bool MM, int TPB = tpb_fft<T, FK_SPEC>(), bool PREC = true,
-          bool TWL = false, class Ctx>
+          bool TWL = false, int PLAN = 0, class Ctx>
 BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __restrict__ Q,
                              const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                              T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
                              const double* __restrict__ coef, bool qrev = false) {
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
-  using F = LineFft<T, L, NL, !MM, LAST_PAIRED, TWL>;
+  using F = LineFft<T, L, NL, !MM, LAST_PAIRED, TWL, PLAN>;
   const T invN = T(1) / T(L);
   const int tid = ctx.tid, c = MM ? tid / G : tid % NL;
   int g = MM ? tid % G : tid / NL;
@@ -1700,7 +1700,7 @@ constexpr size_t upd_twl_bytes() { return upd_twl<T>() ? (size_t)L * sizeof(cx<T
 template <typename T>
 constexpr bool upd_persistent() { return sizeof(T) == 4; }
 
-template <typename T, int L, typename TQ, bool FULL, bool MM, bool PREC = true, class Ctx>
+template <typename T, int L, typename TQ, bool FULL, bool MM, bool PREC = true, int PLAN = 0, class Ctx>
 BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restrict__ Q,
                            const T* __restrict__ V1, const T* __restrict__ V2, T* __restrict__ Vout,
                            T* __restrict__ Zout, int64_t M, const TimeTables<T>& tb,
@@ -1710,7 +1710,7 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
   TimeTables<T> tl = tb;
   if constexpr (upd_twl<T>() && PREC) {
     // the stage twiddles in LDS, after the exchange lines and the reduction slots
-    using F = LineFft<T, L, TPB / (L / fft_V(L)), !MM, LAST_PAIRED, true>;
+    using F = LineFft<T, L, TPB / (L / fft_V(L)), !MM, LAST_PAIRED, true, PLAN>;
     cx<T>* twl = reinterpret_cast<cx<T>*>(red + TPB);
     F::template build_twl<TPB>(ctx, twl, tb.tw);
     ctx.sync();
@@ -1719,11 +1719,11 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
   double part = 0.0;
   if constexpr (upd_persistent<T>()) {
     for (int64_t tile = ctx.bid; tile < ntiles; tile += ctx.nbx)
-      part += time_upd_tile<T, L, TQ, FULL, MM, TPB, PREC, upd_twl<T>() && PREC>(ctx, lds, tile, Q, V1, V2, Vout,
-                                                                                 Zout, M, tl, coef, qrev);
+      part += time_upd_tile<T, L, TQ, FULL, MM, TPB, PREC, upd_twl<T>() && PREC, PLAN>(ctx, lds, tile, Q, V1, V2,
+                                                                                       Vout, Zout, M, tl, coef, qrev);
   } else {
-    part = time_upd_tile<T, L, TQ, FULL, MM, TPB, PREC, upd_twl<T>() && PREC>(ctx, lds, ctx.bid, Q, V1, V2, Vout,
-                                                                               Zout, M, tl, coef, qrev);
+    part = time_upd_tile<T, L, TQ, FULL, MM, TPB, PREC, upd_twl<T>() && PREC, PLAN>(ctx, lds, ctx.bid, Q, V1, V2,
+                                                                                     Vout, Zout, M, tl, coef, qrev);
   }
   const double sum = block_sum<tpb_fft<T, FK_SPEC>()>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;
@@ -2120,7 +2120,7 @@ constexpr size_t bt_cs_lds() {
 template <int L, int TPB>
 constexpr size_t bt_upd_lds() { return bt_lds_base<L, TPB>() + (size_t)L * sizeof(cx<float>); }
 
-template <int L, typename TQ, bool FULL, int TPB, class Ctx>
+template <int L, typename TQ, bool FULL, int TPB, int PLAN, class Ctx>
 BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q, const float* __restrict__ V1,
                          const float* __restrict__ V2, float* __restrict__ Vout, float* __restrict__ Zout,
                          const BatchVec& bv, const BatchTabs& bt, double* __restrict__ partials) {
@@ -2149,7 +2149,7 @@ BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q
   // the stage twiddles in LDS (time pass with TWL), after the exchange lines
   // and the reduction slots
   {
-    using FT = LineFft<float, L, NL, false, LAST_PAIRED, true>;
+    using FT = LineFft<float, L, NL, false, LAST_PAIRED, true, PLAN>;
     cx<float>* twl = reinterpret_cast<cx<float>*>(smem + bt_lds_base<L, TPB>());
     FT::template build_twl<TPB>(ctx, twl, bt.tw);
     ctx.sync();
@@ -2157,7 +2157,7 @@ BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q
   }
   const int64_t o = (int64_t)s * bv.n;
   const double* coef = FULL ? bv.states[s].coef_v : &bv.states[s].rinv;
-  const double part = time_upd_tile<float, L, TQ, FULL, true, TPB, true, true>(
+  const double part = time_upd_tile<float, L, TQ, FULL, true, TPB, true, true, PLAN>(
       ctx, reinterpret_cast<cx<float>*>(smem), tile, Q + o, FULL ? V1 + o : nullptr, FULL ? V2 + o : nullptr,
       Vout ? Vout + o : nullptr, Zout + o, bv.M, tb, coef);
   const double sum = block_sum<TPB>(ctx, red, part);
@@ -2165,7 +2165,7 @@ BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q
 }
 
 // FP32 sine-coordinate matvec (N-point form): Q = Y T Z, partial sums of <Q, Z>
-template <int L, int TPB, class Ctx>
+template <int L, int TPB, int PLAN, class Ctx>
 BLTT_HD void bt_cs_body(Ctx& ctx, unsigned char* smem, const float* __restrict__ Z, float* __restrict__ Q,
                         const BatchVec& bv, const BatchTabs& bt, double* __restrict__ partials) {
   constexpr int NL = TPB / (L / fft_V(L));
@@ -2190,15 +2190,16 @@ BLTT_HD void bt_cs_body(Ctx& ctx, unsigned char* smem, const float* __restrict__
   const int64_t o = (int64_t)s * bv.n;
   double part;
   if constexpr (bt_cs_stage<L, TPB>()) {
-    CsStage<float, L, TPB> st;
+    CsStage<float, L, TPB, PLAN> st;
     st.tabs = reinterpret_cast<cx<float>*>(smem + bt_lds_base<L, TPB>());
     st.load(ctx, tb);
-    part = matvec_cs_tile<float, L, MV_DOT, TPB, true>(ctx, reinterpret_cast<cx<float>*>(smem), tile,
+    part = matvec_cs_tile<float, L, MV_DOT, TPB, true, PLAN>(ctx, reinterpret_cast<cx<float>*>(smem), tile,
                                                        const_cast<float*>(Z) + o, Q + o, nullptr, bv.M,
                                                        st.tables(tb), IterUpd{}, &st);
   } else {
-    part = matvec_cs_tile<float, L, MV_DOT, TPB>(ctx, reinterpret_cast<cx<float>*>(smem), tile,
-                                                 const_cast<float*>(Z) + o, Q + o, nullptr, bv.M, tb, IterUpd{});
+    part = matvec_cs_tile<float, L, MV_DOT, TPB, false, PLAN>(ctx, reinterpret_cast<cx<float>*>(smem), tile,
+                                                              const_cast<float*>(Z) + o, Q + o, nullptr, bv.M, tb,
+                                                              IterUpd{});
   }
   const double sum = block_sum<TPB>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;

@@ -72,6 +72,27 @@ constexpr int fft_r(int L, int s) {
          : L == 2048 ? (s == 2 ? 8 : 16)
                      : 16;  // 4096
 }
+// Radix plans.  Plan 0 is the table above; plan 1 splits the stages after the
+// first radix-16 one the other way where that is possible with the same
+// registers: 16*16*4 for L = 1024 and 16*4*8 for L = 512 (other lengths: plan 0).
+// Which one runs faster is a property of the machine and the kernel around the
+// transform, chosen at setup by timing both.
+constexpr bool fft_plan_alt(int L) { return L == 512 || L == 1024; }
+constexpr int fft_rp(int L, int s, int plan) {
+  return plan == 1 && L == 1024  ? (s == 0 ? 16 : (s == 1 ? 16 : 4))
+         : plan == 1 && L == 512 ? (s == 0 ? 16 : (s == 1 ? 4 : 8))
+                                 : fft_r(L, s);
+}
+constexpr int fft_sigma_p(int L, int s, int plan) {
+  int p = 1;
+  for (int i = 0; i <= s; ++i) p *= fft_rp(L, i, plan);
+  return L / p;
+}
+constexpr int fft_rho_p(int L, int s, int plan) {
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= fft_rp(L, i, plan);
+  return p;
+}
 constexpr int fft_sigma(int L, int s) {
   int p = 1;
   for (int i = 0; i <= s; ++i) p *= fft_r(L, i);
@@ -195,12 +216,12 @@ enum LastMode {
 // build_twl) instead of power products of the global table: for stage s, entry
 // off_s + (u-1) sg_s + j holds w^(u j L/B_s) for butterfly j = beta mod sg_s,
 // so consecutive lanes read consecutive entries.
-template <typename T, int L, int NL, bool INTERLEAVED, int LAST, bool TWL = false>
+template <typename T, int L, int NL, bool INTERLEAVED, int LAST, bool TWL = false, int PLAN = 0>
 struct LineFft {
   static constexpr int V = fft_V(L);
   static constexpr int S = fft_S(L);
   static constexpr int G = L / V;             // threads per line
-  static constexpr int RL = fft_r(L, S - 1);  // last radix
+  static constexpr int RL = fft_rp(L, S - 1, PLAN);         // last radix
   static constexpr int K = L / RL;            // last-stage butterflies per line
   static constexpr int LP = fft_padded(L);    // padded line length
   static constexpr int LDS_ELEMS = NL * LP;
@@ -218,7 +239,7 @@ struct LineFft {
   // LDS twiddle table: offset of stage s, and the total length (< L)
   static constexpr int twl_off(int s) {
     int o = 0;
-    for (int i = 0; i < s; ++i) o += (fft_r(L, i) - 1) * fft_sigma(L, i);
+    for (int i = 0; i < s; ++i) o += (fft_rp(L, i, PLAN) - 1) * fft_sigma_p(L, i, PLAN);
     return o;
   }
   static constexpr int TWL_LEN = twl_off(S - 1) > 0 ? twl_off(S - 1) : 1;
@@ -254,12 +275,12 @@ struct LineFft {
   BLTT_HD static constexpr int twl_src(int i) {
     int s = 0;
     while (s < S - 2 && i >= twl_off(s + 1)) ++s;
-    const int sg = fft_sigma(L, s), LB = L / (fft_r(L, s) * sg), e = i - twl_off(s);
+    const int sg = fft_sigma_p(L, s, PLAN), LB = L / (fft_rp(L, s, PLAN) * sg), e = i - twl_off(s);
     return (e / sg + 1) * (e % sg) * LB;
   }
   template <int s, int r>
   BLTT_HD static void stage_twiddles(cx<T>* pw, const cx<T>* tw, int b) {
-    constexpr int sg = fft_sigma(L, s), B = r * sg;
+    constexpr int sg = fft_sigma_p(L, s, PLAN), B = r * sg;
     if constexpr (TWL) {
       constexpr int o = twl_off(s);
       const int j = b % sg;
@@ -269,7 +290,7 @@ struct LineFft {
       twiddle_powers<r>(pw, tw, (b % sg) * (L / B));
     }
   }
-  static_assert(S == 1 || fft_r(L, 0) == V, "first stage must use all registers");
+  static_assert(S == 1 || fft_rp(L, 0, PLAN) == V, "first stage must use all registers");
   static_assert(LAST != LAST_PAIRED || S == 1 || V >= 2 * RL, "pairing needs two butterflies");
 
   BLTT_HD static int idx(int c, int pos) {
@@ -279,7 +300,7 @@ struct LineFft {
 
   template <int s>
   BLTT_HD static int pos(int b, int t) {
-    constexpr int sg = fft_sigma(L, s), r = fft_r(L, s);
+    constexpr int sg = fft_sigma_p(L, s, PLAN), r = fft_rp(L, s, PLAN);
     return (b / sg) * (r * sg) + (b % sg) + t * sg;
   }
 
@@ -288,13 +309,13 @@ struct LineFft {
     const int p = b * RL;
     int k = 0;
 #pragma unroll
-    for (int s = 0; s < S - 1; ++s) k += ((p / fft_sigma(L, s)) % fft_r(L, s)) * fft_rho(L, s);
+    for (int s = 0; s < S - 1; ++s) k += ((p / fft_sigma_p(L, s, PLAN)) % fft_rp(L, s, PLAN)) * fft_rho_p(L, s, PLAN);
     return k;
   }
   BLTT_HD static int blk_of_klow(int kl) {
     int b = 0;
 #pragma unroll
-    for (int s = 0; s < S - 1; ++s) b += ((kl / fft_rho(L, s)) % fft_r(L, s)) * (fft_sigma(L, s) / RL);
+    for (int s = 0; s < S - 1; ++s) b += ((kl / fft_rho_p(L, s, PLAN)) % fft_rp(L, s, PLAN)) * (fft_sigma_p(L, s, PLAN) / RL);
     return b;
   }
 
@@ -341,21 +362,21 @@ struct LineFft {
   template <int s>
   static constexpr int pf_per() {
     int n = 0;
-    if (fft_sigma(L, s) > 1)
-      for (int u = 1; u < fft_r(L, s); u <<= 1) ++n;
+    if (fft_sigma_p(L, s, PLAN) > 1)
+      for (int u = 1; u < fft_rp(L, s, PLAN); u <<= 1) ++n;
     return n;
   }
   template <int s>
   static constexpr int pf_off() {
     int o = 0;
-    if constexpr (s > 0) o = pf_off<s - 1>() + (V / fft_r(L, s - 1)) * pf_per<s - 1>();
+    if constexpr (s > 0) o = pf_off<s - 1>() + (V / fft_rp(L, s - 1, PLAN)) * pf_per<s - 1>();
     return o;
   }
-  static constexpr int PF_LEN = pf_off<S - 1>() + (V / fft_r(L, S - 1)) * pf_per<S - 1>();
+  static constexpr int PF_LEN = pf_off<S - 1>() + (V / fft_rp(L, S - 1, PLAN)) * pf_per<S - 1>();
   template <int s>
   BLTT_HD static void pf_load(cx<T>* pre, const cx<T>* tw, int g) {
     if constexpr (s < S) {
-      constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), NB = V / r, P = pf_per<s>();
+      constexpr int r = fft_rp(L, s, PLAN), sg = fft_sigma_p(L, s, PLAN), NB = V / r, P = pf_per<s>();
       if constexpr (P > 0) {
 #pragma unroll
         for (int w = 0; w < NB; ++w) {
@@ -377,7 +398,7 @@ struct LineFft {
 
   template <int s, bool PF, class Ctx>
   BLTT_HD static void fwd_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw, const cx<T>* pre) {
-    constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), NB = V / r;
+    constexpr int r = fft_rp(L, s, PLAN), sg = fft_sigma_p(L, s, PLAN), NB = V / r;
     if constexpr (s > 0) {
 #pragma unroll
       for (int w = 0; w < NB; ++w) {
@@ -423,7 +444,7 @@ struct LineFft {
 
   template <int s, class Ctx>
   BLTT_HD static void inv_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
-    constexpr int r = fft_r(L, s), sg = fft_sigma(L, s), NB = V / r;
+    constexpr int r = fft_rp(L, s, PLAN), sg = fft_sigma_p(L, s, PLAN), NB = V / r;
     if constexpr (s < S - 1) {
 #pragma unroll
       for (int w = 0; w < NB; ++w) {

@@ -7,21 +7,21 @@
 
 namespace bltt {
 
-template <int L, typename TQ, bool FULL, int TPB>
+template <int L, typename TQ, bool FULL, int TPB, int PLAN>
 __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<float>()))) __launch_bounds__(TPB, 1) void k_bt_upd(
     const TQ* __restrict__ Q, const float* __restrict__ V1, const float* __restrict__ V2, float* __restrict__ Vout,
     float* __restrict__ Zout, BatchVec bv, BatchTabs bt, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
   DevCtx ctx = make_ctx();
-  bt_upd_body<L, TQ, FULL, TPB>(ctx, smem, Q, V1, V2, Vout, Zout, bv, bt, partials);
+  bt_upd_body<L, TQ, FULL, TPB, PLAN>(ctx, smem, Q, V1, V2, Vout, Zout, bv, bt, partials);
 }
 
-template <int L, int TPB>
+template <int L, int TPB, int PLAN>
 __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<float>()))) __launch_bounds__(TPB, 1) void k_bt_cs(
     const float* __restrict__ Z, float* __restrict__ Q, BatchVec bv, BatchTabs bt, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
   DevCtx ctx = make_ctx();
-  bt_cs_body<L, TPB>(ctx, smem, Z, Q, bv, bt, partials);
+  bt_cs_body<L, TPB, PLAN>(ctx, smem, Z, Q, bv, bt, partials);
 }
 
 template <int L2>
@@ -64,22 +64,22 @@ __global__ __launch_bounds__(TPB_EW) void k_bt_transpose(const double* const* __
 // launchers
 // ---------------------------------------------------------------------------
 
-template <int L, int TPB>
+template <int L, int TPB, int PLAN>
 static hipError_t go_bt(int which, const void* Q, const float* V1, const float* V2, float* Vout, float* Z,
                         float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials, hipStream_t s) {
   const int64_t blocks = bv.T * bv.S;
   const size_t lds = bt_upd_lds<L, TPB>(), lds_cs = bt_cs_lds<L, TPB>();
   switch (which) {
     case BT_START:
-      hipLaunchKernelGGL((k_bt_upd<L, double, false, TPB>), dim3((unsigned)blocks), dim3(TPB), lds, s,
+      hipLaunchKernelGGL((k_bt_upd<L, double, false, TPB, PLAN>), dim3((unsigned)blocks), dim3(TPB), lds, s,
                          (const double*)Q, V1, V2, Vout, Z, bv, bt, partials);
       break;
     case BT_UPD:
-      hipLaunchKernelGGL((k_bt_upd<L, float, true, TPB>), dim3((unsigned)blocks), dim3(TPB), lds, s, (const float*)Q,
+      hipLaunchKernelGGL((k_bt_upd<L, float, true, TPB, PLAN>), dim3((unsigned)blocks), dim3(TPB), lds, s, (const float*)Q,
                          V1, V2, Vout, Z, bv, bt, partials);
       break;
     case BT_MATVEC:
-      hipLaunchKernelGGL((k_bt_cs<L, TPB>), dim3((unsigned)blocks), dim3(TPB), lds_cs, s,
+      hipLaunchKernelGGL((k_bt_cs<L, TPB, PLAN>), dim3((unsigned)blocks), dim3(TPB), lds_cs, s,
                          (const float*)Z, Qout, bv, bt, partials);
       break;
     default:
@@ -88,13 +88,19 @@ static hipError_t go_bt(int which, const void* Q, const float* V1, const float* 
   return hipGetLastError();
 }
 
-hipError_t launch_bt(int which, int L, int tpb, const void* Q, const float* V1, const float* V2, float* Vout,
-                     float* Z, float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials, hipStream_t s) {
+hipError_t launch_bt(int which, int L, int tpb, int plan, const void* Q, const float* V1, const float* V2,
+                     float* Vout, float* Z, float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials,
+                     hipStream_t s) {
+  if (plan != 0 && (plan != 1 || !fft_plan_alt(L))) return hipErrorInvalidValue;
 #define BLTT_CASE(LL)                                                                                       \
   case LL:                                                                                                  \
-    if (tpb == 256) return go_bt<LL, 256>(which, Q, V1, V2, Vout, Z, Qout, bv, bt, partials, s);          \
+    if constexpr (fft_plan_alt(LL)) {                                                                       \
+      if (plan == 1 && tpb == 256) return go_bt<LL, 256, 1>(which, Q, V1, V2, Vout, Z, Qout, bv, bt, partials, s); \
+      if (plan == 1 && tpb == 512) return go_bt<LL, 512, 1>(which, Q, V1, V2, Vout, Z, Qout, bv, bt, partials, s); \
+    }                                                                                                       \
+    if (tpb == 256) return go_bt<LL, 256, 0>(which, Q, V1, V2, Vout, Z, Qout, bv, bt, partials, s);       \
     if constexpr (LL >= 32)                                                                                 \
-      if (tpb == 512) return go_bt<LL, 512>(which, Q, V1, V2, Vout, Z, Qout, bv, bt, partials, s);        \
+      if (tpb == 512) return go_bt<LL, 512, 0>(which, Q, V1, V2, Vout, Z, Qout, bv, bt, partials, s);     \
     return hipErrorInvalidValue;
   switch (L) {
     BLTT_CASE(2) BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64)
@@ -166,18 +172,21 @@ hipError_t launch_bt_transpose(const double* const* in_p, const double* in_b, do
   return hipGetLastError();
 }
 
-template <int L, int TPB>
+template <int L, int TPB, int PLAN = 0>
 static hipError_t attr_bt() {
   const int bytes = (int)bt_upd_lds<L, TPB>();
   hipError_t e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_upd<L, double, false, TPB>),
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_upd<L, double, false, TPB, PLAN>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
     return e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_upd<L, float, true, TPB>),
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_upd<L, float, true, TPB, PLAN>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
     return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_cs<L, TPB>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bt_cs_lds<L, TPB>());
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_cs<L, TPB, PLAN>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bt_cs_lds<L, TPB>())) != hipSuccess)
+    return e;
+  if constexpr (PLAN == 0 && fft_plan_alt(L)) return attr_bt<L, TPB, 1>();
+  return hipSuccess;
 }
 template <int L2>
 static hipError_t attr_bt_resid() {

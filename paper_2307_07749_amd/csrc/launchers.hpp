@@ -52,10 +52,11 @@ inline int64_t upd_blocks(int L, int64_t M, int64_t max_blocks) {
 // (persistent: at most max_blocks workgroups, *nparts receives the partial count)
 // prec false: no preconditioner (Zout = vhat; FP64 only)
 // qrev (start only): read Q with its time lines reversed, i.e. vhat = cq Y Q
+// plan: radix plan of the FP32 transforms (0, or 1 where fft_plan_alt(L); FP64 runs plan 0)
 template <typename T, typename TQ>
 hipError_t launch_time_upd(int L, bool full, bool prec, const TQ* Q, const T* V1, const T* V2, T* Vout, T* Zout, int64_t M,
                            const TimeTables<T>& tb, const double* coef, double* partials, int64_t max_blocks,
-                           int64_t* nparts, hipStream_t s, bool qrev = false);
+                           int64_t* nparts, hipStream_t s, bool qrev = false, int plan = 0);
 
 // up: refinement update of the iterate z (MV_RESID with TERM_SPEC only; k = 0 for none)
 template <typename T>
@@ -68,7 +69,7 @@ hipError_t launch_matvec_fft(int L, int mode, int term, T* z, T* out, const T* f
 template <typename T>
 hipError_t launch_matvec_cs(int L, int mode, T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb,
                             const IterUpd& up, double* partials, int64_t max_blocks, int64_t* nparts,
-                            hipStream_t s);
+                            hipStream_t s, int plan = 0);
 
 template <typename T>
 hipError_t launch_matvec_short(int mode, const T* z, T* out, const T* fin, int64_t M,
@@ -126,8 +127,10 @@ enum { BT_START = 0, BT_UPD = 1, BT_MATVEC = 2 };
 
 // BT_START: Z = P^{-1} (rinv_s Q) with Q the FP64 residual, Vout = rinv_s Q;
 // BT_UPD: Vout = coef_v (Q, V1, V2), Z = P^{-1} Vout; BT_MATVEC: Qout = Y T Z.
-hipError_t launch_bt(int which, int L, int tpb, const void* Q, const float* V1, const float* V2, float* Vout,
-                     float* Z, float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials, hipStream_t s);
+// plan: radix plan of the transforms (0, or 1 where fft_plan_alt(L))
+hipError_t launch_bt(int which, int L, int tpb, int plan, const void* Q, const float* V1, const float* V2,
+                     float* Vout, float* Z, float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials,
+                     hipStream_t s);
 int64_t bt_tiles(int L, int tpb, int64_t M);
 hipError_t launch_bt_resid(int L2, double* const* u, double* R, const double* Fh, const BatchVec& bv,
                            const BatchTabs& bt, const ZPool& pool, const double* zb, int K, int u_zero,

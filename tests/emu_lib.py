@@ -89,6 +89,7 @@ def lib():
         L.emu_resid_f64.argtypes = args + [P, P, P]
         L.emu_resid_f64.restype = ctypes.c_double
         L.emu_error.restype = ctypes.c_int
+        L.emu_set_plan.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -390,3 +391,17 @@ def resid_upd(prob, u, f, Zs, y, s, u_zero, two_n=False):
                                  int(u_zero), int(two_n))
     _check(gu, gf, gr)
     return gu.data.copy(), gr.data.copy(), ss
+
+
+class radix_plan:
+    """with radix_plan(1): the emulated FP32 time pass and N-point matvec use
+    the alternative radix plan (16*16*4 at N = 1024, 16*4*8 at N = 512)."""
+
+    def __init__(self, plan):
+        self.plan = plan
+
+    def __enter__(self):
+        lib().emu_set_plan(self.plan)
+
+    def __exit__(self, *exc):
+        lib().emu_set_plan(0)

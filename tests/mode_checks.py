@@ -33,3 +33,51 @@ def mode_errors(sysm, u, f, modes):
 def worst(errs, floor, target):
     """The largest ratio of a mode's error to what it is allowed (<= 1 passes)."""
     return float(np.max(errs / (target + floor)))
+
+
+# ---------------------------------------------------------------------------
+# step-kernel error metrics (sine-coordinate lines, element by element)
+# ---------------------------------------------------------------------------
+
+def _is64(dtype) -> bool:
+    return "64" in str(dtype)
+
+
+def line_err(got, ref):
+    """max over lines of max|got - ref| / max|ref| within the line (rows)."""
+    got = np.asarray(got, np.float64).reshape(ref.shape)
+    den = np.maximum(np.abs(ref).max(axis=1), 1e-300)
+    return float((np.abs(got - ref).max(axis=1) / den).max())
+
+
+def pair_err(got, ref, inp, sysm, modes, M):
+    """Time-pass error of each line, normwise over its packed pair.  The kernel
+    transforms sine modes 2j and 2j+1 as the real and imaginary parts of one
+    complex line (the last mode alone when M is odd), so its rounding is
+    relative to that complex line: it scales with the larger input of the
+    pair times the larger multiplier either mode applies,
+    max_k |lambda_{i,k}|^{-1} (eq. (9)).  When one mode's input or output is
+    much larger than its partner's, the smaller one's relative error grows by
+    that ratio (cross-talk of the two-for-one split)."""
+    got = np.asarray(got, np.float64).reshape(ref.shape)
+    row = {int(i): k for k, i in enumerate(modes)}
+    pn = (1.0 / np.abs(O.mode_precond(sysm, modes).lam)).max(axis=0)
+    im = np.abs(np.asarray(inp, np.float64)).max(axis=1)
+    part = [row[min(int(i) ^ 1, M - 1)] for i in modes]
+    scale = np.maximum(im, im[part]) * np.maximum(pn, pn[part])
+    return float((np.abs(got - ref).max(axis=1) / np.maximum(scale, 1e-300)).max())
+
+
+def tol_time(dtype, N, alpha):
+    """Rounding of the time pass on a packed pair (normwise, see pair_err):
+    four N-point transforms
+    (eps log2 N each) between alpha^{-n/N} scalings that amplify it by up to
+    1/alpha, with a margin of two: 2 eps log2(2N) / alpha (FP32).  In FP64 the
+    oracle's own dense N x N Fourier products dominate (error growing like
+    eps N / alpha): 4 eps (N + 16) / alpha."""
+    if _is64(dtype):
+        return 4 * 1.1e-16 * (N + 16) / alpha
+    return 2 * 6e-8 * math.log2(2 * N) / alpha
+
+
+TOL_MV = {"float64": 1e-12, "float32": 2e-5}

@@ -68,6 +68,7 @@ struct Lds {
 };
 
 int g_error = 0;
+int g_plan = 0;  // radix plan of the FP32 sine-basis transforms
 
 void run_grid(int tpb, int gx, int gy, size_t lds_bytes,
               const std::function<void(HostCtx&, unsigned char*)>& body) {
@@ -593,6 +594,18 @@ struct UpdRun {
       run_grid(tpb_fft<T, FK_SPEC>(), (int)(upd_persistent<T>() ? std::min<int64_t>(tiles, 3) : tiles), 1,
                fft_lds_bytes<T, FK_SPEC>(L) + upd_twl_bytes<T, L>(), [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Ft::LDS_ELEMS);
+                 // radix plan 1 where it exists (FP32, L = 512, 1024), plan 0 otherwise
+                 if constexpr (sizeof(T) == 4 && fft_plan_alt(L)) {
+                   if (g_plan == 1) {
+                     if (full)
+                       time_upd_body<T, L, TQ, true, true, true, 1>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2,
+                                                                    Vout, Zout, M, tb, coef, partials);
+                     else
+                       time_upd_body<T, L, TQ, false, true, true, 1>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2,
+                                                                     Vout, Zout, M, tb, coef, partials, qrev);
+                     return;
+                   }
+                 }
                  if (full)
                    time_upd_body<T, L, TQ, true, true>(c, reinterpret_cast<cx<T>*>(lds), red, Q, V1, V2, Vout, Zout, M,
                                                        tb, coef, partials);
@@ -629,6 +642,13 @@ struct MvSpecRun {
                cs_lds_bytes<T, L>(), [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
                  cx<T>* tabs = reinterpret_cast<cx<T>*>(lds + cs_lds_base<T, L>());
+                 if constexpr (sizeof(T) == 4 && fft_plan_alt(L)) {
+                   if (g_plan == 1) {
+                     matvec_cs_body<T, L, MODE, 1>(c, reinterpret_cast<cx<T>*>(lds), red, tabs, z, out, fin, M, tb,
+                                                   up, partials);
+                     return;
+                   }
+                 }
                  matvec_cs_body<T, L, MODE>(c, reinterpret_cast<cx<T>*>(lds), red, tabs, z, out, fin, M, tb, up,
                                             partials);
                });
@@ -789,6 +809,8 @@ void emu_wx_f32(const float* Z, float* Wa, const float* Wb, float* X, int64_t n,
 
 
 int emu_error(void) { return g_error; }
+// radix plan of the FP32 time pass and N-point matvec (0 or 1)
+void emu_set_plan(int plan) { g_plan = plan; }
 
 #define EMU_ARGS int dim, const int *m, const double *h, int64_t N, double alpha, const double *p, const double *q
 #define EMU_P make_problem(dim, m, h, N, alpha, p, q)

@@ -287,3 +287,32 @@ def test_resid_with_update(kind, dim, m, N, u_zero, two_n, nz):
     ref = mm(prob, O.time_reverse((ft - U(prob, O.bltt_apply(sysm, U(prob, ut).reshape(N, -1)))).reshape(N, -1)))
     assert rel(r, ref) < 1e-12
     assert abs(ss - np.dot(ref, ref)) < 1e-10 * np.dot(ref, ref)
+
+
+@pytest.mark.parametrize("kind,dim,m,N,alpha", [("frac", 1, 7, 1024, 0.01), ("frac", 2, 3, 512, 0.05),
+                                                ("heat", 1, 5, 1024, 0.01), ("cn", 2, 3, 512, 0.2)])
+def test_alternative_radix_plan(kind, dim, m, N, alpha):
+    """The FP32 time pass and N-point matvec with the alternative radix plan
+    (16*16*4 at N = 1024, 16*4*8 at N = 512) against the oracle, to the same
+    bars as the default plan, and against the default plan itself."""
+    prob = prob_of(kind, dim, m, N, alpha)
+    sysm = O.from_problem(prob)
+    P = O.precond_setup(sysm)
+    rng = np.random.default_rng(N + m)
+    Q, V1, V2 = (rng.standard_normal(prob.n) for _ in range(3))
+    coef = [0.7, -1.3, 0.4]
+    v0, z0, d0 = E.time_upd(prob, Q, V1, V2, coef, True, np.float32)
+    with E.radix_plan(1):
+        v1, z1, d1 = E.time_upd(prob, Q, V1, V2, coef, True, np.float32)
+        s1, ds1 = E.sym_spec(prob, Q, np.float32, form="cs")
+    s0, ds0 = E.sym_spec(prob, Q, np.float32, form="cs")
+    cast = lambda a: a.astype(np.float32).astype(np.float64)
+    vhat = coef[0] * cast(Q) + coef[1] * cast(V1) + coef[2] * cast(V2)
+    ref = ref_prec_sine(prob, sysm, P, vhat)
+    assert np.array_equal(v1, v0)
+    assert rel(z1, ref) < 5e-5 / alpha ** 0.5 and rel(z0, ref) < 5e-5 / alpha ** 0.5
+    assert rel(z1, z0) < 5e-5 / alpha ** 0.5
+    # a different butterfly order: the plan really changed (rounding differs)
+    assert not np.array_equal(z1, z0) and not np.array_equal(s1, s0)
+    refs = ref_sym_sine(prob, sysm, cast(Q))
+    assert rel(s1, refs) < TOL[np.float32] * 50 and rel(s0, refs) < TOL[np.float32] * 50

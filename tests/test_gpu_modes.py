@@ -28,6 +28,7 @@ import pytest
 from oracle import bltt_oracle as O
 from paper_2307_07749_amd import bltt
 from paper_2307_07749_amd import workloads as W
+from tests.mode_checks import TOL_MV, line_err, pair_err, tol_time
 
 pytestmark = pytest.mark.gpu
 
@@ -41,46 +42,6 @@ def _device():
     torch.cuda.set_device(0)
     yield
     torch.cuda.synchronize()
-
-
-def line_err(got, ref):
-    """max over lines of max|got - ref| / max|ref| within the line (rows)."""
-    got = np.asarray(got, np.float64).reshape(ref.shape)
-    den = np.maximum(np.abs(ref).max(axis=1), 1e-300)
-    return float((np.abs(got - ref).max(axis=1) / den).max())
-
-
-def pair_err(got, ref, inp, sysm, modes, M):
-    """Time-pass error of each line, normwise over its packed pair.  The kernel
-    transforms sine modes 2j and 2j+1 as the real and imaginary parts of one
-    complex line (the last mode alone when M is odd), so its rounding is
-    relative to that complex line: it scales with the larger input of the
-    pair times the larger multiplier either mode applies,
-    max_k |lambda_{i,k}|^{-1} (eq. (9)).  When one mode's input or output is
-    much larger than its partner's, the smaller one's relative error grows by
-    that ratio (cross-talk of the two-for-one split)."""
-    got = np.asarray(got, np.float64).reshape(ref.shape)
-    row = {int(i): k for k, i in enumerate(modes)}
-    pn = (1.0 / np.abs(O.mode_precond(sysm, modes).lam)).max(axis=0)
-    im = np.abs(np.asarray(inp, np.float64)).max(axis=1)
-    part = [row[min(int(i) ^ 1, M - 1)] for i in modes]
-    scale = np.maximum(im, im[part]) * np.maximum(pn, pn[part])
-    return float((np.abs(got - ref).max(axis=1) / np.maximum(scale, 1e-300)).max())
-
-
-def tol_time(dtype, N, alpha):
-    """Rounding of the time pass on a packed pair (normwise, see pair_err):
-    four N-point transforms
-    (eps log2 N each) between alpha^{-n/N} scalings that amplify it by up to
-    1/alpha, with a margin of two: 2 eps log2(2N) / alpha (FP32).  In FP64 the
-    oracle's own dense N x N Fourier products dominate (error growing like
-    eps N / alpha): 4 eps (N + 16) / alpha."""
-    if dtype == torch.float64:
-        return 4 * 1.1e-16 * (N + 16) / alpha
-    return 2 * 6e-8 * math.log2(2 * N) / alpha
-
-
-TOL_MV = {torch.float64: 1e-12, torch.float32: 2e-5}
 
 
 def prob_of(kind, dim, m, N, alpha, gamma=0.3):
@@ -126,9 +87,9 @@ def test_modes_steps_whole_vectors(kind, dim, m, N, alpha):
             z = cast(rng.standard_normal((M, N)))
             q, dq = s.modes_sym(cuda(z.ravel(), dt))
             ref = O.mode_sym_apply(sysm, z, modes)
-            assert line_err(q.cpu().numpy(), ref) < TOL_MV[dt], ("sym", dt)
+            assert line_err(q.cpu().numpy(), ref) < TOL_MV[str(dt).split('.')[-1]], ("sym", dt)
             dref = float(np.sum(ref * z))
-            assert abs(dq - dref) <= TOL_MV[dt] * np.linalg.norm(ref) * np.linalg.norm(z), ("sym dot", dt)
+            assert abs(dq - dref) <= TOL_MV[str(dt).split('.')[-1]] * np.linalg.norm(ref) * np.linalg.norm(z), ("sym dot", dt)
 
             # fused Lanczos update + P^{-1}: vhat = c0 q + c1 v1 + c2 v2, z = P^{-1} vhat
             qv, v1, v2 = (cast(rng.standard_normal((M, N))) for _ in range(3))
@@ -229,7 +190,7 @@ def test_modes_steps_bench_workload_sampled():
         zl = lines(z, M, N, modes)
         err = line_err(lines(q, M, N, modes), O.mode_sym_apply(sysm, zl, modes))
         print(f"  sym fp32 line err {err:.2e}", flush=True)
-        assert err < TOL_MV[torch.float32]
+        assert err < TOL_MV['float32']
         # FP32 fused Lanczos update + time pass (persistent kernel, full form)
         v1 = torch.from_numpy(rng.standard_normal(prob.n, dtype=np.float32)).cuda()
         coef = (0.9, -0.6, 0.2)
