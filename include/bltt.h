@@ -129,6 +129,12 @@ typedef struct {
                              setup autotuner: read when it holds an entry for
                              this shape, appended to when the tuner had to run  */
   int32_t fft_plan;       /* BLTT_PLAN_AUTO (default), _BASE or _ALT           */
+  int32_t eager;          /* 0 (default): the sine-basis MINRES loop captures
+                             each iteration's kernels once as a HIP graph (one
+                             per iteration position: 7 in FP64, one per stored
+                             vector in a MIXED sweep) and replays it; 1: every
+                             kernel is launched directly.  Both give identical
+                             results; with profiling on the loop is eager.   */
 } bltt_options;
 
 /* Per-solve report. */

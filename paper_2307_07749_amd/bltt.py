@@ -44,7 +44,8 @@ class Blocks(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("check_factor", ctypes.c_double), ("basis", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("initial_guess", ctypes.c_int32), ("plan_cache", ctypes.c_char_p), ("fft_plan", ctypes.c_int32)]
+                ("initial_guess", ctypes.c_int32), ("plan_cache", ctypes.c_char_p), ("fft_plan", ctypes.c_int32),
+                ("eager", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -152,7 +153,7 @@ class Solver:
     def __init__(self, dim: int, m, h, p, q, alpha: float, precision: int = FP64, inner_tol: float = 0.0,
                  max_refine: int = 0, check_factor: float = 0.0, basis: int = 0, precond: int = 0, stream=None,
                  face=None, abar: float = 1.0, initial_guess: bool = False, plan_cache: str | None = None,
-                 fft_plan: int = PLAN_AUTO):
+                 fft_plan: int = PLAN_AUTO, eager: bool = False):
         L = load()
         self._L = L
         m = list(m)
@@ -175,7 +176,7 @@ class Solver:
         self.initial_guess = bool(initial_guess)
         self._plan_cache = plan_cache.encode() if plan_cache else None
         opt = Options(precision, inner_tol, max_refine, check_factor, basis, precond, int(bool(initial_guess)),
-                      self._plan_cache, int(fft_plan))
+                      self._plan_cache, int(fft_plan), int(bool(eager)))
         self.stream = stream
         handle = ctypes.c_void_p()
         if face is None:

@@ -109,6 +109,28 @@ hipError_t g_config_err = hipSuccess;
 // layout of bltt_handle::step_dev
 constexpr int STEP_COEF = 0, STEP_SCALE = 4, STEP_Y = 8, STEP_LEN = STEP_Y + ZB_MAX;
 
+// Executable graphs of one form of the sine-basis MINRES loop, one per
+// iteration position (the buffers an iteration touches repeat with the
+// rotation of the Lanczos and direction vectors; a stored-basis sweep writes a
+// new pool vector at every position).  pubs: the mirror publications one
+// replay makes.  X and hist: the iterate and history buffers the nodes write;
+// a call with other ones rebuilds the graphs.
+struct IterGraphs {
+  static constexpr int CAP = ZB_MAX > 7 ? ZB_MAX : 7;
+  hipGraphExec_t exec[CAP] = {};
+  int32_t pubs[CAP] = {};
+  const void* X = nullptr;
+  const double* hist = nullptr;
+  void reset() {
+    for (hipGraphExec_t& e : exec) {
+      if (e) (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
+    X = nullptr;
+    hist = nullptr;
+  }
+};
+
 }  // namespace
 
 struct bltt_handle {
@@ -143,6 +165,17 @@ struct bltt_handle {
   int64_t np_aux = 0;
   SolverState* state = nullptr;
   SolverState* state_host = nullptr;
+  // host-mapped pinned copy of the state that every scalar kernel publishes
+  // (mirror: host address, mirror_dev: its device address); seq_host counts
+  // the publications enqueued, so the host waits for mirror->seq to reach it
+  SolverState* mirror = nullptr;
+  SolverState* mirror_dev = nullptr;
+  int32_t seq_host = 0;
+  // one HIP graph per iteration position of the sine-basis MINRES loop,
+  // captured on cap_stream (the caller's stream may be the null stream, which
+  // cannot be captured) and launched on stream
+  hipStream_t cap_stream = nullptr;
+  IterGraphs graphs[3];  // FP64 direction form, FP32 direction form, FP32 stored basis
   double* hist_dev = nullptr;
   int64_t hist_cap = 0;
   double* coef_one = nullptr;
@@ -553,20 +586,69 @@ int precond(bltt_handle* h, const T* in, const T* v1, const T* v2, T* vout, cons
   return BLTT_OK;
 }
 
+// Every phase the host reads afterwards publishes the state to the host
+// mirror; the delta phase, read by the device only, does not.
 int scalar(bltt_handle* h, int phase, int64_t np, double* hist, bool with_aux = false, bool zbasis = false) {
   ProfScope ps(h, BLTT_K_OTHER, 8.0 * np);
+  const bool publish = phase != SC_DELTA;
   ZBasis zb;
   zb.om = zbasis ? h->zb_dev : nullptr;
   zb.y = zbasis ? h->zb_dev + 2 * h->zb_K : nullptr;
   zb.K = zbasis ? h->zb_K : 0;
   HIPCHK(launch_scalar(phase, h->state, h->partials, np, with_aux ? h->partials_aux : nullptr,
-                       with_aux ? h->np_aux : 0, hist, h->red_scratch, h->red_half, zb, h->stream));
+                       with_aux ? h->np_aux : 0, hist, h->red_scratch, h->red_half, zb, h->stream,
+                       publish ? h->mirror_dev : nullptr));
+  if (publish) h->seq_host += 1;
   return BLTT_OK;
 }
 
+// The state after the last scalar kernel enqueued: wait until its publication
+// reaches the host mirror (polling, with the stream queried now and then so a
+// finished stream whose mirror did not move is an error rather than a hang),
+// then copy it to state_host.  Work enqueued after that scalar kernel may
+// still be running.
 int read_state(bltt_handle* h) {
-  HIPCHK(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
+  const int32_t want = h->seq_host;
+  for (uint32_t spin = 0;; ++spin) {
+    if (__atomic_load_n(&h->mirror->seq, __ATOMIC_ACQUIRE) == want) break;
+    if ((spin & 255u) == 255u) {
+      const hipError_t q = hipStreamQuery(h->stream);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(&h->mirror->seq, __ATOMIC_ACQUIRE) == want) break;
+        return BLTT_EHIP;
+      }
+      if (q != hipErrorNotReady) return BLTT_EHIP;
+    }
+  }
+  std::memcpy(h->state_host, (const void*)h->mirror, sizeof(SolverState));
+  return BLTT_OK;
+}
+
+// Record what step() enqueues on h->stream into *exec (step runs with
+// h->stream set to the handle's capture stream), then launch it on the
+// caller's stream.  The publications step() counted into seq_host are the
+// graph's; *pubs keeps their number for later replays.
+template <class Step>
+int capture_and_launch(bltt_handle* h, Step&& step, hipGraphExec_t* exec, int32_t* pubs) {
+  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  const hipStream_t user = h->stream;
+  const int32_t seq0 = h->seq_host;
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  h->stream = h->cap_stream;
+  const int rc = step();
+  h->stream = user;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+  hipError_t ei = hipErrorUnknown;
+  if (!rc && e == hipSuccess && graph) ei = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (rc || ei != hipSuccess) {
+    *exec = nullptr;
+    h->seq_host = seq0;
+    return rc ? rc : BLTT_EHIP;
+  }
+  *pubs = h->seq_host - seq0;
+  HIPCHK(hipGraphLaunch(*exec, h->stream));
   return BLTT_OK;
 }
 
@@ -668,7 +750,9 @@ int minres_core(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   }
   res->iters = j > maxit ? maxit : j;
   if (hist_host) {
-    HIPCHK(hipMemcpy(hist_host, h->hist_dev, sizeof(double) * (size_t)(res->iters + 1), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(hist_host, h->hist_dev, sizeof(double) * (size_t)(res->iters + 1), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
   }
   return BLTT_OK;
 }
@@ -732,21 +816,49 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   const double* coef_v = h->state->coef_v;
   const double* coef_w = h->state->coef_w;
   res->status = BLTT_NOCONV;
+  // graph replay unless profiling (which times every kernel) or asked not to
+  IterGraphs* g = nullptr;
+  if (!h->prof && !h->opt.eager) {
+    g = &h->graphs[zbasis ? 2 : (sizeof(T) == 8 ? 0 : 1)];
+    if (g->X != (const void*)X || g->hist != h->hist_dev) {
+      g->reset();
+      g->X = X;
+      g->hist = h->hist_dev;
+    }
+  }
   int j = 0;
   for (j = 1; j <= maxit; ++j) {
-    if ((rc = matvec<T>(h, MV_DOT, TERM_SPEC, Zc, ws.Q, nullptr, &np))) return rc;
-    if ((rc = scalar(h, SC_DELTA, np, nullptr))) return rc;
-    {
-      // at j = 1 there is no v_0: V2 = V1 with a zero coefficient
-      ProfScope ps(h, BLTT_K_TIME, (j > 1 ? 5.0 : 4.0) * n * sizeof(T));
-      HIPCHK(launch_time_upd<T, T>(L, true, h->opt.precond == BLTT_PRECOND_ABAC, ws.Q, Vc, j > 1 ? Vp : Vc, Vn, Zn,
-                                   h->M, tt, coef_v, h->partials, time_blocks<T>(h), &npt, s, false,
-                                   time_plan<T>(h)));
-    }
-    if ((rc = scalar(h, SC_BETA, npt, h->hist_dev, false, zbasis))) return rc;
-    if (!zbasis) {
-      ProfScope ps(h, BLTT_K_WX, (4.0 * sizeof(T) + 2.0 * sizeof(TX)) * n);
-      HIPCHK(launch_wx<T, TX>(Zc, Wa, Wb, X, h->n, coef_w, s));
+    auto step = [&]() -> int {
+      const hipStream_t cs = h->stream;
+      int src;
+      if ((src = matvec<T>(h, MV_DOT, TERM_SPEC, Zc, ws.Q, nullptr, &np))) return src;
+      if ((src = scalar(h, SC_DELTA, np, nullptr))) return src;
+      {
+        // at j = 1 there is no v_0: V2 = V1 with a zero coefficient
+        ProfScope ps(h, BLTT_K_TIME, (j > 1 ? 5.0 : 4.0) * n * sizeof(T));
+        HIPCHK(launch_time_upd<T, T>(L, true, h->opt.precond == BLTT_PRECOND_ABAC, ws.Q, Vc, j > 1 ? Vp : Vc, Vn,
+                                     Zn, h->M, tt, coef_v, h->partials, time_blocks<T>(h), &npt, cs, false,
+                                     time_plan<T>(h)));
+      }
+      if ((src = scalar(h, SC_BETA, npt, h->hist_dev, false, zbasis))) return src;
+      if (!zbasis) {
+        ProfScope ps(h, BLTT_K_WX, (4.0 * sizeof(T) + 2.0 * sizeof(TX)) * n);
+        HIPCHK(launch_wx<T, TX>(Zc, Wa, Wb, X, h->n, coef_w, cs));
+      }
+      return BLTT_OK;
+    };
+    if (g) {
+      // FP64/FP32 direction form: j = 1, then the period-6 rotation (V by 3,
+      // Z and W by 2); stored basis: one position per pool vector
+      const int key = zbasis ? j : (j == 1 ? 0 : 1 + (j - 2) % 6);
+      if (!g->exec[key]) {
+        if ((rc = capture_and_launch(h, step, &g->exec[key], &g->pubs[key]))) return rc;
+      } else {
+        h->seq_host += g->pubs[key];
+        HIPCHK(hipGraphLaunch(g->exec[key], s));
+      }
+    } else if ((rc = step())) {
+      return rc;
     }
     {
       T* t = Vp;
@@ -787,7 +899,9 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   }
   res->iters = j > maxit ? maxit : j;
   if (hist_host) {
-    HIPCHK(hipMemcpy(hist_host, h->hist_dev, sizeof(double) * (size_t)(res->iters + 1), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(hist_host, h->hist_dev, sizeof(double) * (size_t)(res->iters + 1), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
   }
   return BLTT_OK;
 }
@@ -995,6 +1109,9 @@ void bltt_destroy(bltt_handle* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->state_host) (void)hipHostFree(h->state_host);
+  if (h->mirror) (void)hipHostFree((void*)h->mirror);
+  for (IterGraphs& g : h->graphs) g.reset();
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
 }
 
@@ -1022,6 +1139,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (opt->precond != BLTT_PRECOND_ABAC && opt->precond != BLTT_PRECOND_NONE) return BLTT_EINVAL;
     if (opt->initial_guess != 0 && opt->initial_guess != 1) return BLTT_EINVAL;
     if (opt->fft_plan < BLTT_PLAN_AUTO || opt->fft_plan > BLTT_PLAN_ALT) return BLTT_EINVAL;
+    if (opt->eager != 0 && opt->eager != 1) return BLTT_EINVAL;
     // the unpreconditioned comparator runs the FP64 sine-basis path
     if (opt->precond == BLTT_PRECOND_NONE && (opt->precision != BLTT_FP64 || opt->basis != BLTT_BASIS_SINE))
       return BLTT_EUNSUPPORTED;
@@ -1083,6 +1201,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (opt->check_factor >= 1.0) h->opt.check_factor = opt->check_factor;
     h->opt.initial_guess = opt->initial_guess;
     h->opt.fft_plan = opt->fft_plan;
+    h->opt.eager = opt->eager;
     if (opt->plan_cache) h->plan_cache = opt->plan_cache;
   }
   h->opt.plan_cache = nullptr;  // the handle keeps its own copy of the path
@@ -1144,6 +1263,11 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
   std::memset(h->state_host, 0, sizeof(SolverState));
   if (hipMemcpy(h->state, h->state_host, sizeof(SolverState), hipMemcpyHostToDevice) != hipSuccess)
     return fail(BLTT_EHIP);
+  if (hipHostMalloc((void**)&h->mirror, sizeof(SolverState), hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess)
+    return fail(BLTT_ENOMEM);
+  std::memset((void*)h->mirror, 0, sizeof(SolverState));
+  if (hipHostGetDevicePointer((void**)&h->mirror_dev, (void*)h->mirror, 0) != hipSuccess) return fail(BLTT_EHIP);
   {
     std::vector<double> one = {1.0, 0.0, 0.0, 0.0};
     if ((rc = upload<double>(h, &h->coef_one, one))) return fail(rc);

@@ -1878,7 +1878,7 @@ struct SolverState {
   int32_t iter;
   int32_t status;    // 0 running, 1 exact convergence (beta = 0), -3 NaN, -4 breakdown
   int32_t done;      // batched sweeps: this system's sweep has stopped
-  int32_t pad;
+  int32_t seq;       // publications to the host mirror so far (k_scalar with a mirror)
 };
 
 // First stage of a long reduction: workgroup b sums partials

@@ -56,13 +56,27 @@ __global__ __launch_bounds__(TPB_EW) void k_reduce(const double* __restrict__ in
   reduce_chunk_body(ctx, red, in, n, out);
 }
 
+// mirror: null, or the host-mapped pinned copy of the state that the host
+// polls instead of synchronising the stream.  Thread 0 (which made every
+// write to *st) copies the state, then, after a system-scope fence, bumps
+// st->seq and stores it into mirror->seq last, so a host that sees the new
+// sequence number sees the whole state.
 __global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __restrict__ st,
                                                    const double* __restrict__ partials, int64_t np,
                                                    const double* __restrict__ aux, int64_t naux,
-                                                   double* __restrict__ hist, ZBasis zb) {
+                                                   double* __restrict__ hist, ZBasis zb, SolverState* mirror) {
   __shared__ double red[TPB_EW];
   DevCtx ctx = make_ctx();
   scalar_body(ctx, red, phase, st, partials, np, aux, naux, hist, zb);
+  if (mirror && ctx.tid == 0) {
+    const int32_t seq = st->seq + 1;
+    st->seq = seq;
+    SolverState copy = *st;
+    copy.seq = seq - 1;  // the mirror's current number, unchanged until the fence below
+    *mirror = copy;
+    __threadfence_system();
+    __hip_atomic_store(&mirror->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 template <typename T>
@@ -130,7 +144,7 @@ hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, 
 }
 hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
                          int64_t naux, double* hist, double* scratch, int64_t scratch_half, ZBasis zb,
-                         hipStream_t s) {
+                         hipStream_t s, SolverState* mirror) {
   // long partial-sum arrays go through one wide first stage (into scratch,
   // aux at scratch + scratch_half)
   if (np > RED_CHUNK) {
@@ -147,7 +161,7 @@ hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int
     aux = scratch + scratch_half;
     naux = nb;
   }
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(TPB_EW), 0, s, phase, st, partials, np, aux, naux, hist, zb);
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(TPB_EW), 0, s, phase, st, partials, np, aux, naux, hist, zb, mirror);
   return hipGetLastError();
 }
 

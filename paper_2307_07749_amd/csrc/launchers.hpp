@@ -111,9 +111,11 @@ template <typename TD>
 hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, hipStream_t s);
 // scratch: 2*scratch_half doubles for the first reduction stage of long
 // partial-sum arrays (at most scratch_half workgroups of RED_CHUNK each)
+// mirror: null, or a host-mapped pinned SolverState the kernel publishes the
+// state to (st->seq counts the publications; the host polls mirror->seq)
 hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
                          int64_t naux, double* hist, double* scratch, int64_t scratch_half, ZBasis zb,
-                         hipStream_t s);
+                         hipStream_t s, SolverState* mirror = nullptr);
 // u += (*sptr) * sum_i y[i] Z_i over the zl.k stored vectors
 template <typename T>
 hipError_t launch_combine(double* u, const ZList<T>& zl, const double* y, const double* sptr, int64_t n,

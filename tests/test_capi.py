@@ -37,7 +37,7 @@ def test_version_and_strerror():
     assert bltt.strerror(12345) == "unknown status"
 
 
-def _setup(prob, N=None, M=None, alpha=None, dim=None, m=None, precision=bltt.FP64):
+def _setup(prob, N=None, M=None, alpha=None, dim=None, m=None, precision=bltt.FP64, eager=0):
     L = bltt.load()
     blk = bltt.Blocks()
     blk.dim = prob.dim if dim is None else dim
@@ -50,6 +50,7 @@ def _setup(prob, N=None, M=None, alpha=None, dim=None, m=None, precision=bltt.FP
     blk.p = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     blk.q = q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     opt = bltt.Options(precision, 0.0, 0, 0.0)
+    opt.eager = eager
     h = ctypes.c_void_p()
     rc = L.bltt_setup(ctypes.byref(blk), prob.N if N is None else N, prob.M if M is None else M,
                       prob.alpha if alpha is None else alpha, ctypes.byref(opt), None, ctypes.byref(h))
@@ -63,6 +64,7 @@ def test_invalid_arguments_rejected_on_host():
     assert _setup(prob, M=prob.M + 1)[0] == -1
     assert _setup(prob, dim=4)[0] == -1
     assert _setup(prob, precision=7)[0] == -1
+    assert _setup(prob, eager=2)[0] == -1
     L = bltt.load()
     assert L.bltt_setup(None, 16, 49, 0.1, None, None, None) == -1
     assert L.bltt_pminres(None, None, 1e-8, 10, None, None, None, None) == -1
