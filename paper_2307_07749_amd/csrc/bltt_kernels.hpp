@@ -1059,7 +1059,13 @@ BLTT_HD void dst_x_body(Ctx& ctx, cx<T>* lds, double* red, const T* in,
 
 // Lines along a strided dimension: line l has elements at
 // (l / S) * S * m + (l % S) + j * S, j < m.  In place.
-template <typename T, int L, class Ctx>
+// PAIRED (S and nlines even): the two lines of a thread's pair, la even and
+// la + 1, are adjacent in memory and share one 2-element access.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair2 {
+  T a, b;
+};
+template <typename T, int L, bool PAIRED, class Ctx>
 BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t nlines, int64_t S,
                               const DstTables<T>& tb) {
   constexpr int TPB = tpb_fft<T, FK_DSTS>();
@@ -1069,9 +1075,10 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
   const int tid = ctx.tid, c = tid % NL, g = tid / NL;
   const int64_t la = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, lb = la + 1;
   const bool va = la < nlines, vb = lb < nlines;
-  const int64_t lac = va ? la : nlines - 1, lbc = vb ? lb : nlines - 1;
+  // PAIRED: va implies vb, and a missing pair reads the last pair (in bounds)
+  const int64_t lac = va ? la : (PAIRED ? nlines - 2 : nlines - 1), lbc = vb ? lb : nlines - 1;
   const int64_t basea = (lac / S) * S * m + (lac % S);
-  const int64_t baseb = (lbc / S) * S * m + (lbc % S);
+  const int64_t baseb = PAIRED ? basea + 1 : (lbc / S) * S * m + (lbc % S);
   const T ma = va ? T(1) : T(0), mb = vb ? T(1) : T(0);
   constexpr int VH = V / 2;
   cx<T> v[V];
@@ -1080,7 +1087,12 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
     const int p = g + t * s0;
     const int64_t xi = p > 0 ? p - 1 : 0;
     const T w = p > 0 ? T(1) : T(0);
-    v[t] = mkc<T>(x[basea + xi * S] * (w * ma), x[baseb + xi * S] * (w * mb));
+    if constexpr (PAIRED) {
+      const Pair2<T> ab = *reinterpret_cast<const Pair2<T>*>(x + basea + xi * S);
+      v[t] = mkc<T>(ab.a * (w * ma), ab.b * (w * mb));
+    } else {
+      v[t] = mkc<T>(x[basea + xi * S] * (w * ma), x[baseb + xi * S] * (w * mb));
+    }
   }
   odd_mirror<F, T, L>(ctx, v, lds, c, g);
   F::forward(ctx, v, lds, c, g, tb.tw);
@@ -1092,8 +1104,15 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
       const int k = F::freq(g, w, u);
       if (k >= 1 && k <= m) {
         const cx<T> zk = v[w * F::RL + u];
-        if (va) x[basea + (int64_t)(k - 1) * S] = -zk.im * tb.nrm;
-        if (vb) x[baseb + (int64_t)(k - 1) * S] = zk.re * tb.nrm;
+        if constexpr (PAIRED) {
+          Pair2<T> ab;
+          ab.a = -zk.im * tb.nrm;
+          ab.b = zk.re * tb.nrm;
+          if (va) *reinterpret_cast<Pair2<T>*>(x + basea + (int64_t)(k - 1) * S) = ab;
+        } else {
+          if (va) x[basea + (int64_t)(k - 1) * S] = -zk.im * tb.nrm;
+          if (vb) x[baseb + (int64_t)(k - 1) * S] = zk.re * tb.nrm;
+        }
       }
     }
   }

@@ -21,12 +21,12 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
                          partials, sten);
 }
 
-template <typename T, int L>
+template <typename T, int L, bool PAIRED>
 __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_DSTS>()), waves_fft<T>()) void k_dst_strided(T* __restrict__ x, int64_t nlines, int64_t S,
                                                               DstTables<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   DevCtx ctx = make_ctx();
-  dst_strided_body<T, L>(ctx, reinterpret_cast<cx<T>*>(smem), x, nlines, S, tb);
+  dst_strided_body<T, L, PAIRED>(ctx, reinterpret_cast<cx<T>*>(smem), x, nlines, S, tb);
 }
 
 template <typename T, int L>
@@ -118,7 +118,13 @@ template <typename T, int L>
 static hipError_t go_ds(T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s) {
   const int64_t blocks = fft_blocks<T, FK_DSTS>(L, nlines);
   const size_t lds = fft_lds_bytes<T, FK_DSTS>(L);
-  hipLaunchKernelGGL((k_dst_strided<T, L>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_DSTS>()), lds, s, x, nlines, S, tb);
+  // adjacent line pairs (S and nlines even) load and store as one 2-element access
+  if (S % 2 == 0 && nlines % 2 == 0)
+    hipLaunchKernelGGL((k_dst_strided<T, L, true>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_DSTS>()), lds, s, x,
+                       nlines, S, tb);
+  else
+    hipLaunchKernelGGL((k_dst_strided<T, L, false>), dim3((unsigned)blocks), dim3(tpb_fft<T, FK_DSTS>()), lds, s, x,
+                       nlines, S, tb);
   return hipGetLastError();
 }
 
@@ -177,7 +183,10 @@ static hipError_t attr_dst() {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bt)) != hipSuccess)
       return e;
   }
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_strided<T, L>),
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_strided<T, L, false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bs)) != hipSuccess)
+    return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_strided<T, L, true>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bs);
 }
 

@@ -181,7 +181,10 @@ struct DstSRun {
     static void run(T* x, int64_t nlines, int64_t S, const DstTables<T>& tb) {
       run_grid(tpb_fft<T, FK_DSTS>(), (int)fft_blocks<T, FK_DSTS>(L, nlines), 1, fft_lds_bytes<T, FK_DSTS>(L),
                [&](HostCtx& c, unsigned char* lds) {
-        dst_strided_body<T, L>(c, reinterpret_cast<cx<T>*>(lds), x, nlines, S, tb);
+        if (S % 2 == 0 && nlines % 2 == 0)
+          dst_strided_body<T, L, true>(c, reinterpret_cast<cx<T>*>(lds), x, nlines, S, tb);
+        else
+          dst_strided_body<T, L, false>(c, reinterpret_cast<cx<T>*>(lds), x, nlines, S, tb);
       });
     }
   };
