@@ -25,8 +25,16 @@
  *    iteration limit was reached (outputs are still valid), a negative
  *    BLTT_E* code on error (outputs untouched unless stated).
  *  - Size limits: N and every m_d + 1 must be powers of two with
- *    2 <= N <= 2048 and 2 <= 2(m_d + 1) <= 2048; p may be dense; q may have at
+ *    1 <= N <= 2048 and 2 <= 2(m_d + 1) <= 2048; p may be dense; q may have at
  *    most 4 leading non-zero taps (q[k] = 0 for k >= 4).  Other inputs give
+ *    BLTT_EUNSUPPORTED.
+ *  - N = 1 (a single block, Section 3): the alpha-circulant of one block is
+ *    the block itself, so P_alpha = |A_(0)| = A_(0) and MINRES ends after one
+ *    iteration at u = A_(0)^{-1} f; bltt_pminres forms that iterate per sine
+ *    mode in FP64 in either precision.  At N = 1 the variable-coefficient
+ *    setup, BLTT_PRECOND_NONE, the batched setup and the step entry points
+ *    that apply a time operator (bltt_apply_sym, bltt_apply_precond,
+ *    bltt_modes_sym, bltt_modes_lanczos*, bltt_modes_resid) give
  *    BLTT_EUNSUPPORTED.
  *  - A handle is not thread-safe; distinct handles are independent.
  */

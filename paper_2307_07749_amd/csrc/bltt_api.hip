@@ -1144,7 +1144,13 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (opt->precond == BLTT_PRECOND_NONE && (opt->precision != BLTT_FP64 || opt->basis != BLTT_BASIS_SINE))
       return BLTT_EUNSUPPORTED;
   }
-  if (!check_power(N, 2, 2048)) return BLTT_EUNSUPPORTED;
+  // N = 1 (one block, Section 3): P_alpha = |A_(0)| = A_(0), solved per sine
+  // mode; the variable-coefficient and unpreconditioned variants need N >= 2
+  if (N == 1) {
+    if (face || (opt && opt->precond == BLTT_PRECOND_NONE)) return BLTT_EUNSUPPORTED;
+  } else if (!check_power(N, 2, 2048)) {
+    return BLTT_EUNSUPPORTED;
+  }
   for (int d = 0; d < blk->dim; ++d)
     if (!check_power(2 * ((int64_t)blk->m[d] + 1), 4, 2048)) return BLTT_EUNSUPPORTED;
   int qtaps = 0, ptaps = 0;
@@ -1205,6 +1211,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (opt->plan_cache) h->plan_cache = opt->plan_cache;
   }
   h->opt.plan_cache = nullptr;  // the handle keeps its own copy of the path
+  if (N == 1) h->opt.basis = BLTT_BASIS_SINE;  // the single-step solve runs in sine coordinates
   if (face) {
     h->var = true;
     h->abar = abar;
@@ -1289,7 +1296,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     if (h->opt.precision == BLTT_MIXED)
       if ((rc = build_zpool(h))) return fail(rc);
   }
-  if (sine && h->opt.precision == BLTT_MIXED && h->opt.precond == BLTT_PRECOND_ABAC && !h->var)
+  if (sine && h->opt.precision == BLTT_MIXED && h->opt.precond == BLTT_PRECOND_ABAC && !h->var && N > 1)
     if ((rc = tune_fp32_plans(h, (int)(h->max_blocks / 4)))) return fail(rc);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(BLTT_EHIP);
   h->setup_ms = now_ms() - t0;
@@ -1356,6 +1363,33 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
     if (bn2 == 0.0) {
       relres = 0.0;
       HIPCHK(launch_fill<double>(uhat, h->n, 0.0, s));
+    } else if (h->N == 1) {
+      // One block: P_alpha = |A_(0)| = A_(0) (the alpha-circulant of a single
+      // block has no wrap, and A_(0) is SPD), so P^{-1} Y A = I and MINRES
+      // reaches u = A_(0)^{-1} f in its first iteration, whatever the
+      // precision; that iterate is formed directly, mode by mode, in FP64.
+      const double* mu = tables<double>(h).mu;
+      double r0 = 1.0;
+      if (guess) {
+        HIPCHK(launch_single_step(fhat, uhat, h->M, mu, h->p[0], h->q[0], 0, h->partials, &np, s));
+        if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+        if ((rc = read_state(h))) return rc;
+        r0 = std::sqrt(h->state_host->norm2) / bnorm;
+        if (!std::isfinite(r0)) return BLTT_ENAN;
+      }
+      if (guess && r0 <= tol) {
+        relres = r0;
+      } else {
+        HIPCHK(launch_single_step(fhat, uhat, h->M, mu, h->p[0], h->q[0], 1, h->partials, &np, s));
+        if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
+        if ((rc = read_state(h))) return rc;
+        relres = std::sqrt(h->state_host->norm2) / bnorm;
+        if (!std::isfinite(relres)) return BLTT_ENAN;
+        total_iters = 1;
+        if (hist) hist[1] = relres;
+      }
+      outer = 1;
+      status = relres <= tol ? BLTT_OK : BLTT_NOCONV;
     } else if (h->opt.precision == BLTT_FP64) {
       CoreResult cr;
       double r0 = 1.0;
@@ -1604,6 +1638,7 @@ static int step_prepare(bltt_handle* h, int32_t precision) {
 
 int bltt_apply_sym(bltt_handle* h, int32_t precision, const void* x_dev, void* y_dev) {
   if (!h || !x_dev || !y_dev) return BLTT_EINVAL;
+  if (h->N == 1) return BLTT_EUNSUPPORTED;
   const int64_t bytes = h->n * (precision == BLTT_FP64 ? 8 : 4);
   if (overlaps(x_dev, y_dev, bytes)) return BLTT_EINVAL;
   int rc = step_prepare(h, precision);
@@ -1620,6 +1655,7 @@ int bltt_apply_sym(bltt_handle* h, int32_t precision, const void* x_dev, void* y
 
 int bltt_apply_precond(bltt_handle* h, int32_t precision, const void* x_dev, void* y_dev) {
   if (!h || !x_dev || !y_dev) return BLTT_EINVAL;
+  if (h->N == 1) return BLTT_EUNSUPPORTED;
   const int64_t bytes = h->n * (precision == BLTT_FP64 ? 8 : 4);
   if (overlaps(x_dev, y_dev, bytes)) return BLTT_EINVAL;
   int rc = step_prepare(h, precision);
@@ -1745,7 +1781,7 @@ int bltt_modes_backward(bltt_handle* h, double* xhat_dev, double* x_dev) {
 int bltt_modes_sym(bltt_handle* h, int32_t precision, const void* z_dev, void* q_dev, double* dot) {
   if (!h || !z_dev || !q_dev) return BLTT_EINVAL;
   if (precision != BLTT_FP64 && precision != BLTT_FP32) return BLTT_EINVAL;
-  if (h->var) return BLTT_EUNSUPPORTED;
+  if (h->var || h->N == 1) return BLTT_EUNSUPPORTED;
   const int64_t bytes = h->n * (precision == BLTT_FP64 ? 8 : 4);
   if (overlaps(z_dev, q_dev, bytes)) return BLTT_EINVAL;
   int rc = step_tables_for(h, precision);
@@ -1767,7 +1803,7 @@ namespace {
 int lanczos_args(const bltt_handle* h, int32_t precision, const void* q_dev, const void* v1_dev, const void* v2_dev,
                  const void* vout_dev, const void* zout_dev) {
   if (!h || !q_dev || !zout_dev) return BLTT_EINVAL;
-  if (h->var) return BLTT_EUNSUPPORTED;
+  if (h->var || h->N == 1) return BLTT_EUNSUPPORTED;
   if (precision != BLTT_FP64 && precision != BLTT_FP32 && precision != BLTT_MIXED) return BLTT_EINVAL;
   if (precision == BLTT_MIXED && (v1_dev || v2_dev)) return BLTT_EINVAL;
   if (h->opt.precond != BLTT_PRECOND_ABAC && precision != BLTT_FP64) return BLTT_EUNSUPPORTED;
@@ -1849,7 +1885,7 @@ int bltt_modes_lanczos(bltt_handle* h, int32_t precision, const void* q_dev, con
 int bltt_modes_resid(bltt_handle* h, const double* fhat_dev, double* u_dev, double* r_dev,
                      const float* const* z_dev, const double* y, int32_t k, double scale, double* norm2) {
   if (!h || !fhat_dev || !u_dev || !r_dev) return BLTT_EINVAL;
-  if (h->var) return BLTT_EUNSUPPORTED;
+  if (h->var || h->N == 1) return BLTT_EUNSUPPORTED;
   if (k < 0 || k > ZB_MAX || (k > 0 && (!z_dev || !y))) return BLTT_EINVAL;
   const int64_t b8 = h->n * 8;
   if (overlaps(fhat_dev, r_dev, b8) || overlaps(u_dev, r_dev, b8) || overlaps(u_dev, fhat_dev, b8))

@@ -79,6 +79,42 @@ __global__ __launch_bounds__(TPB_EW) void k_scalar(int phase, SolverState* __res
   }
 }
 
+// One time step (N = 1): A = A_(0) = p_0 I + q_0 L_h is diagonal in sine
+// coordinates, lambda_i = p_0 + q_0 mu_i.  solve: uhat = fhat / lambda (the
+// single-block system, Section 3 with N = 1); then r = fhat - lambda uhat and
+// one partial sum of ||r||^2 per workgroup.
+__global__ __launch_bounds__(TPB_EW) void k_single_step(const double* __restrict__ fhat, double* __restrict__ uhat,
+                                                        int64_t M, const double* __restrict__ mu, double p0,
+                                                        double q0, int solve, double* __restrict__ partials) {
+  __shared__ double red[TPB_EW];
+  DevCtx ctx = make_ctx();
+  double part = 0.0;
+  const int64_t stride = (int64_t)ctx.nbx * TPB_EW;
+  for (int64_t i = (int64_t)ctx.bid * TPB_EW + ctx.tid; i < M; i += stride) {
+    const double lam = p0 + q0 * mu[i];
+    double u;
+    if (solve) {
+      u = fhat[i] / lam;
+      uhat[i] = u;
+    } else {
+      u = uhat[i];
+    }
+    const double r = fhat[i] - lam * u;
+    part += r * r;
+  }
+  const double sum = block_sum<TPB_EW>(ctx, red, part);
+  if (ctx.tid == 0) partials[ctx.bid] = sum;
+}
+
+hipError_t launch_single_step(const double* fhat, double* uhat, int64_t M, const double* mu, double p0, double q0,
+                              int solve, double* partials, int64_t* nparts, hipStream_t s) {
+  const int64_t blocks = ew_blocks(M);
+  if (nparts) *nparts = blocks;
+  hipLaunchKernelGGL(k_single_step, dim3((unsigned)blocks), dim3(TPB_EW), 0, s, fhat, uhat, M, mu, p0, q0, solve,
+                     partials);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(TPB_EW) void k_combine(double* __restrict__ u, ZList<T> zl,
                                                     const double* __restrict__ y, const double* __restrict__ sptr,

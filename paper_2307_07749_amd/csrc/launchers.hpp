@@ -113,6 +113,10 @@ hipError_t launch_axpy64(double* u, const TD* d, int64_t n, const double* sptr, 
 // partial-sum arrays (at most scratch_half workgroups of RED_CHUNK each)
 // mirror: null, or a host-mapped pinned SolverState the kernel publishes the
 // state to (st->seq counts the publications; the host polls mirror->seq)
+// one time step (N = 1): uhat = fhat / (p0 + q0 mu) when solve, then the
+// partial sums of ||fhat - (p0 + q0 mu) uhat||^2
+hipError_t launch_single_step(const double* fhat, double* uhat, int64_t M, const double* mu, double p0, double q0,
+                              int solve, double* partials, int64_t* nparts, hipStream_t s);
 hipError_t launch_scalar(int phase, SolverState* st, const double* partials, int64_t np, const double* aux,
                          int64_t naux, double* hist, double* scratch, int64_t scratch_half, ZBasis zb,
                          hipStream_t s, SolverState* mirror = nullptr);

@@ -1,8 +1,9 @@
 // CPU workgroup emulator for the HIP kernel bodies (test infrastructure).
 //
 // Runs the __host__ __device__ kernel bodies of the GPU path on host threads:
-// one std::thread per GPU thread of a workgroup, the workgroup barrier mapped
-// to a host barrier and LDS to a host array.  The tests use it to check the
+// one host thread per GPU thread of a workgroup (from a pool that lives as
+// long as the process), the workgroup barrier mapped to a host barrier and LDS
+// to a host array.  The tests use it to check the
 // kernels' index arithmetic and numerics on the CPU (with bounds-checked
 // buffers) before anything runs on a GPU.  Built with hipcc as host code; never
 // loaded by the solver.
@@ -70,21 +71,69 @@ struct Lds {
 int g_error = 0;
 int g_plan = 0;  // radix plan of the FP32 sine-basis transforms
 
+// Worker threads for the emulated workgroups, created on first need and kept:
+// run(n, job) runs job(t) on workers t = 0..n-1 at once (every one of them, as
+// the workgroup barrier needs) and returns when all have finished.
+class Pool {
+ public:
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    go_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  void run(int n, const std::function<void(int)>& job) {
+    std::unique_lock<std::mutex> lk(m_);
+    while ((int)th_.size() < n) {
+      const int idx = (int)th_.size();
+      th_.emplace_back([this, idx] { loop(idx); });
+    }
+    job_ = &job;
+    active_ = n;
+    pending_ = n;
+    ++gen_;
+    go_.notify_all();
+    done_.wait(lk, [&] { return pending_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  void loop(int idx) {
+    long seen = 0;
+    std::unique_lock<std::mutex> lk(m_);
+    for (;;) {
+      go_.wait(lk, [&] { return stop_ || (gen_ != seen && idx < active_); });
+      if (stop_) return;
+      seen = gen_;
+      const std::function<void(int)>* job = job_;
+      lk.unlock();
+      (*job)(idx);
+      lk.lock();
+      if (--pending_ == 0) done_.notify_all();
+    }
+  }
+  std::mutex m_;
+  std::condition_variable go_, done_;
+  std::vector<std::thread> th_;
+  const std::function<void(int)>* job_ = nullptr;
+  long gen_ = 0;
+  int active_ = 0, pending_ = 0;
+  bool stop_ = false;
+};
+Pool g_pool;
+
 void run_grid(int tpb, int gx, int gy, size_t lds_bytes,
               const std::function<void(HostCtx&, unsigned char*)>& body) {
   for (int by = 0; by < gy; ++by) {
     for (int bx = 0; bx < gx; ++bx) {
       Lds lds(lds_bytes);
       Barrier bar(tpb);
-      std::vector<std::thread> th;
-      th.reserve((size_t)tpb);
-      for (int t = 0; t < tpb; ++t) {
-        th.emplace_back([&, t] {
-          HostCtx c{t, bx, by, gx, &bar};
-          body(c, lds.base());
-        });
-      }
-      for (auto& x : th) x.join();
+      g_pool.run(tpb, [&](int t) {
+        HostCtx c{t, bx, by, gx, &bar};
+        body(c, lds.base());
+      });
       if (!lds.intact()) g_error = 1;
     }
   }
@@ -102,20 +151,30 @@ std::vector<T> to_t(const std::vector<double>& v) {
 }
 
 // ---- dispatch over the compile-time line length
+// EMU_MAX_L (the sanitizer build): only line lengths up to it are compiled;
+// longer ones set g_error = 2.
+#ifndef EMU_MAX_L
+#define EMU_MAX_L 4096
+#endif
+template <template <int> class F, int LL, typename... A>
+void run_L(A&&... a) {
+  if constexpr (LL <= EMU_MAX_L) F<LL>::run(a...);
+  else g_error = 2;
+}
 template <template <int> class F, typename... A>
 void with_L(int L, A&&... a) {
   switch (L) {
-    case 2: F<2>::run(a...); break;
-    case 4: F<4>::run(a...); break;
-    case 8: F<8>::run(a...); break;
-    case 16: F<16>::run(a...); break;
-    case 32: F<32>::run(a...); break;
-    case 64: F<64>::run(a...); break;
-    case 128: F<128>::run(a...); break;
-    case 256: F<256>::run(a...); break;
-    case 512: F<512>::run(a...); break;
-    case 1024: F<1024>::run(a...); break;
-    case 2048: F<2048>::run(a...); break;
+    case 2: run_L<F, 2>(a...); break;
+    case 4: run_L<F, 4>(a...); break;
+    case 8: run_L<F, 8>(a...); break;
+    case 16: run_L<F, 16>(a...); break;
+    case 32: run_L<F, 32>(a...); break;
+    case 64: run_L<F, 64>(a...); break;
+    case 128: run_L<F, 128>(a...); break;
+    case 256: run_L<F, 256>(a...); break;
+    case 512: run_L<F, 512>(a...); break;
+    case 1024: run_L<F, 1024>(a...); break;
+    case 2048: run_L<F, 2048>(a...); break;
     default: g_error = 2;
   }
 }
@@ -123,7 +182,7 @@ void with_L(int L, A&&... a) {
 // matvec line lengths are 2N (4..4096)
 template <template <int> class F, typename... A>
 void with_L2(int L, A&&... a) {
-  if (L == 4096) F<4096>::run(a...);
+  if (L == 4096) run_L<F, 4096>(a...);
   else with_L<F>(L, a...);
 }
 

@@ -83,6 +83,26 @@ def test_unsupported_sizes_rejected_on_host():
     assert _setup(prob)[0] == -7
 
 
+def test_single_block_limits_rejected_on_host():
+    """N = 1 is supported for constant-coefficient ABAC handles only."""
+    prob = W.heat_bdf(1, 7, 1, 0.1)
+    L = bltt.load()
+    blk = bltt.Blocks()
+    blk.dim = 1
+    blk.m[0], blk.m[1], blk.m[2] = 7, 1, 1
+    blk.h[0] = blk.h[1] = blk.h[2] = prob.h[0]
+    p = np.ascontiguousarray(prob.p)
+    q = np.ascontiguousarray(prob.q)
+    blk.p = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    blk.q = q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    none = bltt.Options(bltt.FP64, 0.0, 0, 0.0, bltt.SINE, bltt.PRECOND_NONE)
+    assert L.bltt_setup(ctypes.byref(blk), 1, 7, 0.1, ctypes.byref(none), None, ctypes.byref(h)) == -7
+    face = np.ones(8)
+    faces = (ctypes.c_void_p * 3)(face.ctypes.data, None, None)
+    assert L.bltt_setup_varcoef(ctypes.byref(blk), faces, 1.0, 1, 7, 0.1, None, None, ctypes.byref(h)) == -7
+
+
 def test_assumption_violation_rejected_on_host():
     prob = W.heat_bdf(1, 7, 8, 0.1)
     prob.p[1] = -4.0 * prob.p[0]                        # |A_1| dominates A_0 on low modes

@@ -289,6 +289,21 @@ def test_pminres_reaches_exact_solution(kind, alpha):
     assert res.iters <= 16
 
 
+@pytest.mark.parametrize("kind,dim", [("frac", 1), ("heat", 2), ("cn", 2), ("frac", 3)])
+def test_single_block_is_one_iteration(kind, dim):
+    """N = 1 (Section 3 with a single block): C_alpha = A_(0), so P_alpha =
+    |A_(0)| = A_(0) and the first MINRES iterate is A_(0)^{-1} f; checked
+    against a dense LU solve of the single block."""
+    m = {1: 15, 2: 7, 3: 3}[dim]
+    sysm = tiny(kind, dim=dim, m=m, N=1, alpha=0.05)
+    f = np.random.default_rng(11).standard_normal(sysm.M)
+    res = O.pminres(sysm, f, 1e-12, 10)
+    ref = np.linalg.solve(dense_A(sysm), f)
+    assert res.converged and res.iters == 1
+    assert np.linalg.norm(res.x.ravel() - ref) <= 1e-13 * np.linalg.norm(ref)
+    assert np.allclose(O.exact_solve(sysm, f).ravel(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
 def test_pminres_matches_scipy_minres():
     """Same preconditioned MINRES solution as scipy's implementation."""
     sysm = tiny("frac", dim=1, m=15, N=16, alpha=0.05, gamma=0.4)
