@@ -1710,8 +1710,18 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
 // (tb.tw then points to it; built once per workgroup).
 template <typename T>
 constexpr bool upd_twl() { return sizeof(T) == 4; }
+// The spectra sigma_k, rho_k of eq. (9) go to LDS beside the twiddles where
+// that still leaves two workgroups per CU: every tile reads 2 (V/2 + 1)
+// entries of each, which from global memory are dependent L2 round trips
+// inside the transform pipeline.
 template <typename T, int L>
-constexpr size_t upd_twl_bytes() { return upd_twl<T>() ? (size_t)L * sizeof(cx<T>) : 0; }
+constexpr bool upd_spec_lds() {
+  return upd_twl<T>() && fft_lds_bytes<T, FK_SPEC>(L) + 3 * (size_t)L * sizeof(cx<T>) <= 80 * 1024;
+}
+template <typename T, int L>
+constexpr size_t upd_twl_bytes() {
+  return upd_twl<T>() ? (size_t)(upd_spec_lds<T, L>() ? 3 : 1) * L * sizeof(cx<T>) : 0;
+}
 
 // FP32 runs persistently (workgroup b takes tiles b, b + nbx, ...); FP64,
 // whose registers allow one wavefront per SIMD, one tile per workgroup.  One
@@ -1732,6 +1742,16 @@ BLTT_HD void time_upd_body(Ctx& ctx, cx<T>* lds, double* red, const TQ* __restri
     using F = LineFft<T, L, TPB / (L / fft_V(L)), !MM, LAST_PAIRED, true, PLAN>;
     cx<T>* twl = reinterpret_cast<cx<T>*>(red + TPB);
     F::template build_twl<TPB>(ctx, twl, tb.tw);
+    if constexpr (upd_spec_lds<T, L>()) {
+      cx<T>* sgl = twl + L;
+      cx<T>* rhl = sgl + L;
+      for (int i = ctx.tid; i < L; i += TPB) {
+        sgl[i] = tb.sigma[i];
+        rhl[i] = tb.rho[i];
+      }
+      tl.sigma = sgl;
+      tl.rho = rhl;
+    }
     ctx.sync();
     tl.tw = twl;
   }
