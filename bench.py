@@ -256,6 +256,7 @@ def main() -> int:
 
     # ---- mixed path (the headline): timed with profiling off
     mixed = bltt.Solver.from_problem(prob, precision=bltt.MIXED, basis=basis)
+    plans = mixed.plan_info()  # what the setup autotuner chose (or read from a plan cache)
     u_mixed = torch.empty_like(f)
     log(f"[bench] {args.workload}: n={prob.n} warmup={args.warmup} steps={args.steps}")
     ms_mixed, (iters_mixed, info_mixed, rc_mixed) = timed(mixed, u_mixed, "mixed")
@@ -351,7 +352,7 @@ def main() -> int:
                    "precision": "mixed (FP32 MINRES sweeps, FP64 refinement)", "basis": args.basis},
         "mixed": {"ms_per_solve": ms_mixed, "ms_per_solve_profiled": ms_prof, "iters_inner": iters_mixed,
                   "iters_outer": info_mixed["iters_outer"], "true_relres": info_mixed["true_relres"],
-                  "status": int(rc_mixed), "kernels": kernels},
+                  "status": int(rc_mixed), "plans": plans, "kernels": kernels},
         "fp64": fp64,
         "per_iter": per_iter,
         "roofline": roofline,

@@ -403,14 +403,15 @@ void bltt_destroy_batched(bltt_batch *b);
 /*
  * bltt_plan_info -- the kernel plans a handle runs with: radix plans of the
  * FP32 time pass and N-point matvec (0 or 1), workgroups of the persistent
- * FP32 time pass, and where they came from (bltt_plan_source).  Any output
- * pointer may be NULL.  Errors: BLTT_EINVAL.
+ * FP32 time pass, workgroups of the FP32 N-point matvec (0: one per tile of
+ * modes, else that many persistent ones), and where they came from
+ * (bltt_plan_source).  Any output pointer may be NULL.  Errors: BLTT_EINVAL.
  * bltt_batch_plans -- per shape class of a batch: the radix plan (0 or 1) the
  * setup chose with the workgroup size of bltt_batch_classes (room for that
  * many classes; NULL allowed).  Errors: BLTT_EINVAL.
  */
 int bltt_plan_info(const bltt_handle *h, int32_t *time_plan, int32_t *cs_plan, int64_t *time_blocks,
-                   int32_t *source);
+                   int64_t *cs_blocks, int32_t *source);
 int bltt_batch_plans(const bltt_batch *b, int32_t *plans);
 
 /* Release all device memory and tables of the handle (NULL is a no-op). */

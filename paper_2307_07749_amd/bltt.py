@@ -100,7 +100,8 @@ def load() -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.bltt_profile_read.restype = ctypes.c_int
     L.bltt_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int32)]
     L.bltt_plan_info.restype = ctypes.c_int
     L.bltt_batch_plans.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     L.bltt_batch_plans.restype = ctypes.c_int
@@ -266,11 +267,11 @@ class Solver:
     def plan_info(self) -> dict:
         """Kernel plans of the FP32 sine-basis iteration (bltt_plan_info)."""
         tp, cp, src = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
-        blocks = ctypes.c_int64(0)
+        blocks, cs_blocks = ctypes.c_int64(0), ctypes.c_int64(0)
         _check(self._L.bltt_plan_info(self._h, ctypes.byref(tp), ctypes.byref(cp), ctypes.byref(blocks),
-                                      ctypes.byref(src)))
+                                      ctypes.byref(cs_blocks), ctypes.byref(src)))
         return {"time_plan": tp.value, "cs_plan": cp.value, "time_blocks": blocks.value,
-                "source": PLAN_SOURCES.get(src.value, src.value)}
+                "cs_blocks": cs_blocks.value, "source": PLAN_SOURCES.get(src.value, src.value)}
 
     def apply_space(self, x, y=None):
         """y = (I_N (x) U) x, the orthonormal sine transform of every time slice."""

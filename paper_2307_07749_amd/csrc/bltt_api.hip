@@ -193,6 +193,7 @@ struct bltt_handle {
   // the N-point matvec, workgroups of the persistent time pass (tuned at setup)
   int plan_time = 0, plan_cs = 0;
   int64_t time_blocks = 0;  // 0: max_blocks
+  int64_t cs_blocks = 0;    // FP32 N-point matvec workgroups, 0: one per tile
   int plan_source = BLTT_PLAN_SOURCE_DEFAULT;
   std::vector<void*> allocs;
   // per-kernel timing (bltt_profile_enable)
@@ -304,6 +305,8 @@ template <typename T>
 int time_plan(const bltt_handle* h) { return sizeof(T) == 4 ? h->plan_time : 0; }
 template <typename T>
 int cs_plan(const bltt_handle* h) { return sizeof(T) == 4 ? h->plan_cs : 0; }
+template <typename T>
+int64_t cs_blocks(const bltt_handle* h) { return sizeof(T) == 4 ? h->cs_blocks : 0; }
 
 template <typename T>
 int build_tables(bltt_handle* h) {
@@ -487,7 +490,7 @@ int matvec(bltt_handle* h, int mode, int term, const T* z, T* out, const T* fin,
       // FP32: N-point circulant + skew-circulant form (one wavefront per line pair)
       ProfScope ps(h, mode == MV_DOT ? BLTT_K_MATVEC : BLTT_K_RESID64, (mode == MV_DOT ? 2.0 : 3.0) * h->n * sizeof(T));
       HIPCHK(launch_matvec_cs<T>((int)h->N, mode, const_cast<T*>(z), out, fin, h->M, cs_tables<T>(h), up,
-                                 h->partials, h->max_blocks, np, h->stream, cs_plan<T>(h)));
+                                 h->partials, cs_blocks<T>(h), np, h->stream, cs_plan<T>(h)));
       return BLTT_OK;
     }
     if (mode == MV_RESID && term == TERM_STENCIL && !h->var) {
@@ -983,11 +986,13 @@ int tune_fp32_plans(bltt_handle* h, int cus) {
   if (plans::lookup(h->plan_cache, key, &val)) {
     auto f = plans::fields(val);
     const int pt = (int)f["time_plan"], pc = (int)f["cs_plan"];
-    const long bpc = f["blocks_per_cu"];
-    if ((pt == 0 || (pt == 1 && alt)) && (pc == 0 || (pc == 1 && alt)) && bpc >= 1 && bpc <= 64) {
+    const long bpc = f["blocks_per_cu"], cpc = f["cs_blocks_per_cu"];  // absent: 0, one tile per workgroup
+    if ((pt == 0 || (pt == 1 && alt)) && (pc == 0 || (pc == 1 && alt)) && bpc >= 1 && bpc <= 64 && cpc >= 0 &&
+        cpc <= 64) {
       h->plan_time = pt;
       h->plan_cs = pc;
       h->time_blocks = bpc * (int64_t)cus;
+      h->cs_blocks = cpc * (int64_t)cus;
       h->plan_source = BLTT_PLAN_SOURCE_CACHE;
       return BLTT_OK;
     }
@@ -1007,7 +1012,7 @@ int tune_fp32_plans(bltt_handle* h, int cus) {
   int rc = BLTT_OK;
   auto time_it = [&](auto&& launch, float* best_ms) {
     float best = 1e30f;
-    for (int rep = 0; rep < 4 && rc == BLTT_OK; ++rep) {
+    for (int rep = 0; rep < 8 && rc == BLTT_OK; ++rep) {
       if (hipEventRecord(a, s) != hipSuccess || launch() != hipSuccess || hipEventRecord(z, s) != hipSuccess ||
           hipEventSynchronize(z) != hipSuccess) {
         rc = BLTT_EHIP;
@@ -1042,20 +1047,28 @@ int tune_fp32_plans(bltt_handle* h, int cus) {
       }
     }
   }
+  // the N-point matvec: radix plan, and one tile per workgroup (per = 0) or
+  // 2, 4, 8 persistent workgroups per CU
   int bc_plan = 0;
-  if (rc == BLTT_OK && alt && !short_p(h)) {
+  int64_t bc_blocks = 0;
+  if (rc == BLTT_OK && !short_p(h)) {
     float best_c = 1e30f;
-    for (int plan = 0; plan <= 1; ++plan) {
-      float ms = 1e30f;
-      int64_t np = 0;
-      time_it([&]() {
-        return launch_matvec_cs<float>(L, MV_DOT, w.Z[0], w.Q, nullptr, h->M, cs_tables<float>(h), IterUpd{},
-                                       h->partials, h->max_blocks, &np, s, plan);
-      }, &ms);
-      if (rc) break;
-      if (ms < best_c) {
-        best_c = ms;
-        bc_plan = plan;
+    for (int plan = 0; plan <= (alt ? 1 : 0); ++plan) {
+      for (int per : {0, 2, 4, 8}) {
+        const int64_t blocks = per * (int64_t)cus;
+        if (per > 0 && blocks >= tiles) continue;  // the same launch as one tile per workgroup
+        float ms = 1e30f;
+        int64_t np = 0;
+        time_it([&]() {
+          return launch_matvec_cs<float>(L, MV_DOT, w.Z[0], w.Q, nullptr, h->M, cs_tables<float>(h), IterUpd{},
+                                         h->partials, blocks, &np, s, plan);
+        }, &ms);
+        if (rc) break;
+        if (ms < best_c) {
+          best_c = ms;
+          bc_plan = plan;
+          bc_blocks = blocks;
+        }
       }
     }
   }
@@ -1065,10 +1078,12 @@ int tune_fp32_plans(bltt_handle* h, int cus) {
   h->plan_time = bt_plan;
   h->plan_cs = bc_plan;
   h->time_blocks = bt_blocks;
+  h->cs_blocks = bc_blocks;
   h->plan_source = BLTT_PLAN_SOURCE_TIMED;
   plans::store(h->plan_cache, key,
                "time_plan=" + std::to_string(bt_plan) + " cs_plan=" + std::to_string(bc_plan) +
-                   " blocks_per_cu=" + std::to_string(bt_blocks / cus));
+                   " blocks_per_cu=" + std::to_string(bt_blocks / cus) +
+                   " cs_blocks_per_cu=" + std::to_string(bc_blocks / cus));
   return BLTT_OK;
 }
 
@@ -1079,11 +1094,12 @@ extern "C" {
 const char* bltt_version(void) { return "bltt-mi355x 0.2"; }
 
 int bltt_plan_info(const bltt_handle* h, int32_t* time_plan, int32_t* cs_plan, int64_t* time_blocks,
-                   int32_t* source) {
+                   int64_t* cs_blocks, int32_t* source) {
   if (!h) return BLTT_EINVAL;
   if (time_plan) *time_plan = h->plan_time;
   if (cs_plan) *cs_plan = h->plan_cs;
   if (time_blocks) *time_blocks = h->time_blocks > 0 ? h->time_blocks : h->max_blocks;
+  if (cs_blocks) *cs_blocks = h->cs_blocks;
   if (source) *source = h->plan_source;
   return BLTT_OK;
 }

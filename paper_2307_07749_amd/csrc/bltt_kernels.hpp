@@ -564,7 +564,8 @@ struct CsStage {
 // TPB: workgroup size (2*TPB/G modes per tile); the batched kernels choose it per shape.
 // TWL: the tables are the LDS copies of CsStage (stage twiddles, spectra in
 // register order), whose registers `stage` holds: the tile stores them and
-// synchronises once its line loads are issued.
+// synchronises once its line loads are issued (a null `stage`: the tables are
+// in LDS already, stored by an earlier tile of the workgroup).
 template <typename T, int L, int MODE, int TPB = tpb_fft<T, FK_SPEC>(), bool TWL = false, int PLAN = 0, class Ctx,
           class Stage = CsStage<T, L, TPB, PLAN>>
 BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
@@ -573,7 +574,14 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
   constexpr int N = L;
   using F = LineFft<T, L, NL, false, LAST_DEFAULT, TWL, PLAN>;
-  const int tid = ctx.tid, c = tid / G, g = tid % G;
+  const int tid = ctx.tid, c = tid / G;
+  int g = tid % G;
+#if defined(__HIP_DEVICE_COMPILE__)
+  // g opaque to the compiler, so that a tile loop around this function does
+  // not keep g-dependent table reads live across tiles at the cost of occupancy
+  asm volatile("" : "+v"(g));
+  g &= G - 1;
+#endif
   const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
   const bool va = ia < M, vb = ib < M;
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
@@ -600,8 +608,10 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   // the staged tables (CsStage) are stored and become visible here, with the
   // line's loads already in flight
   if constexpr (TWL) {
-    stage->store(ctx);
-    ctx.sync();
+    if (stage) {
+      stage->store(ctx);
+      ctx.sync();
+    }
   }
   if (upd) {
     // stored-vector loop outside the time loop: one vector's loads in flight together
@@ -737,20 +747,31 @@ constexpr size_t cs_lds_bytes() { return cs_lds_base<T, L>() + (cs_stage<T, L>()
 // One tile per workgroup (a loop over tiles lets the compiler keep the
 // loop-invariant twiddle and spectrum loads live across tiles, which costs
 // half the occupancy here); one partial sum per workgroup.  `tabs`: LDS for
-// the staged tables when cs_stage holds.
+// the staged tables when cs_stage holds.  Workgroup b takes tiles b, b + nbx,
+// ...: one tile each when the grid covers every tile, or persistently, with
+// the tables staged once by the first tile.
 template <typename T, int L, int MODE, int PLAN = 0, class Ctx>
 BLTT_HD void matvec_cs_body(Ctx& ctx, cx<T>* lds, double* red, cx<T>* tabs, T* z, T* __restrict__ out,
                             const T* __restrict__ fin, int64_t M, const MatvecCSTables<T>& tb, const IterUpd& up,
                             double* __restrict__ partials) {
   constexpr int TPB = tpb_fft<T, FK_SPEC>();
-  double part;
+  const int64_t ntiles = fft_tiles<T, FK_SPEC>(L, M);
+  double part = 0.0;
   if constexpr (cs_stage<T, L>()) {
-    CsStage<T, L, TPB, PLAN> st;
+    using Stage = CsStage<T, L, TPB, PLAN>;
+    Stage st;
     st.tabs = tabs;
     st.load(ctx, tb);
-    part = matvec_cs_tile<T, L, MODE, TPB, true, PLAN>(ctx, lds, ctx.bid, z, out, fin, M, st.tables(tb), up, &st);
+    const MatvecCSTables<T> lt = st.tables(tb);
+    int64_t tile = ctx.bid;
+    if (tile < ntiles)
+      part = matvec_cs_tile<T, L, MODE, TPB, true, PLAN>(ctx, lds, tile, z, out, fin, M, lt, up, &st);
+    for (tile += ctx.nbx; tile < ntiles; tile += ctx.nbx)
+      part += matvec_cs_tile<T, L, MODE, TPB, true, PLAN>(ctx, lds, tile, z, out, fin, M, lt, up,
+                                                          static_cast<Stage*>(nullptr));
   } else {
-    part = matvec_cs_tile<T, L, MODE, TPB, false, PLAN>(ctx, lds, ctx.bid, z, out, fin, M, tb, up);
+    for (int64_t tile = ctx.bid; tile < ntiles; tile += ctx.nbx)
+      part += matvec_cs_tile<T, L, MODE, TPB, false, PLAN>(ctx, lds, tile, z, out, fin, M, tb, up);
   }
   const double sum = block_sum<TPB>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;

@@ -10,7 +10,7 @@
 namespace bltt {
 
 template <typename T, int L, int MODE, int PLAN>
-__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_matvec_cs(
+__global__ __attribute__((amdgpu_waves_per_eu(MODE == MV_DOT ? min_waves_upd<T>() : 1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_SPEC>()), waves_fft<T>()) void k_matvec_cs(
     T* z, T* __restrict__ out, const T* __restrict__ fin, int64_t M, MatvecCSTables<T> tb, IterUpd up,
     double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -25,8 +25,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
 template <typename T, int L, int PLAN = 0>
 static hipError_t go_cs(int mode, T* z, T* out, const T* fin, int64_t M, const MatvecCSTables<T>& tb,
                         const IterUpd& up, double* partials, int64_t max_blocks, int64_t* nparts, hipStream_t s) {
-  (void)max_blocks;  // one tile per workgroup
-  const int64_t blocks = fft_tiles<T, FK_SPEC>(L, M);
+  // max_blocks > 0: at most that many workgroups, each looping over tiles;
+  // 0: one tile per workgroup
+  const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
+  const int64_t blocks = max_blocks > 0 ? std::min(tiles, max_blocks) : tiles;
   const size_t lds = cs_lds_bytes<T, L>();
   if (nparts) *nparts = blocks;
   if (mode == MV_DOT)

@@ -90,6 +90,7 @@ def lib():
         L.emu_resid_f64.restype = ctypes.c_double
         L.emu_error.restype = ctypes.c_int
         L.emu_set_plan.argtypes = [ctypes.c_int]
+        L.emu_set_cs_blocks.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -405,3 +406,17 @@ class radix_plan:
 
     def __exit__(self, *exc):
         lib().emu_set_plan(0)
+
+
+class cs_blocks:
+    """with cs_blocks(n): the emulated N-point matvec runs on n persistent
+    workgroups (each looping over tiles of mode pairs) instead of one per tile."""
+
+    def __init__(self, blocks):
+        self.blocks = blocks
+
+    def __enter__(self):
+        lib().emu_set_cs_blocks(self.blocks)
+
+    def __exit__(self, *exc):
+        lib().emu_set_cs_blocks(0)

@@ -70,6 +70,7 @@ struct Lds {
 
 int g_error = 0;
 int g_plan = 0;  // radix plan of the FP32 sine-basis transforms
+int g_cs_blocks = 0;  // workgroups of the N-point matvec (0: one per tile)
 
 // Worker threads for the emulated workgroups, created on first need and kept:
 // run(n, job) runs job(t) on workers t = 0..n-1 at once (every one of them, as
@@ -700,7 +701,9 @@ struct MvSpecRun {
                     double* partials) {
       constexpr int NL = lines_per_block<T, FK_SPEC>(L);
       using Fm = LineFft<T, L, NL, false, LAST_DEFAULT>;
-      run_grid(tpb_fft<T, FK_SPEC>(), (int)fft_tiles<T, FK_SPEC>(L, M), 1,
+      const int64_t tiles = fft_tiles<T, FK_SPEC>(L, M);
+      const int blocks = (int)(g_cs_blocks > 0 ? std::min<int64_t>(tiles, g_cs_blocks) : tiles);
+      run_grid(tpb_fft<T, FK_SPEC>(), blocks, 1,
                cs_lds_bytes<T, L>(), [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
                  cx<T>* tabs = reinterpret_cast<cx<T>*>(lds + cs_lds_base<T, L>());
@@ -873,6 +876,8 @@ void emu_wx_f32(const float* Z, float* Wa, const float* Wb, float* X, int64_t n,
 int emu_error(void) { return g_error; }
 // radix plan of the FP32 time pass and N-point matvec (0 or 1)
 void emu_set_plan(int plan) { g_plan = plan; }
+// workgroups of the N-point matvec (0: one per tile, else persistent)
+void emu_set_cs_blocks(int blocks) { g_cs_blocks = blocks; }
 
 #define EMU_ARGS int dim, const int *m, const double *h, int64_t N, double alpha, const double *p, const double *q
 #define EMU_P make_problem(dim, m, h, N, alpha, p, q)

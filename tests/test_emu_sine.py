@@ -289,6 +289,25 @@ def test_resid_with_update(kind, dim, m, N, u_zero, two_n, nz):
     assert abs(ss - np.dot(ref, ref)) < 1e-10 * np.dot(ref, ref)
 
 
+@pytest.mark.parametrize("plan", [0, 1])
+@pytest.mark.parametrize("kind,dim,m,N,blocks", [("frac", 2, 7, 1024, 3), ("frac", 2, 15, 64, 1),
+                                                 ("cn", 1, 31, 512, 1)])
+def test_persistent_matvec(kind, dim, m, N, blocks, plan):
+    """The N-point matvec on a few persistent workgroups, each looping over
+    tiles (the tables staged once by its first tile): the same products as one
+    tile per workgroup, bit for bit, and the same dot up to summation order."""
+    if plan == 1 and N not in (512, 1024):
+        pytest.skip("the alternative plan exists at N = 512 and 1024")
+    prob = prob_of(kind, dim, m, N, 0.05)
+    Q = np.random.default_rng(N + m).standard_normal(prob.n)
+    with E.radix_plan(plan):
+        s0, d0 = E.sym_spec(prob, Q, np.float32, form="cs")
+        with E.cs_blocks(blocks):
+            s1, d1 = E.sym_spec(prob, Q, np.float32, form="cs")
+    assert np.array_equal(s1, s0)
+    assert d1 == pytest.approx(d0, rel=1e-12)
+
+
 @pytest.mark.parametrize("kind,dim,m,N,alpha", [("frac", 1, 7, 1024, 0.01), ("frac", 2, 3, 512, 0.05),
                                                 ("heat", 1, 5, 1024, 0.01), ("cn", 2, 3, 512, 0.2)])
 def test_alternative_radix_plan(kind, dim, m, N, alpha):

@@ -96,6 +96,7 @@ def test_autotuner_writes_and_reads_plan_cache(tmp_path):
     assert first["time_plan"] in (0, 1) and first["cs_plan"] in (0, 1)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     assert first["time_blocks"] in (2 * cus, 4 * cus, 8 * cus)
+    assert first["cs_blocks"] in (0, 2 * cus, 4 * cus, 8 * cus)
     lines = open(cache).read().splitlines()
     assert len(lines) == 1 and "N=1024" in lines[0] and "M=3969" in lines[0]
     s = bltt.Solver.from_problem(prob, precision=bltt.MIXED, plan_cache=cache)
@@ -106,8 +107,8 @@ def test_autotuner_writes_and_reads_plan_cache(tmp_path):
     finally:
         s.close()
     assert second["source"] == "cache"
-    assert {k: second[k] for k in ("time_plan", "cs_plan", "time_blocks")} == \
-        {k: first[k] for k in ("time_plan", "cs_plan", "time_blocks")}
+    assert {k: second[k] for k in ("time_plan", "cs_plan", "time_blocks", "cs_blocks")} == \
+        {k: first[k] for k in ("time_plan", "cs_plan", "time_blocks", "cs_blocks")}
     assert rc == bltt.OK and info["true_relres"] <= 1e-8
     assert len(open(cache).read().splitlines()) == 1
     # an FP64 handle runs no FP32 kernels: nothing to tune
