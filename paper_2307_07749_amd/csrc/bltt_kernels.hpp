@@ -45,11 +45,18 @@ template <typename T, int FK>
 constexpr int lines_per_block(int L) {
   return tpb_fft<T, FK>() / (L / (L < 16 ? L : 16));
 }
-// dynamic LDS: NL padded lines + one double per thread for reductions
+// The FP64 sine transforms (strided lines, and x-lines fused with the layout
+// change) exchange real and imaginary parts in turn (LineFft SPLIT): half the
+// LDS per workgroup, so three waves per SIMD fit where two did.
+template <typename T>
+constexpr bool dst_split() { return sizeof(T) == 8; }
+// dynamic LDS: NL padded lines (half as many bytes for a split exchange) + one
+// double per thread for reductions
 template <typename T, int FK>
 constexpr size_t fft_lds_bytes(int L) {
-  return (size_t)lines_per_block<T, FK>(L) * (size_t)fft_padded(L) * sizeof(cx<T>) +
-         (size_t)tpb_fft<T, FK>() * sizeof(double);
+  const size_t slots = (size_t)lines_per_block<T, FK>(L) * (size_t)fft_padded(L);
+  const bool split = FK == FK_DSTS && dst_split<T>();
+  return (split ? (slots + 1) / 2 : slots) * sizeof(cx<T>) + (size_t)tpb_fft<T, FK>() * sizeof(double);
 }
 // workgroups of a launch over `units` spatial points or lines, rounded up to a
 // multiple of 8 for the XCD-aware tile order
@@ -966,14 +973,38 @@ BLTT_HD void odd_mirror(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g) {
   constexpr int V = fft_V(L), s0 = fft_sigma(L, 0), VH = V / 2;
   // slots t < V/2 hold positions p = g + t*s0 < L/2 (loaded), slots t >= V/2
   // the positions p >= L/2, whose values are -e_{L-p} (e_{L/2} = 0)
+  if constexpr (F::SPLIT_X) {
+    // real parts, then imaginary parts, through the T buffer
+    T* ls = reinterpret_cast<T*>(lds);
 #pragma unroll
-  for (int t = 0; t < VH; ++t) lds[F::idx(c, g + t * s0)] = v[t];
-  ctx.sync();
+    for (int t = 0; t < VH; ++t) ls[F::idx(c, g + t * s0)] = v[t].re;
+    ctx.sync();
+    T re[VH];
 #pragma unroll
-  for (int t = VH; t < V; ++t) {
-    const int p = g + t * s0;
-    const cx<T> w = lds[F::idx(c, p == L / 2 ? 0 : L - p)];
-    v[t] = p == L / 2 ? mkc<T>(T(0), T(0)) : mkc<T>(-w.re, -w.im);
+    for (int t = VH; t < V; ++t) {
+      const int p = g + t * s0;
+      re[t - VH] = ls[F::idx(c, p == L / 2 ? 0 : L - p)];
+    }
+    ctx.sync();
+#pragma unroll
+    for (int t = 0; t < VH; ++t) ls[F::idx(c, g + t * s0)] = v[t].im;
+    ctx.sync();
+#pragma unroll
+    for (int t = VH; t < V; ++t) {
+      const int p = g + t * s0;
+      const T im = ls[F::idx(c, p == L / 2 ? 0 : L - p)];
+      v[t] = p == L / 2 ? mkc<T>(T(0), T(0)) : mkc<T>(-re[t - VH], -im);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < VH; ++t) lds[F::idx(c, g + t * s0)] = v[t];
+    ctx.sync();
+#pragma unroll
+    for (int t = VH; t < V; ++t) {
+      const int p = g + t * s0;
+      const cx<T> w = lds[F::idx(c, p == L / 2 ? 0 : L - p)];
+      v[t] = p == L / 2 ? mkc<T>(T(0), T(0)) : mkc<T>(-w.re, -w.im);
+    }
   }
 }
 
@@ -1091,7 +1122,7 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
                               const DstTables<T>& tb) {
   constexpr int TPB = tpb_fft<T, FK_DSTS>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
-  using F = LineFft<T, L, NL, true, LAST_DEFAULT>;
+  using F = LineFft<T, L, NL, true, LAST_DEFAULT, false, 0, dst_split<T>()>;
   const int m = L / 2 - 1;
   const int tid = ctx.tid, c = tid % NL, g = tid / NL;
   const int64_t la = xcd_tile(ctx.bid, ctx.nbx) * (2 * NL) + 2 * c, lb = la + 1;
@@ -1165,7 +1196,9 @@ BLTT_HD void dst_xt_body(Ctx& ctx, cx<T>* lds, double* red, const T* __restrict_
   // linear last stage both ways: lane g holds frequencies g + G w + u K, so
   // DIR 1's global stores coalesce and DIR 0's stage writes hit consecutive
   // banks (the default deal puts consecutive lanes 16 entries apart)
-  using F = LineFft<T, L, NL, false, LAST_LINEAR>;
+  using F = LineFft<T, L, NL, false, LAST_LINEAR, false, 0, dst_split<T>()>;
+  static_assert((size_t)W2 * (L / 2 - 1) * sizeof(T) <= (size_t)F::LDS_ELEMS * sizeof(cx<T>),
+                "the staging rows fit in the exchange buffer");
   static_assert(G <= TPB, "one line per at most one workgroup");
   const int m = L / 2 - 1;
   const int64_t rows = M / m, nblk = (N + W2 - 1) / W2;

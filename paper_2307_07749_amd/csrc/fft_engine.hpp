@@ -216,7 +216,10 @@ enum LastMode {
 // build_twl) instead of power products of the global table: for stage s, entry
 // off_s + (u-1) sg_s + j holds w^(u j L/B_s) for butterfly j = beta mod sg_s,
 // so consecutive lanes read consecutive entries.
-template <typename T, int L, int NL, bool INTERLEAVED, int LAST, bool TWL = false, int PLAN = 0>
+// SPLIT: every exchange moves the real parts, then the imaginary parts,
+// through an LDS buffer of T (half the bytes of one of cx<T>), so that more
+// workgroups fit on a CU; `lds` then points to that T buffer.
+template <typename T, int L, int NL, bool INTERLEAVED, int LAST, bool TWL = false, int PLAN = 0, bool SPLIT = false>
 struct LineFft {
   static constexpr int V = fft_V(L);
   static constexpr int S = fft_S(L);
@@ -224,7 +227,9 @@ struct LineFft {
   static constexpr int RL = fft_rp(L, S - 1, PLAN);         // last radix
   static constexpr int K = L / RL;            // last-stage butterflies per line
   static constexpr int LP = fft_padded(L);    // padded line length
-  static constexpr int LDS_ELEMS = NL * LP;
+  // exchange buffer, in units of cx<T>
+  static constexpr int LDS_ELEMS = SPLIT ? (NL * LP + 1) / 2 : NL * LP;
+  static constexpr bool SPLIT_X = SPLIT;
   // Lines stored one after another (not interleaved) and at most one
   // wavefront per line: every exchange stays inside one wavefront, whose LDS
   // accesses execute in order, so a wavefront-scope barrier replaces the
@@ -399,7 +404,7 @@ struct LineFft {
   template <int s, bool PF, class Ctx>
   BLTT_HD static void fwd_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw, const cx<T>* pre) {
     constexpr int r = fft_rp(L, s, PLAN), sg = fft_sigma_p(L, s, PLAN), NB = V / r;
-    if constexpr (s > 0) {
+    if constexpr (s > 0 && !SPLIT) {
 #pragma unroll
       for (int w = 0; w < NB; ++w) {
         const int b = beta<s>(g, w);
@@ -424,16 +429,51 @@ struct LineFft {
       }
     }
     if constexpr (s + 1 < S) {
-      xsync(ctx);
+      if constexpr (SPLIT) {
+        split_exchange<s, s + 1>(ctx, v, lds, c, g);
+      } else {
+        xsync(ctx);
 #pragma unroll
-      for (int w = 0; w < NB; ++w) {
-        const int b = beta<s>(g, w);
+        for (int w = 0; w < NB; ++w) {
+          const int b = beta<s>(g, w);
 #pragma unroll
-        for (int u = 0; u < r; ++u) lds[idx(c, pos<s>(b, u))] = v[w * r + u];
+          for (int u = 0; u < r; ++u) lds[idx(c, pos<s>(b, u))] = v[w * r + u];
+        }
+        xsync(ctx);
       }
-      xsync(ctx);
       fwd_stage<s + 1, PF>(ctx, v, lds, c, g, tw, pre);
     }
+  }
+
+  // SPLIT: the exchange from the slots of stage sw to those of stage sr, real
+  // parts first (each part's writes, a barrier, its reads), then the
+  // imaginary parts; a barrier between the two passes keeps the second
+  // pass's writes behind every read of the first.
+  template <int sw, int sr, class Ctx>
+  BLTT_HD static void split_exchange(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g) {
+    constexpr int rw = fft_rp(L, sw, PLAN), rr = fft_rp(L, sr, PLAN);
+    T* ls = reinterpret_cast<T*>(lds);
+    T re[V];
+    xsync(ctx);
+#pragma unroll
+    for (int w = 0; w < V / rw; ++w)
+#pragma unroll
+      for (int u = 0; u < rw; ++u) ls[idx(c, pos<sw>(beta<sw>(g, w), u))] = v[w * rw + u].re;
+    xsync(ctx);
+#pragma unroll
+    for (int w = 0; w < V / rr; ++w)
+#pragma unroll
+      for (int t = 0; t < rr; ++t) re[w * rr + t] = ls[idx(c, pos<sr>(beta<sr>(g, w), t))];
+    xsync(ctx);
+#pragma unroll
+    for (int w = 0; w < V / rw; ++w)
+#pragma unroll
+      for (int u = 0; u < rw; ++u) ls[idx(c, pos<sw>(beta<sw>(g, w), u))] = v[w * rw + u].im;
+    xsync(ctx);
+#pragma unroll
+    for (int w = 0; w < V / rr; ++w)
+#pragma unroll
+      for (int t = 0; t < rr; ++t) v[w * rr + t] = mkc<T>(re[w * rr + t], ls[idx(c, pos<sr>(beta<sr>(g, w), t))]);
   }
 
   // ---- inverse: v[w*RL+u] = X[freq(g,w,u)]  ->  v[w*r0+t] = L x[pos<0>(beta<0>(g,w),t)]
@@ -445,7 +485,7 @@ struct LineFft {
   template <int s, class Ctx>
   BLTT_HD static void inv_stage(Ctx& ctx, cx<T>* v, cx<T>* lds, int c, int g, const cx<T>* tw) {
     constexpr int r = fft_rp(L, s, PLAN), sg = fft_sigma_p(L, s, PLAN), NB = V / r;
-    if constexpr (s < S - 1) {
+    if constexpr (s < S - 1 && !SPLIT) {
 #pragma unroll
       for (int w = 0; w < NB; ++w) {
         const int b = beta<s>(g, w);
@@ -464,14 +504,18 @@ struct LineFft {
       dft<r, +1>(v + w * r);
     }
     if constexpr (s > 0) {
-      xsync(ctx);
+      if constexpr (SPLIT) {
+        split_exchange<s, s - 1>(ctx, v, lds, c, g);
+      } else {
+        xsync(ctx);
 #pragma unroll
-      for (int w = 0; w < NB; ++w) {
-        const int b = beta<s>(g, w);
+        for (int w = 0; w < NB; ++w) {
+          const int b = beta<s>(g, w);
 #pragma unroll
-        for (int t = 0; t < r; ++t) lds[idx(c, pos<s>(b, t))] = v[w * r + t];
+          for (int t = 0; t < r; ++t) lds[idx(c, pos<s>(b, t))] = v[w * r + t];
+        }
+        xsync(ctx);
       }
-      xsync(ctx);
       inv_stage<s - 1>(ctx, v, lds, c, g, tw);
     }
   }

@@ -21,25 +21,32 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_
                          partials, sten);
 }
 
+template <typename T, int L>
+constexpr size_t dstxt_lds_bytes() {
+  const size_t slots = (size_t)(DSTXT_TPB / (L / fft_V(L))) * (size_t)fft_padded(L);
+  return (dst_split<T>() ? (slots + 1) / 2 : slots) * sizeof(cx<T>) + DSTXT_TPB * sizeof(double);
+}
+// waves per SIMD the FP64 sine transforms ask for: the split exchange leaves
+// LDS for three, and their registers fit three (at most 168 VGPRs)
+template <typename T>
+constexpr int dst_min_waves() { return dst_split<T>() ? 3 : 1; }
+template <typename T>
+constexpr int dst_max_waves() { return dst_split<T>() ? 4 : max_waves_fft<T>(); }
+
 template <typename T, int L, bool PAIRED>
-__global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, FK_DSTS>()), waves_fft<T>()) void k_dst_strided(T* __restrict__ x, int64_t nlines, int64_t S,
+__global__ __attribute__((amdgpu_waves_per_eu(dst_min_waves<T>(), dst_max_waves<T>()))) __launch_bounds__((tpb_fft<T, FK_DSTS>()), waves_fft<T>()) void k_dst_strided(T* __restrict__ x, int64_t nlines, int64_t S,
                                                               DstTables<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   DevCtx ctx = make_ctx();
   dst_strided_body<T, L, PAIRED>(ctx, reinterpret_cast<cx<T>*>(smem), x, nlines, S, tb);
 }
 
-template <typename T, int L>
-constexpr size_t dstxt_lds_bytes() {
-  return (size_t)(DSTXT_TPB / (L / fft_V(L))) * (size_t)fft_padded(L) * sizeof(cx<T>) + DSTXT_TPB * sizeof(double);
-}
-
 template <typename T, int L, int DIR>
-__global__ __launch_bounds__(DSTXT_TPB) void k_dst_xt(const T* __restrict__ in, T* __restrict__ out, int64_t N,
+__global__ __attribute__((amdgpu_waves_per_eu(dst_min_waves<T>(), dst_max_waves<T>()))) __launch_bounds__(DSTXT_TPB) void k_dst_xt(const T* __restrict__ in, T* __restrict__ out, int64_t N,
                                                       int64_t M, DstTables<T> tb, double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NL = DSTXT_TPB / (L / fft_V(L));
-  using F = LineFft<T, L, NL, false, LAST_DEFAULT>;
+  using F = LineFft<T, L, NL, false, LAST_LINEAR, false, 0, dst_split<T>()>;
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
   dst_xt_body<T, L, DIR>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, out, N, M, tb, partials);

@@ -387,7 +387,7 @@ struct DstXtRun {
     static void run(int dir, const double* in, double* out, int64_t N, int64_t M, const DstTables<double>& tb,
                     double* partials) {
       constexpr int NL = DSTXT_TPB / (L / fft_V(L));
-      using Fx = LineFft<double, L, NL, false, LAST_DEFAULT>;
+      using Fx = LineFft<double, L, NL, false, LAST_LINEAR, false, 0, dst_split<double>()>;
       constexpr int m = L / 2 - 1;
       const int64_t blocks = dstxt_blocks(M / m, N, dstxt_lines<double, L>());
       run_grid(DSTXT_TPB, (int)blocks, 1, sizeof(cx<double>) * Fx::LDS_ELEMS + DSTXT_TPB * sizeof(double),
