@@ -30,7 +30,7 @@ HOT_CLASSES = {"sine": ["matvec", "time_prec", "wx_update"],
 
 def cpu_baseline(workload: str, tol: float, budget_s: float = 12.0) -> dict:
     """The CPU oracle, as it stands, on a bounded sample of the workload: the
-    same problem with m = 63 (M = 63^2) instead of 511, solved repeatedly until
+    same problem with m = 127 (M = 127^2) instead of 511, solved repeatedly until
     `budget_s` seconds have passed; scaled to the full M linearly (a lower
     bound on the oracle's time, whose sine transforms grow faster than M)."""
     import numpy as np
@@ -38,7 +38,7 @@ def cpu_baseline(workload: str, tol: float, budget_s: float = 12.0) -> dict:
     from paper_2307_07749_amd import workloads as W
 
     full, seed = W.workload(workload)
-    m_s = 63
+    m_s = 127
     prob = W.fractional_l1(full.dim, m_s, full.N, full.meta["gamma"], full.alpha)
     f = W.rhs_normal(prob, seed)
     sysm = O.from_problem(prob)
