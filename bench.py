@@ -161,13 +161,14 @@ def batched_bench(args) -> int:
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     tpbs = b.classes()
+    radix_plans = b.plans()  # per class: 0 = 16*8*8 / 16*8*4, 1 = 16*16*4 / 16*4*8 (N = 1024 / 512)
     b.close()
     out = {"metric": "batched time-to-1e-8 solves, 64 uneven 2D fractional instances x 4 RHS",
            "value": len(fs) * 1e3 / ms, "unit": "system-solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "batched64x4", "systems": len(fs), "unknowns": unknowns, "tol": args.tol,
-                      "classes": len(tpbs), "workgroup_sizes": tpbs},
+                      "classes": len(tpbs), "workgroup_sizes": tpbs, "radix_plans": radix_plans},
            "iters": {"min": min(iters), "max": max(iters)},
            "max_true_relres": max(inf["true_relres"] for inf in infos), "status": int(rc),
            "unknowns_per_s": unknowns * 1e3 / ms}
