@@ -211,8 +211,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the solver on one GPU only "
-              f"(one MI355X holds the whole workload; see DESIGN.md for how it would shard)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported; the solver runs on one GPU only "
+              f"(one MI355X holds the whole workload; a run over several GPUs would split the sine modes, "
+              f"with two all-to-all transposes per solve)", file=sys.stderr)
         return 2
 
     if args.workload == "batched64x4":

@@ -21,7 +21,7 @@ lower triangular Toeplitz systems" (arXiv 2307.07749):
   (Definitions 2-3, eqs. (11)-(13)); P^{-1} y = C^{-1/2} (C^{-1/2})^* y applied
   as two three-step procedures (Section 5.1).
 
-Readings where the paper is silent or ambiguous (each is listed in the design doc):
+Readings where the paper is silent or ambiguous:
   * MINRES is not printed; the standard preconditioned MINRES of Paige-Saunders
     in the Elman-Silvester-Wathen form is used, zero initial guess.
   * The stopping test is the relative, unpreconditioned 2-norm of the
