@@ -1133,6 +1133,10 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
   const int64_t baseb = PAIRED ? basea + 1 : (lbc / S) * S * m + (lbc % S);
   const T ma = va ? T(1) : T(0), mb = vb ? T(1) : T(0);
   constexpr int VH = V / 2;
+  // every stage's twiddle bases in flight with the line's loads, so no stage
+  // waits for its table after an exchange barrier
+  cx<T> pre[F::PF_LEN > 0 ? F::PF_LEN : 1];
+  F::template pf_load<0>(pre, tb.tw, g);
   cx<T> v[V];
 #pragma unroll
   for (int t = 0; t < VH; ++t) {
@@ -1147,7 +1151,7 @@ BLTT_HD void dst_strided_body(Ctx& ctx, cx<T>* lds, T* __restrict__ x, int64_t n
     }
   }
   odd_mirror<F, T, L>(ctx, v, lds, c, g);
-  F::forward(ctx, v, lds, c, g, tb.tw);
+  F::forward_pf(ctx, v, lds, c, g, pre);
   // all reads of this workgroup's lines happened before the barriers inside forward()
 #pragma unroll
   for (int w = 0; w < V / F::RL; ++w) {
