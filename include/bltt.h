@@ -398,7 +398,7 @@ int bltt_setup_batched(const bltt_blocks *blk, const int64_t *N, const int64_t *
 int bltt_pminres_batched(bltt_batch *b, const double *const *f_dev, double tol, int32_t maxit,
                          double *const *u_dev, int32_t *iters, double *hist, bltt_info *info);
 int bltt_batch_classes(const bltt_batch *b, int32_t *nclasses, int32_t *tpb);
-void bltt_destroy_batched(bltt_batch *b);
+void bltt_destroy_batched(bltt_batch *b);  /* the same as bltt_destroy on a batch */
 
 /*
  * bltt_plan_info -- the kernel plans a handle runs with: radix plans of the
@@ -414,8 +414,11 @@ int bltt_plan_info(const bltt_handle *h, int32_t *time_plan, int32_t *cs_plan, i
                    int64_t *cs_blocks, int32_t *source);
 int bltt_batch_plans(const bltt_batch *b, int32_t *plans);
 
-/* Release all device memory and tables of the handle (NULL is a no-op). */
-void bltt_destroy(bltt_handle *h);
+/* Release all device memory, tables, graphs and streams of a handle from
+ * bltt_setup, bltt_setup_varcoef or bltt_setup_batched (the handle types are
+ * told apart by a tag the library keeps in each); NULL is a no-op.  The
+ * handle must not be used afterwards. */
+void bltt_destroy(void *handle);
 
 /* Static message for a status code. */
 const char *bltt_strerror(int code);

@@ -444,7 +444,7 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None):
-            self._L.bltt_destroy_batched(self._h)
+            self._L.bltt_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -134,6 +134,7 @@ struct IterGraphs {
 }  // namespace
 
 struct bltt_handle {
+  uint32_t magic = HANDLE_MAGIC;  // first member (bltt_destroy tells handle types apart)
   hipStream_t stream = nullptr;
   int device = 0;  // device current at setup (its scratch copy serves the no-alloc entry point)
   int dim = 0;
@@ -1119,8 +1120,16 @@ const char* bltt_strerror(int code) {
   return "unknown status";
 }
 
-void bltt_destroy(bltt_handle* h) {
-  if (!h) return;
+void bltt_destroy(void* handle) {
+  if (!handle) return;
+  const uint32_t magic = *static_cast<const uint32_t*>(handle);
+  if (magic == BATCH_MAGIC) {
+    bltt_destroy_batched(static_cast<bltt_batch*>(handle));
+    return;
+  }
+  if (magic != HANDLE_MAGIC) return;
+  bltt_handle* h = static_cast<bltt_handle*>(handle);
+  h->magic = 0;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (void* p : h->allocs) (void)hipFree(p);
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);

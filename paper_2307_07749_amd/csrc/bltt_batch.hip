@@ -81,6 +81,7 @@ struct BatchClass {
 }  // namespace
 
 struct bltt_batch {
+  uint32_t magic = BATCH_MAGIC;  // first member (bltt_destroy tells handle types apart)
   int count = 0, nrhs = 0;
   bltt_options opt{};
   std::string plan_cache;  // autotuner plan file ("" = none)
@@ -444,7 +445,8 @@ enum Step { ST_START, ST_ITER, ST_RESID, ST_FINISH, ST_DONE };
 extern "C" {
 
 void bltt_destroy_batched(bltt_batch* b) {
-  if (!b) return;
+  if (!b || b->magic != BATCH_MAGIC) return;
+  b->magic = 0;
   for (auto& c : b->cls) {
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     destroy_class(c);

@@ -10,6 +10,10 @@
 
 namespace bltt {
 
+// First member of every handle type, so that one destroy call serves them all
+constexpr uint32_t HANDLE_MAGIC = 0x424c5448u;  // single system
+constexpr uint32_t BATCH_MAGIC = 0x424c5442u;   // batch
+
 // Device-side context: thread/block indices and the workgroup barrier.
 struct DevCtx {
   int tid, bid, bid_y, nbx;

@@ -155,3 +155,23 @@ def test_batched_rejects_aliased_outputs():
         assert rc == bltt.OK
     finally:
         b.close()
+
+
+def test_one_destroy_for_both_handle_types():
+    """bltt_destroy releases a batch as well as a single-system handle (each
+    keeps a type tag as its first member); the batch alias does the same."""
+    probs = [W.fractional_l1(2, 7, 64, 0.4, 0.01), W.fractional_l1(1, 15, 32, 0.6, 0.05)]
+    L = bltt.load()
+    for _ in range(2):
+        b = bltt.Batch(probs, 1)
+        L.bltt_destroy(b._h)          # the batch through the common entry point
+        b._h = None
+        s = bltt.Solver.from_problem(probs[0], precision=bltt.MIXED)
+        L.bltt_destroy(s._h)
+        s._h = None
+    b = bltt.Batch(probs, 2)
+    fs = [torch.from_numpy(W.rhs_normal(p, 7 + k)).cuda() for p in probs for k in range(2)]
+    _, _, _, _, rc = b.pminres(fs, 1e-8, 200)
+    L.bltt_destroy_batched(b._h)
+    b._h = None
+    assert rc == bltt.OK
