@@ -343,7 +343,9 @@ enum bltt_kernel_class {
   BLTT_K_WX = 5,            /* MINRES direction and iterate update               */
   BLTT_K_RESID64 = 6,       /* FP64 residual Y(f - A u)                          */
   BLTT_K_OTHER = 7,         /* right-hand side, casts, fills, scalar kernels     */
-  BLTT_K_COUNT = 8
+  BLTT_K_TIME_START = 8,    /* time pass of a Krylov start (z_1 = P^{-1} b, sine
+                               basis); BLTT_K_TIME counts the iterations' passes */
+  BLTT_K_COUNT = 9
 };
 int bltt_profile_enable(bltt_handle *h, int32_t enable);
 int bltt_profile_read(bltt_handle *h, int32_t kernel_class, int64_t *launches, double *total_ms,

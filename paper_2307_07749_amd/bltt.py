@@ -20,7 +20,8 @@ SINE, PHYSICAL = 0, 1  # Krylov basis (bltt_basis)
 PRECOND_ABAC, PRECOND_NONE = 0, 1  # bltt_precond
 PLAN_AUTO, PLAN_BASE, PLAN_ALT = 0, 1, 2  # bltt_fft_plan
 PLAN_SOURCES = {0: "default", 1: "timed", 2: "cache", 3: "forced"}
-KERNEL_CLASSES = ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update", "resid64", "other"]
+KERNEL_CLASSES = ["matvec", "dst_x_vupd", "dst_strided", "time_prec", "dst_x_dot", "wx_update", "resid64", "other",
+                  "time_start"]
 OK, NOCONV = 0, 1
 STATUS = {0: "BLTT_OK", 1: "BLTT_NOCONV", -1: "BLTT_EINVAL", -2: "BLTT_EASSUMPTION", -3: "BLTT_ENAN",
           -4: "BLTT_EBREAKDOWN", -5: "BLTT_ENOMEM", -6: "BLTT_EHIP", -7: "BLTT_EUNSUPPORTED"}

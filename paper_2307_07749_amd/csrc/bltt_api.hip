@@ -195,6 +195,7 @@ struct bltt_handle {
   int plan_time = 0, plan_cs = 0;
   int64_t time_blocks = 0;  // 0: max_blocks
   int64_t cs_blocks = 0;    // FP32 N-point matvec workgroups, 0: one per tile
+  double* rsc_dev = nullptr;  // 1/scale of the FP32 residual the refinement hands to its next sweep
   int plan_source = BLTT_PLAN_SOURCE_DEFAULT;
   std::vector<void*> allocs;
   // per-kernel timing (bltt_profile_enable)
@@ -808,7 +809,7 @@ int minres_spec(bltt_handle* h, TX* X, int maxit, double eta_tol, const double* 
   // v_1 = b, z_1 = P^{-1} b, beta_1 = sqrt(<b, z_1>)
   {
     const bool copy = (const void*)bsrc != (const void*)Vc;
-    ProfScope ps(h, BLTT_K_TIME, n * (sizeof(TB) + (copy ? 2.0 : 1.0) * sizeof(T)));
+    ProfScope ps(h, BLTT_K_TIME_START, n * (sizeof(TB) + (copy ? 2.0 : 1.0) * sizeof(T)));
     HIPCHK(launch_time_upd<T, TB>(L, false, h->opt.precond == BLTT_PRECOND_ABAC, bsrc, nullptr, nullptr,
                                   copy ? Vc : nullptr, Zc, h->M, tt, bcoef, h->partials, time_blocks<T>(h), &npt, s,
                                   brev, time_plan<T>(h)));
@@ -1304,6 +1305,7 @@ int setup_impl(const bltt_blocks* blk, const double* const* face, double abar, i
     std::vector<double> one = {1.0, 0.0, 0.0, 0.0};
     if ((rc = upload<double>(h, &h->coef_one, one))) return fail(rc);
     if ((rc = dalloc(h, &h->step_dev, (size_t)STEP_LEN))) return fail(rc);
+    if ((rc = dalloc(h, &h->rsc_dev, 1))) return fail(rc);
   }
   for (int d = 0; d < h->dim; ++d)
     if (h->var && (rc = upload<double>(h, &h->face_dev[d], face_host[d]))) return fail(rc);
@@ -1450,11 +1452,18 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         relres = std::sqrt(h->state_host->norm2) / bnorm;
       }
     } else {
-      // FP64 refinement around FP32 MINRES sweeps on r / ||r|| (state->rinv)
+      // FP64 refinement around FP32 MINRES sweeps on r / ||r|| (state->rinv).
+      // With dense p the residual pass hands the next sweep its right-hand
+      // side as FP32, r / ||fhat|| (read once; its norm is summed in FP64 before
+      // the rounding, and the rounding, 6e-8 relative, is far inside the
+      // sweep's own tolerance); that sweep then runs on it unscaled and its
+      // update is multiplied by ||fhat|| (rsc_dev).
       double rnorm = bnorm;
       status = BLTT_NOCONV;
       int hist_pos = 0;
       std::vector<double> hbuf;
+      bool r32 = false;  // the current residual is in w32.V[0] as FP32, times 1/||fhat||
+      HIPCHK(hipMemcpyAsync(h->rsc_dev, &bnorm, sizeof(double), hipMemcpyHostToDevice, s));
       if (guess) {
         // refinement from uhat: the first sweep solves for the residual of the guess
         if ((rc = matvec<double>(h, MV_RESID, TERM_SPEC, uhat, h->R64, fhat, &np))) return rc;
@@ -1475,8 +1484,14 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
         hbuf.assign((size_t)left + 2, 0.0);
         // r = b = Y fhat on the first sweep (read from fhat reversed), then the residual
         const bool from_b = outer == 0 && !guess;
-        rc = minres_spec<float, float, double>(h, nullptr, left, sweep_tol(h, tol, relres), nullptr, 0.0, 1.0, hbuf.data(),
-                                               &cr, from_b ? fhat : h->R64, &h->state->rinv, true, from_b);
+        const bool rhs32 = r32;  // this sweep's right-hand side is r / ||fhat|| in FP32
+        if (rhs32)
+          rc = minres_spec<float, float, float>(h, nullptr, left, sweep_tol(h, tol, relres), nullptr, 0.0, 1.0,
+                                                hbuf.data(), &cr, h->w32.V[0], h->coef_one, true, false);
+        else
+          rc = minres_spec<float, float, double>(h, nullptr, left, sweep_tol(h, tol, relres), nullptr, 0.0, 1.0,
+                                                 hbuf.data(), &cr, from_b ? fhat : h->R64, &h->state->rinv, true,
+                                                 from_b);
         if (rc) return rc;
         if (hist)
           for (int k = 1; k <= cr.iters; ++k) hist[hist_pos + k] = hbuf[(size_t)k];
@@ -1500,12 +1515,15 @@ int bltt_pminres(bltt_handle* h, const double* f_dev, double tol, int32_t maxit,
           for (int i = 0; i < ZB_MAX; ++i) up.z[i] = i < cr.iters ? h->zpool[i] : nullptr;
           up.k = cr.iters;
           up.y = ycoef;
-          up.s = &h->state->rscale;
+          up.s = rhs32 ? h->rsc_dev : &h->state->rscale;
           up.u_zero = outer == 1 && !guess ? 1 : 0;
-          ProfScope ps(h, BLTT_K_RESID64, (32.0 + 4.0 * cr.iters - (up.u_zero ? 8.0 : 0.0)) * h->n);
+          up.r32 = h->w32.V[0];
+          up.r32_scale = 1.0 / bnorm;
+          ProfScope ps(h, BLTT_K_RESID64, (28.0 + 4.0 * cr.iters - (up.u_zero ? 8.0 : 0.0)) * h->n);
           HIPCHK(launch_matvec_fft<double>((int)(2 * h->N), MV_RESID, TERM_SPEC, uhat, h->R64, fhat, h->M,
                                            mv_tables<double>(h), up, h->partials, s));
           np = mv_blocks<double>(true, (int)(2 * h->N), h->M);
+          r32 = true;
         }
         if ((rc = scalar(h, SC_NORM, np, nullptr))) return rc;
         if ((rc = read_state(h))) return rc;

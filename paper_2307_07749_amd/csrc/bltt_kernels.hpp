@@ -279,6 +279,11 @@ struct IterUpd {
   const double* y;
   const double* s;
   int u_zero;        // u not read (first sweep: the iterate starts at zero)
+  // non-null: the residual goes to r32 as FP32, times r32_scale, instead of
+  // to `out` (the next sweep's right-hand side, read once in FP32); its norm
+  // is still summed in FP64 before the rounding
+  float* r32 = nullptr;
+  double r32_scale = 1.0;
 };
 
 // Layout (MM): false = time-major vectors (element (i, n) at n*M + i, the ABI
@@ -289,7 +294,7 @@ struct IterUpd {
 // Batched use: the stored vectors of system s start at up.z[i] + zoff, and
 // k >= 0 / y / sptr replace up.k / up.y / up.s (the pointer table stays in the
 // kernel arguments instead of a per-thread copy).
-template <typename T, int L, int MODE, int TERM, bool MM, class Ctx>
+template <typename T, int L, int MODE, int TERM, bool MM, bool R32 = false, class Ctx>
 BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
                                const T* __restrict__ fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
                                int64_t zoff = 0, int k = -1, const double* y = nullptr,
@@ -460,14 +465,17 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
       }
     } else {
       const int64_t off = (int64_t)n * ts;
+      (void)off;
       if (va) {
         const T r = fa[MODE == MV_RESID ? t : 0] - ya;
-        oa[offr] = r;
+        if constexpr (R32) up.r32[sa + offr] = (float)(r * up.r32_scale);
+        else oa[offr] = r;
         part += (double)r * (double)r;
       }
       if (vb) {
         const T r = fb[MODE == MV_RESID ? t : 0] - yb;
-        ob[offr] = r;
+        if constexpr (R32) up.r32[sb + offr] = (float)(r * up.r32_scale);
+        else ob[offr] = r;
         part += (double)r * (double)r;
       }
     }
@@ -477,11 +485,11 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
   return part;
 }
 
-template <typename T, int L, int MODE, int TERM, bool MM, class Ctx>
+template <typename T, int L, int MODE, int TERM, bool MM, bool R32 = false, class Ctx>
 BLTT_HD void matvec_fft_body(Ctx& ctx, cx<T>* lds, double* red, T* z, T* __restrict__ out,
                              const T* __restrict__ fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
                              double* __restrict__ partials) {
-  const double part = matvec_fft_tile<T, L, MODE, TERM, MM>(ctx, lds, xcd_tile(ctx.bid, ctx.nbx), z, out, fin, M,
+  const double part = matvec_fft_tile<T, L, MODE, TERM, MM, R32>(ctx, lds, xcd_tile(ctx.bid, ctx.nbx), z, out, fin, M,
                                                               tb, up);
   const double s = block_sum<tpb_fft<T, fk_mv<MM, L>()>()>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = s;

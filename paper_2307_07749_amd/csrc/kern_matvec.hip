@@ -4,7 +4,8 @@
 
 namespace bltt {
 
-template <typename T, int L, int MODE, int TERM>
+// R32: the residual is written as FP32 to up.r32 (FP64 sine-coordinate residual only)
+template <typename T, int L, int MODE, int TERM, bool R32 = false>
 __global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<T>()))) __launch_bounds__((tpb_fft<T, fk_mv<TERM == TERM_SPEC, L>()>()), waves_fft<T>()) void k_matvec_fft(T* z, T* __restrict__ out,
                                                              const T* __restrict__ fin, int64_t M,
                                                              MatvecTables<T> tb, IterUpd up,
@@ -15,8 +16,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<T>()))) __launch_
   DevCtx ctx = make_ctx();
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
   // the sine-coordinate forms work on the mode-major layout
-  matvec_fft_body<T, L, MODE, TERM, TERM == TERM_SPEC>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin, M, tb,
-                                                       up, partials);
+  matvec_fft_body<T, L, MODE, TERM, TERM == TERM_SPEC, R32>(ctx, reinterpret_cast<cx<T>*>(smem), red, z, out, fin,
+                                                            M, tb, up, partials);
 }
 
 template <typename T, int MODE>
@@ -45,6 +46,14 @@ static hipError_t go_mv(int mode, int term, T* z, T* out, const T* fin, int64_t 
     const unsigned blocks = (unsigned)fft_blocks<T, FK>(L, M);                                        \
     const unsigned tpb = (unsigned)tpb_fft<T, FK>();                                                  \
     const size_t lds = fft_lds_bytes<T, FK>(L);                                                       \
+    if constexpr (sizeof(T) == 8 && MO == MV_RESID && TE == TERM_SPEC) {                             \
+      if (up.r32) {                                                                                   \
+        hipLaunchKernelGGL((k_matvec_fft<T, L, MO, TE, true>), dim3(blocks), dim3(tpb), lds, s, z, out, fin, \
+                           M, tb, up, partials);                                                      \
+        return hipGetLastError();                                                                     \
+      }                                                                                               \
+    }                                                                                                 \
+    if (up.r32) return hipErrorInvalidValue;                                                          \
     hipLaunchKernelGGL((k_matvec_fft<T, L, MO, TE>), dim3(blocks), dim3(tpb), lds, s, z, out, fin, M, tb, \
                        up, partials);                                                                 \
     return hipGetLastError();                                                                         \
@@ -132,6 +141,10 @@ static hipError_t attr_mv() {
   if (e != hipSuccess) return e;
   BLTT_MV_VARIANTS(BLTT_ATTR1)
 #undef BLTT_ATTR1
+  if constexpr (sizeof(T) == 8)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_matvec_fft<T, L, MV_RESID, TERM_SPEC, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fft_lds_bytes<T, fk_mv<true, L>()>(L));
   return e;
 }
 

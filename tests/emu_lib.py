@@ -76,6 +76,9 @@ def lib():
         L.emu_resid_upd_f64.argtypes = args + [P, P, P, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
                                                ctypes.c_int]
         L.emu_resid_upd_f64.restype = ctypes.c_double
+        L.emu_resid_upd_r32_f64.argtypes = args + [P, P, P, ctypes.c_double, P, ctypes.c_int, P, ctypes.c_double,
+                                                   ctypes.c_int]
+        L.emu_resid_upd_r32_f64.restype = ctypes.c_double
         L.emu_state_size.restype = ctypes.c_int64
         L.emu_transpose_f64.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
         L.emu_set_faces.argtypes = [P, P, P]
@@ -390,6 +393,20 @@ def resid_upd(prob, u, f, Zs, y, s, u_zero, two_n=False):
     yy = np.ascontiguousarray(y, dtype=np.float64)
     ss = lib().emu_resid_upd_f64(*args, gu.ptr, gf.ptr, gr.ptr, zs.ctypes.data, len(Zs), yy.ctypes.data, float(s),
                                  int(u_zero), int(two_n))
+    _check(gu, gf, gr)
+    return gu.data.copy(), gr.data.copy(), ss
+
+
+def resid_upd_r32(prob, u, f, Zs, y, s, u_zero, r32_scale):
+    """As resid_upd in the 2N-point form, with the residual returned as FP32, times r32_scale."""
+    args, keep = _common(prob)
+    gu = Guarded(u, np.float64)
+    gf = Guarded(f, np.float64)
+    gr = Guarded(np.zeros(u.size), np.float32)
+    zs = np.ascontiguousarray(np.stack(Zs).astype(np.float32))
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    ss = lib().emu_resid_upd_r32_f64(*args, gu.ptr, gf.ptr, gr.ptr, float(r32_scale), zs.ctypes.data, len(Zs),
+                                     yy.ctypes.data, float(s), int(u_zero))
     _check(gu, gf, gr)
     return gu.data.copy(), gr.data.copy(), ss
 

@@ -734,6 +734,13 @@ struct MvSpec2nRun {
       run_grid(tpb_fft<T, FK>(), (int)fft_blocks<T, FK>(L, M), 1, fft_lds_bytes<T, FK>(L),
                [&](HostCtx& c, unsigned char* lds) {
                  double* red = reinterpret_cast<double*>(lds + sizeof(cx<T>) * Fm::LDS_ELEMS);
+                 if constexpr (sizeof(T) == 8 && MODE == MV_RESID) {
+                   if (up.r32) {
+                     matvec_fft_body<T, L, MODE, TERM_SPEC, true, true>(c, reinterpret_cast<cx<T>*>(lds), red, z,
+                                                                        out, fin, M, tb, up, partials);
+                     return;
+                   }
+                 }
                  matvec_fft_body<T, L, MODE, TERM_SPEC, true>(c, reinterpret_cast<cx<T>*>(lds), red, z, out, fin, M,
                                                               tb, up, partials);
                });
@@ -954,6 +961,22 @@ double emu_resid_upd_f64(EMU_ARGS, double* u, const double* f, double* r, const 
   up.s = &s;
   up.u_zero = u_zero;
   return apply_spec<double, MV_RESID>(P, u, r, f, true, &up, two_n != 0);
+}
+// as emu_resid_upd_f64 in the 2N-point form, with the residual written as FP32
+// to r32, times r32_scale (r is not written)
+double emu_resid_upd_r32_f64(EMU_ARGS, double* u, const double* f, float* r32, double r32_scale, const float* zs,
+                             int k, const double* y, double s, int u_zero) {
+  const Problem P = EMU_P;
+  IterUpd up{};
+  for (int i = 0; i < ZB_MAX; ++i) up.z[i] = i < k ? zs + (int64_t)i * P.N * P.M : nullptr;
+  up.k = k;
+  up.y = y;
+  up.s = &s;
+  up.u_zero = u_zero;
+  up.r32 = r32;
+  up.r32_scale = r32_scale;
+  std::vector<double> unused((size_t)(P.N * P.M), 0.0);
+  return apply_spec<double, MV_RESID>(P, u, unused.data(), f, true, &up, true);
 }
 
 }  // extern "C"

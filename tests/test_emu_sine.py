@@ -289,6 +289,24 @@ def test_resid_with_update(kind, dim, m, N, u_zero, two_n, nz):
     assert abs(ss - np.dot(ref, ref)) < 1e-10 * np.dot(ref, ref)
 
 
+@pytest.mark.parametrize("u_zero", [False, True])
+@pytest.mark.parametrize("kind,dim,m,N", [("frac", 1, 31, 32), ("frac", 2, 7, 64)])
+def test_resid_with_update_fp32_output(kind, dim, m, N, u_zero):
+    """The refinement step handing the next sweep an FP32 right-hand side:
+    the same update and residual as the FP64 output, the residual rounded
+    once to FP32 after scaling, and the norm summed before the rounding."""
+    prob = prob_of(kind, dim, m, N)
+    rng = np.random.default_rng(52)
+    u, f = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
+    Zs = [rng.standard_normal(prob.n).astype(np.float32) for _ in range(4)]
+    y, s, scale = np.array([0.5, -1.25, 2.0, 0.75]), 0.37, 1.0 / 37.5
+    u64, r64, ss64 = E.resid_upd(prob, u, f, Zs, y, s, u_zero, True)
+    u32, r32, ss32 = E.resid_upd_r32(prob, u, f, Zs, y, s, u_zero, scale)
+    assert np.array_equal(u32, u64)
+    assert ss32 == ss64
+    assert np.array_equal(r32.astype(np.float32), (r64 * scale).astype(np.float32))
+
+
 @pytest.mark.parametrize("plan", [0, 1])
 @pytest.mark.parametrize("kind,dim,m,N,blocks", [("frac", 2, 7, 1024, 3), ("frac", 2, 15, 64, 1),
                                                  ("cn", 1, 31, 512, 1)])
