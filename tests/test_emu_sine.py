@@ -104,7 +104,7 @@ def test_time_upd_fp64_rhs(kind, dim, m, N, alpha):
 
 
 SPEC_CASES = [("frac", 1, 31, 32), ("heat", 2, 7, 16), ("cn", 2, 5, 8), ("frac", 3, 3, 8), ("cn", 3, 3, 4),
-              ("frac", 1, 3, 2048), ("heat", 1, 3, 2), ("frac", 2, 15, 64)]
+              ("frac", 1, 3, 2048), ("heat", 1, 3, 2), ("frac", 2, 15, 64), ("frac", 1, 7, 1024)]
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -269,7 +269,8 @@ def test_stored_basis_cap():
 @pytest.mark.parametrize("nz", [3, 6])
 @pytest.mark.parametrize("two_n", [False, True])
 @pytest.mark.parametrize("u_zero", [False, True])
-@pytest.mark.parametrize("kind,dim,m,N", [("frac", 1, 31, 32), ("cn", 2, 5, 8), ("frac", 2, 7, 64)])
+@pytest.mark.parametrize("kind,dim,m,N", [("frac", 1, 31, 32), ("cn", 2, 5, 8), ("frac", 2, 7, 64),
+                                          ("frac", 1, 5, 1024)])
 def test_resid_with_update(kind, dim, m, N, u_zero, two_n, nz):
     """The mixed path's fused refinement step: u <- u + s sum_i y_i Z_i, then
     r = Y(f - A u), against the same two steps in FP64 on the host (nz = 6:
@@ -290,7 +291,7 @@ def test_resid_with_update(kind, dim, m, N, u_zero, two_n, nz):
 
 
 @pytest.mark.parametrize("u_zero", [False, True])
-@pytest.mark.parametrize("kind,dim,m,N", [("frac", 1, 31, 32), ("frac", 2, 7, 64)])
+@pytest.mark.parametrize("kind,dim,m,N", [("frac", 1, 31, 32), ("frac", 2, 7, 64), ("frac", 2, 3, 1024)])
 def test_resid_with_update_fp32_output(kind, dim, m, N, u_zero):
     """The refinement step handing the next sweep an FP32 right-hand side:
     the same update and residual as the FP64 output, the residual rounded
