@@ -1,4 +1,4 @@
-// Driver for the sanitizer build of the kernel-body emulator (emu.cpp): runs
+// Main program of the sanitizer build of the kernel-body emulator (emu.cpp): runs
 // every emulated kernel family once per problem on exactly sized host arrays,
 // so that AddressSanitizer flags any access outside them and
 // UndefinedBehaviorSanitizer any undefined arithmetic (shifts, overflow,
