@@ -440,6 +440,7 @@ MatvecTables<T> mv_tables(bltt_handle* h) {
   for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
   tb.qtaps = h->qtaps;
   tb.grid = make_grid(h);
+  tb.mx = (int)h->m[0];
   return tb;
 }
 
@@ -454,6 +455,7 @@ MatvecCSTables<T> cs_tables(bltt_handle* h) {
   tb.mu = t.mu;
   for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
   tb.qtaps = h->qtaps;
+  tb.mx = (int)h->m[0];
   return tb;
 }
 
@@ -553,6 +555,7 @@ TimeTables<T> time_tables(bltt_handle* h, bool aux) {
   for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
   tt.qtaps = h->qtaps;
   tt.aux = aux ? h->partials_aux : nullptr;
+  tt.mx = (int)h->m[0];
   return tt;
 }
 

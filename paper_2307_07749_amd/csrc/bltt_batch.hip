@@ -133,6 +133,7 @@ BatchVec bvec(BatchClass& c) {
   BatchVec bv;
   bv.n = c.n;
   bv.M = c.M;
+  bv.mx = c.m[0];
   bv.T = c.T;
   bv.S = c.S;
   bv.active = c.active_dev;

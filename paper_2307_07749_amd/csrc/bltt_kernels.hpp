@@ -110,6 +110,34 @@ constexpr int ZB_MAX = 32;   // stored Z vectors of one FP32 sweep, at most
 // ---------------------------------------------------------------------------
 BLTT_HD int64_t xcd_tile(int bid, int nb) { return (int64_t)(bid & 7) * (nb >> 3) + (bid >> 3); }
 
+// The two sine modes that share complex line t of the sine-basis kernels
+// (mode-major vectors, modes numbered x fastest in rows of mx = m_0, which is
+// odd).  Pairing 2j with 2j+1 throughout would put the last mode of every
+// other row, the highest x frequency and the smallest in a solve, in one line
+// with the first of the next row, the lowest and the largest; FP32 transforms
+// of that line leave the small mode with the large one's rounding, amplified
+// by their ratio (about 4 (m_0 + 1)^2 / pi^2).  Instead each row pairs its
+// modes 2j, 2j+1 within the row, and the last modes of rows r and r+1 (r even)
+// pair with each other: both carry the highest x frequency, so their scales
+// stay within a small factor.  There are ceil(M/2) lines either way; ib = M
+// (no partner) for a lone last mode, and ia >= M past the last line.  With
+// mx = 1 this is the plain 2j, 2j+1 pairing.
+BLTT_HD void mode_pair(int64_t t, int64_t M, int mx, int64_t& ia, int64_t& ib) {
+  const uint32_t pr = (uint32_t)(mx - 1) >> 1;
+  const uint32_t rows = (uint32_t)M / (uint32_t)mx;
+  const uint32_t within = rows * pr;
+  const uint32_t tt = (uint32_t)t;
+  if (tt < within) {
+    const uint32_t r = tt / pr, j = tt - r * pr;
+    ia = (int64_t)r * mx + 2 * (int64_t)j;
+    ib = ia + 1;
+  } else {
+    const int64_t r = 2 * (int64_t)(tt - within);
+    ia = r * mx + mx - 1;
+    ib = r + 1 < (int64_t)rows ? ia + mx : M;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // workgroup sum of one double per thread, result valid in thread 0
 // ---------------------------------------------------------------------------
@@ -264,6 +292,7 @@ struct MatvecTables {
   T q[4];
   int qtaps;
   Grid grid;
+  int mx = 1;         // mode-major lines: modes per x-row (mode_pair)
 };
 
 enum { MV_DOT = 0, MV_RESID = 1 };
@@ -305,7 +334,8 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
   constexpr int N = L / 2, VH = V / 2;  // slots t < VH hold times g + t*s0 < N
   using F = LineFft<T, L, NL, !MM, LAST_DEFAULT>;
   const int tid = ctx.tid, c = MM ? tid / G : tid % NL, g = MM ? tid % G : tid / NL;
-  const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
+  int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
+  if constexpr (MM) mode_pair(tile * NL + c, M, tb.mx, ia, ib);
   const bool va = ia < M, vb = ib < M;
   const T* za = z + ia;
   const T* zb = z + ib;
@@ -514,6 +544,7 @@ struct MatvecCSTables {
   const T* mu;
   T q[4];
   int qtaps;
+  int mx = 1;          // modes per x-row (mode_pair)
 };
 
 // Index of the spectrum entry register slot (w, u) of lane g multiplies: the
@@ -597,7 +628,8 @@ BLTT_HD double matvec_cs_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __res
   asm volatile("" : "+v"(g));
   g &= G - 1;
 #endif
-  const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
+  int64_t ia, ib;
+  mode_pair(tile * NL + c, M, tb.mx, ia, ib);
   const bool va = ia < M, vb = ib < M;
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
   const int64_t la = iac * N, lb = ibc * N;
@@ -1343,6 +1375,7 @@ struct TimeTables {
   T q[4];              // leading taps of q
   int qtaps;
   double* aux;         // per-workgroup sum_i mu_i sum_n (q * t_i)[N-1-n] t_i[n] (or null)
+  int mx = 1;          // mode-major lines: modes per x-row (mode_pair)
 };
 
 // 1 / (N s), s the principal square root of lambda (Re lambda > 0, Definition 2):
@@ -1662,7 +1695,8 @@ BLTT_HD double time_upd_tile(Ctx& ctx, cx<T>* lds, int64_t tile, const TQ* __res
   // per-lane base and compile-time offsets (the ds instructions' immediates)
   g &= G - 1;
 #endif
-  const int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
+  int64_t ia = tile * (2 * NL) + 2 * c, ib = ia + 1;
+  if constexpr (MM) mode_pair(tile * NL + c, M, tb.mx, ia, ib);
   const bool va = ia < M, vb = ib < M;
   const int64_t iac = va ? ia : M - 1, ibc = vb ? ib : M - 1;
   // element (i, n): time-major n*M + i, or mode-major i*N + n (N = L)
@@ -2194,6 +2228,7 @@ struct BatchTabs {
 struct BatchVec {
   int64_t n, M, T;        // elements per system, modes, tiles per system
   int S;
+  int mx = 1;             // modes per x-row (mode_pair)
   const int* active;      // outer loop running (per system)
   const double* etol;     // sweep tolerance on |eta|/eta0 (per system)
   SolverState* states;    // per system
@@ -2251,6 +2286,7 @@ BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q
   for (int k = 0; k < 4; ++k) tb.q[k] = ip.q32[k];
   tb.qtaps = ip.qtaps;
   tb.aux = nullptr;
+  tb.mx = bv.mx;
   // the stage twiddles in LDS (time pass with TWL), after the exchange lines
   // and the reduction slots
   {
@@ -2292,6 +2328,7 @@ BLTT_HD void bt_cs_body(Ctx& ctx, unsigned char* smem, const float* __restrict__
   tb.mu = bt.mu32;
   for (int k = 0; k < 4; ++k) tb.q[k] = ip.q32[k];
   tb.qtaps = ip.qtaps;
+  tb.mx = bv.mx;
   const int64_t o = (int64_t)s * bv.n;
   double part;
   if constexpr (bt_cs_stage<L, TPB>()) {
@@ -2335,6 +2372,7 @@ BLTT_HD void bt_resid_body(Ctx& ctx, unsigned char* smem, double* const* __restr
   tb.mu = bt.mu64;
   for (int k = 0; k < 4; ++k) tb.q[k] = ip.q64[k];
   tb.qtaps = ip.qtaps;
+  tb.mx = bv.mx;
   const int64_t o = (int64_t)s * bv.n;
   const int k = bv.states[s].iter < K ? bv.states[s].iter : K - 1;
   const double part = matvec_fft_tile<double, L2, MV_RESID, TERM_SPEC, true>(

@@ -81,6 +81,7 @@ def lib():
         L.emu_resid_upd_r32_f64.restype = ctypes.c_double
         L.emu_state_size.restype = ctypes.c_int64
         L.emu_transpose_f64.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+        L.emu_mode_pairs.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int64, P, P]
         L.emu_set_faces.argtypes = [P, P, P]
         L.emu_resid_full_f64.argtypes = args + [P, P, P, ctypes.c_int]
         L.emu_resid_full_f64.restype = ctypes.c_double
@@ -371,6 +372,13 @@ def transpose(x, R, C, rev=False):
     lib().emu_transpose_f64(gi.ptr, go.ptr, R, C, int(rev))
     _check(gi, go)
     return go.data.copy()
+
+
+def mode_pairs(M, mx, count):
+    """(ia, ib) of complex lines 0..count-1 as the sine-basis kernels pair modes."""
+    ia, ib = np.zeros(count, np.int64), np.zeros(count, np.int64)
+    lib().emu_mode_pairs(M, mx, count, ia.ctypes.data, ib.ctypes.data)
+    return ia, ib
 
 
 def combine_f32(u, Zs, y, s):

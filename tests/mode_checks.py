@@ -50,20 +50,33 @@ def line_err(got, ref):
     return float((np.abs(got - ref).max(axis=1) / den).max())
 
 
+def pair_partner(i, M, mx):
+    """The sine mode that shares mode i's complex line in the sine-basis
+    kernels.  Modes are numbered x fastest in rows of mx (odd); within a row
+    modes 2j and 2j+1 of the row pair up, and the last modes of rows r and
+    r+1 (r even) pair with each other; a lone last mode is its own partner.
+    (With mx = 1 this is i ^ 1.)"""
+    r, x = divmod(int(i), int(mx))
+    if x < mx - 1:
+        return r * mx + (x ^ 1)
+    rr = r ^ 1
+    return rr * mx + mx - 1 if rr < M // mx else int(i)
+
+
 def pair_err(got, ref, inp, sysm, modes, M):
     """Time-pass error of each line, normwise over its packed pair.  The kernel
-    transforms sine modes 2j and 2j+1 as the real and imaginary parts of one
-    complex line (the last mode alone when M is odd), so its rounding is
-    relative to that complex line: it scales with the larger input of the
-    pair times the larger multiplier either mode applies,
-    max_k |lambda_{i,k}|^{-1} (eq. (9)).  When one mode's input or output is
-    much larger than its partner's, the smaller one's relative error grows by
-    that ratio (cross-talk of the two-for-one split)."""
+    transforms two sine modes (pair_partner) as the real and imaginary parts
+    of one complex line, so its rounding is relative to that complex line: it
+    scales with the larger input of the pair times the larger multiplier
+    either mode applies, max_k |lambda_{i,k}|^{-1} (eq. (9)).  When one mode's
+    input or output is much larger than its partner's, the smaller one's
+    relative error grows by that ratio (cross-talk of the two-for-one split),
+    which is why the kernels pair modes of neighbouring x frequency."""
     got = np.asarray(got, np.float64).reshape(ref.shape)
     row = {int(i): k for k, i in enumerate(modes)}
     pn = (1.0 / np.abs(O.mode_precond(sysm, modes).lam)).max(axis=0)
     im = np.abs(np.asarray(inp, np.float64)).max(axis=1)
-    part = [row[min(int(i) ^ 1, M - 1)] for i in modes]
+    part = [row[pair_partner(i, M, sysm.ms[0])] for i in modes]
     scale = np.maximum(im, im[part]) * np.maximum(pn, pn[part])
     return float((np.abs(got - ref).max(axis=1) / np.maximum(scale, 1e-300)).max())
 

@@ -350,6 +350,7 @@ TimeTables<T> time_tables(const Problem& P, const HostTables<T>& ht) {
   tt.log2_alpha_over_N = (T)(std::log2(P.alpha) / (double)P.N);
   for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
   tt.qtaps = qtaps;
+  tt.mx = (int)P.m[0];
   tt.aux = nullptr;
   return tt;
 }
@@ -503,6 +504,7 @@ double apply_sym(const Problem& P, const T* z, T* out, bool force_fft, bool sten
     tb.phat = ht.phat.data();
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
     tb.qtaps = qtaps;
+    tb.mx = (int)P.m[0];
     tb.grid = grid_of(P);
     std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
     with_L2<MvRun<T>::template R>((int)(2 * P.N), z, out, P.M, tb, partials.data(), stencil);
@@ -583,6 +585,7 @@ double apply_resid_full(const Problem& P, const T* u, const T* f, T* r, bool for
     tb.phat = ht.phat.data();
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
     tb.qtaps = qtaps;
+    tb.mx = (int)P.m[0];
     tb.grid = grid_of(P);
     std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
     with_L2<MvResFullRun<T>::template R>((int)(2 * P.N), u, r, f, P.M, tb, partials.data());
@@ -602,6 +605,7 @@ double apply_resid(const Problem& P, const T* u, const T* f, T* r) {
   tb.phat = ht.phat.data();
   for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
   tb.qtaps = qtaps;
+  tb.mx = (int)P.m[0];
   tb.grid = grid_of(P);
   std::vector<double> partials((size_t)fft_blocks<T, FK_MV>((int)(2 * P.N), P.M));
   with_L2<MvResRun<T>::template R>((int)(2 * P.N), u, r, f, P.M, tb, partials.data());
@@ -785,6 +789,7 @@ double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force
     tb.mu = ht.mu.data();
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
     tb.qtaps = qtaps;
+    tb.mx = (int)P.m[0];
     tb.grid = grid_of(P);
     IterUpd up{};
     if (upd) up = *upd;
@@ -804,6 +809,7 @@ double apply_spec(const Problem& P, const T* z, T* out, const T* fin, bool force
     tb.mu = ht.mu.data();
     for (int k = 0; k < 4; ++k) tb.q[k] = (T)(k < qtaps ? P.q[(size_t)k] : 0.0);
     tb.qtaps = qtaps;
+    tb.mx = (int)P.m[0];
     IterUpd up{};
     if (upd) up = *upd;
     std::vector<double> partials((size_t)fft_tiles<T, FK_SPEC>((int)P.N, P.M), 0.0);
@@ -879,6 +885,11 @@ void emu_wx_f32(const float* Z, float* Wa, const float* Wb, float* X, int64_t n,
   apply_wx<float>(Z, Wa, Wb, X, n, coef);
 }
 
+
+// the kernels' assignment of sine modes to complex lines, for lines 0..count-1
+void emu_mode_pairs(int64_t M, int mx, int64_t count, int64_t* ia, int64_t* ib) {
+  for (int64_t t = 0; t < count; ++t) mode_pair(t, M, mx, ia[t], ib[t]);
+}
 
 int emu_error(void) { return g_error; }
 // radix plan of the FP32 time pass and N-point matvec (0 or 1)

@@ -16,6 +16,7 @@ import pytest
 from oracle import bltt_oracle as O
 from paper_2307_07749_amd import workloads as W
 from tests import emu_lib as E
+from tests.mode_checks import pair_partner
 
 TOL = {np.float64: 1e-12, np.float32: 2e-5}
 
@@ -191,6 +192,38 @@ def test_transpose(R, C, rev):
 
 SINE_IO_CASES = [("frac", 1, 31, 32), ("heat", 2, 7, 16), ("frac", 2, 15, 40), ("cn", 3, 3, 8), ("heat", 1, 3, 2),
                  ("frac", 2, 63, 5), ("heat", 1, 511, 9), ("frac", 2, 255, 3)]
+
+
+@pytest.mark.parametrize("dim,m", [(1, 1), (1, 7), (2, 1), (2, 7), (2, 31), (3, 3), (3, 15), (2, 1023)])
+def test_mode_pairing(dim, m):
+    """The kernels' assignment of sine modes to complex lines (mode_pair):
+    ceil(M/2) lines holding every mode exactly once; partners inside a row of
+    m_0 modes are x neighbours 2j, 2j+1 of the row, and a row's last mode (the
+    highest x frequency) shares its line only with the last mode of the
+    neighbouring row, never with a low one; lines past the end hold nothing;
+    the tests' pair_partner agrees."""
+    M = m ** dim
+    lines = (M + 1) // 2
+    ia, ib = E.mode_pairs(M, m, lines + 3)
+    assert np.all(ia[lines:] >= M) and np.all(ib[lines:] >= M)
+    ia, ib = ia[:lines], ib[:lines]
+    assert np.all(ia < M)
+    assert np.array_equal(np.sort(np.concatenate([ia, ib[ib < M]])), np.arange(M))
+    ra, xa = np.divmod(ia, m)
+    two = ib < M
+    rb, xb = np.divmod(ib[two], m)
+    ra2, xa2 = ra[two], xa[two]
+    inside = (rb == ra2) & (xa2 % 2 == 0) & (xb == xa2 + 1)
+    ends = (xa2 == m - 1) & (xb == m - 1) & (ra2 % 2 == 0) & (rb == ra2 + 1)
+    assert np.all(inside | ends)
+    # a lone mode is the last one of the last (even-numbered) row
+    assert np.all(xa[~two] == m - 1) and np.sum(~two) == M % 2
+    rng = np.random.default_rng(m)
+    for t in rng.integers(0, lines, 50):
+        a, b = int(ia[t]), int(ib[t])
+        assert pair_partner(a, M, m) == (b if b < M else a)
+        if b < M:
+            assert pair_partner(b, M, m) == a
 
 
 @pytest.mark.parametrize("kind,dim,m,N", SINE_IO_CASES)

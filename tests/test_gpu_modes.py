@@ -28,7 +28,7 @@ import pytest
 from oracle import bltt_oracle as O
 from paper_2307_07749_amd import bltt
 from paper_2307_07749_amd import workloads as W
-from tests.mode_checks import TOL_MV, line_err, pair_err, tol_time
+from tests.mode_checks import TOL_MV, line_err, pair_err, pair_partner, tol_time
 
 pytestmark = pytest.mark.gpu
 
@@ -160,15 +160,13 @@ def test_modes_steps_reject_overlap_and_varcoef():
 # the bench's launch configuration, on sampled lines
 # --------------------------------------------------------------------------
 
-def sample_modes(M, rng, k=10, m0=None):
-    """Whole packed pairs (2j, 2j+1): the first ones, a middle one, the
-    ragged last mode, random ones and, on a grid with an odd row length m0,
-    pairs that straddle a row end (the highest x mode of one row with the
-    lowest of the next: the largest eigenvalue contrast within a pair)."""
+def sample_modes(M, rng, m0, k=10):
+    """Whole packed pairs (pair_partner): the first ones, a middle one, the
+    last mode, random ones and the row ends (the highest x mode of a row,
+    packed with the highest x mode of the neighbouring row)."""
     base = [0, 2, M // 2, M - 1] + [int(i) for i in rng.integers(0, M, k)]
-    if m0:
-        base += [m0 - 1, 3 * m0 - 1, (m0 // 2) * m0 - 1]
-    return sorted(set(min(i ^ b, M - 1) for i in base for b in (0, 1)))
+    base += [m0 - 1, 2 * m0 - 1, 3 * m0 - 1, (m0 // 2) * m0 - 1]
+    return sorted(set(j for i in base if i < M for j in (i, pair_partner(i, M, m0))))
 
 
 def lines(t, M, N, modes):
