@@ -170,7 +170,14 @@ typedef struct bltt_handle bltt_handle;
  * (MIXED also allocates the FP64 refinement vectors).
  *   blk    block description (N entries of p and q)
  *   N      number of time steps (blocks); M must equal m[0]*...*m[dim-1]
- *   alpha  in (0, 1]
+ *   alpha  in (0, 1]; the FP64 preconditioner uses it as given.  Everything
+ *          that applies the preconditioner in FP32 (the sweeps of BLTT_MIXED,
+ *          the FP32 step entry points, the batched sweeps) uses
+ *          alpha' = max(alpha, 1e-4) instead: an FP32 time pass scales its
+ *          lines by up to 1/alpha around its transforms, so its rounding
+ *          grows like eps_32/alpha, and below 1e-4 the sweeps slow down
+ *          (and fail to converge at 1e-8).  P_alpha' is an SPD preconditioner
+ *          of the same system, and the FP64 refinement solves that system.
  *   opt    options or NULL
  *   stream hipStream_t (void*) for all work of this handle
  *   out    receives the new handle; untouched on error

@@ -310,6 +310,12 @@ int cs_plan(const bltt_handle* h) { return sizeof(T) == 4 ? h->plan_cs : 0; }
 template <typename T>
 int64_t cs_blocks(const bltt_handle* h) { return sizeof(T) == 4 ? h->cs_blocks : 0; }
 
+// alpha of the preconditioner that precision T applies (ALPHA_MIN_FP32)
+template <typename T>
+double prec_alpha(const bltt_handle* h) {
+  return sizeof(T) == 4 ? std::max(h->alpha, ALPHA_MIN_FP32) : h->alpha;
+}
+
 template <typename T>
 int build_tables(bltt_handle* h) {
   DeviceTables<T>& t = tables<T>(h);
@@ -318,10 +324,11 @@ int build_tables(bltt_handle* h) {
   if ((rc = upload_c<T>(h, &t.tw_time, host::twiddles((int)h->N)))) return rc;
   for (int d = 0; d < h->dim; ++d)
     if ((rc = upload_c<T>(h, &t.tw_dst[d], host::twiddles(2 * (h->m[d] + 1))))) return rc;
-  if ((rc = upload<T>(h, &t.dinv, host::alpha_pow(h->N, h->alpha, -1.0)))) return rc;
-  if ((rc = upload<T>(h, &t.d2, host::alpha_pow(h->N, h->alpha, 2.0)))) return rc;
-  if ((rc = upload_c<T>(h, &t.sigma, host::alpha_spectrum(h->p, h->alpha)))) return rc;
-  if ((rc = upload_c<T>(h, &t.rho, host::alpha_spectrum(h->q, h->alpha)))) return rc;
+  const double alpha = prec_alpha<T>(h);
+  if ((rc = upload<T>(h, &t.dinv, host::alpha_pow(h->N, alpha, -1.0)))) return rc;
+  if ((rc = upload<T>(h, &t.d2, host::alpha_pow(h->N, alpha, 2.0)))) return rc;
+  if ((rc = upload_c<T>(h, &t.sigma, host::alpha_spectrum(h->p, alpha)))) return rc;
+  if ((rc = upload_c<T>(h, &t.rho, host::alpha_spectrum(h->q, alpha)))) return rc;
   {
     // Laplacian eigenvalue of each sine mode, of abar L_h for a variable coefficient
     std::vector<double> mu = host::lap_eigs(h->dim, h->m, h->h);
@@ -551,7 +558,7 @@ TimeTables<T> time_tables(bltt_handle* h, bool aux) {
   tt.sigma = t.sigma;
   tt.rho = t.rho;
   tt.mu = t.mu;
-  tt.log2_alpha_over_N = (T)(std::log2(h->alpha) / (double)h->N);
+  tt.log2_alpha_over_N = (T)(std::log2(prec_alpha<T>(h)) / (double)h->N);
   for (int k = 0; k < 4; ++k) tt.q[k] = (T)(k < h->qtaps ? h->q[(size_t)k] : 0.0);
   tt.qtaps = h->qtaps;
   tt.aux = aux ? h->partials_aux : nullptr;

@@ -346,15 +346,17 @@ int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const doub
     auto app = [](std::vector<cx<float>>& dst, const std::vector<host::cd>& src) {
       for (const auto& v : src) dst.push_back(mkc<float>((float)v.real(), (float)v.imag()));
     };
-    app(sig, host::alpha_spectrum(p, alpha[gi]));
-    app(rho, host::alpha_spectrum(q, alpha[gi]));
+    // the FP32 sweeps' preconditioner: alpha' = max(alpha, 1e-4), as for one system
+    const double a32 = std::max(alpha[gi], ALPHA_MIN_FP32);
+    app(sig, host::alpha_spectrum(p, a32));
+    app(rho, host::alpha_spectrum(q, a32));
     app(chat, host::circulant_spectrum(p, false));
     app(shat, host::circulant_spectrum(p, true));
     for (const auto& v : host::matvec_spectrum(p)) phat.push_back(mkc<double>(v.real(), v.imag()));
     int qt = 0;
     for (int64_t j = 0; j < N; ++j)
       if (q[(size_t)j] != 0.0) qt = (int)j + 1;
-    ip[(size_t)k].l2a = (float)(std::log2(alpha[gi]) / (double)N);
+    ip[(size_t)k].l2a = (float)(std::log2(a32) / (double)N);
     ip[(size_t)k].qtaps = qt;
     for (int j = 0; j < 4; ++j) {
       ip[(size_t)k].q32[j] = (float)(j < qt ? q[(size_t)j] : 0.0);

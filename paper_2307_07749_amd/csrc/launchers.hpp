@@ -10,6 +10,15 @@
 
 namespace bltt {
 
+// Smallest alpha of the FP32 preconditioner (the mixed path's sweeps and the
+// FP32 step entry points): an FP32 time pass scales its lines by up to
+// 1/alpha around its transforms, so its rounding grows like eps_32/alpha.
+// Below 1e-4 the mixed path's sweeps converge more slowly (8 iterations at
+// 1e-5, 12 at 1e-6 against 6) and not at all at 1e-8; they use
+// P_alpha' with alpha' = max(alpha, 1e-4), an SPD preconditioner of the same
+// system.  The FP64 residual and the FP64 path use alpha itself.
+constexpr double ALPHA_MIN_FP32 = 1e-4;
+
 // First member of every handle type, so that one destroy call serves them all
 constexpr uint32_t HANDLE_MAGIC = 0x424c5448u;  // single system
 constexpr uint32_t BATCH_MAGIC = 0x424c5442u;   // batch
