@@ -1,6 +1,7 @@
 """A seeded sweep over the supported shape space (Section 5 problems: 1D to
-3D, m + 1 from 2 to 1024, N from 1 to 2048, the three block families, both
-precisions and both bases), each solve checked against the oracle:
+3D, m + 1 from 2 to 1024, N from 1 to 2048, the three block families, alpha
+from 1e-8 to 0.5, both precisions and both bases), each solve checked
+against the oracle:
   * the returned u meets the stopping test when the residual is formed by the
     oracle's own operator (dense Toeplitz products of eq. (3) in physical
     space), which shares nothing with the kernels;
@@ -39,11 +40,11 @@ def _cases(seed=23, count=48):
         logn = min(11, int(np.floor(np.log2(max(2.0, 3e5 / m ** dim)))))
         N = 2 ** int(rng.integers(0, logn + 1))
         kind = ("frac", "heat", "cn")[int(rng.integers(0, 3))]
-        alpha = float(10 ** rng.uniform(-3, np.log10(0.5)))
+        alpha = float(10 ** rng.uniform(-8, np.log10(0.5)))
         gamma = float(rng.uniform(0.1, 0.9))
         prec = (bltt.FP64, bltt.MIXED)[int(rng.integers(0, 2))]
         basis = bltt.SINE if (N == 1 or rng.random() < 0.6) else bltt.PHYSICAL
-        out.append((kind, dim, m, N, round(alpha, 5), round(gamma, 3), prec, basis))
+        out.append((kind, dim, m, N, float(f"{alpha:.4g}"), round(gamma, 3), prec, basis))
     return out
 
 
@@ -81,6 +82,6 @@ def test_shape_sweep(case):
     # the sine basis reports the residual of the transformed system, which
     # differs from this one by the transforms' FP64 rounding times cond(A)
     assert relres <= tol + 2e-11
-    # error over tolerance: at most 5.4 (FP64) and 1.3 (mixed) over 500
-    # seeded shapes of this generator
+    # error over tolerance (a conditioning factor): at most 12.5 (FP64) and
+    # 1.3 (mixed) over 900 seeded shapes of this generator and its variants
     assert err <= 30 * tol
