@@ -13,6 +13,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "bltt.h"
@@ -1022,67 +1023,81 @@ int tune_fp32_plans(bltt_handle* h, int cus) {
     return BLTT_EHIP;
   }
   int rc = BLTT_OK;
-  auto time_it = [&](auto&& launch, float* best_ms) {
-    float best = 1e30f;
-    for (int rep = 0; rep < 8 && rc == BLTT_OK; ++rep) {
-      if (hipEventRecord(a, s) != hipSuccess || launch() != hipSuccess || hipEventRecord(z, s) != hipSuccess ||
-          hipEventSynchronize(z) != hipSuccess) {
-        rc = BLTT_EHIP;
-        break;
+  // Every candidate launch is timed once per round, the candidates in turn,
+  // over 8 rounds (the first a warm-up); each keeps its best time.  Taking the
+  // candidates in turn rather than one after another keeps clock and thermal
+  // drift during the tuning from favouring whichever ran last.
+  struct Cand {
+    std::function<hipError_t()> launch;
+    int plan;
+    int64_t blocks;
+    float best;
+  };
+  auto tournament = [&](std::vector<Cand>& cands) -> int {
+    for (int rep = 0; rep < 8; ++rep) {
+      for (Cand& c : cands) {
+        if (hipEventRecord(a, s) != hipSuccess || c.launch() != hipSuccess || hipEventRecord(z, s) != hipSuccess ||
+            hipEventSynchronize(z) != hipSuccess)
+          return BLTT_EHIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, a, z) != hipSuccess) return BLTT_EHIP;
+        if (rep > 0 && ms < c.best) c.best = ms;
       }
-      float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, a, z) != hipSuccess) rc = BLTT_EHIP;
-      if (rep > 0 && ms < best) best = ms;
     }
-    *best_ms = best;
+    return BLTT_OK;
   };
   const TimeTables<float> tt = time_tables<float>(h, false);
   const int64_t tiles = fft_tiles<float, FK_SPEC>(L, h->M);
-  float best_t = 1e30f;
   int bt_plan = 0;
   int64_t bt_blocks = h->max_blocks;
-  for (int plan = 0; plan <= (alt ? 1 : 0); ++plan) {
-    for (int per : {2, 4, 8}) {
-      const int64_t blocks = per * (int64_t)cus;
-      if (per > 2 && (per / 2) * (int64_t)cus >= tiles) continue;  // same launch as the smaller count
-      float ms = 1e30f;
-      int64_t np = 0;
-      time_it([&]() {
-        return launch_time_upd<float, float>(L, true, true, w.Q, w.V[0], w.V[1], w.V[2], w.Z[0], h->M, tt,
-                                             h->coef_one, h->partials, blocks, &np, s, false, plan);
-      }, &ms);
-      if (rc) break;
-      if (ms < best_t) {
-        best_t = ms;
-        bt_plan = plan;
-        bt_blocks = blocks;
+  {
+    std::vector<Cand> cands;
+    for (int plan = 0; plan <= (alt ? 1 : 0); ++plan)
+      for (int per : {2, 4, 8}) {
+        const int64_t blocks = per * (int64_t)cus;
+        if (per > 2 && (per / 2) * (int64_t)cus >= tiles) continue;  // same launch as the smaller count
+        cands.push_back({[&, plan, blocks]() {
+                           int64_t np = 0;
+                           return launch_time_upd<float, float>(L, true, true, w.Q, w.V[0], w.V[1], w.V[2], w.Z[0],
+                                                                h->M, tt, h->coef_one, h->partials, blocks, &np, s,
+                                                                false, plan);
+                         },
+                         plan, blocks, 1e30f});
       }
-    }
+    rc = tournament(cands);
+    float best = 1e30f;
+    for (const Cand& c : cands)
+      if (c.best < best) {
+        best = c.best;
+        bt_plan = c.plan;
+        bt_blocks = c.blocks;
+      }
   }
-  // the N-point matvec: radix plan, and one tile per workgroup (per = 0) or
+  // the N-point matvec: radix plan, and one tile per workgroup (blocks 0) or
   // 2, 4, 8 persistent workgroups per CU
   int bc_plan = 0;
   int64_t bc_blocks = 0;
   if (rc == BLTT_OK && !short_p(h)) {
-    float best_c = 1e30f;
-    for (int plan = 0; plan <= (alt ? 1 : 0); ++plan) {
+    std::vector<Cand> cands;
+    for (int plan = 0; plan <= (alt ? 1 : 0); ++plan)
       for (int per : {0, 2, 4, 8}) {
         const int64_t blocks = per * (int64_t)cus;
         if (per > 0 && blocks >= tiles) continue;  // the same launch as one tile per workgroup
-        float ms = 1e30f;
-        int64_t np = 0;
-        time_it([&]() {
-          return launch_matvec_cs<float>(L, MV_DOT, w.Z[0], w.Q, nullptr, h->M, cs_tables<float>(h), IterUpd{},
-                                         h->partials, blocks, &np, s, plan);
-        }, &ms);
-        if (rc) break;
-        if (ms < best_c) {
-          best_c = ms;
-          bc_plan = plan;
-          bc_blocks = blocks;
-        }
+        cands.push_back({[&, plan, blocks]() {
+                           int64_t np = 0;
+                           return launch_matvec_cs<float>(L, MV_DOT, w.Z[0], w.Q, nullptr, h->M, cs_tables<float>(h),
+                                                          IterUpd{}, h->partials, blocks, &np, s, plan);
+                         },
+                         plan, blocks, 1e30f});
       }
-    }
+    rc = tournament(cands);
+    float best = 1e30f;
+    for (const Cand& c : cands)
+      if (c.best < best) {
+        best = c.best;
+        bc_plan = c.plan;
+        bc_blocks = c.blocks;
+      }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(z);
