@@ -60,6 +60,7 @@ struct BatchClass {
   SolverState* states_host = nullptr;
   int* act_host = nullptr;         // pinned staging of the active flags
   double* etol_dev = nullptr;      // per-system sweep tolerance
+  double* bscale_dev = nullptr;    // per-system ||fhat|| (scale of the FP32 residual hand-over)
   double* etol_host = nullptr;     // pinned staging of it
   double** uptr_host = nullptr;    // pinned staging of the caller's u pointers
   int sweeps = 0;                  // sweeps completed in the current solve
@@ -138,6 +139,7 @@ BatchVec bvec(BatchClass& c) {
   bv.S = c.S;
   bv.active = c.active_dev;
   bv.etol = c.etol_dev;
+  bv.bscale = c.bscale_dev;
   bv.states = c.states;
   return bv;
 }
@@ -383,6 +385,7 @@ int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const doub
   c.tabs.sys_inst = c.sys_inst_dev;
   // per-system state
   if ((rc = balloc(b, &c.active_dev, (size_t)S)) || (rc = balloc(b, &c.etol_dev, (size_t)S)) ||
+      (rc = balloc(b, &c.bscale_dev, (size_t)S)) ||
       (rc = balloc(b, &c.states, (size_t)S)) ||
       (rc = balloc(b, &c.zb, (size_t)(3 * BT_POOL * S))))
     return rc;
@@ -653,8 +656,13 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
         r.status = BLTT_OK;
         r.relres = 0.0;
       }
+      // ||fhat_s||: the residual passes hand the next sweep r/||fhat_s|| in
+      // FP32 (1 for a zero right-hand side, whose system never runs)
+      c.etol_host[s] = r.bnorm > 0.0 ? r.bnorm : 1.0;
       if (hist) hist[(size_t)c.sys_global[(size_t)s] * (size_t)(maxit + 1)] = 1.0;
     }
+    HIPCHK(hipMemcpyAsync(c.bscale_dev, c.etol_host, sizeof(double) * (size_t)c.S, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
   }
   std::vector<double> hbuf;
   bool any = true;
@@ -684,7 +692,13 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
                                 c.stream));
           HIPCHK(hipMemcpyAsync(c.etol_dev, c.etol_host, sizeof(double) * (size_t)c.S, hipMemcpyHostToDevice,
                                 c.stream));
-          HIPCHK(launch_bt(BT_START, (int)c.N, c.tpb, c.plan, c.R64, nullptr, nullptr, c.V[0], c.pool.z[0], nullptr, bv,
+          // the first sweep starts from b = Y fhat in FP64; later ones from the
+          // FP32 residual r/||fhat|| the residual pass left in V[0]
+          if (c.sweeps > 0)
+            HIPCHK(launch_bt(BT_START32, (int)c.N, c.tpb, c.plan, c.V[0], nullptr, nullptr, nullptr, c.pool.z[0],
+                             nullptr, bv, c.tabs, c.partials, c.stream));
+          else
+            HIPCHK(launch_bt(BT_START, (int)c.N, c.tpb, c.plan, c.R64, nullptr, nullptr, c.V[0], c.pool.z[0], nullptr, bv,
                            c.tabs, c.partials, c.stream));
           HIPCHK(launch_bt_scalar(SC_START, bv, c.partials, c.T, c.hist_dev, c.hist_stride, c.zb, BT_POOL,
                                   inner_tol, BT_POOL - 1, c.stream));
@@ -704,7 +718,7 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
         int64_t T2 = 0;
         const int u_zero = c.sweeps == 1 ? 1 : 0;  // the first sweep writes uhat without reading it
         HIPCHK(launch_bt_resid((int)(2 * c.N), c.uptr_dev, c.R64, c.F64, bv, c.tabs, c.pool, c.zb, BT_POOL, u_zero,
-                               c.partials, &T2, c.stream));
+                               c.partials, &T2, c.V[0], c.stream));
         HIPCHK(launch_bt_scalar(SC_NORM, bv, c.partials, T2, nullptr, 0, nullptr, BT_POOL, inner_tol, BT_POOL - 1,
                                 c.stream));
         if ((rc = read_states(c))) return rc;

@@ -327,7 +327,7 @@ template <typename T, int L, int MODE, int TERM, bool MM, bool R32 = false, clas
 BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __restrict__ out,
                                const T* __restrict__ fin, int64_t M, const MatvecTables<T>& tb, const IterUpd& up,
                                int64_t zoff = 0, int k = -1, const double* y = nullptr,
-                               const double* sptr = nullptr) {
+                               const double* sptr = nullptr, float* r32o = nullptr, double r32so = 1.0) {
   static_assert(!(MM && TERM == TERM_STENCIL), "the stencil needs the time-major layout");
   constexpr int TPB = tpb_fft<T, fk_mv<MM, L>()>();
   constexpr int V = fft_V(L), G = L / V, NL = TPB / G, s0 = fft_sigma(L, 0);
@@ -349,6 +349,10 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
   const double* uy = y ? y : up.y;
   const bool upd = MODE == MV_RESID && uk > 0;
   const double us = upd ? *(sptr ? sptr : up.s) : 0.0;
+  // FP32 residual output (R32): the batched caller passes its system's
+  // buffer and scale here instead of in up
+  float* const r32p = r32o ? r32o : up.r32;
+  const double r32s = r32o ? r32so : up.r32_scale;
   cx<T> v[V], zin[VH];
   T ra[VH], rb[VH];
 #pragma unroll
@@ -498,13 +502,13 @@ BLTT_HD double matvec_fft_tile(Ctx& ctx, cx<T>* lds, int64_t tile, T* z, T* __re
       (void)off;
       if (va) {
         const T r = fa[MODE == MV_RESID ? t : 0] - ya;
-        if constexpr (R32) up.r32[sa + offr] = (float)(r * up.r32_scale);
+        if constexpr (R32) r32p[sa + offr] = (float)(r * r32s);
         else oa[offr] = r;
         part += (double)r * (double)r;
       }
       if (vb) {
         const T r = fb[MODE == MV_RESID ? t : 0] - yb;
-        if constexpr (R32) up.r32[sb + offr] = (float)(r * up.r32_scale);
+        if constexpr (R32) r32p[sb + offr] = (float)(r * r32s);
         else ob[offr] = r;
         part += (double)r * (double)r;
       }
@@ -2229,6 +2233,10 @@ struct BatchVec {
   int64_t n, M, T;        // elements per system, modes, tiles per system
   int S;
   int mx = 1;             // modes per x-row (mode_pair)
+  // per system ||fhat||: a refinement residual pass writes r/||fhat|| in FP32
+  // for the next sweep and scales the iterate update by ||fhat|| (null: the
+  // residual goes out in FP64)
+  const double* bscale = nullptr;
   const int* active;      // outer loop running (per system)
   const double* etol;     // sweep tolerance on |eta|/eta0 (per system)
   SolverState* states;    // per system
@@ -2297,7 +2305,10 @@ BLTT_HD void bt_upd_body(Ctx& ctx, unsigned char* smem, const TQ* __restrict__ Q
     tb.tw = twl;
   }
   const int64_t o = (int64_t)s * bv.n;
-  const double* coef = FULL ? bv.states[s].coef_v : &bv.states[s].rinv;
+  // a start from the FP32 residual r/||fhat|| runs on it as it is (the
+  // iterate update carries ||fhat||); from FP64 it normalises by 1/||r||
+  const double one[4] = {1.0, 0.0, 0.0, 0.0};
+  const double* coef = FULL ? bv.states[s].coef_v : (sizeof(TQ) == 4 ? one : &bv.states[s].rinv);
   const double part = time_upd_tile<float, L, TQ, FULL, true, TPB, true, true, PLAN>(
       ctx, reinterpret_cast<cx<float>*>(smem), tile, Q + o, FULL ? V1 + o : nullptr, FULL ? V2 + o : nullptr,
       Vout ? Vout + o : nullptr, Zout + o, bv.M, tb, coef);
@@ -2350,11 +2361,13 @@ BLTT_HD void bt_cs_body(Ctx& ctx, unsigned char* smem, const float* __restrict__
 // FP64 refinement step per system: u_s <- u_s + rscale_s sum_i y_i Z_i (the
 // sweep's stored vectors, pool.z[i] + s*n), R = Y(F - A u_s) (2N-point form),
 // partial sums of ||R||^2.  T2 tiles per system.
-template <int L2, class Ctx>
+// R32: the residual goes to r32 + s*n as FP32 r/||fhat_s|| (bv.bscale) for
+// the next sweep, and the update is scaled by ||fhat_s||.
+template <int L2, bool R32 = false, class Ctx>
 BLTT_HD void bt_resid_body(Ctx& ctx, unsigned char* smem, double* const* __restrict__ u, double* __restrict__ R,
                            const double* __restrict__ Fh, const BatchVec& bv, const BatchTabs& bt,
                            const IterUpd& pool, const double* __restrict__ zb, int K, int64_t T2,
-                           double* __restrict__ partials) {
+                           double* __restrict__ partials, float* __restrict__ r32 = nullptr) {
   constexpr int NL = tpb_fft<double, fk_mv<true, L2>()>() / (L2 / fft_V(L2));
   using F = LineFft<double, L2, NL, false, LAST_DEFAULT>;
   double* red = reinterpret_cast<double*>(smem + sizeof(cx<double>) * F::LDS_ELEMS);
@@ -2375,9 +2388,16 @@ BLTT_HD void bt_resid_body(Ctx& ctx, unsigned char* smem, double* const* __restr
   tb.mx = bv.mx;
   const int64_t o = (int64_t)s * bv.n;
   const int k = bv.states[s].iter < K ? bv.states[s].iter : K - 1;
-  const double part = matvec_fft_tile<double, L2, MV_RESID, TERM_SPEC, true>(
-      ctx, reinterpret_cast<cx<double>*>(smem), tile, u[s], R + o, Fh + o, bv.M, tb, pool, o, k,
-      zb + (int64_t)s * 3 * K + 2 * K, &bv.states[s].rscale);
+  double part;
+  if constexpr (R32) {
+    part = matvec_fft_tile<double, L2, MV_RESID, TERM_SPEC, true, true>(
+        ctx, reinterpret_cast<cx<double>*>(smem), tile, u[s], R + o, Fh + o, bv.M, tb, pool, o, k,
+        zb + (int64_t)s * 3 * K + 2 * K, &bv.bscale[s], r32 + o, 1.0 / bv.bscale[s]);
+  } else {
+    part = matvec_fft_tile<double, L2, MV_RESID, TERM_SPEC, true>(
+        ctx, reinterpret_cast<cx<double>*>(smem), tile, u[s], R + o, Fh + o, bv.M, tb, pool, o, k,
+        zb + (int64_t)s * 3 * K + 2 * K, &bv.states[s].rscale);
+  }
   const double sum = block_sum<tpb_fft<double, fk_mv<true, L2>()>()>(ctx, red, part);
   if (ctx.tid == 0) partials[ctx.bid] = sum;
 }

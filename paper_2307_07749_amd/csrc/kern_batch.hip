@@ -24,13 +24,14 @@ __global__ __attribute__((amdgpu_waves_per_eu(1, max_waves_fft<float>()))) __lau
   bt_cs_body<L, TPB, PLAN>(ctx, smem, Z, Q, bv, bt, partials);
 }
 
-template <int L2>
+template <int L2, bool R32 = false>
 __global__ __attribute__((amdgpu_waves_per_eu(2, max_waves_fft<double>()))) __launch_bounds__((tpb_fft<double, fk_mv<true, L2>()>()), 1) void k_bt_resid(
     double* const* __restrict__ u, double* __restrict__ R, const double* __restrict__ Fh, BatchVec bv, BatchTabs bt,
-    IterUpd pool, const double* __restrict__ zb, int K, int64_t T2, double* __restrict__ partials) {
+    IterUpd pool, const double* __restrict__ zb, int K, int64_t T2, double* __restrict__ partials,
+    float* __restrict__ r32) {
   extern __shared__ __align__(16) unsigned char smem[];
   DevCtx ctx = make_ctx();
-  bt_resid_body<L2>(ctx, smem, u, R, Fh, bv, bt, pool, zb, K, T2, partials);
+  bt_resid_body<L2, R32>(ctx, smem, u, R, Fh, bv, bt, pool, zb, K, T2, partials, r32);
 }
 
 __global__ __launch_bounds__(TPB_EW) void k_bt_scalar(int phase, SolverState* __restrict__ states,
@@ -78,6 +79,10 @@ static hipError_t go_bt(int which, const void* Q, const float* V1, const float* 
       hipLaunchKernelGGL((k_bt_upd<L, float, true, TPB, PLAN>), dim3((unsigned)blocks), dim3(TPB), lds, s, (const float*)Q,
                          V1, V2, Vout, Z, bv, bt, partials);
       break;
+    case BT_START32:
+      hipLaunchKernelGGL((k_bt_upd<L, float, false, TPB, PLAN>), dim3((unsigned)blocks), dim3(TPB), lds, s,
+                         (const float*)Q, V1, V2, Vout, Z, bv, bt, partials);
+      break;
     case BT_MATVEC:
       hipLaunchKernelGGL((k_bt_cs<L, TPB, PLAN>), dim3((unsigned)blocks), dim3(TPB), lds_cs, s,
                          (const float*)Z, Qout, bv, bt, partials);
@@ -118,7 +123,8 @@ int64_t bt_tiles(int L, int tpb, int64_t M) {
 template <int L2>
 static hipError_t go_bt_resid(double* const* u, double* R, const double* Fh, const BatchVec& bv, const BatchTabs& bt,
                               const ZPool& pool, const double* zb, int K, int u_zero, double* partials,
-                              int64_t* T2out, hipStream_t s) {
+                              int64_t* T2out, float* r32, hipStream_t s) {
+  if (r32 && !bv.bscale) return hipErrorInvalidValue;
   IterUpd up{};
   for (int i = 0; i < ZB_MAX; ++i) up.z[i] = i < K ? pool.z[i] : nullptr;
   up.k = 0;
@@ -127,17 +133,21 @@ static hipError_t go_bt_resid(double* const* u, double* R, const double* Fh, con
   const int64_t T2 = fft_tiles<double, FK>(L2, bv.M);
   if (T2out) *T2out = T2;
   const size_t lds = fft_lds_bytes<double, FK>(L2);
-  hipLaunchKernelGGL((k_bt_resid<L2>), dim3((unsigned)(T2 * bv.S)), dim3(tpb_fft<double, FK>()), lds, s, u, R, Fh,
-                     bv, bt, up, zb, K, T2, partials);
+  if (r32)
+    hipLaunchKernelGGL((k_bt_resid<L2, true>), dim3((unsigned)(T2 * bv.S)), dim3(tpb_fft<double, FK>()), lds, s, u, R,
+                       Fh, bv, bt, up, zb, K, T2, partials, r32);
+  else
+    hipLaunchKernelGGL((k_bt_resid<L2>), dim3((unsigned)(T2 * bv.S)), dim3(tpb_fft<double, FK>()), lds, s, u, R, Fh,
+                       bv, bt, up, zb, K, T2, partials, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_bt_resid(int L2, double* const* u, double* R, const double* Fh, const BatchVec& bv,
                            const BatchTabs& bt, const ZPool& pool, const double* zb, int K, int u_zero,
-                           double* partials, int64_t* T2, hipStream_t s) {
+                           double* partials, int64_t* T2, float* r32, hipStream_t s) {
   switch (L2) {
 #define BLTT_CASE(LL) \
-  case LL: return go_bt_resid<LL>(u, R, Fh, bv, bt, pool, zb, K, u_zero, partials, T2, s);
+  case LL: return go_bt_resid<LL>(u, R, Fh, bv, bt, pool, zb, K, u_zero, partials, T2, r32, s);
     BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64) BLTT_CASE(128)
     BLTT_CASE(256) BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048) BLTT_CASE(4096)
 #undef BLTT_CASE
@@ -182,6 +192,9 @@ static hipError_t attr_bt() {
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_upd<L, float, true, TPB, PLAN>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
     return e;
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_upd<L, float, false, TPB, PLAN>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+    return e;
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_cs<L, TPB, PLAN>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bt_cs_lds<L, TPB>())) != hipSuccess)
     return e;
@@ -190,8 +203,12 @@ static hipError_t attr_bt() {
 }
 template <int L2>
 static hipError_t attr_bt_resid() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_resid<L2>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)fft_lds_bytes<double, fk_mv<true, L2>()>(L2));
+  const int bytes = (int)fft_lds_bytes<double, fk_mv<true, L2>()>(L2);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_resid<L2>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_resid<L2, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t configure_batch_kernels() {

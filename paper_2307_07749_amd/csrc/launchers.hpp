@@ -142,18 +142,22 @@ hipError_t launch_combine(double* u, const ZList<T>& zl, const double* y, const 
 // batched sine-basis kernels (kern_batch.hip): S systems of one shape, vectors
 // back to back (system s at s*n), per-instance tables
 // ---------------------------------------------------------------------------
-enum { BT_START = 0, BT_UPD = 1, BT_MATVEC = 2 };
+enum { BT_START = 0, BT_UPD = 1, BT_MATVEC = 2, BT_START32 = 3 };
 
 // BT_START: Z = P^{-1} (rinv_s Q) with Q the FP64 residual, Vout = rinv_s Q;
-// BT_UPD: Vout = coef_v (Q, V1, V2), Z = P^{-1} Vout; BT_MATVEC: Qout = Y T Z.
+// BT_START32: Z = P^{-1} Q with Q the FP32 residual r/||fhat_s|| a residual
+// pass left (Vout null: Q itself is v_1); BT_UPD: Vout = coef_v (Q, V1, V2),
+// Z = P^{-1} Vout; BT_MATVEC: Qout = Y T Z.
 // plan: radix plan of the transforms (0, or 1 where fft_plan_alt(L))
 hipError_t launch_bt(int which, int L, int tpb, int plan, const void* Q, const float* V1, const float* V2,
                      float* Vout, float* Z, float* Qout, const BatchVec& bv, const BatchTabs& bt, double* partials,
                      hipStream_t s);
 int64_t bt_tiles(int L, int tpb, int64_t M);
+// r32 non-null (with bv.bscale): the residual goes to r32 as FP32 r/||fhat_s||
+// and the update is scaled by ||fhat_s||; null: R in FP64, scaled by ||r_s||
 hipError_t launch_bt_resid(int L2, double* const* u, double* R, const double* Fh, const BatchVec& bv,
                            const BatchTabs& bt, const ZPool& pool, const double* zb, int K, int u_zero,
-                           double* partials, int64_t* T2, hipStream_t s);
+                           double* partials, int64_t* T2, float* r32, hipStream_t s);
 hipError_t launch_bt_scalar(int phase, const BatchVec& bv, const double* partials, int64_t T, double* hist,
                             int64_t hist_stride, double* zb, int K, double inner_tol, int cap, hipStream_t s);
 hipError_t launch_bt_rhs(const double* f, double* b, int64_t N, const BatchVec& bv, double* partials, int64_t* BPS,
