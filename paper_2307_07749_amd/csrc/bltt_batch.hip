@@ -62,7 +62,9 @@ struct BatchClass {
   double* etol_dev = nullptr;      // per-system sweep tolerance
   double* bscale_dev = nullptr;    // per-system ||fhat|| (scale of the FP32 residual hand-over)
   double* etol_host = nullptr;     // pinned staging of it
-  double** uptr_host = nullptr;    // pinned staging of the caller's u pointers
+  double** uptr_host = nullptr;    // pinned staging of the iterate pointers (uhat of each system in R64)
+  double** xptr_host = nullptr;    // pinned staging of the caller's f (in) or u (out) pointers
+  double** xptr_dev = nullptr;
   int sweeps = 0;                  // sweeps completed in the current solve
   double* partials = nullptr;
   int64_t partials_cap = 0;
@@ -89,7 +91,6 @@ struct bltt_batch {
   hipStream_t stream = nullptr;
   std::vector<BatchClass> cls;
   std::vector<void*> allocs;
-  double* coef_one = nullptr;
   double setup_ms = 0.0;
 };
 
@@ -152,34 +153,15 @@ DstTables<double> dst_tab(const BatchClass& c, int d) {
   return tb;
 }
 
-VupdStencil<double> no_stencil(const BatchClass& c) {
-  VupdStencil<double> st{};
-  st.z = nullptr;
-  st.qtaps = 0;
-  st.grid.dim = c.dim;
-  for (int d = 0; d < 3; ++d) {
-    st.grid.m[d] = c.m[d];
-    st.grid.inv_h2[d] = 0.0;
-  }
-  st.N = (int)c.N;
-  st.R = c.M / c.m[0];
-  return st;
-}
-
-// (I x U) on the time-major vector of one system: in -> out (x-lines), then
-// the strided dimensions in place on out (all systems of the class when
-// out covers them: slices are independent)
-hipError_t space_x(bltt_batch* b, BatchClass& c, const double* in, double* out, int64_t nsys) {
-  const int Lx = 2 * (c.m[0] + 1);
-  return launch_dst_x<double>(Lx, KIND_VUPD, in, nullptr, nullptr, nullptr, nullptr, out, nsys * c.n / c.m[0],
-                              dst_tab(c, 0), b->coef_one, nullptr, no_stencil(c), c.stream);
-}
-hipError_t space_strided_all(BatchClass& c, double* x) {
+// y and z sine transforms of every system's mode-major vector in place (the
+// class buffer x: systems back to back, n elements each); reverse: z first
+hipError_t space_strided_mm_all(BatchClass& c, double* x, bool reverse) {
   for (int k = 1; k < c.dim; ++k) {
-    int64_t S = 1;
-    for (int e = 0; e < k; ++e) S *= c.m[e];
-    const hipError_t e = launch_dst_strided<double>(2 * (c.m[k] + 1), x, (int64_t)c.S * c.n / c.m[k], S,
-                                                    dst_tab(c, k), c.stream);
+    const int d = reverse ? c.dim - k : k;
+    int64_t S = c.N;
+    for (int e = 0; e < d; ++e) S *= c.m[e];
+    const hipError_t e = launch_dst_strided<double>(2 * (c.m[d] + 1), x, (int64_t)c.S * c.n / c.m[d], S,
+                                                    dst_tab(c, d), c.stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -398,7 +380,8 @@ int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const doub
   if (hipHostMalloc((void**)&c.states_host, sizeof(SolverState) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c.act_host, sizeof(int) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c.etol_host, sizeof(double) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c.uptr_host, sizeof(double*) * (size_t)S, hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc((void**)&c.uptr_host, sizeof(double*) * (size_t)S, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c.xptr_host, sizeof(double*) * (size_t)S, hipHostMallocDefault) != hipSuccess)
     return BLTT_ENOMEM;
   c.hist_stride = BT_POOL + 2;
   if ((rc = balloc(b, &c.hist_dev, (size_t)(c.hist_stride * S)))) return rc;
@@ -416,7 +399,7 @@ int build_class(bltt_batch* b, BatchClass& c, const bltt_blocks* blk, const doub
     if ((rc = balloc(b, &c.pool.z[i], ns))) return rc;
   for (int i = BT_POOL; i < ZB_MAX; ++i) c.pool.z[i] = nullptr;
   if ((rc = balloc(b, &c.F64, ns)) || (rc = balloc(b, &c.R64, ns))) return rc;
-  if ((rc = balloc(b, &c.uptr_dev, (size_t)S))) return rc;
+  if ((rc = balloc(b, &c.uptr_dev, (size_t)S)) || (rc = balloc(b, &c.xptr_dev, (size_t)S))) return rc;
   HIPCHK(hipMemsetAsync(c.Q, 0, ns * sizeof(float), c.stream));
   for (auto& v : c.V) HIPCHK(hipMemsetAsync(v, 0, ns * sizeof(float), c.stream));
   for (int i = 0; i < 2; ++i) HIPCHK(hipMemsetAsync(c.pool.z[i], 0, ns * sizeof(float), c.stream));
@@ -434,6 +417,7 @@ void destroy_class(BatchClass& c) {
   if (c.act_host) (void)hipHostFree(c.act_host);
   if (c.etol_host) (void)hipHostFree(c.etol_host);
   if (c.uptr_host) (void)hipHostFree(c.uptr_host);
+  if (c.xptr_host) (void)hipHostFree(c.xptr_host);
 }
 
 // per-system bookkeeping of one solve
@@ -520,10 +504,6 @@ int bltt_setup_batched(const bltt_blocks* blk, const int64_t* N, const int64_t* 
     return code;
   };
   if (configure_kernels_once() != hipSuccess) return fail(BLTT_EHIP);
-  {
-    std::vector<double> one = {1.0, 0.0, 0.0, 0.0};
-    if (int rc = bupload(b, &b->coef_one, one)) return fail(rc);
-  }
   // shape classes
   std::map<std::tuple<int64_t, int, int, int, int, double, double, double>, int> key;
   for (int i = 0; i < count; ++i) {
@@ -624,11 +604,14 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
     runs[ci].assign((size_t)c.S, SysRun{});
     HIPCHK(hipStreamWaitEvent(c.stream, start, 0));
     // fhat = (I x U) f per system (time-major into R64), transposed to mode-major F64
-    for (int s = 0; s < c.S; ++s) HIPCHK(space_x(b, c, f_dev[c.sys_global[(size_t)s]], c.R64 + (int64_t)s * c.n, 1));
-    HIPCHK(space_strided_all(c, c.R64));
-    HIPCHK(launch_bt_transpose(nullptr, c.R64, nullptr, c.F64, c.n, c.N, c.M, c.S, c.stream));
+    for (int s = 0; s < c.S; ++s) c.xptr_host[s] = const_cast<double*>(f_dev[c.sys_global[(size_t)s]]);
+    HIPCHK(hipMemcpyAsync(c.xptr_dev, c.xptr_host, sizeof(double*) * (size_t)c.S, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(launch_bt_dst_xt<double>(2 * (c.m[0] + 1), 0, (const double* const*)c.xptr_dev, nullptr, nullptr, c.F64,
+                                    c.n, c.N, c.M, c.S, dst_tab(c, 0), c.stream));
+    HIPCHK(space_strided_mm_all(c, c.F64, false));
     for (int s = 0; s < c.S; ++s) {
-      c.uptr_host[s] = u_dev[c.sys_global[(size_t)s]];
+      // uhat lives in R64 once the first sweep's start has read b from there
+      c.uptr_host[s] = c.R64 + (int64_t)s * c.n;
       c.act_host[s] = 1;
     }
     c.sweeps = 0;
@@ -725,16 +708,15 @@ int bltt_pminres_batched(bltt_batch* b, const double* const* f_dev, double tol, 
         continue;
       }
       if (step[ci] == ST_FINISH) {
-        // systems that never ran (zero right-hand side) still hold scratch: zero them first
-        for (int s = 0; s < c.S; ++s)
-          if (R[(size_t)s].outer == 0)
-            HIPCHK(hipMemsetAsync(u_dev[c.sys_global[(size_t)s]], 0, sizeof(double) * (size_t)c.n, c.stream));
-        // u = (I x U) uhat: mode-major -> time-major R64, then the transforms into u
-        HIPCHK(launch_bt_transpose((const double* const*)c.uptr_dev, nullptr, nullptr, c.R64, c.n, c.M, c.N, c.S,
-                                   c.stream));
-        HIPCHK(space_strided_all(c, c.R64));
-        for (int s = 0; s < c.S; ++s)
-          HIPCHK(space_x(b, c, c.R64 + (int64_t)s * c.n, u_dev[c.sys_global[(size_t)s]], 1));
+        // u = (I x U) uhat: y/z transforms of uhat in R64, then the x-transform
+        // fused with the move to the caller's time-major u (a system that never
+        // ran, a zero right-hand side, still holds b = 0 there)
+        HIPCHK(space_strided_mm_all(c, c.R64, true));
+        for (int s = 0; s < c.S; ++s) c.xptr_host[s] = u_dev[c.sys_global[(size_t)s]];
+        HIPCHK(hipMemcpyAsync(c.xptr_dev, c.xptr_host, sizeof(double*) * (size_t)c.S, hipMemcpyHostToDevice,
+                              c.stream));
+        HIPCHK(launch_bt_dst_xt<double>(2 * (c.m[0] + 1), 1, nullptr, c.R64, c.xptr_dev, nullptr, c.n, c.N, c.M,
+                                        c.S, dst_tab(c, 0), c.stream));
         HIPCHK(hipEventRecord(c.ev, c.stream));
         step[ci] = ST_DONE;
         continue;

@@ -2422,18 +2422,4 @@ BLTT_HD void bt_rhs_body(Ctx& ctx, double* red, const double* __restrict__ f, do
   if (ctx.tid == 0) partials[ctx.bid] = sum;
 }
 
-// per-system transpose: out_s (C x R) = in_s^T; in and out are either pointer
-// arrays (per system) or a base with stride n
-template <class Ctx>
-BLTT_HD void bt_transpose_body(Ctx& ctx, double* tile, const double* const* __restrict__ in_p,
-                               const double* __restrict__ in_b, double* const* __restrict__ out_p,
-                               double* __restrict__ out_b, int64_t n, int64_t R, int64_t C, int64_t tiles) {
-  const int64_t s = ctx.bid / tiles;
-  Ctx c2 = ctx;
-  c2.bid = (int)(ctx.bid % tiles);
-  const double* in = in_p ? in_p[s] : in_b + s * n;
-  double* out = out_p ? out_p[s] : out_b + s * n;
-  transpose_body<double, false>(c2, tile, in, out, R, C);
-}
-
 }  // namespace bltt

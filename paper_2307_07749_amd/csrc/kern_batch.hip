@@ -52,15 +52,6 @@ __global__ __launch_bounds__(TPB_EW) void k_bt_rhs(const double* __restrict__ f,
   bt_rhs_body(ctx, red, f, b, log2N, n, BPS, partials);
 }
 
-__global__ __launch_bounds__(TPB_EW) void k_bt_transpose(const double* const* __restrict__ in_p,
-                                                         const double* __restrict__ in_b, double* const* __restrict__ out_p,
-                                                         double* __restrict__ out_b, int64_t n, int64_t R, int64_t C,
-                                                         int64_t tiles) {
-  __shared__ double tile[TR_TILE * (TR_TILE + 1)];
-  DevCtx ctx = make_ctx();
-  bt_transpose_body(ctx, tile, in_p, in_b, out_p, out_b, n, R, C, tiles);
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -170,15 +161,6 @@ hipError_t launch_bt_rhs(const double* f, double* b, int64_t N, const BatchVec& 
   const int64_t bps = std::min<int64_t>(ew_blocks(bv.n), 1024);
   if (BPS) *BPS = bps;
   hipLaunchKernelGGL(k_bt_rhs, dim3((unsigned)(bps * bv.S)), dim3(TPB_EW), 0, s, f, b, log2N, bv.n, bps, partials);
-  return hipGetLastError();
-}
-
-hipError_t launch_bt_transpose(const double* const* in_p, const double* in_b, double* const* out_p, double* out_b,
-                               int64_t n, int64_t R, int64_t C, int S, hipStream_t s) {
-  const int64_t tiles = ((C + TR_TILE - 1) / TR_TILE) * ((R + TR_TILE - 1) / TR_TILE);
-  if (tiles * S > 2147483647LL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_bt_transpose, dim3((unsigned)(tiles * S)), dim3(TPB_EW), 0, s, in_p, in_b, out_p, out_b, n, R,
-                     C, tiles);
   return hipGetLastError();
 }
 

@@ -52,6 +52,57 @@ __global__ __attribute__((amdgpu_waves_per_eu(dst_min_waves<T>(), dst_max_waves<
   dst_xt_body<T, L, DIR>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, out, N, M, tb, partials);
 }
 
+// The same pass for S systems of one shape at once: workgroup b works on
+// system b / bps (bps workgroups each, the single-system grid); each side is
+// a pointer per system (p) or a base with stride n (b).
+template <typename T, int L, int DIR>
+__global__ __attribute__((amdgpu_waves_per_eu(dst_min_waves<T>(), dst_max_waves<T>()))) __launch_bounds__(DSTXT_TPB) void k_bt_dst_xt(
+    const T* const* __restrict__ in_p, const T* __restrict__ in_b, T* const* __restrict__ out_p,
+    T* __restrict__ out_b, int64_t n, int64_t N, int64_t M, DstTables<T> tb, int bps) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NL = DSTXT_TPB / (L / fft_V(L));
+  using F = LineFft<T, L, NL, false, LAST_LINEAR, false, 0, dst_split<T>()>;
+  DevCtx ctx = make_ctx();
+  const int s = ctx.bid / bps;
+  ctx.bid -= s * bps;
+  ctx.nbx = bps;
+  const T* in = in_p ? in_p[s] : in_b + (int64_t)s * n;
+  T* out = out_p ? out_p[s] : out_b + (int64_t)s * n;
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * F::LDS_ELEMS);
+  dst_xt_body<T, L, DIR>(ctx, reinterpret_cast<cx<T>*>(smem), red, in, out, N, M, tb, nullptr);
+}
+
+template <typename T, int L>
+static hipError_t go_bt_dxt(int dir, const T* const* in_p, const T* in_b, T* const* out_p, T* out_b, int64_t n,
+                            int64_t N, int64_t M, int S, const DstTables<T>& tb, hipStream_t s) {
+  constexpr int m = L / 2 - 1;
+  if (M % m != 0 || n != N * M || S < 1 || (!in_p && !in_b) || (!out_p && !out_b)) return hipErrorInvalidValue;
+  const int64_t bps = dstxt_blocks(M / m, N, dstxt_lines<T, L>());
+  if (bps < 1 || bps * S > 2147483647LL) return hipErrorInvalidValue;
+  const size_t lds = dstxt_lds_bytes<T, L>();
+  const dim3 grid((unsigned)(bps * S)), block(DSTXT_TPB);
+  if (dir == 0)
+    hipLaunchKernelGGL((k_bt_dst_xt<T, L, 0>), grid, block, lds, s, in_p, in_b, out_p, out_b, n, N, M, tb, (int)bps);
+  else
+    hipLaunchKernelGGL((k_bt_dst_xt<T, L, 1>), grid, block, lds, s, in_p, in_b, out_p, out_b, n, N, M, tb, (int)bps);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bt_dst_xt(int L, int dir, const T* const* in_p, const T* in_b, T* const* out_p, T* out_b,
+                            int64_t n, int64_t N, int64_t M, int S, const DstTables<T>& tb, hipStream_t s) {
+  switch (L) {
+#define BLTT_CASE(LL) \
+  case LL: return go_bt_dxt<T, LL>(dir, in_p, in_b, out_p, out_b, n, N, M, S, tb, s);
+    BLTT_CASE(4) BLTT_CASE(8) BLTT_CASE(16) BLTT_CASE(32) BLTT_CASE(64) BLTT_CASE(128) BLTT_CASE(256)
+    BLTT_CASE(512) BLTT_CASE(1024) BLTT_CASE(2048)
+#undef BLTT_CASE
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_bt_dst_xt<double>(int, int, const double* const*, const double*, double* const*, double*,
+                                             int64_t, int64_t, int64_t, int, const DstTables<double>&, hipStream_t);
+
 template <typename T, int L>
 static hipError_t go_dxt(int dir, const T* in, T* out, int64_t N, int64_t M, const DstTables<T>& tb,
                          double* partials, int64_t* nparts, hipStream_t s) {
@@ -187,6 +238,12 @@ static hipError_t attr_dst() {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bt)) != hipSuccess)
       return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_xt<T, L, 1>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bt)) != hipSuccess)
+      return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_dst_xt<T, L, 0>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bt)) != hipSuccess)
+      return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_dst_xt<T, L, 1>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bt)) != hipSuccess)
       return e;
   }

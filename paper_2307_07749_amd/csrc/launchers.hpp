@@ -101,6 +101,12 @@ hipError_t launch_dst_xt(int L, int dir, const T* in, T* out, int64_t N, int64_t
                          double* partials, int64_t* nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_dst_strided(int L, T* x, int64_t nlines, int64_t S, const DstTables<T>& tb, hipStream_t s);
+// launch_dst_xt for S systems of one shape (n = N M elements each) in one
+// launch; each side is a device array of per-system pointers (p) or a base
+// with stride n (b), the other null.  No norm partial sums.  FP64.
+template <typename T>
+hipError_t launch_bt_dst_xt(int L, int dir, const T* const* in_p, const T* in_b, T* const* out_p, T* out_b,
+                            int64_t n, int64_t N, int64_t M, int S, const DstTables<T>& tb, hipStream_t s);
 
 // kernel attribute setup (dynamic LDS above 64 KiB): configure_kernels_once
 // runs it once per process
@@ -162,7 +168,4 @@ hipError_t launch_bt_scalar(int phase, const BatchVec& bv, const double* partial
                             int64_t hist_stride, double* zb, int K, double inner_tol, int cap, hipStream_t s);
 hipError_t launch_bt_rhs(const double* f, double* b, int64_t N, const BatchVec& bv, double* partials, int64_t* BPS,
                          hipStream_t s);
-hipError_t launch_bt_transpose(const double* const* in_p, const double* in_b, double* const* out_p, double* out_b,
-                               int64_t n, int64_t R, int64_t C, int S, hipStream_t s);
-
 }  // namespace bltt
